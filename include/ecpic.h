@@ -1,0 +1,183 @@
+/*
+ * ecpic.h -- C-ABI of the MI355X (gfx950) library for the energy-conserving
+ * particle-in-cell step of the reduced 1D relativistic Vlasov-Maxwell model
+ * without spin (Li, "Energy conserving particle-in-cell methods for
+ * relativistic Vlasov-Maxwell equations of laser-plasma interaction").
+ *
+ * State (Section 3.1, eq. dis): particle positions x_a and momenta p_a with a
+ * common weight w, V1 coefficients e_x and V0 coefficients e_y, e_z, a_y,
+ * a_z on a periodic uniform grid of M cells, B-splines of degree p (V0) and
+ * p-1 (V1).  Units are those of the reduced model (Section 2.1): c = 1,
+ * plasma frequency 1 at density 1, ions a uniform neutralising background.
+ *
+ * Every call returns an ecpic_status.  Unless stated otherwise:
+ *   - host arrays are read or written during the call only and never kept;
+ *   - device pointers (the *_dev calls) must be device memory of the context's
+ *     device, stay valid for the call, and are accessed on the context's stream;
+ *   - ECPIC_EINVAL leaves the state unchanged;
+ *   - a context is bound to one device and one stream and is not thread-safe.
+ * All computation of the step runs in HIP kernels on the GPU; there is no CPU
+ * fallback, and ecpic_create fails with ECPIC_EDEVICE when no gfx950 device
+ * is usable.
+ */
+#ifndef ECPIC_H
+#define ECPIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ecpic_ctx ecpic_ctx;
+
+typedef enum {
+    ECPIC_OK = 0,
+    ECPIC_EINVAL = -1,     /* bad argument or configuration; state unchanged */
+    ECPIC_ENOMEM = -2,     /* device or host allocation failed */
+    ECPIC_ENOTCONV = -3,   /* Picard iteration hit picard_max_iter; the step is rolled back */
+    ECPIC_EDEVICE = -4,    /* HIP runtime error or no usable device */
+    ECPIC_ENONFINITE = -5, /* a NaN/Inf appeared; state undefined until set again */
+    ECPIC_ECFL = -6,       /* a particle tried to move a full cell or more in one step */
+    ECPIC_ESTATE = -7      /* call out of order (e.g. step before set_particles) */
+} ecpic_status;
+
+/* Arithmetic of the particle sweeps of Subsystem I. */
+typedef enum {
+    ECPIC_FP64 = 0,       /* every sweep in FP64 */
+    ECPIC_FP32_MIXED = 1  /* FP32 gather/push/deposit sweeps with compensated (two-sum) cell
+                             accumulation, then FP64 sweeps until the FP64 test passes; the
+                             residual test, field update and diagnostics stay FP64 */
+} ecpic_precision;
+
+/* Initial Picard iterate of Subsystem I. */
+typedef enum {
+    ECPIC_WS_EXPLICIT = 0, /* delta^(0) = dt p / gamma(x^n, p^n), e^(0) = e_x^n */
+    ECPIC_WS_MLP = 2       /* delta^(0) from the learned predictor (see ecpic_ws_*) */
+} ecpic_warmstart;
+
+/* Ordering of the Picard map of Subsystem I.  Both converge to the same fixed
+ * point of the scheme (Section 4.2, Subsystem I); they differ in which
+ * increment feeds the current of a sweep. */
+typedef enum {
+    ECPIC_MAP_JACOBI = 0, /* current of sweep k from delta^(k); commit x^n + delta^(k),
+                             the momentum of sweep k and e^(k+1) */
+    ECPIC_MAP_SEIDEL = 1  /* current of sweep k from delta^(k+1), the increment the sweep
+                             has just produced; commit x^n + delta^(k+1), e^(k+1) and the
+                             momentum re-evaluated from both */
+} ecpic_map;
+
+typedef struct {
+    double L;                 /* domain length; grid x_j = j L/M (Section 3.1) */
+    int32_t M;                /* cells = number of V0 and V1 coefficients; M >= degree + 3 */
+    int32_t degree;           /* V0 spline degree p in [2, 5]; V1 has degree p - 1 */
+    int64_t n_particles;      /* N >= 0 */
+    double weight;            /* w_a for all particles; 0 => L / N (mean density 1) */
+    double dt;                /* time step; must satisfy dt < L/M (at most one cell per step) */
+    double picard_tol;        /* absolute max-norm tolerance on the increments (Section 5) */
+    int32_t picard_max_iter;  /* sweeps per substep before ECPIC_ENOTCONV; 0 => 50 */
+    int32_t precision;        /* ecpic_precision */
+    int32_t warmstart;        /* ecpic_warmstart */
+    int32_t map;              /* ecpic_map */
+    int32_t device;           /* HIP device ordinal */
+    void *stream;             /* hipStream_t to run on (e.g. torch's); NULL => library-owned */
+} ecpic_config;
+
+typedef struct {
+    int32_t sweeps;   /* Picard sweeps (Subsystem I) or iterations (Subsystem II) */
+    int32_t fp32_sweeps; /* of which in FP32 (precision form) */
+    double residual;  /* last max-norm increment (length / field units) */
+} ecpic_iter_stats;
+
+typedef struct {
+    double kinetic;   /* sum_a w (gamma_a - 1) */
+    double e_long;    /* 1/2 e_x^T M1 e_x */
+    double e_trans;   /* 1/2 (e_y^T M0 e_y + e_z^T M0 e_z) */
+    double b_trans;   /* 1/2 (a_y^T K a_y + a_z^T K a_z), K = G^T M1 G */
+    double total;     /* discrete Hamiltonian H (eq. discrete_H, spin term off) */
+} ecpic_energy_parts;
+
+/* Create a context on cfg->device; allocates every device buffer it needs for
+ * N particles and M cells.  *out receives the context.  Errors: EINVAL for an
+ * invalid config (degree outside [2,5], M < degree + 3, dt >= L/M, N < 0,
+ * non-positive L or tol), EDEVICE when the device is missing or not gfx950,
+ * ENOMEM. */
+int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out);
+
+/* Release every resource of ctx (NULL is allowed). */
+int ecpic_destroy(ecpic_ctx *ctx);
+
+/* Particle state (f_h of eq. f_dirac).  x: positions, any real (wrapped into
+ * [0, L)); p: momenta p_x; n must equal n_particles.  Host arrays, copied.  The
+ * library keeps particles cell-sorted internally and remembers each particle's
+ * index, so get_particles returns them in the order given here. */
+int ecpic_set_particles(ecpic_ctx *ctx, const double *x, const double *p, int64_t n);
+int ecpic_get_particles(ecpic_ctx *ctx, double *x, double *p, int64_t n);
+/* Same, with device arrays of length n (float64). */
+int ecpic_set_particles_dev(ecpic_ctx *ctx, const double *x, const double *p, int64_t n);
+int ecpic_get_particles_dev(ecpic_ctx *ctx, double *x, double *p, int64_t n);
+
+/* Field coefficients (eqs. fem_e, fem_a), host arrays of length M; a NULL input
+ * sets that field to zero, a NULL output skips it. */
+int ecpic_set_fields(ecpic_ctx *ctx, const double *ex, const double *ey, const double *ez,
+                     const double *ay, const double *az);
+int ecpic_get_fields(ecpic_ctx *ctx, double *ex, double *ey, double *ez, double *ay, double *az);
+
+/* Set e_x to the solution of the discrete Poisson equation of the second remark
+ * of Section 4.2, G^T M1 e_x = dx 1 - Lambda0(X)^T W 1, in the zero-mean gauge
+ * (the right-hand side is taken minus its mean if the weights do not
+ * neutralise the background exactly). */
+int ecpic_solve_gauss(ecpic_ctx *ctx);
+
+/* Subsystem I (Section 4.2): solve the implicit discrete-gradient update of
+ * (x, p, e_x) with a_perp frozen, by Picard sweeps to picard_tol.  stats may be
+ * NULL.  ENOTCONV rolls back to the state before the call. */
+int ecpic_substep_particles(ecpic_ctx *ctx, ecpic_iter_stats *stats);
+
+/* Subsystem II (Section 4.2): solve the update of (e_y, e_z, a_y, a_z) with the
+ * particles frozen, by fixed-point iteration on e_perp with the matrix
+ * M0 + dt^2 K / 4 inverted exactly and the particle term lagged.  ENOTCONV
+ * rolls back. */
+int ecpic_substep_fields(ecpic_ctx *ctx, ecpic_iter_stats *stats);
+
+/* nsteps Lie-Trotter steps, Subsystem I then II (Section 5; Subsystem III is the
+ * identity without spin).  per_step_I / per_step_II: arrays of nsteps entries
+ * or NULL.  On ENOTCONV the failing step is rolled back and *steps_done (if
+ * not NULL) tells how many steps completed. */
+int ecpic_step(ecpic_ctx *ctx, int32_t nsteps, ecpic_iter_stats *per_step_I,
+               ecpic_iter_stats *per_step_II, int32_t *steps_done);
+
+/* Current of straight segments: J_j = w sum_a int_{x0_a}^{x1_a} Lambda1_j (the
+ * time-averaged basis of the Subsystem I scheme times the displacement).  x0,
+ * x1: host arrays of n unwrapped positions with |x1 - x0| < dx; J: host array
+ * of length M, overwritten. */
+int ecpic_deposit_current(ecpic_ctx *ctx, const double *x0, const double *x1, int64_t n,
+                          double *J);
+
+/* Charge rho = Lambda0(X)^T W 1 of the current particles (second remark of
+ * Section 4.2); rho: host array of length M. */
+int ecpic_deposit_charge(ecpic_ctx *ctx, double *rho);
+
+/* Discrete Hamiltonian (eq. discrete_H with the spin term off). */
+int ecpic_energy(ecpic_ctx *ctx, ecpic_energy_parts *out);
+
+/* Gauss-law residual r = G^T M1 e_x + Lambda0(X)^T W 1 - dx 1 (second remark of
+ * Section 4.2 with the background of the Poisson equation of Section 2.1);
+ * *linf = max_j |r_j|; vec (length M) may be NULL. */
+int ecpic_gauss_residual(ecpic_ctx *ctx, double *linf, double *vec);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable != 0 starts
+ * recording (and clears the totals); ecpic_kernel_time returns the accumulated
+ * milliseconds and launch count of the named kernel family ("sweep_I",
+ * "field_I", "commit_I", "sweep_II", "field_II", ...). */
+int ecpic_profile_enable(ecpic_ctx *ctx, int32_t enable);
+int ecpic_kernel_time(ecpic_ctx *ctx, const char *name, double *ms, int64_t *launches);
+
+/* Static description of the error code. */
+const char *ecpic_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ECPIC_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) implementation of the energy-conserving PIC step of the
+reduced 1D relativistic Vlasov-Maxwell model (Li, arXiv 2203.06513).
+
+The computation lives in the HIP library ``libecpic.so`` (C-ABI in
+``include/ecpic.h``); this package only builds and binds it.
+"""
+from ._lib import (Context, EcpicError, EXPORTS, FP32_MIXED, FP64, MAP_JACOBI, MAP_SEIDEL,  # noqa: F401
+                   WS_EXPLICIT, WS_MLP, LIB_PATH, load)

@@ -1,0 +1,157 @@
+// Small device helpers: wave/block reductions, padded stores, scans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.hpp"
+
+namespace ecpic {
+
+constexpr int WAVE = 64;
+constexpr int MAX_BLOCK = 256;
+constexpr int MAX_WAVES = MAX_BLOCK / WAVE;
+
+__device__ __forceinline__ double dbits(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long bitsd(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Sum NV per-thread values over the block in a fixed order; thread t < NV gets
+// total t in out.  lds must hold MAX_WAVES * NV doubles.
+template <int NV>
+__device__ __forceinline__ double block_sum_slot(const double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = wave_sum(v[i]);
+        if (lane == 0) lds[wid * NV + i] = s;
+    }
+    __syncthreads();
+    double out = 0.0;
+    if ((int)threadIdx.x < NV) {
+        for (int w = 0; w < nw; ++w) out += lds[w * NV + threadIdx.x];
+    }
+    __syncthreads();
+    return out;
+}
+
+// Max and OR over the block; result valid in thread 0.
+__device__ __forceinline__ void block_max_or(double &m, int &f, double *ldsd, int *ldsi) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    m = wave_max(m);
+    f = wave_or(f);
+    if (lane == 0) { ldsd[wid] = m; ldsi[wid] = f; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) { m = fmax(m, ldsd[w]); f |= ldsi[w]; }
+    }
+    __syncthreads();
+}
+
+// Write v as coefficient j in [0, M) of a padded periodic array (all aliases).
+__device__ __forceinline__ void store_padded(double *f, int M, int j, double v) {
+    const int r = (HALO + M - 1) / M;
+    for (int q = -r; q <= r; ++q) {
+        int idx = j + q * M;
+        if (idx >= -HALO && idx < M + HALO) f[idx + HALO] = v;
+    }
+}
+
+__device__ __forceinline__ int imod(int j, int M) {
+    int r = j % M;
+    return r < 0 ? r + M : r;
+}
+
+// Exclusive scan of one int per thread over a block of blockDim.x <= 1024
+// threads; returns the exclusive prefix, *total gets the block sum.
+__device__ __forceinline__ int block_exscan(int v, int *lds /* >= 32 */, int *total) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) { int t = lds[w]; lds[w] = acc; acc += t; }
+        lds[nw] = acc;
+    }
+    __syncthreads();
+    int res = lds[wid] + x - v;
+    *total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+// Build an item list from per-cell counts (single block).  start[c] must hold
+// the exclusive scan of counts, start[M] = N.
+__device__ inline void build_items(const int32_t *count, const int32_t *start, int M, int chunk, int64_t N,
+                            ItemList out, int *lds) {
+    // items per cell, exclusive scan -> cell_first
+    const int per = (M + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * per;
+    int local = 0;
+    for (int c = c0; c < c0 + per && c < M; ++c) local += (count[c] + chunk - 1) / chunk;
+    int total;
+    int off = block_exscan(local, lds, &total);
+    for (int c = c0; c < c0 + per && c < M; ++c) {
+        const int n = count[c];
+        const int ni = (n + chunk - 1) / chunk;
+        out.cell_first[c] = off;
+        for (int q = 0; q < ni; ++q) {
+            out.cell[off + q] = c;
+            out.begin[off + q] = start[c] + (int)(((int64_t)n * q) / ni);
+        }
+        off += ni;
+    }
+    if (threadIdx.x == 0) {
+        out.cell_first[M] = total;
+        out.begin[total] = (int)N;
+        *out.n_items = total;
+    }
+}
+
+// Exclusive scan of count[0..M) into start[0..M] (single block).
+__device__ inline void scan_cells(const int32_t *count, int32_t *start, int M, int *lds) {
+    const int per = (M + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * per;
+    int local = 0;
+    for (int c = c0; c < c0 + per && c < M; ++c) local += count[c];
+    int total;
+    int off = block_exscan(local, lds, &total);
+    for (int c = c0; c < c0 + per && c < M; ++c) { start[c] = off; off += count[c]; }
+    if (threadIdx.x == 0) start[M] = total;
+}
+
+}  // namespace ecpic

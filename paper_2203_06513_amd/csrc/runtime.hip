@@ -1,0 +1,922 @@
+// Host runtime of libecpic: context, device buffers, the Picard drivers of the
+// two substeps, the Lie-Trotter step and the C-ABI entry points of ecpic.h.
+//
+// Picard driver.  Every kernel of a substep reads the device-resident status
+// (sweep count, convergence, error flags) and turns into a no-op once the
+// substep has converged or failed.  The host therefore enqueues as many
+// sweeps as the previous step needed, then the commit, then Subsystem II
+// (gated on Subsystem I's commit), and synchronises once per step; only when
+// a substep needs more sweeps than predicted does it enqueue more.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ecpic.h"
+#include "internal.hpp"
+
+namespace ecpic {
+void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, const SweepIArgs &a);
+void launch_field_I(int P, int grid, hipStream_t s, const FieldIArgs &a);
+void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a);
+void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s);
+void launch_mark(DevStatus *st, hipStream_t s);
+void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
+void launch_field_II(int P, int grid, hipStream_t s, const FieldIIArgs &a);
+void launch_rhs_II(int grid, hipStream_t s, const DevStatus *st, const double *eyn, const double *ezn,
+                   const double *ayn, const double *azn, const double *m0, const double *kr, int P, double r2,
+                   double ck, int M, double *ry, double *rz);
+void launch_conv(int grid, hipStream_t s, const DevStatus *st, const double *in, double *out, const double *taps,
+                 int ntaps, int mlo, double alpha, int M);
+void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const double *eyn, const double *ezn,
+                      const double *ayn, const double *azn, const double *ey0, const double *ey1,
+                      const double *ez0, const double *ez1, double *ey_next, double *ez_next, double *ay_next,
+                      double *az_next, double half_dt, int M);
+void launch_energy(int P, int grid, int block, hipStream_t s, const double *xi, const double *p, ItemList items,
+                   const double *ay, const double *az, double *part);
+void launch_energy_final(hipStream_t s, const double *part, const int32_t *n_items, double w, const double *ex,
+                         const double *ey, const double *ez, const double *ay, const double *az,
+                         const double *m0, const double *m1, const double *kr, int P, int M, double dx,
+                         double *out);
+void launch_charge(int P, int grid, int block, hipStream_t s, const double *xi, ItemList items, double *part,
+                   double w, int M, double *rho);
+void launch_gauss(hipStream_t s, const double *rho, const double *ex, const double *m1, int P, int M, double dx,
+                  double *r, unsigned long long *maxbits);
+void launch_poisson_rhs(hipStream_t s, const double *rho, int M, double dx, double *u);
+void launch_pad(hipStream_t s, const double *in, double *out, double alpha, int M);
+void launch_unpad(hipStream_t s, const double *in, double *out, int M);
+void launch_init_particles(hipStream_t s, const double *x, const double *p, int64_t n, double L, double inv_dx,
+                           int M, double *xi, double *pp, int32_t *key, int32_t *val);
+void radix_sort(hipStream_t s, int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v1, int64_t n, int key_bits,
+                int32_t *hist, int32_t **kres, int32_t **vres);
+void launch_gather_sorted(hipStream_t s, const int32_t *val, const double *xi_t, const double *p_t, int64_t n,
+                          double *xi, double *p, int32_t *id);
+void launch_count_cells(hipStream_t s, const int32_t *key, int64_t n, int32_t *count);
+void launch_items_from_counts(hipStream_t s, const int32_t *count, int32_t *start, int M, int chunk, int64_t N,
+                              ItemList out);
+void launch_unpermute(hipStream_t s, const double *xi, const double *p, const int32_t *id, int64_t n, double dx,
+                      double *x_out, double *p_out);
+void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
+                             double dx, double w, int M, double *J, int *flags);
+}  // namespace ecpic
+
+using namespace ecpic;
+
+namespace {
+
+// ---- closed-form matrix rows (Section 3.1) ---------------------------------
+// The mass matrix of degree-d B-splines on a uniform grid is dx times the
+// circulant whose row holds the cardinal B-spline of degree 2d+1 at the
+// integers, i.e. Eulerian numbers A(2d+1, k)/(2d+1)!.
+int64_t eulerian(int n, int k) {
+    int64_t s = 0;
+    for (int j = 0; j <= k; ++j) {
+        int64_t b = 1;
+        for (int q = 1; q <= j; ++q) b = b * (n + 1 - j + q) / q;   // C(n+1, j)
+        int64_t pw = 1;
+        for (int q = 0; q < n; ++q) pw *= (k + 1 - j);
+        s += (j % 2 == 0) ? b * pw : -b * pw;
+    }
+    return s;
+}
+
+std::vector<double> mass_row(int d) {   // length 2d+1, dimensionless
+    const int n = 2 * d + 1;
+    double f = 1.0;
+    for (int q = 2; q <= n; ++q) f *= q;
+    std::vector<double> r(n);
+    for (int k = 0; k < n; ++k) r[k] = (double)eulerian(n, k) / f;
+    return r;
+}
+
+// First row of the periodic inverse of a symmetric banded circulant (row of
+// half width b), from its eigenvalues lambda_k = sum_s row_s cos(2 pi k s/M):
+// c_m = (1/M) sum_k cos(2 pi k m/M) / lambda_k.  Entries are kept while
+// |c_m| > rel |c_0|; if that reaches half the period all M entries are used.
+void inverse_taps(const std::vector<double> &row, int M, double rel, std::vector<double> &taps, int &mlo) {
+    const int b = ((int)row.size() - 1) / 2;
+    const long double tw = 2.0L * 3.14159265358979323846264338327950288L / (long double)M;
+    std::vector<long double> inv(M);
+    for (int k = 0; k < M; ++k) {
+        long double lam = 0.0L;
+        for (int s = -b; s <= b; ++s) lam += (long double)row[s + b] * cosl(tw * (long double)(((int64_t)k * (s + M)) % M));
+        inv[k] = 1.0L / lam;
+    }
+    auto coef = [&](int m) {
+        long double s = 0.0L;
+        for (int k = 0; k < M; ++k) s += inv[k] * cosl(tw * (long double)(((int64_t)k * m) % M));
+        return (double)(s / (long double)M);
+    };
+    const double c0 = coef(0);
+    int T = 0;
+    const int half = (M - 1) / 2;
+    std::vector<double> c(1, c0);
+    while (T < half) {
+        const double v = coef(T + 1);
+        c.push_back(v);
+        ++T;
+        if (std::fabs(v) < rel * std::fabs(c0) && T >= 2) break;
+    }
+    if (T >= half) {   // full period
+        mlo = -half;
+        const int cnt = M;
+        taps.assign(cnt, 0.0);
+        for (int i = 0; i < cnt; ++i) {
+            const int m = mlo + i;
+            taps[i] = coef(((m % M) + M) % M);
+        }
+        return;
+    }
+    mlo = -T;
+    taps.assign(2 * T + 1, 0.0);
+    for (int m = -T; m <= T; ++m) taps[m + T] = c[std::abs(m)];
+}
+
+struct Prof {
+    bool on = false;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e;
+        hipEventCreate(&e);
+        return e;
+    }
+};
+
+}  // namespace
+
+struct ecpic_ctx {
+    ecpic_config cfg{};
+    int M = 0, P = 0, kmax = 50, block = 256, chunk = 2048, max_items = 0;
+    int64_t N = 0;
+    double L = 0, dx = 0, inv_dx = 0, w = 0, dt = 0, tol = 0;
+    bool seidel = false;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+
+    Particles pb[2]{};
+    int cur = 0;
+    double *dbuf[2]{};
+    ItemList items[2]{};
+    int icur = 0;
+    int n_items_host = 0;
+    int32_t *cnt = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
+    double *part = nullptr;
+
+    // padded fields: [0]/[1] = current / next (swapped on commit)
+    double *ex[2]{}, *ey[2]{}, *ez[2]{}, *ay[2]{}, *az[2]{};
+    int exc = 0, trc = 0;
+    double *ek[2]{};
+    double *eyk[2]{}, *ezk[2]{};
+    double *E0y = nullptr, *E0z = nullptr, *ry = nullptr, *rz = nullptr;
+    double *taps1 = nullptr, *tapsA = nullptr;
+    int nt1 = 0, mlo1 = 0, ntA = 0, mloA = 0;
+    std::vector<double> m0row, m1row, krow;
+
+    DevStatus *stI = nullptr, *stII = nullptr;
+    struct HostMirror {
+        DevStatus I, II;
+        int32_t n_items_next;
+    } *h = nullptr;
+
+    double *rho = nullptr, *rvec = nullptr, *uvec = nullptr, *out5 = nullptr, *part_e = nullptr;
+    unsigned long long *maxbits = nullptr;
+    int32_t *count = nullptr;
+    bool have_particles = false;
+    int guessI = 4, guessII = 4;
+    Prof prof;
+};
+
+namespace {
+
+#define HIPCHK(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) {                                                                     \
+            std::fprintf(stderr, "ecpic: %s failed: %s (%s:%d)\n", #x, hipGetErrorString(e_), __FILE__, \
+                         __LINE__);                                                                 \
+            return ECPIC_EDEVICE;                                                                   \
+        }                                                                                           \
+    } while (0)
+
+template <typename T>
+int dalloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) return ECPIC_ENOMEM;
+    return ECPIC_OK;
+}
+
+void flush_prof(ecpic_ctx *c) {
+    for (auto &pe : c->prof.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pe.second.first, pe.second.second) == hipSuccess) {
+            auto &a = c->prof.acc[pe.first];
+            a.first += ms;
+            a.second += 1;
+        }
+        c->prof.pool.push_back(pe.second.first);
+        c->prof.pool.push_back(pe.second.second);
+    }
+    c->prof.pending.clear();
+}
+
+// Launch wrapped in timing events when profiling is on.
+template <typename F>
+void timed(ecpic_ctx *c, const char *name, F &&launch) {
+    if (!c->prof.on) { launch(); return; }
+    hipEvent_t a = c->prof.get(), b = c->prof.get();
+    hipEventRecord(a, c->stream);
+    launch();
+    hipEventRecord(b, c->stream);
+    c->prof.pending.push_back({name, {a, b}});
+}
+
+int sync(ecpic_ctx *c) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    flush_prof(c);
+    return ECPIC_OK;
+}
+
+int particle_grid(ecpic_ctx *c, bool exact) { return std::max(1, exact ? c->n_items_host : c->max_items); }
+
+// ---- Subsystem I ----------------------------------------------------------
+SweepIArgs sweep_args(ecpic_ctx *c) {
+    SweepIArgs a{};
+    a.xi = c->pb[c->cur].xi;
+    a.p = c->pb[c->cur].p;
+    a.d0 = c->dbuf[0];
+    a.d1 = c->dbuf[1];
+    a.items = c->items[c->icur];
+    a.ay = c->ay[c->trc];
+    a.az = c->az[c->trc];
+    a.en = c->ex[c->exc];
+    a.ek0 = c->ek[0];
+    a.ek1 = c->ek[1];
+    a.part = c->part;
+    a.st = c->stI;
+    a.dt = c->dt;
+    a.dt_dx = c->dt / c->dx;
+    a.inv_dx = c->inv_dx;
+    a.explicit_start = 1;
+    return a;
+}
+
+void enqueue_sweeps_I(ecpic_ctx *c, int count) {
+    const SweepIArgs a = sweep_args(c);
+    FieldIArgs f{};
+    f.items = c->items[c->icur];
+    f.part = c->part;
+    f.taps = c->taps1;
+    f.ntaps = c->nt1;
+    f.mlo = c->mlo1;
+    f.en = c->ex[c->exc];
+    f.ek0 = c->ek[0];
+    f.ek1 = c->ek[1];
+    f.st = c->stI;
+    f.w = c->w;
+    f.tol = c->tol;
+    f.dx = c->dx;
+    f.M = c->M;
+    const int gridp = particle_grid(c, true), gridf = (c->M + 255) / 256;
+    for (int i = 0; i < count; ++i) {
+        timed(c, "sweep_I", [&] { launch_sweep_I(c->P, c->seidel, gridp, c->block, c->stream, a); });
+        timed(c, "field_I", [&] { launch_field_I(c->P, gridf, c->stream, f); });
+    }
+}
+
+void enqueue_commit_I(ecpic_ctx *c) {
+    CommitIArgs a{};
+    a.cur = c->pb[c->cur];
+    a.nxt = c->pb[c->cur ^ 1];
+    a.d0 = c->dbuf[0];
+    a.d1 = c->dbuf[1];
+    a.items = c->items[c->icur];
+    a.items_next = c->items[c->icur ^ 1];
+    a.ay = c->ay[c->trc];
+    a.az = c->az[c->trc];
+    a.en = c->ex[c->exc];
+    a.ek0 = c->ek[0];
+    a.ek1 = c->ek[1];
+    a.ex_next = c->ex[c->exc ^ 1];
+    a.cnt = c->cnt;
+    a.tot = c->tot;
+    a.base = c->base;
+    a.nstart = c->nstart;
+    a.st = c->stI;
+    a.dt = c->dt;
+    a.dt_dx = c->dt / c->dx;
+    a.inv_dx = c->inv_dx;
+    a.M = c->M;
+    a.chunk = c->chunk;
+    a.seidel = c->seidel;
+    a.explicit_start = 1;
+    a.N = c->N;
+    timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, true), c->block, c->stream, a); });
+}
+
+// ---- Subsystem II ---------------------------------------------------------
+struct IIView {
+    const double *xi, *p;
+    ItemList items;
+    bool exact;
+};
+
+void enqueue_begin_II(ecpic_ctx *c, bool gated) {
+    launch_begin(c->stII, gated ? c->stI : nullptr, c->stream);
+    const int g = (c->M + 255) / 256;
+    const double r = c->dt / (2.0 * c->dx);
+    launch_rhs_II(g, c->stream, c->stII, c->ey[c->trc], c->ez[c->trc], c->ay[c->trc], c->az[c->trc],
+                  c->m0row.data(), c->krow.data(), c->P, r * r, c->dt / (c->dx * c->dx), c->M, c->ry, c->rz);
+    launch_conv(g, c->stream, c->stII, c->ry, c->E0y, c->tapsA, c->ntA, c->mloA, 1.0, c->M);
+    launch_conv(g, c->stream, c->stII, c->rz, c->E0z, c->tapsA, c->ntA, c->mloA, 1.0, c->M);
+}
+
+void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
+    SweepIIArgs a{};
+    a.xi = v.xi;
+    a.p = v.p;
+    a.items = v.items;
+    a.ayn = c->ay[c->trc];
+    a.azn = c->az[c->trc];
+    a.eyn = c->ey[c->trc];
+    a.ezn = c->ez[c->trc];
+    a.ey0 = c->eyk[0];
+    a.ey1 = c->eyk[1];
+    a.ez0 = c->ezk[0];
+    a.ez1 = c->ezk[1];
+    a.part = c->part;
+    a.st = c->stII;
+    a.half_dt = 0.5 * c->dt;
+    FieldIIArgs f{};
+    f.items = v.items;
+    f.part = c->part;
+    f.taps = c->tapsA;
+    f.ntaps = c->ntA;
+    f.mlo = c->mloA;
+    f.E0y = c->E0y;
+    f.E0z = c->E0z;
+    f.eyn = c->ey[c->trc];
+    f.ezn = c->ez[c->trc];
+    f.ey0 = c->eyk[0];
+    f.ey1 = c->eyk[1];
+    f.ez0 = c->ezk[0];
+    f.ez1 = c->ezk[1];
+    f.st = c->stII;
+    f.coef = c->dt * c->w / c->dx;
+    f.tol = c->tol;
+    f.M = c->M;
+    const int gridp = particle_grid(c, v.exact), gridf = (c->M + 255) / 256;
+    for (int i = 0; i < count; ++i) {
+        timed(c, "sweep_II", [&] { launch_sweep_II(c->P, gridp, c->block, c->stream, a); });
+        timed(c, "field_II", [&] { launch_field_II(c->P, gridf, c->stream, f); });
+    }
+}
+
+void enqueue_commit_II(ecpic_ctx *c) {
+    const int t = c->trc, n = t ^ 1;
+    timed(c, "commit_II", [&] {
+        launch_commit_II((c->M + 255) / 256, c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t],
+                         c->eyk[0], c->eyk[1], c->ezk[0], c->ezk[1], c->ey[n], c->ez[n], c->ay[n], c->az[n],
+                         0.5 * c->dt, c->M);
+        launch_mark(c->stII, c->stream);
+    });
+}
+
+int read_status(ecpic_ctx *c) {
+    HIPCHK(hipMemcpyAsync(&c->h->I, c->stI, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->h->II, c->stII, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&c->h->n_items_next, c->items[c->icur ^ 1].n_items, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int flags_to_status(int32_t f) {
+    if (f & FLAG_NONFINITE) return ECPIC_ENONFINITE;
+    if (f & FLAG_CFL) return ECPIC_ECFL;
+    if (f & FLAG_ORDER) return ECPIC_EDEVICE;
+    return ECPIC_OK;
+}
+
+// Finish Subsystem I (more sweeps / commit) after a status read.
+int finish_I(ecpic_ctx *c, bool *recommitted) {
+    *recommitted = false;
+    while (true) {
+        const DevStatus &s = c->h->I;
+        if (s.flags) return flags_to_status(s.flags);
+        if (s.committed) return ECPIC_OK;
+        if (!s.converged) {
+            if (s.k >= c->kmax) return ECPIC_ENOTCONV;
+            enqueue_sweeps_I(c, std::min(2, c->kmax - s.k));
+        }
+        enqueue_commit_I(c);
+        *recommitted = true;
+        int rc = read_status(c);
+        if (rc) return rc;
+    }
+}
+
+int finish_II(ecpic_ctx *c, const IIView &v) {
+    while (true) {
+        const DevStatus &s = c->h->II;
+        if (s.flags) return flags_to_status(s.flags);
+        if (!s.gate) return ECPIC_ESTATE;
+        if (s.committed) return ECPIC_OK;
+        if (!s.converged) {
+            if (s.k >= c->kmax) return ECPIC_ENOTCONV;
+            enqueue_iters_II(c, v, std::min(2, c->kmax - s.k));
+        }
+        enqueue_commit_II(c);
+        int rc = read_status(c);
+        if (rc) return rc;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *ecpic_strerror(int s) {
+    switch (s) {
+        case ECPIC_OK: return "ok";
+        case ECPIC_EINVAL: return "invalid argument or configuration";
+        case ECPIC_ENOMEM: return "out of memory";
+        case ECPIC_ENOTCONV: return "Picard iteration did not converge; step rolled back";
+        case ECPIC_EDEVICE: return "HIP device error or no usable gfx950 device";
+        case ECPIC_ENONFINITE: return "non-finite value in the state";
+        case ECPIC_ECFL: return "a particle moved a full cell or more in one step";
+        case ECPIC_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"
+
+// ---- context life cycle and state I/O ----------------------------------------
+namespace {
+
+int check_device(int dev) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0 || dev < 0 || dev >= n) return ECPIC_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return ECPIC_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        std::fprintf(stderr, "ecpic: device %d is %s, this library is built for gfx950\n", dev, prop.gcnArchName);
+        return ECPIC_EDEVICE;
+    }
+    return ECPIC_OK;
+}
+
+void free_all(ecpic_ctx *c) {
+    auto F = [](void *p) { if (p) hipFree(p); };
+    for (int b = 0; b < 2; ++b) {
+        F(c->pb[b].xi); F(c->pb[b].p); F(c->pb[b].id); F(c->dbuf[b]);
+        F(c->items[b].cell); F(c->items[b].begin); F(c->items[b].cell_first); F(c->items[b].n_items);
+        F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
+        F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
+    }
+    F(c->cnt); F(c->tot); F(c->base); F(c->nstart); F(c->part);
+    F(c->E0y); F(c->E0z); F(c->ry); F(c->rz); F(c->taps1); F(c->tapsA);
+    F(c->stI); F(c->stII);
+    F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
+    if (c->h) hipHostFree(c->h);
+    for (auto &e : c->prof.pool) hipEventDestroy(e);
+    for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
+    if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+}
+
+int alloc_all(ecpic_ctx *c) {
+    const int M = c->M, MP = M + 2 * HALO;
+    const int64_t N = c->N;
+    int rc = 0;
+    for (int b = 0; b < 2; ++b) {
+        rc |= dalloc(&c->pb[b].xi, N); rc |= dalloc(&c->pb[b].p, N); rc |= dalloc(&c->pb[b].id, N);
+        rc |= dalloc(&c->dbuf[b], N);
+        rc |= dalloc(&c->items[b].cell, c->max_items); rc |= dalloc(&c->items[b].begin, c->max_items + 1);
+        rc |= dalloc(&c->items[b].cell_first, M + 1); rc |= dalloc(&c->items[b].n_items, 1);
+        rc |= dalloc(&c->ex[b], MP); rc |= dalloc(&c->ey[b], MP); rc |= dalloc(&c->ez[b], MP);
+        rc |= dalloc(&c->ay[b], MP); rc |= dalloc(&c->az[b], MP);
+        rc |= dalloc(&c->ek[b], MP); rc |= dalloc(&c->eyk[b], MP); rc |= dalloc(&c->ezk[b], MP);
+    }
+    rc |= dalloc(&c->cnt, (size_t)c->max_items * 3);
+    rc |= dalloc(&c->tot, (size_t)M * 3);
+    rc |= dalloc(&c->base, (size_t)c->max_items * 3);
+    rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
+    rc |= dalloc(&c->part, (size_t)c->max_items * 2 * (c->P + 1));
+    rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M); rc |= dalloc(&c->ry, M); rc |= dalloc(&c->rz, M);
+    rc |= dalloc(&c->stI, 1); rc |= dalloc(&c->stII, 1);
+    rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
+    rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
+    rc |= dalloc(&c->count, M);
+    if (rc) return ECPIC_ENOMEM;
+    if (hipHostMalloc((void **)&c->h, sizeof(*c->h), hipHostMallocDefault) != hipSuccess) return ECPIC_ENOMEM;
+    // fields start at zero, items empty
+    for (int b = 0; b < 2; ++b) {
+        for (double *f : {c->ex[b], c->ey[b], c->ez[b], c->ay[b], c->az[b], c->ek[b], c->eyk[b], c->ezk[b]})
+            launch_pad(c->stream, nullptr, f, 0.0, M);
+    }
+    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(int32_t) * M, c->stream));
+    launch_items_from_counts(c->stream, c->count, c->nstart, M, c->chunk, 0, c->items[0]);
+    HIPCHK(hipMemsetAsync(c->stI, 0, sizeof(DevStatus), c->stream));
+    HIPCHK(hipMemsetAsync(c->stII, 0, sizeof(DevStatus), c->stream));
+    // closed-form rows and inverse taps
+    c->m0row = mass_row(c->P);
+    c->m1row = mass_row(c->P - 1);
+    c->krow.assign(2 * c->P + 1, 0.0);
+    for (int k = -c->P; k <= c->P; ++k) {
+        auto m = [&](int q) { return (q >= -(c->P - 1) && q <= c->P - 1) ? c->m1row[q + c->P - 1] : 0.0; };
+        c->krow[k + c->P] = 2.0 * m(k) - m(k - 1) - m(k + 1);
+    }
+    std::vector<double> t1, tA, arow(2 * c->P + 1);
+    inverse_taps(c->m1row, M, 1e-18, t1, c->mlo1);
+    const double r = c->dt / (2.0 * c->dx);
+    for (int k = 0; k <= 2 * c->P; ++k) arow[k] = c->m0row[k] + r * r * c->krow[k];
+    inverse_taps(arow, M, 1e-18, tA, c->mloA);
+    c->nt1 = (int)t1.size();
+    c->ntA = (int)tA.size();
+    if (dalloc(&c->taps1, t1.size()) || dalloc(&c->tapsA, tA.size())) return ECPIC_ENOMEM;
+    HIPCHK(hipMemcpyAsync(c->taps1, t1.data(), sizeof(double) * t1.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->tapsA, tA.data(), sizeof(double) * tA.size(), hipMemcpyHostToDevice, c->stream));
+    return sync(c);
+}
+
+int upload_padded(ecpic_ctx *c, const double *host, double *dev_pad) {
+    if (!host) {
+        launch_pad(c->stream, nullptr, dev_pad, 0.0, c->M);
+        return ECPIC_OK;
+    }
+    HIPCHK(hipMemcpyAsync(c->uvec, host, sizeof(double) * c->M, hipMemcpyHostToDevice, c->stream));
+    launch_pad(c->stream, c->uvec, dev_pad, 1.0, c->M);
+    return sync(c);
+}
+
+int download_padded(ecpic_ctx *c, const double *dev_pad, double *host) {
+    if (!host) return ECPIC_OK;
+    launch_unpad(c->stream, dev_pad, c->rvec, c->M);
+    HIPCHK(hipMemcpyAsync(host, c->rvec, sizeof(double) * c->M, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+// Sort arbitrary device arrays (x, p) into the context (cell-sorted, ids).
+int load_particles_dev(ecpic_ctx *c, const double *x, const double *p) {
+    const int64_t N = c->N;
+    int32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr, *hist = nullptr;
+    double *xt = nullptr, *pt = nullptr;
+    const int64_t nblk = (N + 4095) / 4096;
+    int rc = dalloc(&k0, N) | dalloc(&v0, N) | dalloc(&k1, N) | dalloc(&v1, N) | dalloc(&hist, 16 * nblk + 1) |
+             dalloc(&xt, N) | dalloc(&pt, N);
+    if (rc == ECPIC_OK) {
+        Particles &d = c->pb[c->cur];
+        if (N > 0) {
+            launch_init_particles(c->stream, x, p, N, c->L, c->inv_dx, c->M, xt, pt, k0, v0);
+            int bits = 0;
+            while ((1 << bits) < c->M) ++bits;
+            int32_t *ks, *vs;
+            radix_sort(c->stream, k0, v0, k1, v1, N, std::max(bits, 1), hist, &ks, &vs);
+            launch_gather_sorted(c->stream, vs, xt, pt, N, d.xi, d.p, d.id);
+            hipMemsetAsync(c->count, 0, sizeof(int32_t) * c->M, c->stream);
+            launch_count_cells(c->stream, ks, N, c->count);
+        } else {
+            hipMemsetAsync(c->count, 0, sizeof(int32_t) * c->M, c->stream);
+        }
+        launch_items_from_counts(c->stream, c->count, c->nstart, c->M, c->chunk, N, c->items[c->icur]);
+        hipMemcpyAsync(&c->h->n_items_next, c->items[c->icur].n_items, sizeof(int32_t), hipMemcpyDeviceToHost,
+                       c->stream);
+        rc = sync(c);
+        c->n_items_host = c->h->n_items_next;
+    }
+    for (void *q : {(void *)k0, (void *)v0, (void *)k1, (void *)v1, (void *)hist, (void *)xt, (void *)pt})
+        if (q) hipFree(q);
+    if (rc == ECPIC_OK) c->have_particles = true;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
+    if (!cfg || !out) return ECPIC_EINVAL;
+    *out = nullptr;
+    const ecpic_config &g = *cfg;
+    if (!(g.L > 0.0) || g.degree < 2 || g.degree > MAX_DEG || g.M < g.degree + 3 || g.n_particles < 0 ||
+        g.n_particles > (int64_t)0x7fffffff - 1 || !(g.dt > 0.0) || !(g.dt < g.L / g.M) || !(g.picard_tol > 0.0) ||
+        g.picard_max_iter < 0 || (g.precision != ECPIC_FP64 && g.precision != ECPIC_FP32_MIXED) ||
+        (g.map != ECPIC_MAP_JACOBI && g.map != ECPIC_MAP_SEIDEL) ||
+        (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_MLP) || g.weight < 0.0)
+        return ECPIC_EINVAL;
+    int rc = check_device(g.device);
+    if (rc) return rc;
+    if (hipSetDevice(g.device) != hipSuccess) return ECPIC_EDEVICE;
+    ecpic_ctx *c = new ecpic_ctx();
+    c->cfg = g;
+    c->device = g.device;
+    c->M = g.M;
+    c->P = g.degree;
+    c->N = g.n_particles;
+    c->L = g.L;
+    c->dx = g.L / g.M;
+    c->inv_dx = (double)g.M / g.L;
+    c->w = g.weight > 0.0 ? g.weight : (g.n_particles > 0 ? g.L / (double)g.n_particles : 0.0);
+    c->dt = g.dt;
+    c->tol = g.picard_tol;
+    c->kmax = g.picard_max_iter > 0 ? std::min(g.picard_max_iter, MAX_HIST) : 50;
+    c->seidel = g.map == ECPIC_MAP_SEIDEL;
+    const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
+    c->block = ppc >= 512 ? 256 : (ppc >= 128 ? 128 : 64);
+    c->chunk = 2048;
+    c->max_items = (int)(g.M + g.n_particles / c->chunk + 2);
+    if (g.stream) {
+        c->stream = (hipStream_t)g.stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return ECPIC_EDEVICE; }
+        c->own_stream = true;
+    }
+    rc = alloc_all(c);
+    if (rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return ECPIC_OK;
+}
+
+int ecpic_destroy(ecpic_ctx *c) {
+    if (!c) return ECPIC_OK;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return ECPIC_OK;
+}
+
+int ecpic_set_particles(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    double *dx_ = nullptr, *dp_ = nullptr;
+    if (dalloc(&dx_, n) || dalloc(&dp_, n)) { if (dx_) hipFree(dx_); return ECPIC_ENOMEM; }
+    int rc = ECPIC_OK;
+    if (n > 0) {
+        if (hipMemcpyAsync(dx_, x, sizeof(double) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(dp_, p, sizeof(double) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            rc = ECPIC_EDEVICE;
+    }
+    if (rc == ECPIC_OK) rc = load_particles_dev(c, dx_, dp_);
+    hipFree(dx_);
+    hipFree(dp_);
+    return rc;
+}
+
+int ecpic_set_particles_dev(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    return load_particles_dev(c, x, p);
+}
+
+int ecpic_get_particles_dev(ecpic_ctx *c, double *x, double *p, int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const Particles &d = c->pb[c->cur];
+    launch_unpermute(c->stream, d.xi, d.p, d.id, n, c->dx, x, p);
+    return sync(c);
+}
+
+int ecpic_get_particles(ecpic_ctx *c, double *x, double *p, int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    double *dx_ = nullptr, *dp_ = nullptr;
+    if (dalloc(&dx_, n) || dalloc(&dp_, n)) { if (dx_) hipFree(dx_); return ECPIC_ENOMEM; }
+    int rc = ecpic_get_particles_dev(c, dx_, dp_, n);
+    if (rc == ECPIC_OK && n > 0) {
+        if (hipMemcpy(x, dx_, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(p, dp_, sizeof(double) * n, hipMemcpyDeviceToHost) != hipSuccess)
+            rc = ECPIC_EDEVICE;
+    }
+    hipFree(dx_);
+    hipFree(dp_);
+    return rc;
+}
+
+int ecpic_set_fields(ecpic_ctx *c, const double *ex, const double *ey, const double *ez, const double *ay,
+                     const double *az) {
+    if (!c) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    int rc = upload_padded(c, ex, c->ex[c->exc]);
+    if (!rc) rc = upload_padded(c, ey, c->ey[c->trc]);
+    if (!rc) rc = upload_padded(c, ez, c->ez[c->trc]);
+    if (!rc) rc = upload_padded(c, ay, c->ay[c->trc]);
+    if (!rc) rc = upload_padded(c, az, c->az[c->trc]);
+    if (!rc) rc = sync(c);
+    return rc;
+}
+
+int ecpic_get_fields(ecpic_ctx *c, double *ex, double *ey, double *ez, double *ay, double *az) {
+    if (!c) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    int rc = download_padded(c, c->ex[c->exc], ex);
+    if (!rc) rc = download_padded(c, c->ey[c->trc], ey);
+    if (!rc) rc = download_padded(c, c->ez[c->trc], ez);
+    if (!rc) rc = download_padded(c, c->ay[c->trc], ay);
+    if (!rc) rc = download_padded(c, c->az[c->trc], az);
+    return rc;
+}
+
+int ecpic_deposit_charge(ecpic_ctx *c, double *rho) {
+    if (!c || !rho) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    launch_charge(c->P, particle_grid(c, true), c->block, c->stream, c->pb[c->cur].xi, c->items[c->icur], c->part,
+                  c->w, c->M, c->rho);
+    HIPCHK(hipMemcpyAsync(rho, c->rho, sizeof(double) * c->M, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int ecpic_solve_gauss(ecpic_ctx *c) {
+    if (!c) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    launch_charge(c->P, particle_grid(c, true), c->block, c->stream, c->pb[c->cur].xi, c->items[c->icur], c->part,
+                  c->w, c->M, c->rho);
+    launch_poisson_rhs(c->stream, c->rho, c->M, c->dx, c->uvec);
+    launch_conv((c->M + 255) / 256, c->stream, nullptr, c->uvec, c->rvec, c->taps1, c->nt1, c->mlo1, 1.0 / c->dx,
+                c->M);
+    launch_pad(c->stream, c->rvec, c->ex[c->exc], 1.0, c->M);
+    return sync(c);
+}
+
+int ecpic_gauss_residual(ecpic_ctx *c, double *linf, double *vec) {
+    if (!c || !linf) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    launch_charge(c->P, particle_grid(c, true), c->block, c->stream, c->pb[c->cur].xi, c->items[c->icur], c->part,
+                  c->w, c->M, c->rho);
+    HIPCHK(hipMemsetAsync(c->maxbits, 0, sizeof(unsigned long long), c->stream));
+    launch_gauss(c->stream, c->rho, c->ex[c->exc], c->m1row.data(), c->P, c->M, c->dx, c->rvec, c->maxbits);
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, c->maxbits, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    if (vec) HIPCHK(hipMemcpyAsync(vec, c->rvec, sizeof(double) * c->M, hipMemcpyDeviceToHost, c->stream));
+    int rc = sync(c);
+    std::memcpy(linf, &bits, sizeof(double));
+    return rc;
+}
+
+int ecpic_energy(ecpic_ctx *c, ecpic_energy_parts *out) {
+    if (!c || !out) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const Particles &d = c->pb[c->cur];
+    launch_energy(c->P, particle_grid(c, true), c->block, c->stream, d.xi, d.p, c->items[c->icur], c->ay[c->trc],
+                  c->az[c->trc], c->part_e);
+    launch_energy_final(c->stream, c->part_e, c->items[c->icur].n_items, c->w, c->ex[c->exc], c->ey[c->trc],
+                        c->ez[c->trc], c->ay[c->trc], c->az[c->trc], c->m0row.data(), c->m1row.data(),
+                        c->krow.data(), c->P, c->M, c->dx, c->out5);
+    double h5[5];
+    HIPCHK(hipMemcpyAsync(h5, c->out5, sizeof(h5), hipMemcpyDeviceToHost, c->stream));
+    int rc = sync(c);
+    out->kinetic = h5[0]; out->e_long = h5[1]; out->e_trans = h5[2]; out->b_trans = h5[3]; out->total = h5[4];
+    return rc;
+}
+
+int ecpic_deposit_current(ecpic_ctx *c, const double *x0, const double *x1, int64_t n, double *J) {
+    if (!c || !J || n < 0 || (n > 0 && (!x0 || !x1))) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    double *a = nullptr, *b = nullptr, *dJ = nullptr;
+    int *fl = nullptr;
+    if (dalloc(&a, n) || dalloc(&b, n) || dalloc(&dJ, c->M) || dalloc(&fl, 1)) {
+        for (void *q : {(void *)a, (void *)b, (void *)dJ, (void *)fl}) if (q) hipFree(q);
+        return ECPIC_ENOMEM;
+    }
+    int rc = ECPIC_OK;
+    if (n > 0) {
+        hipMemcpyAsync(a, x0, sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(b, x1, sizeof(double) * n, hipMemcpyHostToDevice, c->stream);
+    }
+    hipMemsetAsync(dJ, 0, sizeof(double) * c->M, c->stream);
+    hipMemsetAsync(fl, 0, sizeof(int), c->stream);
+    launch_deposit_segments(c->P, c->stream, a, b, n, c->inv_dx, c->dx, c->w, c->M, dJ, fl);
+    int hf = 0;
+    hipMemcpyAsync(J, dJ, sizeof(double) * c->M, hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(&hf, fl, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    rc = sync(c);
+    if (!rc && hf) rc = ECPIC_ECFL;
+    for (void *q : {(void *)a, (void *)b, (void *)dJ, (void *)fl}) hipFree(q);
+    return rc;
+}
+
+// ---- substeps and steps -------------------------------------------------------
+int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
+    if (!c) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    launch_begin(c->stI, nullptr, c->stream);
+    launch_begin(c->stII, c->stI, c->stream);   // keeps Subsystem II idle
+    enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
+    enqueue_commit_I(c);
+    int rc = read_status(c);
+    bool again = false;
+    if (!rc) rc = finish_I(c, &again);
+    if (stats) {
+        stats->sweeps = c->h->I.k;
+        stats->fp32_sweeps = c->h->I.fp32_sweeps;
+        stats->residual = c->h->I.res;
+    }
+    if (rc) return rc;
+    c->guessI = std::max(1, c->h->I.k);
+    c->cur ^= 1;
+    c->icur ^= 1;
+    c->exc ^= 1;
+    c->n_items_host = c->h->n_items_next;
+    return ECPIC_OK;
+}
+
+int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
+    if (!c) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    enqueue_begin_II(c, false);
+    IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true};
+    enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
+    enqueue_commit_II(c);
+    int rc = read_status(c);
+    if (!rc) rc = finish_II(c, v);
+    if (stats) {
+        stats->sweeps = c->h->II.k;
+        stats->fp32_sweeps = 0;
+        stats->residual = c->h->II.res;
+    }
+    if (rc) return rc;
+    c->guessII = std::max(1, c->h->II.k);
+    c->trc ^= 1;
+    return ECPIC_OK;
+}
+
+int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII, int32_t *steps_done) {
+    if (!c || nsteps < 0) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    if (steps_done) *steps_done = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        // Subsystem I, its commit, then Subsystem II on the committed state
+        launch_begin(c->stI, nullptr, c->stream);
+        enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
+        enqueue_commit_I(c);
+        enqueue_begin_II(c, true);
+        IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
+        enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
+        enqueue_commit_II(c);
+        int rc = read_status(c);
+        bool again = false;
+        if (!rc) rc = finish_I(c, &again);
+        if (!rc && again) {   // Subsystem I needed extra sweeps: run II now
+            enqueue_begin_II(c, true);
+            enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
+            enqueue_commit_II(c);
+            rc = read_status(c);
+        }
+        if (!rc) rc = finish_II(c, v);
+        if (sI) { sI[s].sweeps = c->h->I.k; sI[s].fp32_sweeps = c->h->I.fp32_sweeps; sI[s].residual = c->h->I.res; }
+        if (sII) { sII[s].sweeps = c->h->II.k; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
+        if (rc) return rc;   // nothing swapped: the step is rolled back
+        c->guessI = std::max(1, c->h->I.k);
+        c->guessII = std::max(1, c->h->II.k);
+        c->cur ^= 1;
+        c->icur ^= 1;
+        c->exc ^= 1;
+        c->trc ^= 1;
+        c->n_items_host = c->h->n_items_next;
+        if (steps_done) *steps_done = s + 1;
+    }
+    return ECPIC_OK;
+}
+
+int ecpic_profile_enable(ecpic_ctx *c, int32_t enable) {
+    if (!c) return ECPIC_EINVAL;
+    sync(c);
+    c->prof.on = enable != 0;
+    if (c->prof.on) c->prof.acc.clear();
+    return ECPIC_OK;
+}
+
+int ecpic_kernel_time(ecpic_ctx *c, const char *name, double *ms, int64_t *launches) {
+    if (!c || !name || !ms || !launches) return ECPIC_EINVAL;
+    sync(c);
+    auto it = c->prof.acc.find(name);
+    *ms = it == c->prof.acc.end() ? 0.0 : it->second.first;
+    *launches = it == c->prof.acc.end() ? 0 : it->second.second;
+    return ECPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Device-side B-spline pieces for the uniform periodic grid of Section 3.1.
+//
+// On cell c with local coordinate t in [0, 1), the degree-D splines that do not
+// vanish are N^D_{c-m}(x) = B_D(t + m), m = 0..D.  Each piece is a polynomial,
+// written here in monomials from the truncated-power form of the cardinal
+// B-spline,
+//     B_D(u) = 1/D! sum_{k=0}^{D+1} (-1)^k C(D+1, k) (u - k)_+^D,
+// so on [m, m+1):  B_D(t + m) = sum_i c[m][i] t^i with
+//     c[m][i] = C(D, i)/D! sum_{k=0}^{m} (-1)^k C(D+1, k) (m - k)^(D - i).
+// The coefficients are generated at compile time; nothing here is shared with
+// the CPU oracle (which evaluates splines by the Cox-de Boor recursion).
+//
+// Line means.  The Subsystem I scheme (Section 4.2) needs the time average
+// of Lambda1 along the straight step x(tau), which for a step inside one cell
+// from t = a to t = b is (Q(b) - Q(a))/(b - a) with Q the antiderivative of the
+// piece.  For each monomial (b^(i+1) - a^(i+1)) / ((i+1)(b - a)) = h_i(a, b)/(i+1)
+// with h_i(a, b) = sum_{j=0}^{i} a^j b^(i-j): a polynomial in (a, b), so the
+// mean has no 0/0 when the step is tiny or zero (which the paper's first remark
+// of Section 4.2 handles approximately).  A step that enters a neighbouring
+// cell is split at the knot and the two piece means are combined with the
+// length fractions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecpic {
+
+constexpr int64_t ipow(int64_t b, int e) {
+    int64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+constexpr int64_t binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    int64_t r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+constexpr int64_t factorial(int n) {
+    int64_t r = 1;
+    for (int i = 2; i <= n; ++i) r *= i;
+    return r;
+}
+
+template <int D>
+struct Pieces {
+    double c[D + 1][D + 1];   // c[m][i]: coefficient of t^i of B_D(t + m)
+    double q[D + 1][D + 1];   // q[m][i] = c[m][i] / (i + 1): weights of h_i in the line mean
+    constexpr Pieces() : c{}, q{} {
+        for (int m = 0; m <= D; ++m) {
+            for (int i = 0; i <= D; ++i) {
+                int64_t s = 0;
+                for (int k = 0; k <= m; ++k) {
+                    int64_t term = binom(D + 1, k) * ipow(m - k, D - i);
+                    s += (k % 2 == 0) ? term : -term;
+                }
+                c[m][i] = (double)(binom(D, i) * s) / (double)factorial(D);
+                q[m][i] = c[m][i] / (double)(i + 1);
+            }
+        }
+    }
+};
+
+// B[m] = B_D(t + m), m = 0..D (the D+1 splines alive on the cell, index c - m).
+template <int D, typename T>
+__device__ __forceinline__ void basis_values(T t, T (&B)[D + 1]) {
+    constexpr Pieces<D> P{};
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+        T v = (T)P.c[m][D];
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) v = v * t + (T)P.c[m][i];
+        B[m] = v;
+    }
+}
+
+// Complete homogeneous polynomials h_0..h_D of (a, b).
+template <int D, typename T>
+__device__ __forceinline__ void homog(T a, T b, T (&h)[D + 1]) {
+    h[0] = (T)1;
+    T ai = (T)1;
+#pragma unroll
+    for (int i = 1; i <= D; ++i) {
+        ai = ai * a;
+        h[i] = h[i - 1] * b + ai;
+    }
+}
+
+// Mean over [a, b] (0 <= a <= b <= 1, possibly a == b) of B_D(t + m), m = 0..D.
+template <int D, typename T>
+__device__ __forceinline__ void piece_means(T a, T b, T (&avg)[D + 1]) {
+    constexpr Pieces<D> P{};
+    T h[D + 1];
+    homog<D>(a, b, h);
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+        T v = (T)0;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) v = v + (T)P.q[m][i] * h[i];
+        avg[m] = v;
+    }
+}
+
+// Line mean of the V1 basis (degree P-1) along a step that starts at t0 in
+// [0, 1) of cell c0 and ends at t1 = t0 + dr in (-1, 2) (cell units, c0 frame);
+// s = +1 / -1 / 0 tells whether the end lies in cell c0+1 / c0-1 / c0.
+// Output lb[k], k = 0..P+1, is the mean of Lambda1_{c0-P+k}.
+template <int P, typename T>
+__device__ __forceinline__ void line_mean_v1(T t0, T t1, int s, T (&lb)[P + 2]) {
+    constexpr int D = P - 1;
+    const T one = (T)1, zero = (T)0;
+    T t1c = t1 < zero ? zero : (t1 > one ? one : t1);
+    T a = t0 < t1c ? t0 : t1c;
+    T b = t0 < t1c ? t1c : t0;
+    T avgA[D + 1];
+    piece_means<D>(a, b, avgA);
+    // second piece in the neighbour cell: [0, t1 - 1] (s = +1) or [t1 + 1, 1] (s = -1)
+    T as = s > 0 ? zero : (s < 0 ? t1 + one : zero);
+    T bs = s > 0 ? t1 - one : (s < 0 ? one : zero);
+    T avgB[D + 1];
+    piece_means<D>(as, bs, avgB);
+    T lenA = b - a, lenB = bs - as;
+    T wB = s != 0 ? lenB / (lenA + lenB) : zero;
+    T wA = one - wB;
+#pragma unroll
+    for (int k = 0; k <= P + 1; ++k) {
+        // main piece: index c0 - m  <->  k = P - m
+        T v = (k >= 1 && k <= P) ? wA * avgA[P - k] : zero;
+        // neighbour piece: index c0 + s - m  <->  k = P + s - m
+        T vr = (P + 1 - k >= 0 && P + 1 - k <= D) ? avgB[(P + 1 - k) < 0 ? 0 : ((P + 1 - k) > D ? D : (P + 1 - k))] : zero;
+        T vl = (P - 1 - k >= 0 && P - 1 - k <= D) ? avgB[(P - 1 - k) < 0 ? 0 : ((P - 1 - k) > D ? D : (P - 1 - k))] : zero;
+        lb[k] = v + wB * (s > 0 ? vr : vl);
+    }
+}
+
+}  // namespace ecpic

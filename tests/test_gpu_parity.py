@@ -1,0 +1,326 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Same seeded inputs on both sides; every comparison is element by element with
+the bar ||gpu - oracle||_inf / ||oracle||_inf <= 1e-12 per array (positions
+compared on the circle, relative to L), and equal Picard sweep counts.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2203_06513_amd as ec
+import workloads
+from oracle import Oracle, initial_state
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max(initial=0.0) / max(np.abs(b).max(initial=0.0), 1e-300)
+
+
+def xrel(a, b, L):
+    d = np.mod(np.asarray(a) - np.asarray(b) + L / 2, L) - L / 2
+    return np.abs(d).max(initial=0.0) / L
+
+
+def assert_state_close(g, s, L, tol=TOL, keys=("ex", "ey", "ez", "ay", "az")):
+    errs = {"x": xrel(g["x"], s["x"], L), "p": rel(g["p"], s["p"])}
+    for k in keys:
+        errs[k] = rel(g[k], s[k]) if np.abs(s[k]).max() > 0 else np.abs(g[k]).max()
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"parity above {tol}: {bad} (all: {errs})"
+    return errs
+
+
+def gpu_ctx(w, n=None, **kw):
+    return ec.Context.from_workload(w, n=n, **kw)
+
+
+# --------------------------------------------------------------------------
+# building blocks
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_deposit_current_segments(p):
+    """Line integrals of Lambda1 along straight segments, including knot crossings,
+    periodic wrap and zero-length steps."""
+    M, L = 16, 3.0
+    dx = L / M
+    rng = np.random.default_rng(p)
+    n = 4000
+    x0 = rng.uniform(0, L, n)
+    x0[:10] = np.arange(10) * dx                 # exactly on knots
+    x1 = x0 + rng.uniform(-0.95, 0.95, n) * dx
+    x1[10:20] = x0[10:20]                        # zero length
+    x0[20:25] = L - 1e-14; x1[20:25] = L + 0.3 * dx      # wrap right
+    x0[25:30] = 1e-14; x1[25:30] = -0.4 * dx             # wrap left
+    o = Oracle(L=L, M=M, p=p, n=n, w=0.37, dt=0.01)
+    with ec.Context(L=L, M=M, degree=p, n_particles=0, dt=0.01, tol=1e-12, weight=0.37) as c:
+        J = c.deposit_current(x0, x1)
+    Jo = o.deposit_current(x0, x1)
+    assert rel(J, Jo) <= 1e-13
+    assert abs(J.sum() - 0.37 * (x1 - x0).sum()) <= 1e-12
+
+
+@pytest.mark.parametrize("name,n", [("langmuir64", None), ("paper51", None), ("pump2048", 200_000)])
+def test_sort_charge_poisson_energy(name, n):
+    w = workloads.get(name)
+    arr = workloads.generate(w, n=n)
+    nn = len(arr["x"])
+    o = Oracle.from_workload(w, n=nn)
+    s = initial_state(o, arr)
+    with gpu_ctx(w, n=nn) as c:
+        c.load(arr)
+        g = c.state()
+        rho = c.deposit_charge()
+        E = c.energy()
+        gmax = c.gauss_residual()
+    # round trip of the particles through the cell sort
+    np.testing.assert_array_equal(g["p"], arr["p"])
+    assert xrel(g["x"], arr["x"], w.L) <= 1e-15
+    assert rel(rho, o.deposit_charge(s["x"])) <= 1e-13
+    assert rel(g["ex"], s["ex"]) <= TOL
+    assert rel(E, o.energy(s)) <= 1e-13
+    assert gmax <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Subsystem I and II, one call from an identical state
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seidel", [0, 1])
+@pytest.mark.parametrize("name,n", [("langmuir64", None), ("paper51", None)])
+def test_subsystem_I_one_call(name, n, seidel):
+    w = workloads.get(name)
+    arr = workloads.generate(w, n=n)
+    o = Oracle.from_workload(w, n=n, seidel=seidel)
+    s = initial_state(o, arr)
+    st, k_o, r_o = o.substep_I(s)
+    assert st == 0
+    with gpu_ctx(w, n=n, map=seidel) as c:
+        c.load(arr)
+        k_g, r_g = c.substep_particles()
+        g = c.state()
+    assert k_g == k_o
+    assert_state_close(g, s, w.L)
+
+
+@pytest.mark.parametrize("name", ["langmuir64", "paper51"])
+def test_subsystem_II_one_call(name):
+    w = workloads.get(name)
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w)
+    s = initial_state(o, arr)
+    st, k_o, r_o = o.substep_II(s)
+    assert st == 0
+    with gpu_ctx(w) as c:
+        c.load(arr)
+        k_g, r_g = c.substep_fields()
+        g = c.state()
+    assert k_g == k_o
+    assert_state_close(g, s, w.L)
+
+
+@pytest.mark.parametrize("seidel", [0, 1])
+@pytest.mark.parametrize("p", [2, 5])
+def test_other_degrees_one_step(p, seidel):
+    w = workloads.get("langmuir64").scaled(degree=p, n_particles=3000, M=32)
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=seidel)
+    s = initial_state(o, arr)
+    st, kI, kII, _ = o.step(s, 2)
+    assert st == 0
+    with gpu_ctx(w, map=seidel) as c:
+        c.load(arr)
+        rc, done, gI, gII, _ = c.step(2)
+        g = c.state()
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L)
+
+
+# --------------------------------------------------------------------------
+# Lie-Trotter steps and run-level invariants
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seidel", [0, 1])
+def test_langmuir64_ten_steps(seidel):
+    w = workloads.get("langmuir64")
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=seidel)
+    s = initial_state(o, arr)
+    st, kI, kII, E = o.step(s, 10, energies=True)
+    assert st == 0
+    with gpu_ctx(w, map=seidel) as c:
+        c.load(arr)
+        H0 = c.energy()[4]
+        rc, done, gI, gII, _ = c.step(10)
+        g = c.state()
+        H = c.energy()[4]
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L, tol=1e-11)
+    assert abs(H - E[-1, 4]) / E[0, 4] <= 1e-12
+    assert abs(H0 - E[0, 4]) / E[0, 4] <= 1e-13
+
+
+def test_langmuir64_full_run_invariants():
+    """The whole langmuir64 run (100 steps): energy drift and Gauss law held, and the energy
+    history tracks the oracle's."""
+    w = workloads.get("langmuir64")
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=1)
+    s = initial_state(o, arr)
+    st, kI, kII, E = o.step(s, w.steps, energies=True)
+    assert st == 0
+    Hs = []
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        g0 = c.gauss_residual()
+        Hs.append(c.energy()[4])
+        for _ in range(w.steps // 10):
+            c.step(10)
+            Hs.append(c.energy()[4])
+        g1 = c.gauss_residual()
+    Hs = np.array(Hs)
+    assert np.abs(Hs - Hs[0]).max() / Hs[0] <= 1e-11
+    assert np.abs(Hs - E[::10, 4]).max() / Hs[0] <= 1e-11
+    assert g1 <= 1e-13 and g0 <= 1e-13
+
+
+def test_paper51_run_invariants():
+    w = workloads.get("paper51")
+    arr = workloads.generate(w)
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        H0 = c.energy()[4]
+        g0, r0 = c.gauss_residual(vec=True)
+        rc, done, gI, gII, _ = c.step(400)
+        H1 = c.energy()[4]
+        g1, r1 = c.gauss_residual(vec=True)
+    assert done == 400
+    assert abs(H1 - H0) / H0 <= 1e-11
+    assert np.abs(r1 - r0).max() <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# full-size pump2048 in the bench launch configuration: sampled per-particle
+# checks of the committed state against the oracle's scheme equations
+# --------------------------------------------------------------------------
+
+def test_pump2048_full_size_step_properties():
+    w = workloads.get("pump2048")
+    arr = workloads.generate(w)
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        s0 = c.state()
+        H0 = c.energy()[4]
+        gr0, r0 = c.gauss_residual(vec=True)
+        k, res = c.substep_particles()
+        s1 = c.state()
+        gr1, r1 = c.gauss_residual(vec=True)
+        c.substep_fields()
+        s2 = c.state()
+        H2 = c.energy()[4]
+    assert res <= w.tol
+    # Gauss law carried exactly through the substep (second remark, Section 4.2)
+    assert np.abs(r1 - r0).max() <= 1e-13
+    # energy through one full step
+    assert abs(H2 - H0) / H0 <= 1e-12
+    # sampled particles satisfy the Subsystem I equations with the committed fields
+    o = Oracle.from_workload(w, n=1)
+    gy, gz = o.G(s0["ay"]), o.G(s0["az"])
+    ebar = 0.5 * (s0["ex"] + s1["ex"])
+    rng = np.random.default_rng(0)
+    idx = rng.choice(w.n_particles, 3000, replace=False)
+    for a in idx:
+        delta = np.mod(s1["x"][a] - s0["x"][a] + w.L / 2, w.L) - w.L / 2
+        p1, dn, _, _ = o.particle_map(s0["x"][a], s0["p"][a], delta, s0["ay"], s0["az"], gy, gz, ebar)
+        assert abs(p1 - s1["p"][a]) <= 1e-12
+        assert abs(dn - delta) <= 5 * w.tol
+    # oracle diagnostics of the GPU state agree with the GPU's own
+    on = Oracle.from_workload(w)
+    assert abs(on.energy(s2)[4] - H2) / H2 <= 1e-13
+    assert on.gauss_residual(s1["x"], s1["ex"]) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# edge cases
+# --------------------------------------------------------------------------
+
+def test_vacuum_no_particles():
+    w = workloads.small(M=16, L=4.0, n=0, dt=0.05)
+    arr = workloads.generate(w)
+    o = Oracle(L=w.L, M=w.M, p=3, n=0, w=0.0, dt=w.dt, tol=w.tol)
+    s = {k: np.array(v, float) for k, v in arr.items()}
+    s["ex"] = np.zeros(w.M)
+    st, kI, kII, _ = o.step(s, 3)
+    assert st == 0
+    with ec.Context(L=w.L, M=w.M, degree=3, n_particles=0, dt=w.dt, tol=w.tol) as c:
+        c.set_particles(np.zeros(0), np.zeros(0))
+        c.set_fields(None, arr["ey"], arr["ez"], arr["ay"], arr["az"])
+        rc, done, gI, gII, _ = c.step(3)
+        g = c.state()
+    assert_state_close(g, s, w.L, keys=("ey", "ez", "ay", "az"))
+
+
+@pytest.mark.parametrize("seidel", [0, 1])
+def test_tiny_and_degenerate_particles(seidel):
+    """Three particles with boundary positions, a particle exactly on a knot, p = 0, and an
+    unsorted input order; followed over several steps."""
+    w = workloads.small(M=8, L=2.0, n=6, dt=0.05, amplitude=0.4, sigma=0.5)
+    L, dx = w.L, w.dx
+    arr = workloads.generate(w)
+    arr["x"] = np.array([L - 1e-15, 0.0, 3 * dx, 1.3, 0.2, 1.9999])
+    arr["p"] = np.array([0.9, -0.7, 0.0, -0.2, 0.35, 0.6])
+    o = Oracle.from_workload(w, seidel=seidel, tol=1e-14)
+    s = initial_state(o, arr)
+    st, kI, kII, _ = o.step(s, 5)
+    assert st == 0
+    with gpu_ctx(w, map=seidel, tol=1e-14) as c:
+        c.load(arr)
+        rc, done, gI, gII, _ = c.step(5)
+        g = c.state()
+    assert gI.tolist() == kI.tolist()
+    assert_state_close(g, s, L)
+
+
+def test_not_converged_rolls_back():
+    w = workloads.get("langmuir64").scaled(n_particles=2000, kmax=2)
+    arr = workloads.generate(w)
+    with gpu_ctx(w, max_iter=2) as c:
+        c.load(arr)
+        before = c.state()
+        rc, done, gI, gII, _ = c.step(1, check=False)
+        after = c.state()
+    assert rc == -3 and done == 0
+    for k in before:
+        np.testing.assert_array_equal(before[k], after[k])
+
+
+def test_deterministic_and_resumable():
+    """Two runs from one state are bitwise equal (no floating-point atomics in the step), and a
+    run split in two through get/set of the state matches the uninterrupted one."""
+    w = workloads.get("langmuir64")
+    arr = workloads.generate(w)
+    outs = []
+    for split in (False, False, True):
+        with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+            c.load(arr)
+            if split:
+                c.step(3)
+                mid = c.state()
+            else:
+                c.step(6)
+                outs.append(c.state())
+                continue
+        with gpu_ctx(w, map=ec.MAP_SEIDEL) as c2:
+            c2.set_particles(mid["x"], mid["p"])
+            c2.set_fields(mid["ex"], mid["ey"], mid["ez"], mid["ay"], mid["az"])
+            c2.step(3)
+            outs.append(c2.state())
+    for k in outs[0]:
+        np.testing.assert_array_equal(outs[0][k], outs[1][k])
+    assert_state_close(outs[2], outs[0], w.L, tol=1e-12)
