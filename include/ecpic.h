@@ -173,6 +173,12 @@ int ecpic_gauss_residual(ecpic_ctx *ctx, double *linf, double *vec);
 int ecpic_profile_enable(ecpic_ctx *ctx, int32_t enable);
 int ecpic_kernel_time(ecpic_ctx *ctx, const char *name, double *ms, int64_t *launches);
 
+/* Bandwidth reference: times reps launches of a plain streaming copy kernel that
+ * reads and writes `bytes` bytes each (buffers allocated for the call) and
+ * returns the mean milliseconds per copy.  The same kernel is the calibration
+ * reference for hardware fetch/write byte counters. */
+int ecpic_bandwidth_probe(ecpic_ctx *ctx, int64_t bytes, int32_t reps, double *ms_per_copy);
+
 /* Static description of the error code. */
 const char *ecpic_strerror(int status);
 

@@ -12,7 +12,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libecpic.so")
+LIB_PATH = os.environ.get("ECPIC_LIB") or os.path.join(_HERE, "libecpic.so")
 
 OK, EINVAL, ENOMEM, ENOTCONV, EDEVICE, ENONFINITE, ECFL, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
@@ -25,7 +25,7 @@ EXPORTS = (
     "ecpic_set_particles_dev", "ecpic_get_particles_dev", "ecpic_set_fields", "ecpic_get_fields",
     "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_fields", "ecpic_step",
     "ecpic_deposit_current", "ecpic_deposit_charge", "ecpic_energy", "ecpic_gauss_residual",
-    "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_strerror",
+    "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_bandwidth_probe", "ecpic_strerror",
 )
 
 
@@ -81,6 +81,7 @@ def load() -> C.CDLL:
         L.ecpic_gauss_residual.argtypes = [V, C.POINTER(C.c_double), V]
         L.ecpic_profile_enable.argtypes = [V, C.c_int32]
         L.ecpic_kernel_time.argtypes = [V, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.ecpic_bandwidth_probe.argtypes = [V, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         L.ecpic_strerror.argtypes = [C.c_int]
         L.ecpic_strerror.restype = C.c_char_p
         for f in EXPORTS:
@@ -249,6 +250,12 @@ class Context:
     # -- timing -----------------------------------------------------------------
     def profile(self, enable: bool = True):
         _ck(self._lib.ecpic_profile_enable(self._h, int(enable)), "profile_enable")
+
+    def bandwidth_probe(self, nbytes: int, reps: int = 20) -> float:
+        """Mean ms of a plain copy kernel that reads and writes nbytes each."""
+        ms = C.c_double(0.0)
+        _ck(self._lib.ecpic_bandwidth_probe(self._h, int(nbytes), int(reps), C.byref(ms)), "bandwidth_probe")
+        return ms.value
 
     def kernel_time(self, name: str):
         ms = C.c_double(0.0); n = C.c_int64(0)

@@ -22,26 +22,28 @@ namespace ecpic {
 constexpr int HALO = 8;
 constexpr int MAX_DEG = 5;
 constexpr int MAX_HIST = 128;
+constexpr int MAX_CHUNK = 2048;   // particles of one work item (one cell or a part of it)
 
 // Error bits raised by kernels.
 enum : int32_t { FLAG_NONFINITE = 1, FLAG_CFL = 2, FLAG_ORDER = 4 };
 
-// Picard bookkeeping of one substep, device-resident.  Kernels read it to pick
-// buffers and to skip work once the substep has converged or failed, so that
-// the host can enqueue sweeps ahead of knowing the outcome.
+// Picard bookkeeping of one substep, device-resident.  The host enqueues
+// sweeps with their index k; sweep k first decides whether sweep k-1 already met
+// the tolerance (from the maxima of sweep k-1, kept in slot (k-1)&1) and, if so,
+// records kconv = k-1 and does nothing.  Every kernel of the substep is a no-op
+// once kconv >= 0 or an error flag is set, so the host can enqueue sweeps ahead
+// of knowing the outcome and synchronise once per step.
 struct DevStatus {
-    unsigned long long rx_bits;   // running max |d^(k+1) - d^(k)| (cell units), as bits
-    unsigned long long re_bits;   // running max field increment, as bits
-    int32_t k;                    // sweeps completed
-    int32_t converged;
-    int32_t kconv;                // sweep index that met the tolerance
+    unsigned long long rx_bits[2];   // max |d^(k+1) - d^(k)| (cell units) of sweep k, slot k&1, as bits
+    unsigned long long re_bits[2];   // max field increment of sweep k, slot k&1, as bits
+    int32_t kconv;                   // sweep index that met the tolerance, -1 before
     int32_t committed;
-    int32_t flags;                // FLAG_* bits
-    uint32_t counter;             // blocks finished in the current field kernel
-    int32_t gate;                 // substep allowed to run (Subsystem II waits on I)
-    int32_t fp32_sweeps;          // sweeps done in FP32 (precision form)
-    double res;                   // last residual (length / field units)
-    double res_hist[MAX_HIST];
+    int32_t flags;                   // FLAG_* bits
+    int32_t gate;                    // substep allowed to run (Subsystem II waits on I)
+    int32_t fp32_sweeps;             // sweeps done in FP32 (precision form)
+    int32_t pad_;
+    double res;                      // residual of sweep kconv (length / field units)
+    double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
 
 struct ItemList {
@@ -62,13 +64,13 @@ struct SweepIArgs {
     const double *xi, *p;
     double *d0, *d1;               // iterate buffers, d^(k) = k&1 ? d1 : d0
     ItemList items;
-    const double *ay, *az;         // padded a_perp^n
-    const double *en;              // padded e_x^n
-    const double *ek0, *ek1;       // padded e_x iterates, e^(k) = k==0 ? en : (k&1 ? ek1 : ek0)
+    const double *coefA;           // A-records of a_perp^n
+    const double *coefE0, *coefE1; // E-records of ebar^(k) = (e^n + e^(k))/2, by parity of k
     double *part;                  // [max_items][deg+2]
     DevStatus *st;
-    double dt, dt_dx, inv_dx;
+    double dt, dt_dx, inv_dx, dx, tol;
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
+    int32_t k;                     // sweep index
 };
 
 struct FieldIArgs {
@@ -78,24 +80,28 @@ struct FieldIArgs {
     int32_t ntaps, mlo;            // e_j = en_j - w sum_i taps[i] S_{j - (mlo + i)}
     const double *en;
     double *ek0, *ek1;
+    double *coefE0, *coefE1;
     DevStatus *st;
-    double w, tol, dx;
+    double w;
     int32_t M;
+    int32_t k;
 };
 
 struct CommitIArgs {
     Particles cur, nxt;
     const double *d0, *d1;
     ItemList items, items_next;
-    const double *ay, *az, *en, *ek0, *ek1;
+    const double *coefA, *coefE0, *coefE1;
+    const double *ek0, *ek1;
     double *ex_next;               // padded e_x^{n+1}
     int32_t *cnt;                  // [max_items][3] movers left / stay / right
     int32_t *tot;                  // [M][3]
     int32_t *base;                 // [max_items][3]
-    int32_t *nstart;               // [M + 1]
+    int32_t *nstart;               // [2M + 1]
     DevStatus *st;
-    double dt, dt_dx, inv_dx;
-    int32_t M, chunk, seidel, explicit_start;
+    double dt, dt_dx, inv_dx, dx, tol;
+    int32_t M, chunk, seidel;
+    int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int64_t N;
 };
 
@@ -103,12 +109,12 @@ struct CommitIArgs {
 struct SweepIIArgs {
     const double *xi, *p;
     ItemList items;
-    const double *ayn, *azn, *eyn, *ezn;      // padded state at the substep start
-    const double *ey0, *ey1, *ez0, *ez1;      // padded iterates
+    const double *coefAn;                     // A-records of a_perp^n
+    const double *coefAk0, *coefAk1;          // A-records of a^(k) = a^n - dt/2 (e^n + e^(k)), by parity
     double *part;                             // [max_items][2 (deg+1)]
     DevStatus *st;
-    const DevStatus *gate;                    // Subsystem I status (must be committed)
-    double half_dt;
+    double tol;
+    int32_t k;
 };
 
 struct FieldIIArgs {
@@ -117,13 +123,14 @@ struct FieldIIArgs {
     const double *taps;                       // first row of (M0^ + r^2 K^)^{-1}
     int32_t ntaps, mlo;
     const double *E0y, *E0z;                  // A^{-1} (constant right-hand side), unpadded
-    const double *eyn, *ezn;
-    double *ey0, *ey1, *ez0, *ez1;
+    const double *eyn, *ezn, *ayn, *azn;      // padded state at the substep start
+    double *ey0, *ey1, *ez0, *ez1;            // padded iterates
+    double *coefAk0, *coefAk1;
     DevStatus *st;
-    const DevStatus *gate;
     double coef;                              // dt w / dx
-    double tol;
+    double half_dt;
     int32_t M;
+    int32_t k;
 };
 
 }  // namespace ecpic

@@ -333,8 +333,9 @@ __global__ void __launch_bounds__(256) k_unpermute(const double *xi, const doubl
     p_out[d] = p[i];
 }
 
-// Current of arbitrary straight segments (a checking entry point, not the
-// sweep): J_j += w dx (t1 - t0) lbar_j, by floating-point atomics.
+// Current of arbitrary straight segments (a checking entry point built from
+// the same segment formulas as the sweep): J_j += w dx int Lambda1_j dxi, by
+// floating-point atomics.
 template <int P>
 __global__ void __launch_bounds__(256) k_deposit_segments(const double *x0, const double *x1, int64_t n,
                                                           double inv_dx, double dx, double w, int M,
@@ -348,10 +349,17 @@ __global__ void __launch_bounds__(256) k_deposit_segments(const double *x0, cons
     const double t1 = x1[i] * inv_dx - cf;
     if (!(t1 > -1.0 && t1 < 2.0)) { atomicOr(flags, FLAG_CFL); return; }
     const int s = t1 >= 1.0 ? 1 : (t1 < 0.0 ? -1 : 0);
-    double lb[P + 2];
-    line_mean_v1<P>(t0, t1, s, lb);
+    double I[P + 2];
+    segment_integrals<P>(t0, t1, s, I);
 #pragma unroll
-    for (int q = 0; q < P + 2; ++q) atomicAdd(&J[imod(c - P + q, M)], w * dx * (t1 - t0) * lb[q]);
+    for (int q = 0; q < P + 2; ++q) atomicAdd(&J[imod(c - P + q, M)], w * dx * I[q]);
+}
+
+// Plain streaming copy of n doubles (16-byte accesses): the calibration kernel
+// for bandwidth and for the fetch/write counters.
+__global__ void __launch_bounds__(256) k_copy(const double2 *in, double2 *out, int64_t n2) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[i];
 }
 
 // ---- launchers ------------------------------------------------------------
@@ -456,6 +464,10 @@ void launch_unpermute(hipStream_t s, const double *xi, const double *p, const in
     if (n > 0)
         hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xi, p, id, n, dx, x_out,
                            p_out);
+}
+
+void launch_copy(hipStream_t s, const double *in, double *out, int64_t n) {
+    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, (const double2 *)in, (double2 *)out, n / 2);
 }
 
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,

@@ -29,15 +29,19 @@ void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s);
 void launch_mark(DevStatus *st, hipStream_t s);
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
 void launch_field_II(int P, int grid, hipStream_t s, const FieldIIArgs &a);
-void launch_rhs_II(int grid, hipStream_t s, const DevStatus *st, const double *eyn, const double *ezn,
-                   const double *ayn, const double *azn, const double *m0, const double *kr, int P, double r2,
-                   double ck, int M, double *ry, double *rz);
-void launch_conv(int grid, hipStream_t s, const DevStatus *st, const double *in, double *out, const double *taps,
-                 int ntaps, int mlo, double alpha, int M);
+void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double *ay, const double *az,
+                         const double *e, double *coefA, double *coefE, int M);
+void launch_prep_II(int P, hipStream_t s, const DevStatus *st, const double *ayn, const double *azn,
+                    const double *eyn, const double *ezn, double dt, double *coefAn, double *coefAk0, int M);
+void launch_E0_II(hipStream_t s, const DevStatus *st, const double *eyn, const double *ezn, const double *ayn,
+                  const double *azn, const double *m0, const double *kr, int P, double r2, double ck,
+                  const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z);
+void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
+                 double alpha, int M);
 void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const double *eyn, const double *ezn,
                       const double *ayn, const double *azn, const double *ey0, const double *ey1,
                       const double *ez0, const double *ez1, double *ey_next, double *ez_next, double *ay_next,
-                      double *az_next, double half_dt, int M);
+                      double *az_next, double half_dt, int M, int nsweeps, double tol);
 void launch_energy(int P, int grid, int block, hipStream_t s, const double *xi, const double *p, ItemList items,
                    const double *ay, const double *az, double *part);
 void launch_energy_final(hipStream_t s, const double *part, const int32_t *n_items, double w, const double *ex,
@@ -64,6 +68,7 @@ void launch_unpermute(hipStream_t s, const double *xi, const double *p, const in
                       double *x_out, double *p_out);
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
                              double dx, double w, int M, double *J, int *flags);
+void launch_copy(hipStream_t s, const double *in, double *out, int64_t n);
 }  // namespace ecpic
 
 using namespace ecpic;
@@ -177,7 +182,8 @@ struct ecpic_ctx {
     int exc = 0, trc = 0;
     double *ek[2]{};
     double *eyk[2]{}, *ezk[2]{};
-    double *E0y = nullptr, *E0z = nullptr, *ry = nullptr, *rz = nullptr;
+    double *E0y = nullptr, *E0z = nullptr;
+    double *coefA = nullptr, *coefE[2]{}, *coefAn = nullptr, *coefAk[2]{};
     double *taps1 = nullptr, *tapsA = nullptr;
     int nt1 = 0, mlo1 = 0, ntA = 0, mloA = 0;
     std::vector<double> m0row, m1row, krow;
@@ -193,6 +199,7 @@ struct ecpic_ctx {
     int32_t *count = nullptr;
     bool have_particles = false;
     int guessI = 4, guessII = 4;
+    int kI = 0, kII = 0;   // sweeps / iterations enqueued in the current substeps
     Prof prof;
 };
 
@@ -257,22 +264,22 @@ SweepIArgs sweep_args(ecpic_ctx *c) {
     a.d0 = c->dbuf[0];
     a.d1 = c->dbuf[1];
     a.items = c->items[c->icur];
-    a.ay = c->ay[c->trc];
-    a.az = c->az[c->trc];
-    a.en = c->ex[c->exc];
-    a.ek0 = c->ek[0];
-    a.ek1 = c->ek[1];
+    a.coefA = c->coefA;
+    a.coefE0 = c->coefE[0];
+    a.coefE1 = c->coefE[1];
     a.part = c->part;
     a.st = c->stI;
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
     a.inv_dx = c->inv_dx;
+    a.dx = c->dx;
+    a.tol = c->tol;
     a.explicit_start = 1;
     return a;
 }
 
 void enqueue_sweeps_I(ecpic_ctx *c, int count) {
-    const SweepIArgs a = sweep_args(c);
+    SweepIArgs a = sweep_args(c);
     FieldIArgs f{};
     f.items = c->items[c->icur];
     f.part = c->part;
@@ -282,13 +289,14 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.en = c->ex[c->exc];
     f.ek0 = c->ek[0];
     f.ek1 = c->ek[1];
+    f.coefE0 = c->coefE[0];
+    f.coefE1 = c->coefE[1];
     f.st = c->stI;
     f.w = c->w;
-    f.tol = c->tol;
-    f.dx = c->dx;
     f.M = c->M;
     const int gridp = particle_grid(c, true), gridf = (c->M + 255) / 256;
     for (int i = 0; i < count; ++i) {
+        a.k = f.k = c->kI++;
         timed(c, "sweep_I", [&] { launch_sweep_I(c->P, c->seidel, gridp, c->block, c->stream, a); });
         timed(c, "field_I", [&] { launch_field_I(c->P, gridf, c->stream, f); });
     }
@@ -302,9 +310,9 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.d1 = c->dbuf[1];
     a.items = c->items[c->icur];
     a.items_next = c->items[c->icur ^ 1];
-    a.ay = c->ay[c->trc];
-    a.az = c->az[c->trc];
-    a.en = c->ex[c->exc];
+    a.coefA = c->coefA;
+    a.coefE0 = c->coefE[0];
+    a.coefE1 = c->coefE[1];
     a.ek0 = c->ek[0];
     a.ek1 = c->ek[1];
     a.ex_next = c->ex[c->exc ^ 1];
@@ -316,10 +324,12 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
     a.inv_dx = c->inv_dx;
+    a.dx = c->dx;
+    a.tol = c->tol;
     a.M = c->M;
     a.chunk = c->chunk;
     a.seidel = c->seidel;
-    a.explicit_start = 1;
+    a.nsweeps = c->kI;
     a.N = c->N;
     timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, true), c->block, c->stream, a); });
 }
@@ -332,13 +342,16 @@ struct IIView {
 };
 
 void enqueue_begin_II(ecpic_ctx *c, bool gated) {
+    c->kII = 0;
     launch_begin(c->stII, gated ? c->stI : nullptr, c->stream);
-    const int g = (c->M + 255) / 256;
     const double r = c->dt / (2.0 * c->dx);
-    launch_rhs_II(g, c->stream, c->stII, c->ey[c->trc], c->ez[c->trc], c->ay[c->trc], c->az[c->trc],
-                  c->m0row.data(), c->krow.data(), c->P, r * r, c->dt / (c->dx * c->dx), c->M, c->ry, c->rz);
-    launch_conv(g, c->stream, c->stII, c->ry, c->E0y, c->tapsA, c->ntA, c->mloA, 1.0, c->M);
-    launch_conv(g, c->stream, c->stII, c->rz, c->E0z, c->tapsA, c->ntA, c->mloA, 1.0, c->M);
+    const int t = c->trc;
+    timed(c, "begin_II", [&] {
+        launch_prep_II(c->P, c->stream, c->stII, c->ay[t], c->az[t], c->ey[t], c->ez[t], c->dt, c->coefAn,
+                       c->coefAk[0], c->M);
+        launch_E0_II(c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t], c->m0row.data(), c->krow.data(),
+                     c->P, r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
+    });
 }
 
 void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
@@ -346,17 +359,12 @@ void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
     a.xi = v.xi;
     a.p = v.p;
     a.items = v.items;
-    a.ayn = c->ay[c->trc];
-    a.azn = c->az[c->trc];
-    a.eyn = c->ey[c->trc];
-    a.ezn = c->ez[c->trc];
-    a.ey0 = c->eyk[0];
-    a.ey1 = c->eyk[1];
-    a.ez0 = c->ezk[0];
-    a.ez1 = c->ezk[1];
+    a.coefAn = c->coefAn;
+    a.coefAk0 = c->coefAk[0];
+    a.coefAk1 = c->coefAk[1];
     a.part = c->part;
     a.st = c->stII;
-    a.half_dt = 0.5 * c->dt;
+    a.tol = c->tol;
     FieldIIArgs f{};
     f.items = v.items;
     f.part = c->part;
@@ -367,16 +375,21 @@ void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
     f.E0z = c->E0z;
     f.eyn = c->ey[c->trc];
     f.ezn = c->ez[c->trc];
+    f.ayn = c->ay[c->trc];
+    f.azn = c->az[c->trc];
     f.ey0 = c->eyk[0];
     f.ey1 = c->eyk[1];
     f.ez0 = c->ezk[0];
     f.ez1 = c->ezk[1];
+    f.coefAk0 = c->coefAk[0];
+    f.coefAk1 = c->coefAk[1];
     f.st = c->stII;
     f.coef = c->dt * c->w / c->dx;
-    f.tol = c->tol;
+    f.half_dt = 0.5 * c->dt;
     f.M = c->M;
     const int gridp = particle_grid(c, v.exact), gridf = (c->M + 255) / 256;
     for (int i = 0; i < count; ++i) {
+        a.k = f.k = c->kII++;
         timed(c, "sweep_II", [&] { launch_sweep_II(c->P, gridp, c->block, c->stream, a); });
         timed(c, "field_II", [&] { launch_field_II(c->P, gridf, c->stream, f); });
     }
@@ -387,7 +400,7 @@ void enqueue_commit_II(ecpic_ctx *c) {
     timed(c, "commit_II", [&] {
         launch_commit_II((c->M + 255) / 256, c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t],
                          c->eyk[0], c->eyk[1], c->ezk[0], c->ezk[1], c->ey[n], c->ez[n], c->ay[n], c->az[n],
-                         0.5 * c->dt, c->M);
+                         0.5 * c->dt, c->M, c->kII, c->tol);
         launch_mark(c->stII, c->stream);
     });
 }
@@ -408,15 +421,24 @@ int flags_to_status(int32_t f) {
 }
 
 // Finish Subsystem I (more sweeps / commit) after a status read.
+void enqueue_begin_I(ecpic_ctx *c) {
+    c->kI = 0;
+    launch_begin(c->stI, nullptr, c->stream);
+    timed(c, "begin_I", [&] {
+        launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
+                            c->coefE[0], c->M);
+    });
+}
+
 int finish_I(ecpic_ctx *c, bool *recommitted) {
     *recommitted = false;
     while (true) {
         const DevStatus &s = c->h->I;
         if (s.flags) return flags_to_status(s.flags);
         if (s.committed) return ECPIC_OK;
-        if (!s.converged) {
-            if (s.k >= c->kmax) return ECPIC_ENOTCONV;
-            enqueue_sweeps_I(c, std::min(2, c->kmax - s.k));
+        if (s.kconv < 0) {
+            if (c->kI >= c->kmax) return ECPIC_ENOTCONV;
+            enqueue_sweeps_I(c, std::min(2, c->kmax - c->kI));
         }
         enqueue_commit_I(c);
         *recommitted = true;
@@ -431,9 +453,9 @@ int finish_II(ecpic_ctx *c, const IIView &v) {
         if (s.flags) return flags_to_status(s.flags);
         if (!s.gate) return ECPIC_ESTATE;
         if (s.committed) return ECPIC_OK;
-        if (!s.converged) {
-            if (s.k >= c->kmax) return ECPIC_ENOTCONV;
-            enqueue_iters_II(c, v, std::min(2, c->kmax - s.k));
+        if (s.kconv < 0) {
+            if (c->kII >= c->kmax) return ECPIC_ENOTCONV;
+            enqueue_iters_II(c, v, std::min(2, c->kmax - c->kII));
         }
         enqueue_commit_II(c);
         int rc = read_status(c);
@@ -486,7 +508,8 @@ void free_all(ecpic_ctx *c) {
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
     F(c->cnt); F(c->tot); F(c->base); F(c->nstart); F(c->part);
-    F(c->E0y); F(c->E0z); F(c->ry); F(c->rz); F(c->taps1); F(c->tapsA);
+    F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
+    F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAn); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->stI); F(c->stII);
     F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
     if (c->h) hipHostFree(c->h);
@@ -513,7 +536,11 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
     rc |= dalloc(&c->part, (size_t)c->max_items * 2 * (c->P + 1));
-    rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M); rc |= dalloc(&c->ry, M); rc |= dalloc(&c->rz, M);
+    rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M);
+    const size_t nrec = (size_t)(M + 2);
+    rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAn, nrec * 2 * (c->P + 1));
+    rc |= dalloc(&c->coefAk[0], nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAk[1], nrec * 2 * (c->P + 1));
+    rc |= dalloc(&c->coefE[0], nrec * c->P); rc |= dalloc(&c->coefE[1], nrec * c->P);
     rc |= dalloc(&c->stI, 1); rc |= dalloc(&c->stII, 1);
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
@@ -634,7 +661,7 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->seidel = g.map == ECPIC_MAP_SEIDEL;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
     c->block = ppc >= 512 ? 256 : (ppc >= 128 ? 128 : 64);
-    c->chunk = 2048;
+    c->chunk = MAX_CHUNK;
     c->max_items = (int)(g.M + g.n_particles / c->chunk + 2);
     if (g.stream) {
         c->stream = (hipStream_t)g.stream;
@@ -751,8 +778,7 @@ int ecpic_solve_gauss(ecpic_ctx *c) {
     launch_charge(c->P, particle_grid(c, true), c->block, c->stream, c->pb[c->cur].xi, c->items[c->icur], c->part,
                   c->w, c->M, c->rho);
     launch_poisson_rhs(c->stream, c->rho, c->M, c->dx, c->uvec);
-    launch_conv((c->M + 255) / 256, c->stream, nullptr, c->uvec, c->rvec, c->taps1, c->nt1, c->mlo1, 1.0 / c->dx,
-                c->M);
+    launch_conv((c->M + 255) / 256, c->stream, c->uvec, c->rvec, c->taps1, c->nt1, c->mlo1, 1.0 / c->dx, c->M);
     launch_pad(c->stream, c->rvec, c->ex[c->exc], 1.0, c->M);
     return sync(c);
 }
@@ -821,7 +847,7 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     if (!c) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    launch_begin(c->stI, nullptr, c->stream);
+    enqueue_begin_I(c);
     launch_begin(c->stII, c->stI, c->stream);   // keeps Subsystem II idle
     enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
     enqueue_commit_I(c);
@@ -829,12 +855,12 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     bool again = false;
     if (!rc) rc = finish_I(c, &again);
     if (stats) {
-        stats->sweeps = c->h->I.k;
+        stats->sweeps = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
         stats->fp32_sweeps = c->h->I.fp32_sweeps;
         stats->residual = c->h->I.res;
     }
     if (rc) return rc;
-    c->guessI = std::max(1, c->h->I.k);
+    c->guessI = std::max(1, c->h->I.kconv + 1);
     c->cur ^= 1;
     c->icur ^= 1;
     c->exc ^= 1;
@@ -853,12 +879,12 @@ int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
     int rc = read_status(c);
     if (!rc) rc = finish_II(c, v);
     if (stats) {
-        stats->sweeps = c->h->II.k;
+        stats->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
         stats->fp32_sweeps = 0;
         stats->residual = c->h->II.res;
     }
     if (rc) return rc;
-    c->guessII = std::max(1, c->h->II.k);
+    c->guessII = std::max(1, c->h->II.kconv + 1);
     c->trc ^= 1;
     return ECPIC_OK;
 }
@@ -870,7 +896,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
     if (steps_done) *steps_done = 0;
     for (int s = 0; s < nsteps; ++s) {
         // Subsystem I, its commit, then Subsystem II on the committed state
-        launch_begin(c->stI, nullptr, c->stream);
+        enqueue_begin_I(c);
         enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
         enqueue_commit_I(c);
         enqueue_begin_II(c, true);
@@ -887,11 +913,13 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             rc = read_status(c);
         }
         if (!rc) rc = finish_II(c, v);
-        if (sI) { sI[s].sweeps = c->h->I.k; sI[s].fp32_sweeps = c->h->I.fp32_sweeps; sI[s].residual = c->h->I.res; }
-        if (sII) { sII[s].sweeps = c->h->II.k; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
+        const int nI = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
+        const int nII = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
+        if (sI) { sI[s].sweeps = nI; sI[s].fp32_sweeps = c->h->I.fp32_sweeps; sI[s].residual = c->h->I.res; }
+        if (sII) { sII[s].sweeps = nII; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
         if (rc) return rc;   // nothing swapped: the step is rolled back
-        c->guessI = std::max(1, c->h->I.k);
-        c->guessII = std::max(1, c->h->II.k);
+        c->guessI = std::max(1, nI);
+        c->guessII = std::max(1, nII);
         c->cur ^= 1;
         c->icur ^= 1;
         c->exc ^= 1;
@@ -908,6 +936,31 @@ int ecpic_profile_enable(ecpic_ctx *c, int32_t enable) {
     c->prof.on = enable != 0;
     if (c->prof.on) c->prof.acc.clear();
     return ECPIC_OK;
+}
+
+int ecpic_bandwidth_probe(ecpic_ctx *c, int64_t bytes, int32_t reps, double *ms_per_copy) {
+    if (!c || bytes < 16 || reps < 1 || !ms_per_copy) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    const int64_t n = (bytes / 16) * 2;
+    double *a = nullptr, *b = nullptr;
+    if (dalloc(&a, n) || dalloc(&b, n)) { if (a) hipFree(a); return ECPIC_ENOMEM; }
+    hipMemsetAsync(a, 0, sizeof(double) * n, c->stream);
+    launch_copy(c->stream, a, b, n);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps; ++r) launch_copy(c->stream, (r & 1) ? b : a, (r & 1) ? a : b, n);
+    hipEventRecord(e1, c->stream);
+    int rc = sync(c);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    *ms_per_copy = (double)ms / reps;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(a);
+    hipFree(b);
+    return rc;
 }
 
 int ecpic_kernel_time(ecpic_ctx *c, const char *name, double *ms, int64_t *launches) {

@@ -136,4 +136,51 @@ __device__ __forceinline__ void line_mean_v1(T t0, T t1, int s, T (&lb)[P + 2]) 
     }
 }
 
+// Geometry of a step from t0 in [0, 1) of cell c to t1 in (-1, 2) (c frame):
+// the main piece stays in cell c, the side piece (if any) lies in cell c + s.
+// sA, sB are the signed lengths of the pieces, [aA, bA] and [aB, bB] their
+// (unsigned) extents in the local coordinate of their own cell.
+template <typename T>
+struct Seg {
+    T aA, bA, sA, aB, bB, sB;
+};
+
+template <typename T>
+__device__ __forceinline__ Seg<T> make_seg(T t0, T t1, int s) {
+    const T one = (T)1, zero = (T)0;
+    Seg<T> g;
+    const T t1c = t1 < zero ? zero : (t1 > one ? one : t1);
+    g.aA = t0 < t1c ? t0 : t1c;
+    g.bA = t0 < t1c ? t1c : t0;
+    g.sA = t1c - t0;
+    g.aB = s > 0 ? zero : (s < 0 ? t1 + one : zero);
+    g.bB = s > 0 ? t1 - one : (s < 0 ? one : zero);
+    g.sB = t1 - t1c;
+    return g;
+}
+
+// Integrals of the V1 basis (degree P-1) along a step, in cell units:
+// I[k] = int Lambda1_{c-P+k} dxi, k = 0..P+1, as the signed piece lengths times
+// the piece means (the same formulas the sweep accumulates as moments).
+template <int P, typename T>
+__device__ __forceinline__ void segment_integrals(T t0, T t1, int s, T (&I)[P + 2]) {
+    constexpr int D = P - 1;
+    constexpr Pieces<D> Q{};
+    const Seg<T> g = make_seg(t0, t1, s);
+    T hA[D + 1], hB[D + 1];
+    homog<D>(g.aA, g.bA, hA);
+    homog<D>(g.aB, g.bB, hB);
+#pragma unroll
+    for (int k = 0; k <= P + 1; ++k) I[k] = (T)0;
+#pragma unroll
+    for (int m = 0; m <= D; ++m) {
+        T vA = (T)0, vB = (T)0;
+#pragma unroll
+        for (int i = 0; i <= D; ++i) { vA += (T)Q.q[m][i] * hA[i]; vB += (T)Q.q[m][i] * hB[i]; }
+        I[P - m] += g.sA * vA;                  // index c - m
+        if (s > 0) I[P + 1 - m] += g.sB * vB;   // index c + 1 - m
+        if (s < 0) I[P - 1 - m] += g.sB * vB;   // index c - 1 - m
+    }
+}
+
 }  // namespace ecpic

@@ -1,46 +1,56 @@
 // Subsystem I of the Poisson splitting (Section 4.2): implicit discrete-gradient
 // update of (x, p, e_x) with a_perp frozen, solved by Picard sweeps.
 //
-// One sweep k, for every particle a (cell-local coordinates, d = delta/dx):
-//   A0 = A_perp(x_a), A1 = A_perp(x_a + delta^(k))          V0 gathers
-//   g00 = gamma(p_a, A0), g01 = gamma(p_a, A1)
-//   lbar = time-averaged Lambda1 along x_a -> x_a + delta^(k) (line mean)
-//   F = lbar.ebar - (A0 + A1).(lbar.G a) / (dx (g00 + g01))
-//   p1 = p_a + dt F,  g11 = gamma(p1, A1),  delta^(k+1) = dt (p_a + p1)/(g01 + g11)
-//   S += (x1 - x0)/dx * lbar   (current of the step, Jacobi: delta^(k); Seidel: delta^(k+1))
-// then e^(k+1) = e_x^n - w M1^-1 (dx S) (field kernel), with the divided
-// difference (A1 - A0)/(x1 - x0) taken as lbar.(G a), the 0/0-free identity.
-#include "common.hpp"
-#include "spline.hpp"
+// One sweep k, for every particle (cell-local coordinate t, d = delta/dx):
+//   A0 = A(t0), A1 = A(t1), t1 = t0 + d^(k)          (V0 gathers)
+//   g00 = gamma(p, A0), g01 = gamma(p, A1)
+//   lbar = mean of Lambda1 along the step; DA = (A1 - A0)/(t1 - t0) = lbar.(G a) dx
+//   F = lbar.ebar - (A0 + A1).DA / (dx (g00 + g01))
+//   p1 = p + dt F,  g11 = gamma(p1, A1),  d^(k+1) = (dt/dx) (p + p1)/(g01 + g11)
+//   current += int Lambda1 along the step (Jacobi: of d^(k); Seidel: of d^(k+1))
+// and then e^(k+1) = e_x^n - w M1^-1 (dx S) (field kernel).  A block owns one
+// cell, so A, the divided differences and the line means are polynomials of
+// the particle's local coordinates whose coefficients (coef.hpp) the block
+// loads once; the current is accumulated as the moments sum (signed length) *
+// h_i of its pieces and turned into the per-cell deposit once per block.  A
+// step that enters a neighbour cell (at most one, since |d| < 1) adds a second
+// piece; waves with no such step skip that code.
+#include "coef.hpp"
 
 namespace ecpic {
 
 template <int P>
-struct Window1 {
-    double ay[P + 3], az[P + 3];   // V0 coefficients of cells c-P-1 .. c+1
-    double gy[P + 2], gz[P + 2];   // (G a) * dx on V1 indices c-P .. c+1
-    double eb[P + 2];              // ebar on V1 indices c-P .. c+1
+struct Coef1 {
+    double ay[3][P + 1], az[3][P + 1];   // A on cells c-1, c, c+1
+    double eb[3][P];                     // ebar piece-mean weights on cells c-1, c, c+1
 };
 
 template <int P>
-__device__ __forceinline__ void load_window1(Window1<P> &w, int c, const double *ay, const double *az,
-                                             const double *en, const double *ek) {
-    const int b0 = c - P - 1 + HALO;
+__device__ __forceinline__ void load_coef1(Coef1<P> &k, int c, const double *coefA, const double *coefE) {
+    constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
+    const double *a = coefA + (size_t)(rec_index(c) - 1) * NA;
+    const double *e = coefE + (size_t)(rec_index(c) - 1) * NE;
 #pragma unroll
-    for (int k = 0; k < P + 3; ++k) { w.ay[k] = ay[b0 + k]; w.az[k] = az[b0 + k]; }
+    for (int r = 0; r < 3; ++r) {
 #pragma unroll
-    for (int k = 0; k < P + 2; ++k) {
-        w.gy[k] = w.ay[k + 1] - w.ay[k];
-        w.gz[k] = w.az[k + 1] - w.az[k];
-        w.eb[k] = 0.5 * (en[b0 + 1 + k] + ek[b0 + 1 + k]);
+        for (int i = 0; i <= P; ++i) {
+            k.ay[r][i] = a[r * NA + i];
+            k.az[r][i] = a[r * NA + P + 1 + i];
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) k.eb[r][i] = e[r * NE + i];
     }
 }
 
-// Position bookkeeping: xi0 in [c, c+1); the end point is the rounded
-// xi0 + d, so that deposit and committed position describe the same segment.
+template <int P>
+struct Moments {
+    double A[P], R[P], L[P];   // sum over particles of (signed piece length) h_i(piece)
+};
+
+// End point of a step: xi0 in [c, c+1), t1 = (xi0 + d) - c is exact in floating
+// point, so the committed position and the deposited segment agree.
 __device__ __forceinline__ void end_point(double xi0, double d, int c, double &t1, int &s, int &flags) {
-    double xi1 = xi0 + d;
-    t1 = xi1 - (double)c;
+    t1 = (xi0 + d) - (double)c;
     if (!(t1 > -1.0 && t1 < 2.0)) {   // |d| >= 1 cell, or NaN
         flags |= FLAG_CFL;
         t1 = t1 >= 2.0 ? 1.5 : (t1 <= -1.0 ? -0.5 : 0.5);
@@ -49,183 +59,427 @@ __device__ __forceinline__ void end_point(double xi0, double d, int c, double &t
 }
 
 template <int P>
-__device__ __forceinline__ void particle_map(const Window1<P> &w, double t0, double p0, double d,
-                                             bool explicit_start, int c, double xi0, double dt,
-                                             double dt_dx, double inv_dx, double &dn, double &p1,
-                                             double &d_used, double (&lb)[P + 2], double &dr,
-                                             int &flags) {
-    double B0[P + 1];
-    basis_values<P>(t0, B0);
-    double A0y = 0.0, A0z = 0.0;
+__device__ __forceinline__ void deposit(Moments<P> &mo, double t0, double t1, int s) {
+    const Seg<double> g = make_seg(t0, t1, s);
+    double h[P];
+    homog<P - 1>(g.aA, g.bA, h);
 #pragma unroll
-    for (int m = 0; m <= P; ++m) {
-        A0y += w.ay[P + 1 - m] * B0[m];
-        A0z += w.az[P + 1 - m] * B0[m];
+    for (int i = 0; i < P; ++i) mo.A[i] = fma(g.sA, h[i], mo.A[i]);
+    if (__ballot(s != 0)) {
+        homog<P - 1>(g.aB, g.bB, h);
+        const double sr = s > 0 ? g.sB : 0.0, sl = s < 0 ? g.sB : 0.0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            mo.R[i] = fma(sr, h[i], mo.R[i]);
+            mo.L[i] = fma(sl, h[i], mo.L[i]);
+        }
     }
-    const double pp = p0 * p0;
-    const double g00 = sqrt(1.0 + pp + A0y * A0y + A0z * A0z);
-    if (explicit_start) d = dt_dx * p0 / g00;
-    d_used = d;
+}
+
+__device__ __forceinline__ double dt_dx_times(double dt_dx, double p) { return dt_dx * p; }
+
+struct MapOut {
+    double dn, p1, dused, t1;
+    int s;
+};
+
+// The particle map of one sweep (see the file header).
+template <int P>
+__device__ __forceinline__ MapOut particle_map(const Coef1<P> &k, double xi0, int c, double p0, double d,
+                                               bool explicit_start, double dt, double dt_dx, double inv_dx,
+                                               int &flags) {
+    MapOut o;
+    double t0 = xi0 - (double)c;
+    if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
+    const double A0y = horner<P + 1>(k.ay[1], t0), A0z = horner<P + 1>(k.az[1], t0);
+    const double q0 = fma(p0, p0, 1.0);
+    const double g00 = fsqrt(q0 + A0y * A0y + A0z * A0z);
+    if (explicit_start) d = dt_dx * p0 * frcp(g00);
+    o.dused = d;
     double t1;
     int s;
     end_point(xi0, d, c, t1, s, flags);
-    dr = t1 - t0;
-    double B1[P + 1];
-    basis_values<P>(t1 - (double)s, B1);
-    double y0 = 0.0, yR = 0.0, yL = 0.0, z0 = 0.0, zR = 0.0, zL = 0.0;
-#pragma unroll
-    for (int m = 0; m <= P; ++m) {
-        y0 += w.ay[P + 1 - m] * B1[m]; yR += w.ay[P + 2 - m] * B1[m]; yL += w.ay[P - m] * B1[m];
-        z0 += w.az[P + 1 - m] * B1[m]; zR += w.az[P + 2 - m] * B1[m]; zL += w.az[P - m] * B1[m];
+    o.t1 = t1;
+    o.s = s;
+    const Seg<double> g = make_seg(t0, t1, s);
+    double hA[P];
+    homog<P - 1>(g.aA, g.bA, hA);
+    double LE = pmean<P>(k.eb[1], hA);
+    double DAy = divdiff<P>(k.ay[1], hA), DAz = divdiff<P>(k.az[1], hA);
+    double A1y, A1z;
+    if (__ballot(s != 0)) {
+        const double tl = t1 - (double)s;
+        const double yc = horner<P + 1>(k.ay[1], tl), yr = horner<P + 1>(k.ay[2], tl), yl = horner<P + 1>(k.ay[0], tl);
+        const double zc = horner<P + 1>(k.az[1], tl), zr = horner<P + 1>(k.az[2], tl), zl = horner<P + 1>(k.az[0], tl);
+        A1y = s > 0 ? yr : (s < 0 ? yl : yc);
+        A1z = s > 0 ? zr : (s < 0 ? zl : zc);
+        double hB[P];
+        homog<P - 1>(g.aB, g.bB, hB);
+        const double EB = s > 0 ? pmean<P>(k.eb[2], hB) : pmean<P>(k.eb[0], hB);
+        const double DyB = s > 0 ? divdiff<P>(k.ay[2], hB) : divdiff<P>(k.ay[0], hB);
+        const double DzB = s > 0 ? divdiff<P>(k.az[2], hB) : divdiff<P>(k.az[0], hB);
+        if (s != 0) {
+            const double inv = frcp(g.sA + g.sB);
+            LE = (g.sA * LE + g.sB * EB) * inv;
+            DAy = (g.sA * DAy + g.sB * DyB) * inv;
+            DAz = (g.sA * DAz + g.sB * DzB) * inv;
+        }
+    } else {
+        A1y = horner<P + 1>(k.ay[1], t1);
+        A1z = horner<P + 1>(k.az[1], t1);
     }
-    const double A1y = s > 0 ? yR : (s < 0 ? yL : y0);
-    const double A1z = s > 0 ? zR : (s < 0 ? zL : z0);
     const double qa1 = A1y * A1y + A1z * A1z;
-    const double g01 = sqrt(1.0 + pp + qa1);
-    line_mean_v1<P>(t0, t1, s, lb);
-    double LE = 0.0, LGy = 0.0, LGz = 0.0;
+    const double g01 = fsqrt(q0 + qa1);
+    const double F = LE - ((A0y + A1y) * DAy + (A0z + A1z) * DAz) * inv_dx * frcp(g00 + g01);
+    o.p1 = fma(dt, F, p0);
+    const double g11 = fsqrt(fma(o.p1, o.p1, 1.0) + qa1);
+    o.dn = dt_dx * (p0 + o.p1) * frcp(g01 + g11);
+    if (!(fabs(o.dn) < 1.0e300) || !(fabs(o.p1) < 1.0e300)) flags |= FLAG_NONFINITE;
+    return o;
+}
+
+// Block sum of the moments and conversion to the P+2 V1 slots of the item
+// (slot q <-> V1 index c - P + q); thread q < P+2 returns slot q.
+// Block sum of the moments and conversion to the P+2 V1 slots of the item
+// (slot q <-> V1 index c - P + q); thread q < P+2 returns slot q.  The 3P wave
+// reductions are kept apart by scheduling barriers so they do not all stay
+// live at once.
+template <int P>
+__device__ __forceinline__ double moments_to_slots(const Moments<P> &mo, double *lds) {
+    constexpr Pieces<P - 1> Q{};
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = (blockDim.x + WAVE - 1) / WAVE;
 #pragma unroll
-    for (int k = 0; k < P + 2; ++k) {
-        LE += lb[k] * w.eb[k];
-        LGy += lb[k] * w.gy[k];
-        LGz += lb[k] * w.gz[k];
+    for (int i = 0; i < 3 * P; ++i) {
+        const double v = i < P ? mo.A[i] : (i < 2 * P ? mo.R[i - P] : mo.L[i - 2 * P]);
+        const double s = wave_sum(v);
+        if (lane == 0) lds[wid * 3 * P + i] = s;
+        __builtin_amdgcn_sched_barrier(0);
     }
-    const double F = LE - ((A0y + A1y) * LGy + (A0z + A1z) * LGz) * inv_dx / (g00 + g01);
-    p1 = p0 + dt * F;
-    const double g11 = sqrt(1.0 + p1 * p1 + qa1);
-    dn = dt_dx * (p0 + p1) / (g01 + g11);
+    __syncthreads();
+    double out = 0.0;
+    const int q = threadIdx.x;
+    if (q < P + 2) {
+#pragma unroll
+        for (int i = 0; i < 3 * P; ++i) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += lds[w * 3 * P + i];
+            const int grp = i / P, ii = i % P;   // 0: cell c, 1: c+1, 2: c-1
+            const int m = (grp == 0 ? P : (grp == 1 ? P + 1 : P - 1)) - q;   // index c + shift - m == c - P + q
+            if (m >= 0 && m < P) out += Q.q[m][ii] * t;
+        }
+    }
+    __syncthreads();
+    return out;
+}
+
+// The sweep.  The block's own-cell coefficients stay in registers; the three
+// cells' records are also staged in LDS, where the rare steps that enter a
+// neighbour cell read them with a per-lane (position-dependent) address.  Each
+// thread carries two particles per iteration so that their dependent FP64
+// chains interleave.
+template <int P>
+struct Own {
+    double ay[P + 1], az[P + 1], eb[P];
+};
+
+template <int P>
+struct LdsRec {   // one cell's coefficients in LDS
+    double ay[P + 1], az[P + 1], eb[P];
+};
+
+struct Lane {
+    double xi0, p0, d, t0, t1, q0, A0y, A0z, g00;
+    int s;
+};
+
+template <int P>
+__device__ __forceinline__ void stage_gather(const Own<P> &o, Lane &L, int c, bool explicit_start, double dt_dx,
+                                             int &flags) {
+    L.t0 = L.xi0 - (double)c;
+    if (!(L.t0 >= 0.0 && L.t0 < 1.0)) { flags |= FLAG_ORDER; L.t0 = 0.5; }
+    L.A0y = horner<P + 1>(o.ay, L.t0);
+    L.A0z = horner<P + 1>(o.az, L.t0);
+    L.q0 = fma(L.p0, L.p0, 1.0);
+    L.g00 = fsqrt(L.q0 + L.A0y * L.A0y + L.A0z * L.A0z);
+    if (explicit_start) L.d = dt_dx * L.p0 * frcp(L.g00);
+    end_point(L.xi0, L.d, c, L.t1, L.s, flags);
+}
+
+// Momentum update and next increment; anycross is wave-uniform.
+template <int P>
+__device__ __forceinline__ void stage_push(const Own<P> &o, const LdsRec<P> *rec, bool anycross, const Lane &L,
+                                           double dt, double dt_dx, double inv_dx, double &p1, double &dn,
+                                           int &flags) {
+    const double t1c = fmin(fmax(L.t1, 0.0), 1.0);
+    double h[P];
+    homog<P - 1>(fmin(L.t0, t1c), fmax(L.t0, t1c), h);
+    double LE = pmean<P>(o.eb, h);
+    double DAy = divdiff<P>(o.ay, h), DAz = divdiff<P>(o.az, h);
+    double A1y, A1z;
+    if (anycross) {
+        // record of the cell holding t1, indexed arithmetically (t1 in (-1, 2))
+        const int r = (int)floor(L.t1) + 1;
+        const LdsRec<P> &nb = rec[r];
+        const double tl = L.t1 - (double)(r - 1);
+        A1y = horner<P + 1>(nb.ay, tl);
+        A1z = horner<P + 1>(nb.az, tl);
+        if (L.s != 0) {
+            // piece inside cell c + s: [0, t1 - 1] or [t1 + 1, 1]
+            double hb[P];
+            homog<P - 1>(L.s > 0 ? 0.0 : tl, L.s > 0 ? tl : 1.0, hb);
+            const double sA = t1c - L.t0, sB = L.t1 - t1c;
+            const double inv = frcp(L.t1 - L.t0);
+            LE = (sA * LE + sB * pmean<P>(nb.eb, hb)) * inv;
+            DAy = (sA * DAy + sB * divdiff<P>(nb.ay, hb)) * inv;
+            DAz = (sA * DAz + sB * divdiff<P>(nb.az, hb)) * inv;
+        }
+    } else {
+        A1y = horner<P + 1>(o.ay, L.t1);
+        A1z = horner<P + 1>(o.az, L.t1);
+    }
+    const double qa1 = A1y * A1y + A1z * A1z;
+    const double g01 = fsqrt(L.q0 + qa1);
+    const double F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
+    p1 = fma(dt, F, L.p0);
+    const double g11 = fsqrt(fma(p1, p1, 1.0) + qa1);
+    dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
     if (!(fabs(dn) < 1.0e300) || !(fabs(p1) < 1.0e300)) flags |= FLAG_NONFINITE;
+}
+
+// Moments of a step from t0 to t1 (end in cell c + s); scale 0 drops it.
+template <int P>
+__device__ __forceinline__ void stage_deposit(Moments<P> &mo, bool anycross, double t0, double t1, int s,
+                                              double scale) {
+    const double t1c = fmin(fmax(t1, 0.0), 1.0);
+    double h[P];
+    homog<P - 1>(fmin(t0, t1c), fmax(t0, t1c), h);
+    const double sA = scale * (t1c - t0);
+#pragma unroll
+    for (int i = 0; i < P; ++i) mo.A[i] = fma(sA, h[i], mo.A[i]);
+    if (anycross) {
+        const double tl = t1 - (double)s;
+        homog<P - 1>(s > 0 ? 0.0 : (s < 0 ? tl : 0.0), s > 0 ? tl : (s < 0 ? 1.0 : 0.0), h);
+        const double sB = scale * (t1 - t1c);
+        const double sr = s > 0 ? sB : 0.0, sl = s < 0 ? sB : 0.0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            mo.R[i] = fma(sr, h[i], mo.R[i]);
+            mo.L[i] = fma(sl, h[i], mo.L[i]);
+        }
+    }
+}
+
+// Has sweep k-1 met the tolerance?  Records kconv if so.
+__device__ __forceinline__ bool prev_converged(DevStatus *st, int k, double dx, double tol, bool writer) {
+    if (k <= 0) return false;
+    const double r = fmax(dbits(st->rx_bits[(k - 1) & 1]) * dx, dbits(st->re_bits[(k - 1) & 1]));
+    if (writer && k - 1 < MAX_HIST) st->res_hist[k - 1] = r;
+    if (r <= tol) {
+        if (writer) { st->kconv = k - 1; st->res = r; }
+        return true;
+    }
+    return false;
 }
 
 template <int P, bool SEIDEL>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
-    __shared__ double lds[MAX_WAVES * (P + 2)];
+    __shared__ double lds[MAX_WAVES * 3 * P];
     __shared__ double ldsm[MAX_WAVES];
     __shared__ int ldsf[MAX_WAVES];
-    const DevStatus *st = a.st;
+    __shared__ LdsRec<P> rec[3];   // cells c-1, c, c+1
+    DevStatus *st = a.st;
     const int item = blockIdx.x;
     if (item >= *a.items.n_items) return;
-    if (!st->gate | st->converged | st->flags) return;
-    const int k = st->k;
+    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    const int k = a.k;
+    if (prev_converged(st, k, a.dx, a.tol, threadIdx.x == 0)) return;
     const double *din = (k & 1) ? a.d1 : a.d0;
     double *dout = (k & 1) ? a.d0 : a.d1;
-    const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
+    const double *coefE = (k & 1) ? a.coefE1 : a.coefE0;
     const bool explicit_start = (k == 0) && a.explicit_start;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
-
-    Window1<P> w;
-    load_window1<P>(w, c, a.ay, a.az, a.en, ek);
-
-    double acc[P + 2];
+    {
+        constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
+        const double *ra = a.coefA + (size_t)(rec_index(c) - 1) * NA;
+        const double *re = coefE + (size_t)(rec_index(c) - 1) * NE;
+        const int t = threadIdx.x;
+        if (t < 3 * NA) {
+            const int r = t / NA, i = t % NA;
+            if (i <= P) rec[r].ay[i] = ra[t];
+            else rec[r].az[i - P - 1] = ra[t];
+        } else if (t < 3 * NA + 3 * NE) {
+            const int u = t - 3 * NA, r = u / NE, i = u % NE;
+            rec[r].eb[i] = re[u];
+        }
+    }
+    Own<P> o1;
+    {
+        const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
+        const double *re = coefE + (size_t)rec_index(c) * RecE<P>::N;
 #pragma unroll
-    for (int q = 0; q < P + 2; ++q) acc[q] = 0.0;
+        for (int i = 0; i <= P; ++i) { o1.ay[i] = ra[i]; o1.az[i] = ra[P + 1 + i]; }
+#pragma unroll
+        for (int i = 0; i < P; ++i) o1.eb[i] = re[i];
+    }
+    __syncthreads();
+    Moments<P> mo;
+#pragma unroll
+    for (int i = 0; i < P; ++i) { mo.A[i] = 0.0; mo.R[i] = 0.0; mo.L[i] = 0.0; }
     double rmax = 0.0;
     int flags = 0;
-    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const double xi0 = a.xi[i];
-        const double p0 = a.p[i];
-        const double dprev = explicit_start ? 0.0 : din[i];
-        double t0 = xi0 - (double)c;
-        if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
-        double dn, p1, dused, dr, lb[P + 2];
-        particle_map<P>(w, t0, p0, dprev, explicit_start, c, xi0, a.dt, a.dt_dx, a.inv_dx, dn, p1, dused,
-                        lb, dr, flags);
-        if (!SEIDEL && explicit_start) a.d0[i] = dused;   // keep d^(0) for a Jacobi commit
-        dout[i] = dn;
-        rmax = fmax(rmax, fabs(dn - dused));
+    const int B = blockDim.x;
+    for (int ia = beg + threadIdx.x; ia < end; ia += B) {
+        Lane La;
+        La.xi0 = a.xi[ia];
+        La.p0 = a.p[ia];
+        La.d = explicit_start ? 0.0 : din[ia];
+        stage_gather<P>(o1, La, c, explicit_start, a.dt_dx, flags);
+        const bool cross1 = __ballot(La.s != 0) != 0;
+        double pa, dna;
+        stage_push<P>(o1, rec, cross1, La, a.dt, a.dt_dx, a.inv_dx, pa, dna, flags);
+        if (!SEIDEL && explicit_start) a.d0[ia] = La.d;   // keep d^(0) for a Jacobi commit
+        dout[ia] = dna;
+        rmax = fmax(rmax, fabs(dna - La.d));
         if (SEIDEL) {
-            double t1;
-            int s;
-            end_point(xi0, dn, c, t1, s, flags);
-            line_mean_v1<P>(t0, t1, s, lb);
-            dr = t1 - t0;
+            double ta;
+            int sa;
+            end_point(La.xi0, dna, c, ta, sa, flags);
+            stage_deposit<P>(mo, __ballot(sa != 0) != 0, La.t0, ta, sa, 1.0);
+        } else {
+            stage_deposit<P>(mo, cross1, La.t0, La.t1, La.s, 1.0);
         }
-#pragma unroll
-        for (int q = 0; q < P + 2; ++q) acc[q] += dr * lb[q];
     }
-    const double tot = block_sum_slot<P + 2>(acc, lds);
+    const double tot = moments_to_slots<P>(mo, lds);
     if ((int)threadIdx.x < P + 2) a.part[(size_t)item * (P + 2) + threadIdx.x] = tot;
     block_max_or(rmax, flags, ldsm, ldsf);
     if (threadIdx.x == 0) {
-        atomicMax(&a.st->rx_bits, bitsd(rmax));
-        if (flags) atomicOr(&a.st->flags, flags);
+        atomicMax(&st->rx_bits[k & 1], bitsd(rmax));
+        if (flags) atomicOr(&st->flags, flags);
     }
 }
 
-// Assemble the current of V1 index j from the item partials (fixed order:
-// cells j-1 .. j+P ascending, items of a cell ascending).
-template <int P>
-__device__ __forceinline__ double assemble_current(const ItemList &it, const double *part, int j, int M) {
-    double s = 0.0;
+// Partial sums of the items of cell c (usually one item), slot by slot.
+template <int NS>
+__device__ __forceinline__ void cell_partials(const ItemList &it, const double *part, int c, double (&v)[NS]) {
 #pragma unroll
-    for (int r = 0; r < P + 2; ++r) {
-        const int c = imod(j - 1 + r, M);
-        const int slot = P + 1 - r;   // V1 index c - P + slot == j (unwrapped)
-        const int i0 = it.cell_first[c], i1 = it.cell_first[c + 1];
-        for (int i = i0; i < i1; ++i) s += part[(size_t)i * (P + 2) + slot];
+    for (int q = 0; q < NS; ++q) v[q] = 0.0;
+    const int i0 = it.cell_first[c], i1 = it.cell_first[c + 1];
+    for (int i = i0; i < i1; ++i) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) v[q] += part[(size_t)i * NS + q];
     }
-    return s;
 }
 
-// Field update of one sweep and the convergence test.  Block b produces
-// e^(k+1) on cells [256 b, 256 b + 256); the last block to finish decides.
+// sum_i taps[i] S[q0 + ntaps - 1 - i] with four independent accumulators.
+__device__ __forceinline__ double conv4(const double *taps, int ntaps, const double *S) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 3 < ntaps; i += 4) {
+        a0 = fma(taps[i], S[ntaps - 1 - i], a0);
+        a1 = fma(taps[i + 1], S[ntaps - 2 - i], a1);
+        a2 = fma(taps[i + 2], S[ntaps - 3 - i], a2);
+        a3 = fma(taps[i + 3], S[ntaps - 4 - i], a3);
+    }
+    for (; i < ntaps; ++i) a0 = fma(taps[i], S[ntaps - 1 - i], a0);
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Field update of sweep k and the E-records of the next ebar.  Block b
+// produces e^(k+1) on cells [256 b - P + 1, 256 b + 256) (the first P - 1 only
+// to form the records).  The item partials are first summed per cell into LDS
+// (two dependent global reads), the current S assembled from them, and the
+// M1 inverse applied as a convolution.
 template <int P>
 __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
-    extern __shared__ double S[];
+    extern __shared__ double smem[];
     __shared__ double ldsm[MAX_WAVES];
     __shared__ int ldsf[MAX_WAVES];
-    __shared__ int last;
+    constexpr int NS = P + 2;
     DevStatus *st = a.st;
-    if (!st->gate | st->converged | st->flags) return;
-    const int k = st->k;
+    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    const int k = a.k;
     const int M = a.M;
-    const int j0 = blockIdx.x * 256;
+    const int j0 = blockIdx.x * 256 - (P - 1);   // first cell computed
+    const int nout = 256 + P - 1;
     const int mhi = a.mlo + a.ntaps - 1;
-    const int len = 256 + a.ntaps - 1;
-    for (int idx = threadIdx.x; idx < len; idx += blockDim.x) {
-        const int j = imod(j0 - mhi + idx, M);
-        S[idx] = assemble_current<P>(a.items, a.part, j, M);
+    const int slen = nout + a.ntaps - 1;         // S on cells [j0 - mhi, j0 - mhi + slen)
+    const int clo = j0 - mhi - 1;                // S_j needs the partials of cells j-1 .. j+P
+    const int clen = slen + P + 1;
+    double *cp = smem;
+    double *S = cp + (size_t)clen * NS;
+    double *enl = S + slen;
+    for (int t = threadIdx.x; t < clen; t += blockDim.x) {
+        double v[NS];
+        cell_partials<NS>(a.items, a.part, imod(clo + t, M), v);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < slen; t += blockDim.x) {
+        double sum = 0.0;
+#pragma unroll
+        for (int r = 0; r < NS; ++r) sum += cp[(t + r) * NS + (P + 1 - r)];   // cell (j-1+r): slot P+1-r
+        S[t] = sum;
     }
     __syncthreads();
     const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
     double *eout = (k & 1) ? a.ek0 : a.ek1;
+    double *Eout = ((k + 1) & 1) ? a.coefE1 : a.coefE0;
     double re = 0.0;
     int flags = 0;
-    const int j = j0 + threadIdx.x;
-    if (j < M) {
-        double conv = 0.0;
-        for (int i = 0; i < a.ntaps; ++i) conv += a.taps[i] * S[threadIdx.x + mhi - (a.mlo + i)];
+    for (int q = threadIdx.x; q < nout; q += blockDim.x) {
+        const int jj = j0 + q;
+        const int j = imod(jj, M);
+        // S_{j - m} for m = mlo + i sits at S[q + mhi - m]
+        const double conv = conv4(a.taps, a.ntaps, S + q);
         const double enew = a.en[j + HALO] - a.w * conv;
-        store_padded(eout, M, j, enew);
-        re = fabs(enew - ek[j + HALO]);
-        if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
+        enl[q] = enew;
+        if (q >= P - 1 && jj < M) {
+            store_padded(eout, M, j, enew);
+            re = fmax(re, fabs(enew - ek[j + HALO]));
+            if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
+        }
+    }
+    __syncthreads();
+    {
+        const int q = threadIdx.x + P - 1;
+        const int j = j0 + q;
+        if (j < M) {
+            double r[P];
+            make_recE<P>([&](int jj) { return 0.5 * (a.en[imod(jj, M) + HALO] + enl[jj - j0]); }, j, r);
+            for (int i = 0; i < P; ++i) store_record(Eout, M, j, RecE<P>::N, i, r[i]);
+        }
     }
     block_max_or(re, flags, ldsm, ldsf);
     if (threadIdx.x == 0) {
-        atomicMax(&st->re_bits, bitsd(re));
+        atomicMax(&st->re_bits[k & 1], bitsd(re));
         if (flags) atomicOr(&st->flags, flags);
-        __threadfence();
-        const unsigned ticket = atomicAdd(&st->counter, 1u);
-        last = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        __threadfence();
-        const double rx = dbits(atomicAdd(&st->rx_bits, 0ull)) * a.dx;
-        const double rf = dbits(atomicAdd(&st->re_bits, 0ull));
-        const double r = fmax(rx, rf);
-        st->res = r;
-        if (k < MAX_HIST) st->res_hist[k] = r;
-        if (r <= a.tol && st->flags == 0) {
-            st->converged = 1;
-            st->kconv = k;
+        if (blockIdx.x == 0) {   // clear the slots sweep k+1 accumulates into
+            st->rx_bits[(k + 1) & 1] = 0ull;
+            st->re_bits[(k + 1) & 1] = 0ull;
         }
-        st->rx_bits = 0ull;
-        st->re_bits = 0ull;
-        st->counter = 0u;
-        __threadfence();
-        st->k = k + 1;
+    }
+}
+
+// Records of a substep start: A-records of a_perp and E-records of e.
+template <int P>
+__global__ void __launch_bounds__(256) k_prep_records(const DevStatus *st, const double *ay, const double *az,
+                                                      const double *e, double *coefA, double *coefE, int M) {
+    if (st && !st->gate) return;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= M) return;
+    double ry[P + 1], rz[P + 1];
+    make_recA<P>(ay, az, c, ry, rz);
+    for (int i = 0; i <= P; ++i) {
+        store_record(coefA, M, c, RecA<P>::N, i, ry[i]);
+        store_record(coefA, M, c, RecA<P>::N, P + 1 + i, rz[i]);
+    }
+    if (coefE) {
+        double r[P];
+        make_recE<P>([&](int jj) { return e[jj + HALO]; }, c, r);
+        for (int i = 0; i < P; ++i) store_record(coefE, M, c, RecE<P>::N, i, r[i]);
     }
 }
 
@@ -235,28 +489,34 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
 // c'+1], each group in the old order (a stable three-way merge).
 
 struct CommitPick {
-    const double *d;     // increment to commit
-    const double *ek;    // e iterate used in ebar for the momentum
-    const double *enew;  // e_x^{n+1}
+    const double *d;       // increment to commit
+    const double *coefE;   // ebar records for the committed momentum
+    const double *enew;    // e_x^{n+1}
 };
 
-__device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a) {
-    const int kc = a.st->kconv;
+__device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a, int kc) {
     CommitPick r;
-    const double *e_after = ((kc + 1) & 1) ? a.ek1 : a.ek0;   // e^(kc+1)
-    r.enew = e_after;
+    r.enew = ((kc + 1) & 1) ? a.ek1 : a.ek0;   // e^(kc+1)
     if (a.seidel) {
-        r.d = ((kc + 1) & 1) ? a.d1 : a.d0;    // delta^(kc+1)
-        r.ek = e_after;
+        r.d = ((kc + 1) & 1) ? a.d1 : a.d0;     // delta^(kc+1)
+        r.coefE = ((kc + 1) & 1) ? a.coefE1 : a.coefE0;
     } else {
-        r.d = (kc & 1) ? a.d1 : a.d0;          // delta^(kc)
-        r.ek = kc == 0 ? a.en : ((kc & 1) ? a.ek1 : a.ek0);
+        r.d = (kc & 1) ? a.d1 : a.d0;           // delta^(kc)
+        r.coefE = (kc & 1) ? a.coefE1 : a.coefE0;
     }
     return r;
 }
 
 __device__ __forceinline__ bool commit_enabled(const DevStatus *st) {
-    return st->gate && st->converged && !st->committed && st->flags == 0;
+    return st->gate && st->kconv >= 0 && !st->committed && st->flags == 0;
+}
+
+// Converged sweep index for the commit, making the test of the last enqueued
+// sweep if no later sweep made it; -1 if the commit must not run.
+__device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, double dx, double tol, bool writer) {
+    if (!st->gate || st->flags || st->committed) return -1;
+    if (st->kconv >= 0) return st->kconv;
+    return prev_converged(st, nsweeps, dx, tol, writer) ? nsweeps - 1 : -1;
 }
 
 __device__ __forceinline__ int mover_type(double xi0, double d, int c) {
@@ -267,8 +527,10 @@ __device__ __forceinline__ int mover_type(double xi0, double d, int c) {
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_count(CommitIArgs a) {
     __shared__ int lds[MAX_WAVES * 3];
     const int item = blockIdx.x;
-    if (item >= *a.items.n_items || !commit_enabled(a.st)) return;
-    const CommitPick pk = commit_pick(a);
+    const int kc = settle_last(a.st, a.nsweeps, a.dx, a.tol, item == 0 && threadIdx.x == 0);
+    if (kc < 0) return;
+    if (item >= *a.items.n_items) return;
+    const CommitPick pk = commit_pick(a, kc);
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     int n0 = 0, n1 = 0, n2 = 0;
@@ -325,7 +587,7 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     build_items(ncount, a.nstart, M, a.chunk, a.N, a.items_next, lds);
     __syncthreads();
     // e_x^{n+1}
-    const CommitPick pk = commit_pick(a);
+    const CommitPick pk = commit_pick(a, a.st->kconv);
     for (int idx = threadIdx.x; idx < M + 2 * HALO; idx += blockDim.x) a.ex_next[idx] = pk.enew[idx];
 }
 
@@ -334,12 +596,12 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
     __shared__ int wc[MAX_WAVES][3];
     const int item = blockIdx.x;
     if (item >= *a.items.n_items || !commit_enabled(a.st)) return;
-    const CommitPick pk = commit_pick(a);
+    const CommitPick pk = commit_pick(a, a.st->kconv);
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int M = a.M;
-    Window1<P> w;
-    load_window1<P>(w, c, a.ay, a.az, a.en, pk.ek);
+    Coef1<P> kc;
+    load_coef1<P>(kc, c, a.coefA, pk.coefE);
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = (blockDim.x + WAVE - 1) / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
@@ -356,10 +618,8 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
             const double p0 = a.cur.p[i];
             const double d = pk.d[i];
             pid = a.cur.id[i];
-            double t0 = xi0 - (double)c;
-            if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
-            double dn, dused, dr, lb[P + 2];
-            particle_map<P>(w, t0, p0, d, false, c, xi0, a.dt, a.dt_dx, a.inv_dx, dn, p1, dused, lb, dr, flags);
+            const MapOut o = particle_map<P>(kc, xi0, c, p0, d, false, a.dt, a.dt_dx, a.inv_dx, flags);
+            p1 = o.p1;
             t = mover_type(xi0, d, c);
             xin = xi0 + d;
             if (xin >= (double)M) xin -= (double)M;
@@ -393,18 +653,17 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
 }
 
 __global__ void k_mark_committed(DevStatus *st) {
-    if (st->converged && !st->committed && st->flags == 0 && st->gate) st->committed = 1;
+    if (st->kconv >= 0 && !st->committed && st->flags == 0 && st->gate) st->committed = 1;
 }
 
 __global__ void k_begin(DevStatus *st, const DevStatus *gate) {
-    st->rx_bits = 0ull;
-    st->re_bits = 0ull;
-    st->k = 0;
-    st->converged = 0;
+    st->rx_bits[0] = 0ull;
+    st->rx_bits[1] = 0ull;
+    st->re_bits[0] = 0ull;
+    st->re_bits[1] = 0ull;
     st->kconv = -1;
     st->committed = 0;
     st->flags = 0;
-    st->counter = 0u;
     st->fp32_sweeps = 0;
     st->res = 0.0;
     st->gate = gate ? gate->committed : 1;   // 0: every kernel of the substep skips
@@ -422,10 +681,20 @@ void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, cons
 }
 
 void launch_field_I(int P, int grid, hipStream_t s, const FieldIArgs &a) {
-    const size_t lds = sizeof(double) * (256 + a.ntaps);
+    const int slen = 256 + P - 1 + a.ntaps - 1;
+    const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + 256 + P);
 #define ECPIC_F(PP) case PP: hipLaunchKernelGGL((k_field_I<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F(2) ECPIC_F(3) ECPIC_F(4) ECPIC_F(5) }
 #undef ECPIC_F
+}
+
+void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double *ay, const double *az,
+                         const double *e, double *coefA, double *coefE, int M) {
+    const int grid = (M + 255) / 256;
+#define ECPIC_PR(PP) \
+    case PP: hipLaunchKernelGGL((k_prep_records<PP>), dim3(grid), dim3(256), 0, s, st, ay, az, e, coefA, coefE, M); break;
+    switch (P) { ECPIC_PR(2) ECPIC_PR(3) ECPIC_PR(4) ECPIC_PR(5) }
+#undef ECPIC_PR
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
