@@ -41,6 +41,44 @@ __device__ __forceinline__ int wave_isum(int v) {
     return v;
 }
 
+// Cross-lane moves by DPP (no LDS).  Rows disabled by ROWMASK read as 0.
+template <int CTRL, int ROWMASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane
+// (quad swaps, half-row and row mirrors, then the two row broadcasts that leave
+// the total in lane 63).  All lanes must be active.
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_d<0xB1>(v);         // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);         // quad_perm [2,3,0,1]
+    v += dpp_d<0x141>(v);        // row_half_mirror
+    v += dpp_d<0x140>(v);        // row_mirror
+    v += dpp_d<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp_d<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+    return readlane_d(v, WAVE - 1);
+}
+
+// Max over the wave (arguments >= 0), returned to every lane.
+__device__ __forceinline__ double wave_max_dpp(double v) {
+    v = fmax(v, dpp_d<0xB1>(v));
+    v = fmax(v, dpp_d<0x4E>(v));
+    v = fmax(v, dpp_d<0x141>(v));
+    v = fmax(v, dpp_d<0x140>(v));
+    v = fmax(v, dpp_d<0x142, 0xA>(v));
+    v = fmax(v, dpp_d<0x143, 0xC>(v));
+    return readlane_d(v, WAVE - 1);
+}
+
 // Sum NV per-thread values over the block in a fixed order; thread t < NV gets
 // total t in out.  lds must hold MAX_WAVES * NV doubles.
 template <int NV>

@@ -35,6 +35,7 @@ enum : int32_t { FLAG_NONFINITE = 1, FLAG_CFL = 2, FLAG_ORDER = 4 };
 // of knowing the outcome and synchronise once per step.
 struct DevStatus {
     unsigned long long rx_bits[2];   // max |d^(k+1) - d^(k)| (cell units) of sweep k, slot k&1, as bits
+                                     // (gathered from the sweep's partials by the field kernel)
     unsigned long long re_bits[2];   // max field increment of sweep k, slot k&1, as bits
     int32_t kconv;                   // sweep index that met the tolerance, -1 before
     int32_t committed;
@@ -66,7 +67,7 @@ struct SweepIArgs {
     ItemList items;
     const double *coefA;           // A-records of a_perp^n
     const double *coefE0, *coefE1; // E-records of ebar^(k) = (e^n + e^(k))/2, by parity of k
-    double *part;                  // [max_items][deg+2]
+    double *part;                  // [max_items][waves per item][deg+4]: P+2 current slots, residual, flags
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
@@ -85,6 +86,7 @@ struct FieldIArgs {
     double w;
     int32_t M;
     int32_t k;
+    int32_t wpi;                   // waves per item of the sweep (partials per item)
 };
 
 struct CommitIArgs {
@@ -111,7 +113,7 @@ struct SweepIIArgs {
     ItemList items;
     const double *coefAn;                     // A-records of a_perp^n
     const double *coefAk0, *coefAk1;          // A-records of a^(k) = a^n - dt/2 (e^n + e^(k)), by parity
-    double *part;                             // [max_items][2 (deg+1)]
+    double *part;                             // [max_items][waves per item][2 (deg+1)]
     DevStatus *st;
     double tol;
     int32_t k;
@@ -131,6 +133,7 @@ struct FieldIIArgs {
     double half_dt;
     int32_t M;
     int32_t k;
+    int32_t wpi;                              // waves per item of the particle pass
 };
 
 }  // namespace ecpic

@@ -23,12 +23,12 @@
 
 namespace ecpic {
 void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, const SweepIArgs &a);
-void launch_field_I(int P, int grid, hipStream_t s, const FieldIArgs &a);
+void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a);
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a);
 void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s);
 void launch_mark(DevStatus *st, hipStream_t s);
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
-void launch_field_II(int P, int grid, hipStream_t s, const FieldIIArgs &a);
+void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a);
 void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double *ay, const double *az,
                          const double *e, double *coefA, double *coefE, int M);
 void launch_prep_II(int P, hipStream_t s, const DevStatus *st, const double *ayn, const double *azn,
@@ -294,11 +294,12 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.st = c->stI;
     f.w = c->w;
     f.M = c->M;
-    const int gridp = particle_grid(c, true), gridf = (c->M + 255) / 256;
+    f.wpi = c->block / 64;
+    const int gridp = particle_grid(c, true);
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kI++;
         timed(c, "sweep_I", [&] { launch_sweep_I(c->P, c->seidel, gridp, c->block, c->stream, a); });
-        timed(c, "field_I", [&] { launch_field_I(c->P, gridf, c->stream, f); });
+        timed(c, "field_I", [&] { launch_field_I(c->P, c->M, c->stream, f); });
     }
 }
 
@@ -387,11 +388,12 @@ void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
     f.coef = c->dt * c->w / c->dx;
     f.half_dt = 0.5 * c->dt;
     f.M = c->M;
-    const int gridp = particle_grid(c, v.exact), gridf = (c->M + 255) / 256;
+    f.wpi = c->block / 64;
+    const int gridp = particle_grid(c, v.exact);
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kII++;
         timed(c, "sweep_II", [&] { launch_sweep_II(c->P, gridp, c->block, c->stream, a); });
-        timed(c, "field_II", [&] { launch_field_II(c->P, gridf, c->stream, f); });
+        timed(c, "field_II", [&] { launch_field_II(c->P, c->M, c->stream, f); });
     }
 }
 
@@ -535,7 +537,8 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->tot, (size_t)M * 3);
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
-    rc |= dalloc(&c->part, (size_t)c->max_items * 2 * (c->P + 1));
+    // per item and wave: Subsystem I P+4 values, Subsystem II 2 (P+1)
+    rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 1), c->P + 4));
     rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M);
     const size_t nrec = (size_t)(M + 2);
     rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAn, nrec * 2 * (c->P + 1));

@@ -138,46 +138,36 @@ __device__ __forceinline__ MapOut particle_map(const Coef1<P> &k, double xi0, in
     return o;
 }
 
-// Block sum of the moments and conversion to the P+2 V1 slots of the item
-// (slot q <-> V1 index c - P + q); thread q < P+2 returns slot q.
-// Block sum of the moments and conversion to the P+2 V1 slots of the item
-// (slot q <-> V1 index c - P + q); thread q < P+2 returns slot q.  The 3P wave
-// reductions are kept apart by scheduling barriers so they do not all stay
-// live at once.
+// Wave sum of the moments and conversion to the P+2 V1 slots of the wave's
+// particles (slot q <-> V1 index c - P + q); lane q < P+2 returns slot q.
 template <int P>
-__device__ __forceinline__ double moments_to_slots(const Moments<P> &mo, double *lds) {
+__device__ __forceinline__ double moments_to_slots(const Moments<P> &mo) {
     constexpr Pieces<P - 1> Q{};
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const int nw = (blockDim.x + WAVE - 1) / WAVE;
+    double t[3 * P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        t[i] = wave_sum_dpp(mo.A[i]);
+        t[P + i] = wave_sum_dpp(mo.R[i]);
+        t[2 * P + i] = wave_sum_dpp(mo.L[i]);
+    }
+    const int q = threadIdx.x & (WAVE - 1);
+    double out = 0.0;
 #pragma unroll
     for (int i = 0; i < 3 * P; ++i) {
-        const double v = i < P ? mo.A[i] : (i < 2 * P ? mo.R[i - P] : mo.L[i - 2 * P]);
-        const double s = wave_sum(v);
-        if (lane == 0) lds[wid * 3 * P + i] = s;
-        __builtin_amdgcn_sched_barrier(0);
+        const int grp = i / P, ii = i % P;   // 0: cell c, 1: c+1, 2: c-1
+        const int m = (grp == 0 ? P : (grp == 1 ? P + 1 : P - 1)) - q;   // index c + shift - m == c - P + q
+        out += (m >= 0 && m < P) ? Q.q[m < 0 ? 0 : (m >= P ? P - 1 : m)][ii] * t[i] : 0.0;
     }
-    __syncthreads();
-    double out = 0.0;
-    const int q = threadIdx.x;
-    if (q < P + 2) {
-#pragma unroll
-        for (int i = 0; i < 3 * P; ++i) {
-            double t = 0.0;
-            for (int w = 0; w < nw; ++w) t += lds[w * 3 * P + i];
-            const int grp = i / P, ii = i % P;   // 0: cell c, 1: c+1, 2: c-1
-            const int m = (grp == 0 ? P : (grp == 1 ? P + 1 : P - 1)) - q;   // index c + shift - m == c - P + q
-            if (m >= 0 && m < P) out += Q.q[m][ii] * t;
-        }
-    }
-    __syncthreads();
     return out;
 }
 
 // The sweep.  The block's own-cell coefficients stay in registers; the three
 // cells' records are also staged in LDS, where the rare steps that enter a
-// neighbour cell read them with a per-lane (position-dependent) address.  Each
-// thread carries two particles per iteration so that their dependent FP64
-// chains interleave.
+// neighbour cell read them with a per-lane (position-dependent) address.  The
+// waves of a block share only that staging: each wave takes every nw-th row of
+// 64 particles of the item, loads the next row while it computes the current
+// one, and writes its own partial slots (P+2 current sums, its residual max and
+// its error flags), which the field kernel assembles per cell.
 template <int P>
 struct Own {
     double ay[P + 1], az[P + 1], eb[P];
@@ -284,9 +274,6 @@ __device__ __forceinline__ bool prev_converged(DevStatus *st, int k, double dx, 
 
 template <int P, bool SEIDEL>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
-    __shared__ double lds[MAX_WAVES * 3 * P];
-    __shared__ double ldsm[MAX_WAVES];
-    __shared__ int ldsf[MAX_WAVES];
     __shared__ LdsRec<P> rec[3];   // cells c-1, c, c+1
     DevStatus *st = a.st;
     const int item = blockIdx.x;
@@ -300,6 +287,18 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     const bool explicit_start = (k == 0) && a.explicit_start;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    // first row of this wave (clamped index: lanes past the end recompute the
+    // item's last particle and discard it)
+    int ia = beg + wid * WAVE + lane;
+    double nx, np, nd;
+    {
+        const int il = min(ia, end - 1);
+        nx = a.xi[il];
+        np = a.p[il];
+        nd = explicit_start ? 0.0 : din[il];
+    }
     {
         constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
         const double *ra = a.coefA + (size_t)(rec_index(c) - 1) * NA;
@@ -329,35 +328,45 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     for (int i = 0; i < P; ++i) { mo.A[i] = 0.0; mo.R[i] = 0.0; mo.L[i] = 0.0; }
     double rmax = 0.0;
     int flags = 0;
-    const int B = blockDim.x;
-    for (int ia = beg + threadIdx.x; ia < end; ia += B) {
+    const int stride = nw * WAVE;
+    for (int row = beg + wid * WAVE; row < end; row += stride, ia += stride) {
         Lane La;
-        La.xi0 = a.xi[ia];
-        La.p0 = a.p[ia];
-        La.d = explicit_start ? 0.0 : din[ia];
+        La.xi0 = nx;
+        La.p0 = np;
+        La.d = nd;
+        const bool valid = ia < end;
+        if (row + stride < end) {   // prefetch the next row
+            const int il = min(ia + stride, end - 1);
+            nx = a.xi[il];
+            np = a.p[il];
+            nd = explicit_start ? 0.0 : din[il];
+        }
         stage_gather<P>(o1, La, c, explicit_start, a.dt_dx, flags);
         const bool cross1 = __ballot(La.s != 0) != 0;
         double pa, dna;
         stage_push<P>(o1, rec, cross1, La, a.dt, a.dt_dx, a.inv_dx, pa, dna, flags);
-        if (!SEIDEL && explicit_start) a.d0[ia] = La.d;   // keep d^(0) for a Jacobi commit
-        dout[ia] = dna;
-        rmax = fmax(rmax, fabs(dna - La.d));
+        if (valid) {
+            if (!SEIDEL && explicit_start) a.d0[ia] = La.d;   // keep d^(0) for a Jacobi commit
+            dout[ia] = dna;
+            rmax = fmax(rmax, fabs(dna - La.d));
+        }
+        const double w = valid ? 1.0 : 0.0;
         if (SEIDEL) {
             double ta;
             int sa;
             end_point(La.xi0, dna, c, ta, sa, flags);
-            stage_deposit<P>(mo, __ballot(sa != 0) != 0, La.t0, ta, sa, 1.0);
+            stage_deposit<P>(mo, __ballot(sa != 0) != 0, La.t0, ta, sa, w);
         } else {
-            stage_deposit<P>(mo, cross1, La.t0, La.t1, La.s, 1.0);
+            stage_deposit<P>(mo, cross1, La.t0, La.t1, La.s, w);
         }
     }
-    const double tot = moments_to_slots<P>(mo, lds);
-    if ((int)threadIdx.x < P + 2) a.part[(size_t)item * (P + 2) + threadIdx.x] = tot;
-    block_max_or(rmax, flags, ldsm, ldsf);
-    if (threadIdx.x == 0) {
-        atomicMax(&st->rx_bits[k & 1], bitsd(rmax));
-        if (flags) atomicOr(&st->flags, flags);
-    }
+    const double slot = moments_to_slots<P>(mo);
+    rmax = wave_max_dpp(rmax);
+    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
+    double *out = a.part + ((size_t)item * nw + wid) * (P + 4);
+    if (lane < P + 2) out[lane] = slot;
+    else if (lane == P + 2) out[lane] = rmax;
+    else if (lane == P + 3) out[lane] = (double)fl;
 }
 
 // Partial sums of the items of cell c (usually one item), slot by slot.
@@ -372,47 +381,63 @@ __device__ __forceinline__ void cell_partials(const ItemList &it, const double *
     }
 }
 
-// sum_i taps[i] S[q0 + ntaps - 1 - i] with four independent accumulators.
-__device__ __forceinline__ double conv4(const double *taps, int ntaps, const double *S) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = 0;
-    for (; i + 3 < ntaps; i += 4) {
-        a0 = fma(taps[i], S[ntaps - 1 - i], a0);
-        a1 = fma(taps[i + 1], S[ntaps - 2 - i], a1);
-        a2 = fma(taps[i + 2], S[ntaps - 3 - i], a2);
-        a3 = fma(taps[i + 3], S[ntaps - 4 - i], a3);
+// Sum of the wave partials of cell c (its items times wpi waves each): the P+2
+// current slots, the max of the residuals and the OR of the flags.
+template <int P>
+__device__ __forceinline__ void cell_partials_I(const ItemList &it, const double *part, int c, int wpi,
+                                                double (&v)[P + 2], double &rx, int &flags) {
+#pragma unroll
+    for (int q = 0; q < P + 2; ++q) v[q] = 0.0;
+    const int u0 = it.cell_first[c] * wpi, u1 = it.cell_first[c + 1] * wpi;
+    for (int u = u0; u < u1; ++u) {
+        const double *w = part + (size_t)u * (P + 4);
+#pragma unroll
+        for (int q = 0; q < P + 2; ++q) v[q] += w[q];
+        rx = fmax(rx, w[P + 2]);
+        flags |= (int)w[P + 3];
     }
-    for (; i < ntaps; ++i) a0 = fma(taps[i], S[ntaps - 1 - i], a0);
-    return (a0 + a1) + (a2 + a3);
 }
 
 // Field update of sweep k and the E-records of the next ebar.  Block b
-// produces e^(k+1) on cells [256 b - P + 1, 256 b + 256) (the first P - 1 only
-// to form the records).  The item partials are first summed per cell into LDS
-// (two dependent global reads), the current S assembled from them, and the
-// M1 inverse applied as a convolution.
+// computes e^(k+1) on the FIELD_OUT cells starting at b * TILE - (P - 1) (the
+// first P - 1 only to form the records of cells b * TILE .. b * TILE + TILE - 1).
+// The wave partials are summed per cell into LDS, the current S assembled from
+// them, and the M1 inverse applied as a convolution: four lanes share an output,
+// each taking every fourth tap, and their sums are combined in a fixed order.
+constexpr int FIELD_OUT = 64;
+
 template <int P>
 __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     extern __shared__ double smem[];
-    __shared__ double ldsm[MAX_WAVES];
+    __shared__ double ldsm[MAX_WAVES], ldsx[MAX_WAVES];
     __shared__ int ldsf[MAX_WAVES];
     constexpr int NS = P + 2;
+    constexpr int TILE = FIELD_OUT - (P - 1);
     DevStatus *st = a.st;
     if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
     const int M = a.M;
-    const int j0 = blockIdx.x * 256 - (P - 1);   // first cell computed
-    const int nout = 256 + P - 1;
+    const int j0 = blockIdx.x * TILE - (P - 1);   // first cell computed
     const int mhi = a.mlo + a.ntaps - 1;
-    const int slen = nout + a.ntaps - 1;         // S on cells [j0 - mhi, j0 - mhi + slen)
-    const int clo = j0 - mhi - 1;                // S_j needs the partials of cells j-1 .. j+P
+    const int slen = FIELD_OUT + a.ntaps - 1;     // S on cells [j0 - mhi, j0 - mhi + slen)
+    const int clo = j0 - mhi - 1;                 // S_j needs the partials of cells j-1 .. j+P
     const int clen = slen + P + 1;
     double *cp = smem;
     double *S = cp + (size_t)clen * NS;
-    double *enl = S + slen;
+    double *tp = S + slen;
+    double *enl = tp + a.ntaps;
+    const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
+    // loads that do not depend on the partials: this quad's output cell
+    const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
+    const int jq = j0 + quad, jqm = imod(jq, M);
+    const double en_q = a.en[jqm + HALO];
+    const double ek_q = ek[jqm + HALO];
+    for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
+    double rx = 0.0;
+    int flags = 0;
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         double v[NS];
-        cell_partials<NS>(a.items, a.part, imod(clo + t, M), v);
+        cell_partials_I<P>(a.items, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
 #pragma unroll
         for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
     }
@@ -424,39 +449,60 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         S[t] = sum;
     }
     __syncthreads();
-    const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
     double *eout = (k & 1) ? a.ek0 : a.ek1;
     double *Eout = ((k + 1) & 1) ? a.coefE1 : a.coefE0;
     double re = 0.0;
-    int flags = 0;
-    for (int q = threadIdx.x; q < nout; q += blockDim.x) {
-        const int jj = j0 + q;
-        const int j = imod(jj, M);
-        // S_{j - m} for m = mlo + i sits at S[q + mhi - m]
-        const double conv = conv4(a.taps, a.ntaps, S + q);
-        const double enew = a.en[j + HALO] - a.w * conv;
-        enl[q] = enew;
-        if (q >= P - 1 && jj < M) {
-            store_padded(eout, M, j, enew);
-            re = fmax(re, fabs(enew - ek[j + HALO]));
-            if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
+    {
+        // S_{j - m} for m = mlo + i sits at S[quad + mhi - m] = S[quad + ntaps - 1 - i]
+        const double *Sq = S + quad + a.ntaps - 1;
+        double acc0 = 0.0, acc1 = 0.0;
+        int i = ql;
+        for (; i + 4 < a.ntaps; i += 8) {
+            acc0 = fma(tp[i], Sq[-i], acc0);
+            acc1 = fma(tp[i + 4], Sq[-i - 4], acc1);
+        }
+        if (i < a.ntaps) acc0 = fma(tp[i], Sq[-i], acc0);
+        double conv = acc0 + acc1;
+        conv += dpp_d<0xB1>(conv);   // quad_perm [1,0,3,2]
+        conv += dpp_d<0x4E>(conv);   // quad_perm [2,3,0,1]
+        const double enew = en_q - a.w * conv;
+        if (ql == 0) {
+            enl[quad] = enew;
+            if (quad >= P - 1 && jq < M) {
+                store_padded(eout, M, jqm, enew);
+                re = fabs(enew - ek_q);
+                if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
+            }
         }
     }
     __syncthreads();
     {
         const int q = threadIdx.x + P - 1;
         const int j = j0 + q;
-        if (j < M) {
+        if (q < FIELD_OUT && j < M) {
             double r[P];
             make_recE<P>([&](int jj) { return 0.5 * (a.en[imod(jj, M) + HALO] + enl[jj - j0]); }, j, r);
             for (int i = 0; i < P; ++i) store_record(Eout, M, j, RecE<P>::N, i, r[i]);
         }
     }
-    block_max_or(re, flags, ldsm, ldsf);
+    re = wave_max(re);
+    rx = wave_max(rx);
+    flags = wave_or(flags);
+    {
+        const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+        if (lane == 0) { ldsm[wid] = re; ldsx[wid] = rx; ldsf[wid] = flags; }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) {
+            re = fmax(re, ldsm[w]);
+            rx = fmax(rx, ldsx[w]);
+            flags |= ldsf[w];
+        }
         atomicMax(&st->re_bits[k & 1], bitsd(re));
+        atomicMax(&st->rx_bits[k & 1], bitsd(rx));
         if (flags) atomicOr(&st->flags, flags);
-        if (blockIdx.x == 0) {   // clear the slots sweep k+1 accumulates into
+        if (blockIdx.x == 0) {   // clear the slots field kernel k+1 accumulates into
             st->rx_bits[(k + 1) & 1] = 0ull;
             st->re_bits[(k + 1) & 1] = 0ull;
         }
@@ -680,9 +726,10 @@ void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, cons
 #undef ECPIC_SW
 }
 
-void launch_field_I(int P, int grid, hipStream_t s, const FieldIArgs &a) {
-    const int slen = 256 + P - 1 + a.ntaps - 1;
-    const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + 256 + P);
+void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
+    const int grid = (M + FIELD_OUT - (P - 1) - 1) / (FIELD_OUT - (P - 1));
+    const int slen = FIELD_OUT + a.ntaps - 1;
+    const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + a.ntaps + FIELD_OUT);
 #define ECPIC_F(PP) case PP: hipLaunchKernelGGL((k_field_I<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F(2) ECPIC_F(3) ECPIC_F(4) ECPIC_F(5) }
 #undef ECPIC_F

@@ -42,9 +42,11 @@ __device__ __forceinline__ void sub2_coef(const double *cn, const double *ck, do
     cz = (Akz + Anz) * inv;
 }
 
+// The particle pass.  Each wave takes every nw-th row of 64 particles of the
+// item, loads the next row while it computes the current one, and writes its
+// own 2 (P+1) partial slots (V0 slot q <-> index c - P + q, y then z).
 template <int P>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
-    __shared__ double lds[MAX_WAVES * 2 * (P + 1)];
     constexpr int NA = RecA<P>::N;
     DevStatus *st = a.st;
     const int item = blockIdx.x;
@@ -54,6 +56,15 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
     if (prev_converged2(st, k, a.tol, threadIdx.x == 0)) return;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    int ia = beg + wid * WAVE + lane;
+    double nx, np;
+    {
+        const int il = min(ia, end - 1);
+        nx = a.xi[il];
+        np = a.p[il];
+    }
     const double *rn = a.coefAn + (size_t)rec_index(c) * NA;
     const double *rk = ((k & 1) ? a.coefAk1 : a.coefAk0) + (size_t)rec_index(c) * NA;
     double cn[NA], ck[NA];
@@ -63,109 +74,98 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
 #pragma unroll
     for (int i = 0; i <= P; ++i) { my[i] = 0.0; mz[i] = 0.0; }
     int flags = 0;
-    const int B = blockDim.x;
-    for (int ia = beg + threadIdx.x; ia < end; ia += 2 * B) {
-        const int ib = ia + B;
-        const bool vb = ib < end;
-        const int ibs = vb ? ib : ia;
-        const double xa = a.xi[ia], xb = a.xi[ibs];
-        const double pa = a.p[ia], pb = a.p[ibs];
-        double ta = xa - (double)c, tb = xb - (double)c;
-        if (!(ta >= 0.0 && ta < 1.0)) { flags |= FLAG_ORDER; ta = 0.5; }
-        if (!(tb >= 0.0 && tb < 1.0)) { flags |= FLAG_ORDER; tb = 0.5; }
-        double cya, cza, cyb, czb;
-        sub2_coef<P>(cn, ck, ta, pa, cya, cza);
-        sub2_coef<P>(cn, ck, tb, pb, cyb, czb);
-        const double wb = vb ? 1.0 : 0.0;
-        cyb *= wb;
-        czb *= wb;
-        double sa = 1.0, sb = 1.0;
+    const int stride = nw * WAVE;
+    for (int row = beg + wid * WAVE; row < end; row += stride, ia += stride) {
+        const double x0 = nx, p0 = np;
+        const bool valid = ia < end;
+        if (row + stride < end) {   // prefetch the next row
+            const int il = min(ia + stride, end - 1);
+            nx = a.xi[il];
+            np = a.p[il];
+        }
+        double t = x0 - (double)c;
+        if (!(t >= 0.0 && t < 1.0)) { flags |= FLAG_ORDER; t = 0.5; }
+        double cy, cz;
+        sub2_coef<P>(cn, ck, t, p0, cy, cz);
+        const double wv = valid ? 1.0 : 0.0;
+        cy *= wv;
+        cz *= wv;
+        double tp = 1.0;
 #pragma unroll
         for (int j = 0; j <= P; ++j) {
-            my[j] = fma(cya, sa, fma(cyb, sb, my[j]));
-            mz[j] = fma(cza, sa, fma(czb, sb, mz[j]));
-            sa *= ta;
-            sb *= tb;
+            my[j] = fma(cy, tp, my[j]);
+            mz[j] = fma(cz, tp, mz[j]);
+            tp *= t;
         }
     }
-    // block sums of the moments, then V0 slot q <-> index c - P + q
-    double v[2 * (P + 1)];
+    // wave sums of the moments, then lane q < 2 (P+1) forms slot q
+    double ty[P + 1], tz[P + 1];
 #pragma unroll
-    for (int j = 0; j <= P; ++j) { v[j] = my[j]; v[P + 1 + j] = mz[j]; }
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const int nw = (blockDim.x + WAVE - 1) / WAVE;
-#pragma unroll 1
-    for (int j = 0; j < 2 * (P + 1); ++j) {
-        const double s = wave_sum(v[j]);
-        if (lane == 0) lds[wid * 2 * (P + 1) + j] = s;
+    for (int j = 0; j <= P; ++j) {
+        ty[j] = wave_sum_dpp(my[j]);
+        tz[j] = wave_sum_dpp(mz[j]);
     }
-    __syncthreads();
-    const int q = threadIdx.x;
-    if (q < 2 * (P + 1)) {
-        constexpr Pieces<P> Bp{};
-        const int comp = q / (P + 1), slot = q % (P + 1), m = P - slot;
-        double out = 0.0;
-        for (int j = 0; j <= P; ++j) {
-            double t = 0.0;
-            for (int w = 0; w < nw; ++w) t += lds[w * 2 * (P + 1) + comp * (P + 1) + j];
-            out += Bp.c[m][j] * t;
-        }
-        a.part[(size_t)item * 2 * (P + 1) + q] = out;
+    constexpr Pieces<P> Bp{};
+    const int comp = lane / (P + 1), slot = lane % (P + 1), m = P - slot;
+    double out = 0.0;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) out += Bp.c[m < 0 ? 0 : m][j] * (comp == 0 ? ty[j] : tz[j]);
+    if (lane < 2 * (P + 1)) a.part[((size_t)item * nw + wid) * 2 * (P + 1) + lane] = out;
+    if (__ballot(flags != 0)) {
+        flags = wave_or(flags);
+        if (lane == 0) atomicOr(&st->flags, flags);
     }
-    flags = wave_or(flags);
-    if (lane == 0 && flags) atomicOr(&st->flags, flags);
 }
 
-// sum_i taps[i] S[ntaps - 1 - i] for two interleaved vectors, split accumulators.
-__device__ __forceinline__ void conv2x2(const double *taps, int ntaps, const double *Sy, const double *Sz,
-                                       double &cy, double &cz) {
-    double y0 = 0.0, y1 = 0.0, z0 = 0.0, z1 = 0.0;
-    int i = 0;
-    for (; i + 1 < ntaps; i += 2) {
-        y0 = fma(taps[i], Sy[ntaps - 1 - i], y0);
-        z0 = fma(taps[i], Sz[ntaps - 1 - i], z0);
-        y1 = fma(taps[i + 1], Sy[ntaps - 2 - i], y1);
-        z1 = fma(taps[i + 1], Sz[ntaps - 2 - i], z1);
-    }
-    if (i < ntaps) {
-        y0 = fma(taps[i], Sy[ntaps - 1 - i], y0);
-        z0 = fma(taps[i], Sz[ntaps - 1 - i], z0);
-    }
-    cy = y0 + y1;
-    cz = z0 + z1;
-}
+// Field iterate k+1 of Subsystem II and the A-records of a^(k+1).  Block b
+// computes e^(k+1) on the FIELD2_OUT cells from b * TILE - P (the first P only
+// to form the records of cells b * TILE .. b * TILE + TILE - 1).  The item
+// partials are summed per cell into LDS, the two deposits assembled, and the
+// inverse of (M0^ + r^2 K^) applied as a convolution by four lanes per output
+// (every fourth tap each, combined in a fixed order).
+constexpr int FIELD2_OUT = 64;
 
-// New e_perp iterate, A-records of the next a^(k+1).  Block b computes e on
-// cells [256 b - P, 256 b + 256) (the first P only for records).
 template <int P>
 __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     extern __shared__ double smem[];
     __shared__ double ldsm[MAX_WAVES];
     __shared__ int ldsf[MAX_WAVES];
     constexpr int NA = RecA<P>::N, NS = 2 * (P + 1);
+    constexpr int TILE = FIELD2_OUT - P;
     DevStatus *st = a.st;
     if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
     const int M = a.M;
-    const int j0 = blockIdx.x * 256 - P;
-    const int nout = 256 + P;
+    const int j0 = blockIdx.x * TILE - P;
     const int mhi = a.mlo + a.ntaps - 1;
-    const int slen = nout + a.ntaps - 1;   // b on cells [j0 - mhi, j0 - mhi + slen)
-    const int clo = j0 - mhi;              // b_j needs the partials of cells j .. j+P
+    const int slen = FIELD2_OUT + a.ntaps - 1;   // b on cells [j0 - mhi, j0 - mhi + slen)
+    const int clo = j0 - mhi;                    // b_j needs the partials of cells j .. j+P
     const int clen = slen + P;
     double *cp = smem;
     double *Sy = cp + (size_t)clen * NS;
     double *Sz = Sy + slen;
-    double *eyl = Sz + slen;
-    double *ezl = eyl + nout;
+    double *tp = Sz + slen;
+    double *eyl = tp + a.ntaps;
+    double *ezl = eyl + FIELD2_OUT;
+    const double *eyk = k == 0 ? a.eyn : ((k & 1) ? a.ey1 : a.ey0);
+    const double *ezk = k == 0 ? a.ezn : ((k & 1) ? a.ez1 : a.ez0);
+    const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
+    const int jq = j0 + quad, jqm = imod(jq, M);
+    const double E0y_q = a.E0y[jqm], E0z_q = a.E0z[jqm];
+    const double eyk_q = eyk[jqm + HALO], ezk_q = ezk[jqm + HALO];
+    for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         const int c = imod(clo + t, M);
+        double v[NS];
 #pragma unroll
-        for (int q = 0; q < NS; ++q) cp[t * NS + q] = 0.0;
-        for (int i = a.items.cell_first[c]; i < a.items.cell_first[c + 1]; ++i) {
+        for (int q = 0; q < NS; ++q) v[q] = 0.0;
+        const int u0 = a.items.cell_first[c] * a.wpi, u1 = a.items.cell_first[c + 1] * a.wpi;
+        for (int u = u0; u < u1; ++u) {   // the wave partials of the cell's items
 #pragma unroll
-            for (int q = 0; q < NS; ++q) cp[t * NS + q] += a.part[(size_t)i * NS + q];
+            for (int q = 0; q < NS; ++q) v[q] += a.part[(size_t)u * NS + q];
         }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < slen; t += blockDim.x) {
@@ -179,34 +179,40 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
         Sz[t] = sz;
     }
     __syncthreads();
-    const double *eyk = k == 0 ? a.eyn : ((k & 1) ? a.ey1 : a.ey0);
-    const double *ezk = k == 0 ? a.ezn : ((k & 1) ? a.ez1 : a.ez0);
     double *eyo = (k & 1) ? a.ey0 : a.ey1;
     double *ezo = (k & 1) ? a.ez0 : a.ez1;
     double *Aout = ((k + 1) & 1) ? a.coefAk1 : a.coefAk0;
     double re = 0.0;
     int flags = 0;
-    for (int q = threadIdx.x; q < nout; q += blockDim.x) {
-        const int jj = j0 + q;
-        const int j = imod(jj, M);
-        double cy, cz;
-        conv2x2(a.taps, a.ntaps, Sy + q, Sz + q, cy, cz);
-        const double ny = a.E0y[j] + a.coef * cy;
-        const double nz = a.E0z[j] + a.coef * cz;
-        eyl[q] = ny;
-        ezl[q] = nz;
-        if (q >= P && jj < M) {
-            store_padded(eyo, M, j, ny);
-            store_padded(ezo, M, j, nz);
-            re = fmax(re, fmax(fabs(ny - eyk[j + HALO]), fabs(nz - ezk[j + HALO])));
-            if (!(fabs(ny) < 1.0e300) || !(fabs(nz) < 1.0e300)) flags |= FLAG_NONFINITE;
+    {
+        const double *Syq = Sy + quad + a.ntaps - 1, *Szq = Sz + quad + a.ntaps - 1;
+        double cy = 0.0, cz = 0.0;
+        for (int i = ql; i < a.ntaps; i += 4) {
+            cy = fma(tp[i], Syq[-i], cy);
+            cz = fma(tp[i], Szq[-i], cz);
+        }
+        cy += dpp_d<0xB1>(cy);
+        cz += dpp_d<0xB1>(cz);
+        cy += dpp_d<0x4E>(cy);
+        cz += dpp_d<0x4E>(cz);
+        const double ny = E0y_q + a.coef * cy;
+        const double nz = E0z_q + a.coef * cz;
+        if (ql == 0) {
+            eyl[quad] = ny;
+            ezl[quad] = nz;
+            if (quad >= P && jq < M) {
+                store_padded(eyo, M, jqm, ny);
+                store_padded(ezo, M, jqm, nz);
+                re = fmax(fabs(ny - eyk_q), fabs(nz - ezk_q));
+                if (!(fabs(ny) < 1.0e300) || !(fabs(nz) < 1.0e300)) flags |= FLAG_NONFINITE;
+            }
         }
     }
     __syncthreads();
     {
         const int q = threadIdx.x + P;
         const int j = j0 + q;
-        if (j < M) {
+        if (q < FIELD2_OUT && j < M) {
             constexpr Pieces<P> B{};
             for (int i = 0; i <= P; ++i) {
                 double sy = 0.0, sz = 0.0;
@@ -338,9 +344,10 @@ void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArg
 #undef ECPIC_S2
 }
 
-void launch_field_II(int P, int grid, hipStream_t s, const FieldIIArgs &a) {
-    const int slen = 256 + P + a.ntaps - 1;
-    const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + 2 * (256 + P));
+void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
+    const int grid = (M + FIELD2_OUT - P - 1) / (FIELD2_OUT - P);
+    const int slen = FIELD2_OUT + a.ntaps - 1;
+    const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + a.ntaps + 2 * FIELD2_OUT);
 #define ECPIC_F2(PP) case PP: hipLaunchKernelGGL((k_field_II<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F2(2) ECPIC_F2(3) ECPIC_F2(4) ECPIC_F2(5) }
 #undef ECPIC_F2
