@@ -81,6 +81,8 @@ typedef struct {
     int32_t map;              /* ecpic_map */
     int32_t device;           /* HIP device ordinal */
     void *stream;             /* hipStream_t to run on (e.g. torch's); NULL => library-owned */
+    int32_t fp32_sweeps;      /* ECPIC_FP32_MIXED: FP32 sweeps that open every Subsystem I substep
+                                 before the FP64 ones; 0 => 2.  Ignored for ECPIC_FP64. */
 } ecpic_config;
 
 typedef struct {

@@ -39,7 +39,7 @@ class Config(C.Structure):
     _fields_ = [("L", C.c_double), ("M", C.c_int32), ("degree", C.c_int32), ("n_particles", C.c_int64),
                 ("weight", C.c_double), ("dt", C.c_double), ("picard_tol", C.c_double),
                 ("picard_max_iter", C.c_int32), ("precision", C.c_int32), ("warmstart", C.c_int32),
-                ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -118,11 +118,11 @@ class Context:
     def __init__(self, L: float, M: int, degree: int, n_particles: int, dt: float, tol: float,
                  weight: float = 0.0, max_iter: int = 0, precision: int = FP64,
                  warmstart: int = WS_EXPLICIT, map: int = MAP_JACOBI, device: int = 0,
-                 stream: Optional[int] = None):
+                 stream: Optional[int] = None, fp32_sweeps: int = 0):
         self._lib = load()
         self.cfg = Config(float(L), int(M), int(degree), int(n_particles), float(weight), float(dt),
                           float(tol), int(max_iter), int(precision), int(warmstart), int(map), int(device),
-                          C.c_void_p(stream) if stream else None)
+                          C.c_void_p(stream) if stream else None, int(fp32_sweeps))
         self.M = int(M)
         self.N = int(n_particles)
         h = C.c_void_p()
@@ -199,9 +199,11 @@ class Context:
         _ck(self._lib.ecpic_solve_gauss(self._h), "solve_gauss")
 
     def substep_particles(self):
+        """Returns (sweeps, residual); last_stats_I keeps (sweeps, fp32_sweeps, residual)."""
         st = IterStats()
         rc = self._lib.ecpic_substep_particles(self._h, C.byref(st))
         _ck(rc, "substep_particles")
+        self.last_stats_I = (st.sweeps, st.fp32_sweeps, st.residual)
         return st.sweeps, st.residual
 
     def substep_fields(self):

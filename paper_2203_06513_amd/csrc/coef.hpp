@@ -68,26 +68,26 @@ __device__ __forceinline__ void make_recE(F e_at, int c, double (&r)[P]) {
     }
 }
 
-template <int N>
-__device__ __forceinline__ double horner(const double *c, double t) {
-    double v = c[N - 1];
+template <int N, typename T>
+__device__ __forceinline__ T horner(const T *c, T t) {
+    T v = c[N - 1];
 #pragma unroll
     for (int i = N - 2; i >= 0; --i) v = fma(v, t, c[i]);
     return v;
 }
 
 // (A(b) - A(a))/(b - a) for A = sum_{i=0}^{P} c_i t^i, given h_0..h_{P-1} of (a, b).
-template <int P>
-__device__ __forceinline__ double divdiff(const double *c, const double (&h)[P]) {
-    double v = 0.0;
+template <int P, typename T>
+__device__ __forceinline__ T divdiff(const T *c, const T (&h)[P]) {
+    T v = (T)0;
 #pragma unroll
     for (int i = 1; i <= P; ++i) v = fma(c[i], h[i - 1], v);
     return v;
 }
 
-template <int P>
-__device__ __forceinline__ double pmean(const double *w, const double (&h)[P]) {
-    double v = 0.0;
+template <int P, typename T>
+__device__ __forceinline__ T pmean(const T *w, const T (&h)[P]) {
+    T v = (T)0;
 #pragma unroll
     for (int i = 0; i < P; ++i) v = fma(w[i], h[i], v);
     return v;
@@ -109,17 +109,19 @@ __device__ __forceinline__ double frcp(double x) {
 }
 
 __device__ __forceinline__ double fsqrt(double q) {   // q >= 1
-    const double y = __builtin_amdgcn_rsq(q);
-    double s = q * y, h = 0.5 * y;
-    double r = fma(-s, h, 0.5);
-    s = fma(s, r, s);
-    h = fma(h, r, h);
-    r = fma(-s, h, 0.5);
-    s = fma(s, r, s);
-    h = fma(h, r, h);
+    // one Newton step on the reciprocal square root (relative error ~1e-15),
+    // then one exact-residual correction of the root itself
+    const double y0 = __builtin_amdgcn_rsq(q);
+    const double e = fma(-q * y0, y0, 1.0);
+    const double h = 0.5 * fma(y0, 0.5 * e, y0);   // ~ 1 / (2 sqrt(q))
+    const double s = 2.0 * h * q;
     const double d = fma(-s, s, q);
     return fma(d, h, s);
 }
 #endif
+
+// Single precision: the hardware square root and reciprocal (about 1 ulp).
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fsqrt(float q) { return __builtin_amdgcn_sqrtf(q); }
 
 }  // namespace ecpic

@@ -113,6 +113,21 @@ __device__ __forceinline__ void block_max_or(double &m, int &f, double *ldsd, in
     __syncthreads();
 }
 
+// Status of a substep about to start; gate_src (the substep it follows) must
+// have committed without a flag, else every kernel of this substep skips.
+__device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate_src) {
+    st->rx_bits[0] = 0ull;
+    st->rx_bits[1] = 0ull;
+    st->re_bits[0] = 0ull;
+    st->re_bits[1] = 0ull;
+    st->kconv = -1;
+    st->committed = 0;
+    st->flags = 0;
+    st->fp32_sweeps = 0;
+    st->res = 0.0;
+    st->gate = gate_src ? (gate_src->committed && gate_src->flags == 0) : 1;
+}
+
 // Write v as coefficient j in [0, M) of a padded periodic array (all aliases).
 __device__ __forceinline__ void store_padded(double *f, int M, int j, double v) {
     const int r = (HALO + M - 1) / M;

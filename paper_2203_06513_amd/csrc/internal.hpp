@@ -42,7 +42,7 @@ struct DevStatus {
     int32_t flags;                   // FLAG_* bits
     int32_t gate;                    // substep allowed to run (Subsystem II waits on I)
     int32_t fp32_sweeps;             // sweeps done in FP32 (precision form)
-    int32_t pad_;
+    int32_t n_items_next;            // item count of the re-sorted particles (Subsystem I commit)
     double res;                      // residual of sweep kconv (length / field units)
     double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
@@ -64,14 +64,20 @@ struct Particles {
 struct SweepIArgs {
     const double *xi, *p;
     double *d0, *d1;               // iterate buffers, d^(k) = k&1 ? d1 : d0
+    float *f0, *f1;                // single precision iterate buffers (precision form), same parity
+    const float *d32in;            // FP64 sweep reading d^(k) from a single precision buffer, or null
     ItemList items;
     const double *coefA;           // A-records of a_perp^n
     const double *coefE0, *coefE1; // E-records of ebar^(k) = (e^n + e^(k))/2, by parity of k
     double *part;                  // [max_items][waves per item][deg+4]: P+2 current slots, residual, flags
+    int32_t *cnt;                  // [max_items][3] movers left / stay / right of the increment a commit
+                                   // after this sweep would take
+    int32_t *wpre;                 // [max_items][waves per item][3] the same, exclusive prefix over waves
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
     int32_t k;                     // sweep index
+    int32_t first64;               // index of the first FP64 sweep (0 for the plain method)
 };
 
 struct FieldIArgs {
@@ -96,14 +102,15 @@ struct CommitIArgs {
     const double *coefA, *coefE0, *coefE1;
     const double *ek0, *ek1;
     double *ex_next;               // padded e_x^{n+1}
-    int32_t *cnt;                  // [max_items][3] movers left / stay / right
+    const int32_t *cnt, *wpre;     // mover counts of the converged sweep (see SweepIArgs)
     int32_t *tot;                  // [M][3]
-    int32_t *base;                 // [max_items][3]
+    int32_t *base;                 // [max_items][3] destination of each item's first mover of each kind
     int32_t *nstart;               // [2M + 1]
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
-    int32_t M, chunk, seidel;
+    int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
+    int32_t first64;               // index of the first FP64 sweep
     int64_t N;
 };
 

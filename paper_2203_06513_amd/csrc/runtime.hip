@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -22,20 +23,18 @@
 #include "internal.hpp"
 
 namespace ecpic {
-void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, const SweepIArgs &a);
+void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a);
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a);
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a);
 void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s);
-void launch_mark(DevStatus *st, hipStream_t s);
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a);
-void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double *ay, const double *az,
+void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, const double *az,
                          const double *e, double *coefA, double *coefE, int M);
-void launch_prep_II(int P, hipStream_t s, const DevStatus *st, const double *ayn, const double *azn,
-                    const double *eyn, const double *ezn, double dt, double *coefAn, double *coefAk0, int M);
-void launch_E0_II(hipStream_t s, const DevStatus *st, const double *eyn, const double *ezn, const double *ayn,
-                  const double *azn, const double *m0, const double *kr, int P, double r2, double ck,
-                  const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z);
+void launch_begin_II(int P, hipStream_t s, DevStatus *st, const DevStatus *gate_src, const double *ayn,
+                     const double *azn, const double *eyn, const double *ezn, double dt, double *coefAn,
+                     double *coefAk0, const double *m0, const double *kr, double r2, double ck, const double *taps,
+                     int ntaps, int mlo, int M, double *E0y, double *E0z);
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
                  double alpha, int M);
 void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const double *eyn, const double *ezn,
@@ -171,10 +170,12 @@ struct ecpic_ctx {
     Particles pb[2]{};
     int cur = 0;
     double *dbuf[2]{};
+    float *fbuf[2]{};          // single precision iterate (precision form)
+    int k32 = 0;               // FP32 sweeps opening each Subsystem I substep
     ItemList items[2]{};
     int icur = 0;
     int n_items_host = 0;
-    int32_t *cnt = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
+    int32_t *cnt = nullptr, *wpre = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
     double *part = nullptr;
 
     // padded fields: [0]/[1] = current / next (swapped on commit)
@@ -193,6 +194,7 @@ struct ecpic_ctx {
         DevStatus I, II;
         int32_t n_items_next;
     } *h = nullptr;
+    static_assert(offsetof(HostMirror, II) == sizeof(DevStatus), "statuses are copied as one block");
 
     double *rho = nullptr, *rvec = nullptr, *uvec = nullptr, *out5 = nullptr, *part_e = nullptr;
     unsigned long long *maxbits = nullptr;
@@ -263,11 +265,16 @@ SweepIArgs sweep_args(ecpic_ctx *c) {
     a.p = c->pb[c->cur].p;
     a.d0 = c->dbuf[0];
     a.d1 = c->dbuf[1];
+    a.f0 = c->fbuf[0];
+    a.f1 = c->fbuf[1];
+    a.first64 = c->k32;
     a.items = c->items[c->icur];
     a.coefA = c->coefA;
     a.coefE0 = c->coefE[0];
     a.coefE1 = c->coefE[1];
     a.part = c->part;
+    a.cnt = c->cnt;
+    a.wpre = c->wpre;
     a.st = c->stI;
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
@@ -298,7 +305,10 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     const int gridp = particle_grid(c, true);
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kI++;
-        timed(c, "sweep_I", [&] { launch_sweep_I(c->P, c->seidel, gridp, c->block, c->stream, a); });
+        const bool fp32 = a.k < c->k32;
+        a.d32in = (c->k32 > 0 && a.k == c->k32) ? c->fbuf[c->k32 & 1] : nullptr;
+        timed(c, fp32 ? "sweep_I32" : "sweep_I",
+              [&] { launch_sweep_I(c->P, c->seidel, fp32, gridp, c->block, c->stream, a); });
         timed(c, "field_I", [&] { launch_field_I(c->P, c->M, c->stream, f); });
     }
 }
@@ -318,6 +328,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.ek1 = c->ek[1];
     a.ex_next = c->ex[c->exc ^ 1];
     a.cnt = c->cnt;
+    a.wpre = c->wpre;
     a.tot = c->tot;
     a.base = c->base;
     a.nstart = c->nstart;
@@ -330,7 +341,9 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.M = c->M;
     a.chunk = c->chunk;
     a.seidel = c->seidel;
+    a.wpi = c->block / 64;
     a.nsweeps = c->kI;
+    a.first64 = c->k32;
     a.N = c->N;
     timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, true), c->block, c->stream, a); });
 }
@@ -344,14 +357,12 @@ struct IIView {
 
 void enqueue_begin_II(ecpic_ctx *c, bool gated) {
     c->kII = 0;
-    launch_begin(c->stII, gated ? c->stI : nullptr, c->stream);
     const double r = c->dt / (2.0 * c->dx);
     const int t = c->trc;
     timed(c, "begin_II", [&] {
-        launch_prep_II(c->P, c->stream, c->stII, c->ay[t], c->az[t], c->ey[t], c->ez[t], c->dt, c->coefAn,
-                       c->coefAk[0], c->M);
-        launch_E0_II(c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t], c->m0row.data(), c->krow.data(),
-                     c->P, r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
+        launch_begin_II(c->P, c->stream, c->stII, gated ? c->stI : nullptr, c->ay[t], c->az[t], c->ey[t], c->ez[t],
+                        c->dt, c->coefAn, c->coefAk[0], c->m0row.data(), c->krow.data(), r * r,
+                        c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
     });
 }
 
@@ -403,15 +414,12 @@ void enqueue_commit_II(ecpic_ctx *c) {
         launch_commit_II((c->M + 255) / 256, c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t],
                          c->eyk[0], c->eyk[1], c->ezk[0], c->ezk[1], c->ey[n], c->ez[n], c->ay[n], c->az[n],
                          0.5 * c->dt, c->M, c->kII, c->tol);
-        launch_mark(c->stII, c->stream);
     });
 }
 
 int read_status(ecpic_ctx *c) {
-    HIPCHK(hipMemcpyAsync(&c->h->I, c->stI, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&c->h->II, c->stII, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipMemcpyAsync(&c->h->n_items_next, c->items[c->icur ^ 1].n_items, sizeof(int32_t),
-                          hipMemcpyDeviceToHost, c->stream));
+    // both statuses in one copy (stII = stI + 1, and I, II adjacent in the mirror)
+    HIPCHK(hipMemcpyAsync(&c->h->I, c->stI, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
     return sync(c);
 }
 
@@ -425,9 +433,8 @@ int flags_to_status(int32_t f) {
 // Finish Subsystem I (more sweeps / commit) after a status read.
 void enqueue_begin_I(ecpic_ctx *c) {
     c->kI = 0;
-    launch_begin(c->stI, nullptr, c->stream);
     timed(c, "begin_I", [&] {
-        launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
+        launch_prep_records(c->P, c->stream, c->stI, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                             c->coefE[0], c->M);
     });
 }
@@ -504,15 +511,15 @@ int check_device(int dev) {
 void free_all(ecpic_ctx *c) {
     auto F = [](void *p) { if (p) hipFree(p); };
     for (int b = 0; b < 2; ++b) {
-        F(c->pb[b].xi); F(c->pb[b].p); F(c->pb[b].id); F(c->dbuf[b]);
+        F(c->pb[b].xi); F(c->pb[b].p); F(c->pb[b].id); F(c->dbuf[b]); F(c->fbuf[b]);
         F(c->items[b].cell); F(c->items[b].begin); F(c->items[b].cell_first); F(c->items[b].n_items);
         F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
-    F(c->cnt); F(c->tot); F(c->base); F(c->nstart); F(c->part);
+    F(c->cnt); F(c->wpre); F(c->tot); F(c->base); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAn); F(c->coefAk[0]); F(c->coefAk[1]);
-    F(c->stI); F(c->stII);
+    F(c->stI);   // stII lives in the same allocation
     F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
     if (c->h) hipHostFree(c->h);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
@@ -527,15 +534,17 @@ int alloc_all(ecpic_ctx *c) {
     for (int b = 0; b < 2; ++b) {
         rc |= dalloc(&c->pb[b].xi, N); rc |= dalloc(&c->pb[b].p, N); rc |= dalloc(&c->pb[b].id, N);
         rc |= dalloc(&c->dbuf[b], N);
+        if (c->k32 > 0) rc |= dalloc(&c->fbuf[b], N);
         rc |= dalloc(&c->items[b].cell, c->max_items); rc |= dalloc(&c->items[b].begin, c->max_items + 1);
         rc |= dalloc(&c->items[b].cell_first, M + 1); rc |= dalloc(&c->items[b].n_items, 1);
         rc |= dalloc(&c->ex[b], MP); rc |= dalloc(&c->ey[b], MP); rc |= dalloc(&c->ez[b], MP);
         rc |= dalloc(&c->ay[b], MP); rc |= dalloc(&c->az[b], MP);
         rc |= dalloc(&c->ek[b], MP); rc |= dalloc(&c->eyk[b], MP); rc |= dalloc(&c->ezk[b], MP);
     }
-    rc |= dalloc(&c->cnt, (size_t)c->max_items * 3);
     rc |= dalloc(&c->tot, (size_t)M * 3);
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
+    rc |= dalloc(&c->cnt, (size_t)c->max_items * 3);
+    rc |= dalloc(&c->wpre, (size_t)c->max_items * (c->block / 64) * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
     // per item and wave: Subsystem I P+4 values, Subsystem II 2 (P+1)
     rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 1), c->P + 4));
@@ -544,7 +553,8 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAn, nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefAk[0], nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAk[1], nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefE[0], nrec * c->P); rc |= dalloc(&c->coefE[1], nrec * c->P);
-    rc |= dalloc(&c->stI, 1); rc |= dalloc(&c->stII, 1);
+    rc |= dalloc(&c->stI, 2);
+    if (c->stI) c->stII = c->stI + 1;
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
     rc |= dalloc(&c->count, M);
@@ -642,6 +652,7 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     if (!(g.L > 0.0) || g.degree < 2 || g.degree > MAX_DEG || g.M < g.degree + 3 || g.n_particles < 0 ||
         g.n_particles > (int64_t)0x7fffffff - 1 || !(g.dt > 0.0) || !(g.dt < g.L / g.M) || !(g.picard_tol > 0.0) ||
         g.picard_max_iter < 0 || (g.precision != ECPIC_FP64 && g.precision != ECPIC_FP32_MIXED) ||
+        g.fp32_sweeps < 0 || g.fp32_sweeps > 16 ||
         (g.map != ECPIC_MAP_JACOBI && g.map != ECPIC_MAP_SEIDEL) ||
         (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_MLP) || g.weight < 0.0)
         return ECPIC_EINVAL;
@@ -662,6 +673,7 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->tol = g.picard_tol;
     c->kmax = g.picard_max_iter > 0 ? std::min(g.picard_max_iter, MAX_HIST) : 50;
     c->seidel = g.map == ECPIC_MAP_SEIDEL;
+    c->k32 = g.precision == ECPIC_FP32_MIXED ? (g.fp32_sweeps > 0 ? g.fp32_sweeps : 2) : 0;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
     c->block = ppc >= 512 ? 256 : (ppc >= 128 ? 128 : 64);
     c->chunk = MAX_CHUNK;
@@ -859,7 +871,7 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     if (!rc) rc = finish_I(c, &again);
     if (stats) {
         stats->sweeps = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
-        stats->fp32_sweeps = c->h->I.fp32_sweeps;
+        stats->fp32_sweeps = std::min(c->kI, c->k32);
         stats->residual = c->h->I.res;
     }
     if (rc) return rc;
@@ -867,7 +879,7 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     c->cur ^= 1;
     c->icur ^= 1;
     c->exc ^= 1;
-    c->n_items_host = c->h->n_items_next;
+    c->n_items_host = c->h->I.n_items_next;
     return ECPIC_OK;
 }
 
@@ -918,7 +930,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         if (!rc) rc = finish_II(c, v);
         const int nI = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
         const int nII = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
-        if (sI) { sI[s].sweeps = nI; sI[s].fp32_sweeps = c->h->I.fp32_sweeps; sI[s].residual = c->h->I.res; }
+        if (sI) { sI[s].sweeps = nI; sI[s].fp32_sweeps = std::min(c->kI, c->k32); sI[s].residual = c->h->I.res; }
         if (sII) { sII[s].sweeps = nII; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
         if (rc) return rc;   // nothing swapped: the step is rolled back
         c->guessI = std::max(1, nI);
@@ -927,7 +939,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         c->icur ^= 1;
         c->exc ^= 1;
         c->trc ^= 1;
-        c->n_items_host = c->h->n_items_next;
+        c->n_items_host = c->h->I.n_items_next;
         if (steps_done) *steps_done = s + 1;
     }
     return ECPIC_OK;

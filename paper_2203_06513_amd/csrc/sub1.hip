@@ -15,6 +15,8 @@
 // h_i of its pieces and turned into the per-cell deposit once per block.  A
 // step that enters a neighbour cell (at most one, since |d| < 1) adds a second
 // piece; waves with no such step skip that code.
+#include <type_traits>
+
 #include "coef.hpp"
 
 namespace ecpic {
@@ -58,25 +60,6 @@ __device__ __forceinline__ void end_point(double xi0, double d, int c, double &t
     s = t1 >= 1.0 ? 1 : (t1 < 0.0 ? -1 : 0);
 }
 
-template <int P>
-__device__ __forceinline__ void deposit(Moments<P> &mo, double t0, double t1, int s) {
-    const Seg<double> g = make_seg(t0, t1, s);
-    double h[P];
-    homog<P - 1>(g.aA, g.bA, h);
-#pragma unroll
-    for (int i = 0; i < P; ++i) mo.A[i] = fma(g.sA, h[i], mo.A[i]);
-    if (__ballot(s != 0)) {
-        homog<P - 1>(g.aB, g.bB, h);
-        const double sr = s > 0 ? g.sB : 0.0, sl = s < 0 ? g.sB : 0.0;
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            mo.R[i] = fma(sr, h[i], mo.R[i]);
-            mo.L[i] = fma(sl, h[i], mo.L[i]);
-        }
-    }
-}
-
-__device__ __forceinline__ double dt_dx_times(double dt_dx, double p) { return dt_dx * p; }
 
 struct MapOut {
     double dn, p1, dused, t1;
@@ -161,65 +144,100 @@ __device__ __forceinline__ double moments_to_slots(const Moments<P> &mo) {
     return out;
 }
 
+// Values per wave in the partials of a sweep: P+2 current slots, the residual
+// max and the flags.
+template <int P>
+struct UnitI {
+    static constexpr int N = P + 4;
+};
+
+// The rows (64 particles) of an item are split into nw contiguous runs, one per
+// wave of the block, so that a wave's particles are consecutive in the sorted
+// order (the commit relies on it to keep the order stable).
+__device__ __forceinline__ void wave_range(int beg, int end, int wid, int nw, int &wb, int &we) {
+    const int rows = (end - beg + WAVE - 1) / WAVE;
+    const int rpw = (rows + nw - 1) / nw;
+    wb = min(beg + wid * rpw * WAVE, end);
+    we = min(wb + rpw * WAVE, end);
+}
+
 // The sweep.  The block's own-cell coefficients stay in registers; the three
 // cells' records are also staged in LDS, where the rare steps that enter a
 // neighbour cell read them with a per-lane (position-dependent) address.  The
-// waves of a block share only that staging: each wave takes every nw-th row of
-// 64 particles of the item, loads the next row while it computes the current
-// one, and writes its own partial slots (P+2 current sums, its residual max and
-// its error flags), which the field kernel assembles per cell.
-template <int P>
+// waves of a block share only that staging: each wave takes its run of rows of
+// the item, loads the next row while it computes the current one, and writes
+// its own partial values (UnitI), which the field kernel assembles per cell.
+// At the end the block counts the particles that would leave to the left,
+// stay or leave to the right if the sweep's increment were committed, per item
+// and per wave (the commit places the movers from them).
+template <int P, typename T>
 struct Own {
-    double ay[P + 1], az[P + 1], eb[P];
+    T ay[P + 1], az[P + 1], eb[P];
 };
 
-template <int P>
+template <int P, typename T>
 struct LdsRec {   // one cell's coefficients in LDS
-    double ay[P + 1], az[P + 1], eb[P];
+    T ay[P + 1], az[P + 1], eb[P];
 };
 
+template <typename T>
 struct Lane {
-    double xi0, p0, d, t0, t1, q0, A0y, A0z, g00;
+    T t0, p0, d, t1, q0, A0y, A0z, g00;
     int s;
 };
 
-template <int P>
-__device__ __forceinline__ void stage_gather(const Own<P> &o, Lane &L, int c, bool explicit_start, double dt_dx,
-                                             int &flags) {
-    L.t0 = L.xi0 - (double)c;
-    if (!(L.t0 >= 0.0 && L.t0 < 1.0)) { flags |= FLAG_ORDER; L.t0 = 0.5; }
+// Cell-local end point and cell change of a step (single precision sweeps).
+__device__ __forceinline__ void end_point(float t0, float d, float &t1, int &s, int &flags) {
+    t1 = t0 + d;
+    if (!(t1 > -1.0f && t1 < 2.0f)) {
+        flags |= FLAG_CFL;
+        t1 = t1 >= 2.0f ? 1.5f : (t1 <= -1.0f ? -0.5f : 0.5f);
+    }
+    s = t1 >= 1.0f ? 1 : (t1 < 0.0f ? -1 : 0);
+}
+
+// Gather at the step start, gamma there, the explicit first increment if asked,
+// and the end point of the current increment.  xi0 - c is exact in FP64; the
+// single precision sweeps round it once.
+template <int P, typename T>
+__device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, double xi0, int c, bool explicit_start,
+                                             T dt_dx, int &flags) {
+    const double t0 = xi0 - (double)c;
+    L.t0 = (T)t0;
+    if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; L.t0 = (T)0.5; }
     L.A0y = horner<P + 1>(o.ay, L.t0);
     L.A0z = horner<P + 1>(o.az, L.t0);
-    L.q0 = fma(L.p0, L.p0, 1.0);
+    L.q0 = fma(L.p0, L.p0, (T)1);
     L.g00 = fsqrt(L.q0 + L.A0y * L.A0y + L.A0z * L.A0z);
     if (explicit_start) L.d = dt_dx * L.p0 * frcp(L.g00);
-    end_point(L.xi0, L.d, c, L.t1, L.s, flags);
+    if constexpr (sizeof(T) == 8) end_point(xi0, L.d, c, L.t1, L.s, flags);
+    else end_point(L.t0, L.d, L.t1, L.s, flags);
 }
 
 // Momentum update and next increment; anycross is wave-uniform.
-template <int P>
-__device__ __forceinline__ void stage_push(const Own<P> &o, const LdsRec<P> *rec, bool anycross, const Lane &L,
-                                           double dt, double dt_dx, double inv_dx, double &p1, double &dn,
-                                           int &flags) {
-    const double t1c = fmin(fmax(L.t1, 0.0), 1.0);
-    double h[P];
+template <int P, typename T>
+__device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
+                                           const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags) {
+    const T zero = (T)0, one = (T)1;
+    const T t1c = fmin(fmax(L.t1, zero), one);
+    T h[P];
     homog<P - 1>(fmin(L.t0, t1c), fmax(L.t0, t1c), h);
-    double LE = pmean<P>(o.eb, h);
-    double DAy = divdiff<P>(o.ay, h), DAz = divdiff<P>(o.az, h);
-    double A1y, A1z;
+    T LE = pmean<P>(o.eb, h);
+    T DAy = divdiff<P>(o.ay, h), DAz = divdiff<P>(o.az, h);
+    T A1y, A1z;
     if (anycross) {
         // record of the cell holding t1, indexed arithmetically (t1 in (-1, 2))
         const int r = (int)floor(L.t1) + 1;
-        const LdsRec<P> &nb = rec[r];
-        const double tl = L.t1 - (double)(r - 1);
+        const LdsRec<P, T> &nb = rec[r];
+        const T tl = L.t1 - (T)(r - 1);
         A1y = horner<P + 1>(nb.ay, tl);
         A1z = horner<P + 1>(nb.az, tl);
         if (L.s != 0) {
             // piece inside cell c + s: [0, t1 - 1] or [t1 + 1, 1]
-            double hb[P];
-            homog<P - 1>(L.s > 0 ? 0.0 : tl, L.s > 0 ? tl : 1.0, hb);
-            const double sA = t1c - L.t0, sB = L.t1 - t1c;
-            const double inv = frcp(L.t1 - L.t0);
+            T hb[P];
+            homog<P - 1>(L.s > 0 ? zero : tl, L.s > 0 ? tl : one, hb);
+            const T sA = t1c - L.t0, sB = L.t1 - t1c;
+            const T inv = frcp(L.t1 - L.t0);
             LE = (sA * LE + sB * pmean<P>(nb.eb, hb)) * inv;
             DAy = (sA * DAy + sB * divdiff<P>(nb.ay, hb)) * inv;
             DAz = (sA * DAz + sB * divdiff<P>(nb.az, hb)) * inv;
@@ -228,41 +246,78 @@ __device__ __forceinline__ void stage_push(const Own<P> &o, const LdsRec<P> *rec
         A1y = horner<P + 1>(o.ay, L.t1);
         A1z = horner<P + 1>(o.az, L.t1);
     }
-    const double qa1 = A1y * A1y + A1z * A1z;
-    const double g01 = fsqrt(L.q0 + qa1);
-    const double F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
+    const T qa1 = A1y * A1y + A1z * A1z;
+    const T g01 = fsqrt(L.q0 + qa1);
+    const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
     p1 = fma(dt, F, L.p0);
-    const double g11 = fsqrt(fma(p1, p1, 1.0) + qa1);
+    const T g11 = fsqrt(fma(p1, p1, one) + qa1);
     dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
-    if (!(fabs(dn) < 1.0e300) || !(fabs(p1) < 1.0e300)) flags |= FLAG_NONFINITE;
+    const T big = sizeof(T) == 8 ? (T)1.0e300 : (T)1.0e30f;
+    if (!(fabs(dn) < big) || !(fabs(p1) < big)) flags |= FLAG_NONFINITE;
 }
 
-// Moments of a step from t0 to t1 (end in cell c + s); scale 0 drops it.
+// Single precision moments with Knuth's TwoSum compensation: every product and
+// every addition leaves its rounding error in the companion sum.
 template <int P>
-__device__ __forceinline__ void stage_deposit(Moments<P> &mo, bool anycross, double t0, double t1, int s,
-                                              double scale) {
-    const double t1c = fmin(fmax(t1, 0.0), 1.0);
-    double h[P];
+struct Moments32 {
+    float A[P], R[P], L[P];
+    float cA[P], cR[P], cL[P];
+};
+
+__device__ __forceinline__ void acc_two_sum(float &s, float &c, float a, float b) {
+#pragma clang fp contract(off)
+    const float x = a * b;
+    const float ex = fmaf(a, b, -x);
+    const float t = s + x;
+    const float bp = t - s;
+    const float e = (s - (t - bp)) + (x - bp);
+    s = t;
+    c += e + ex;
+}
+
+__device__ __forceinline__ void acc(double &s, double a, double b) { s = fma(a, b, s); }
+
+template <int P>
+__device__ __forceinline__ void acc_A(Moments<P> &mo, int i, double a, double b) { acc(mo.A[i], a, b); }
+template <int P>
+__device__ __forceinline__ void acc_R(Moments<P> &mo, int i, double a, double b) { acc(mo.R[i], a, b); }
+template <int P>
+__device__ __forceinline__ void acc_L(Moments<P> &mo, int i, double a, double b) { acc(mo.L[i], a, b); }
+template <int P>
+__device__ __forceinline__ void acc_A(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.A[i], mo.cA[i], a, b); }
+template <int P>
+__device__ __forceinline__ void acc_R(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.R[i], mo.cR[i], a, b); }
+template <int P>
+__device__ __forceinline__ void acc_L(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.L[i], mo.cL[i], a, b); }
+
+// Moments of a step from t0 to t1 (end in cell c + s); scale 0 drops it.
+template <int P, typename T, typename MO>
+__device__ __forceinline__ void stage_deposit(MO &mo, bool anycross, T t0, T t1, int s, T scale) {
+    const T zero = (T)0, one = (T)1;
+    const T t1c = fmin(fmax(t1, zero), one);
+    T h[P];
     homog<P - 1>(fmin(t0, t1c), fmax(t0, t1c), h);
-    const double sA = scale * (t1c - t0);
+    const T sA = scale * (t1c - t0);
 #pragma unroll
-    for (int i = 0; i < P; ++i) mo.A[i] = fma(sA, h[i], mo.A[i]);
+    for (int i = 0; i < P; ++i) acc_A<P>(mo, i, sA, h[i]);
     if (anycross) {
-        const double tl = t1 - (double)s;
-        homog<P - 1>(s > 0 ? 0.0 : (s < 0 ? tl : 0.0), s > 0 ? tl : (s < 0 ? 1.0 : 0.0), h);
-        const double sB = scale * (t1 - t1c);
-        const double sr = s > 0 ? sB : 0.0, sl = s < 0 ? sB : 0.0;
+        const T tl = t1 - (T)s;
+        homog<P - 1>(s > 0 ? zero : (s < 0 ? tl : zero), s > 0 ? tl : (s < 0 ? one : zero), h);
+        const T sB = scale * (t1 - t1c);
+        const T sr = s > 0 ? sB : zero, sl = s < 0 ? sB : zero;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            mo.R[i] = fma(sr, h[i], mo.R[i]);
-            mo.L[i] = fma(sl, h[i], mo.L[i]);
+            acc_R<P>(mo, i, sr, h[i]);
+            acc_L<P>(mo, i, sl, h[i]);
         }
     }
 }
 
-// Has sweep k-1 met the tolerance?  Records kconv if so.
-__device__ __forceinline__ bool prev_converged(DevStatus *st, int k, double dx, double tol, bool writer) {
-    if (k <= 0) return false;
+// Has sweep k-1 met the tolerance?  Records kconv if so.  Only FP64 sweeps
+// (index >= first64) can end the iteration.
+__device__ __forceinline__ bool prev_converged(DevStatus *st, int k, int first64, double dx, double tol,
+                                               bool writer) {
+    if (k <= first64) return false;
     const double r = fmax(dbits(st->rx_bits[(k - 1) & 1]) * dx, dbits(st->re_bits[(k - 1) & 1]));
     if (writer && k - 1 < MAX_HIST) st->res_hist[k - 1] = r;
     if (r <= tol) {
@@ -272,32 +327,65 @@ __device__ __forceinline__ bool prev_converged(DevStatus *st, int k, double dx, 
     return false;
 }
 
-template <int P, bool SEIDEL>
+template <int P>
+__device__ __forceinline__ void to_double(const Moments<P> &m, Moments<P> &o) { o = m; }
+template <int P>
+__device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        o.A[i] = (double)m.A[i] + (double)m.cA[i];
+        o.R[i] = (double)m.R[i] + (double)m.cR[i];
+        o.L[i] = (double)m.L[i] + (double)m.cL[i];
+    }
+}
+
+// One Picard sweep in precision T.  T = double is the method itself; T = float
+// is the cheap first phase of the precision form: the same map with the
+// particle arithmetic, the increments (a float iterate) and the per-lane
+// moments (compensated) in single precision, while the partials, the field
+// update and the convergence test stay in FP64.  A float sweep never ends the
+// iteration and is never committed; the first FP64 sweep after it reads its
+// float increments (d32in).
+template <int P, bool SEIDEL, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
-    __shared__ LdsRec<P> rec[3];   // cells c-1, c, c+1
+    constexpr bool F64 = sizeof(T) == 8;
+    using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
+    __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
+    __shared__ int wcnt[MAX_WAVES][3];
     DevStatus *st = a.st;
     const int item = blockIdx.x;
     if (item >= *a.items.n_items) return;
     if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
-    if (prev_converged(st, k, a.dx, a.tol, threadIdx.x == 0)) return;
-    const double *din = (k & 1) ? a.d1 : a.d0;
-    double *dout = (k & 1) ? a.d0 : a.d1;
+    if (F64 && prev_converged(st, k, a.first64, a.dx, a.tol, threadIdx.x == 0)) return;
+    const T *din;
+    T *dout;
+    if constexpr (F64) {
+        din = (k & 1) ? a.d1 : a.d0;
+        dout = (k & 1) ? a.d0 : a.d1;
+    } else {
+        din = (k & 1) ? a.f1 : a.f0;
+        dout = (k & 1) ? a.f0 : a.f1;
+    }
+    const float *d32in = F64 ? a.d32in : nullptr;   // FP64 sweep right after the float ones
     const double *coefE = (k & 1) ? a.coefE1 : a.coefE0;
     const bool explicit_start = (k == 0) && a.explicit_start;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
-    // first row of this wave (clamped index: lanes past the end recompute the
-    // item's last particle and discard it)
-    int ia = beg + wid * WAVE + lane;
-    double nx, np, nd;
-    {
-        const int il = min(ia, end - 1);
+    int wb, we;
+    wave_range(beg, end, wid, nw, wb, we);
+    // first row of this wave (clamped index: lanes past the run recompute its
+    // last particle and discard it)
+    int ia = wb + lane;
+    double nx = 0.0, np = 0.0;
+    T nd = (T)0;
+    if (wb < we) {
+        const int il = min(ia, we - 1);
         nx = a.xi[il];
         np = a.p[il];
-        nd = explicit_start ? 0.0 : din[il];
+        nd = explicit_start ? (T)0 : (d32in ? (T)d32in[il] : din[il]);
     }
     {
         constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
@@ -306,78 +394,91 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
         const int t = threadIdx.x;
         if (t < 3 * NA) {
             const int r = t / NA, i = t % NA;
-            if (i <= P) rec[r].ay[i] = ra[t];
-            else rec[r].az[i - P - 1] = ra[t];
+            if (i <= P) rec[r].ay[i] = (T)ra[t];
+            else rec[r].az[i - P - 1] = (T)ra[t];
         } else if (t < 3 * NA + 3 * NE) {
             const int u = t - 3 * NA, r = u / NE, i = u % NE;
-            rec[r].eb[i] = re[u];
+            rec[r].eb[i] = (T)re[u];
         }
     }
-    Own<P> o1;
+    Own<P, T> o1;
     {
         const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
         const double *re = coefE + (size_t)rec_index(c) * RecE<P>::N;
 #pragma unroll
-        for (int i = 0; i <= P; ++i) { o1.ay[i] = ra[i]; o1.az[i] = ra[P + 1 + i]; }
+        for (int i = 0; i <= P; ++i) { o1.ay[i] = (T)ra[i]; o1.az[i] = (T)ra[P + 1 + i]; }
 #pragma unroll
-        for (int i = 0; i < P; ++i) o1.eb[i] = re[i];
+        for (int i = 0; i < P; ++i) o1.eb[i] = (T)re[i];
     }
     __syncthreads();
-    Moments<P> mo;
-#pragma unroll
-    for (int i = 0; i < P; ++i) { mo.A[i] = 0.0; mo.R[i] = 0.0; mo.L[i] = 0.0; }
-    double rmax = 0.0;
+    MO mo{};
+    const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx;
+    T rmax = (T)0;
     int flags = 0;
-    const int stride = nw * WAVE;
-    for (int row = beg + wid * WAVE; row < end; row += stride, ia += stride) {
-        Lane La;
-        La.xi0 = nx;
-        La.p0 = np;
+    int nleft = 0, nstay = 0, nright = 0;
+    for (int row = wb; row < we; row += WAVE, ia += WAVE) {
+        Lane<T> La;
+        const double xi0 = nx;
+        La.p0 = (T)np;
         La.d = nd;
-        const bool valid = ia < end;
-        if (row + stride < end) {   // prefetch the next row
-            const int il = min(ia + stride, end - 1);
+        const bool valid = ia < we;
+        if (row + WAVE < we) {   // prefetch the next row
+            const int il = min(ia + WAVE, we - 1);
             nx = a.xi[il];
             np = a.p[il];
-            nd = explicit_start ? 0.0 : din[il];
+            nd = explicit_start ? (T)0 : (d32in ? (T)d32in[il] : din[il]);
         }
-        stage_gather<P>(o1, La, c, explicit_start, a.dt_dx, flags);
+        stage_gather<P, T>(o1, La, xi0, c, explicit_start, dt_dx, flags);
         const bool cross1 = __ballot(La.s != 0) != 0;
-        double pa, dna;
-        stage_push<P>(o1, rec, cross1, La, a.dt, a.dt_dx, a.inv_dx, pa, dna, flags);
+        T pa, dna;
+        stage_push<P, T>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
         if (valid) {
-            if (!SEIDEL && explicit_start) a.d0[ia] = La.d;   // keep d^(0) for a Jacobi commit
+            // keep d^(k) in FP64 where a Jacobi commit may take it
+            if constexpr (F64)
+                if (!SEIDEL && (explicit_start || d32in)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
             dout[ia] = dna;
             rmax = fmax(rmax, fabs(dna - La.d));
         }
-        const double w = valid ? 1.0 : 0.0;
+        const T w = valid ? (T)1 : (T)0;
+        int sc;   // cell change of the increment a commit after this sweep would take
         if (SEIDEL) {
-            double ta;
-            int sa;
-            end_point(La.xi0, dna, c, ta, sa, flags);
-            stage_deposit<P>(mo, __ballot(sa != 0) != 0, La.t0, ta, sa, w);
+            T ta;
+            if constexpr (F64) end_point(xi0, dna, c, ta, sc, flags);
+            else end_point(La.t0, dna, ta, sc, flags);
+            stage_deposit<P, T>(mo, __ballot(sc != 0) != 0, La.t0, ta, sc, w);
         } else {
-            stage_deposit<P>(mo, cross1, La.t0, La.t1, La.s, w);
+            sc = La.s;
+            stage_deposit<P, T>(mo, cross1, La.t0, La.t1, La.s, w);
+        }
+        if constexpr (F64) {
+            nleft += __popcll(__ballot(valid && sc < 0));
+            nright += __popcll(__ballot(valid && sc > 0));
+            nstay += __popcll(__ballot(valid && sc == 0));
         }
     }
-    const double slot = moments_to_slots<P>(mo);
-    rmax = wave_max_dpp(rmax);
+    Moments<P> md;
+    to_double<P>(mo, md);
+    const double slot = moments_to_slots<P>(md);
+    const double rm = wave_max_dpp((double)rmax);
     const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
-    double *out = a.part + ((size_t)item * nw + wid) * (P + 4);
-    if (lane < P + 2) out[lane] = slot;
-    else if (lane == P + 2) out[lane] = rmax;
-    else if (lane == P + 3) out[lane] = (double)fl;
-}
-
-// Partial sums of the items of cell c (usually one item), slot by slot.
-template <int NS>
-__device__ __forceinline__ void cell_partials(const ItemList &it, const double *part, int c, double (&v)[NS]) {
-#pragma unroll
-    for (int q = 0; q < NS; ++q) v[q] = 0.0;
-    const int i0 = it.cell_first[c], i1 = it.cell_first[c + 1];
-    for (int i = i0; i < i1; ++i) {
-#pragma unroll
-        for (int q = 0; q < NS; ++q) v[q] += part[(size_t)i * NS + q];
+    double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
+    double v = slot;
+    v = lane == P + 2 ? rm : v;
+    v = lane == P + 3 ? (double)fl : v;
+    if (lane < UnitI<P>::N) out[lane] = v;
+    if constexpr (F64) {
+        if (lane == 0) { wcnt[wid][0] = nleft; wcnt[wid][1] = nstay; wcnt[wid][2] = nright; }
+        __syncthreads();
+        if (lane < 3) {
+            int pre = 0, tot = 0;
+            for (int w = 0; w < nw; ++w) {
+                const int n = wcnt[w][lane];
+                pre += w < wid ? n : 0;
+                tot += n;
+            }
+            a.wpre[((size_t)item * nw + wid) * 3 + lane] = pre;
+            if (wid == 0) a.cnt[(size_t)item * 3 + lane] = tot;
+        }
     }
 }
 
@@ -390,7 +491,7 @@ __device__ __forceinline__ void cell_partials_I(const ItemList &it, const double
     for (int q = 0; q < P + 2; ++q) v[q] = 0.0;
     const int u0 = it.cell_first[c] * wpi, u1 = it.cell_first[c + 1] * wpi;
     for (int u = u0; u < u1; ++u) {
-        const double *w = part + (size_t)u * (P + 4);
+        const double *w = part + (size_t)u * UnitI<P>::N;
 #pragma unroll
         for (int q = 0; q < P + 2; ++q) v[q] += w[q];
         rx = fmax(rx, w[P + 2]);
@@ -511,9 +612,9 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
 
 // Records of a substep start: A-records of a_perp and E-records of e.
 template <int P>
-__global__ void __launch_bounds__(256) k_prep_records(const DevStatus *st, const double *ay, const double *az,
+__global__ void __launch_bounds__(256) k_prep_records(DevStatus *st_init, const double *ay, const double *az,
                                                       const double *e, double *coefA, double *coefE, int M) {
-    if (st && !st->gate) return;
+    if (st_init && blockIdx.x == 0 && threadIdx.x == 0) init_status(st_init, nullptr);
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= M) return;
     double ry[P + 1], rz[P + 1];
@@ -553,16 +654,18 @@ __device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a, int kc) 
     return r;
 }
 
+// The scatter runs when the substep converged (kconv >= 0) without a flag.
 __device__ __forceinline__ bool commit_enabled(const DevStatus *st) {
-    return st->gate && st->kconv >= 0 && !st->committed && st->flags == 0;
+    return st->gate && st->kconv >= 0 && st->flags == 0;
 }
 
 // Converged sweep index for the commit, making the test of the last enqueued
 // sweep if no later sweep made it; -1 if the commit must not run.
-__device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, double dx, double tol, bool writer) {
+__device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first64, double dx, double tol,
+                                           bool writer) {
     if (!st->gate || st->flags || st->committed) return -1;
     if (st->kconv >= 0) return st->kconv;
-    return prev_converged(st, nsweeps, dx, tol, writer) ? nsweeps - 1 : -1;
+    return prev_converged(st, nsweeps, first64, dx, tol, writer) ? nsweeps - 1 : -1;
 }
 
 __device__ __forceinline__ int mover_type(double xi0, double d, int c) {
@@ -570,34 +673,17 @@ __device__ __forceinline__ int mover_type(double xi0, double d, int c) {
     return t1 >= 1.0 ? 2 : (t1 < 0.0 ? 0 : 1);   // 0 left, 1 stay, 2 right
 }
 
-__global__ void __launch_bounds__(MAX_BLOCK) k_commit_count(CommitIArgs a) {
-    __shared__ int lds[MAX_WAVES * 3];
-    const int item = blockIdx.x;
-    const int kc = settle_last(a.st, a.nsweeps, a.dx, a.tol, item == 0 && threadIdx.x == 0);
-    if (kc < 0) return;
-    if (item >= *a.items.n_items) return;
-    const CommitPick pk = commit_pick(a, kc);
-    const int c = a.items.cell[item];
-    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
-    int n0 = 0, n1 = 0, n2 = 0;
-    for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-        const int t = mover_type(a.cur.xi[i], pk.d[i], c);
-        n0 += t == 0; n1 += t == 1; n2 += t == 2;
-    }
-    n0 = wave_isum(n0); n1 = wave_isum(n1); n2 = wave_isum(n2);
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    if (lane == 0) { lds[wid * 3] = n0; lds[wid * 3 + 1] = n1; lds[wid * 3 + 2] = n2; }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        int s = 0;
-        for (int w = 0; w < (int)(blockDim.x + WAVE - 1) / WAVE; ++w) s += lds[w * 3 + threadIdx.x];
-        a.cnt[item * 3 + threadIdx.x] = s;
-    }
-}
-
+// Single block: settles the convergence test, then from the mover counts the
+// converged sweep left computes the destinations of every item's left / stay /
+// right movers, the item list of the new order and e_x^{n+1}.
+template <int P>
 __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     __shared__ int lds[40];
-    if (!commit_enabled(a.st)) return;
+    __shared__ int kcs;
+    if (threadIdx.x == 0) kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, true);
+    __syncthreads();
+    const int kc = kcs;
+    if (kc < 0) return;
     const int M = a.M;
     const ItemList &it = a.items;
     // totals per old cell and exclusive prefix of each item within its cell
@@ -617,7 +703,7 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     __syncthreads();
     scan_cells(ncount, a.nstart, M, lds);
     __syncthreads();
-    // destination bases of each old item's three groups
+    // destination bases of each item's three groups
     for (int c = threadIdx.x; c < M; c += blockDim.x) {
         const int cm = imod(c - 1, M), cp = imod(c + 1, M), cmm = imod(c - 2, M);
         const int bL = a.nstart[cm] + a.tot[cmm * 3 + 2] + a.tot[cm * 3 + 1];
@@ -633,29 +719,40 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     build_items(ncount, a.nstart, M, a.chunk, a.N, a.items_next, lds);
     __syncthreads();
     // e_x^{n+1}
-    const CommitPick pk = commit_pick(a, a.st->kconv);
+    const CommitPick pk = commit_pick(a, kc);
     for (int idx = threadIdx.x; idx < M + 2 * HALO; idx += blockDim.x) a.ex_next[idx] = pk.enew[idx];
+    if (threadIdx.x == 0) {
+        a.st->n_items_next = *a.items_next.n_items;
+        a.st->committed = 1;
+    }
 }
 
+// Moves every particle to its place in the new cell order, with the committed
+// momentum re-evaluated.  Each wave handles the same run of rows as in the
+// sweep, so its movers of each kind are consecutive from the base the scan
+// gave it; ballots rank them within a row.
 template <int P>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
-    __shared__ int wc[MAX_WAVES][3];
     const int item = blockIdx.x;
     if (item >= *a.items.n_items || !commit_enabled(a.st)) return;
     const CommitPick pk = commit_pick(a, a.st->kconv);
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int M = a.M;
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    int wb, we;
+    wave_range(beg, end, wid, nw, wb, we);
     Coef1<P> kc;
     load_coef1<P>(kc, c, a.coefA, pk.coefE);
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const int nw = (blockDim.x + WAVE - 1) / WAVE;
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    int run0 = a.base[item * 3 + 0], run1 = a.base[item * 3 + 1], run2 = a.base[item * 3 + 2];
+    const int32_t *bs = a.base + (size_t)item * 3;
+    const int32_t *ws = a.wpre + ((size_t)item * nw + wid) * 3;
+    int run0 = bs[0] + ws[0], run1 = bs[1] + ws[1], run2 = bs[2] + ws[2];
     int flags = 0;
-    for (int r0 = beg; r0 < end; r0 += blockDim.x) {
-        const int i = r0 + threadIdx.x;
-        const bool valid = i < end;
+    for (int r0 = wb; r0 < we; r0 += WAVE) {
+        const int i = r0 + lane;
+        const bool valid = i < we;
         int t = -1;
         double xin = 0.0, p1 = 0.0;
         int32_t pid = 0;
@@ -675,52 +772,38 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
             }
         }
         const unsigned long long b0 = __ballot(t == 0), b1 = __ballot(t == 1), b2 = __ballot(t == 2);
-        if (lane == 0) { wc[wid][0] = __popcll(b0); wc[wid][1] = __popcll(b1); wc[wid][2] = __popcll(b2); }
-        __syncthreads();
-        int pre0 = 0, pre1 = 0, pre2 = 0, s0 = 0, s1 = 0, s2 = 0;
-        for (int q = 0; q < nw; ++q) {
-            if (q < wid) { pre0 += wc[q][0]; pre1 += wc[q][1]; pre2 += wc[q][2]; }
-            s0 += wc[q][0]; s1 += wc[q][1]; s2 += wc[q][2];
-        }
         if (valid) {
             int dest;
-            if (t == 0) dest = run0 + pre0 + __popcll(b0 & lt);
-            else if (t == 1) dest = run1 + pre1 + __popcll(b1 & lt);
-            else dest = run2 + pre2 + __popcll(b2 & lt);
+            if (t == 0) dest = run0 + __popcll(b0 & lt);
+            else if (t == 1) dest = run1 + __popcll(b1 & lt);
+            else dest = run2 + __popcll(b2 & lt);
             a.nxt.xi[dest] = xin;
             a.nxt.p[dest] = p1;
             a.nxt.id[dest] = pid;
         }
-        run0 += s0; run1 += s1; run2 += s2;
-        __syncthreads();
+        run0 += __popcll(b0);
+        run1 += __popcll(b1);
+        run2 += __popcll(b2);
     }
-    flags = wave_or(flags);
-    if (lane == 0 && flags) atomicOr(&a.st->flags, flags);
+    if (__ballot(flags != 0)) {
+        flags = wave_or(flags);
+        if (lane == 0) atomicOr(&a.st->flags, flags);
+    }
 }
 
-__global__ void k_mark_committed(DevStatus *st) {
-    if (st->kconv >= 0 && !st->committed && st->flags == 0 && st->gate) st->committed = 1;
-}
-
-__global__ void k_begin(DevStatus *st, const DevStatus *gate) {
-    st->rx_bits[0] = 0ull;
-    st->rx_bits[1] = 0ull;
-    st->re_bits[0] = 0ull;
-    st->re_bits[1] = 0ull;
-    st->kconv = -1;
-    st->committed = 0;
-    st->flags = 0;
-    st->fp32_sweeps = 0;
-    st->res = 0.0;
-    st->gate = gate ? gate->committed : 1;   // 0: every kernel of the substep skips
-}
+__global__ void k_begin(DevStatus *st, const DevStatus *gate) { init_status(st, gate); }
 
 // ---- launchers ------------------------------------------------------------
-void launch_sweep_I(int P, bool seidel, int grid, int block, hipStream_t s, const SweepIArgs &a) {
-#define ECPIC_SW(PP)                                                                              \
-    case PP:                                                                                      \
-        if (seidel) hipLaunchKernelGGL((k_sweep_I<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
-        else hipLaunchKernelGGL((k_sweep_I<PP, false>), dim3(grid), dim3(block), 0, s, a);        \
+void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a) {
+#define ECPIC_SW(PP)                                                                                         \
+    case PP:                                                                                                 \
+        if (fp32) {                                                                                          \
+            if (seidel) hipLaunchKernelGGL((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), 0, s, a);  \
+            else hipLaunchKernelGGL((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), 0, s, a);        \
+        } else {                                                                                             \
+            if (seidel) hipLaunchKernelGGL((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), 0, s, a); \
+            else hipLaunchKernelGGL((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), 0, s, a);       \
+        }                                                                                                    \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW
@@ -735,7 +818,7 @@ void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
 #undef ECPIC_F
 }
 
-void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double *ay, const double *az,
+void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, const double *az,
                          const double *e, double *coefA, double *coefE, int M) {
     const int grid = (M + 255) / 256;
 #define ECPIC_PR(PP) \
@@ -745,18 +828,18 @@ void launch_prep_records(int P, hipStream_t s, const DevStatus *st, const double
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
-    hipLaunchKernelGGL(k_commit_count, dim3(grid), dim3(block), 0, s, a);
-    hipLaunchKernelGGL(k_commit_scan, dim3(1), dim3(1024), 0, s, a);
-#define ECPIC_C(PP) case PP: hipLaunchKernelGGL((k_commit_scatter<PP>), dim3(grid), dim3(block), 0, s, a); break;
+#define ECPIC_C(PP)                                                                              \
+    case PP:                                                                                     \
+        hipLaunchKernelGGL((k_commit_scan<PP>), dim3(1), dim3(1024), 0, s, a);                   \
+        hipLaunchKernelGGL((k_commit_scatter<PP>), dim3(grid), dim3(block), 0, s, a);            \
+        break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C
-    hipLaunchKernelGGL(k_mark_committed, dim3(1), dim3(1), 0, s, a.st);
 }
 
 void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s) {
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, st, gate);
 }
 
-void launch_mark(DevStatus *st, hipStream_t s) { hipLaunchKernelGGL(k_mark_committed, dim3(1), dim3(1), 0, s, st); }
 
 }  // namespace ecpic

@@ -241,68 +241,79 @@ struct Stencil {
     int half;
 };
 
-// Start of Subsystem II: A-records of a^n and of a^(0) = a^n - dt e^n.
+// Start of Subsystem II.  Block 0 resets the status (gated on Subsystem I
+// having committed).  Block b, on cells b * FIELD2_OUT .. + FIELD2_OUT - 1,
+// writes the A-records of a^n and of a^(0) = a^n - dt e^n (the iterate for
+// e^(0) = e^n), and the constant part of every iterate,
+//   E0 = A^-1 [(M0^ - r^2 K^) e^n + (dt/dx^2) K^ a^n],   A = M0^ + r^2 K^,
+// with the stencils applied on a window in LDS and A^-1 as a convolution by
+// four lanes per output.
 template <int P>
-__global__ void __launch_bounds__(256) k_prep_II(const DevStatus *st, const double *ayn, const double *azn,
-                                                 const double *eyn, const double *ezn, double dt, double *coefAn,
-                                                 double *coefAk0, int M) {
-    if (!st->gate) return;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= M) return;
-    constexpr Pieces<P> B{};
-    constexpr int NA = RecA<P>::N;
-    for (int i = 0; i <= P; ++i) {
-        double ny = 0.0, nz = 0.0, ky = 0.0, kz = 0.0;
-        for (int m = 0; m <= P; ++m) {
-            const int j = c - m + HALO;
-            ny += ayn[j] * B.c[m][i];
-            nz += azn[j] * B.c[m][i];
-            ky += (ayn[j] - dt * eyn[j]) * B.c[m][i];
-            kz += (azn[j] - dt * ezn[j]) * B.c[m][i];
-        }
-        store_record(coefAn, M, c, NA, i, ny);
-        store_record(coefAn, M, c, NA, P + 1 + i, nz);
-        store_record(coefAk0, M, c, NA, i, ky);
-        store_record(coefAk0, M, c, NA, P + 1 + i, kz);
-    }
-}
-
-// E0 = A^{-1} [(M0^ - r^2 K^) e^n + (dt/dx^2) K^ a^n] for both components: the
-// right-hand side is formed on the block's input window in LDS and convolved
-// with the first row of A^{-1}.
-__global__ void __launch_bounds__(256) k_E0_II(const DevStatus *st, const double *eyn, const double *ezn,
-                                               const double *ayn, const double *azn, Stencil m0, Stencil kk,
-                                               double r2, double ck, const double *taps, int ntaps, int mlo, int M,
-                                               double *E0y, double *E0z) {
-    extern __shared__ double R[];   // [2][256 + ntaps]
-    if (!st->gate) return;
-    const int j0 = blockIdx.x * 256;
+__global__ void __launch_bounds__(256) k_begin_II(DevStatus *st, const DevStatus *gate_src, const double *ayn,
+                                                  const double *azn, const double *eyn, const double *ezn,
+                                                  double dt, double *coefAn, double *coefAk0, Stencil m0,
+                                                  Stencil kk, double r2, double ck, const double *taps, int ntaps,
+                                                  int mlo, int M, double *E0y, double *E0z) {
+    extern __shared__ double R[];   // [2][FIELD2_OUT + ntaps - 1] + taps
+    const bool g = gate_src ? (gate_src->committed && gate_src->flags == 0) : true;
+    if (blockIdx.x == 0 && threadIdx.x == 0) init_status(st, gate_src);
+    if (!g) return;
+    const int j0 = blockIdx.x * FIELD2_OUT;
     const int mhi = mlo + ntaps - 1;
-    const int len = 256 + ntaps - 1;
-    double *Ry = R, *Rz = R + len;
+    const int len = FIELD2_OUT + ntaps - 1;
+    double *Ry = R, *Rz = R + len, *tp = Rz + len;
+    for (int t = threadIdx.x; t < ntaps; t += blockDim.x) tp[t] = taps[t];
     for (int idx = threadIdx.x; idx < len; idx += blockDim.x) {
         const int j = imod(j0 - mhi + idx, M);
         double sy = 0.0, sz = 0.0;
         for (int q = -m0.half; q <= m0.half; ++q) {
             const double cm = m0.v[q + m0.half] - r2 * kk.v[q + kk.half];
             const double ka = ck * kk.v[q + kk.half];
-            sy += cm * eyn[j + q + HALO] + ka * ayn[j + q + HALO];
-            sz += cm * ezn[j + q + HALO] + ka * azn[j + q + HALO];
+            const int jq = imod(j + q, M) + HALO;
+            sy += cm * eyn[jq] + ka * ayn[jq];
+            sz += cm * ezn[jq] + ka * azn[jq];
         }
         Ry[idx] = sy;
         Rz[idx] = sz;
     }
-    __syncthreads();
-    const int j = j0 + threadIdx.x;
-    if (j >= M) return;
-    double cy = 0.0, cz = 0.0;
-    for (int i = 0; i < ntaps; ++i) {
-        const int o = threadIdx.x + mhi - (mlo + i);
-        cy = fma(taps[i], Ry[o], cy);
-        cz = fma(taps[i], Rz[o], cz);
+    {
+        const int c = j0 + (int)threadIdx.x;
+        if ((int)threadIdx.x < FIELD2_OUT && c < M) {
+            constexpr Pieces<P> B{};
+            constexpr int NA = RecA<P>::N;
+            for (int i = 0; i <= P; ++i) {
+                double ny = 0.0, nz = 0.0, ky = 0.0, kz = 0.0;
+                for (int m = 0; m <= P; ++m) {
+                    const int j = c - m + HALO;
+                    ny += ayn[j] * B.c[m][i];
+                    nz += azn[j] * B.c[m][i];
+                    ky += (ayn[j] - dt * eyn[j]) * B.c[m][i];
+                    kz += (azn[j] - dt * ezn[j]) * B.c[m][i];
+                }
+                store_record(coefAn, M, c, NA, i, ny);
+                store_record(coefAn, M, c, NA, P + 1 + i, nz);
+                store_record(coefAk0, M, c, NA, i, ky);
+                store_record(coefAk0, M, c, NA, P + 1 + i, kz);
+            }
+        }
     }
-    E0y[j] = cy;
-    E0z[j] = cz;
+    __syncthreads();
+    const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
+    const double *Ryq = Ry + quad + ntaps - 1, *Rzq = Rz + quad + ntaps - 1;
+    double cy = 0.0, cz = 0.0;
+    for (int i = ql; i < ntaps; i += 4) {
+        cy = fma(tp[i], Ryq[-i], cy);
+        cz = fma(tp[i], Rzq[-i], cz);
+    }
+    cy += dpp_d<0xB1>(cy);
+    cz += dpp_d<0xB1>(cz);
+    cy += dpp_d<0x4E>(cy);
+    cz += dpp_d<0x4E>(cz);
+    const int j = j0 + quad;
+    if (ql == 0 && j < M) {
+        E0y[j] = cy;
+        E0z[j] = cz;
+    }
 }
 
 // out_j = alpha * sum_i taps[i] in[(j - mlo - i) mod M]  (in, out unpadded)
@@ -315,18 +326,22 @@ __global__ void __launch_bounds__(256) k_conv(const double *in, double *out, con
     out[j] = alpha * s;
 }
 
+// Commit of Subsystem II: e_perp^{n+1} = e^(kc+1), a^{n+1} = a^n - dt/2 (e^n + e^{n+1}).
+// Every block settles the convergence test on its own (same answer); block 0
+// records the commit.  Running it again is harmless (same writes).
 __global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const double *eyn, const double *ezn,
                                                    const double *ayn, const double *azn, const double *ey0,
                                                    const double *ey1, const double *ez0, const double *ez1,
                                                    double *ey_next, double *ez_next, double *ay_next,
                                                    double *az_next, double half_dt, int M, int nsweeps,
                                                    double tol) {
-    if (!st->gate || st->flags || st->committed) return;
+    if (!st->gate || st->flags) return;
     int kc = st->kconv;
     if (kc < 0) {
         if (!prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0)) return;
         kc = nsweeps - 1;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->committed = 1;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const double *eya = ((kc + 1) & 1) ? ey1 : ey0;
@@ -353,27 +368,22 @@ void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
 #undef ECPIC_F2
 }
 
-void launch_prep_II(int P, hipStream_t s, const DevStatus *st, const double *ayn, const double *azn,
-                    const double *eyn, const double *ezn, double dt, double *coefAn, double *coefAk0, int M) {
-    const int grid = (M + 255) / 256;
-#define ECPIC_P2(PP)                                                                                       \
-    case PP:                                                                                               \
-        hipLaunchKernelGGL((k_prep_II<PP>), dim3(grid), dim3(256), 0, s, st, ayn, azn, eyn, ezn, dt, coefAn, \
-                           coefAk0, M);                                                                    \
-        break;
-    switch (P) { ECPIC_P2(2) ECPIC_P2(3) ECPIC_P2(4) ECPIC_P2(5) }
-#undef ECPIC_P2
-}
-
-void launch_E0_II(hipStream_t s, const DevStatus *st, const double *eyn, const double *ezn, const double *ayn,
-                  const double *azn, const double *m0, const double *kr, int P, double r2, double ck,
-                  const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z) {
+void launch_begin_II(int P, hipStream_t s, DevStatus *st, const DevStatus *gate_src, const double *ayn,
+                     const double *azn, const double *eyn, const double *ezn, double dt, double *coefAn,
+                     double *coefAk0, const double *m0, const double *kr, double r2, double ck, const double *taps,
+                     int ntaps, int mlo, int M, double *E0y, double *E0z) {
     Stencil a{}, b{};
     a.half = P; b.half = P;
     for (int q = 0; q <= 2 * P; ++q) { a.v[q] = m0[q]; b.v[q] = kr[q]; }
-    const size_t lds = sizeof(double) * 2 * (256 + ntaps);
-    hipLaunchKernelGGL(k_E0_II, dim3((M + 255) / 256), dim3(256), lds, s, st, eyn, ezn, ayn, azn, a, b, r2, ck, taps,
-                       ntaps, mlo, M, E0y, E0z);
+    const int grid = (M + FIELD2_OUT - 1) / FIELD2_OUT;
+    const size_t lds = sizeof(double) * (2 * (FIELD2_OUT + ntaps - 1) + ntaps);
+#define ECPIC_B2(PP)                                                                                        \
+    case PP:                                                                                                \
+        hipLaunchKernelGGL((k_begin_II<PP>), dim3(grid), dim3(256), lds, s, st, gate_src, ayn, azn, eyn, ezn, \
+                           dt, coefAn, coefAk0, a, b, r2, ck, taps, ntaps, mlo, M, E0y, E0z);               \
+        break;
+    switch (P) { ECPIC_B2(2) ECPIC_B2(3) ECPIC_B2(4) ECPIC_B2(5) }
+#undef ECPIC_B2
 }
 
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
