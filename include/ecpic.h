@@ -168,6 +168,64 @@ int ecpic_energy(ecpic_ctx *ctx, ecpic_energy_parts *out);
  * *linf = max_j |r_j|; vec (length M) may be NULL. */
 int ecpic_gauss_residual(ecpic_ctx *ctx, double *linf, double *vec);
 
+/* ---- Learned warm start of Subsystem I ------------------------------------
+ * The initial Picard iterate of Subsystem I (Section 4.2 leaves it open) can
+ * come from a small network instead of the explicit predictor: an MLP
+ * D -> 64 -> 64 -> 2, GELU (tanh form), D = 3 + 6 (degree + 1), fed the
+ * particle's features
+ *   [t - 1/2, p, gamma0 - 1, a_y[c-p..c+p+1], a_z[c-p..c+p+1], e_x[c-p..c+p+1]]
+ * (t = x/dx - c in cell c, gamma0 = sqrt(1 + p^2 + |A_perp(x)|^2)) and trained
+ * on the converged increments
+ *   [(delta - dt p/gamma0)/dt^2, (p^{n+1} - p)/dt].
+ * With the network enabled every Subsystem I substep starts with a predictor
+ * pass: the network is evaluated per cell on an 8 x 8 grid of (t, p) nodes
+ * (BF16 matrix cores, FP32 accumulation), each particle interpolates its cell's
+ * table for delta^(1), and the current of delta^(1) gives a consistent e^(1);
+ * the ordinary Picard sweeps follow to the same tolerance, so the network only
+ * changes how many are needed.  Parameters are one flat float vector
+ *   [W1 (64 x D) | b1 | W2 (64 x 64) | b2 | W3 (2 x 64) | b3 |
+ *    mu (D + 2) | sd (D + 2) | p_lo, p_hi]
+ * (normalisation of features and targets, momentum range of the table). */
+typedef struct {
+    int32_t steps;   /* Adam steps; 0 => 2000 */
+    int32_t batch;   /* samples per step, a multiple of 32; 0 => 1024 */
+    float lr;        /* Adam step size; 0 => 1e-3 */
+    uint64_t seed;   /* initial weights and sample draws (counter-based) */
+} ecpic_ws_train_config;
+
+/* From the next step on, record one training pair per committed Subsystem I
+ * substep for every particle with id % stride == (step count % stride), into a
+ * device buffer of `capacity` pairs (reallocated if the capacity changes;
+ * recording restarts from empty).  stride = 0 stops recording.  ENOMEM if the
+ * buffer cannot be allocated. */
+int ecpic_ws_record(ecpic_ctx *ctx, int32_t stride, int64_t capacity);
+/* Number of pairs held (at most the capacity). */
+int ecpic_ws_records(ecpic_ctx *ctx, int64_t *n);
+/* Copy the first n pairs to host arrays feat (n x D) and targ (n x 2) (either may
+ * be NULL); EINVAL if n exceeds the pairs held. */
+int ecpic_ws_get_records(ecpic_ctx *ctx, float *feat, float *targ, int64_t n);
+/* Train from scratch on the recorded pairs (FP32 forward/backward and Adam on
+ * the GPU; normalisation from the pairs' mean and standard deviation).
+ * *final_loss = mean squared error (normalised targets) of the last batch.
+ * ESTATE without recorded pairs. */
+int ecpic_ws_train(ecpic_ctx *ctx, const ecpic_ws_train_config *cfg, float *final_loss);
+/* Length of the flat parameter vector. */
+int ecpic_ws_n_params(ecpic_ctx *ctx, int64_t *n);
+/* Copy the parameters out / in (host arrays of ecpic_ws_n_params floats). */
+int ecpic_ws_get_weights(ecpic_ctx *ctx, float *w, int64_t n);
+int ecpic_ws_set_weights(ecpic_ctx *ctx, const float *w, int64_t n);
+/* Use (on != 0) or stop using the network for the following substeps; ESTATE
+ * if it has neither been trained nor set. */
+int ecpic_ws_enable(ecpic_ctx *ctx, int32_t on);
+/* Gradient (length n_params minus the normalisation tail) and loss of the mean
+ * squared error over n samples given already normalised: x (n x D), y (n x 2),
+ * host arrays.  The computation is the training kernels'.  ESTATE without a
+ * network. */
+int ecpic_ws_grad(ecpic_ctx *ctx, const float *x, const float *y, int64_t n, float *grad, float *loss);
+/* The per-cell tables of the increment target (physical units, [M][8 t][8 p],
+ * t_i = i/7, p_j = p_lo + j (p_hi - p_lo)/7) for the current state; host array. */
+int ecpic_ws_table(ecpic_ctx *ctx, float *table);
+
 /* Per-kernel timing with HIP events on the context's stream.  enable != 0 starts
  * recording (and clears the totals); ecpic_kernel_time returns the accumulated
  * milliseconds and launch count of the named kernel family ("sweep_I",

@@ -26,6 +26,8 @@ EXPORTS = (
     "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_fields", "ecpic_step",
     "ecpic_deposit_current", "ecpic_deposit_charge", "ecpic_energy", "ecpic_gauss_residual",
     "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_bandwidth_probe", "ecpic_strerror",
+    "ecpic_ws_record", "ecpic_ws_records", "ecpic_ws_get_records", "ecpic_ws_train", "ecpic_ws_n_params",
+    "ecpic_ws_get_weights", "ecpic_ws_set_weights", "ecpic_ws_enable", "ecpic_ws_grad", "ecpic_ws_table",
 )
 
 
@@ -44,6 +46,10 @@ class Config(C.Structure):
 
 class IterStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("fp32_sweeps", C.c_int32), ("residual", C.c_double)]
+
+
+class WsTrainConfig(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64)]
 
 
 class EnergyParts(C.Structure):
@@ -82,6 +88,18 @@ def load() -> C.CDLL:
         L.ecpic_profile_enable.argtypes = [V, C.c_int32]
         L.ecpic_kernel_time.argtypes = [V, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.ecpic_bandwidth_probe.argtypes = [V, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
+        I64P = C.POINTER(C.c_int64)
+        FP = C.POINTER(C.c_float)
+        L.ecpic_ws_record.argtypes = [V, C.c_int32, C.c_int64]
+        L.ecpic_ws_records.argtypes = [V, I64P]
+        L.ecpic_ws_get_records.argtypes = [V, V, V, C.c_int64]
+        L.ecpic_ws_train.argtypes = [V, C.POINTER(WsTrainConfig), FP]
+        L.ecpic_ws_n_params.argtypes = [V, I64P]
+        L.ecpic_ws_get_weights.argtypes = [V, V, C.c_int64]
+        L.ecpic_ws_set_weights.argtypes = [V, V, C.c_int64]
+        L.ecpic_ws_enable.argtypes = [V, C.c_int32]
+        L.ecpic_ws_grad.argtypes = [V, V, V, C.c_int64, V, FP]
+        L.ecpic_ws_table.argtypes = [V, V]
         L.ecpic_strerror.argtypes = [C.c_int]
         L.ecpic_strerror.restype = C.c_char_p
         for f in EXPORTS:
@@ -248,6 +266,63 @@ class Context:
         _ck(self._lib.ecpic_deposit_current(self._h, x0.ctypes.data, x1.ctypes.data, len(x0), J.ctypes.data),
             "deposit_current")
         return J
+
+    # -- learned warm start -----------------------------------------------------
+    def ws_record(self, stride: int, capacity: int = 0):
+        _ck(self._lib.ecpic_ws_record(self._h, int(stride), int(capacity)), "ws_record")
+
+    def ws_records(self) -> int:
+        n = C.c_int64(0)
+        _ck(self._lib.ecpic_ws_records(self._h, C.byref(n)), "ws_records")
+        return n.value
+
+    def ws_n_features(self) -> int:
+        return 3 + 6 * (self.cfg.degree + 1)
+
+    def ws_get_records(self, n: Optional[int] = None):
+        n = self.ws_records() if n is None else int(n)
+        f = np.empty((n, self.ws_n_features()), np.float32)
+        t = np.empty((n, 2), np.float32)
+        _ck(self._lib.ecpic_ws_get_records(self._h, f.ctypes.data, t.ctypes.data, n), "ws_get_records")
+        return f, t
+
+    def ws_train(self, steps: int = 0, batch: int = 0, lr: float = 0.0, seed: int = 0) -> float:
+        cfg = WsTrainConfig(int(steps), int(batch), float(lr), int(seed))
+        loss = C.c_float(0.0)
+        _ck(self._lib.ecpic_ws_train(self._h, C.byref(cfg), C.byref(loss)), "ws_train")
+        return loss.value
+
+    def ws_n_params(self) -> int:
+        n = C.c_int64(0)
+        _ck(self._lib.ecpic_ws_n_params(self._h, C.byref(n)), "ws_n_params")
+        return n.value
+
+    def ws_get_weights(self) -> np.ndarray:
+        w = np.empty(self.ws_n_params(), np.float32)
+        _ck(self._lib.ecpic_ws_get_weights(self._h, w.ctypes.data, len(w)), "ws_get_weights")
+        return w
+
+    def ws_set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _ck(self._lib.ecpic_ws_set_weights(self._h, w.ctypes.data, len(w)), "ws_set_weights")
+
+    def ws_enable(self, on: bool = True):
+        _ck(self._lib.ecpic_ws_enable(self._h, int(bool(on))), "ws_enable")
+
+    def ws_grad(self, x, y):
+        x = np.ascontiguousarray(x, dtype=np.float32); y = np.ascontiguousarray(y, dtype=np.float32)
+        n = x.shape[0]
+        D = self.ws_n_features()
+        g = np.empty(self.ws_n_params() - 2 * (D + 2) - 2, np.float32)
+        loss = C.c_float(0.0)
+        _ck(self._lib.ecpic_ws_grad(self._h, x.ctypes.data, y.ctypes.data, n, g.ctypes.data, C.byref(loss)),
+            "ws_grad")
+        return g, loss.value
+
+    def ws_table(self) -> np.ndarray:
+        t = np.empty((self.M, 8, 8), np.float32)
+        _ck(self._lib.ecpic_ws_table(self._h, t.ctypes.data), "ws_table")
+        return t
 
     # -- timing -----------------------------------------------------------------
     def profile(self, enable: bool = True):

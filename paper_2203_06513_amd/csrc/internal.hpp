@@ -60,6 +60,30 @@ struct Particles {
     int32_t *id;
 };
 
+// ---- learned warm start ----------------------------------------------------
+// A multilayer perceptron D -> 64 -> 64 -> 2 (GELU, tanh form) predicts the
+// converged increment of Subsystem I from a particle's local state.  It is
+// evaluated per cell on a WS_NT x WS_NP grid of (local coordinate, momentum)
+// nodes and the particles interpolate their cell's table.
+constexpr int WS_H = 64;
+constexpr int WS_NT = 8, WS_NP = 8;
+__host__ __device__ constexpr int ws_d(int P) { return 3 + 6 * (P + 1); }
+__host__ __device__ constexpr int ws_nparams(int D) { return WS_H * D + WS_H + WS_H * WS_H + WS_H + 2 * WS_H + 2; }
+
+struct WsNet {
+    const float *theta;      // [W1 (H x D) | b1 | W2 (H x H) | b2 | W3 (2 x H) | b3]
+    const float *mu, *sd;    // [D + 2] normalisation of the features, then of the targets
+    const float *prange;     // [2] momentum range of the table nodes
+};
+
+struct WsRecord {
+    float *feat, *targ;      // [cap][D], [cap][2]
+    int64_t cap;
+    int64_t base;            // first slot of this step
+    int32_t stride, phase;   // record the particles with id % stride == phase (stride 0: off)
+    const double *ay, *az, *ex;   // padded a_perp^n, e_x^n
+};
+
 // ---- Subsystem I ---------------------------------------------------------
 struct SweepIArgs {
     const double *xi, *p;
@@ -78,6 +102,9 @@ struct SweepIArgs {
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
     int32_t k;                     // sweep index
     int32_t first64;               // index of the first FP64 sweep (0 for the plain method)
+    const float *table;            // warm-start tables [M][WS_NT * WS_NP] (predictor pass)
+    const float *prange;           // their momentum range
+    const float *ytarget;          // target normalisation (mu, sd of the increment target)
 };
 
 struct FieldIArgs {
@@ -111,6 +138,7 @@ struct CommitIArgs {
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
+    WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     int64_t N;
 };
 

@@ -68,6 +68,15 @@ void launch_unpermute(hipStream_t s, const double *xi, const double *p, const in
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
                              double dx, double w, int M, double *J, int *flags);
 void launch_copy(hipStream_t s, const double *in, double *out, int64_t n);
+void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a);
+void launch_ws_init(int P, hipStream_t s, float *theta, uint64_t seed);
+void launch_ws_stats(hipStream_t s, const float *feat, const float *targ, int64_t n, int D, float *mu, float *sd,
+                     float *prange);
+void launch_ws_step(int P, hipStream_t s, float *theta, float *m, float *v, const float *mu, const float *sd,
+                    const float *feat, const float *targ, int64_t n, int direct, uint64_t seed, int64_t step, int B,
+                    float *pgrad, float *ploss, float lr, int update, float *grad_out, float *loss_out);
+void launch_ws_table(int P, hipStream_t s, const WsNet &net, const double *coefA, const double *ay,
+                     const double *az, const double *ex, int M, float *table);
 }  // namespace ecpic
 
 using namespace ecpic;
@@ -172,6 +181,19 @@ struct ecpic_ctx {
     double *dbuf[2]{};
     float *fbuf[2]{};          // single precision iterate (precision form)
     int k32 = 0;               // FP32 sweeps opening each Subsystem I substep
+
+    // learned warm start: network (theta, Adam moments, normalisation), the
+    // per-cell tables, recorded training pairs and training scratch
+    int wsD = 0, wsNP = 0;
+    float *ws_theta = nullptr, *ws_m = nullptr, *ws_v = nullptr;
+    float *ws_norm = nullptr;  // mu[D+2] | sd[D+2] | prange[2]
+    float *ws_table = nullptr;
+    float *ws_feat = nullptr, *ws_targ = nullptr;
+    int64_t ws_cap = 0, ws_base = 0;
+    int ws_stride = 0, ws_phase = 0;
+    float *ws_pgrad = nullptr, *ws_ploss = nullptr, *ws_loss = nullptr;
+    int ws_pblocks = 0;
+    bool ws_ready = false, ws_on = false;
     ItemList items[2]{};
     int icur = 0;
     int n_items_host = 0;
@@ -303,14 +325,34 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.M = c->M;
     f.wpi = c->block / 64;
     const int gridp = particle_grid(c, true);
+    const int mlp = c->ws_on ? 1 : 0;
+    const int first64 = mlp + c->k32;
+    a.first64 = first64;
+    a.explicit_start = !mlp;
+    a.table = c->ws_table;
+    a.prange = c->ws_norm + 2 * (c->wsD + 2);
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kI++;
-        const bool fp32 = a.k < c->k32;
-        a.d32in = (c->k32 > 0 && a.k == c->k32) ? c->fbuf[c->k32 & 1] : nullptr;
-        timed(c, fp32 ? "sweep_I32" : "sweep_I",
-              [&] { launch_sweep_I(c->P, c->seidel, fp32, gridp, c->block, c->stream, a); });
+        if (mlp && a.k == 0) {   // the predictor pass takes the place of sweep 0
+            timed(c, "ws_predict", [&] { launch_ws_predict(c->P, gridp, c->block, c->stream, a); });
+        } else {
+            const bool fp32 = a.k < first64;
+            a.d32in = (c->k32 > 0 && a.k == first64) ? c->fbuf[first64 & 1] : nullptr;
+            timed(c, fp32 ? "sweep_I32" : "sweep_I",
+                  [&] { launch_sweep_I(c->P, c->seidel, fp32, gridp, c->block, c->stream, a); });
+        }
         timed(c, "field_I", [&] { launch_field_I(c->P, c->M, c->stream, f); });
     }
+}
+
+// Picard sweeps of the last Subsystem I substep (the predictor pass not
+// counted) and how many of them ran in FP32.
+int sweeps_done_I(const ecpic_ctx *c) {
+    const int n = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
+    return c->ws_on ? n - 1 : n;
+}
+int fp32_sweeps_done_I(const ecpic_ctx *c) {
+    return std::min(std::max(c->kI - (c->ws_on ? 1 : 0), 0), c->k32);
 }
 
 void enqueue_commit_I(ecpic_ctx *c) {
@@ -343,7 +385,18 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.seidel = c->seidel;
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
-    a.first64 = c->k32;
+    a.first64 = (c->ws_on ? 1 : 0) + c->k32;
+    if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
+        a.rec.feat = c->ws_feat;
+        a.rec.targ = c->ws_targ;
+        a.rec.cap = c->ws_cap;
+        a.rec.base = c->ws_base;
+        a.rec.stride = c->ws_stride;
+        a.rec.phase = c->ws_phase;
+        a.rec.ay = c->ay[c->trc];
+        a.rec.az = c->az[c->trc];
+        a.rec.ex = c->ex[c->exc];
+    }
     a.N = c->N;
     timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, true), c->block, c->stream, a); });
 }
@@ -437,6 +490,20 @@ void enqueue_begin_I(ecpic_ctx *c) {
         launch_prep_records(c->P, c->stream, c->stI, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                             c->coefE[0], c->M);
     });
+    if (c->ws_on) {
+        WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
+        timed(c, "ws_table", [&] {
+            launch_ws_table(c->P, c->stream, net, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M,
+                            c->ws_table);
+        });
+    }
+}
+
+// Slots of the training pairs advance after every committed Subsystem I step.
+void advance_records(ecpic_ctx *c) {
+    if (c->ws_stride <= 0) return;
+    c->ws_base += (c->N + c->ws_stride - 1) / c->ws_stride;
+    c->ws_phase = (c->ws_phase + 1) % c->ws_stride;
 }
 
 int finish_I(ecpic_ctx *c, bool *recommitted) {
@@ -520,6 +587,8 @@ void free_all(ecpic_ctx *c) {
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAn); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->stI);   // stII lives in the same allocation
+    F(c->ws_theta); F(c->ws_m); F(c->ws_v); F(c->ws_norm); F(c->ws_table); F(c->ws_feat); F(c->ws_targ);
+    F(c->ws_pgrad); F(c->ws_ploss); F(c->ws_loss);
     F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
     if (c->h) hipHostFree(c->h);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
@@ -554,6 +623,11 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->coefAk[0], nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAk[1], nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefE[0], nrec * c->P); rc |= dalloc(&c->coefE[1], nrec * c->P);
     rc |= dalloc(&c->stI, 2);
+    c->wsD = ws_d(c->P);
+    c->wsNP = ws_nparams(c->wsD);
+    rc |= dalloc(&c->ws_theta, c->wsNP); rc |= dalloc(&c->ws_m, c->wsNP); rc |= dalloc(&c->ws_v, c->wsNP);
+    rc |= dalloc(&c->ws_norm, 2 * (c->wsD + 2) + 2); rc |= dalloc(&c->ws_table, (size_t)M * WS_NT * WS_NP);
+    rc |= dalloc(&c->ws_loss, 1);
     if (c->stI) c->stII = c->stI + 1;
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
@@ -870,8 +944,8 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     bool again = false;
     if (!rc) rc = finish_I(c, &again);
     if (stats) {
-        stats->sweeps = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
-        stats->fp32_sweeps = std::min(c->kI, c->k32);
+        stats->sweeps = sweeps_done_I(c);
+        stats->fp32_sweeps = fp32_sweeps_done_I(c);
         stats->residual = c->h->I.res;
     }
     if (rc) return rc;
@@ -880,6 +954,7 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     c->icur ^= 1;
     c->exc ^= 1;
     c->n_items_host = c->h->I.n_items_next;
+    advance_records(c);
     return ECPIC_OK;
 }
 
@@ -930,7 +1005,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         if (!rc) rc = finish_II(c, v);
         const int nI = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
         const int nII = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
-        if (sI) { sI[s].sweeps = nI; sI[s].fp32_sweeps = std::min(c->kI, c->k32); sI[s].residual = c->h->I.res; }
+        if (sI) { sI[s].sweeps = sweeps_done_I(c); sI[s].fp32_sweeps = fp32_sweeps_done_I(c); sI[s].residual = c->h->I.res; }
         if (sII) { sII[s].sweeps = nII; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
         if (rc) return rc;   // nothing swapped: the step is rolled back
         c->guessI = std::max(1, nI);
@@ -940,9 +1015,159 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         c->exc ^= 1;
         c->trc ^= 1;
         c->n_items_host = c->h->I.n_items_next;
+        advance_records(c);
         if (steps_done) *steps_done = s + 1;
     }
     return ECPIC_OK;
+}
+
+// ---- learned warm start ------------------------------------------------------
+int ecpic_ws_record(ecpic_ctx *c, int32_t stride, int64_t capacity) {
+    if (!c || stride < 0 || (stride > 0 && capacity <= 0)) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    if (sync(c)) return ECPIC_EDEVICE;
+    if (stride == 0) { c->ws_stride = 0; return ECPIC_OK; }
+    if (capacity != c->ws_cap) {
+        if (c->ws_feat) hipFree(c->ws_feat);
+        if (c->ws_targ) hipFree(c->ws_targ);
+        c->ws_feat = nullptr; c->ws_targ = nullptr; c->ws_cap = 0;
+        if (dalloc(&c->ws_feat, (size_t)capacity * c->wsD) || dalloc(&c->ws_targ, (size_t)capacity * 2))
+            return ECPIC_ENOMEM;
+        c->ws_cap = capacity;
+    }
+    c->ws_stride = stride;
+    c->ws_phase = 0;
+    c->ws_base = 0;
+    return ECPIC_OK;
+}
+
+int ecpic_ws_records(ecpic_ctx *c, int64_t *n) {
+    if (!c || !n) return ECPIC_EINVAL;
+    *n = std::min(c->ws_base, c->ws_cap);
+    return ECPIC_OK;
+}
+
+int ecpic_ws_get_records(ecpic_ctx *c, float *feat, float *targ, int64_t n) {
+    if (!c || n < 0 || n > std::min(c->ws_base, c->ws_cap)) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    if (n == 0) return ECPIC_OK;
+    if (feat) HIPCHK(hipMemcpyAsync(feat, c->ws_feat, sizeof(float) * n * c->wsD, hipMemcpyDeviceToHost, c->stream));
+    if (targ) HIPCHK(hipMemcpyAsync(targ, c->ws_targ, sizeof(float) * n * 2, hipMemcpyDeviceToHost, c->stream));
+    return sync(c);
+}
+
+int ecpic_ws_n_params(ecpic_ctx *c, int64_t *n) {
+    if (!c || !n) return ECPIC_EINVAL;
+    *n = c->wsNP + 2 * (c->wsD + 2) + 2;
+    return ECPIC_OK;
+}
+
+static int ws_scratch(ecpic_ctx *c, int nblk) {
+    if (nblk <= c->ws_pblocks) return ECPIC_OK;
+    if (c->ws_pgrad) hipFree(c->ws_pgrad);
+    if (c->ws_ploss) hipFree(c->ws_ploss);
+    c->ws_pgrad = nullptr; c->ws_ploss = nullptr; c->ws_pblocks = 0;
+    if (dalloc(&c->ws_pgrad, (size_t)nblk * c->wsNP) || dalloc(&c->ws_ploss, nblk)) return ECPIC_ENOMEM;
+    c->ws_pblocks = nblk;
+    return ECPIC_OK;
+}
+
+int ecpic_ws_train(ecpic_ctx *c, const ecpic_ws_train_config *tc, float *final_loss) {
+    if (!c || !tc || tc->steps < 0 || tc->batch < 0 || tc->batch % 32 || tc->lr < 0.0f) return ECPIC_EINVAL;
+    const int64_t n = std::min(c->ws_base, c->ws_cap);
+    if (n < 1) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int steps = tc->steps ? tc->steps : 2000, B = tc->batch ? tc->batch : 1024;
+    const float lr = tc->lr > 0.0f ? tc->lr : 1e-3f;
+    int rc = ws_scratch(c, B / 32);
+    if (rc) return rc;
+    float *mu = c->ws_norm, *sd = c->ws_norm + (c->wsD + 2), *pr = c->ws_norm + 2 * (c->wsD + 2);
+    launch_ws_init(c->P, c->stream, c->ws_theta, tc->seed);
+    HIPCHK(hipMemsetAsync(c->ws_m, 0, sizeof(float) * c->wsNP, c->stream));
+    HIPCHK(hipMemsetAsync(c->ws_v, 0, sizeof(float) * c->wsNP, c->stream));
+    launch_ws_stats(c->stream, c->ws_feat, c->ws_targ, n, c->wsD, mu, sd, pr);
+    for (int t = 0; t < steps; ++t)
+        launch_ws_step(c->P, c->stream, c->ws_theta, c->ws_m, c->ws_v, mu, sd, c->ws_feat, c->ws_targ, n, 0,
+                       tc->seed, t, B, c->ws_pgrad, c->ws_ploss, lr, 1, nullptr,
+                       (t == steps - 1) ? c->ws_loss : nullptr);
+    float l = 0.0f;
+    if (steps > 0) HIPCHK(hipMemcpyAsync(&l, c->ws_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    rc = sync(c);
+    if (rc) return rc;
+    if (final_loss) *final_loss = l;
+    c->ws_ready = true;
+    return ECPIC_OK;
+}
+
+int ecpic_ws_get_weights(ecpic_ctx *c, float *w, int64_t n) {
+    int64_t need = 0;
+    if (!c || !w || ecpic_ws_n_params(c, &need) || n != need) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    HIPCHK(hipMemcpyAsync(w, c->ws_theta, sizeof(float) * c->wsNP, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(w + c->wsNP, c->ws_norm, sizeof(float) * (need - c->wsNP), hipMemcpyDeviceToHost,
+                          c->stream));
+    return sync(c);
+}
+
+int ecpic_ws_set_weights(ecpic_ctx *c, const float *w, int64_t n) {
+    int64_t need = 0;
+    if (!c || !w || ecpic_ws_n_params(c, &need) || n != need) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    HIPCHK(hipMemcpyAsync(c->ws_theta, w, sizeof(float) * c->wsNP, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(c->ws_norm, w + c->wsNP, sizeof(float) * (need - c->wsNP), hipMemcpyHostToDevice,
+                          c->stream));
+    int rc = sync(c);
+    if (!rc) c->ws_ready = true;
+    return rc;
+}
+
+int ecpic_ws_enable(ecpic_ctx *c, int32_t on) {
+    if (!c) return ECPIC_EINVAL;
+    if (on && !c->ws_ready) return ECPIC_ESTATE;
+    c->ws_on = on != 0;
+    return ECPIC_OK;
+}
+
+int ecpic_ws_grad(ecpic_ctx *c, const float *x, const float *y, int64_t n, float *grad, float *loss) {
+    if (!c || !x || !y || !grad || n < 1 || n > (1 << 20)) return ECPIC_EINVAL;
+    if (!c->ws_ready) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int D = c->wsD, nblk = (int)((n + 31) / 32);
+    int rc = ws_scratch(c, nblk);
+    if (rc) return rc;
+    float *dx = nullptr, *dy = nullptr, *dn = nullptr, *dg = nullptr;
+    rc = dalloc(&dx, (size_t)n * D) | dalloc(&dy, (size_t)n * 2) | dalloc(&dn, 2 * (D + 2)) | dalloc(&dg, c->wsNP);
+    if (!rc) {
+        std::vector<float> norm(2 * (D + 2), 0.0f);
+        for (int i = 0; i < D + 2; ++i) norm[D + 2 + i] = 1.0f;   // inputs given normalised
+        hipMemcpyAsync(dx, x, sizeof(float) * n * D, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(dy, y, sizeof(float) * n * 2, hipMemcpyHostToDevice, c->stream);
+        hipMemcpyAsync(dn, norm.data(), sizeof(float) * norm.size(), hipMemcpyHostToDevice, c->stream);
+        launch_ws_step(c->P, c->stream, c->ws_theta, c->ws_m, c->ws_v, dn, dn + D + 2, dx, dy, n, 1, 0, 0, 0,
+                       c->ws_pgrad, c->ws_ploss, 0.0f, 0, dg, c->ws_loss);
+        hipMemcpyAsync(grad, dg, sizeof(float) * c->wsNP, hipMemcpyDeviceToHost, c->stream);
+        float l = 0.0f;
+        hipMemcpyAsync(&l, c->ws_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream);
+        rc = sync(c);
+        if (loss) *loss = l;
+    } else {
+        rc = ECPIC_ENOMEM;
+    }
+    for (void *q : {(void *)dx, (void *)dy, (void *)dn, (void *)dg}) if (q) hipFree(q);
+    return rc;
+}
+
+int ecpic_ws_table(ecpic_ctx *c, float *table) {
+    if (!c || !table) return ECPIC_EINVAL;
+    if (!c->ws_ready) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
+    launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
+                        c->coefE[0], c->M);
+    launch_ws_table(c->P, c->stream, net, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M, c->ws_table);
+    HIPCHK(hipMemcpyAsync(table, c->ws_table, sizeof(float) * c->M * WS_NT * WS_NP, hipMemcpyDeviceToHost,
+                          c->stream));
+    return sync(c);
 }
 
 int ecpic_profile_enable(ecpic_ctx *c, int32_t enable) {

@@ -482,6 +482,69 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     }
 }
 
+// Predictor pass of the learned warm start, run as sweep 0: each particle's
+// increment delta^(1) = dt p/gamma0 + dt^2 y, with y interpolated bilinearly in
+// its cell's table of network outputs over (t, p) nodes, and the current of
+// that increment deposited like a sweep's, so that the field kernel after it
+// makes e^(1) consistent with delta^(1).  The later sweeps start from both.
+template <int P>
+__global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
+    DevStatus *st = a.st;
+    const int item = blockIdx.x;
+    if (item >= *a.items.n_items) return;
+    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    const int c = a.items.cell[item];
+    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    int wb, we;
+    wave_range(beg, end, wid, nw, wb, we);
+    const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
+    double ay[P + 1], az[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) { ay[i] = ra[i]; az[i] = ra[P + 1 + i]; }
+    const float *tab = a.table + (size_t)c * (WS_NT * WS_NP);
+    const float plo = a.prange[0], phi = a.prange[1];
+    const float pscale = (float)(WS_NP - 1) / (phi - plo);
+    const double dt2_dx = a.dt * a.dt * a.inv_dx;
+    Moments<P> mo{};
+    int flags = 0;
+    for (int row = wb; row < we; row += WAVE) {
+        const int ia = row + lane;
+        const bool valid = ia < we;
+        const int il = valid ? ia : we - 1;
+        const double xi0 = a.xi[il], p0 = a.p[il];
+        double t0 = xi0 - (double)c;
+        if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
+        const double A0y = horner<P + 1>(ay, t0), A0z = horner<P + 1>(az, t0);
+        const double g00 = fsqrt(fma(p0, p0, 1.0) + A0y * A0y + A0z * A0z);
+        const float ft = (float)t0 * (float)(WS_NT - 1);
+        const int it = min((int)ft, WS_NT - 2);
+        const float wt = ft - (float)it;
+        const float fp = fminf(fmaxf(((float)p0 - plo) * pscale, 0.0f), (float)(WS_NP - 1));
+        const int ip = min((int)fp, WS_NP - 2);
+        const float wp = fp - (float)ip;
+        const float *q = tab + it * WS_NP + ip;
+        const float y = (1.0f - wt) * ((1.0f - wp) * q[0] + wp * q[1]) + wt * ((1.0f - wp) * q[WS_NP] + wp * q[WS_NP + 1]);
+        const double d = a.dt_dx * p0 * frcp(g00) + dt2_dx * (double)y;
+        double t1;
+        int s;
+        end_point(xi0, d, c, t1, s, flags);
+        stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
+        if (valid) {
+            a.d1[ia] = d;
+            if (a.f1) a.f1[ia] = (float)d;
+        }
+    }
+    const double slot = moments_to_slots<P>(mo);
+    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
+    double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
+    double v = slot;
+    v = lane == P + 2 ? 0.0 : v;
+    v = lane == P + 3 ? (double)fl : v;
+    if (lane < UnitI<P>::N) out[lane] = v;
+}
+
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
 // current slots, the max of the residuals and the OR of the flags.
 template <int P>
@@ -727,6 +790,31 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     }
 }
 
+// One training pair of the learned warm start: the particle's features at the
+// step start and the converged increments (see mlp.hip for the definitions).
+template <int P>
+__device__ __forceinline__ void record_pair(const CommitIArgs &a, const Coef1<P> &kc, int c, int pid, double xi0,
+                                            double p0, double d, double p1) {
+    constexpr int D = ws_d(P);
+    const int64_t slot = a.rec.base + pid / a.rec.stride;
+    if (slot >= a.rec.cap) return;
+    const double t0 = xi0 - (double)c;
+    const double Ay = horner<P + 1>(kc.ay[1], t0), Az = horner<P + 1>(kc.az[1], t0);
+    const double g0 = sqrt(1.0 + p0 * p0 + Ay * Ay + Az * Az);
+    float *f = a.rec.feat + slot * D;
+    f[0] = (float)(t0 - 0.5);
+    f[1] = (float)p0;
+    f[2] = (float)(g0 - 1.0);
+    for (int j = -P; j <= P + 1; ++j) {
+        const int jj = imod(c + j, a.M) + HALO;
+        f[3 + j + P] = (float)a.rec.ay[jj];
+        f[3 + 2 * (P + 1) + j + P] = (float)a.rec.az[jj];
+        f[3 + 4 * (P + 1) + j + P] = (float)a.rec.ex[jj];
+    }
+    a.rec.targ[slot * 2] = (float)((d * a.dx - a.dt * p0 / g0) / (a.dt * a.dt));
+    a.rec.targ[slot * 2 + 1] = (float)((p1 - p0) / a.dt);
+}
+
 // Moves every particle to its place in the new cell order, with the committed
 // momentum re-evaluated.  Each wave handles the same run of rows as in the
 // sweep, so its movers of each kind are consecutive from the base the scan
@@ -764,6 +852,7 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
             const MapOut o = particle_map<P>(kc, xi0, c, p0, d, false, a.dt, a.dt_dx, a.inv_dx, flags);
             p1 = o.p1;
             t = mover_type(xi0, d, c);
+            if (a.rec.stride > 0 && pid % a.rec.stride == a.rec.phase) record_pair<P>(a, kc, c, pid, xi0, p0, d, p1);
             xin = xi0 + d;
             if (xin >= (double)M) xin -= (double)M;
             else if (xin < 0.0) {
@@ -807,6 +896,12 @@ void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStrea
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW
+}
+
+void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a) {
+#define ECPIC_WP(PP) case PP: hipLaunchKernelGGL((k_ws_predict<PP>), dim3(grid), dim3(block), 0, s, a); break;
+    switch (P) { ECPIC_WP(2) ECPIC_WP(3) ECPIC_WP(4) ECPIC_WP(5) }
+#undef ECPIC_WP
 }
 
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
