@@ -1,13 +1,21 @@
-"""Benchmark: converged particle-steps/s of the full Lie-Trotter step (Subsystem I
+"""Benchmark: converged particle-steps/s of full Lie-Trotter steps (Subsystem I
 + II, every step converged to the Picard tolerance) on the pump2048 workload
-(L = 64 pi, 2048 cells, cubic splines, 2e6 particles, dt = 0.02, tol 1e-12),
-plain FP64 on one MI355X.
+(L = 64 pi, 2048 cells, cubic splines, 2e6 particles, dt = 0.02, tol 1e-12) on
+one MI355X, for the two forms the metric compares:
 
-Prints ONE JSON line.  Inputs are resident in HBM before the timed region; the
-timed region is `--steps` steps of ecpic_step.  A second pass with per-kernel
-HIP events (on the library's stream) gives the average duration of the
-dominant kernel (the Subsystem I sweep) for the roofline object; the CPU
-baseline is the FP64 oracle timed on a bounded sample of the same workload.
+* plain FP64: every Picard sweep in FP64 from the explicit initial iterate;
+* FP32 + learned warm start: a predictor pass from the network (trained first on
+  pairs the method produced, training time reported apart), then FP32 sweeps,
+  then FP64 sweeps to the same tolerance.
+
+Prints ONE JSON line.  `value` is the throughput of the second form (the
+whole hot path: network tables, predictor, FP32 and FP64 sweeps, field
+solves, commit, Subsystem II); the plain form's throughput, sweep counts and
+energy drift sit beside it.  Inputs are resident in HBM before each timed
+region.  A separate pass with per-kernel HIP events (on the library's stream)
+gives the average duration of the dominant kernel, the FP64 Subsystem I sweep,
+for the roofline object; the CPU baseline is the FP64 oracle timed on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -32,7 +40,7 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_I_pump2048_pmc.txt")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sub1.hip", "spline.hpp", "common.hpp", "internal.hpp"):
+    for f in ("sub1.hip", "spline.hpp", "common.hpp", "internal.hpp", "coef.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2203_06513_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -46,12 +54,11 @@ def traffic_from_profile(n_particles: int):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             d[k.strip()] = v.strip()
-    if "bytes_per_launch" in d:
-        d["n_particles"] = int(d.get("n_particles", -1))
-        d["bytes_per_launch"] = float(d["bytes_per_launch"])
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n_particles") != n_particles:
+    if "bytes_per_launch" not in d:
         return None
-    return d.get("bytes_per_launch")
+    if d.get("kernel_source_hash") != kernel_source_hash() or int(d.get("n_particles", -1)) != n_particles:
+        return None
+    return float(d["bytes_per_launch"])
 
 
 def cpu_baseline(w, n_sample: int, steps: int):
@@ -68,8 +75,8 @@ def cpu_baseline(w, n_sample: int, steps: int):
     dt = time.perf_counter() - t0
     assert st == 0
     return {"value": n_sample * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"pump2048 grid/fields/dt/tol with the first {n_sample} of its 2e6 particles, "
-                      f"{steps} Lie-Trotter steps (Seidel map), {dt:.1f} s single-threaded",
+            "sample": f"pump2048 grid/fields/dt/tol with the first {n_sample} of its {w.n_particles} particles, "
+                      f"{steps} Lie-Trotter steps (plain FP64, Seidel map), {dt:.1f} s single-threaded",
             "mean_sweeps_I": float(np.mean(kI)), "mean_iters_II": float(np.mean(kII))}
 
 
@@ -81,16 +88,47 @@ def _device_sync():
         torch.cuda.synchronize()
 
 
+def timed_run(ctx, steps: int):
+    """K steps bracketed by device synchronisation; energy and Gauss law around them."""
+    H0 = ctx.energy()[4]
+    g0, r0 = ctx.gauss_residual(vec=True)
+    _device_sync()
+    t0 = time.perf_counter()
+    rc, done, kI, kII, k32 = ctx.step(steps)
+    _device_sync()
+    elapsed = time.perf_counter() - t0
+    if rc != 0 or done != steps:
+        raise SystemExit(f"bench.py: ecpic_step stopped after {done} of {steps} steps (status {rc})")
+    H1 = ctx.energy()[4]
+    g1, r1 = ctx.gauss_residual(vec=True)
+    return {"elapsed": elapsed, "kI": kI, "kII": kII, "k32": k32, "drift": abs(H1 - H0) / abs(H0),
+            "gauss": float(np.abs(r1 - r0).max())}
+
+
+def kernel_profile(ctx, steps: int, names):
+    ctx.profile(True)
+    ctx.step(steps)
+    out = {}
+    for name in names:
+        ms, n = ctx.kernel_time(name)
+        if n:
+            out[name] = {"ms_total": ms, "launches": n, "us_avg": 1e3 * ms / n}
+    ctx.profile(False)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="pump2048")
-    ap.add_argument("--map", default="seidel", choices=["seidel", "jacobi"])
+    ap.add_argument("--fp32-sweeps", type=int, default=1)
+    ap.add_argument("--record-steps", type=int, default=20)
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=400_000)
+    ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     args = ap.parse_args()
 
@@ -104,43 +142,47 @@ def main():
 
     w = workloads.get(args.workload)
     arr = workloads.generate(w)
-    mp = ec.MAP_SEIDEL if args.map == "seidel" else ec.MAP_JACOBI
-    ctx = ec.Context.from_workload(w, map=mp)
-    ctx.load(arr)
-    ctx.step(args.warmup)
-    H0 = ctx.energy()[4]
-    g0, r0 = ctx.gauss_residual(vec=True)
+    N = w.n_particles
+    names = ("ws_table", "ws_predict", "sweep_I32", "sweep_I", "field_I", "commit_I", "sweep_II", "field_II",
+             "begin_I", "begin_II", "commit_II")
 
-    _device_sync()
-    t0 = time.perf_counter()
-    rc, done, kI, kII, _ = ctx.step(args.steps)
-    _device_sync()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    if rc != 0 or done != args.steps:
-        raise SystemExit(f"bench.py: ecpic_step stopped after {done} of {args.steps} steps (status {rc})")
-    H1 = ctx.energy()[4]
-    g1, r1 = ctx.gauss_residual(vec=True)
-    value = w.n_particles * args.steps / elapsed
-
-    # per-kernel durations from HIP events on the library stream (separate pass)
-    ctx.profile(True)
-    ctx.step(args.profile_steps)
-    kernels = {}
-    for name in ("sweep_I", "field_I", "commit_I", "sweep_II", "field_II", "commit_II"):
-        ms, n = ctx.kernel_time(name)
-        kernels[name] = {"ms_total": ms, "launches": n, "us_avg": 1e3 * ms / max(n, 1)}
-    ctx.profile(False)
-    sweep_us = kernels["sweep_I"]["us_avg"]
-    S = float(np.mean(kI))
-    alg_bytes = w.n_particles * (24.0 + 32.0 * (S - 1.0)) / S
-    achieved = alg_bytes / (sweep_us * 1e-6) / 1e9
+    # ---- plain FP64 ---------------------------------------------------------
+    plain = ec.Context.from_workload(w, map=ec.MAP_SEIDEL)
+    plain.load(arr)
+    plain.step(args.warmup)
+    rp = timed_run(plain, args.steps)
+    kp = kernel_profile(plain, args.profile_steps, names)
     copy_bytes = 1 << 30
-    copy_ms = ctx.bandwidth_probe(copy_bytes, reps=10)
-    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
-    ctx.close()
+    copy_ms = plain.bandwidth_probe(copy_bytes, reps=10)
+    plain.close()
 
-    tr = traffic_from_profile(w.n_particles)
+    # ---- FP32 + learned warm start -----------------------------------------
+    lw = ec.Context.from_workload(w, map=ec.MAP_SEIDEL, precision=ec.FP32_MIXED, fp32_sweeps=args.fp32_sweeps)
+    lw.load(arr)
+    stride = max(1, N // 100_000)
+    lw.ws_record(stride, 2_100_000)
+    t0 = time.perf_counter()
+    lw.step(args.record_steps)
+    lw.ws_record(0)
+    t1 = time.perf_counter()
+    loss = lw.ws_train(steps=args.train_steps, batch=1024, lr=2e-3, seed=5)
+    t2 = time.perf_counter()
+    lw.ws_enable(True)
+    lw.step(args.warmup)
+    rl = timed_run(lw, args.steps)
+    kl = kernel_profile(lw, args.profile_steps, names)
+    lw.close()
+
+    value = N * args.steps / rl["elapsed"]
+    value_plain = N * args.steps / rp["elapsed"]
+
+    # roofline of the dominant kernel, the FP64 Subsystem I sweep, in the plain form
+    S = float(np.mean(rp["kI"]))
+    sweep_us = kp["sweep_I"]["us_avg"]
+    alg_bytes = N * (24.0 + 32.0 * (S - 1.0)) / S
+    achieved = alg_bytes / (sweep_us * 1e-6) / 1e9
+    copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -148,25 +190,34 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
+        "ms_per_step": 1e3 * rl["elapsed"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32+bf16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: L={w.L / np.pi:g}pi, M={w.M}, degree {w.degree}, N={w.n_particles}, "
+        "config": {"workload": f"{w.name}: L={w.L / np.pi:g}pi, M={w.M}, degree {w.degree}, N={N}, "
                                f"dt={w.dt}, tol={w.tol}, wave={w.wave} a0={w.amplitude} mode {w.wave_mode}, "
                                f"sigma={w.sigma}",
-                   "form": "plain FP64", "picard_map": args.map,
-                   "mean_sweeps_I": float(np.mean(kI)), "mean_iters_II": float(np.mean(kII)),
-                   "rel_energy_drift": abs(H1 - H0) / abs(H0),
-                   "gauss_change_linf": float(np.abs(r1 - r0).max())},
+                   "form": f"FP32+learned warm start ({args.fp32_sweeps} FP32 sweep(s), then FP64 to tol)",
+                   "picard_map": "seidel",
+                   "mean_sweeps_I": float(np.mean(rl["kI"])), "mean_fp32_sweeps_I": float(np.mean(rl["k32"])),
+                   "predictor_passes_per_step": 1, "mean_iters_II": float(np.mean(rl["kII"])),
+                   "rel_energy_drift": rl["drift"], "gauss_change_linf": rl["gauss"],
+                   "training": {"pairs": int(min(args.record_steps * ((N + stride - 1) // stride), 2_100_000)),
+                                "record_steps": args.record_steps, "record_s": t1 - t0,
+                                "train_steps": args.train_steps, "train_s": t2 - t1, "final_loss": loss},
+                   "plain_fp64": {"value": value_plain, "ms_per_step": 1e3 * rp["elapsed"] / args.steps,
+                                  "mean_sweeps_I": S, "mean_iters_II": float(np.mean(rp["kII"])),
+                                  "rel_energy_drift": rp["drift"], "gauss_change_linf": rp["gauss"]},
+                   "speedup_vs_plain_fp64": value / value_plain},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": tr,
-                     "kernel": "k_sweep_I (Subsystem I Picard sweep)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(N),
+                     "kernel": "k_sweep_I<3,true,double> (FP64 Subsystem I sweep, plain form)",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sweep_us, "copy_probe_GBs": copy_gbs},
-        "kernels": kernels,
+        "kernels_plain": {k: round(v["us_avg"], 2) for k, v in kp.items()},
+        "kernels_learned": {k: round(v["us_avg"], 2) for k, v in kl.items()},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_steps)

@@ -358,8 +358,8 @@ __global__ void __launch_bounds__(256) k_deposit_segments(const double *x0, cons
 // Plain streaming copy of n doubles (16-byte accesses): the calibration kernel
 // for bandwidth and for the fetch/write counters.
 __global__ void __launch_bounds__(256) k_copy(const double2 *in, double2 *out, int64_t n2) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = in[i];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // one 16-byte element per thread
+    if (i < n2) out[i] = in[i];
 }
 
 // ---- launchers ------------------------------------------------------------
@@ -467,7 +467,8 @@ void launch_unpermute(hipStream_t s, const double *xi, const double *p, const in
 }
 
 void launch_copy(hipStream_t s, const double *in, double *out, int64_t n) {
-    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, s, (const double2 *)in, (double2 *)out, n / 2);
+    const int64_t n2 = n / 2;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, n2);
 }
 
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,

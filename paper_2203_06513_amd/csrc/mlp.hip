@@ -38,6 +38,13 @@ constexpr float GA = 0.044715f;
 
 __device__ __forceinline__ float gelu_t(float z) { return 0.5f * z * (1.0f + tanhf(GC * (z + GA * z * z * z))); }
 
+// The same function written as z sigma(2u) = z / (1 + exp(-2u)), u = sqrt(2/pi)(z + 0.044715 z^3),
+// with the hardware exponential and reciprocal (inference tables).
+__device__ __forceinline__ float gelu_fast(float z) {
+    const float u2 = 2.0f * GC * fmaf(GA * z, z * z, z);
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-u2));
+}
+
 __device__ __forceinline__ float gelu_g(float z) {
     const float t = tanhf(GC * (z + GA * z * z * z));
     return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * GC * (1.0f + 3.0f * GA * z * z);
@@ -210,44 +217,62 @@ __global__ void __launch_bounds__(256) k_ws_adam(float *theta, float *m, float *
     }
 }
 
+// W2 in BF16 (row-major, rows padded to WS_H + 4) for the table kernel.
+template <int D>
+__global__ void __launch_bounds__(256) k_ws_w2_bf16(const float *theta, unsigned short *w2b) {
+    using L = Lay<D>;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < H * H) w2b[(q / H) * (H + 4) + (q % H)] = to_bf16(theta[L::W2 + q]);
+}
+
 // Per-cell tables of the increment target (physical units) on the node grid
 // t_i = i / (WS_NT - 1), p_j = p_lo + j (p_hi - p_lo) / (WS_NP - 1): one wave per
-// cell, one node per lane.  Layer 1 splits into the cell's constant window part
-// (once per cell) and the node part; layer 2, 64 x 64 x 64, runs on the matrix
-// cores (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation); layer 3
-// keeps only the increment output.
+// cell (four cells per block, sharing the staged W2), one node per lane.
+// Layer 1 splits into the cell's constant window part (once per cell) and the
+// node part; layer 2, 64 x 64 x 64, runs on the matrix cores
+// (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation); layer 3 keeps
+// only the increment output.
+constexpr int WS_CELLS = 4;
+
 template <int P>
-__global__ void __launch_bounds__(64) k_ws_table(WsNet net, const double *coefA, const double *ay, const double *az,
-                                                 const double *ex, int M, float *table) {
+__global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const unsigned short *w2b,
+                                                            const double *coefA, const double *ay, const double *az,
+                                                            const double *ex, int M, float *table) {
     constexpr int D = ws_d(P);
     using L = Lay<D>;
     constexpr int RS = H + 4;   // padded bf16 rows (conflict-free 8-byte LDS reads)
     __shared__ __align__(16) unsigned short W2b[H * RS];
-    __shared__ __align__(16) unsigned short H1b[64 * RS];
-    __shared__ float H2s[64 * (H + 1)];
-    __shared__ float c1[H];
-    __shared__ float xw[D];
-    const int c = blockIdx.x, l = threadIdx.x;
-    if (c >= M) return;
+    __shared__ __align__(16) unsigned short H1b[WS_CELLS][64 * RS];
+    __shared__ float ys[WS_CELLS][64];
+    __shared__ float c1[WS_CELLS][H];
+    __shared__ float xw[WS_CELLS][D];
+    const int wv = threadIdx.x / 64, l = threadIdx.x & 63;
+    const int c = blockIdx.x * WS_CELLS + wv;
     const float *th = net.theta;
-    for (int q = l; q < H * H; q += 64) W2b[(q / H) * RS + (q % H)] = to_bf16(th[L::W2 + q]);
+    {
+        const uint2 *src = reinterpret_cast<const uint2 *>(w2b);
+        uint2 *dst = reinterpret_cast<uint2 *>(W2b);
+        for (int q = threadIdx.x; q < H * RS / 4; q += blockDim.x) dst[q] = src[q];
+    }
+    const bool live = c < M;
+    const int cc = live ? c : M - 1;
     for (int i = 3 + l; i < D; i += 64) {
         const int u = i - 3, f = u / (2 * (P + 1)), j = u % (2 * (P + 1)) - P;   // field f at cell c + j
         const double *src = f == 0 ? ay : (f == 1 ? az : ex);
-        const double raw = src[imod(c + j, M) + HALO];
-        xw[i] = ((float)raw - net.mu[i]) / net.sd[i];
+        const double raw = src[imod(cc + j, M) + HALO];
+        xw[wv][i] = ((float)raw - net.mu[i]) / net.sd[i];
     }
     __syncthreads();
     {
         float z = th[L::B1 + l];
-        for (int i = 3; i < D; ++i) z = fmaf(th[L::W1 + l * D + i], xw[i], z);
-        c1[l] = z;
+        for (int i = 3; i < D; ++i) z = fmaf(th[L::W1 + l * D + i], xw[wv][i], z);
+        c1[wv][l] = z;
     }
     const int it = l / WS_NP, ip = l % WS_NP;
     const double t = (double)it / (WS_NT - 1);
     const float plo = net.prange[0], phi = net.prange[1];
     const float p = plo + (phi - plo) * (float)ip / (float)(WS_NP - 1);
-    const double *ra = coefA + (size_t)rec_index(c) * RecA<P>::N;
+    const double *ra = coefA + (size_t)rec_index(cc) * RecA<P>::N;
     double Ay = ra[P], Az = ra[2 * P + 1];
     for (int i = P - 1; i >= 0; --i) {
         Ay = fma(Ay, t, ra[i]);
@@ -258,33 +283,45 @@ __global__ void __launch_bounds__(64) k_ws_table(WsNet net, const double *coefA,
     const float x1 = (p - net.mu[1]) / net.sd[1];
     const float x2 = ((float)(g0 - 1.0) - net.mu[2]) / net.sd[2];
     __syncthreads();
+    unsigned short *h1 = H1b[wv];
     for (int h = 0; h < H; ++h) {
-        const float z = c1[h] + th[L::W1 + h * D] * x0 + th[L::W1 + h * D + 1] * x1 + th[L::W1 + h * D + 2] * x2;
-        H1b[l * RS + h] = to_bf16(gelu_t(z));
+        const float z = c1[wv][h] + th[L::W1 + h * D] * x0 + th[L::W1 + h * D + 1] * x1 + th[L::W1 + h * D + 2] * x2;
+        h1[l * RS + h] = to_bf16(gelu_fast(z));
     }
     __syncthreads();
-    // Z2[m][n] = sum_k H1[m][k] W2[n][k]: A = H1 (rows m), B[k][n] = W2[n][k]
+    // Z2[m][n] = sum_k H1[m][k] W2[n][k]: A = H1 (rows m), B[k][n] = W2[n][k].
+    // Each lane folds its columns of GELU(Z2) into the first output at once
+    // (y[m] = b3 + sum_n W3[0][n] GELU(Z2[m][n])); the 16 lanes of a row group
+    // then sum their columns in a fixed order.
     const int r16 = l & 15, kq = (l >> 4) * 4;
     for (int mt = 0; mt < 4; ++mt) {
+        float yp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         for (int nt = 0; nt < 4; ++nt) {
             f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int ks = 0; ks < 4; ++ks) {
-                const bf16x4 av = *reinterpret_cast<const bf16x4 *>(&H1b[(mt * 16 + r16) * RS + ks * 16 + kq]);
+                const bf16x4 av = *reinterpret_cast<const bf16x4 *>(&h1[(mt * 16 + r16) * RS + ks * 16 + kq]);
                 const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(&W2b[(nt * 16 + r16) * RS + ks * 16 + kq]);
                 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
             }
+            const float bias = th[L::B2 + nt * 16 + r16], w3 = th[L::W3 + nt * 16 + r16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {   // acc[i] = Z2[mt*16 + kq + i][nt*16 + r16]
-                const int m = mt * 16 + kq + i, nn = nt * 16 + r16;
-                H2s[m * (H + 1) + nn] = gelu_t(acc[i] + th[L::B2 + nn]);
-            }
+            for (int i = 0; i < 4; ++i)   // acc[i] = Z2[mt*16 + kq + i][nt*16 + r16]
+                yp[i] = fmaf(w3, gelu_fast(acc[i] + bias), yp[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int off = 8; off >= 1; off >>= 1) yp[i] += __shfl_xor(yp[i], off, 16);
+        }
+        if (r16 == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ys[wv][mt * 16 + kq + i] = yp[i];
         }
     }
     __syncthreads();
-    float y = th[L::B3];
-    for (int h = 0; h < H; ++h) y = fmaf(th[L::W3 + h], H2s[l * (H + 1) + h], y);
-    table[(size_t)c * (WS_NT * WS_NP) + l] = net.mu[D] + net.sd[D] * y;
+    const float y = th[L::B3] + ys[wv][l];
+    if (live) table[(size_t)c * (WS_NT * WS_NP) + l] = net.mu[D] + net.sd[D] * y;
 }
 
 // ---- launchers ------------------------------------------------------------
@@ -318,10 +355,20 @@ void launch_ws_step(int P, hipStream_t s, float *theta, float *m, float *v, cons
                        (int)(step + 1), update, grad_out, ploss, 1.0f / (2.0f * (float)cnt), loss_out);
 }
 
-void launch_ws_table(int P, hipStream_t s, const WsNet &net, const double *coefA, const double *ay,
-                     const double *az, const double *ex, int M, float *table) {
-#define ECPIC_WT(PP) \
-    case PP: hipLaunchKernelGGL((k_ws_table<PP>), dim3(M), dim3(64), 0, s, net, coefA, ay, az, ex, M, table); break;
+void launch_ws_w2_bf16(int P, hipStream_t s, const float *theta, unsigned short *w2b) {
+#define ECPIC_WB(PP) case PP: hipLaunchKernelGGL((k_ws_w2_bf16<ws_d(PP)>), dim3(H * H / 256), dim3(256), 0, s, theta, w2b); break;
+    switch (P) { ECPIC_WB(2) ECPIC_WB(3) ECPIC_WB(4) ECPIC_WB(5) }
+#undef ECPIC_WB
+}
+
+void launch_ws_table(int P, hipStream_t s, const WsNet &net, const unsigned short *w2b, const double *coefA,
+                     const double *ay, const double *az, const double *ex, int M, float *table) {
+    const int grid = (M + WS_CELLS - 1) / WS_CELLS;
+#define ECPIC_WT(PP)                                                                                             \
+    case PP:                                                                                                     \
+        hipLaunchKernelGGL((k_ws_table<PP>), dim3(grid), dim3(64 * WS_CELLS), 0, s, net, w2b, coefA, ay, az, ex, \
+                           M, table);                                                                            \
+        break;
     switch (P) { ECPIC_WT(2) ECPIC_WT(3) ECPIC_WT(4) ECPIC_WT(5) }
 #undef ECPIC_WT
 }

@@ -75,8 +75,9 @@ void launch_ws_stats(hipStream_t s, const float *feat, const float *targ, int64_
 void launch_ws_step(int P, hipStream_t s, float *theta, float *m, float *v, const float *mu, const float *sd,
                     const float *feat, const float *targ, int64_t n, int direct, uint64_t seed, int64_t step, int B,
                     float *pgrad, float *ploss, float lr, int update, float *grad_out, float *loss_out);
-void launch_ws_table(int P, hipStream_t s, const WsNet &net, const double *coefA, const double *ay,
-                     const double *az, const double *ex, int M, float *table);
+void launch_ws_w2_bf16(int P, hipStream_t s, const float *theta, unsigned short *w2b);
+void launch_ws_table(int P, hipStream_t s, const WsNet &net, const unsigned short *w2b, const double *coefA,
+                     const double *ay, const double *az, const double *ex, int M, float *table);
 }  // namespace ecpic
 
 using namespace ecpic;
@@ -188,6 +189,7 @@ struct ecpic_ctx {
     float *ws_theta = nullptr, *ws_m = nullptr, *ws_v = nullptr;
     float *ws_norm = nullptr;  // mu[D+2] | sd[D+2] | prange[2]
     float *ws_table = nullptr;
+    unsigned short *ws_w2b = nullptr;   // W2 in BF16 for the tables
     float *ws_feat = nullptr, *ws_targ = nullptr;
     int64_t ws_cap = 0, ws_base = 0;
     int ws_stride = 0, ws_phase = 0;
@@ -493,7 +495,7 @@ void enqueue_begin_I(ecpic_ctx *c) {
     if (c->ws_on) {
         WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
         timed(c, "ws_table", [&] {
-            launch_ws_table(c->P, c->stream, net, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M,
+            launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M,
                             c->ws_table);
         });
     }
@@ -588,7 +590,7 @@ void free_all(ecpic_ctx *c) {
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAn); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->stI);   // stII lives in the same allocation
     F(c->ws_theta); F(c->ws_m); F(c->ws_v); F(c->ws_norm); F(c->ws_table); F(c->ws_feat); F(c->ws_targ);
-    F(c->ws_pgrad); F(c->ws_ploss); F(c->ws_loss);
+    F(c->ws_pgrad); F(c->ws_ploss); F(c->ws_loss); F(c->ws_w2b);
     F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
     if (c->h) hipHostFree(c->h);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
@@ -627,7 +629,7 @@ int alloc_all(ecpic_ctx *c) {
     c->wsNP = ws_nparams(c->wsD);
     rc |= dalloc(&c->ws_theta, c->wsNP); rc |= dalloc(&c->ws_m, c->wsNP); rc |= dalloc(&c->ws_v, c->wsNP);
     rc |= dalloc(&c->ws_norm, 2 * (c->wsD + 2) + 2); rc |= dalloc(&c->ws_table, (size_t)M * WS_NT * WS_NP);
-    rc |= dalloc(&c->ws_loss, 1);
+    rc |= dalloc(&c->ws_loss, 1); rc |= dalloc(&c->ws_w2b, (size_t)WS_H * (WS_H + 4));
     if (c->stI) c->stII = c->stI + 1;
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
@@ -749,8 +751,16 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->seidel = g.map == ECPIC_MAP_SEIDEL;
     c->k32 = g.precision == ECPIC_FP32_MIXED ? (g.fp32_sweeps > 0 ? g.fp32_sweeps : 2) : 0;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
-    c->block = ppc >= 512 ? 256 : (ppc >= 128 ? 128 : 64);
     c->chunk = MAX_CHUNK;
+    // Waves per work item: enough items x waves to give every SIMD (1024 on the
+    // chip) about four waves, and otherwise as few waves per item as possible,
+    // so each wave streams many rows of particles (measured best on the pump
+    // and Langmuir workloads).
+    {
+        const double items = (double)g.M * std::max(1.0, std::ceil(ppc / c->chunk));
+        const int wpi = (int)std::min(4.0, std::max(1.0, std::ceil(4096.0 / items)));
+        c->block = 64 * wpi;
+    }
     c->max_items = (int)(g.M + g.n_particles / c->chunk + 2);
     if (g.stream) {
         c->stream = (hipStream_t)g.stream;
@@ -1090,6 +1100,7 @@ int ecpic_ws_train(ecpic_ctx *c, const ecpic_ws_train_config *tc, float *final_l
         launch_ws_step(c->P, c->stream, c->ws_theta, c->ws_m, c->ws_v, mu, sd, c->ws_feat, c->ws_targ, n, 0,
                        tc->seed, t, B, c->ws_pgrad, c->ws_ploss, lr, 1, nullptr,
                        (t == steps - 1) ? c->ws_loss : nullptr);
+    launch_ws_w2_bf16(c->P, c->stream, c->ws_theta, c->ws_w2b);
     float l = 0.0f;
     if (steps > 0) HIPCHK(hipMemcpyAsync(&l, c->ws_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     rc = sync(c);
@@ -1116,6 +1127,7 @@ int ecpic_ws_set_weights(ecpic_ctx *c, const float *w, int64_t n) {
     HIPCHK(hipMemcpyAsync(c->ws_theta, w, sizeof(float) * c->wsNP, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->ws_norm, w + c->wsNP, sizeof(float) * (need - c->wsNP), hipMemcpyHostToDevice,
                           c->stream));
+    launch_ws_w2_bf16(c->P, c->stream, c->ws_theta, c->ws_w2b);
     int rc = sync(c);
     if (!rc) c->ws_ready = true;
     return rc;
@@ -1164,7 +1176,7 @@ int ecpic_ws_table(ecpic_ctx *c, float *table) {
     WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
     launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                         c->coefE[0], c->M);
-    launch_ws_table(c->P, c->stream, net, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M, c->ws_table);
+    launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M, c->ws_table);
     HIPCHK(hipMemcpyAsync(table, c->ws_table, sizeof(float) * c->M * WS_NT * WS_NP, hipMemcpyDeviceToHost,
                           c->stream));
     return sync(c);
