@@ -102,9 +102,9 @@ struct SweepIArgs {
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
     int32_t k;                     // sweep index
     int32_t first64;               // index of the first FP64 sweep (0 for the plain method)
-    const float *table;            // warm-start tables [M][WS_NT * WS_NP] (predictor pass)
-    const float *prange;           // their momentum range
-    const float *ytarget;          // target normalisation (mu, sd of the increment target)
+    // predictor pass of the learned warm start
+    WsNet ws;
+    const float *ws_table;         // [M][WS_NT * WS_NP] network outputs of this substep
 };
 
 struct FieldIArgs {

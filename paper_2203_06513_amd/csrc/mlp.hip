@@ -10,7 +10,7 @@
 // function of (t, p) per cell.  It is evaluated with BF16 matrix cores on a
 // WS_NT x WS_NP grid of nodes per cell, and each particle interpolates its
 // cell's table (see the predictor pass in sub1.hip).
-#include "coef.hpp"
+#include "sweep.hpp"
 
 namespace ecpic {
 
@@ -225,54 +225,47 @@ __global__ void __launch_bounds__(256) k_ws_w2_bf16(const float *theta, unsigned
     if (q < H * H) w2b[(q / H) * (H + 4) + (q % H)] = to_bf16(theta[L::W2 + q]);
 }
 
-// Per-cell tables of the increment target (physical units) on the node grid
-// t_i = i / (WS_NT - 1), p_j = p_lo + j (p_hi - p_lo) / (WS_NP - 1): one wave per
-// cell (four cells per block, sharing the staged W2), one node per lane.
-// Layer 1 splits into the cell's constant window part (once per cell) and the
-// node part; layer 2, 64 x 64 x 64, runs on the matrix cores
-// (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation); layer 3 keeps
-// only the increment output.
-constexpr int WS_CELLS = 4;
+// The network's increment target (physical units) on the node grid of cell c,
+// t_i = i / (WS_NT - 1), p_j = p_lo + j (p_hi - p_lo) / (WS_NP - 1), one node per
+// lane (node l = i WS_NP + j).  Layer 1 splits into the cell's constant window
+// part (once per cell) and the node part; layer 2, 64 x 64 x 64, runs on the
+// matrix cores (v_mfma_f32_16x16x16_bf16: BF16 inputs, FP32 accumulation), and
+// each lane folds its columns of GELU(Z2) into the output at once
+// (y[m] = b3 + sum_n W3[0][n] GELU(Z2[m][n])); the 16 lanes of a row group sum
+// their columns in a fixed order.  `nshare` waves (index `wshare`) split the
+// hidden units of layer 1 and the column tiles of layer 2 between them and
+// their partial outputs are summed in wave order.  Every thread of the block
+// calls it (it holds block barriers).  W2b is the staged BF16 W2 (rows of
+// WS_H + 4); h1, c1, xw and ys (nshare x 64) are the sharers' LDS scratch.
+constexpr int WS_RS = WS_H + 4;
 
 template <int P>
-__global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const unsigned short *w2b,
-                                                            const double *coefA, const double *ay, const double *az,
-                                                            const double *ex, int M, float *table) {
+__device__ __forceinline__ float ws_cell_table(const WsNet &net, const unsigned short *W2b, unsigned short *h1,
+                                               float *c1, float *xw, float *ys, int c, const double *coefA,
+                                               const double *ay, const double *az, const double *ex, int M,
+                                               int wshare, int nshare, int l) {
     constexpr int D = ws_d(P);
     using L = Lay<D>;
-    constexpr int RS = H + 4;   // padded bf16 rows (conflict-free 8-byte LDS reads)
-    __shared__ __align__(16) unsigned short W2b[H * RS];
-    __shared__ __align__(16) unsigned short H1b[WS_CELLS][64 * RS];
-    __shared__ float ys[WS_CELLS][64];
-    __shared__ float c1[WS_CELLS][H];
-    __shared__ float xw[WS_CELLS][D];
-    const int wv = threadIdx.x / 64, l = threadIdx.x & 63;
-    const int c = blockIdx.x * WS_CELLS + wv;
     const float *th = net.theta;
-    {
-        const uint2 *src = reinterpret_cast<const uint2 *>(w2b);
-        uint2 *dst = reinterpret_cast<uint2 *>(W2b);
-        for (int q = threadIdx.x; q < H * RS / 4; q += blockDim.x) dst[q] = src[q];
-    }
-    const bool live = c < M;
-    const int cc = live ? c : M - 1;
-    for (int i = 3 + l; i < D; i += 64) {
-        const int u = i - 3, f = u / (2 * (P + 1)), j = u % (2 * (P + 1)) - P;   // field f at cell c + j
-        const double *src = f == 0 ? ay : (f == 1 ? az : ex);
-        const double raw = src[imod(cc + j, M) + HALO];
-        xw[wv][i] = ((float)raw - net.mu[i]) / net.sd[i];
+    if (wshare == 0) {
+        for (int i = 3 + l; i < D; i += 64) {
+            const int u = i - 3, f = u / (2 * (P + 1)), j = u % (2 * (P + 1)) - P;   // field f at cell c + j
+            const double *src = f == 0 ? ay : (f == 1 ? az : ex);
+            const double raw = src[imod(c + j, M) + HALO];
+            xw[i] = ((float)raw - net.mu[i]) / net.sd[i];
+        }
     }
     __syncthreads();
-    {
+    if (wshare == 0) {
         float z = th[L::B1 + l];
-        for (int i = 3; i < D; ++i) z = fmaf(th[L::W1 + l * D + i], xw[wv][i], z);
-        c1[wv][l] = z;
+        for (int i = 3; i < D; ++i) z = fmaf(th[L::W1 + l * D + i], xw[i], z);
+        c1[l] = z;
     }
     const int it = l / WS_NP, ip = l % WS_NP;
     const double t = (double)it / (WS_NT - 1);
     const float plo = net.prange[0], phi = net.prange[1];
     const float p = plo + (phi - plo) * (float)ip / (float)(WS_NP - 1);
-    const double *ra = coefA + (size_t)rec_index(cc) * RecA<P>::N;
+    const double *ra = coefA + (size_t)rec_index(c) * RecA<P>::N;
     double Ay = ra[P], Az = ra[2 * P + 1];
     for (int i = P - 1; i >= 0; --i) {
         Ay = fma(Ay, t, ra[i]);
@@ -283,45 +276,140 @@ __global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const uns
     const float x1 = (p - net.mu[1]) / net.sd[1];
     const float x2 = ((float)(g0 - 1.0) - net.mu[2]) / net.sd[2];
     __syncthreads();
-    unsigned short *h1 = H1b[wv];
-    for (int h = 0; h < H; ++h) {
-        const float z = c1[wv][h] + th[L::W1 + h * D] * x0 + th[L::W1 + h * D + 1] * x1 + th[L::W1 + h * D + 2] * x2;
-        h1[l * RS + h] = to_bf16(gelu_fast(z));
+    {
+        const int h0 = wshare * H / nshare, h1e = (wshare + 1) * H / nshare;
+        for (int h = h0; h < h1e; ++h) {
+            const float z = c1[h] + th[L::W1 + h * D] * x0 + th[L::W1 + h * D + 1] * x1 + th[L::W1 + h * D + 2] * x2;
+            h1[l * WS_RS + h] = to_bf16(gelu_fast(z));
+        }
     }
     __syncthreads();
-    // Z2[m][n] = sum_k H1[m][k] W2[n][k]: A = H1 (rows m), B[k][n] = W2[n][k].
-    // Each lane folds its columns of GELU(Z2) into the first output at once
-    // (y[m] = b3 + sum_n W3[0][n] GELU(Z2[m][n])); the 16 lanes of a row group
-    // then sum their columns in a fixed order.
-    const int r16 = l & 15, kq = (l >> 4) * 4;
-    for (int mt = 0; mt < 4; ++mt) {
-        float yp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int nt = 0; nt < 4; ++nt) {
-            f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    {
+        const int r16 = l & 15, kq = (l >> 4) * 4;
+        const int n0 = wshare * 4 / nshare, n1 = (wshare + 1) * 4 / nshare;
+        float *yw = ys + wshare * 64;
+        for (int mt = 0; mt < 4; ++mt) {
+            float yp[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int nt = n0; nt < n1; ++nt) {
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const bf16x4 av = *reinterpret_cast<const bf16x4 *>(&h1[(mt * 16 + r16) * RS + ks * 16 + kq]);
-                const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(&W2b[(nt * 16 + r16) * RS + ks * 16 + kq]);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+                for (int ks = 0; ks < 4; ++ks) {
+                    const bf16x4 av = *reinterpret_cast<const bf16x4 *>(&h1[(mt * 16 + r16) * WS_RS + ks * 16 + kq]);
+                    const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(&W2b[(nt * 16 + r16) * WS_RS + ks * 16 + kq]);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+                }
+                const float bias = th[L::B2 + nt * 16 + r16], w3 = th[L::W3 + nt * 16 + r16];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)   // acc[i] = Z2[mt*16 + kq + i][nt*16 + r16]
+                    yp[i] = fmaf(w3, gelu_fast(acc[i] + bias), yp[i]);
             }
-            const float bias = th[L::B2 + nt * 16 + r16], w3 = th[L::W3 + nt * 16 + r16];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)   // acc[i] = Z2[mt*16 + kq + i][nt*16 + r16]
-                yp[i] = fmaf(w3, gelu_fast(acc[i] + bias), yp[i]);
-        }
+            for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+                for (int off = 8; off >= 1; off >>= 1) yp[i] += __shfl_xor(yp[i], off, 16);
+            }
+            if (r16 == 0) {
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) yp[i] += __shfl_xor(yp[i], off, 16);
-        }
-        if (r16 == 0) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ys[wv][mt * 16 + kq + i] = yp[i];
+                for (int i = 0; i < 4; ++i) yw[mt * 16 + kq + i] = yp[i];
+            }
         }
     }
     __syncthreads();
-    const float y = th[L::B3] + ys[wv][l];
-    if (live) table[(size_t)c * (WS_NT * WS_NP) + l] = net.mu[D] + net.sd[D] * y;
+    float y = 0.0f;
+    for (int w = 0; w < nshare; ++w) y += ys[w * 64 + l];
+    return net.mu[D] + net.sd[D] * (th[L::B3] + y);
+}
+
+__device__ __forceinline__ void stage_w2b(const unsigned short *w2b, unsigned short *W2b) {
+    const uint2 *src = reinterpret_cast<const uint2 *>(w2b);
+    uint2 *dst = reinterpret_cast<uint2 *>(W2b);
+    for (int q = threadIdx.x; q < H * WS_RS / 4; q += blockDim.x) dst[q] = src[q];
+}
+
+// Tables of all cells (four cells per block, one wave each), for inspection.
+constexpr int WS_CELLS = 4;
+
+template <int P>
+__global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const unsigned short *w2b,
+                                                            const double *coefA, const double *ay, const double *az,
+                                                            const double *ex, int M, float *table) {
+    constexpr int D = ws_d(P);
+    __shared__ __align__(16) unsigned short W2b[H * WS_RS];
+    __shared__ __align__(16) unsigned short H1b[WS_CELLS][64 * WS_RS];
+    __shared__ float ys[WS_CELLS][64], c1[WS_CELLS][H], xw[WS_CELLS][D];
+    const int wv = threadIdx.x / 64, l = threadIdx.x & 63;
+    const int c = blockIdx.x * WS_CELLS + wv;
+    stage_w2b(w2b, W2b);
+    const bool live = c < M;
+    const float y = ws_cell_table<P>(net, W2b, H1b[wv], c1[wv], xw[wv], ys[wv], live ? c : M - 1, coefA, ay, az, ex,
+                                     M, 0, 1, l);
+    if (live) table[(size_t)c * (WS_NT * WS_NP) + l] = y;
+}
+
+// Predictor pass of the learned warm start, run as sweep 0: each particle's
+// increment delta^(1) = dt p/gamma0 + dt^2 y, with y interpolated bilinearly in
+// its cell's (t, p) table of network outputs (k_ws_table, same substep), and
+// the current of that increment deposited like a sweep's, so that the field
+// kernel after it makes e^(1) consistent with delta^(1).  The Picard sweeps
+// start from both.
+template <int P>
+__global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
+    __shared__ float tab[WS_NT * WS_NP];
+    DevStatus *st = a.st;
+    const int item = blockIdx.x;
+    if (item >= *a.items.n_items) return;
+    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    const int c = a.items.cell[item];
+    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    int wb, we;
+    wave_range(beg, end, wid, nw, wb, we);
+    if (threadIdx.x < WS_NT * WS_NP) tab[threadIdx.x] = a.ws_table[(size_t)c * (WS_NT * WS_NP) + threadIdx.x];
+    const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
+    double cay[P + 1], caz[P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i) { cay[i] = ra[i]; caz[i] = ra[P + 1 + i]; }
+    const float plo = a.ws.prange[0], phi = a.ws.prange[1];
+    const float pscale = (float)(WS_NP - 1) / (phi - plo);
+    const double dt2_dx = a.dt * a.dt * a.inv_dx;
+    __syncthreads();
+    Moments<P> mo{};
+    int flags = 0;
+    for (int row = wb; row < we; row += WAVE) {
+        const int ia = row + lane;
+        const bool valid = ia < we;
+        const int il = valid ? ia : we - 1;
+        const double xi0 = a.xi[il], p0 = a.p[il];
+        double t0 = xi0 - (double)c;
+        if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
+        const double A0y = horner<P + 1>(cay, t0), A0z = horner<P + 1>(caz, t0);
+        const double g00 = fsqrt(fma(p0, p0, 1.0) + A0y * A0y + A0z * A0z);
+        const float ft = (float)t0 * (float)(WS_NT - 1);
+        const int it = min((int)ft, WS_NT - 2);
+        const float wt = ft - (float)it;
+        const float fp = fminf(fmaxf(((float)p0 - plo) * pscale, 0.0f), (float)(WS_NP - 1));
+        const int ip = min((int)fp, WS_NP - 2);
+        const float wp = fp - (float)ip;
+        const float *q = tab + it * WS_NP + ip;
+        const float y = (1.0f - wt) * ((1.0f - wp) * q[0] + wp * q[1]) + wt * ((1.0f - wp) * q[WS_NP] + wp * q[WS_NP + 1]);
+        const double d = a.dt_dx * p0 * frcp(g00) + dt2_dx * (double)y;
+        double t1;
+        int s;
+        end_point(xi0, d, c, t1, s, flags);
+        stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
+        if (valid) {
+            a.d1[ia] = d;
+            if (a.f1) a.f1[ia] = (float)d;
+        }
+    }
+    const double slot = moments_to_slots<P>(mo);
+    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
+    double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
+    double v = slot;
+    v = lane == P + 2 ? 0.0 : v;
+    v = lane == P + 3 ? (double)fl : v;
+    if (lane < UnitI<P>::N) out[lane] = v;
 }
 
 // ---- launchers ------------------------------------------------------------
@@ -359,6 +447,12 @@ void launch_ws_w2_bf16(int P, hipStream_t s, const float *theta, unsigned short 
 #define ECPIC_WB(PP) case PP: hipLaunchKernelGGL((k_ws_w2_bf16<ws_d(PP)>), dim3(H * H / 256), dim3(256), 0, s, theta, w2b); break;
     switch (P) { ECPIC_WB(2) ECPIC_WB(3) ECPIC_WB(4) ECPIC_WB(5) }
 #undef ECPIC_WB
+}
+
+void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a) {
+#define ECPIC_WP(PP) case PP: hipLaunchKernelGGL((k_ws_predict<PP>), dim3(grid), dim3(block), 0, s, a); break;
+    switch (P) { ECPIC_WP(2) ECPIC_WP(3) ECPIC_WP(4) ECPIC_WP(5) }
+#undef ECPIC_WP
 }
 
 void launch_ws_table(int P, hipStream_t s, const WsNet &net, const unsigned short *w2b, const double *coefA,

@@ -175,6 +175,11 @@ struct ecpic_ctx {
     bool seidel = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // Second stream for the warm-start tables of the next step, which overlap
+    // Subsystem II of the current one (default priority like the main stream).
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_ready = nullptr, ev_table = nullptr;
+    bool table_pending = false;
     int device = 0;
 
     Particles pb[2]{};
@@ -331,8 +336,8 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     const int first64 = mlp + c->k32;
     a.first64 = first64;
     a.explicit_start = !mlp;
-    a.table = c->ws_table;
-    a.prange = c->ws_norm + 2 * (c->wsD + 2);
+    a.ws = WsNet{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
+    a.ws_table = c->ws_table;
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kI++;
         if (mlp && a.k == 0) {   // the predictor pass takes the place of sweep 0
@@ -488,17 +493,44 @@ int flags_to_status(int32_t f) {
 // Finish Subsystem I (more sweeps / commit) after a status read.
 void enqueue_begin_I(ecpic_ctx *c) {
     c->kI = 0;
+    const bool have_table = c->table_pending;
+    if (c->table_pending) {   // the tables read coefA, which prep_records rewrites
+        hipStreamWaitEvent(c->stream, c->ev_table, 0);
+        c->table_pending = false;
+    }
     timed(c, "begin_I", [&] {
         launch_prep_records(c->P, c->stream, c->stI, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                             c->coefE[0], c->M);
     });
-    if (c->ws_on) {
+    if (c->ws_on && !have_table) {
         WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
         timed(c, "ws_table", [&] {
-            launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->M,
-                            c->ws_table);
+            launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc],
+                            c->M, c->ws_table);
         });
     }
+}
+
+// Tables for the next step's predictor, on the second stream, as soon as
+// e_x^{n+1} is committed: they run while Subsystem II of this step does.  The
+// transverse features are those of a_perp^n (Subsystem II has not produced
+// a_perp^{n+1} yet); the tables only seed the Picard iteration.
+void enqueue_next_tables(ecpic_ctx *c) {
+    if (!c->ws_on) return;
+    WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
+    hipEventRecord(c->ev_ready, c->stream);
+    hipStreamWaitEvent(c->aux, c->ev_ready, 0);
+    launch_ws_table(c->P, c->aux, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc ^ 1], c->M,
+                    c->ws_table);
+    hipEventRecord(c->ev_table, c->aux);
+    c->table_pending = true;
+}
+
+// A rolled-back step leaves no tables behind (they would describe its state).
+void drop_next_tables(ecpic_ctx *c) {
+    if (!c->table_pending) return;
+    hipStreamWaitEvent(c->stream, c->ev_table, 0);
+    c->table_pending = false;
 }
 
 // Slots of the training pairs advance after every committed Subsystem I step.
@@ -595,6 +627,9 @@ void free_all(ecpic_ctx *c) {
     if (c->h) hipHostFree(c->h);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
     for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
+    if (c->aux) { hipStreamSynchronize(c->aux); hipStreamDestroy(c->aux); }
+    if (c->ev_ready) hipEventDestroy(c->ev_ready);
+    if (c->ev_table) hipEventDestroy(c->ev_table);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
 }
 
@@ -768,6 +803,13 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
         if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return ECPIC_EDEVICE; }
         c->own_stream = true;
     }
+    if (hipStreamCreate(&c->aux) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_table, hipEventDisableTiming) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return ECPIC_EDEVICE;
+    }
     rc = alloc_all(c);
     if (rc) {
         free_all(c);
@@ -790,6 +832,7 @@ int ecpic_destroy(ecpic_ctx *c) {
 int ecpic_set_particles(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
     if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     double *dx_ = nullptr, *dp_ = nullptr;
     if (dalloc(&dx_, n) || dalloc(&dp_, n)) { if (dx_) hipFree(dx_); return ECPIC_ENOMEM; }
     int rc = ECPIC_OK;
@@ -807,6 +850,7 @@ int ecpic_set_particles(ecpic_ctx *c, const double *x, const double *p, int64_t 
 int ecpic_set_particles_dev(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
     if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     return load_particles_dev(c, x, p);
 }
 
@@ -840,6 +884,7 @@ int ecpic_set_fields(ecpic_ctx *c, const double *ex, const double *ey, const dou
                      const double *az) {
     if (!c) return ECPIC_EINVAL;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     int rc = upload_padded(c, ex, c->ex[c->exc]);
     if (!rc) rc = upload_padded(c, ey, c->ey[c->trc]);
     if (!rc) rc = upload_padded(c, ez, c->ez[c->trc]);
@@ -999,6 +1044,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         enqueue_begin_I(c);
         enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
         enqueue_commit_I(c);
+        enqueue_next_tables(c);
         enqueue_begin_II(c, true);
         IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
         enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
@@ -1017,7 +1063,10 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         const int nII = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
         if (sI) { sI[s].sweeps = sweeps_done_I(c); sI[s].fp32_sweeps = fp32_sweeps_done_I(c); sI[s].residual = c->h->I.res; }
         if (sII) { sII[s].sweeps = nII; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
-        if (rc) return rc;   // nothing swapped: the step is rolled back
+        if (rc) {   // nothing swapped: the step is rolled back
+            drop_next_tables(c);
+            return rc;
+        }
         c->guessI = std::max(1, nI);
         c->guessII = std::max(1, nII);
         c->cur ^= 1;
@@ -1087,6 +1136,7 @@ int ecpic_ws_train(ecpic_ctx *c, const ecpic_ws_train_config *tc, float *final_l
     const int64_t n = std::min(c->ws_base, c->ws_cap);
     if (n < 1) return ECPIC_ESTATE;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     const int steps = tc->steps ? tc->steps : 2000, B = tc->batch ? tc->batch : 1024;
     const float lr = tc->lr > 0.0f ? tc->lr : 1e-3f;
     int rc = ws_scratch(c, B / 32);
@@ -1124,6 +1174,7 @@ int ecpic_ws_set_weights(ecpic_ctx *c, const float *w, int64_t n) {
     int64_t need = 0;
     if (!c || !w || ecpic_ws_n_params(c, &need) || n != need) return ECPIC_EINVAL;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     HIPCHK(hipMemcpyAsync(c->ws_theta, w, sizeof(float) * c->wsNP, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->ws_norm, w + c->wsNP, sizeof(float) * (need - c->wsNP), hipMemcpyHostToDevice,
                           c->stream));
@@ -1136,6 +1187,8 @@ int ecpic_ws_set_weights(ecpic_ctx *c, const float *w, int64_t n) {
 int ecpic_ws_enable(ecpic_ctx *c, int32_t on) {
     if (!c) return ECPIC_EINVAL;
     if (on && !c->ws_ready) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    drop_next_tables(c);
     c->ws_on = on != 0;
     return ECPIC_OK;
 }
@@ -1173,6 +1226,7 @@ int ecpic_ws_table(ecpic_ctx *c, float *table) {
     if (!c || !table) return ECPIC_EINVAL;
     if (!c->ws_ready) return ECPIC_ESTATE;
     hipSetDevice(c->device);
+    drop_next_tables(c);
     WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
     launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                         c->coefE[0], c->M);

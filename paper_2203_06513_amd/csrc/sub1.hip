@@ -17,7 +17,7 @@
 // piece; waves with no such step skip that code.
 #include <type_traits>
 
-#include "coef.hpp"
+#include "sweep.hpp"
 
 namespace ecpic {
 
@@ -43,23 +43,6 @@ __device__ __forceinline__ void load_coef1(Coef1<P> &k, int c, const double *coe
         for (int i = 0; i < P; ++i) k.eb[r][i] = e[r * NE + i];
     }
 }
-
-template <int P>
-struct Moments {
-    double A[P], R[P], L[P];   // sum over particles of (signed piece length) h_i(piece)
-};
-
-// End point of a step: xi0 in [c, c+1), t1 = (xi0 + d) - c is exact in floating
-// point, so the committed position and the deposited segment agree.
-__device__ __forceinline__ void end_point(double xi0, double d, int c, double &t1, int &s, int &flags) {
-    t1 = (xi0 + d) - (double)c;
-    if (!(t1 > -1.0 && t1 < 2.0)) {   // |d| >= 1 cell, or NaN
-        flags |= FLAG_CFL;
-        t1 = t1 >= 2.0 ? 1.5 : (t1 <= -1.0 ? -0.5 : 0.5);
-    }
-    s = t1 >= 1.0 ? 1 : (t1 < 0.0 ? -1 : 0);
-}
-
 
 struct MapOut {
     double dn, p1, dused, t1;
@@ -121,46 +104,6 @@ __device__ __forceinline__ MapOut particle_map(const Coef1<P> &k, double xi0, in
     return o;
 }
 
-// Wave sum of the moments and conversion to the P+2 V1 slots of the wave's
-// particles (slot q <-> V1 index c - P + q); lane q < P+2 returns slot q.
-template <int P>
-__device__ __forceinline__ double moments_to_slots(const Moments<P> &mo) {
-    constexpr Pieces<P - 1> Q{};
-    double t[3 * P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        t[i] = wave_sum_dpp(mo.A[i]);
-        t[P + i] = wave_sum_dpp(mo.R[i]);
-        t[2 * P + i] = wave_sum_dpp(mo.L[i]);
-    }
-    const int q = threadIdx.x & (WAVE - 1);
-    double out = 0.0;
-#pragma unroll
-    for (int i = 0; i < 3 * P; ++i) {
-        const int grp = i / P, ii = i % P;   // 0: cell c, 1: c+1, 2: c-1
-        const int m = (grp == 0 ? P : (grp == 1 ? P + 1 : P - 1)) - q;   // index c + shift - m == c - P + q
-        out += (m >= 0 && m < P) ? Q.q[m < 0 ? 0 : (m >= P ? P - 1 : m)][ii] * t[i] : 0.0;
-    }
-    return out;
-}
-
-// Values per wave in the partials of a sweep: P+2 current slots, the residual
-// max and the flags.
-template <int P>
-struct UnitI {
-    static constexpr int N = P + 4;
-};
-
-// The rows (64 particles) of an item are split into nw contiguous runs, one per
-// wave of the block, so that a wave's particles are consecutive in the sorted
-// order (the commit relies on it to keep the order stable).
-__device__ __forceinline__ void wave_range(int beg, int end, int wid, int nw, int &wb, int &we) {
-    const int rows = (end - beg + WAVE - 1) / WAVE;
-    const int rpw = (rows + nw - 1) / nw;
-    wb = min(beg + wid * rpw * WAVE, end);
-    we = min(wb + rpw * WAVE, end);
-}
-
 // The sweep.  The block's own-cell coefficients stay in registers; the three
 // cells' records are also staged in LDS, where the rare steps that enter a
 // neighbour cell read them with a per-lane (position-dependent) address.  The
@@ -185,16 +128,6 @@ struct Lane {
     T t0, p0, d, t1, q0, A0y, A0z, g00;
     int s;
 };
-
-// Cell-local end point and cell change of a step (single precision sweeps).
-__device__ __forceinline__ void end_point(float t0, float d, float &t1, int &s, int &flags) {
-    t1 = t0 + d;
-    if (!(t1 > -1.0f && t1 < 2.0f)) {
-        flags |= FLAG_CFL;
-        t1 = t1 >= 2.0f ? 1.5f : (t1 <= -1.0f ? -0.5f : 0.5f);
-    }
-    s = t1 >= 1.0f ? 1 : (t1 < 0.0f ? -1 : 0);
-}
 
 // Gather at the step start, gamma there, the explicit first increment if asked,
 // and the end point of the current increment.  xi0 - c is exact in FP64; the
@@ -254,63 +187,6 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
     dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
     const T big = sizeof(T) == 8 ? (T)1.0e300 : (T)1.0e30f;
     if (!(fabs(dn) < big) || !(fabs(p1) < big)) flags |= FLAG_NONFINITE;
-}
-
-// Single precision moments with Knuth's TwoSum compensation: every product and
-// every addition leaves its rounding error in the companion sum.
-template <int P>
-struct Moments32 {
-    float A[P], R[P], L[P];
-    float cA[P], cR[P], cL[P];
-};
-
-__device__ __forceinline__ void acc_two_sum(float &s, float &c, float a, float b) {
-#pragma clang fp contract(off)
-    const float x = a * b;
-    const float ex = fmaf(a, b, -x);
-    const float t = s + x;
-    const float bp = t - s;
-    const float e = (s - (t - bp)) + (x - bp);
-    s = t;
-    c += e + ex;
-}
-
-__device__ __forceinline__ void acc(double &s, double a, double b) { s = fma(a, b, s); }
-
-template <int P>
-__device__ __forceinline__ void acc_A(Moments<P> &mo, int i, double a, double b) { acc(mo.A[i], a, b); }
-template <int P>
-__device__ __forceinline__ void acc_R(Moments<P> &mo, int i, double a, double b) { acc(mo.R[i], a, b); }
-template <int P>
-__device__ __forceinline__ void acc_L(Moments<P> &mo, int i, double a, double b) { acc(mo.L[i], a, b); }
-template <int P>
-__device__ __forceinline__ void acc_A(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.A[i], mo.cA[i], a, b); }
-template <int P>
-__device__ __forceinline__ void acc_R(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.R[i], mo.cR[i], a, b); }
-template <int P>
-__device__ __forceinline__ void acc_L(Moments32<P> &mo, int i, float a, float b) { acc_two_sum(mo.L[i], mo.cL[i], a, b); }
-
-// Moments of a step from t0 to t1 (end in cell c + s); scale 0 drops it.
-template <int P, typename T, typename MO>
-__device__ __forceinline__ void stage_deposit(MO &mo, bool anycross, T t0, T t1, int s, T scale) {
-    const T zero = (T)0, one = (T)1;
-    const T t1c = fmin(fmax(t1, zero), one);
-    T h[P];
-    homog<P - 1>(fmin(t0, t1c), fmax(t0, t1c), h);
-    const T sA = scale * (t1c - t0);
-#pragma unroll
-    for (int i = 0; i < P; ++i) acc_A<P>(mo, i, sA, h[i]);
-    if (anycross) {
-        const T tl = t1 - (T)s;
-        homog<P - 1>(s > 0 ? zero : (s < 0 ? tl : zero), s > 0 ? tl : (s < 0 ? one : zero), h);
-        const T sB = scale * (t1 - t1c);
-        const T sr = s > 0 ? sB : zero, sl = s < 0 ? sB : zero;
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            acc_R<P>(mo, i, sr, h[i]);
-            acc_L<P>(mo, i, sl, h[i]);
-        }
-    }
 }
 
 // Has sweep k-1 met the tolerance?  Records kconv if so.  Only FP64 sweeps
@@ -480,69 +356,6 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
             if (wid == 0) a.cnt[(size_t)item * 3 + lane] = tot;
         }
     }
-}
-
-// Predictor pass of the learned warm start, run as sweep 0: each particle's
-// increment delta^(1) = dt p/gamma0 + dt^2 y, with y interpolated bilinearly in
-// its cell's table of network outputs over (t, p) nodes, and the current of
-// that increment deposited like a sweep's, so that the field kernel after it
-// makes e^(1) consistent with delta^(1).  The later sweeps start from both.
-template <int P>
-__global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
-    DevStatus *st = a.st;
-    const int item = blockIdx.x;
-    if (item >= *a.items.n_items) return;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
-    const int c = a.items.cell[item];
-    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    const int nw = blockDim.x / WAVE;
-    int wb, we;
-    wave_range(beg, end, wid, nw, wb, we);
-    const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
-    double ay[P + 1], az[P + 1];
-#pragma unroll
-    for (int i = 0; i <= P; ++i) { ay[i] = ra[i]; az[i] = ra[P + 1 + i]; }
-    const float *tab = a.table + (size_t)c * (WS_NT * WS_NP);
-    const float plo = a.prange[0], phi = a.prange[1];
-    const float pscale = (float)(WS_NP - 1) / (phi - plo);
-    const double dt2_dx = a.dt * a.dt * a.inv_dx;
-    Moments<P> mo{};
-    int flags = 0;
-    for (int row = wb; row < we; row += WAVE) {
-        const int ia = row + lane;
-        const bool valid = ia < we;
-        const int il = valid ? ia : we - 1;
-        const double xi0 = a.xi[il], p0 = a.p[il];
-        double t0 = xi0 - (double)c;
-        if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
-        const double A0y = horner<P + 1>(ay, t0), A0z = horner<P + 1>(az, t0);
-        const double g00 = fsqrt(fma(p0, p0, 1.0) + A0y * A0y + A0z * A0z);
-        const float ft = (float)t0 * (float)(WS_NT - 1);
-        const int it = min((int)ft, WS_NT - 2);
-        const float wt = ft - (float)it;
-        const float fp = fminf(fmaxf(((float)p0 - plo) * pscale, 0.0f), (float)(WS_NP - 1));
-        const int ip = min((int)fp, WS_NP - 2);
-        const float wp = fp - (float)ip;
-        const float *q = tab + it * WS_NP + ip;
-        const float y = (1.0f - wt) * ((1.0f - wp) * q[0] + wp * q[1]) + wt * ((1.0f - wp) * q[WS_NP] + wp * q[WS_NP + 1]);
-        const double d = a.dt_dx * p0 * frcp(g00) + dt2_dx * (double)y;
-        double t1;
-        int s;
-        end_point(xi0, d, c, t1, s, flags);
-        stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
-        if (valid) {
-            a.d1[ia] = d;
-            if (a.f1) a.f1[ia] = (float)d;
-        }
-    }
-    const double slot = moments_to_slots<P>(mo);
-    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
-    double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
-    double v = slot;
-    v = lane == P + 2 ? 0.0 : v;
-    v = lane == P + 3 ? (double)fl : v;
-    if (lane < UnitI<P>::N) out[lane] = v;
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -896,12 +709,6 @@ void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStrea
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW
-}
-
-void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a) {
-#define ECPIC_WP(PP) case PP: hipLaunchKernelGGL((k_ws_predict<PP>), dim3(grid), dim3(block), 0, s, a); break;
-    switch (P) { ECPIC_WP(2) ECPIC_WP(3) ECPIC_WP(4) ECPIC_WP(5) }
-#undef ECPIC_WP
 }
 
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
