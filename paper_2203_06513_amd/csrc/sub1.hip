@@ -21,89 +21,6 @@
 
 namespace ecpic {
 
-template <int P>
-struct Coef1 {
-    double ay[3][P + 1], az[3][P + 1];   // A on cells c-1, c, c+1
-    double eb[3][P];                     // ebar piece-mean weights on cells c-1, c, c+1
-};
-
-template <int P>
-__device__ __forceinline__ void load_coef1(Coef1<P> &k, int c, const double *coefA, const double *coefE) {
-    constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
-    const double *a = coefA + (size_t)(rec_index(c) - 1) * NA;
-    const double *e = coefE + (size_t)(rec_index(c) - 1) * NE;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int i = 0; i <= P; ++i) {
-            k.ay[r][i] = a[r * NA + i];
-            k.az[r][i] = a[r * NA + P + 1 + i];
-        }
-#pragma unroll
-        for (int i = 0; i < P; ++i) k.eb[r][i] = e[r * NE + i];
-    }
-}
-
-struct MapOut {
-    double dn, p1, dused, t1;
-    int s;
-};
-
-// The particle map of one sweep (see the file header).
-template <int P>
-__device__ __forceinline__ MapOut particle_map(const Coef1<P> &k, double xi0, int c, double p0, double d,
-                                               bool explicit_start, double dt, double dt_dx, double inv_dx,
-                                               int &flags) {
-    MapOut o;
-    double t0 = xi0 - (double)c;
-    if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
-    const double A0y = horner<P + 1>(k.ay[1], t0), A0z = horner<P + 1>(k.az[1], t0);
-    const double q0 = fma(p0, p0, 1.0);
-    const double g00 = fsqrt(q0 + A0y * A0y + A0z * A0z);
-    if (explicit_start) d = dt_dx * p0 * frcp(g00);
-    o.dused = d;
-    double t1;
-    int s;
-    end_point(xi0, d, c, t1, s, flags);
-    o.t1 = t1;
-    o.s = s;
-    const Seg<double> g = make_seg(t0, t1, s);
-    double hA[P];
-    homog<P - 1>(g.aA, g.bA, hA);
-    double LE = pmean<P>(k.eb[1], hA);
-    double DAy = divdiff<P>(k.ay[1], hA), DAz = divdiff<P>(k.az[1], hA);
-    double A1y, A1z;
-    if (__ballot(s != 0)) {
-        const double tl = t1 - (double)s;
-        const double yc = horner<P + 1>(k.ay[1], tl), yr = horner<P + 1>(k.ay[2], tl), yl = horner<P + 1>(k.ay[0], tl);
-        const double zc = horner<P + 1>(k.az[1], tl), zr = horner<P + 1>(k.az[2], tl), zl = horner<P + 1>(k.az[0], tl);
-        A1y = s > 0 ? yr : (s < 0 ? yl : yc);
-        A1z = s > 0 ? zr : (s < 0 ? zl : zc);
-        double hB[P];
-        homog<P - 1>(g.aB, g.bB, hB);
-        const double EB = s > 0 ? pmean<P>(k.eb[2], hB) : pmean<P>(k.eb[0], hB);
-        const double DyB = s > 0 ? divdiff<P>(k.ay[2], hB) : divdiff<P>(k.ay[0], hB);
-        const double DzB = s > 0 ? divdiff<P>(k.az[2], hB) : divdiff<P>(k.az[0], hB);
-        if (s != 0) {
-            const double inv = frcp(g.sA + g.sB);
-            LE = (g.sA * LE + g.sB * EB) * inv;
-            DAy = (g.sA * DAy + g.sB * DyB) * inv;
-            DAz = (g.sA * DAz + g.sB * DzB) * inv;
-        }
-    } else {
-        A1y = horner<P + 1>(k.ay[1], t1);
-        A1z = horner<P + 1>(k.az[1], t1);
-    }
-    const double qa1 = A1y * A1y + A1z * A1z;
-    const double g01 = fsqrt(q0 + qa1);
-    const double F = LE - ((A0y + A1y) * DAy + (A0z + A1z) * DAz) * inv_dx * frcp(g00 + g01);
-    o.p1 = fma(dt, F, p0);
-    const double g11 = fsqrt(fma(o.p1, o.p1, 1.0) + qa1);
-    o.dn = dt_dx * (p0 + o.p1) * frcp(g01 + g11);
-    if (!(fabs(o.dn) < 1.0e300) || !(fabs(o.p1) < 1.0e300)) flags |= FLAG_NONFINITE;
-    return o;
-}
-
 // The sweep.  The block's own-cell coefficients stay in registers; the three
 // cells' records are also staged in LDS, where the rare steps that enter a
 // neighbour cell read them with a per-lane (position-dependent) address.  The
@@ -189,6 +106,33 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
     if (!(fabs(dn) < big) || !(fabs(p1) < big)) flags |= FLAG_NONFINITE;
 }
 
+// The records of cells c-1, c, c+1 into LDS (one value per thread; the caller
+// synchronises before reading them) and those of cell c into registers.
+template <int P, typename T>
+__device__ __forceinline__ void stage_records(LdsRec<P, T> *rec, Own<P, T> &o1, const double *coefA,
+                                              const double *coefE, int c) {
+    constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
+    {
+        const double *ra = coefA + (size_t)(rec_index(c) - 1) * NA;
+        const double *re = coefE + (size_t)(rec_index(c) - 1) * NE;
+        const int t = threadIdx.x;
+        if (t < 3 * NA) {
+            const int r = t / NA, i = t % NA;
+            if (i <= P) rec[r].ay[i] = (T)ra[t];
+            else rec[r].az[i - P - 1] = (T)ra[t];
+        } else if (t < 3 * NA + 3 * NE) {
+            const int u = t - 3 * NA, r = u / NE, i = u % NE;
+            rec[r].eb[i] = (T)re[u];
+        }
+    }
+    const double *ra = coefA + (size_t)rec_index(c) * NA;
+    const double *re = coefE + (size_t)rec_index(c) * NE;
+#pragma unroll
+    for (int i = 0; i <= P; ++i) { o1.ay[i] = (T)ra[i]; o1.az[i] = (T)ra[P + 1 + i]; }
+#pragma unroll
+    for (int i = 0; i < P; ++i) o1.eb[i] = (T)re[i];
+}
+
 // Has sweep k-1 met the tolerance?  Records kconv if so.  Only FP64 sweeps
 // (index >= first64) can end the iteration.
 __device__ __forceinline__ bool prev_converged(DevStatus *st, int k, int first64, double dx, double tol,
@@ -263,29 +207,8 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
         np = a.p[il];
         nd = explicit_start ? (T)0 : (d32in ? (T)d32in[il] : din[il]);
     }
-    {
-        constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
-        const double *ra = a.coefA + (size_t)(rec_index(c) - 1) * NA;
-        const double *re = coefE + (size_t)(rec_index(c) - 1) * NE;
-        const int t = threadIdx.x;
-        if (t < 3 * NA) {
-            const int r = t / NA, i = t % NA;
-            if (i <= P) rec[r].ay[i] = (T)ra[t];
-            else rec[r].az[i - P - 1] = (T)ra[t];
-        } else if (t < 3 * NA + 3 * NE) {
-            const int u = t - 3 * NA, r = u / NE, i = u % NE;
-            rec[r].eb[i] = (T)re[u];
-        }
-    }
     Own<P, T> o1;
-    {
-        const double *ra = a.coefA + (size_t)rec_index(c) * RecA<P>::N;
-        const double *re = coefE + (size_t)rec_index(c) * RecE<P>::N;
-#pragma unroll
-        for (int i = 0; i <= P; ++i) { o1.ay[i] = (T)ra[i]; o1.az[i] = (T)ra[P + 1 + i]; }
-#pragma unroll
-        for (int i = 0; i < P; ++i) o1.eb[i] = (T)re[i];
-    }
+    stage_records<P, T>(rec, o1, a.coefA, coefE, c);
     __syncthreads();
     MO mo{};
     const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx;
@@ -403,6 +326,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     double *S = cp + (size_t)clen * NS;
     double *tp = S + slen;
     double *enl = tp + a.ntaps;
+    double *enw = enl + FIELD_OUT;   // e_x^n on the block's cells
     const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
     // loads that do not depend on the partials: this quad's output cell
     const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
@@ -410,6 +334,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     const double en_q = a.en[jqm + HALO];
     const double ek_q = ek[jqm + HALO];
     for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
+    if (threadIdx.x < FIELD_OUT) enw[threadIdx.x] = a.en[imod(j0 + (int)threadIdx.x, M) + HALO];
     double rx = 0.0;
     int flags = 0;
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
@@ -458,7 +383,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         const int j = j0 + q;
         if (q < FIELD_OUT && j < M) {
             double r[P];
-            make_recE<P>([&](int jj) { return 0.5 * (a.en[imod(jj, M) + HALO] + enl[jj - j0]); }, j, r);
+            make_recE<P>([&](int jj) { return 0.5 * (enw[jj - j0] + enl[jj - j0]); }, j, r);
             for (int i = 0; i < P; ++i) store_record(Eout, M, j, RecE<P>::N, i, r[i]);
         }
     }
@@ -544,11 +469,6 @@ __device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first
     return prev_converged(st, nsweeps, first64, dx, tol, writer) ? nsweeps - 1 : -1;
 }
 
-__device__ __forceinline__ int mover_type(double xi0, double d, int c) {
-    const double t1 = (xi0 + d) - (double)c;
-    return t1 >= 1.0 ? 2 : (t1 < 0.0 ? 0 : 1);   // 0 left, 1 stay, 2 right
-}
-
 // Single block: settles the convergence test, then from the mover counts the
 // converged sweep left computes the destinations of every item's left / stay /
 // right movers, the item list of the new order and e_x^{n+1}.
@@ -606,13 +526,13 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
 // One training pair of the learned warm start: the particle's features at the
 // step start and the converged increments (see mlp.hip for the definitions).
 template <int P>
-__device__ __forceinline__ void record_pair(const CommitIArgs &a, const Coef1<P> &kc, int c, int pid, double xi0,
+__device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, double> &o, int c, int pid, double xi0,
                                             double p0, double d, double p1) {
     constexpr int D = ws_d(P);
     const int64_t slot = a.rec.base + pid / a.rec.stride;
     if (slot >= a.rec.cap) return;
     const double t0 = xi0 - (double)c;
-    const double Ay = horner<P + 1>(kc.ay[1], t0), Az = horner<P + 1>(kc.az[1], t0);
+    const double Ay = horner<P + 1>(o.ay, t0), Az = horner<P + 1>(o.az, t0);
     const double g0 = sqrt(1.0 + p0 * p0 + Ay * Ay + Az * Az);
     float *f = a.rec.feat + slot * D;
     f[0] = (float)(t0 - 0.5);
@@ -634,6 +554,7 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Coef1<P>
 // gave it; ballots rank them within a row.
 template <int P>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
+    __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
     const int item = blockIdx.x;
     if (item >= *a.items.n_items || !commit_enabled(a.st)) return;
     const CommitPick pk = commit_pick(a, a.st->kconv);
@@ -644,35 +565,38 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
     const int nw = blockDim.x / WAVE;
     int wb, we;
     wave_range(beg, end, wid, nw, wb, we);
-    Coef1<P> kc;
-    load_coef1<P>(kc, c, a.coefA, pk.coefE);
+    Own<P, double> o1;
+    stage_records<P, double>(rec, o1, a.coefA, pk.coefE, c);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     const int32_t *bs = a.base + (size_t)item * 3;
     const int32_t *ws = a.wpre + ((size_t)item * nw + wid) * 3;
     int run0 = bs[0] + ws[0], run1 = bs[1] + ws[1], run2 = bs[2] + ws[2];
     int flags = 0;
+    __syncthreads();
     for (int r0 = wb; r0 < we; r0 += WAVE) {
         const int i = r0 + lane;
         const bool valid = i < we;
-        int t = -1;
-        double xin = 0.0, p1 = 0.0;
-        int32_t pid = 0;
-        if (valid) {
-            const double xi0 = a.cur.xi[i];
-            const double p0 = a.cur.p[i];
-            const double d = pk.d[i];
-            pid = a.cur.id[i];
-            const MapOut o = particle_map<P>(kc, xi0, c, p0, d, false, a.dt, a.dt_dx, a.inv_dx, flags);
-            p1 = o.p1;
-            t = mover_type(xi0, d, c);
-            if (a.rec.stride > 0 && pid % a.rec.stride == a.rec.phase) record_pair<P>(a, kc, c, pid, xi0, p0, d, p1);
-            xin = xi0 + d;
-            if (xin >= (double)M) xin -= (double)M;
-            else if (xin < 0.0) {
-                xin += (double)M;
-                if (xin >= (double)M) xin = __longlong_as_double(__double_as_longlong((double)M) - 1);
-            }
+        const int il = valid ? i : we - 1;
+        const double xi0 = a.cur.xi[il];
+        const double p0 = a.cur.p[il];
+        const double d = pk.d[il];
+        const int32_t pid = a.cur.id[il];
+        // the committed momentum: the map evaluated at the committed increment
+        Lane<double> La;
+        La.p0 = p0;
+        La.d = d;
+        stage_gather<P, double>(o1, La, xi0, c, false, a.dt_dx, flags);
+        double p1, dn;
+        stage_push<P, double>(o1, rec, __ballot(La.s != 0) != 0, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags);
+        const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
+        double xin = xi0 + d;
+        if (xin >= (double)M) xin -= (double)M;
+        else if (xin < 0.0) {
+            xin += (double)M;
+            if (xin >= (double)M) xin = __longlong_as_double(__double_as_longlong((double)M) - 1);
         }
+        if (valid && a.rec.stride > 0 && pid % a.rec.stride == a.rec.phase)
+            record_pair<P>(a, o1, c, pid, xi0, p0, d, p1);
         const unsigned long long b0 = __ballot(t == 0), b1 = __ballot(t == 1), b2 = __ballot(t == 2);
         if (valid) {
             int dest;
@@ -714,7 +638,7 @@ void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStrea
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
     const int grid = (M + FIELD_OUT - (P - 1) - 1) / (FIELD_OUT - (P - 1));
     const int slen = FIELD_OUT + a.ntaps - 1;
-    const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + a.ntaps + FIELD_OUT);
+    const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + a.ntaps + 2 * FIELD_OUT);
 #define ECPIC_F(PP) case PP: hipLaunchKernelGGL((k_field_I<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F(2) ECPIC_F(3) ECPIC_F(4) ECPIC_F(5) }
 #undef ECPIC_F

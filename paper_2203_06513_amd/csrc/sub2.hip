@@ -147,6 +147,8 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     double *tp = Sz + slen;
     double *eyl = tp + a.ntaps;
     double *ezl = eyl + FIELD2_OUT;
+    double *bay = ezl + FIELD2_OUT;   // a^n - dt/2 e^n on the block's cells (the part of a^(k+1) known now)
+    double *baz = bay + FIELD2_OUT;
     const double *eyk = k == 0 ? a.eyn : ((k & 1) ? a.ey1 : a.ey0);
     const double *ezk = k == 0 ? a.ezn : ((k & 1) ? a.ez1 : a.ez0);
     const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
@@ -154,6 +156,11 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     const double E0y_q = a.E0y[jqm], E0z_q = a.E0z[jqm];
     const double eyk_q = eyk[jqm + HALO], ezk_q = ezk[jqm + HALO];
     for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
+    if (threadIdx.x < FIELD2_OUT) {
+        const int jm = imod(j0 + (int)threadIdx.x, M) + HALO;
+        bay[threadIdx.x] = a.ayn[jm] - a.half_dt * a.eyn[jm];
+        baz[threadIdx.x] = a.azn[jm] - a.half_dt * a.ezn[jm];
+    }
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         const int c = imod(clo + t, M);
         double v[NS];
@@ -186,11 +193,20 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     int flags = 0;
     {
         const double *Syq = Sy + quad + a.ntaps - 1, *Szq = Sz + quad + a.ntaps - 1;
-        double cy = 0.0, cz = 0.0;
-        for (int i = ql; i < a.ntaps; i += 4) {
+        double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0;
+        int i = ql;
+        for (; i + 4 < a.ntaps; i += 8) {
+            cy = fma(tp[i], Syq[-i], cy);
+            cz = fma(tp[i], Szq[-i], cz);
+            cy1 = fma(tp[i + 4], Syq[-i - 4], cy1);
+            cz1 = fma(tp[i + 4], Szq[-i - 4], cz1);
+        }
+        if (i < a.ntaps) {
             cy = fma(tp[i], Syq[-i], cy);
             cz = fma(tp[i], Szq[-i], cz);
         }
+        cy += cy1;
+        cz += cz1;
         cy += dpp_d<0xB1>(cy);
         cz += dpp_d<0xB1>(cz);
         cy += dpp_d<0x4E>(cy);
@@ -217,9 +233,9 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
             for (int i = 0; i <= P; ++i) {
                 double sy = 0.0, sz = 0.0;
                 for (int m = 0; m <= P; ++m) {
-                    const int jj = j - m, jm = imod(jj, M);
-                    const double ay = a.ayn[jm + HALO] - a.half_dt * (a.eyn[jm + HALO] + eyl[jj - j0]);
-                    const double az = a.azn[jm + HALO] - a.half_dt * (a.ezn[jm + HALO] + ezl[jj - j0]);
+                    const int u = j - m - j0;
+                    const double ay = bay[u] - a.half_dt * eyl[u];
+                    const double az = baz[u] - a.half_dt * ezl[u];
                     sy += ay * B.c[m][i];
                     sz += az * B.c[m][i];
                 }
@@ -362,7 +378,7 @@ void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArg
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
     const int grid = (M + FIELD2_OUT - P - 1) / (FIELD2_OUT - P);
     const int slen = FIELD2_OUT + a.ntaps - 1;
-    const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + a.ntaps + 2 * FIELD2_OUT);
+    const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + a.ntaps + 4 * FIELD2_OUT);
 #define ECPIC_F2(PP) case PP: hipLaunchKernelGGL((k_field_II<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F2(2) ECPIC_F2(3) ECPIC_F2(4) ECPIC_F2(5) }
 #undef ECPIC_F2
