@@ -83,6 +83,8 @@ typedef struct {
     void *stream;             /* hipStream_t to run on (e.g. torch's); NULL => library-owned */
     int32_t fp32_sweeps;      /* ECPIC_FP32_MIXED: FP32 sweeps that open every Subsystem I substep
                                  before the FP64 ones; 0 => 2.  Ignored for ECPIC_FP64. */
+    int32_t sweep_guess;      /* sweeps / iterations enqueued per substep before the first status
+                                 read of a step; later steps use what earlier ones needed; 0 => 4 */
 } ecpic_config;
 
 typedef struct {
@@ -145,7 +147,10 @@ int ecpic_substep_fields(ecpic_ctx *ctx, ecpic_iter_stats *stats);
 /* nsteps Lie-Trotter steps, Subsystem I then II (Section 5; Subsystem III is the
  * identity without spin).  per_step_I / per_step_II: arrays of nsteps entries
  * or NULL.  On ENOTCONV the failing step is rolled back and *steps_done (if
- * not NULL) tells how many steps completed. */
+ * not NULL) tells how many steps completed.  Steps are enqueued in batches of
+ * up to 16, each gated on the device on the one before having committed; a
+ * step that needs more sweeps than were enqueued is finished alone and the
+ * batch resumes after it, so the result does not depend on the batching. */
 int ecpic_step(ecpic_ctx *ctx, int32_t nsteps, ecpic_iter_stats *per_step_I,
                ecpic_iter_stats *per_step_II, int32_t *steps_done);
 

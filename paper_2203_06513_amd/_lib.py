@@ -41,7 +41,8 @@ class Config(C.Structure):
     _fields_ = [("L", C.c_double), ("M", C.c_int32), ("degree", C.c_int32), ("n_particles", C.c_int64),
                 ("weight", C.c_double), ("dt", C.c_double), ("picard_tol", C.c_double),
                 ("picard_max_iter", C.c_int32), ("precision", C.c_int32), ("warmstart", C.c_int32),
-                ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32)]
+                ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32),
+                ("sweep_guess", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -136,11 +137,11 @@ class Context:
     def __init__(self, L: float, M: int, degree: int, n_particles: int, dt: float, tol: float,
                  weight: float = 0.0, max_iter: int = 0, precision: int = FP64,
                  warmstart: int = WS_EXPLICIT, map: int = MAP_JACOBI, device: int = 0,
-                 stream: Optional[int] = None, fp32_sweeps: int = 0):
+                 stream: Optional[int] = None, fp32_sweeps: int = 0, sweep_guess: int = 0):
         self._lib = load()
         self.cfg = Config(float(L), int(M), int(degree), int(n_particles), float(weight), float(dt),
                           float(tol), int(max_iter), int(precision), int(warmstart), int(map), int(device),
-                          C.c_void_p(stream) if stream else None, int(fp32_sweeps))
+                          C.c_void_p(stream) if stream else None, int(fp32_sweeps), int(sweep_guess))
         self.M = int(M)
         self.N = int(n_particles)
         h = C.c_void_p()

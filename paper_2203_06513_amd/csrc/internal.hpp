@@ -129,6 +129,7 @@ struct CommitIArgs {
     const double *coefA, *coefE0, *coefE1;
     const double *ek0, *ek1;
     double *ex_next;               // padded e_x^{n+1}
+    DevStatus *stII;               // reset here, gated on this commit (null: leave it)
     const int32_t *cnt, *wpre;     // mover counts of the converged sweep (see SweepIArgs)
     int32_t *tot;                  // [M][3]
     int32_t *base;                 // [max_items][3] destination of each item's first mover of each kind
@@ -138,6 +139,7 @@ struct CommitIArgs {
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
+    int32_t scan_in_lds;           // the scan keeps tot / nstart / counts in LDS (5 M + 1 ints <= 64 KiB)
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     int64_t N;
 };
@@ -146,7 +148,7 @@ struct CommitIArgs {
 struct SweepIIArgs {
     const double *xi, *p;
     ItemList items;
-    const double *coefAn;                     // A-records of a_perp^n
+    const double *coefAn;                     // A-records of a_perp^n (those of Subsystem I)
     const double *coefAk0, *coefAk1;          // A-records of a^(k) = a^n - dt/2 (e^n + e^(k)), by parity
     double *part;                             // [max_items][waves per item][2 (deg+1)]
     DevStatus *st;

@@ -353,12 +353,10 @@ __global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const uns
 // kernel after it makes e^(1) consistent with delta^(1).  The Picard sweeps
 // start from both.
 template <int P>
-__global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
+__device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
     __shared__ float tab[WS_NT * WS_NP];
     DevStatus *st = a.st;
-    const int item = blockIdx.x;
-    if (item >= *a.items.n_items) return;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+        if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
@@ -410,6 +408,14 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
     v = lane == P + 2 ? 0.0 : v;
     v = lane == P + 3 ? (double)fl : v;
     if (lane < UnitI<P>::N) out[lane] = v;
+}
+
+// One block per work item; the grid may exceed the item count (the count of a
+// step enqueued ahead is only known on the device) and the extra blocks exit.
+template <int P>
+__global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
+    if ((int)blockIdx.x >= *a.items.n_items) return;
+    ws_predict_item<P>(a, blockIdx.x);
 }
 
 // ---- launchers ------------------------------------------------------------

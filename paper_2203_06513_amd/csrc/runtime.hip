@@ -31,16 +31,17 @@ void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArg
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a);
 void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, const double *az,
                          const double *e, double *coefA, double *coefE, int M);
-void launch_begin_II(int P, hipStream_t s, DevStatus *st, const DevStatus *gate_src, const double *ayn,
-                     const double *azn, const double *eyn, const double *ezn, double dt, double *coefAn,
-                     double *coefAk0, const double *m0, const double *kr, double r2, double ck, const double *taps,
-                     int ntaps, int mlo, int M, double *E0y, double *E0z);
+void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *gate_src, DevStatus *stII,
+                       const double *ayn, const double *azn,
+                       const double *eyn, const double *ezn, const double *exn, double dt, double *coefA,
+                       double *coefE0, double *coefAk0, int do_II, const double *m0, const double *kr, double r2,
+                       double ck, const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z);
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
                  double alpha, int M);
-void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const double *eyn, const double *ezn,
-                      const double *ayn, const double *azn, const double *ey0, const double *ey1,
-                      const double *ez0, const double *ez1, double *ey_next, double *ez_next, double *ay_next,
-                      double *az_next, double half_dt, int M, int nsweeps, double tol);
+void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
+                      const double *eyn, const double *ezn, const double *ayn, const double *azn, const double *ey0,
+                      const double *ey1, const double *ez0, const double *ez1, double *ey_next, double *ez_next,
+                      double *ay_next, double *az_next, double half_dt, int M, int nsweeps, double tol);
 void launch_energy(int P, int grid, int block, hipStream_t s, const double *xi, const double *p, ItemList items,
                    const double *ay, const double *az, double *part);
 void launch_energy_final(hipStream_t s, const double *part, const int32_t *n_items, double w, const double *ex,
@@ -167,6 +168,10 @@ struct Prof {
 
 }  // namespace
 
+namespace ecpic {
+constexpr int STEP_BATCH = 16;   // steps enqueued before the host reads their statuses
+}
+
 struct ecpic_ctx {
     ecpic_config cfg{};
     int M = 0, P = 0, kmax = 50, block = 256, chunk = 2048, max_items = 0;
@@ -213,16 +218,22 @@ struct ecpic_ctx {
     double *ek[2]{};
     double *eyk[2]{}, *ezk[2]{};
     double *E0y = nullptr, *E0z = nullptr;
-    double *coefA = nullptr, *coefE[2]{}, *coefAn = nullptr, *coefAk[2]{};
+    double *coefA = nullptr, *coefE[2]{}, *coefAk[2]{};
     double *taps1 = nullptr, *tapsA = nullptr;
     int nt1 = 0, mlo1 = 0, ntA = 0, mloA = 0;
     std::vector<double> m0row, m1row, krow;
 
-    DevStatus *stI = nullptr, *stII = nullptr;
+    // Statuses of up to STEP_BATCH steps enqueued ahead, pair by pair (Subsystem
+    // I, II), with their pinned host mirrors; stI, stII, h, hdev point at the
+    // pair of the step being enqueued or inspected.
+    DevStatus *st_ring = nullptr;
     struct HostMirror {
         DevStatus I, II;
         int32_t n_items_next;
-    } *h = nullptr;
+    } *h_ring = nullptr, *h_ring_dev = nullptr;   // host address, device address
+    DevStatus *stI = nullptr, *stII = nullptr;
+    HostMirror *h = nullptr;
+    DevStatus *hdev = nullptr;   // device address of h->I (the Subsystem II commit writes it)
     static_assert(offsetof(HostMirror, II) == sizeof(DevStatus), "statuses are copied as one block");
 
     double *rho = nullptr, *rvec = nullptr, *uvec = nullptr, *out5 = nullptr, *part_e = nullptr;
@@ -230,6 +241,7 @@ struct ecpic_ctx {
     int32_t *count = nullptr;
     bool have_particles = false;
     int guessI = 4, guessII = 4;
+    bool exact_items = true;   // n_items_host is the item count of the step being enqueued
     int kI = 0, kII = 0;   // sweeps / iterations enqueued in the current substeps
     Prof prof;
 };
@@ -287,6 +299,14 @@ int sync(ecpic_ctx *c) {
 
 int particle_grid(ecpic_ctx *c, bool exact) { return std::max(1, exact ? c->n_items_host : c->max_items); }
 
+// Point the current statuses at pair j of the ring.
+void set_slot(ecpic_ctx *c, int j) {
+    c->stI = c->st_ring + 2 * j;
+    c->stII = c->stI + 1;
+    c->h = c->h_ring + j;
+    c->hdev = c->h_ring_dev ? &c->h_ring_dev[j].I : nullptr;
+}
+
 // ---- Subsystem I ----------------------------------------------------------
 SweepIArgs sweep_args(ecpic_ctx *c) {
     SweepIArgs a{};
@@ -331,7 +351,7 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.w = c->w;
     f.M = c->M;
     f.wpi = c->block / 64;
-    const int gridp = particle_grid(c, true);
+    const int gridp = particle_grid(c, c->exact_items);
     const int mlp = c->ws_on ? 1 : 0;
     const int first64 = mlp + c->k32;
     a.first64 = first64;
@@ -376,6 +396,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.ek0 = c->ek[0];
     a.ek1 = c->ek[1];
     a.ex_next = c->ex[c->exc ^ 1];
+    a.stII = c->stII;
     a.cnt = c->cnt;
     a.wpre = c->wpre;
     a.tot = c->tot;
@@ -393,6 +414,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
     a.first64 = (c->ws_on ? 1 : 0) + c->k32;
+    a.scan_in_lds = (5 * (size_t)c->M + 1) * sizeof(int32_t) <= 65536;
     if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
         a.rec.feat = c->ws_feat;
         a.rec.targ = c->ws_targ;
@@ -405,7 +427,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
         a.rec.ex = c->ex[c->exc];
     }
     a.N = c->N;
-    timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, true), c->block, c->stream, a); });
+    timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, c->exact_items), c->block, c->stream, a); });
 }
 
 // ---- Subsystem II ---------------------------------------------------------
@@ -415,23 +437,12 @@ struct IIView {
     bool exact;
 };
 
-void enqueue_begin_II(ecpic_ctx *c, bool gated) {
-    c->kII = 0;
-    const double r = c->dt / (2.0 * c->dx);
-    const int t = c->trc;
-    timed(c, "begin_II", [&] {
-        launch_begin_II(c->P, c->stream, c->stII, gated ? c->stI : nullptr, c->ay[t], c->az[t], c->ey[t], c->ez[t],
-                        c->dt, c->coefAn, c->coefAk[0], c->m0row.data(), c->krow.data(), r * r,
-                        c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
-    });
-}
-
 void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
     SweepIIArgs a{};
     a.xi = v.xi;
     a.p = v.p;
     a.items = v.items;
-    a.coefAn = c->coefAn;
+    a.coefAn = c->coefA;   // a_perp^n: Subsystem I leaves it alone
     a.coefAk0 = c->coefAk[0];
     a.coefAk1 = c->coefAk[1];
     a.part = c->part;
@@ -471,15 +482,17 @@ void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
 void enqueue_commit_II(ecpic_ctx *c) {
     const int t = c->trc, n = t ^ 1;
     timed(c, "commit_II", [&] {
-        launch_commit_II((c->M + 255) / 256, c->stream, c->stII, c->ey[t], c->ez[t], c->ay[t], c->az[t],
+        launch_commit_II((c->M + 255) / 256, c->stream, c->stII, c->stI, c->hdev, c->ey[t], c->ez[t], c->ay[t], c->az[t],
                          c->eyk[0], c->eyk[1], c->ezk[0], c->ezk[1], c->ey[n], c->ez[n], c->ay[n], c->az[n],
                          0.5 * c->dt, c->M, c->kII, c->tol);
     });
 }
 
-int read_status(ecpic_ctx *c) {
-    // both statuses in one copy (stII = stI + 1, and I, II adjacent in the mirror)
-    HIPCHK(hipMemcpyAsync(&c->h->I, c->stI, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
+// The host's view of both statuses: already written by the Subsystem II commit
+// (mirrored), or copied (stII = stI + 1, and I, II adjacent in the mirror).
+int read_status(ecpic_ctx *c, bool mirrored) {
+    if (!mirrored || !c->hdev)
+        HIPCHK(hipMemcpyAsync(&c->h->I, c->stI, 2 * sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
     return sync(c);
 }
 
@@ -491,18 +504,27 @@ int flags_to_status(int32_t f) {
 }
 
 // Finish Subsystem I (more sweeps / commit) after a status read.
-void enqueue_begin_I(ecpic_ctx *c) {
-    c->kI = 0;
+// Start of a step (do_I and do_II), or of one substep: statuses, the records
+// of a^n (both substeps), of e_x^n (Subsystem I) and of a^(0), and E0
+// (Subsystem II).  In a full step the Subsystem I commit resets the Subsystem
+// II status, gated on its own success.
+void enqueue_begin(ecpic_ctx *c, bool do_I, bool do_II, const DevStatus *gate_src = nullptr) {
+    if (do_I) c->kI = 0;
+    if (do_II) c->kII = 0;
     const bool have_table = c->table_pending;
-    if (c->table_pending) {   // the tables read coefA, which prep_records rewrites
+    if (c->table_pending) {   // the tables read coefA, which the start kernel rewrites
         hipStreamWaitEvent(c->stream, c->ev_table, 0);
         c->table_pending = false;
     }
-    timed(c, "begin_I", [&] {
-        launch_prep_records(c->P, c->stream, c->stI, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
-                            c->coefE[0], c->M);
+    const double r = c->dt / (2.0 * c->dx);
+    const int t = c->trc;
+    timed(c, "begin", [&] {
+        launch_begin_step(c->P, c->stream, do_I ? c->stI : nullptr, gate_src, (do_II && !do_I) ? c->stII : nullptr, c->ay[t],
+                          c->az[t], c->ey[t], c->ez[t], do_I ? c->ex[c->exc] : nullptr, c->dt, c->coefA,
+                          do_I ? c->coefE[0] : nullptr, c->coefAk[0], do_II ? 1 : 0, c->m0row.data(), c->krow.data(),
+                          r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
     });
-    if (c->ws_on && !have_table) {
+    if (do_I && c->ws_on && !have_table) {
         WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
         timed(c, "ws_table", [&] {
             launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc],
@@ -552,7 +574,7 @@ int finish_I(ecpic_ctx *c, bool *recommitted) {
         }
         enqueue_commit_I(c);
         *recommitted = true;
-        int rc = read_status(c);
+        int rc = read_status(c, false);
         if (rc) return rc;
     }
 }
@@ -568,7 +590,7 @@ int finish_II(ecpic_ctx *c, const IIView &v) {
             enqueue_iters_II(c, v, std::min(2, c->kmax - c->kII));
         }
         enqueue_commit_II(c);
-        int rc = read_status(c);
+        int rc = read_status(c, true);
         if (rc) return rc;
     }
 }
@@ -619,12 +641,12 @@ void free_all(ecpic_ctx *c) {
     }
     F(c->cnt); F(c->wpre); F(c->tot); F(c->base); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
-    F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAn); F(c->coefAk[0]); F(c->coefAk[1]);
-    F(c->stI);   // stII lives in the same allocation
+    F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
+    F(c->st_ring);
     F(c->ws_theta); F(c->ws_m); F(c->ws_v); F(c->ws_norm); F(c->ws_table); F(c->ws_feat); F(c->ws_targ);
     F(c->ws_pgrad); F(c->ws_ploss); F(c->ws_loss); F(c->ws_w2b);
     F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
-    if (c->h) hipHostFree(c->h);
+    if (c->h_ring) hipHostFree(c->h_ring);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
     for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
     if (c->aux) { hipStreamSynchronize(c->aux); hipStreamDestroy(c->aux); }
@@ -656,21 +678,24 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 1), c->P + 4));
     rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M);
     const size_t nrec = (size_t)(M + 2);
-    rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAn, nrec * 2 * (c->P + 1));
+    rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefAk[0], nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAk[1], nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefE[0], nrec * c->P); rc |= dalloc(&c->coefE[1], nrec * c->P);
-    rc |= dalloc(&c->stI, 2);
+    rc |= dalloc(&c->st_ring, 2 * STEP_BATCH);
     c->wsD = ws_d(c->P);
     c->wsNP = ws_nparams(c->wsD);
     rc |= dalloc(&c->ws_theta, c->wsNP); rc |= dalloc(&c->ws_m, c->wsNP); rc |= dalloc(&c->ws_v, c->wsNP);
     rc |= dalloc(&c->ws_norm, 2 * (c->wsD + 2) + 2); rc |= dalloc(&c->ws_table, (size_t)M * WS_NT * WS_NP);
     rc |= dalloc(&c->ws_loss, 1); rc |= dalloc(&c->ws_w2b, (size_t)WS_H * (WS_H + 4));
-    if (c->stI) c->stII = c->stI + 1;
+
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
     rc |= dalloc(&c->count, M);
     if (rc) return ECPIC_ENOMEM;
-    if (hipHostMalloc((void **)&c->h, sizeof(*c->h), hipHostMallocDefault) != hipSuccess) return ECPIC_ENOMEM;
+    if (hipHostMalloc((void **)&c->h_ring, sizeof(*c->h_ring) * STEP_BATCH, hipHostMallocMapped) != hipSuccess)
+        return ECPIC_ENOMEM;
+    if (hipHostGetDevicePointer((void **)&c->h_ring_dev, c->h_ring, 0) != hipSuccess) c->h_ring_dev = nullptr;
+    set_slot(c, 0);
     // fields start at zero, items empty
     for (int b = 0; b < 2; ++b) {
         for (double *f : {c->ex[b], c->ey[b], c->ez[b], c->ay[b], c->az[b], c->ek[b], c->eyk[b], c->ezk[b]})
@@ -678,8 +703,7 @@ int alloc_all(ecpic_ctx *c) {
     }
     HIPCHK(hipMemsetAsync(c->count, 0, sizeof(int32_t) * M, c->stream));
     launch_items_from_counts(c->stream, c->count, c->nstart, M, c->chunk, 0, c->items[0]);
-    HIPCHK(hipMemsetAsync(c->stI, 0, sizeof(DevStatus), c->stream));
-    HIPCHK(hipMemsetAsync(c->stII, 0, sizeof(DevStatus), c->stream));
+    HIPCHK(hipMemsetAsync(c->st_ring, 0, sizeof(DevStatus) * 2 * STEP_BATCH, c->stream));
     // closed-form rows and inverse taps
     c->m0row = mass_row(c->P);
     c->m1row = mass_row(c->P - 1);
@@ -763,7 +787,7 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     if (!(g.L > 0.0) || g.degree < 2 || g.degree > MAX_DEG || g.M < g.degree + 3 || g.n_particles < 0 ||
         g.n_particles > (int64_t)0x7fffffff - 1 || !(g.dt > 0.0) || !(g.dt < g.L / g.M) || !(g.picard_tol > 0.0) ||
         g.picard_max_iter < 0 || (g.precision != ECPIC_FP64 && g.precision != ECPIC_FP32_MIXED) ||
-        g.fp32_sweeps < 0 || g.fp32_sweeps > 16 ||
+        g.fp32_sweeps < 0 || g.fp32_sweeps > 16 || g.sweep_guess < 0 ||
         (g.map != ECPIC_MAP_JACOBI && g.map != ECPIC_MAP_SEIDEL) ||
         (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_MLP) || g.weight < 0.0)
         return ECPIC_EINVAL;
@@ -785,6 +809,7 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->kmax = g.picard_max_iter > 0 ? std::min(g.picard_max_iter, MAX_HIST) : 50;
     c->seidel = g.map == ECPIC_MAP_SEIDEL;
     c->k32 = g.precision == ECPIC_FP32_MIXED ? (g.fp32_sweeps > 0 ? g.fp32_sweeps : 2) : 0;
+    c->guessI = c->guessII = g.sweep_guess > 0 ? g.sweep_guess : 4;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
     c->chunk = MAX_CHUNK;
     // Waves per work item: enough items x waves to give every SIMD (1024 on the
@@ -991,11 +1016,10 @@ int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
     if (!c) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    enqueue_begin_I(c);
-    launch_begin(c->stII, c->stI, c->stream);   // keeps Subsystem II idle
+    enqueue_begin(c, true, false);
     enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
     enqueue_commit_I(c);
-    int rc = read_status(c);
+    int rc = read_status(c, false);
     bool again = false;
     if (!rc) rc = finish_I(c, &again);
     if (stats) {
@@ -1017,11 +1041,11 @@ int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
     if (!c) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    enqueue_begin_II(c, false);
+    enqueue_begin(c, false, true);
     IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true};
     enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
     enqueue_commit_II(c);
-    int rc = read_status(c);
+    int rc = read_status(c, true);
     if (!rc) rc = finish_II(c, v);
     if (stats) {
         stats->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
@@ -1034,49 +1058,131 @@ int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
     return ECPIC_OK;
 }
 
+namespace {
+
+// Host bookkeeping of one step, as it stood when the step was enqueued.
+struct StepSnap {
+    int cur, icur, exc, trc, n_items;
+    int64_t ws_base;
+    int ws_phase;
+    bool exact;
+};
+
+StepSnap snap(const ecpic_ctx *c) {
+    return {c->cur, c->icur, c->exc, c->trc, c->n_items_host, c->ws_base, c->ws_phase, c->exact_items};
+}
+
+void restore(ecpic_ctx *c, const StepSnap &q) {
+    c->cur = q.cur; c->icur = q.icur; c->exc = q.exc; c->trc = q.trc;
+    c->n_items_host = q.n_items; c->ws_base = q.ws_base; c->ws_phase = q.ws_phase; c->exact_items = q.exact;
+}
+
+// Buffers swap after a committed step.
+void advance(ecpic_ctx *c) {
+    c->cur ^= 1;
+    c->icur ^= 1;
+    c->exc ^= 1;
+    c->trc ^= 1;
+    advance_records(c);
+}
+
+void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII) {
+    if (sI) { sI->sweeps = sweeps_done_I(c); sI->fp32_sweeps = fp32_sweeps_done_I(c); sI->residual = c->h->I.res; }
+    if (sII) {
+        sII->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
+        sII->fp32_sweeps = 0;
+        sII->residual = c->h->II.res;
+    }
+}
+
+}  // namespace
+
 int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII, int32_t *steps_done) {
     if (!c || nsteps < 0) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
     if (steps_done) *steps_done = 0;
-    for (int s = 0; s < nsteps; ++s) {
-        // Subsystem I, its commit, then Subsystem II on the committed state
-        enqueue_begin_I(c);
-        enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
-        enqueue_commit_I(c);
-        enqueue_next_tables(c);
-        enqueue_begin_II(c, true);
-        IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
-        enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
-        enqueue_commit_II(c);
-        int rc = read_status(c);
-        bool again = false;
-        if (!rc) rc = finish_I(c, &again);
-        if (!rc && again) {   // Subsystem I needed extra sweeps: run II now
-            enqueue_begin_II(c, true);
-            enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
-            enqueue_commit_II(c);
-            rc = read_status(c);
+    int done = 0;
+    while (done < nsteps) {
+        // Enqueue a batch of steps, each gated on the one before having
+        // committed, with the current sweep-count guesses; the host reads all
+        // their statuses once at the end.
+        const int K = std::min(STEP_BATCH, nsteps - done);
+        const int gI = std::min(c->guessI, c->kmax), gII = std::min(c->guessII, c->kmax);
+        StepSnap snaps[STEP_BATCH];
+        c->exact_items = true;
+        for (int j = 0; j < K; ++j) {
+            snaps[j] = snap(c);
+            set_slot(c, j);
+            enqueue_begin(c, true, true, j == 0 ? nullptr : c->st_ring + 2 * (j - 1) + 1);
+            enqueue_sweeps_I(c, gI);
+            enqueue_commit_I(c);   // also resets the Subsystem II status, gated on the commit
+            enqueue_next_tables(c);
+            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], c->exact_items};
+            enqueue_iters_II(c, v, gII);
+            enqueue_commit_II(c);   // writes this step's statuses into the host mirror
+            advance(c);
+            c->exact_items = false;   // the item count of the next step is only known on the device
         }
-        if (!rc) rc = finish_II(c, v);
-        const int nI = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
-        const int nII = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
-        if (sI) { sI[s].sweeps = sweeps_done_I(c); sI[s].fp32_sweeps = fp32_sweeps_done_I(c); sI[s].residual = c->h->I.res; }
-        if (sII) { sII[s].sweeps = nII; sII[s].fp32_sweeps = 0; sII[s].residual = c->h->II.res; }
-        if (rc) {   // nothing swapped: the step is rolled back
+        int rc = sync(c);
+        if (rc) return rc;
+        // The next batch enqueues as many sweeps as the most any step of this
+        // one needed: a sweep past convergence exits at once, a missing one
+        // costs a status round trip.
+        int needI = 1, needII = 1;
+        for (int j = 0; j < K; ++j) {
+            set_slot(c, j);
+            c->kI = gI;
+            c->kII = gII;
+            const DevStatus &I = c->h->I, &II = c->h->II;
+            const bool ok = I.committed && II.committed && !I.flags && !II.flags;
+            if (ok) {
+                step_stats(c, sI ? sI + done + j : nullptr, sII ? sII + done + j : nullptr);
+                needI = std::max(needI, I.kconv + 1);
+                needII = std::max(needII, II.kconv + 1);
+                c->guessI = needI;
+                c->guessII = needII;
+                if (j == K - 1) {
+                    c->n_items_host = I.n_items_next;
+                    c->exact_items = true;
+                }
+                continue;
+            }
+            // Step j needs more than was enqueued (or failed): the steps behind
+            // it were gated off.  Finish it from its own state as a lone step.
             drop_next_tables(c);
-            return rc;
+            restore(c, snaps[j]);
+            c->exact_items = true;
+            if (j > 0) c->n_items_host = c->h_ring[j - 1].I.n_items_next;
+            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
+            bool again = false;
+            rc = finish_I(c, &again);
+            if (!rc && again) {   // Subsystem I needed extra sweeps: run II now
+                c->kII = 0;
+                enqueue_iters_II(c, v, gII);
+                enqueue_commit_II(c);
+                rc = read_status(c, true);
+            }
+            if (!rc) rc = finish_II(c, v);
+            step_stats(c, sI ? sI + done + j : nullptr, sII ? sII + done + j : nullptr);
+            if (rc) {   // nothing swapped: the step is rolled back
+                if (steps_done) *steps_done = done + j;
+                return rc;
+            }
+            c->guessI = std::max(needI, c->h->I.kconv + 1);
+            c->guessII = std::max(needII, c->h->II.kconv + 1);
+            advance(c);
+            c->n_items_host = c->h->I.n_items_next;
+            c->exact_items = true;
+            done += j + 1;
+            if (steps_done) *steps_done = done;
+            goto next_batch;
         }
-        c->guessI = std::max(1, nI);
-        c->guessII = std::max(1, nII);
-        c->cur ^= 1;
-        c->icur ^= 1;
-        c->exc ^= 1;
-        c->trc ^= 1;
-        c->n_items_host = c->h->I.n_items_next;
-        advance_records(c);
-        if (steps_done) *steps_done = s + 1;
+        done += K;
+        if (steps_done) *steps_done = done;
+    next_batch:;
     }
+    set_slot(c, 0);
     return ECPIC_OK;
 }
 

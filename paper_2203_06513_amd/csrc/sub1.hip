@@ -167,15 +167,13 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 // iteration and is never committed; the first FP64 sweep after it reads its
 // float increments (d32in).
 template <int P, bool SEIDEL, typename T>
-__global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
+__device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     __shared__ int wcnt[MAX_WAVES][3];
     DevStatus *st = a.st;
-    const int item = blockIdx.x;
-    if (item >= *a.items.n_items) return;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+        if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
     if (F64 && prev_converged(st, k, a.first64, a.dx, a.tol, threadIdx.x == 0)) return;
     const T *din;
@@ -279,6 +277,14 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
             if (wid == 0) a.cnt[(size_t)item * 3 + lane] = tot;
         }
     }
+}
+
+// One block per work item; the grid may exceed the item count (the count of a
+// step enqueued ahead is only known on the device) and the extra blocks exit.
+template <int P, bool SEIDEL, typename T>
+__global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
+    if ((int)blockIdx.x >= *a.items.n_items) return;
+    sweep_I_item<P, SEIDEL, T>(a, blockIdx.x);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -474,14 +480,29 @@ __device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first
 // right movers, the item list of the new order and e_x^{n+1}.
 template <int P>
 __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
+    extern __shared__ int32_t scan_lds[];   // tot, ncount, nstart when they fit (else global scratch)
     __shared__ int lds[40];
     __shared__ int kcs;
-    if (threadIdx.x == 0) kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, true);
+    if (threadIdx.x == 0) {
+        kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, true);
+        if (a.stII) {   // Subsystem II may run only after this commit
+            init_status(a.stII, nullptr);
+            a.stII->gate = kcs >= 0 ? 1 : 0;
+        }
+    }
     __syncthreads();
     const int kc = kcs;
     if (kc < 0) return;
     const int M = a.M;
     const ItemList &it = a.items;
+    {   // e_x^{n+1}
+        const CommitPick pk = commit_pick(a, kc);
+        for (int idx = threadIdx.x; idx < M + 2 * HALO; idx += blockDim.x) a.ex_next[idx] = pk.enew[idx];
+    }
+    const bool in_lds = a.scan_in_lds != 0;
+    int32_t *tot = in_lds ? scan_lds : a.tot;
+    int32_t *nstart = in_lds ? scan_lds + 3 * M : a.nstart;
+    int32_t *ncount = nstart + (M + 1);
     // totals per old cell and exclusive prefix of each item within its cell
     for (int c = threadIdx.x; c < M; c += blockDim.x) {
         int r0 = 0, r1 = 0, r2 = 0;
@@ -489,22 +510,21 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
             a.base[i * 3 + 0] = r0; a.base[i * 3 + 1] = r1; a.base[i * 3 + 2] = r2;
             r0 += a.cnt[i * 3 + 0]; r1 += a.cnt[i * 3 + 1]; r2 += a.cnt[i * 3 + 2];
         }
-        a.tot[c * 3 + 0] = r0; a.tot[c * 3 + 1] = r1; a.tot[c * 3 + 2] = r2;
+        tot[c * 3 + 0] = r0; tot[c * 3 + 1] = r1; tot[c * 3 + 2] = r2;
     }
     __syncthreads();
     // new counts: right-movers of c-1, stayers of c, left-movers of c+1
-    int32_t *ncount = a.nstart + (M + 1);   // scratch of M ints after nstart
     for (int c = threadIdx.x; c < M; c += blockDim.x)
-        ncount[c] = a.tot[imod(c - 1, M) * 3 + 2] + a.tot[c * 3 + 1] + a.tot[imod(c + 1, M) * 3 + 0];
+        ncount[c] = tot[imod(c - 1, M) * 3 + 2] + tot[c * 3 + 1] + tot[imod(c + 1, M) * 3 + 0];
     __syncthreads();
-    scan_cells(ncount, a.nstart, M, lds);
+    scan_cells(ncount, nstart, M, lds);
     __syncthreads();
     // destination bases of each item's three groups
     for (int c = threadIdx.x; c < M; c += blockDim.x) {
         const int cm = imod(c - 1, M), cp = imod(c + 1, M), cmm = imod(c - 2, M);
-        const int bL = a.nstart[cm] + a.tot[cmm * 3 + 2] + a.tot[cm * 3 + 1];
-        const int bS = a.nstart[c] + a.tot[cm * 3 + 2];
-        const int bR = a.nstart[cp];
+        const int bL = nstart[cm] + tot[cmm * 3 + 2] + tot[cm * 3 + 1];
+        const int bS = nstart[c] + tot[cm * 3 + 2];
+        const int bR = nstart[cp];
         for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
             a.base[i * 3 + 0] += bL;
             a.base[i * 3 + 1] += bS;
@@ -512,11 +532,8 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
         }
     }
     __syncthreads();
-    build_items(ncount, a.nstart, M, a.chunk, a.N, a.items_next, lds);
+    build_items(ncount, nstart, M, a.chunk, a.N, a.items_next, lds);
     __syncthreads();
-    // e_x^{n+1}
-    const CommitPick pk = commit_pick(a, kc);
-    for (int idx = threadIdx.x; idx < M + 2 * HALO; idx += blockDim.x) a.ex_next[idx] = pk.enew[idx];
     if (threadIdx.x == 0) {
         a.st->n_items_next = *a.items_next.n_items;
         a.st->committed = 1;
@@ -553,10 +570,9 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, d
 // sweep, so its movers of each kind are consecutive from the base the scan
 // gave it; ballots rank them within a row.
 template <int P>
-__global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
+__device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
-    const int item = blockIdx.x;
-    if (item >= *a.items.n_items || !commit_enabled(a.st)) return;
+    if (!commit_enabled(a.st)) return;
     const CommitPick pk = commit_pick(a, a.st->kconv);
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
@@ -617,6 +633,14 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
     }
 }
 
+// One block per work item; the grid may exceed the item count (the count of a
+// step enqueued ahead is only known on the device) and the extra blocks exit.
+template <int P>
+__global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
+    if ((int)blockIdx.x >= *a.items.n_items) return;
+    commit_scatter_item<P>(a, blockIdx.x);
+}
+
 __global__ void k_begin(DevStatus *st, const DevStatus *gate) { init_status(st, gate); }
 
 // ---- launchers ------------------------------------------------------------
@@ -654,9 +678,10 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
+    const size_t lds = a.scan_in_lds ? sizeof(int32_t) * (5 * (size_t)a.M + 1) : 0;
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
-        hipLaunchKernelGGL((k_commit_scan<PP>), dim3(1), dim3(1024), 0, s, a);                   \
+        hipLaunchKernelGGL((k_commit_scan<PP>), dim3(1), dim3(1024), lds, s, a);                 \
         hipLaunchKernelGGL((k_commit_scatter<PP>), dim3(grid), dim3(block), 0, s, a);            \
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }

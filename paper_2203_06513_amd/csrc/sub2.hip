@@ -12,6 +12,8 @@
 // A^n and A^(k) as per-cell polynomials (coef.hpp) and accumulates the deposit
 // as moments sum_a c_a t_a^i, turned into the P+1 V0 coefficients once per
 // block.
+#include <cstddef>
+
 #include "coef.hpp"
 
 namespace ecpic {
@@ -46,12 +48,10 @@ __device__ __forceinline__ void sub2_coef(const double *cn, const double *ck, do
 // item, loads the next row while it computes the current one, and writes its
 // own 2 (P+1) partial slots (V0 slot q <-> index c - P + q, y then z).
 template <int P>
-__global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
+__device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
     constexpr int NA = RecA<P>::N;
     DevStatus *st = a.st;
-    const int item = blockIdx.x;
-    if (item >= *a.items.n_items) return;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+        if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
     if (prev_converged2(st, k, a.tol, threadIdx.x == 0)) return;
     const int c = a.items.cell[item];
@@ -115,6 +115,14 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
         flags = wave_or(flags);
         if (lane == 0) atomicOr(&st->flags, flags);
     }
+}
+
+// One block per work item; the grid may exceed the item count (the count of a
+// step enqueued ahead is only known on the device) and the extra blocks exit.
+template <int P>
+__global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
+    if ((int)blockIdx.x >= *a.items.n_items) return;
+    sweep_II_item<P>(a, blockIdx.x);
 }
 
 // Field iterate k+1 of Subsystem II and the A-records of a^(k+1).  Block b
@@ -257,40 +265,53 @@ struct Stencil {
     int half;
 };
 
-// Start of Subsystem II.  Block 0 resets the status (gated on Subsystem I
-// having committed).  Block b, on cells b * FIELD2_OUT .. + FIELD2_OUT - 1,
-// writes the A-records of a^n and of a^(0) = a^n - dt e^n (the iterate for
-// e^(0) = e^n), and the constant part of every iterate,
+// Start of a step (or of one substep).  Block 0 resets the statuses it is
+// given (stI for Subsystem I, gated on gate_src, the Subsystem II status of the
+// step before when it was enqueued ahead; stII for a Subsystem II run on its
+// own; in a full step the Subsystem I commit resets stII).  A gated-off step
+// writes nothing else.  Block b, on cells
+// b * FIELD2_OUT .. + FIELD2_OUT - 1, writes the A-records of a^n (shared by
+// both substeps, Subsystem I leaves a_perp alone), with do_I the E-records of
+// e_x^n, and with do_II the A-records of a^(0) = a^n - dt e^n (the iterate for
+// e^(0) = e^n) and the constant part of every Subsystem II iterate,
 //   E0 = A^-1 [(M0^ - r^2 K^) e^n + (dt/dx^2) K^ a^n],   A = M0^ + r^2 K^,
 // with the stencils applied on a window in LDS and A^-1 as a convolution by
 // four lanes per output.
 template <int P>
-__global__ void __launch_bounds__(256) k_begin_II(DevStatus *st, const DevStatus *gate_src, const double *ayn,
-                                                  const double *azn, const double *eyn, const double *ezn,
-                                                  double dt, double *coefAn, double *coefAk0, Stencil m0,
-                                                  Stencil kk, double r2, double ck, const double *taps, int ntaps,
-                                                  int mlo, int M, double *E0y, double *E0z) {
+__global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevStatus *gate_src, DevStatus *stII,
+                                                    const double *ayn,
+                                                    const double *azn, const double *eyn, const double *ezn,
+                                                    const double *exn, double dt, double *coefA, double *coefE0,
+                                                    double *coefAk0, int do_II, Stencil m0, Stencil kk, double r2,
+                                                    double ck, const double *taps, int ntaps, int mlo, int M,
+                                                    double *E0y, double *E0z) {
     extern __shared__ double R[];   // [2][FIELD2_OUT + ntaps - 1] + taps
-    const bool g = gate_src ? (gate_src->committed && gate_src->flags == 0) : true;
-    if (blockIdx.x == 0 && threadIdx.x == 0) init_status(st, gate_src);
-    if (!g) return;
+    // a step enqueued behind another runs only if that one committed
+    const bool go = gate_src ? (gate_src->committed && gate_src->flags == 0) : true;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (stI) init_status(stI, gate_src);
+        if (stII) init_status(stII, nullptr);
+    }
+    if (!go) return;
     const int j0 = blockIdx.x * FIELD2_OUT;
     const int mhi = mlo + ntaps - 1;
     const int len = FIELD2_OUT + ntaps - 1;
     double *Ry = R, *Rz = R + len, *tp = Rz + len;
-    for (int t = threadIdx.x; t < ntaps; t += blockDim.x) tp[t] = taps[t];
-    for (int idx = threadIdx.x; idx < len; idx += blockDim.x) {
-        const int j = imod(j0 - mhi + idx, M);
-        double sy = 0.0, sz = 0.0;
-        for (int q = -m0.half; q <= m0.half; ++q) {
-            const double cm = m0.v[q + m0.half] - r2 * kk.v[q + kk.half];
-            const double ka = ck * kk.v[q + kk.half];
-            const int jq = imod(j + q, M) + HALO;
-            sy += cm * eyn[jq] + ka * ayn[jq];
-            sz += cm * ezn[jq] + ka * azn[jq];
+    if (do_II) {
+        for (int t = threadIdx.x; t < ntaps; t += blockDim.x) tp[t] = taps[t];
+        for (int idx = threadIdx.x; idx < len; idx += blockDim.x) {
+            const int j = imod(j0 - mhi + idx, M);
+            double sy = 0.0, sz = 0.0;
+            for (int q = -m0.half; q <= m0.half; ++q) {
+                const double cm = m0.v[q + m0.half] - r2 * kk.v[q + kk.half];
+                const double ka = ck * kk.v[q + kk.half];
+                const int jq = imod(j + q, M) + HALO;
+                sy += cm * eyn[jq] + ka * ayn[jq];
+                sz += cm * ezn[jq] + ka * azn[jq];
+            }
+            Ry[idx] = sy;
+            Rz[idx] = sz;
         }
-        Ry[idx] = sy;
-        Rz[idx] = sz;
     }
     {
         const int c = j0 + (int)threadIdx.x;
@@ -306,13 +327,21 @@ __global__ void __launch_bounds__(256) k_begin_II(DevStatus *st, const DevStatus
                     ky += (ayn[j] - dt * eyn[j]) * B.c[m][i];
                     kz += (azn[j] - dt * ezn[j]) * B.c[m][i];
                 }
-                store_record(coefAn, M, c, NA, i, ny);
-                store_record(coefAn, M, c, NA, P + 1 + i, nz);
-                store_record(coefAk0, M, c, NA, i, ky);
-                store_record(coefAk0, M, c, NA, P + 1 + i, kz);
+                store_record(coefA, M, c, NA, i, ny);
+                store_record(coefA, M, c, NA, P + 1 + i, nz);
+                if (do_II) {
+                    store_record(coefAk0, M, c, NA, i, ky);
+                    store_record(coefAk0, M, c, NA, P + 1 + i, kz);
+                }
+            }
+            if (coefE0) {
+                double r[P];
+                make_recE<P>([&](int jj) { return exn[jj + HALO]; }, c, r);
+                for (int i = 0; i < P; ++i) store_record(coefE0, M, c, RecE<P>::N, i, r[i]);
             }
         }
     }
+    if (!do_II) return;
     __syncthreads();
     const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
     const double *Ryq = Ry + quad + ntaps - 1, *Rzq = Rz + quad + ntaps - 1;
@@ -345,28 +374,42 @@ __global__ void __launch_bounds__(256) k_conv(const double *in, double *out, con
 // Commit of Subsystem II: e_perp^{n+1} = e^(kc+1), a^{n+1} = a^n - dt/2 (e^n + e^{n+1}).
 // Every block settles the convergence test on its own (same answer); block 0
 // records the commit.  Running it again is harmless (same writes).
-__global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const double *eyn, const double *ezn,
-                                                   const double *ayn, const double *azn, const double *ey0,
-                                                   const double *ey1, const double *ez0, const double *ez1,
-                                                   double *ey_next, double *ez_next, double *ay_next,
-                                                   double *az_next, double half_dt, int M, int nsweeps,
-                                                   double tol) {
-    if (!st->gate || st->flags) return;
-    int kc = st->kconv;
-    if (kc < 0) {
-        if (!prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0)) return;
-        kc = nsweeps - 1;
+__global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const DevStatus *stI, DevStatus *mirror,
+                                                   const double *eyn, const double *ezn, const double *ayn,
+                                                   const double *azn, const double *ey0, const double *ey1,
+                                                   const double *ez0, const double *ez1, double *ey_next,
+                                                   double *ez_next, double *ay_next, double *az_next, double half_dt,
+                                                   int M, int nsweeps, double tol) {
+    int kc = -1;
+    if (st->gate && !st->flags) {
+        kc = st->kconv;
+        if (kc < 0 && prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0)) kc = nsweeps - 1;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->committed = 1;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
-    const double *eya = ((kc + 1) & 1) ? ey1 : ey0;
-    const double *eza = ((kc + 1) & 1) ? ez1 : ez0;
-    const double ny = eya[j + HALO], nz = eza[j + HALO];
-    store_padded(ey_next, M, j, ny);
-    store_padded(ez_next, M, j, nz);
-    store_padded(ay_next, M, j, ayn[j + HALO] - half_dt * (eyn[j + HALO] + ny));
-    store_padded(az_next, M, j, azn[j + HALO] - half_dt * (ezn[j + HALO] + nz));
+    if (kc >= 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->committed = 1;
+        if (j < M) {
+            const double *eya = ((kc + 1) & 1) ? ey1 : ey0;
+            const double *eza = ((kc + 1) & 1) ? ez1 : ez0;
+            const double ny = eya[j + HALO], nz = eza[j + HALO];
+            store_padded(ey_next, M, j, ny);
+            store_padded(ez_next, M, j, nz);
+            store_padded(ay_next, M, j, ayn[j + HALO] - half_dt * (eyn[j + HALO] + ny));
+            store_padded(az_next, M, j, azn[j + HALO] - half_dt * (ezn[j + HALO] + nz));
+        }
+    }
+    if (mirror && blockIdx.x == 0) {
+        // the host's copy of both statuses (the words before the residual
+        // history), written straight into its pinned mirror
+        __syncthreads();
+        constexpr int W = (int)(offsetof(DevStatus, res_hist) / sizeof(int32_t));
+        const int t = threadIdx.x;
+        if (t < 2 * W) {
+            const int32_t *src = reinterpret_cast<const int32_t *>(t < W ? stI : st);
+            int32_t *dst = reinterpret_cast<int32_t *>(mirror + (t < W ? 0 : 1));
+            dst[t % W] = src[t % W];
+        }
+    }
 }
 
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a) {
@@ -384,19 +427,21 @@ void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
 #undef ECPIC_F2
 }
 
-void launch_begin_II(int P, hipStream_t s, DevStatus *st, const DevStatus *gate_src, const double *ayn,
-                     const double *azn, const double *eyn, const double *ezn, double dt, double *coefAn,
-                     double *coefAk0, const double *m0, const double *kr, double r2, double ck, const double *taps,
-                     int ntaps, int mlo, int M, double *E0y, double *E0z) {
+void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *gate_src, DevStatus *stII,
+                       const double *ayn, const double *azn,
+                       const double *eyn, const double *ezn, const double *exn, double dt, double *coefA,
+                       double *coefE0, double *coefAk0, int do_II, const double *m0, const double *kr, double r2,
+                       double ck, const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z) {
     Stencil a{}, b{};
     a.half = P; b.half = P;
     for (int q = 0; q <= 2 * P; ++q) { a.v[q] = m0[q]; b.v[q] = kr[q]; }
     const int grid = (M + FIELD2_OUT - 1) / FIELD2_OUT;
-    const size_t lds = sizeof(double) * (2 * (FIELD2_OUT + ntaps - 1) + ntaps);
-#define ECPIC_B2(PP)                                                                                        \
-    case PP:                                                                                                \
-        hipLaunchKernelGGL((k_begin_II<PP>), dim3(grid), dim3(256), lds, s, st, gate_src, ayn, azn, eyn, ezn, \
-                           dt, coefAn, coefAk0, a, b, r2, ck, taps, ntaps, mlo, M, E0y, E0z);               \
+    const size_t lds = do_II ? sizeof(double) * (2 * (FIELD2_OUT + ntaps - 1) + ntaps) : 0;
+#define ECPIC_B2(PP)                                                                                          \
+    case PP:                                                                                                  \
+        hipLaunchKernelGGL((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn,  \
+                           ezn, exn, dt, coefA, coefE0, coefAk0, do_II, a, b, r2, ck, taps, ntaps, mlo, M, E0y,   \
+                           E0z);                                                                              \
         break;
     switch (P) { ECPIC_B2(2) ECPIC_B2(3) ECPIC_B2(4) ECPIC_B2(5) }
 #undef ECPIC_B2
@@ -407,12 +452,12 @@ void launch_conv(int grid, hipStream_t s, const double *in, double *out, const d
     hipLaunchKernelGGL(k_conv, dim3(grid), dim3(256), 0, s, in, out, taps, ntaps, mlo, alpha, M);
 }
 
-void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const double *eyn, const double *ezn,
-                      const double *ayn, const double *azn, const double *ey0, const double *ey1,
-                      const double *ez0, const double *ez1, double *ey_next, double *ez_next,
+void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
+                      const double *eyn, const double *ezn, const double *ayn, const double *azn, const double *ey0,
+                      const double *ey1, const double *ez0, const double *ez1, double *ey_next, double *ez_next,
                       double *ay_next, double *az_next, double half_dt, int M, int nsweeps, double tol) {
-    hipLaunchKernelGGL(k_commit_II, dim3(grid), dim3(256), 0, s, st, eyn, ezn, ayn, azn, ey0, ey1, ez0, ez1,
-                       ey_next, ez_next, ay_next, az_next, half_dt, M, nsweeps, tol);
+    hipLaunchKernelGGL(k_commit_II, dim3(grid), dim3(256), 0, s, st, stI, mirror, eyn, ezn, ayn, azn, ey0, ey1, ez0,
+                       ez1, ey_next, ez_next, ay_next, az_next, half_dt, M, nsweeps, tol);
 }
 
 }  // namespace ecpic

@@ -324,3 +324,28 @@ def test_deterministic_and_resumable():
     for k in outs[0]:
         np.testing.assert_array_equal(outs[0][k], outs[1][k])
     assert_state_close(outs[2], outs[0], w.L, tol=1e-12)
+
+
+@pytest.mark.parametrize("guess", [1, 3, 8])
+def test_batched_steps_match_single_steps(guess):
+    """Steps enqueued in batches (gated on the device, the host reading statuses once per
+    batch) give bitwise the state and sweep counts of steps run one call at a time, whatever
+    number of sweeps is enqueued ahead: too few sends a step through the lone-step path
+    mid-batch, too many leaves sweeps that exit at once."""
+    w = workloads.get("langmuir64")
+    arr = workloads.generate(w)
+    n = 37   # crosses two batch boundaries and ends on a partial batch
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        ref = [c.step(1) for _ in range(n)]
+        s_ref = c.state()
+    kI_ref = [r[2][0] for r in ref]
+    kII_ref = [r[3][0] for r in ref]
+    with gpu_ctx(w, map=ec.MAP_SEIDEL, sweep_guess=guess) as c:
+        c.load(arr)
+        rc, done, kI, kII, _ = c.step(n)
+        s = c.state()
+    assert rc == 0 and done == n
+    assert kI.tolist() == kI_ref and kII.tolist() == kII_ref
+    for k in s_ref:
+        np.testing.assert_array_equal(s[k], s_ref[k])
