@@ -77,19 +77,20 @@ __device__ __forceinline__ T horner(const T *c, T t) {
 }
 
 // (A(b) - A(a))/(b - a) for A = sum_{i=0}^{P} c_i t^i, given h_0..h_{P-1} of (a, b).
+// (h_0 = 1 for every pair, so the sums start from the first coefficient.)
 template <int P, typename T>
 __device__ __forceinline__ T divdiff(const T *c, const T (&h)[P]) {
-    T v = (T)0;
+    T v = c[1];
 #pragma unroll
-    for (int i = 1; i <= P; ++i) v = fma(c[i], h[i - 1], v);
+    for (int i = 2; i <= P; ++i) v = fma(c[i], h[i - 1], v);
     return v;
 }
 
 template <int P, typename T>
 __device__ __forceinline__ T pmean(const T *w, const T (&h)[P]) {
-    T v = (T)0;
+    T v = w[0];
 #pragma unroll
-    for (int i = 0; i < P; ++i) v = fma(w[i], h[i], v);
+    for (int i = 1; i < P; ++i) v = fma(w[i], h[i], v);
     return v;
 }
 
@@ -109,14 +110,14 @@ __device__ __forceinline__ double frcp(double x) {
 }
 
 __device__ __forceinline__ double fsqrt(double q) {   // q >= 1
-    // one Newton step on the reciprocal square root (relative error ~1e-15),
-    // then one exact-residual correction of the root itself
-    const double y0 = __builtin_amdgcn_rsq(q);
-    const double e = fma(-q * y0, y0, 1.0);
-    const double h = 0.5 * fma(y0, 0.5 * e, y0);   // ~ 1 / (2 sqrt(q))
-    const double s = 2.0 * h * q;
-    const double d = fma(-s, s, q);
-    return fma(d, h, s);
+    // two Newton steps on the root from the hardware reciprocal square root y
+    // (relative error e): s = q y, then s += (q - s^2) h with h = y / 2 fixed;
+    // the error goes e -> ~e^2 -> ~e^3, below rounding
+    const double y = __builtin_amdgcn_rsq(q);
+    const double h = 0.5 * y;
+    double s = q * y;
+    s = fma(fma(-s, s, q), h, s);
+    return fma(fma(-s, s, q), h, s);
 }
 #endif
 

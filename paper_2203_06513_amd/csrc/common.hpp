@@ -113,6 +113,12 @@ __device__ __forceinline__ void block_max_or(double &m, int &f, double *ldsd, in
     __syncthreads();
 }
 
+// Set flag bit f for the whole wave if cond holds in any active lane (the
+// flags are OR-reduced per wave anyway; the test stays in the scalar unit).
+__device__ __forceinline__ void wave_flag(int &flags, bool cond, int f) {
+    if (__builtin_amdgcn_ballot_w64(cond)) flags |= f;
+}
+
 // Status of a substep about to start; gate_src (the substep it follows) must
 // have committed without a flag, else every kernel of this substep skips.
 __device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate_src) {

@@ -49,17 +49,18 @@ struct Lane {
 // Gather at the step start, gamma there, the explicit first increment if asked,
 // and the end point of the current increment.  xi0 - c is exact in FP64; the
 // single precision sweeps round it once.
-template <int P, typename T>
-__device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, double xi0, int c, bool explicit_start,
-                                             T dt_dx, int &flags) {
+template <int P, typename T, bool EXPL>
+__device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, double xi0, int c, T dt_dx,
+                                             int &flags) {
     const double t0 = xi0 - (double)c;
-    L.t0 = (T)t0;
-    if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; L.t0 = (T)0.5; }
+    wave_flag(flags, !(t0 >= 0.0), FLAG_ORDER);
+    wave_flag(flags, !(t0 < 1.0), FLAG_ORDER);
+    L.t0 = (T)fmin(fmax(t0, 0.0), 1.0);
     L.A0y = horner<P + 1>(o.ay, L.t0);
     L.A0z = horner<P + 1>(o.az, L.t0);
     L.q0 = fma(L.p0, L.p0, (T)1);
     L.g00 = fsqrt(L.q0 + L.A0y * L.A0y + L.A0z * L.A0z);
-    if (explicit_start) L.d = dt_dx * L.p0 * frcp(L.g00);
+    if constexpr (EXPL) L.d = dt_dx * L.p0 * frcp(L.g00);
     if constexpr (sizeof(T) == 8) end_point(xi0, L.d, c, L.t1, L.s, flags);
     else end_point(L.t0, L.d, L.t1, L.s, flags);
 }
@@ -76,10 +77,9 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
     T DAy = divdiff<P>(o.ay, h), DAz = divdiff<P>(o.az, h);
     T A1y, A1z;
     if (anycross) {
-        // record of the cell holding t1, indexed arithmetically (t1 in (-1, 2))
-        const int r = (int)floor(L.t1) + 1;
-        const LdsRec<P, T> &nb = rec[r];
-        const T tl = L.t1 - (T)(r - 1);
+        // record of the cell holding t1 (s = floor(t1) in {-1, 0, 1})
+        const LdsRec<P, T> &nb = rec[L.s + 1];
+        const T tl = L.t1 - (T)L.s;
         A1y = horner<P + 1>(nb.ay, tl);
         A1z = horner<P + 1>(nb.az, tl);
         if (L.s != 0) {
@@ -103,34 +103,37 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
     const T g11 = fsqrt(fma(p1, p1, one) + qa1);
     dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
     const T big = sizeof(T) == 8 ? (T)1.0e300 : (T)1.0e30f;
-    if (!(fabs(dn) < big) || !(fabs(p1) < big)) flags |= FLAG_NONFINITE;
+    wave_flag(flags, !(fabs(dn) < big), FLAG_NONFINITE);
+    wave_flag(flags, !(fabs(p1) < big), FLAG_NONFINITE);
 }
 
-// The records of cells c-1, c, c+1 into LDS (one value per thread; the caller
-// synchronises before reading them) and those of cell c into registers.
+// The records of cells c-1, c, c+1 into LDS, one value per thread; the caller
+// synchronises before reading them.
 template <int P, typename T>
-__device__ __forceinline__ void stage_records(LdsRec<P, T> *rec, Own<P, T> &o1, const double *coefA,
-                                              const double *coefE, int c) {
+__device__ __forceinline__ void stage_records(LdsRec<P, T> *rec, const double *coefA, const double *coefE, int c) {
     constexpr int NA = RecA<P>::N, NE = RecE<P>::N;
-    {
-        const double *ra = coefA + (size_t)(rec_index(c) - 1) * NA;
-        const double *re = coefE + (size_t)(rec_index(c) - 1) * NE;
-        const int t = threadIdx.x;
-        if (t < 3 * NA) {
-            const int r = t / NA, i = t % NA;
-            if (i <= P) rec[r].ay[i] = (T)ra[t];
-            else rec[r].az[i - P - 1] = (T)ra[t];
-        } else if (t < 3 * NA + 3 * NE) {
-            const int u = t - 3 * NA, r = u / NE, i = u % NE;
-            rec[r].eb[i] = (T)re[u];
-        }
+    const double *ra = coefA + (size_t)(rec_index(c) - 1) * NA;
+    const double *re = coefE + (size_t)(rec_index(c) - 1) * NE;
+    const int t = threadIdx.x;
+    if (t < 3 * NA) {
+        const int r = t / NA, i = t % NA;
+        if (i <= P) rec[r].ay[i] = (T)ra[t];
+        else rec[r].az[i - P - 1] = (T)ra[t];
+    } else if (t < 3 * NA + 3 * NE) {
+        const int u = t - 3 * NA, r = u / NE, i = u % NE;
+        rec[r].eb[i] = (T)re[u];
     }
-    const double *ra = coefA + (size_t)rec_index(c) * NA;
-    const double *re = coefE + (size_t)rec_index(c) * NE;
+}
+
+// The block's own cell (record 1) from LDS into registers.  Reading them from
+// LDS rather than global memory keeps the particle loop's memory waits
+// counting only its own row loads and stores.
+template <int P, typename T>
+__device__ __forceinline__ void own_from_lds(const LdsRec<P, T> *rec, Own<P, T> &o1) {
 #pragma unroll
-    for (int i = 0; i <= P; ++i) { o1.ay[i] = (T)ra[i]; o1.az[i] = (T)ra[P + 1 + i]; }
+    for (int i = 0; i <= P; ++i) { o1.ay[i] = rec[1].ay[i]; o1.az[i] = rec[1].az[i]; }
 #pragma unroll
-    for (int i = 0; i < P; ++i) o1.eb[i] = (T)re[i];
+    for (int i = 0; i < P; ++i) o1.eb[i] = rec[1].eb[i];
 }
 
 // Has sweep k-1 met the tolerance?  Records kconv if so.  Only FP64 sweeps
@@ -166,7 +169,11 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 // update and the convergence test stay in FP64.  A float sweep never ends the
 // iteration and is never committed; the first FP64 sweep after it reads its
 // float increments (d32in).
-template <int P, bool SEIDEL, typename T>
+// Where d^(k) comes from: computed explicitly (first sweep), read back from the
+// previous FP64 sweep, or read from the last float sweep of the precision form.
+enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2 };
+
+template <int P, bool SEIDEL, typename T, int START>
 __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
@@ -185,9 +192,10 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
         din = (k & 1) ? a.f1 : a.f0;
         dout = (k & 1) ? a.f0 : a.f1;
     }
-    const float *d32in = F64 ? a.d32in : nullptr;   // FP64 sweep right after the float ones
+    const float *d32in = a.d32in;   // FP64 sweep right after the float ones (START_FLOAT)
     const double *coefE = (k & 1) ? a.coefE1 : a.coefE0;
-    const bool explicit_start = (k == 0) && a.explicit_start;
+    constexpr bool explicit_start = START == START_EXPLICIT;
+    constexpr bool from_float = F64 && START == START_FLOAT;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
@@ -199,43 +207,58 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     int ia = wb + lane;
     double nx = 0.0, np = 0.0;
     T nd = (T)0;
+    float nf = 0.0f;   // the float increment (from_float; converted at use)
     if (wb < we) {
         const int il = min(ia, we - 1);
         nx = a.xi[il];
         np = a.p[il];
-        nd = explicit_start ? (T)0 : (d32in ? (T)d32in[il] : din[il]);
+        if constexpr (from_float) nf = d32in[il];
+        else if constexpr (!explicit_start) nd = din[il];
     }
-    Own<P, T> o1;
-    stage_records<P, T>(rec, o1, a.coefA, coefE, c);
+    stage_records<P, T>(rec, a.coefA, coefE, c);
     __syncthreads();
+    Own<P, T> o1;
+    own_from_lds<P, T>(rec, o1);
+    // Every load issued so far (the first row, the records) completes here, so
+    // the loop's memory waits only ever concern the loop's own loads and stores.
+    __builtin_amdgcn_s_waitcnt(0);
     MO mo{};
     const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx;
     T rmax = (T)0;
     int flags = 0;
     int nleft = 0, nstay = 0, nright = 0;
+    // A row's new increments are stored at the start of the next row, just
+    // before its prefetch: the wait for those loads then also covers a store
+    // issued a whole row earlier, instead of one issued moments before.
+    T pend = (T)0;
+    int pend_i = -1;
     for (int row = wb; row < we; row += WAVE, ia += WAVE) {
         Lane<T> La;
         const double xi0 = nx;
         La.p0 = (T)np;
-        La.d = nd;
+        La.d = from_float ? (T)nf : nd;
         const bool valid = ia < we;
-        if (row + WAVE < we) {   // prefetch the next row
+        const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
+        if (pend_i >= 0) dout[pend_i] = pend;
+        {   // prefetch the next row (unconditionally: the last row reloads its last particle)
             const int il = min(ia + WAVE, we - 1);
             nx = a.xi[il];
             np = a.p[il];
-            nd = explicit_start ? (T)0 : (d32in ? (T)d32in[il] : din[il]);
+            if constexpr (from_float) nf = d32in[il];
+            else if constexpr (!explicit_start) nd = din[il];
         }
-        stage_gather<P, T>(o1, La, xi0, c, explicit_start, dt_dx, flags);
+        stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
         const bool cross1 = __ballot(La.s != 0) != 0;
         T pa, dna;
         stage_push<P, T>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
         if (valid) {
             // keep d^(k) in FP64 where a Jacobi commit may take it
             if constexpr (F64)
-                if (!SEIDEL && (explicit_start || d32in)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
-            dout[ia] = dna;
+                if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
             rmax = fmax(rmax, fabs(dna - La.d));
         }
+        pend = dna;
+        pend_i = valid ? ia : -1;
         const T w = valid ? (T)1 : (T)0;
         int sc;   // cell change of the increment a commit after this sweep would take
         if (SEIDEL) {
@@ -248,11 +271,12 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
             stage_deposit<P, T>(mo, cross1, La.t0, La.t1, La.s, w);
         }
         if constexpr (F64) {
-            nleft += __popcll(__ballot(valid && sc < 0));
-            nright += __popcll(__ballot(valid && sc > 0));
-            nstay += __popcll(__ballot(valid && sc == 0));
+            nleft += __popcll(__builtin_amdgcn_ballot_w64(sc < 0) & vmask);
+            nright += __popcll(__builtin_amdgcn_ballot_w64(sc > 0) & vmask);
+            nstay += __popcll(__builtin_amdgcn_ballot_w64(sc == 0) & vmask);
         }
     }
+    if (pend_i >= 0) dout[pend_i] = pend;
     Moments<P> md;
     to_double<P>(mo, md);
     const double slot = moments_to_slots<P>(md);
@@ -284,7 +308,17 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
 template <int P, bool SEIDEL, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     if ((int)blockIdx.x >= *a.items.n_items) return;
-    sweep_I_item<P, SEIDEL, T>(a, blockIdx.x);
+    if (a.k == 0 && a.explicit_start) {
+        sweep_I_item<P, SEIDEL, T, START_EXPLICIT>(a, blockIdx.x);
+        return;
+    }
+    if constexpr (sizeof(T) == 8) {
+        if (a.d32in) {
+            sweep_I_item<P, SEIDEL, T, START_FLOAT>(a, blockIdx.x);
+            return;
+        }
+    }
+    sweep_I_item<P, SEIDEL, T, START_READ>(a, blockIdx.x);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -569,7 +603,7 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, d
 // momentum re-evaluated.  Each wave handles the same run of rows as in the
 // sweep, so its movers of each kind are consecutive from the base the scan
 // gave it; ballots rank them within a row.
-template <int P>
+template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
     if (!commit_enabled(a.st)) return;
@@ -581,27 +615,43 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
     const int nw = blockDim.x / WAVE;
     int wb, we;
     wave_range(beg, end, wid, nw, wb, we);
-    Own<P, double> o1;
-    stage_records<P, double>(rec, o1, a.coefA, pk.coefE, c);
+    stage_records<P, double>(rec, a.coefA, pk.coefE, c);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     const int32_t *bs = a.base + (size_t)item * 3;
     const int32_t *ws = a.wpre + ((size_t)item * nw + wid) * 3;
     int run0 = bs[0] + ws[0], run1 = bs[1] + ws[1], run2 = bs[2] + ws[2];
     int flags = 0;
     __syncthreads();
+    Own<P, double> o1;
+    own_from_lds<P, double>(rec, o1);
+    // the next row's loads are issued before the current row is computed
+    double nx = 0.0, np = 0.0, nd = 0.0;
+    int32_t nid = 0;
+    if (wb < we) {
+        const int il = min(wb + lane, we - 1);
+        nx = a.cur.xi[il];
+        np = a.cur.p[il];
+        nd = pk.d[il];
+        nid = a.cur.id[il];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
     for (int r0 = wb; r0 < we; r0 += WAVE) {
         const int i = r0 + lane;
         const bool valid = i < we;
-        const int il = valid ? i : we - 1;
-        const double xi0 = a.cur.xi[il];
-        const double p0 = a.cur.p[il];
-        const double d = pk.d[il];
-        const int32_t pid = a.cur.id[il];
+        const double xi0 = nx, p0 = np, d = nd;
+        const int32_t pid = nid;
+        {
+            const int il = min(i + WAVE, we - 1);
+            nx = a.cur.xi[il];
+            np = a.cur.p[il];
+            nd = pk.d[il];
+            nid = a.cur.id[il];
+        }
         // the committed momentum: the map evaluated at the committed increment
         Lane<double> La;
         La.p0 = p0;
         La.d = d;
-        stage_gather<P, double>(o1, La, xi0, c, false, a.dt_dx, flags);
+        stage_gather<P, double, false>(o1, La, xi0, c, a.dt_dx, flags);
         double p1, dn;
         stage_push<P, double>(o1, rec, __ballot(La.s != 0) != 0, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags);
         const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
@@ -611,8 +661,8 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             xin += (double)M;
             if (xin >= (double)M) xin = __longlong_as_double(__double_as_longlong((double)M) - 1);
         }
-        if (valid && a.rec.stride > 0 && pid % a.rec.stride == a.rec.phase)
-            record_pair<P>(a, o1, c, pid, xi0, p0, d, p1);
+        if constexpr (RECORD)
+            if (valid && pid % a.rec.stride == a.rec.phase) record_pair<P>(a, o1, c, pid, xi0, p0, d, p1);
         const unsigned long long b0 = __ballot(t == 0), b1 = __ballot(t == 1), b2 = __ballot(t == 2);
         if (valid) {
             int dest;
@@ -635,10 +685,12 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
 
 // One block per work item; the grid may exceed the item count (the count of a
 // step enqueued ahead is only known on the device) and the extra blocks exit.
-template <int P>
+// RECORD: the step also writes training pairs of the learned warm start (a
+// kernel of its own, so the plain one keeps its registers).
+template <int P, bool RECORD>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
     if ((int)blockIdx.x >= *a.items.n_items) return;
-    commit_scatter_item<P>(a, blockIdx.x);
+    commit_scatter_item<P, RECORD>(a, blockIdx.x);
 }
 
 __global__ void k_begin(DevStatus *st, const DevStatus *gate) { init_status(st, gate); }
@@ -682,7 +734,10 @@ void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArg
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
         hipLaunchKernelGGL((k_commit_scan<PP>), dim3(1), dim3(1024), lds, s, a);                 \
-        hipLaunchKernelGGL((k_commit_scatter<PP>), dim3(grid), dim3(block), 0, s, a);            \
+        if (a.rec.stride > 0)                                                                    \
+            hipLaunchKernelGGL((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
+        else                                                                                     \
+            hipLaunchKernelGGL((k_commit_scatter<PP, false>), dim3(grid), dim3(block), 0, s, a); \
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C

@@ -44,9 +44,13 @@ __device__ __forceinline__ void sub2_coef(const double *cn, const double *ck, do
     cz = (Akz + Anz) * inv;
 }
 
+constexpr int SUB2_BATCH = 4;
+
 // The particle pass.  Each wave takes every nw-th row of 64 particles of the
-// item, loads the next row while it computes the current one, and writes its
-// own 2 (P+1) partial slots (V0 slot q <-> index c - P + q, y then z).
+// item and keeps the loads of its next two rows in flight while it computes
+// the current one (a row here is short work, shorter than a memory round
+// trip); it writes its own 2 (P+1) partial slots (V0 slot q <-> index
+// c - P + q, y then z).
 template <int P>
 __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
     constexpr int NA = RecA<P>::N;
@@ -58,12 +62,18 @@ __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
-    int ia = beg + wid * WAVE + lane;
-    double nx, np;
-    {
-        const int il = min(ia, end - 1);
-        nx = a.xi[il];
-        np = a.p[il];
+    const int stride = nw * WAVE;
+    const int last = end - 1;   // items are never empty; loads past the run re-read it
+    const int first = beg + wid * WAVE;
+    // rows are taken in batches of SUB2_BATCH: the loads of the next batch are
+    // issued before the current one is computed, so every memory round trip
+    // has a whole batch of arithmetic to hide behind
+    double xn[SUB2_BATCH], pn[SUB2_BATCH];
+#pragma unroll
+    for (int b = 0; b < SUB2_BATCH; ++b) {
+        const int il = min(first + b * stride + lane, last);
+        xn[b] = a.xi[il];
+        pn[b] = a.p[il];
     }
     const double *rn = a.coefAn + (size_t)rec_index(c) * NA;
     const double *rk = ((k & 1) ? a.coefAk1 : a.coefAk0) + (size_t)rec_index(c) * NA;
@@ -74,28 +84,42 @@ __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
 #pragma unroll
     for (int i = 0; i <= P; ++i) { my[i] = 0.0; mz[i] = 0.0; }
     int flags = 0;
-    const int stride = nw * WAVE;
-    for (int row = beg + wid * WAVE; row < end; row += stride, ia += stride) {
-        const double x0 = nx, p0 = np;
-        const bool valid = ia < end;
-        if (row + stride < end) {   // prefetch the next row
-            const int il = min(ia + stride, end - 1);
-            nx = a.xi[il];
-            np = a.p[il];
-        }
-        double t = x0 - (double)c;
-        if (!(t >= 0.0 && t < 1.0)) { flags |= FLAG_ORDER; t = 0.5; }
-        double cy, cz;
-        sub2_coef<P>(cn, ck, t, p0, cy, cz);
-        const double wv = valid ? 1.0 : 0.0;
-        cy *= wv;
-        cz *= wv;
-        double tp = 1.0;
+    // everything loaded so far completes here, so the loop's waits only
+    // concern its own loads
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int row = first; row < end; row += SUB2_BATCH * stride) {
+        double xc[SUB2_BATCH], pc[SUB2_BATCH];
 #pragma unroll
-        for (int j = 0; j <= P; ++j) {
-            my[j] = fma(cy, tp, my[j]);
-            mz[j] = fma(cz, tp, mz[j]);
-            tp *= t;
+        for (int b = 0; b < SUB2_BATCH; ++b) {
+            xc[b] = xn[b];
+            pc[b] = pn[b];
+        }
+#pragma unroll
+        for (int b = 0; b < SUB2_BATCH; ++b) {
+            const int il = min(row + (SUB2_BATCH + b) * stride + lane, last);
+            xn[b] = a.xi[il];
+            pn[b] = a.p[il];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the arithmetic
+#pragma unroll
+        for (int b = 0; b < SUB2_BATCH; ++b) {
+            const bool valid = row + b * stride + lane < end;
+            double t = xc[b] - (double)c;
+            wave_flag(flags, !(t >= 0.0), FLAG_ORDER);
+            wave_flag(flags, !(t < 1.0), FLAG_ORDER);
+            t = fmin(fmax(t, 0.0), 1.0);
+            double cy, cz;
+            sub2_coef<P>(cn, ck, t, pc[b], cy, cz);
+            const double wv = valid ? 1.0 : 0.0;
+            cy *= wv;
+            cz *= wv;
+            double tp = 1.0;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) {
+                my[j] = fma(cy, tp, my[j]);
+                mz[j] = fma(cz, tp, mz[j]);
+                tp *= t;
+            }
         }
     }
     // wave sums of the moments, then lane q < 2 (P+1) forms slot q

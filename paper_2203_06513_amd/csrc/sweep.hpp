@@ -14,16 +14,15 @@ struct Moments {
 };
 
 // End point of a step: xi0 in [c, c+1), t1 = (xi0 + d) - c is exact in floating
-// point, so the committed position and the deposited segment agree.
+// point, so the committed position and the deposited segment agree.  A step of
+// a cell or more (or NaN) is flagged and its end point clamped into (-1, 2),
+// which leaves every valid one unchanged and keeps the neighbour index in range.
 __device__ __forceinline__ void end_point(double xi0, double d, int c, double &t1, int &s, int &flags) {
     t1 = (xi0 + d) - (double)c;
-    if (!(t1 > -1.0 && t1 < 2.0)) {   // |d| >= 1 cell, or NaN
-        flags |= FLAG_CFL;
-        t1 = t1 >= 2.0 ? 1.5 : (t1 <= -1.0 ? -0.5 : 0.5);
-    }
-    s = t1 >= 1.0 ? 1 : (t1 < 0.0 ? -1 : 0);
+    wave_flag(flags, !(fabs(t1 - 0.5) < 1.5), FLAG_CFL);
+    t1 = fmin(fmax(t1, -0.99999999999999989), 1.9999999999999998);
+    s = (int)floor(t1);
 }
-
 
 // Wave sum of the moments and conversion to the P+2 V1 slots of the wave's
 // particles (slot q <-> V1 index c - P + q); lane q < P+2 returns slot q.
@@ -68,11 +67,9 @@ __device__ __forceinline__ void wave_range(int beg, int end, int wid, int nw, in
 // Cell-local end point and cell change of a step (single precision sweeps).
 __device__ __forceinline__ void end_point(float t0, float d, float &t1, int &s, int &flags) {
     t1 = t0 + d;
-    if (!(t1 > -1.0f && t1 < 2.0f)) {
-        flags |= FLAG_CFL;
-        t1 = t1 >= 2.0f ? 1.5f : (t1 <= -1.0f ? -0.5f : 0.5f);
-    }
-    s = t1 >= 1.0f ? 1 : (t1 < 0.0f ? -1 : 0);
+    wave_flag(flags, !(fabsf(t1 - 0.5f) < 1.5f), FLAG_CFL);
+    t1 = fminf(fmaxf(t1, -0.99999994f), 1.9999999f);
+    s = (int)floorf(t1);
 }
 
 // Single precision moments with Knuth's TwoSum compensation: every product and
