@@ -124,7 +124,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="pump2048")
     ap.add_argument("--fp32-sweeps", type=int, default=1)
-    ap.add_argument("--record-steps", type=int, default=20)
+    ap.add_argument("--record-steps", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -160,9 +160,12 @@ def main():
     lw = ec.Context.from_workload(w, map=ec.MAP_SEIDEL, precision=ec.FP32_MIXED, fp32_sweeps=args.fp32_sweeps)
     lw.load(arr)
     stride = max(1, N // 100_000)
-    lw.ws_record(stride, 2_100_000)
+    per_step = (N + stride - 1) // stride
+    capacity = args.record_steps * per_step
+    lw.ws_record(stride, capacity)
     t0 = time.perf_counter()
     lw.step(args.record_steps)
+    n_pairs = lw.ws_records()
     lw.ws_record(0)
     t1 = time.perf_counter()
     loss = lw.ws_train(steps=args.train_steps, batch=1024, lr=2e-3, seed=5)
@@ -204,7 +207,7 @@ def main():
                    "mean_sweeps_I": float(np.mean(rl["kI"])), "mean_fp32_sweeps_I": float(np.mean(rl["k32"])),
                    "predictor_passes_per_step": 1, "mean_iters_II": float(np.mean(rl["kII"])),
                    "rel_energy_drift": rl["drift"], "gauss_change_linf": rl["gauss"],
-                   "training": {"pairs": int(min(args.record_steps * ((N + stride - 1) // stride), 2_100_000)),
+                   "training": {"pairs": int(n_pairs),
                                 "record_steps": args.record_steps, "record_s": t1 - t0,
                                 "train_steps": args.train_steps, "train_s": t2 - t1, "final_loss": loss},
                    "plain_fp64": {"value": value_plain, "ms_per_step": 1e3 * rp["elapsed"] / args.steps,

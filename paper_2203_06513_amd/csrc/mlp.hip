@@ -352,13 +352,20 @@ __global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const uns
 // the current of that increment deposited like a sweep's, so that the field
 // kernel after it makes e^(1) consistent with delta^(1).  The Picard sweeps
 // start from both.
+constexpr int PRED_BATCH = 4;
+
 template <int P>
 __device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
     __shared__ float tab[WS_NT * WS_NP];
     DevStatus *st = a.st;
-        if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    // item count, status words and item description in one memory round trip
+    const int n_items = *a.items.n_items;
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    asm volatile("" ::"s"(n_items), "s"(sgate), "s"(sflags), "s"(skconv), "s"(c), "s"(beg), "s"(end));
+    if (item >= n_items) return;
+    if (!sgate | sflags | (skconv >= 0)) return;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
     int wb, we;
@@ -371,34 +378,62 @@ __device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
     const float plo = a.ws.prange[0], phi = a.ws.prange[1];
     const float pscale = (float)(WS_NP - 1) / (phi - plo);
     const double dt2_dx = a.dt * a.dt * a.inv_dx;
+    // rows in batches of PRED_BATCH, the next batch's loads issued before the
+    // current one is computed (a row is short work next to a memory round trip)
+    constexpr int B = PRED_BATCH;
+    double xn[B], pn[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int il = min(wb + b * WAVE + lane, we - 1);
+        xn[b] = wb < we ? a.xi[il] : 0.0;
+        pn[b] = wb < we ? a.p[il] : 0.0;
+    }
     __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
     Moments<P> mo{};
     int flags = 0;
-    for (int row = wb; row < we; row += WAVE) {
-        const int ia = row + lane;
-        const bool valid = ia < we;
-        const int il = valid ? ia : we - 1;
-        const double xi0 = a.xi[il], p0 = a.p[il];
-        double t0 = xi0 - (double)c;
-        if (!(t0 >= 0.0 && t0 < 1.0)) { flags |= FLAG_ORDER; t0 = 0.5; }
-        const double A0y = horner<P + 1>(cay, t0), A0z = horner<P + 1>(caz, t0);
-        const double g00 = fsqrt(fma(p0, p0, 1.0) + A0y * A0y + A0z * A0z);
-        const float ft = (float)t0 * (float)(WS_NT - 1);
-        const int it = min((int)ft, WS_NT - 2);
-        const float wt = ft - (float)it;
-        const float fp = fminf(fmaxf(((float)p0 - plo) * pscale, 0.0f), (float)(WS_NP - 1));
-        const int ip = min((int)fp, WS_NP - 2);
-        const float wp = fp - (float)ip;
-        const float *q = tab + it * WS_NP + ip;
-        const float y = (1.0f - wt) * ((1.0f - wp) * q[0] + wp * q[1]) + wt * ((1.0f - wp) * q[WS_NP] + wp * q[WS_NP + 1]);
-        const double d = a.dt_dx * p0 * frcp(g00) + dt2_dx * (double)y;
-        double t1;
-        int s;
-        end_point(xi0, d, c, t1, s, flags);
-        stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
-        if (valid) {
-            a.d1[ia] = d;
-            if (a.f1) a.f1[ia] = (float)d;
+    for (int row = wb; row < we; row += B * WAVE) {
+        double xc[B], pc[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            xc[b] = xn[b];
+            pc[b] = pn[b];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int il = min(row + (B + b) * WAVE + lane, we - 1);
+            xn[b] = a.xi[il];
+            pn[b] = a.p[il];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the arithmetic
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int ia = row + b * WAVE + lane;
+            const bool valid = ia < we;
+            const double xi0 = xc[b], p0 = pc[b];
+            double t0 = xi0 - (double)c;
+            wave_flag(flags, !(t0 >= 0.0), FLAG_ORDER);
+            wave_flag(flags, !(t0 < 1.0), FLAG_ORDER);
+            t0 = fmin(fmax(t0, 0.0), 1.0);
+            const double A0y = horner<P + 1>(cay, t0), A0z = horner<P + 1>(caz, t0);
+            const double g00 = fsqrt(fma(p0, p0, 1.0) + A0y * A0y + A0z * A0z);
+            const float ft = (float)t0 * (float)(WS_NT - 1);
+            const int it = min((int)ft, WS_NT - 2);
+            const float wt = ft - (float)it;
+            const float fp = fminf(fmaxf(((float)p0 - plo) * pscale, 0.0f), (float)(WS_NP - 1));
+            const int ip = min((int)fp, WS_NP - 2);
+            const float wp = fp - (float)ip;
+            const float *q = tab + it * WS_NP + ip;
+            const float y = (1.0f - wt) * ((1.0f - wp) * q[0] + wp * q[1]) + wt * ((1.0f - wp) * q[WS_NP] + wp * q[WS_NP + 1]);
+            const double d = a.dt_dx * p0 * frcp(g00) + dt2_dx * (double)y;
+            double t1;
+            int s;
+            end_point(xi0, d, c, t1, s, flags);
+            stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
+            if (valid) {
+                a.d1[ia] = d;
+                if (a.f1) a.f1[ia] = (float)d;
+            }
         }
     }
     const double slot = moments_to_slots<P>(mo);
@@ -414,7 +449,6 @@ __device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 template <int P>
 __global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
-    if ((int)blockIdx.x >= *a.items.n_items) return;
     ws_predict_item<P>(a, blockIdx.x);
 }
 

@@ -137,17 +137,23 @@ __device__ __forceinline__ void own_from_lds(const LdsRec<P, T> *rec, Own<P, T> 
 }
 
 // Has sweep k-1 met the tolerance?  Records kconv if so.  Only FP64 sweeps
-// (index >= first64) can end the iteration.
+// (index >= first64) can end the iteration.  rxb, reb: the residual slots of
+// sweep k-1, loaded by the caller.
 __device__ __forceinline__ bool prev_converged(DevStatus *st, int k, int first64, double dx, double tol,
-                                               bool writer) {
+                                               bool writer, unsigned long long rxb, unsigned long long reb) {
     if (k <= first64) return false;
-    const double r = fmax(dbits(st->rx_bits[(k - 1) & 1]) * dx, dbits(st->re_bits[(k - 1) & 1]));
+    const double r = fmax(dbits(rxb) * dx, dbits(reb));
     if (writer && k - 1 < MAX_HIST) st->res_hist[k - 1] = r;
     if (r <= tol) {
         if (writer) { st->kconv = k - 1; st->res = r; }
         return true;
     }
     return false;
+}
+
+__device__ __forceinline__ bool prev_converged(DevStatus *st, int k, int first64, double dx, double tol,
+                                               bool writer) {
+    return prev_converged(st, k, first64, dx, tol, writer, st->rx_bits[(k - 1) & 1], st->re_bits[(k - 1) & 1]);
 }
 
 template <int P>
@@ -180,9 +186,19 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     __shared__ int wcnt[MAX_WAVES][3];
     DevStatus *st = a.st;
-        if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
-    if (F64 && prev_converged(st, k, a.first64, a.dx, a.tol, threadIdx.x == 0)) return;
+    // the item count, the status words and the item's description are loaded
+    // together, so the start costs one memory round trip instead of three
+    const int n_items = *a.items.n_items;
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const unsigned long long rxb = st->rx_bits[(k - 1) & 1], reb = st->re_bits[(k - 1) & 1];
+    const int c = a.items.cell[item];
+    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    asm volatile("" ::"s"(n_items), "s"(sgate), "s"(sflags), "s"(skconv), "s"(rxb), "s"(reb), "s"(c), "s"(beg),
+                 "s"(end));
+    if (item >= n_items) return;
+    if (!sgate | sflags | (skconv >= 0)) return;
+    if (F64 && prev_converged(st, k, a.first64, a.dx, a.tol, threadIdx.x == 0, rxb, reb)) return;
     const T *din;
     T *dout;
     if constexpr (F64) {
@@ -196,8 +212,6 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     const double *coefE = (k & 1) ? a.coefE1 : a.coefE0;
     constexpr bool explicit_start = START == START_EXPLICIT;
     constexpr bool from_float = F64 && START == START_FLOAT;
-    const int c = a.items.cell[item];
-    const int beg = a.items.begin[item], end = a.items.begin[item + 1];
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
     int wb, we;
@@ -307,7 +321,6 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 template <int P, bool SEIDEL, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
-    if ((int)blockIdx.x >= *a.items.n_items) return;
     if (a.k == 0 && a.explicit_start) {
         sweep_I_item<P, SEIDEL, T, START_EXPLICIT>(a, blockIdx.x);
         return;
@@ -354,7 +367,8 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     constexpr int NS = P + 2;
     constexpr int TILE = FIELD_OUT - (P - 1);
     DevStatus *st = a.st;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    // the status is tested once the loads that do not depend on it are issued
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
     const int k = a.k;
     const int M = a.M;
     const int j0 = blockIdx.x * TILE - (P - 1);   // first cell computed
@@ -375,6 +389,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     const double ek_q = ek[jqm + HALO];
     for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
     if (threadIdx.x < FIELD_OUT) enw[threadIdx.x] = a.en[imod(j0 + (int)threadIdx.x, M) + HALO];
+    if (!sgate | sflags | (skconv >= 0)) return;
     double rx = 0.0;
     int flags = 0;
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
@@ -495,11 +510,6 @@ __device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a, int kc) 
     return r;
 }
 
-// The scatter runs when the substep converged (kconv >= 0) without a flag.
-__device__ __forceinline__ bool commit_enabled(const DevStatus *st) {
-    return st->gate && st->kconv >= 0 && st->flags == 0;
-}
-
 // Converged sweep index for the commit, making the test of the last enqueued
 // sweep if no later sweep made it; -1 if the commit must not run.
 __device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first64, double dx, double tol,
@@ -606,10 +616,15 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, d
 template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
-    if (!commit_enabled(a.st)) return;
-    const CommitPick pk = commit_pick(a, a.st->kconv);
+    // item count, status words and item description in one memory round trip
+    const int n_items = *a.items.n_items;
+    const int sgate = a.st->gate, sflags = a.st->flags, skconv = a.st->kconv;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    asm volatile("" ::"s"(n_items), "s"(sgate), "s"(sflags), "s"(skconv), "s"(c), "s"(beg), "s"(end));
+    if (item >= n_items) return;
+    if (!(sgate && skconv >= 0 && sflags == 0)) return;   // the commit runs on a converged, unflagged substep
+    const CommitPick pk = commit_pick(a, skconv);
     const int M = a.M;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
@@ -689,7 +704,6 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
 // kernel of its own, so the plain one keeps its registers).
 template <int P, bool RECORD>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
-    if ((int)blockIdx.x >= *a.items.n_items) return;
     commit_scatter_item<P, RECORD>(a, blockIdx.x);
 }
 

@@ -18,9 +18,10 @@
 
 namespace ecpic {
 
-__device__ __forceinline__ bool prev_converged2(DevStatus *st, int k, double tol, bool writer) {
+__device__ __forceinline__ bool prev_converged2(DevStatus *st, int k, double tol, bool writer,
+                                                unsigned long long reb) {
     if (k <= 0) return false;
-    const double r = dbits(st->re_bits[(k - 1) & 1]);
+    const double r = dbits(reb);
     if (writer && k - 1 < MAX_HIST) st->res_hist[k - 1] = r;
     if (r <= tol) {
         if (writer) { st->kconv = k - 1; st->res = r; }
@@ -55,11 +56,17 @@ template <int P>
 __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
     constexpr int NA = RecA<P>::N;
     DevStatus *st = a.st;
-        if (!st->gate | st->flags | (st->kconv >= 0)) return;
     const int k = a.k;
-    if (prev_converged2(st, k, a.tol, threadIdx.x == 0)) return;
+    // item count, status words and item description in one memory round trip
+    const int n_items = *a.items.n_items;
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const unsigned long long reb = st->re_bits[(k - 1) & 1];
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
+    asm volatile("" ::"s"(n_items), "s"(sgate), "s"(sflags), "s"(skconv), "s"(reb), "s"(c), "s"(beg), "s"(end));
+    if (item >= n_items) return;
+    if (!sgate | sflags | (skconv >= 0)) return;
+    if (prev_converged2(st, k, a.tol, threadIdx.x == 0, reb)) return;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
     const int stride = nw * WAVE;
@@ -145,7 +152,6 @@ __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 template <int P>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
-    if ((int)blockIdx.x >= *a.items.n_items) return;
     sweep_II_item<P>(a, blockIdx.x);
 }
 
@@ -165,7 +171,8 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     constexpr int NA = RecA<P>::N, NS = 2 * (P + 1);
     constexpr int TILE = FIELD2_OUT - P;
     DevStatus *st = a.st;
-    if (!st->gate | st->flags | (st->kconv >= 0)) return;
+    // the status is tested once the loads that do not depend on it are issued
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
     const int k = a.k;
     const int M = a.M;
     const int j0 = blockIdx.x * TILE - P;
@@ -193,6 +200,7 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
         bay[threadIdx.x] = a.ayn[jm] - a.half_dt * a.eyn[jm];
         baz[threadIdx.x] = a.azn[jm] - a.half_dt * a.ezn[jm];
     }
+    if (!sgate | sflags | (skconv >= 0)) return;
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         const int c = imod(clo + t, M);
         double v[NS];
@@ -407,7 +415,8 @@ __global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const DevStatu
     int kc = -1;
     if (st->gate && !st->flags) {
         kc = st->kconv;
-        if (kc < 0 && prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0)) kc = nsweeps - 1;
+        if (kc < 0 && prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0, st->re_bits[(nsweeps - 1) & 1]))
+            kc = nsweeps - 1;
     }
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (kc >= 0) {

@@ -246,6 +246,45 @@ def test_pump2048_full_size_step_properties():
     assert on.gauss_residual(s1["x"], s1["ex"]) <= 1e-13
 
 
+def test_stress16384_full_size_step_properties():
+    """The quintic stress workload at full size (1.28e8 particles, 16384 cells): one step
+    in the launch configuration the benchmark uses.  The oracle cannot sum over all
+    particles in test time, so it checks sampled particles one by one and the field parts
+    of the energy; the invariants hold at any size."""
+    w = workloads.get("stress16384")
+    arr = workloads.generate(w)
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        s0 = c.state()
+        E0 = c.energy()
+        gr0, r0 = c.gauss_residual(vec=True)
+        k, res = c.substep_particles()
+        s1 = c.state()
+        gr1, r1 = c.gauss_residual(vec=True)
+        kII, resII = c.substep_fields()
+        s2 = c.state()
+        E2 = c.energy()
+    del arr
+    assert res <= w.tol and resII <= w.tol
+    assert np.abs(r1 - r0).max() <= 1e-13
+    assert abs(E2[4] - E0[4]) / E0[4] <= 1e-12
+    # Subsystem II leaves the particles alone
+    assert np.array_equal(s2["x"], s1["x"]) and np.array_equal(s2["p"], s1["p"])
+    o1 = Oracle.from_workload(w, n=1)
+    for s, E in ((s0, E0), (s2, E2)):
+        ref = o1.energy({"x": s["x"][:1], "p": s["p"][:1], **{f: s[f] for f in ("ex", "ey", "ez", "ay", "az")}})
+        for j in (1, 2, 3):   # field parts: longitudinal, transverse electric, magnetic
+            assert abs(E[j] - ref[j]) <= 1e-13 * max(abs(ref[j]), 1e-300), (j, E[j], ref[j])
+    gy, gz = o1.G(s0["ay"]), o1.G(s0["az"])
+    ebar = 0.5 * (s0["ex"] + s1["ex"])
+    rng = np.random.default_rng(1)
+    for a in rng.choice(w.n_particles, 1500, replace=False):
+        delta = np.mod(s1["x"][a] - s0["x"][a] + w.L / 2, w.L) - w.L / 2
+        p1, dn, _, _ = o1.particle_map(s0["x"][a], s0["p"][a], delta, s0["ay"], s0["az"], gy, gz, ebar)
+        assert abs(p1 - s1["p"][a]) <= 1e-12 * max(1.0, abs(p1))
+        assert abs(dn - delta) <= 5 * w.tol
+
+
 # --------------------------------------------------------------------------
 # edge cases
 # --------------------------------------------------------------------------
