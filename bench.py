@@ -40,7 +40,7 @@ PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_I_pump2048_pmc.txt")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sub1.hip", "spline.hpp", "common.hpp", "internal.hpp", "coef.hpp"):
+    for f in ("sub1.hip", "sweep.hpp", "spline.hpp", "common.hpp", "internal.hpp", "coef.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2203_06513_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -216,7 +216,7 @@ def main():
                    "speedup_vs_plain_fp64": value / value_plain},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(N),
-                     "kernel": "k_sweep_I<3,true,double> (FP64 Subsystem I sweep, plain form)",
+                     "kernel": f"k_sweep_I<{w.degree},true,double> (FP64 Subsystem I sweep, plain form)",
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "avg_launch_us": sweep_us, "copy_probe_GBs": copy_gbs},
         "kernels_plain": {k: round(v["us_avg"], 2) for k, v in kp.items()},

@@ -94,9 +94,8 @@ struct SweepIArgs {
     const double *coefA;           // A-records of a_perp^n
     const double *coefE0, *coefE1; // E-records of ebar^(k) = (e^n + e^(k))/2, by parity of k
     double *part;                  // [max_items][waves per item][deg+4]: P+2 current slots, residual, flags
-    int32_t *cnt;                  // [max_items][3] movers left / stay / right of the increment a commit
-                                   // after this sweep would take
-    int32_t *wpre;                 // [max_items][waves per item][3] the same, exclusive prefix over waves
+    int32_t *wcnt;                 // [max_items][waves per item][3] movers left / stay / right, per wave,
+                                   // of the increment a commit after this sweep would take
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
@@ -130,7 +129,7 @@ struct CommitIArgs {
     const double *ek0, *ek1;
     double *ex_next;               // padded e_x^{n+1}
     DevStatus *stII;               // reset here, gated on this commit (null: leave it)
-    const int32_t *cnt, *wpre;     // mover counts of the converged sweep (see SweepIArgs)
+    const int32_t *wcnt;           // per-wave mover counts of the converged sweep (see SweepIArgs)
     int32_t *tot;                  // [M][3]
     int32_t *base;                 // [max_items][3] destination of each item's first mover of each kind
     int32_t *nstart;               // [2M + 1]

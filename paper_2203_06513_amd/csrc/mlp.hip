@@ -437,7 +437,7 @@ __device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
         }
     }
     const double slot = moments_to_slots<P>(mo);
-    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
+    const int fl = flags;   // wave-uniform (set through wave_flag)
     double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
     double v = slot;
     v = lane == P + 2 ? 0.0 : v;

@@ -180,11 +180,6 @@ struct ecpic_ctx {
     bool seidel = false;
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    // Second stream for the warm-start tables of the next step, which overlap
-    // Subsystem II of the current one (default priority like the main stream).
-    hipStream_t aux = nullptr;
-    hipEvent_t ev_ready = nullptr, ev_table = nullptr;
-    bool table_pending = false;
     int device = 0;
 
     Particles pb[2]{};
@@ -209,7 +204,7 @@ struct ecpic_ctx {
     ItemList items[2]{};
     int icur = 0;
     int n_items_host = 0;
-    int32_t *cnt = nullptr, *wpre = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
+    int32_t *wcnt = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
     double *part = nullptr;
 
     // padded fields: [0]/[1] = current / next (swapped on commit)
@@ -322,8 +317,7 @@ SweepIArgs sweep_args(ecpic_ctx *c) {
     a.coefE0 = c->coefE[0];
     a.coefE1 = c->coefE[1];
     a.part = c->part;
-    a.cnt = c->cnt;
-    a.wpre = c->wpre;
+    a.wcnt = c->wcnt;
     a.st = c->stI;
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
@@ -397,8 +391,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.ek1 = c->ek[1];
     a.ex_next = c->ex[c->exc ^ 1];
     a.stII = c->stII;
-    a.cnt = c->cnt;
-    a.wpre = c->wpre;
+    a.wcnt = c->wcnt;
     a.tot = c->tot;
     a.base = c->base;
     a.nstart = c->nstart;
@@ -511,11 +504,6 @@ int flags_to_status(int32_t f) {
 void enqueue_begin(ecpic_ctx *c, bool do_I, bool do_II, const DevStatus *gate_src = nullptr) {
     if (do_I) c->kI = 0;
     if (do_II) c->kII = 0;
-    const bool have_table = c->table_pending;
-    if (c->table_pending) {   // the tables read coefA, which the start kernel rewrites
-        hipStreamWaitEvent(c->stream, c->ev_table, 0);
-        c->table_pending = false;
-    }
     const double r = c->dt / (2.0 * c->dx);
     const int t = c->trc;
     timed(c, "begin", [&] {
@@ -524,35 +512,13 @@ void enqueue_begin(ecpic_ctx *c, bool do_I, bool do_II, const DevStatus *gate_sr
                           do_I ? c->coefE[0] : nullptr, c->coefAk[0], do_II ? 1 : 0, c->m0row.data(), c->krow.data(),
                           r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
     });
-    if (do_I && c->ws_on && !have_table) {
+    if (do_I && c->ws_on) {   // the predictor's tables, from this step's a_perp^n and e_x^n
         WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
         timed(c, "ws_table", [&] {
             launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc],
                             c->M, c->ws_table);
         });
     }
-}
-
-// Tables for the next step's predictor, on the second stream, as soon as
-// e_x^{n+1} is committed: they run while Subsystem II of this step does.  The
-// transverse features are those of a_perp^n (Subsystem II has not produced
-// a_perp^{n+1} yet); the tables only seed the Picard iteration.
-void enqueue_next_tables(ecpic_ctx *c) {
-    if (!c->ws_on) return;
-    WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
-    hipEventRecord(c->ev_ready, c->stream);
-    hipStreamWaitEvent(c->aux, c->ev_ready, 0);
-    launch_ws_table(c->P, c->aux, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc ^ 1], c->M,
-                    c->ws_table);
-    hipEventRecord(c->ev_table, c->aux);
-    c->table_pending = true;
-}
-
-// A rolled-back step leaves no tables behind (they would describe its state).
-void drop_next_tables(ecpic_ctx *c) {
-    if (!c->table_pending) return;
-    hipStreamWaitEvent(c->stream, c->ev_table, 0);
-    c->table_pending = false;
 }
 
 // Slots of the training pairs advance after every committed Subsystem I step.
@@ -639,7 +605,7 @@ void free_all(ecpic_ctx *c) {
         F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
-    F(c->cnt); F(c->wpre); F(c->tot); F(c->base); F(c->nstart); F(c->part);
+    F(c->wcnt); F(c->tot); F(c->base); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
@@ -649,9 +615,6 @@ void free_all(ecpic_ctx *c) {
     if (c->h_ring) hipHostFree(c->h_ring);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
     for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
-    if (c->aux) { hipStreamSynchronize(c->aux); hipStreamDestroy(c->aux); }
-    if (c->ev_ready) hipEventDestroy(c->ev_ready);
-    if (c->ev_table) hipEventDestroy(c->ev_table);
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
 }
 
@@ -671,8 +634,7 @@ int alloc_all(ecpic_ctx *c) {
     }
     rc |= dalloc(&c->tot, (size_t)M * 3);
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
-    rc |= dalloc(&c->cnt, (size_t)c->max_items * 3);
-    rc |= dalloc(&c->wpre, (size_t)c->max_items * (c->block / 64) * 3);
+    rc |= dalloc(&c->wcnt, (size_t)c->max_items * (c->block / 64) * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
     // per item and wave: Subsystem I P+4 values, Subsystem II 2 (P+1)
     rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 1), c->P + 4));
@@ -828,13 +790,6 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
         if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return ECPIC_EDEVICE; }
         c->own_stream = true;
     }
-    if (hipStreamCreate(&c->aux) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_ready, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_table, hipEventDisableTiming) != hipSuccess) {
-        free_all(c);
-        delete c;
-        return ECPIC_EDEVICE;
-    }
     rc = alloc_all(c);
     if (rc) {
         free_all(c);
@@ -857,7 +812,6 @@ int ecpic_destroy(ecpic_ctx *c) {
 int ecpic_set_particles(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
     if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     double *dx_ = nullptr, *dp_ = nullptr;
     if (dalloc(&dx_, n) || dalloc(&dp_, n)) { if (dx_) hipFree(dx_); return ECPIC_ENOMEM; }
     int rc = ECPIC_OK;
@@ -875,7 +829,6 @@ int ecpic_set_particles(ecpic_ctx *c, const double *x, const double *p, int64_t 
 int ecpic_set_particles_dev(ecpic_ctx *c, const double *x, const double *p, int64_t n) {
     if (!c || n != c->N || (n > 0 && (!x || !p))) return ECPIC_EINVAL;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     return load_particles_dev(c, x, p);
 }
 
@@ -909,7 +862,6 @@ int ecpic_set_fields(ecpic_ctx *c, const double *ex, const double *ey, const dou
                      const double *az) {
     if (!c) return ECPIC_EINVAL;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     int rc = upload_padded(c, ex, c->ex[c->exc]);
     if (!rc) rc = upload_padded(c, ey, c->ey[c->trc]);
     if (!rc) rc = upload_padded(c, ez, c->ez[c->trc]);
@@ -1117,7 +1069,6 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             enqueue_begin(c, true, true, j == 0 ? nullptr : c->st_ring + 2 * (j - 1) + 1);
             enqueue_sweeps_I(c, gI);
             enqueue_commit_I(c);   // also resets the Subsystem II status, gated on the commit
-            enqueue_next_tables(c);
             IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], c->exact_items};
             enqueue_iters_II(c, v, gII);
             enqueue_commit_II(c);   // writes this step's statuses into the host mirror
@@ -1150,7 +1101,6 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             }
             // Step j needs more than was enqueued (or failed): the steps behind
             // it were gated off.  Finish it from its own state as a lone step.
-            drop_next_tables(c);
             restore(c, snaps[j]);
             c->exact_items = true;
             if (j > 0) c->n_items_host = c->h_ring[j - 1].I.n_items_next;
@@ -1242,7 +1192,6 @@ int ecpic_ws_train(ecpic_ctx *c, const ecpic_ws_train_config *tc, float *final_l
     const int64_t n = std::min(c->ws_base, c->ws_cap);
     if (n < 1) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     const int steps = tc->steps ? tc->steps : 2000, B = tc->batch ? tc->batch : 1024;
     const float lr = tc->lr > 0.0f ? tc->lr : 1e-3f;
     int rc = ws_scratch(c, B / 32);
@@ -1280,7 +1229,6 @@ int ecpic_ws_set_weights(ecpic_ctx *c, const float *w, int64_t n) {
     int64_t need = 0;
     if (!c || !w || ecpic_ws_n_params(c, &need) || n != need) return ECPIC_EINVAL;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     HIPCHK(hipMemcpyAsync(c->ws_theta, w, sizeof(float) * c->wsNP, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipMemcpyAsync(c->ws_norm, w + c->wsNP, sizeof(float) * (need - c->wsNP), hipMemcpyHostToDevice,
                           c->stream));
@@ -1294,7 +1242,6 @@ int ecpic_ws_enable(ecpic_ctx *c, int32_t on) {
     if (!c) return ECPIC_EINVAL;
     if (on && !c->ws_ready) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     c->ws_on = on != 0;
     return ECPIC_OK;
 }
@@ -1332,7 +1279,6 @@ int ecpic_ws_table(ecpic_ctx *c, float *table) {
     if (!c || !table) return ECPIC_EINVAL;
     if (!c->ws_ready) return ECPIC_ESTATE;
     hipSetDevice(c->device);
-    drop_next_tables(c);
     WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
     launch_prep_records(c->P, c->stream, nullptr, c->ay[c->trc], c->az[c->trc], c->ex[c->exc], c->coefA,
                         c->coefE[0], c->M);

@@ -184,7 +184,6 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
-    __shared__ int wcnt[MAX_WAVES][3];
     DevStatus *st = a.st;
     const int k = a.k;
     // the item count, the status words and the item's description are loaded
@@ -295,26 +294,16 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     to_double<P>(mo, md);
     const double slot = moments_to_slots<P>(md);
     const double rm = wave_max_dpp((double)rmax);
-    const int fl = __ballot(flags != 0) ? wave_or(flags) : 0;
+    const int fl = flags;   // wave-uniform (set through wave_flag)
     double *out = a.part + ((size_t)item * nw + wid) * UnitI<P>::N;
     double v = slot;
     v = lane == P + 2 ? rm : v;
     v = lane == P + 3 ? (double)fl : v;
     if (lane < UnitI<P>::N) out[lane] = v;
-    if constexpr (F64) {
-        if (lane == 0) { wcnt[wid][0] = nleft; wcnt[wid][1] = nstay; wcnt[wid][2] = nright; }
-        __syncthreads();
-        if (lane < 3) {
-            int pre = 0, tot = 0;
-            for (int w = 0; w < nw; ++w) {
-                const int n = wcnt[w][lane];
-                pre += w < wid ? n : 0;
-                tot += n;
-            }
-            a.wpre[((size_t)item * nw + wid) * 3 + lane] = pre;
-            if (wid == 0) a.cnt[(size_t)item * 3 + lane] = tot;
-        }
-    }
+    // the wave's mover counts; the commit forms the item totals and the
+    // prefixes over waves itself, so waves end without waiting for each other
+    if constexpr (F64)
+        if (lane < 3) a.wcnt[((size_t)item * nw + wid) * 3 + lane] = lane == 0 ? nleft : (lane == 1 ? nstay : nright);
 }
 
 // One block per work item; the grid may exceed the item count (the count of a
@@ -552,7 +541,10 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
         int r0 = 0, r1 = 0, r2 = 0;
         for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
             a.base[i * 3 + 0] = r0; a.base[i * 3 + 1] = r1; a.base[i * 3 + 2] = r2;
-            r0 += a.cnt[i * 3 + 0]; r1 += a.cnt[i * 3 + 1]; r2 += a.cnt[i * 3 + 2];
+            for (int w = 0; w < a.wpi; ++w) {
+                const int32_t *n = a.wcnt + ((size_t)i * a.wpi + w) * 3;
+                r0 += n[0]; r1 += n[1]; r2 += n[2];
+            }
         }
         tot[c * 3 + 0] = r0; tot[c * 3 + 1] = r1; tot[c * 3 + 2] = r2;
     }
@@ -633,8 +625,11 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
     stage_records<P, double>(rec, a.coefA, pk.coefE, c);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     const int32_t *bs = a.base + (size_t)item * 3;
-    const int32_t *ws = a.wpre + ((size_t)item * nw + wid) * 3;
-    int run0 = bs[0] + ws[0], run1 = bs[1] + ws[1], run2 = bs[2] + ws[2];
+    int run0 = bs[0], run1 = bs[1], run2 = bs[2];
+    for (int w = 0; w < wid; ++w) {   // movers of the item's earlier waves
+        const int32_t *n = a.wcnt + ((size_t)item * nw + w) * 3;
+        run0 += n[0]; run1 += n[1]; run2 += n[2];
+    }
     int flags = 0;
     __syncthreads();
     Own<P, double> o1;
@@ -692,10 +687,7 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         run1 += __popcll(b1);
         run2 += __popcll(b2);
     }
-    if (__ballot(flags != 0)) {
-        flags = wave_or(flags);
-        if (lane == 0) atomicOr(&a.st->flags, flags);
-    }
+    if (flags && lane == 0) atomicOr(&a.st->flags, flags);   // flags is wave-uniform (wave_flag)
 }
 
 // One block per work item; the grid may exceed the item count (the count of a

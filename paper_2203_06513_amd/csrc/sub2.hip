@@ -142,10 +142,7 @@ __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
 #pragma unroll
     for (int j = 0; j <= P; ++j) out += Bp.c[m < 0 ? 0 : m][j] * (comp == 0 ? ty[j] : tz[j]);
     if (lane < 2 * (P + 1)) a.part[((size_t)item * nw + wid) * 2 * (P + 1) + lane] = out;
-    if (__ballot(flags != 0)) {
-        flags = wave_or(flags);
-        if (lane == 0) atomicOr(&st->flags, flags);
-    }
+    if (flags && lane == 0) atomicOr(&st->flags, flags);   // flags is wave-uniform (wave_flag)
 }
 
 // One block per work item; the grid may exceed the item count (the count of a

@@ -24,26 +24,29 @@ __device__ __forceinline__ void end_point(double xi0, double d, int c, double &t
     s = (int)floor(t1);
 }
 
-// Wave sum of the moments and conversion to the P+2 V1 slots of the wave's
-// particles (slot q <-> V1 index c - P + q); lane q < P+2 returns slot q.
+// The P+2 V1 slots of the wave's particles (slot q <-> V1 index c - P + q):
+// each lane converts its own moments (linear, cell c: m = P - q, c+1:
+// m = P + 1 - q, c-1: m = P - 1 - q), the P+2 values are summed over the
+// wave, and lane q < P+2 returns slot q.
 template <int P>
 __device__ __forceinline__ double moments_to_slots(const Moments<P> &mo) {
     constexpr Pieces<P - 1> Q{};
-    double t[3 * P];
+    double v[P + 2];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-        t[i] = wave_sum_dpp(mo.A[i]);
-        t[P + i] = wave_sum_dpp(mo.R[i]);
-        t[2 * P + i] = wave_sum_dpp(mo.L[i]);
+    for (int q = 0; q < P + 2; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < P; ++ii) {
+            if (P - q >= 0 && P - q < P) s = fma(Q.q[P - q < P ? P - q : 0][ii], mo.A[ii], s);
+            if (P + 1 - q >= 0 && P + 1 - q < P) s = fma(Q.q[P + 1 - q < P ? P + 1 - q : 0][ii], mo.R[ii], s);
+            if (P - 1 - q >= 0 && P - 1 - q < P) s = fma(Q.q[P - 1 - q >= 0 ? P - 1 - q : 0][ii], mo.L[ii], s);
+        }
+        v[q] = wave_sum_dpp(s);
     }
-    const int q = threadIdx.x & (WAVE - 1);
+    const int lane = threadIdx.x & (WAVE - 1);
     double out = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3 * P; ++i) {
-        const int grp = i / P, ii = i % P;   // 0: cell c, 1: c+1, 2: c-1
-        const int m = (grp == 0 ? P : (grp == 1 ? P + 1 : P - 1)) - q;   // index c + shift - m == c - P + q
-        out += (m >= 0 && m < P) ? Q.q[m < 0 ? 0 : (m >= P ? P - 1 : m)][ii] * t[i] : 0.0;
-    }
+    for (int q = 0; q < P + 2; ++q) out = lane == q ? v[q] : out;
     return out;
 }
 
