@@ -14,6 +14,7 @@
 //               no floating-point atomics).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -171,5 +172,25 @@ struct FieldIIArgs {
     int32_t k;
     int32_t wpi;                              // waves per item of the particle pass
 };
+
+// Kernel launches go through launch_k.  When a profiled launch has set the
+// events below (runtime.hip, timed()), the dispatch packets themselves take the
+// timestamps: the start event with the first kernel of the launch, the stop
+// event with every one, so it ends at the last.  Unset, it is a plain launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+template <typename F, typename... Args>
+inline void launch_k(F kernel, const dim3 &grid, const dim3 &block, size_t lds, hipStream_t s, Args... args) {
+    LaunchEvents &e = g_launch_events;
+    if (!e.start && !e.stop) {
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+        return;
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, e.start, e.stop, 0u, args...);
+    e.start = nullptr;
+}
 
 }  // namespace ecpic

@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *in, double2 *out, i
 
 void launch_energy(int P, int grid, int block, hipStream_t s, const double *xi, const double *p, ItemList items,
                    const double *ay, const double *az, double *part) {
-#define CALL(PP) hipLaunchKernelGGL((k_energy_part<PP>), dim3(grid), dim3(block), 0, s, xi, p, items, ay, az, part)
+#define CALL(PP) launch_k((k_energy_part<PP>), dim3(grid), dim3(block), 0, s, xi, p, items, ay, az, part)
     ECPIC_DISPATCH(P, CALL)
 #undef CALL
 }
@@ -386,17 +386,17 @@ void launch_energy_final(hipStream_t s, const double *part, const int32_t *n_ite
     r.P = P;
     for (int q = 0; q <= 2 * P; ++q) { r.m0[q] = m0[q]; r.kk[q] = kr[q]; }
     for (int q = 0; q <= 2 * P - 2; ++q) r.m1[q] = m1[q];
-    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, s, part, n_items, w, ex, ey, ez, ay, az, r, M, dx,
+    launch_k(k_energy_final, dim3(1), dim3(1024), 0, s, part, n_items, w, ex, ey, ez, ay, az, r, M, dx,
                        out);
 }
 
 void launch_charge(int P, int grid, int block, hipStream_t s, const double *xi, ItemList items, double *part,
                    double w, int M, double *rho) {
-#define CALL(PP) hipLaunchKernelGGL((k_charge_part<PP>), dim3(grid), dim3(block), 0, s, xi, items, part)
+#define CALL(PP) launch_k((k_charge_part<PP>), dim3(grid), dim3(block), 0, s, xi, items, part)
     ECPIC_DISPATCH(P, CALL)
 #undef CALL
 #define CALL(PP) \
-    hipLaunchKernelGGL((k_assemble_charge<PP>), dim3((M + 255) / 256), dim3(256), 0, s, items, part, w, M, rho)
+    launch_k((k_assemble_charge<PP>), dim3((M + 255) / 256), dim3(256), 0, s, items, part, w, M, rho)
     ECPIC_DISPATCH(P, CALL)
 #undef CALL
 }
@@ -406,24 +406,24 @@ void launch_gauss(hipStream_t s, const double *rho, const double *ex, const doub
     Rows rows{};
     rows.P = P;
     for (int q = 0; q <= 2 * P - 2; ++q) rows.m1[q] = m1[q];
-    hipLaunchKernelGGL(k_gauss, dim3((M + 255) / 256), dim3(256), 0, s, rho, ex, rows, M, dx, r, maxbits);
+    launch_k(k_gauss, dim3((M + 255) / 256), dim3(256), 0, s, rho, ex, rows, M, dx, r, maxbits);
 }
 
 void launch_poisson_rhs(hipStream_t s, const double *rho, int M, double dx, double *u) {
-    hipLaunchKernelGGL(k_poisson_rhs, dim3(1), dim3(1024), 0, s, rho, M, dx, u);
+    launch_k(k_poisson_rhs, dim3(1), dim3(1024), 0, s, rho, M, dx, u);
 }
 
 void launch_pad(hipStream_t s, const double *in, double *out, double alpha, int M) {
-    hipLaunchKernelGGL(k_pad, dim3((M + 255) / 256), dim3(256), 0, s, in, out, alpha, M);
+    launch_k(k_pad, dim3((M + 255) / 256), dim3(256), 0, s, in, out, alpha, M);
 }
 
 void launch_unpad(hipStream_t s, const double *in, double *out, int M) {
-    hipLaunchKernelGGL(k_unpad, dim3((M + 255) / 256), dim3(256), 0, s, in, out, M);
+    launch_k(k_unpad, dim3((M + 255) / 256), dim3(256), 0, s, in, out, M);
 }
 
 void launch_init_particles(hipStream_t s, const double *x, const double *p, int64_t n, double L, double inv_dx,
                            int M, double *xi, double *pp, int32_t *key, int32_t *val) {
-    hipLaunchKernelGGL(k_init_particles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, p, n, L, inv_dx, M,
+    launch_k(k_init_particles, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, p, n, L, inv_dx, M,
                        xi, pp, key, val);
 }
 
@@ -433,9 +433,9 @@ void radix_sort(hipStream_t s, int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v
     const int nblk = (int)((n + RADIX_CHUNK - 1) / RADIX_CHUNK);
     int32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int shift = 0; shift < key_bits; shift += 4) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(256), 0, s, ki, n, shift, hist, nblk);
-        hipLaunchKernelGGL(k_exscan_int, dim3(1), dim3(1024), 0, s, hist, (int64_t)16 * nblk);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(256), 0, s, ki, vi, ko, vo, n, shift, hist, nblk);
+        launch_k(k_radix_hist, dim3(nblk), dim3(256), 0, s, ki, n, shift, hist, nblk);
+        launch_k(k_exscan_int, dim3(1), dim3(1024), 0, s, hist, (int64_t)16 * nblk);
+        launch_k(k_radix_scatter, dim3(nblk), dim3(256), 0, s, ki, vi, ko, vo, n, shift, hist, nblk);
         int32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
@@ -445,37 +445,37 @@ void radix_sort(hipStream_t s, int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v
 
 void launch_gather_sorted(hipStream_t s, const int32_t *val, const double *xi_t, const double *p_t, int64_t n,
                           double *xi, double *p, int32_t *id) {
-    hipLaunchKernelGGL(k_gather_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, xi_t, p_t, n, xi,
+    launch_k(k_gather_sorted, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, val, xi_t, p_t, n, xi,
                        p, id);
 }
 
 void launch_count_cells(hipStream_t s, const int32_t *key, int64_t n, int32_t *count) {
     if (n > 0)
-        hipLaunchKernelGGL(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, count);
+        launch_k(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, count);
 }
 
 void launch_items_from_counts(hipStream_t s, const int32_t *count, int32_t *start, int M, int chunk, int64_t N,
                               ItemList out) {
-    hipLaunchKernelGGL(k_items_from_counts, dim3(1), dim3(1024), 0, s, count, start, M, chunk, N, out);
+    launch_k(k_items_from_counts, dim3(1), dim3(1024), 0, s, count, start, M, chunk, N, out);
 }
 
 void launch_unpermute(hipStream_t s, const double *xi, const double *p, const int32_t *id, int64_t n, double dx,
                       double *x_out, double *p_out) {
     if (n > 0)
-        hipLaunchKernelGGL(k_unpermute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xi, p, id, n, dx, x_out,
+        launch_k(k_unpermute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xi, p, id, n, dx, x_out,
                            p_out);
 }
 
 void launch_copy(hipStream_t s, const double *in, double *out, int64_t n) {
     const int64_t n2 = n / 2;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, n2);
+    launch_k(k_copy, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, s, (const double2 *)in, (double2 *)out, n2);
 }
 
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
                              double dx, double w, int M, double *J, int *flags) {
     const unsigned grid = (unsigned)((n + 255) / 256);
 #define CALL(PP) \
-    hipLaunchKernelGGL((k_deposit_segments<PP>), dim3(grid), dim3(256), 0, s, x0, x1, n, inv_dx, dx, w, M, J, flags)
+    launch_k((k_deposit_segments<PP>), dim3(grid), dim3(256), 0, s, x0, x1, n, inv_dx, dx, w, M, J, flags)
     if (n > 0) ECPIC_DISPATCH(P, CALL)
 #undef CALL
 }

@@ -455,14 +455,14 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_ws_predict(SweepIArgs a) {
 // ---- launchers ------------------------------------------------------------
 void launch_ws_init(int P, hipStream_t s, float *theta, uint64_t seed) {
     const int np = ws_nparams(ws_d(P));
-#define ECPIC_WI(PP) case PP: hipLaunchKernelGGL((k_ws_init<ws_d(PP)>), dim3((np + 255) / 256), dim3(256), 0, s, theta, seed); break;
+#define ECPIC_WI(PP) case PP: launch_k((k_ws_init<ws_d(PP)>), dim3((np + 255) / 256), dim3(256), 0, s, theta, seed); break;
     switch (P) { ECPIC_WI(2) ECPIC_WI(3) ECPIC_WI(4) ECPIC_WI(5) }
 #undef ECPIC_WI
 }
 
 void launch_ws_stats(hipStream_t s, const float *feat, const float *targ, int64_t n, int D, float *mu, float *sd,
                      float *prange) {
-    hipLaunchKernelGGL(k_ws_stats, dim3(D + 2), dim3(256), 0, s, feat, targ, n, D, mu, sd, prange);
+    launch_k(k_ws_stats, dim3(D + 2), dim3(256), 0, s, feat, targ, n, D, mu, sd, prange);
 }
 
 // One optimiser step (update != 0) or only the gradient (grad_out) of a batch.
@@ -474,23 +474,23 @@ void launch_ws_step(int P, hipStream_t s, float *theta, float *m, float *v, cons
     const int nblk = (int)((cnt + 31) / 32);
 #define ECPIC_WS(PP)                                                                                      \
     case PP:                                                                                              \
-        hipLaunchKernelGGL((k_ws_fwd_bwd<ws_d(PP)>), dim3(nblk), dim3(64), 0, s, theta, mu, sd, feat, targ, \
+        launch_k((k_ws_fwd_bwd<ws_d(PP)>), dim3(nblk), dim3(64), 0, s, theta, mu, sd, feat, targ, \
                            n, direct, seed, step, B, pgrad, ploss);                                       \
         break;
     switch (P) { ECPIC_WS(2) ECPIC_WS(3) ECPIC_WS(4) ECPIC_WS(5) }
 #undef ECPIC_WS
-    hipLaunchKernelGGL(k_ws_adam, dim3((np + 255) / 256), dim3(256), 0, s, theta, m, v, pgrad, nblk, np, lr,
+    launch_k(k_ws_adam, dim3((np + 255) / 256), dim3(256), 0, s, theta, m, v, pgrad, nblk, np, lr,
                        (int)(step + 1), update, grad_out, ploss, 1.0f / (2.0f * (float)cnt), loss_out);
 }
 
 void launch_ws_w2_bf16(int P, hipStream_t s, const float *theta, unsigned short *w2b) {
-#define ECPIC_WB(PP) case PP: hipLaunchKernelGGL((k_ws_w2_bf16<ws_d(PP)>), dim3(H * H / 256), dim3(256), 0, s, theta, w2b); break;
+#define ECPIC_WB(PP) case PP: launch_k((k_ws_w2_bf16<ws_d(PP)>), dim3(H * H / 256), dim3(256), 0, s, theta, w2b); break;
     switch (P) { ECPIC_WB(2) ECPIC_WB(3) ECPIC_WB(4) ECPIC_WB(5) }
 #undef ECPIC_WB
 }
 
 void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a) {
-#define ECPIC_WP(PP) case PP: hipLaunchKernelGGL((k_ws_predict<PP>), dim3(grid), dim3(block), 0, s, a); break;
+#define ECPIC_WP(PP) case PP: launch_k((k_ws_predict<PP>), dim3(grid), dim3(block), 0, s, a); break;
     switch (P) { ECPIC_WP(2) ECPIC_WP(3) ECPIC_WP(4) ECPIC_WP(5) }
 #undef ECPIC_WP
 }
@@ -500,7 +500,7 @@ void launch_ws_table(int P, hipStream_t s, const WsNet &net, const unsigned shor
     const int grid = (M + WS_CELLS - 1) / WS_CELLS;
 #define ECPIC_WT(PP)                                                                                             \
     case PP:                                                                                                     \
-        hipLaunchKernelGGL((k_ws_table<PP>), dim3(grid), dim3(64 * WS_CELLS), 0, s, net, w2b, coefA, ay, az, ex, \
+        launch_k((k_ws_table<PP>), dim3(grid), dim3(64 * WS_CELLS), 0, s, net, w2b, coefA, ay, az, ex, \
                            M, table);                                                                            \
         break;
     switch (P) { ECPIC_WT(2) ECPIC_WT(3) ECPIC_WT(4) ECPIC_WT(5) }

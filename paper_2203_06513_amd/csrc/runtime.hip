@@ -170,6 +170,7 @@ struct Prof {
 
 namespace ecpic {
 constexpr int STEP_BATCH = 16;   // steps enqueued before the host reads their statuses
+thread_local LaunchEvents g_launch_events;
 }
 
 struct ecpic_ctx {
@@ -275,14 +276,15 @@ void flush_prof(ecpic_ctx *c) {
     c->prof.pending.clear();
 }
 
-// Launch wrapped in timing events when profiling is on.
+// Launch timed when profiling is on: the events are taken by the kernels'
+// dispatch packets (launch_k), so they span the kernels' execution only.
 template <typename F>
 void timed(ecpic_ctx *c, const char *name, F &&launch) {
     if (!c->prof.on) { launch(); return; }
     hipEvent_t a = c->prof.get(), b = c->prof.get();
-    hipEventRecord(a, c->stream);
+    g_launch_events = {a, b};
     launch();
-    hipEventRecord(b, c->stream);
+    g_launch_events = {};
     c->prof.pending.push_back({name, {a, b}});
 }
 

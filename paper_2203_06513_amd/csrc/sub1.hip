@@ -706,11 +706,11 @@ void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStrea
 #define ECPIC_SW(PP)                                                                                         \
     case PP:                                                                                                 \
         if (fp32) {                                                                                          \
-            if (seidel) hipLaunchKernelGGL((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), 0, s, a);  \
-            else hipLaunchKernelGGL((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), 0, s, a);        \
+            if (seidel) launch_k((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), 0, s, a);  \
+            else launch_k((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), 0, s, a);        \
         } else {                                                                                             \
-            if (seidel) hipLaunchKernelGGL((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), 0, s, a); \
-            else hipLaunchKernelGGL((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), 0, s, a);       \
+            if (seidel) launch_k((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), 0, s, a); \
+            else launch_k((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), 0, s, a);       \
         }                                                                                                    \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
@@ -721,7 +721,7 @@ void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a) {
     const int grid = (M + FIELD_OUT - (P - 1) - 1) / (FIELD_OUT - (P - 1));
     const int slen = FIELD_OUT + a.ntaps - 1;
     const size_t lds = sizeof(double) * ((size_t)(slen + P + 1) * (P + 2) + slen + a.ntaps + 2 * FIELD_OUT);
-#define ECPIC_F(PP) case PP: hipLaunchKernelGGL((k_field_I<PP>), dim3(grid), dim3(256), lds, s, a); break;
+#define ECPIC_F(PP) case PP: launch_k((k_field_I<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F(2) ECPIC_F(3) ECPIC_F(4) ECPIC_F(5) }
 #undef ECPIC_F
 }
@@ -730,7 +730,7 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
                          const double *e, double *coefA, double *coefE, int M) {
     const int grid = (M + 255) / 256;
 #define ECPIC_PR(PP) \
-    case PP: hipLaunchKernelGGL((k_prep_records<PP>), dim3(grid), dim3(256), 0, s, st, ay, az, e, coefA, coefE, M); break;
+    case PP: launch_k((k_prep_records<PP>), dim3(grid), dim3(256), 0, s, st, ay, az, e, coefA, coefE, M); break;
     switch (P) { ECPIC_PR(2) ECPIC_PR(3) ECPIC_PR(4) ECPIC_PR(5) }
 #undef ECPIC_PR
 }
@@ -739,18 +739,18 @@ void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArg
     const size_t lds = a.scan_in_lds ? sizeof(int32_t) * (5 * (size_t)a.M + 1) : 0;
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
-        hipLaunchKernelGGL((k_commit_scan<PP>), dim3(1), dim3(1024), lds, s, a);                 \
+        launch_k((k_commit_scan<PP>), dim3(1), dim3(1024), lds, s, a);                 \
         if (a.rec.stride > 0)                                                                    \
-            hipLaunchKernelGGL((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
+            launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
         else                                                                                     \
-            hipLaunchKernelGGL((k_commit_scatter<PP, false>), dim3(grid), dim3(block), 0, s, a); \
+            launch_k((k_commit_scatter<PP, false>), dim3(grid), dim3(block), 0, s, a); \
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C
 }
 
 void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, st, gate);
+    launch_k(k_begin, dim3(1), dim3(1), 0, s, st, gate);
 }
 
 

@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const DevStatu
 }
 
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a) {
-#define ECPIC_S2(PP) case PP: hipLaunchKernelGGL((k_sweep_II<PP>), dim3(grid), dim3(block), 0, s, a); break;
+#define ECPIC_S2(PP) case PP: launch_k((k_sweep_II<PP>), dim3(grid), dim3(block), 0, s, a); break;
     switch (P) { ECPIC_S2(2) ECPIC_S2(3) ECPIC_S2(4) ECPIC_S2(5) }
 #undef ECPIC_S2
 }
@@ -452,7 +452,7 @@ void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
     const int grid = (M + FIELD2_OUT - P - 1) / (FIELD2_OUT - P);
     const int slen = FIELD2_OUT + a.ntaps - 1;
     const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + a.ntaps + 4 * FIELD2_OUT);
-#define ECPIC_F2(PP) case PP: hipLaunchKernelGGL((k_field_II<PP>), dim3(grid), dim3(256), lds, s, a); break;
+#define ECPIC_F2(PP) case PP: launch_k((k_field_II<PP>), dim3(grid), dim3(256), lds, s, a); break;
     switch (P) { ECPIC_F2(2) ECPIC_F2(3) ECPIC_F2(4) ECPIC_F2(5) }
 #undef ECPIC_F2
 }
@@ -469,7 +469,7 @@ void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *ga
     const size_t lds = do_II ? sizeof(double) * (2 * (FIELD2_OUT + ntaps - 1) + ntaps) : 0;
 #define ECPIC_B2(PP)                                                                                          \
     case PP:                                                                                                  \
-        hipLaunchKernelGGL((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn,  \
+        launch_k((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn,  \
                            ezn, exn, dt, coefA, coefE0, coefAk0, do_II, a, b, r2, ck, taps, ntaps, mlo, M, E0y,   \
                            E0z);                                                                              \
         break;
@@ -479,14 +479,14 @@ void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *ga
 
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
                  double alpha, int M) {
-    hipLaunchKernelGGL(k_conv, dim3(grid), dim3(256), 0, s, in, out, taps, ntaps, mlo, alpha, M);
+    launch_k(k_conv, dim3(grid), dim3(256), 0, s, in, out, taps, ntaps, mlo, alpha, M);
 }
 
 void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
                       const double *eyn, const double *ezn, const double *ayn, const double *azn, const double *ey0,
                       const double *ey1, const double *ez0, const double *ez1, double *ey_next, double *ez_next,
                       double *ay_next, double *az_next, double half_dt, int M, int nsweeps, double tol) {
-    hipLaunchKernelGGL(k_commit_II, dim3(grid), dim3(256), 0, s, st, stI, mirror, eyn, ezn, ayn, azn, ey0, ey1, ez0,
+    launch_k(k_commit_II, dim3(grid), dim3(256), 0, s, st, stI, mirror, eyn, ezn, ayn, azn, ey0, ey1, ez0,
                        ez1, ey_next, ez_next, ay_next, az_next, half_dt, M, nsweeps, tol);
 }
 
