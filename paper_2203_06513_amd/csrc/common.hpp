@@ -175,13 +175,19 @@ __device__ __forceinline__ int block_exscan(int v, int *lds /* >= 32 */, int *to
 
 // Build an item list from per-cell counts (single block).  start[c] must hold
 // the exclusive scan of counts, start[M] = N.
-__device__ inline void build_items(const int32_t *count, const int32_t *start, int M, int chunk, int64_t N,
-                            ItemList out, int *lds) {
+// Returns the item count (in every thread).
+__device__ inline int build_items(const int32_t *count, const int32_t *start, int M, int chunk, int64_t N,
+                                  ItemList out, int *lds) {
     // items per cell, exclusive scan -> cell_first
     const int per = (M + blockDim.x - 1) / blockDim.x;
     const int c0 = threadIdx.x * per;
-    int local = 0;
-    for (int c = c0; c < c0 + per && c < M; ++c) local += (count[c] + chunk - 1) / chunk;
+    int local = 0, one_each = 1;
+    for (int c = c0; c < c0 + per && c < M; ++c) {
+        const int ni = (count[c] + chunk - 1) / chunk;
+        local += ni;
+        one_each &= ni == 1;
+    }
+    one_each = __syncthreads_and(one_each);
     int total;
     int off = block_exscan(local, lds, &total);
     for (int c = c0; c < c0 + per && c < M; ++c) {
@@ -197,8 +203,10 @@ __device__ inline void build_items(const int32_t *count, const int32_t *start, i
     if (threadIdx.x == 0) {
         out.cell_first[M] = total;
         out.begin[total] = (int)N;
-        *out.n_items = total;
+        out.n_items[0] = total;
+        out.n_items[1] = one_each;   // item c is cell c's only item
     }
+    return total;
 }
 
 // Exclusive scan of count[0..M) into start[0..M] (single block).

@@ -52,7 +52,8 @@ struct ItemList {
     int32_t *cell;        // [max_items]
     int32_t *begin;       // [max_items + 1]
     int32_t *cell_first;  // [M + 1]: first item of each cell
-    int32_t *n_items;     // device scalar
+    int32_t *n_items;     // device [2]: the item count, and 1 if every cell has exactly one item
+                          // (item c is then cell c), else 0
 };
 
 struct Particles {

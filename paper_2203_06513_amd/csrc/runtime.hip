@@ -629,7 +629,7 @@ int alloc_all(ecpic_ctx *c) {
         rc |= dalloc(&c->dbuf[b], N);
         if (c->k32 > 0) rc |= dalloc(&c->fbuf[b], N);
         rc |= dalloc(&c->items[b].cell, c->max_items); rc |= dalloc(&c->items[b].begin, c->max_items + 1);
-        rc |= dalloc(&c->items[b].cell_first, M + 1); rc |= dalloc(&c->items[b].n_items, 1);
+        rc |= dalloc(&c->items[b].cell_first, M + 1); rc |= dalloc(&c->items[b].n_items, 2);
         rc |= dalloc(&c->ex[b], MP); rc |= dalloc(&c->ey[b], MP); rc |= dalloc(&c->ez[b], MP);
         rc |= dalloc(&c->ay[b], MP); rc |= dalloc(&c->az[b], MP);
         rc |= dalloc(&c->ek[b], MP); rc |= dalloc(&c->eyk[b], MP); rc |= dalloc(&c->ezk[b], MP);
@@ -1071,7 +1071,9 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             enqueue_begin(c, true, true, j == 0 ? nullptr : c->st_ring + 2 * (j - 1) + 1);
             enqueue_sweeps_I(c, gI);
             enqueue_commit_I(c);   // also resets the Subsystem II status, gated on the commit
-            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], c->exact_items};
+            // Subsystem II runs on the order the commit just made, whose item
+            // count only the device knows: launch for the largest count
+            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
             enqueue_iters_II(c, v, gII);
             enqueue_commit_II(c);   // writes this step's statuses into the host mirror
             advance(c);

@@ -326,11 +326,13 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
 // current slots, the max of the residuals and the OR of the flags.
 template <int P>
-__device__ __forceinline__ void cell_partials_I(const ItemList &it, const double *part, int c, int wpi,
-                                                double (&v)[P + 2], double &rx, int &flags) {
+__device__ __forceinline__ void cell_partials_I(const ItemList &it, bool one_each, const double *part, int c,
+                                                int wpi, double (&v)[P + 2], double &rx, int &flags) {
 #pragma unroll
     for (int q = 0; q < P + 2; ++q) v[q] = 0.0;
-    const int u0 = it.cell_first[c] * wpi, u1 = it.cell_first[c + 1] * wpi;
+    // with one item per cell the item index is the cell: no dependent load
+    const int u0 = (one_each ? c : it.cell_first[c]) * wpi;
+    const int u1 = one_each ? u0 + wpi : it.cell_first[c + 1] * wpi;
     for (int u = u0; u < u1; ++u) {
         const double *w = part + (size_t)u * UnitI<P>::N;
 #pragma unroll
@@ -358,6 +360,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     DevStatus *st = a.st;
     // the status is tested once the loads that do not depend on it are issued
     const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const bool one_each = a.items.n_items[1] != 0;
     const int k = a.k;
     const int M = a.M;
     const int j0 = blockIdx.x * TILE - (P - 1);   // first cell computed
@@ -383,7 +386,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     int flags = 0;
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         double v[NS];
-        cell_partials_I<P>(a.items, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
+        cell_partials_I<P>(a.items, one_each, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
 #pragma unroll
         for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
     }
@@ -537,10 +540,13 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     int32_t *nstart = in_lds ? scan_lds + 3 * M : a.nstart;
     int32_t *ncount = nstart + (M + 1);
     // totals per old cell and exclusive prefix of each item within its cell
+    // (with one item per cell, item c is cell c: no dependent load)
+    const bool one_each = it.n_items[1] != 0;
     for (int c = threadIdx.x; c < M; c += blockDim.x) {
         int r0 = 0, r1 = 0, r2 = 0;
-        for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
-            a.base[i * 3 + 0] = r0; a.base[i * 3 + 1] = r1; a.base[i * 3 + 2] = r2;
+        const int i0 = one_each ? c : it.cell_first[c], i1 = one_each ? c + 1 : it.cell_first[c + 1];
+        for (int i = i0; i < i1; ++i) {
+            if (!one_each) { a.base[i * 3 + 0] = r0; a.base[i * 3 + 1] = r1; a.base[i * 3 + 2] = r2; }
             for (int w = 0; w < a.wpi; ++w) {
                 const int32_t *n = a.wcnt + ((size_t)i * a.wpi + w) * 3;
                 r0 += n[0]; r1 += n[1]; r2 += n[2];
@@ -561,17 +567,22 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
         const int bL = nstart[cm] + tot[cmm * 3 + 2] + tot[cm * 3 + 1];
         const int bS = nstart[c] + tot[cm * 3 + 2];
         const int bR = nstart[cp];
-        for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
-            a.base[i * 3 + 0] += bL;
-            a.base[i * 3 + 1] += bS;
-            a.base[i * 3 + 2] += bR;
+        if (one_each) {   // the item's prefix within its cell is zero
+            a.base[c * 3 + 0] = bL;
+            a.base[c * 3 + 1] = bS;
+            a.base[c * 3 + 2] = bR;
+        } else {
+            for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
+                a.base[i * 3 + 0] += bL;
+                a.base[i * 3 + 1] += bS;
+                a.base[i * 3 + 2] += bR;
+            }
         }
     }
     __syncthreads();
-    build_items(ncount, nstart, M, a.chunk, a.N, a.items_next, lds);
-    __syncthreads();
+    const int n_next = build_items(ncount, nstart, M, a.chunk, a.N, a.items_next, lds);
     if (threadIdx.x == 0) {
-        a.st->n_items_next = *a.items_next.n_items;
+        a.st->n_items_next = n_next;
         a.st->committed = 1;
     }
 }

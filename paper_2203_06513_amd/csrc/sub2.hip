@@ -170,6 +170,7 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     DevStatus *st = a.st;
     // the status is tested once the loads that do not depend on it are issued
     const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const bool one_each = a.items.n_items[1] != 0;   // item c is cell c
     const int k = a.k;
     const int M = a.M;
     const int j0 = blockIdx.x * TILE - P;
@@ -203,7 +204,8 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
         double v[NS];
 #pragma unroll
         for (int q = 0; q < NS; ++q) v[q] = 0.0;
-        const int u0 = a.items.cell_first[c] * a.wpi, u1 = a.items.cell_first[c + 1] * a.wpi;
+        const int u0 = (one_each ? c : a.items.cell_first[c]) * a.wpi;
+        const int u1 = one_each ? u0 + a.wpi : a.items.cell_first[c + 1] * a.wpi;
         for (int u = u0; u < u1; ++u) {   // the wave partials of the cell's items
 #pragma unroll
             for (int q = 0; q < NS; ++q) v[q] += a.part[(size_t)u * NS + q];

@@ -326,6 +326,45 @@ def test_tiny_and_degenerate_particles(seidel):
     assert_state_close(g, s, L)
 
 
+def _items_per_step(o, s, w, nsteps, chunk=2048):
+    """Work items (cells cut into pieces of at most `chunk` particles) along the oracle run."""
+    counts = []
+    for _ in range(nsteps + 1):
+        n = np.bincount(np.floor(s["x"] / w.dx).astype(int) % w.M, minlength=w.M)
+        counts.append(int(np.sum((n + chunk - 1) // chunk)))
+        st, _, _, _ = o.step(s, 1)
+        assert st == 0
+    return counts
+
+
+@pytest.mark.parametrize("case", ["sparse", "dense"])
+def test_item_count_changes_within_steps(case):
+    """Steps during which the number of work items changes (particles entering empty cells;
+    a cell's count crossing the item size): Subsystem II runs on the new order, whose item
+    count is only known on the device, and must cover every item."""
+    if case == "sparse":
+        w = workloads.small("sparse", M=64, L=8.0, n=48, dt=0.05, sigma=0.6, amplitude=0.3)
+    else:
+        w = workloads.small("dense", M=8, L=2.0, n=16384, dt=0.05, sigma=0.3, amplitude=0.3)
+    arr = workloads.generate(w)
+    nsteps = 12
+    o = Oracle.from_workload(w, seidel=1)
+    s = initial_state(o, arr)
+    items = _items_per_step(o, {k: v.copy() for k, v in s.items()}, w, nsteps)
+    assert max(items[1:]) > items[0] or len(set(items)) > 1, items   # the case is exercised
+    st, kI, kII, E = o.step(s, nsteps, energies=True)
+    assert st == 0
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        H0 = c.energy()[4]
+        rc, done, gI, gII, _ = c.step(nsteps)
+        g = c.state()
+        H = c.energy()[4]
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L, tol=1e-11)
+    assert abs(H - H0) / H0 <= 1e-12
+
+
 def test_not_converged_rolls_back():
     w = workloads.get("langmuir64").scaled(n_particles=2000, kmax=2)
     arr = workloads.generate(w)
