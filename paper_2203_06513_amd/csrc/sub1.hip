@@ -179,11 +179,19 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 // previous FP64 sweep, or read from the last float sweep of the precision form.
 enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2 };
 
+// Rows a wave must hold for the sweep to queue its crossing lanes (degree >= 4).
+constexpr int QUEUE_MIN_ROWS = 16;
+
+// The queue of crossing lanes (see the sweep loop): per wave, in dynamic LDS,
+// the indices of the particles to redo.  (Keeping their position, momentum
+// and increment there instead of reloading them was measured slower.)
+constexpr int QCAP = 2 * WAVE;
+inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * sizeof(int); }
+
 template <int P, bool SEIDEL, typename T, int START>
-__device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
+__device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsRec<P, T> *rec, int *queue) {
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
-    __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     DevStatus *st = a.st;
     const int k = a.k;
     // the item count, the status words and the item's description are loaded
@@ -245,48 +253,155 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
     // issued a whole row earlier, instead of one issued moments before.
     T pend = (T)0;
     int pend_i = -1;
-    for (int row = wb; row < we; row += WAVE, ia += WAVE) {
-        Lane<T> La;
-        const double xi0 = nx;
-        La.p0 = (T)np;
-        La.d = from_float ? (T)nf : nd;
-        const bool valid = ia < we;
-        const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
-        if (pend_i >= 0) dout[pend_i] = pend;
-        {   // prefetch the next row (unconditionally: the last row reloads its last particle)
-            const int il = min(ia + WAVE, we - 1);
-            nx = a.xi[il];
-            np = a.p[il];
-            if constexpr (from_float) nf = d32in[il];
-            else if constexpr (!explicit_start) nd = din[il];
-        }
-        stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
-        const bool cross1 = __ballot(La.s != 0) != 0;
-        T pa, dna;
-        stage_push<P, T>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
-        if (valid) {
-            // keep d^(k) in FP64 where a Jacobi commit may take it
+    // Lanes whose step crosses a cell boundary (from d^(k) for the push, or
+    // from d^(k+1) for the Seidel deposit) need the neighbour-cell terms; they
+    // are few, so the row is computed with the own-cell terms only, and such a
+    // lane's particle is queued (its index, in LDS) and redone with the full
+    // terms once a whole row of them has gathered.  Without the queue every row
+    // holding one crossing lane would run the neighbour code for all 64 lanes.
+    int *const q = queue + (size_t)wid * QCAP;
+    int qn = 0;   // queued particles (wave-uniform)
+    auto redo = [&](int n) {   // the first n queued particles, with every term
+        const bool qv = lane < n;
+        const int qi = q[qv ? lane : 0];
+        Lane<T> Lq;
+        const double xq = a.xi[qi];
+        Lq.p0 = (T)a.p[qi];
+        if constexpr (from_float) Lq.d = (T)d32in[qi];
+        else if constexpr (!explicit_start) Lq.d = din[qi];
+        stage_gather<P, T, explicit_start>(o1, Lq, xq, c, dt_dx, flags);
+        const bool cr = __ballot(Lq.s != 0) != 0;
+        T pq, dq;
+        stage_push<P, T>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
+        if (qv) {
             if constexpr (F64)
-                if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
-            rmax = fmax(rmax, fabs(dna - La.d));
+                if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[qi] = Lq.d;
+            dout[qi] = dq;
+            rmax = fmax(rmax, fabs(dq - Lq.d));
         }
-        pend = dna;
-        pend_i = valid ? ia : -1;
-        const T w = valid ? (T)1 : (T)0;
-        int sc;   // cell change of the increment a commit after this sweep would take
-        if (SEIDEL) {
-            T ta;
-            if constexpr (F64) end_point(xi0, dna, c, ta, sc, flags);
-            else end_point(La.t0, dna, ta, sc, flags);
-            stage_deposit<P, T>(mo, __ballot(sc != 0) != 0, La.t0, ta, sc, w);
+        const T w = qv ? (T)1 : (T)0;
+        int sc;
+        if constexpr (SEIDEL) {
+            T tq;
+            if constexpr (F64) end_point(xq, dq, c, tq, sc, flags);
+            else end_point(Lq.t0, dq, tq, sc, flags);
+            stage_deposit<P, T>(mo, __ballot(sc != 0) != 0, Lq.t0, tq, sc, w);
         } else {
-            sc = La.s;
-            stage_deposit<P, T>(mo, cross1, La.t0, La.t1, La.s, w);
+            sc = Lq.s;
+            stage_deposit<P, T>(mo, cr, Lq.t0, Lq.t1, Lq.s, w);
         }
         if constexpr (F64) {
-            nleft += __popcll(__builtin_amdgcn_ballot_w64(sc < 0) & vmask);
-            nright += __popcll(__builtin_amdgcn_ballot_w64(sc > 0) & vmask);
-            nstay += __popcll(__builtin_amdgcn_ballot_w64(sc == 0) & vmask);
+            const uint64_t qmask = __builtin_amdgcn_ballot_w64(qv);
+            nleft += __popcll(__builtin_amdgcn_ballot_w64(sc < 0) & qmask);
+            nright += __popcll(__builtin_amdgcn_ballot_w64(sc > 0) & qmask);
+            nstay += __popcll(__builtin_amdgcn_ballot_w64(sc == 0) & qmask);
+        }
+    };
+    // The queue pays for itself on long runs of rows and at high degree (the
+    // neighbour terms cost more there; measured: 11 % faster at degree 5, 10 %
+    // slower at degree 3).  Otherwise a row with a crossing lane computes the
+    // neighbour terms for all its lanes.
+    if (P >= 4 && we - wb >= QUEUE_MIN_ROWS * WAVE) {
+        for (int row = wb; row < we; row += WAVE, ia += WAVE) {
+            Lane<T> La;
+            const double xi0 = nx;
+            La.p0 = (T)np;
+            La.d = from_float ? (T)nf : nd;
+            const bool valid = ia < we;
+            if (pend_i >= 0) dout[pend_i] = pend;
+            {   // prefetch the next row (unconditionally: the last row reloads its last particle)
+                const int il = min(ia + WAVE, we - 1);
+                nx = a.xi[il];
+                np = a.p[il];
+                if constexpr (from_float) nf = d32in[il];
+                else if constexpr (!explicit_start) nd = din[il];
+            }
+            stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
+            // own-cell terms for every lane; a crossing lane's result is discarded
+            // (it stays finite: its end point is clamped into (-1, 2) and |d| < dt/dx < 1)
+            T pa, dna;
+            stage_push<P, T>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            bool cross = La.s != 0;
+            T ta = La.t1;
+            if constexpr (SEIDEL) {
+                int sc;
+                if constexpr (F64) end_point(xi0, dna, c, ta, sc, flags);
+                else end_point(La.t0, dna, ta, sc, flags);
+                cross = cross || sc != 0;
+            }
+            const bool live = valid && !cross;
+            if (live) {
+                // keep d^(k) in FP64 where a Jacobi commit may take it
+                if constexpr (F64)
+                    if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
+                rmax = fmax(rmax, fabs(dna - La.d));
+            }
+            pend = dna;
+            pend_i = live ? ia : -1;
+            // a live lane's step stays in the cell: own-cell deposit, and it stays
+            stage_deposit<P, T>(mo, false, La.t0, ta, 0, live ? (T)1 : (T)0);
+            const uint64_t lmask = __builtin_amdgcn_ballot_w64(live);
+            if constexpr (F64) nstay += __popcll(lmask);
+            const uint64_t dmask = __builtin_amdgcn_ballot_w64(valid && cross);
+            if (dmask) {
+                const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
+                if (valid && cross) q[qn + __popcll(dmask & below)] = ia;
+                qn += __popcll(dmask);
+                if (qn >= WAVE) {
+                    redo(WAVE);
+                    qn -= WAVE;
+                    if (lane < qn) {   // move the rest to the front
+                        const int v = q[WAVE + lane];
+                        q[lane] = v;
+                    }
+                }
+            }
+        }
+        if (qn > 0) redo(qn);
+    } else {
+        for (int row = wb; row < we; row += WAVE, ia += WAVE) {
+            Lane<T> La;
+            const double xi0 = nx;
+            La.p0 = (T)np;
+            La.d = from_float ? (T)nf : nd;
+            const bool valid = ia < we;
+            const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
+            if (pend_i >= 0) dout[pend_i] = pend;
+            {   // prefetch the next row (unconditionally: the last row reloads its last particle)
+                const int il = min(ia + WAVE, we - 1);
+                nx = a.xi[il];
+                np = a.p[il];
+                if constexpr (from_float) nf = d32in[il];
+                else if constexpr (!explicit_start) nd = din[il];
+            }
+            stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
+            const bool cross1 = __ballot(La.s != 0) != 0;
+            T pa, dna;
+            stage_push<P, T>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            if (valid) {
+                // keep d^(k) in FP64 where a Jacobi commit may take it
+                if constexpr (F64)
+                    if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
+                rmax = fmax(rmax, fabs(dna - La.d));
+            }
+            pend = dna;
+            pend_i = valid ? ia : -1;
+            const T w = valid ? (T)1 : (T)0;
+            int sc;   // cell change of the increment a commit after this sweep would take
+            if (SEIDEL) {
+                T ta;
+                if constexpr (F64) end_point(xi0, dna, c, ta, sc, flags);
+                else end_point(La.t0, dna, ta, sc, flags);
+                stage_deposit<P, T>(mo, __ballot(sc != 0) != 0, La.t0, ta, sc, w);
+            } else {
+                sc = La.s;
+                stage_deposit<P, T>(mo, cross1, La.t0, La.t1, La.s, w);
+            }
+            if constexpr (F64) {
+                nleft += __popcll(__builtin_amdgcn_ballot_w64(sc < 0) & vmask);
+                nright += __popcll(__builtin_amdgcn_ballot_w64(sc > 0) & vmask);
+                nstay += __popcll(__builtin_amdgcn_ballot_w64(sc == 0) & vmask);
+            }
         }
     }
     if (pend_i >= 0) dout[pend_i] = pend;
@@ -310,17 +425,19 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item) {
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 template <int P, bool SEIDEL, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
+    __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
+    extern __shared__ int queue[];    // the waves' queues (degree >= 4)
     if (a.k == 0 && a.explicit_start) {
-        sweep_I_item<P, SEIDEL, T, START_EXPLICIT>(a, blockIdx.x);
+        sweep_I_item<P, SEIDEL, T, START_EXPLICIT>(a, blockIdx.x, rec, queue);
         return;
     }
     if constexpr (sizeof(T) == 8) {
         if (a.d32in) {
-            sweep_I_item<P, SEIDEL, T, START_FLOAT>(a, blockIdx.x);
+            sweep_I_item<P, SEIDEL, T, START_FLOAT>(a, blockIdx.x, rec, queue);
             return;
         }
     }
-    sweep_I_item<P, SEIDEL, T, START_READ>(a, blockIdx.x);
+    sweep_I_item<P, SEIDEL, T, START_READ>(a, blockIdx.x, rec, queue);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -714,14 +831,15 @@ __global__ void k_begin(DevStatus *st, const DevStatus *gate) { init_status(st, 
 
 // ---- launchers ------------------------------------------------------------
 void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a) {
+    const size_t lds = P >= 4 ? queue_lds_bytes(block) : 0;   // the queue is used from degree 4 on
 #define ECPIC_SW(PP)                                                                                         \
     case PP:                                                                                                 \
         if (fp32) {                                                                                          \
-            if (seidel) launch_k((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), 0, s, a);  \
-            else launch_k((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), 0, s, a);        \
+            if (seidel) launch_k((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), lds, s, a);  \
+            else launch_k((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), lds, s, a);        \
         } else {                                                                                             \
-            if (seidel) launch_k((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), 0, s, a); \
-            else launch_k((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), 0, s, a);       \
+            if (seidel) launch_k((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), lds, s, a); \
+            else launch_k((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), lds, s, a);       \
         }                                                                                                    \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
