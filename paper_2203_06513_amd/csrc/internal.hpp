@@ -133,7 +133,9 @@ struct CommitIArgs {
     DevStatus *stII;               // reset here, gated on this commit (null: leave it)
     const int32_t *wcnt;           // per-wave mover counts of the converged sweep (see SweepIArgs)
     int32_t *tot;                  // [M][3]
-    int32_t *base;                 // [max_items][3] destination of each item's first mover of each kind
+    int32_t *base;                 // [max_items][3] each item's movers of each kind before it in its cell
+                                   // (written only when some cell has several items)
+    int32_t *cbase;                // [M][3] destination of each cell's first mover of each kind
     int32_t *nstart;               // [2M + 1]
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;

@@ -205,7 +205,7 @@ struct ecpic_ctx {
     ItemList items[2]{};
     int icur = 0;
     int n_items_host = 0;
-    int32_t *wcnt = nullptr, *tot = nullptr, *base = nullptr, *nstart = nullptr;
+    int32_t *wcnt = nullptr, *tot = nullptr, *base = nullptr, *cbase = nullptr, *nstart = nullptr;
     double *part = nullptr;
 
     // padded fields: [0]/[1] = current / next (swapped on commit)
@@ -396,6 +396,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.wcnt = c->wcnt;
     a.tot = c->tot;
     a.base = c->base;
+    a.cbase = c->cbase;
     a.nstart = c->nstart;
     a.st = c->stI;
     a.dt = c->dt;
@@ -607,7 +608,7 @@ void free_all(ecpic_ctx *c) {
         F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
-    F(c->wcnt); F(c->tot); F(c->base); F(c->nstart); F(c->part);
+    F(c->wcnt); F(c->tot); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
@@ -636,6 +637,7 @@ int alloc_all(ecpic_ctx *c) {
     }
     rc |= dalloc(&c->tot, (size_t)M * 3);
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
+    rc |= dalloc(&c->cbase, (size_t)c->M * 3);
     rc |= dalloc(&c->wcnt, (size_t)c->max_items * (c->block / 64) * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
     // per item and wave: Subsystem I P+4 values, Subsystem II 2 (P+1)

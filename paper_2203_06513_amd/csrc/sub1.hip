@@ -659,17 +659,46 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     // totals per old cell and exclusive prefix of each item within its cell
     // (with one item per cell, item c is cell c: no dependent load)
     const bool one_each = it.n_items[1] != 0;
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        int r0 = 0, r1 = 0, r2 = 0;
-        const int i0 = one_each ? c : it.cell_first[c], i1 = one_each ? c + 1 : it.cell_first[c + 1];
-        for (int i = i0; i < i1; ++i) {
-            if (!one_each) { a.base[i * 3 + 0] = r0; a.base[i * 3 + 1] = r1; a.base[i * 3 + 2] = r2; }
-            for (int w = 0; w < a.wpi; ++w) {
-                const int32_t *n = a.wcnt + ((size_t)i * a.wpi + w) * 3;
-                r0 += n[0]; r1 += n[1]; r2 += n[2];
+    const int32_t *__restrict__ wcnt = a.wcnt;
+    const int wpi = a.wpi;
+    // Cells in rounds of SCAN_U per thread, every load of a round issued before
+    // any store, so that one memory round trip serves SCAN_U cells.
+    constexpr int SCAN_U = 4;
+    for (int c0 = threadIdx.x; c0 < M; c0 += SCAN_U * blockDim.x) {
+        int r[SCAN_U][3], lo[SCAN_U], hi[SCAN_U];
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const int c = min(c0 + u * (int)blockDim.x, M - 1);
+            lo[u] = one_each ? c : it.cell_first[c];
+            hi[u] = one_each ? c + 1 : it.cell_first[c + 1];
+            r[u][0] = r[u][1] = r[u][2] = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u)
+            for (int i = lo[u]; i < hi[u]; ++i)
+                for (int w = 0; w < wpi; ++w) {
+                    const int32_t *n = wcnt + ((size_t)i * wpi + w) * 3;
+                    r[u][0] += n[0]; r[u][1] += n[1]; r[u][2] += n[2];
+                }
+#pragma unroll
+        for (int u = 0; u < SCAN_U; ++u) {
+            const int c = c0 + u * (int)blockDim.x;
+            if (c < M) { tot[c * 3 + 0] = r[u][0]; tot[c * 3 + 1] = r[u][1]; tot[c * 3 + 2] = r[u][2]; }
+        }
+        if (!one_each) {   // exclusive prefix of each item within its cell
+#pragma unroll
+            for (int u = 0; u < SCAN_U; ++u) {
+                if (c0 + u * (int)blockDim.x >= M) continue;
+                int q0 = 0, q1 = 0, q2 = 0;
+                for (int i = lo[u]; i < hi[u]; ++i) {
+                    a.base[i * 3 + 0] = q0; a.base[i * 3 + 1] = q1; a.base[i * 3 + 2] = q2;
+                    for (int w = 0; w < wpi; ++w) {
+                        const int32_t *n = wcnt + ((size_t)i * wpi + w) * 3;
+                        q0 += n[0]; q1 += n[1]; q2 += n[2];
+                    }
+                }
             }
         }
-        tot[c * 3 + 0] = r0; tot[c * 3 + 1] = r1; tot[c * 3 + 2] = r2;
     }
     __syncthreads();
     // new counts: right-movers of c-1, stayers of c, left-movers of c+1
@@ -678,23 +707,13 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     __syncthreads();
     scan_cells(ncount, nstart, M, lds);
     __syncthreads();
-    // destination bases of each item's three groups
+    // destination of each cell's first mover of each kind (an item adds its
+    // prefix within the cell, a wave its prefix within the item)
     for (int c = threadIdx.x; c < M; c += blockDim.x) {
         const int cm = imod(c - 1, M), cp = imod(c + 1, M), cmm = imod(c - 2, M);
-        const int bL = nstart[cm] + tot[cmm * 3 + 2] + tot[cm * 3 + 1];
-        const int bS = nstart[c] + tot[cm * 3 + 2];
-        const int bR = nstart[cp];
-        if (one_each) {   // the item's prefix within its cell is zero
-            a.base[c * 3 + 0] = bL;
-            a.base[c * 3 + 1] = bS;
-            a.base[c * 3 + 2] = bR;
-        } else {
-            for (int i = it.cell_first[c]; i < it.cell_first[c + 1]; ++i) {
-                a.base[i * 3 + 0] += bL;
-                a.base[i * 3 + 1] += bS;
-                a.base[i * 3 + 2] += bR;
-            }
-        }
+        a.cbase[c * 3 + 0] = nstart[cm] + tot[cmm * 3 + 2] + tot[cm * 3 + 1];
+        a.cbase[c * 3 + 1] = nstart[c] + tot[cm * 3 + 2];
+        a.cbase[c * 3 + 2] = nstart[cp];
     }
     __syncthreads();
     const int n_next = build_items(ncount, nstart, M, a.chunk, a.N, a.items_next, lds);
@@ -737,11 +756,12 @@ template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
     // item count, status words and item description in one memory round trip
-    const int n_items = *a.items.n_items;
+    const int n_items = a.items.n_items[0], one_each = a.items.n_items[1];
     const int sgate = a.st->gate, sflags = a.st->flags, skconv = a.st->kconv;
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
-    asm volatile("" ::"s"(n_items), "s"(sgate), "s"(sflags), "s"(skconv), "s"(c), "s"(beg), "s"(end));
+    asm volatile("" ::"s"(n_items), "s"(one_each), "s"(sgate), "s"(sflags), "s"(skconv), "s"(c), "s"(beg),
+                 "s"(end));
     if (item >= n_items) return;
     if (!(sgate && skconv >= 0 && sflags == 0)) return;   // the commit runs on a converged, unflagged substep
     const CommitPick pk = commit_pick(a, skconv);
@@ -752,8 +772,12 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
     wave_range(beg, end, wid, nw, wb, we);
     stage_records<P, double>(rec, a.coefA, pk.coefE, c);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    const int32_t *bs = a.base + (size_t)item * 3;
-    int run0 = bs[0], run1 = bs[1], run2 = bs[2];
+    const int32_t *cb = a.cbase + (size_t)c * 3;
+    int run0 = cb[0], run1 = cb[1], run2 = cb[2];
+    if (!one_each) {   // movers of the cell's earlier items
+        const int32_t *bs = a.base + (size_t)item * 3;
+        run0 += bs[0]; run1 += bs[1]; run2 += bs[2];
+    }
     for (int w = 0; w < wid; ++w) {   // movers of the item's earlier waves
         const int32_t *n = a.wcnt + ((size_t)item * nw + w) * 3;
         run0 += n[0]; run1 += n[1]; run2 += n[2];
