@@ -99,12 +99,24 @@ __device__ __forceinline__ double block_sum_slot(const double (&v)[NV], double *
     return out;
 }
 
-// Max and OR over the block; result valid in thread 0.
+// OR over the wave of flag words of the low NB bits, one ballot per bit (no
+// cross-lane data movement).  All lanes must be active.
+template <int NB = 3>
+__device__ __forceinline__ int wave_or_bits(int v) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        if (__builtin_amdgcn_ballot_w64((v >> b) & 1)) r |= 1 << b;
+    return r;
+}
+
+// Max and OR (of flag bits) over the block; result valid in thread 0.  All
+// lanes must be active.
 __device__ __forceinline__ void block_max_or(double &m, int &f, double *ldsd, int *ldsi) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = (blockDim.x + WAVE - 1) / WAVE;
-    m = wave_max(m);
-    f = wave_or(f);
+    m = wave_max_dpp(m);
+    f = wave_or_bits(f);
     if (lane == 0) { ldsd[wid] = m; ldsi[wid] = f; }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -551,9 +551,9 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
             for (int i = 0; i < P; ++i) store_record(Eout, M, j, RecE<P>::N, i, r[i]);
         }
     }
-    re = wave_max(re);
-    rx = wave_max(rx);
-    flags = wave_or(flags);
+    re = wave_max_dpp(re);
+    rx = wave_max_dpp(rx);
+    flags = wave_or_bits(flags);
     {
         const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
         if (lane == 0) { ldsm[wid] = re; ldsx[wid] = rx; ldsf[wid] = flags; }

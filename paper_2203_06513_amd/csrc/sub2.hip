@@ -323,7 +323,6 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
         if (stI) init_status(stI, gate_src);
         if (stII) init_status(stII, nullptr);
     }
-    if (!go) return;
     const int j0 = blockIdx.x * FIELD2_OUT;
     const int mhi = mlo + ntaps - 1;
     const int len = FIELD2_OUT + ntaps - 1;
@@ -344,6 +343,8 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
             Rz[idx] = sz;
         }
     }
+    // (the loads above do not depend on the gate; nothing is written before it)
+    if (!go) return;
     {
         const int c = j0 + (int)threadIdx.x;
         if ((int)threadIdx.x < FIELD2_OUT && c < M) {
