@@ -25,21 +25,6 @@ __device__ __forceinline__ float wave_sumf(float v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
     return v;
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
-}
-__device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, WAVE);
-    return v;
-}
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
 
 // Cross-lane moves by DPP (no LDS).  Rows disabled by ROWMASK read as 0.
 template <int CTRL, int ROWMASK = 0xf>

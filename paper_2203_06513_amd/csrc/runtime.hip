@@ -26,7 +26,6 @@ namespace ecpic {
 void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a);
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a);
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a);
-void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s);
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a);
 void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, const double *az,

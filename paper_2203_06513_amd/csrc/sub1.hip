@@ -851,7 +851,6 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
     commit_scatter_item<P, RECORD>(a, blockIdx.x);
 }
 
-__global__ void k_begin(DevStatus *st, const DevStatus *gate) { init_status(st, gate); }
 
 // ---- launchers ------------------------------------------------------------
 void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a) {
@@ -902,9 +901,6 @@ void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArg
 #undef ECPIC_C
 }
 
-void launch_begin(DevStatus *st, const DevStatus *gate, hipStream_t s) {
-    launch_k(k_begin, dim3(1), dim3(1), 0, s, st, gate);
-}
 
 
 }  // namespace ecpic
