@@ -127,6 +127,8 @@ __device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate
     st->committed = 0;
     st->flags = 0;
     st->fp32_sweeps = 0;
+    st->scan_ticket = 0;
+    st->scan_multi = 0;
     st->res = 0.0;
     st->gate = gate_src ? (gate_src->committed && gate_src->flags == 0) : 1;
 }
@@ -140,14 +142,19 @@ __device__ __forceinline__ void store_padded(double *f, int M, int j, double v) 
     }
 }
 
+// j mod M in [0, M); one compare and add for j in [-M, 2M), a division only
+// beyond (an integer division is tens of instructions).
 __device__ __forceinline__ int imod(int j, int M) {
-    int r = j % M;
+    const int w = j < 0 ? j + M : (j >= M ? j - M : j);
+    if (w >= 0 && w < M) return w;
+    const int r = j % M;
     return r < 0 ? r + M : r;
 }
 
 // Exclusive scan of one int per thread over a block of blockDim.x <= 1024
-// threads; returns the exclusive prefix, *total gets the block sum.
-__device__ __forceinline__ int block_exscan(int v, int *lds /* >= 32 */, int *total) {
+// threads; returns the exclusive prefix, *total gets the block sum.  Each wave
+// scans its values, then every thread adds the wave totals before its own.
+__device__ __forceinline__ int block_exscan(int v, int *lds /* >= 16 */, int *total) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = (blockDim.x + WAVE - 1) / WAVE;
     int x = v;
@@ -158,21 +165,31 @@ __device__ __forceinline__ int block_exscan(int v, int *lds /* >= 32 */, int *to
     }
     if (lane == WAVE - 1) lds[wid] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int w = 0; w < nw; ++w) { int t = lds[w]; lds[w] = acc; acc += t; }
-        lds[nw] = acc;
+    int pre = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < 1024 / WAVE; ++w) {
+        const int t = w < nw ? lds[w] : 0;
+        pre += w < wid ? t : 0;
+        sum += t;
     }
-    __syncthreads();
-    int res = lds[wid] + x - v;
-    *total = lds[nw];
-    __syncthreads();
-    return res;
+    *total = sum;
+    __syncthreads();   // lds may be reused after the return
+    return pre + x - v;
 }
 
-// Build an item list from per-cell counts (single block).  start[c] must hold
-// the exclusive scan of counts, start[M] = N.
-// Returns the item count (in every thread).
+// Neighbours of cell c in [0, M) on the periodic grid (no division).
+__device__ __forceinline__ int cell_prev(int c, int M) { return c == 0 ? M - 1 : c - 1; }
+__device__ __forceinline__ int cell_next(int c, int M) { return c == M - 1 ? 0 : c + 1; }
+
+// Items of a cell of n particles: ceil(n / chunk), 0 for an empty cell.
+__device__ __forceinline__ int items_of(int n, int chunk) {
+    return n <= chunk ? (n > 0 ? 1 : 0) : (n + chunk - 1) / chunk;
+}
+
+// Build an item list from per-cell counts (single block): cell c gets
+// ceil(count[c] / chunk) items of near-equal size.  start[c] must hold the
+// exclusive scan of counts, start[M] = N.  Returns the item count (in every
+// thread).
 __device__ inline int build_items(const int32_t *count, const int32_t *start, int M, int chunk, int64_t N,
                                   ItemList out, int *lds) {
     // items per cell, exclusive scan -> cell_first
@@ -180,7 +197,7 @@ __device__ inline int build_items(const int32_t *count, const int32_t *start, in
     const int c0 = threadIdx.x * per;
     int local = 0, one_each = 1;
     for (int c = c0; c < c0 + per && c < M; ++c) {
-        const int ni = (count[c] + chunk - 1) / chunk;
+        const int ni = items_of(count[c], chunk);
         local += ni;
         one_each &= ni == 1;
     }
@@ -189,9 +206,13 @@ __device__ inline int build_items(const int32_t *count, const int32_t *start, in
     int off = block_exscan(local, lds, &total);
     for (int c = c0; c < c0 + per && c < M; ++c) {
         const int n = count[c];
-        const int ni = (n + chunk - 1) / chunk;
+        const int ni = items_of(n, chunk);
         out.cell_first[c] = off;
-        for (int q = 0; q < ni; ++q) {
+        if (ni > 0) {
+            out.cell[off] = c;
+            out.begin[off] = start[c];
+        }
+        for (int q = 1; q < ni; ++q) {
             out.cell[off + q] = c;
             out.begin[off + q] = start[c] + (int)(((int64_t)n * q) / ni);
         }

@@ -44,6 +44,8 @@ struct DevStatus {
     int32_t gate;                    // substep allowed to run (Subsystem II waits on I)
     int32_t fp32_sweeps;             // sweeps done in FP32 (precision form)
     int32_t n_items_next;            // item count of the re-sorted particles (Subsystem I commit)
+    int32_t scan_ticket;             // blocks of the commit scan done (the last one resets it)
+    int32_t scan_multi;              // the new order has a cell with other than one item
     double res;                      // residual of sweep kconv (length / field units)
     double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
@@ -132,17 +134,15 @@ struct CommitIArgs {
     double *ex_next;               // padded e_x^{n+1}
     DevStatus *stII;               // reset here, gated on this commit (null: leave it)
     const int32_t *wcnt;           // per-wave mover counts of the converged sweep (see SweepIArgs)
-    int32_t *tot;                  // [M][3]
     int32_t *base;                 // [max_items][3] each item's movers of each kind before it in its cell
                                    // (written only when some cell has several items)
     int32_t *cbase;                // [M][3] destination of each cell's first mover of each kind
-    int32_t *nstart;               // [2M + 1]
+    int32_t *nstart;               // [2M + 1]: new start of each cell, N, new count of each cell
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
-    int32_t scan_in_lds;           // the scan keeps tot / nstart / counts in LDS (5 M + 1 ints <= 64 KiB)
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     int64_t N;
 };

@@ -204,7 +204,7 @@ struct ecpic_ctx {
     ItemList items[2]{};
     int icur = 0;
     int n_items_host = 0;
-    int32_t *wcnt = nullptr, *tot = nullptr, *base = nullptr, *cbase = nullptr, *nstart = nullptr;
+    int32_t *wcnt = nullptr, *base = nullptr, *cbase = nullptr, *nstart = nullptr;
     double *part = nullptr;
 
     // padded fields: [0]/[1] = current / next (swapped on commit)
@@ -393,7 +393,6 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.ex_next = c->ex[c->exc ^ 1];
     a.stII = c->stII;
     a.wcnt = c->wcnt;
-    a.tot = c->tot;
     a.base = c->base;
     a.cbase = c->cbase;
     a.nstart = c->nstart;
@@ -409,7 +408,6 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
     a.first64 = (c->ws_on ? 1 : 0) + c->k32;
-    a.scan_in_lds = (5 * (size_t)c->M + 1) * sizeof(int32_t) <= 65536;
     if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
         a.rec.feat = c->ws_feat;
         a.rec.targ = c->ws_targ;
@@ -607,7 +605,7 @@ void free_all(ecpic_ctx *c) {
         F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
-    F(c->wcnt); F(c->tot); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
+    F(c->wcnt); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
@@ -634,7 +632,6 @@ int alloc_all(ecpic_ctx *c) {
         rc |= dalloc(&c->ay[b], MP); rc |= dalloc(&c->az[b], MP);
         rc |= dalloc(&c->ek[b], MP); rc |= dalloc(&c->eyk[b], MP); rc |= dalloc(&c->ezk[b], MP);
     }
-    rc |= dalloc(&c->tot, (size_t)M * 3);
     rc |= dalloc(&c->base, (size_t)c->max_items * 3);
     rc |= dalloc(&c->cbase, (size_t)c->M * 3);
     rc |= dalloc(&c->wcnt, (size_t)c->max_items * (c->block / 64) * 3);
@@ -667,7 +664,8 @@ int alloc_all(ecpic_ctx *c) {
             launch_pad(c->stream, nullptr, f, 0.0, M);
     }
     HIPCHK(hipMemsetAsync(c->count, 0, sizeof(int32_t) * M, c->stream));
-    launch_items_from_counts(c->stream, c->count, c->nstart, M, c->chunk, 0, c->items[0]);
+    for (int b = 0; b < 2; ++b)   // both lists valid (empty) from the start
+        launch_items_from_counts(c->stream, c->count, c->nstart, M, c->chunk, 0, c->items[b]);
     HIPCHK(hipMemsetAsync(c->st_ring, 0, sizeof(DevStatus) * 2 * STEP_BATCH, c->stream));
     // closed-form rows and inverse taps
     c->m0row = mass_row(c->P);

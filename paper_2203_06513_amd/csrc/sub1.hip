@@ -628,17 +628,106 @@ __device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first
     return prev_converged(st, nsweeps, first64, dx, tol, writer) ? nsweeps - 1 : -1;
 }
 
-// Single block: settles the convergence test, then from the mover counts the
-// converged sweep left computes the destinations of every item's left / stay /
-// right movers, the item list of the new order and e_x^{n+1}.
+// The commit's destinations need no scan over the cells.  A particle moves at
+// most one cell, so the particles that end in cells [0, c) are those that
+// started there, plus the left-movers of cell c and the right-movers of cell
+// M-1 (periodic), minus the right-movers of cell c-1 and the left-movers of
+// cell 0:
+//   nstart[c] = start[c] + L_c - R_{c-1} + R_{M-1} - L_0,   nstart[0] = 0,
+// with start[c] the first particle of cell c in the current order and L, S, R
+// a cell's left-movers, stayers and right-movers.  Each cell's value (and its
+// new count R_{c-1} + S_c + L_{c+1}) is local, so the commit scan runs one
+// cell per thread over many blocks; only an item list with other than one item
+// per cell needs a prefix over the cells, built by the last block to finish.
+constexpr int SCAN_CELLS = 256;   // cells (threads) per block
+
+// L, S, R of cell c and its first particle in the current order; with several
+// items in the cell, base gets each item's movers before it in the cell.
+__device__ __forceinline__ void cell_movers(const CommitIArgs &a, bool one_each, int c, bool write_base,
+                                            int (&t)[3], int &start) {
+    const int wpi = a.wpi;
+    if (one_each) {   // item c is cell c: no dependent load
+        start = a.items.begin[c];
+        int n[MAX_WAVES][3];
+#pragma unroll
+        for (int w = 0; w < MAX_WAVES; ++w) {
+            const int32_t *q = a.wcnt + (size_t)(c * wpi + min(w, wpi - 1)) * 3;
+            n[w][0] = q[0]; n[w][1] = q[1]; n[w][2] = q[2];
+        }
+        t[0] = t[1] = t[2] = 0;
+#pragma unroll
+        for (int w = 0; w < MAX_WAVES; ++w)
+            if (w < wpi) { t[0] += n[w][0]; t[1] += n[w][1]; t[2] += n[w][2]; }
+        return;
+    }
+    const int lo = a.items.cell_first[c], hi = a.items.cell_first[c + 1];
+    start = a.items.begin[lo];   // an empty cell starts where the next item does
+    t[0] = t[1] = t[2] = 0;
+    for (int i = lo; i < hi; ++i) {
+        if (write_base) { a.base[i * 3 + 0] = t[0]; a.base[i * 3 + 1] = t[1]; a.base[i * 3 + 2] = t[2]; }
+        for (int w = 0; w < wpi; ++w) {
+            const int32_t *q = a.wcnt + ((size_t)i * wpi + w) * 3;
+            t[0] += q[0]; t[1] += q[1]; t[2] += q[2];
+        }
+    }
+}
+
+// Settles the convergence test (block 0 records it) and resets the Subsystem
+// II status; then, for the cells of this block: e_x^{n+1}, the destinations of
+// each cell's first mover of each kind (an item adds its prefix within the
+// cell, a wave its prefix within the item), the new counts and starts, and the
+// entries of the new item list if it has one item per cell.  The last block
+// to finish completes the list (or builds it whole when some cell has other
+// than one item) and marks the substep committed.
 template <int P>
-__global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
-    extern __shared__ int32_t scan_lds[];   // tot, ncount, nstart when they fit (else global scratch)
-    __shared__ int lds[40];
-    __shared__ int kcs;
-    if (threadIdx.x == 0) {
-        kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, true);
-        if (a.stII) {   // Subsystem II may run only after this commit
+__global__ void __launch_bounds__(SCAN_CELLS) k_commit_scan(CommitIArgs a) {
+    __shared__ int tl[SCAN_CELLS + 3][3];   // L, S, R of cells b0-2 .. b0+SCAN_CELLS (mod M)
+    __shared__ int sl[SCAN_CELLS + 2];      // current start of cells b0-1 .. b0+SCAN_CELLS (mod M)
+    __shared__ int ends[2][3];              // L, S, R of cells 0 and M-1
+    __shared__ int lds[16];
+    __shared__ int kcs, lastb;
+    const int M = a.M;
+    const int b0 = blockIdx.x * SCAN_CELLS, t = threadIdx.x;
+    const int c = b0 + t;
+    const bool live = c < M;
+    const bool one_each = a.items.n_items[1] != 0;
+    const int nex = M + 2 * HALO, nstride = gridDim.x * SCAN_CELLS;
+    // the movers and starts of this block's cells and of its halo cells b0-2,
+    // b0-1, b0+SCAN_CELLS and the end cells 0, M-1, into LDS
+    auto load_movers = [&]() {
+        int tm[3], sm;
+        cell_movers(a, one_each, live ? c : M - 1, live, tm, sm);
+        tl[t + 2][0] = tm[0]; tl[t + 2][1] = tm[1]; tl[t + 2][2] = tm[2];
+        sl[t + 1] = sm;
+        if (t < 5) {
+            const int hc = t == 0 ? imod(b0 - 2, M)
+                         : t == 1 ? imod(b0 - 1, M)
+                         : t == 2 ? imod(b0 + SCAN_CELLS, M)
+                         : t == 3 ? 0 : M - 1;
+            int th[3], sh;
+            cell_movers(a, one_each, hc, false, th, sh);
+            int *dst = t == 0 ? tl[0] : t == 1 ? tl[1] : t == 2 ? tl[SCAN_CELLS + 2] : ends[t - 3];
+            dst[0] = th[0]; dst[1] = th[1]; dst[2] = th[2];
+            if (t == 1) sl[0] = sh;
+            if (t == 2) sl[SCAN_CELLS + 1] = sh;
+        }
+    };
+    // loads first: both candidates for e_x^{n+1} (which one is e^(kc+1)
+    // depends only on the parity of kc) and, with one item per cell, the
+    // movers, whose addresses depend on the cell index only.  A list with
+    // several items per cell is followed only once the test has passed: the
+    // list of a substep that will not commit may be one no commit has written.
+    double e0[2], e1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int idx = min(c + u * nstride, nex - 1);
+        e0[u] = a.ek0[idx];
+        e1[u] = a.ek1[idx];
+    }
+    if (one_each) load_movers();
+    if (t == 0) {
+        kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, blockIdx.x == 0);
+        if (a.stII && blockIdx.x == 0) {   // Subsystem II may run only after this commit
             init_status(a.stII, nullptr);
             a.stII->gate = kcs >= 0 ? 1 : 0;
         }
@@ -646,79 +735,71 @@ __global__ void __launch_bounds__(1024) k_commit_scan(CommitIArgs a) {
     __syncthreads();
     const int kc = kcs;
     if (kc < 0) return;
-    const int M = a.M;
-    const ItemList &it = a.items;
-    {   // e_x^{n+1}
-        const CommitPick pk = commit_pick(a, kc);
-        for (int idx = threadIdx.x; idx < M + 2 * HALO; idx += blockDim.x) a.ex_next[idx] = pk.enew[idx];
+    if (!one_each) {
+        load_movers();
+        __syncthreads();
     }
-    const bool in_lds = a.scan_in_lds != 0;
-    int32_t *tot = in_lds ? scan_lds : a.tot;
-    int32_t *nstart = in_lds ? scan_lds + 3 * M : a.nstart;
-    int32_t *ncount = nstart + (M + 1);
-    // totals per old cell and exclusive prefix of each item within its cell
-    // (with one item per cell, item c is cell c: no dependent load)
-    const bool one_each = it.n_items[1] != 0;
-    const int32_t *__restrict__ wcnt = a.wcnt;
-    const int wpi = a.wpi;
-    // Cells in rounds of SCAN_U per thread, every load of a round issued before
-    // any store, so that one memory round trip serves SCAN_U cells.
-    constexpr int SCAN_U = 4;
-    for (int c0 = threadIdx.x; c0 < M; c0 += SCAN_U * blockDim.x) {
-        int r[SCAN_U][3], lo[SCAN_U], hi[SCAN_U];
+    {   // e_x^{n+1} = e^(kc+1)
+        const bool odd = ((kc + 1) & 1) != 0;
 #pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) {
-            const int c = min(c0 + u * (int)blockDim.x, M - 1);
-            lo[u] = one_each ? c : it.cell_first[c];
-            hi[u] = one_each ? c + 1 : it.cell_first[c + 1];
-            r[u][0] = r[u][1] = r[u][2] = 0;
+        for (int u = 0; u < 2; ++u) {
+            const int idx = c + u * nstride;
+            if (idx < nex) a.ex_next[idx] = odd ? e1[u] : e0[u];
         }
-#pragma unroll
-        for (int u = 0; u < SCAN_U; ++u)
-            for (int i = lo[u]; i < hi[u]; ++i)
-                for (int w = 0; w < wpi; ++w) {
-                    const int32_t *n = wcnt + ((size_t)i * wpi + w) * 3;
-                    r[u][0] += n[0]; r[u][1] += n[1]; r[u][2] += n[2];
-                }
-#pragma unroll
-        for (int u = 0; u < SCAN_U; ++u) {
-            const int c = c0 + u * (int)blockDim.x;
-            if (c < M) { tot[c * 3 + 0] = r[u][0]; tot[c * 3 + 1] = r[u][1]; tot[c * 3 + 2] = r[u][2]; }
+        const double *enew = odd ? a.ek1 : a.ek0;
+        for (int idx = c + 2 * nstride; idx < nex; idx += nstride) a.ex_next[idx] = enew[idx];
+    }
+    // new start of cell b0 + q (mod M), q in [-1, SCAN_CELLS]: slots q + 1 of
+    // sl and q + 2 of tl (L of the cell), q + 1 of tl (R of the cell before)
+    const int wrap = ends[1][2] - ends[0][0];   // R_{M-1} - L_0
+    auto nstart_of = [&](int q) {
+        const int cq = b0 + q;
+        return (cq == 0 || cq == M) ? 0 : sl[q + 1] + tl[q + 2][0] - tl[q + 1][2] + wrap;
+    };
+    int notone = 0;
+    if (live) {
+        const int ns = nstart_of(t), nsm = nstart_of(t - 1), nsp = nstart_of(t + 1);
+        const int Rm = tl[t + 1][2], Sm = tl[t + 1][1], Rmm = tl[t][2];
+        const int Lp = c == M - 1 ? ends[0][0] : tl[t + 3][0];
+        const int cnt = Rm + tl[t + 2][1] + Lp;   // R_{c-1} + S_c + L_{c+1}
+        a.cbase[c * 3 + 0] = nsm + Rmm + Sm;      // left-movers: after R_{c-2} and S_{c-1} in cell c-1
+        a.cbase[c * 3 + 1] = ns + Rm;             // stayers: after R_{c-1}
+        a.cbase[c * 3 + 2] = nsp;                 // right-movers: first in cell c+1
+        int32_t *ncount = a.nstart + (M + 1);
+        a.nstart[c] = ns;
+        ncount[c] = cnt;
+        notone = items_of(cnt, a.chunk) != 1;
+        a.items_next.cell[c] = c;                 // the list if every cell has one item
+        a.items_next.begin[c] = ns;
+        a.items_next.cell_first[c] = c;
+    }
+    // this block's writes are made visible device-wide before it takes its
+    // ticket; the last block sees every block's (fence after the ticket)
+    __threadfence();
+    notone = __syncthreads_or(notone);
+    if (t == 0) {
+        if (notone) {
+            atomicOr(&a.st->scan_multi, 1);
+            __threadfence();
         }
-        if (!one_each) {   // exclusive prefix of each item within its cell
-#pragma unroll
-            for (int u = 0; u < SCAN_U; ++u) {
-                if (c0 + u * (int)blockDim.x >= M) continue;
-                int q0 = 0, q1 = 0, q2 = 0;
-                for (int i = lo[u]; i < hi[u]; ++i) {
-                    a.base[i * 3 + 0] = q0; a.base[i * 3 + 1] = q1; a.base[i * 3 + 2] = q2;
-                    for (int w = 0; w < wpi; ++w) {
-                        const int32_t *n = wcnt + ((size_t)i * wpi + w) * 3;
-                        q0 += n[0]; q1 += n[1]; q2 += n[2];
-                    }
-                }
-            }
-        }
+        lastb = atomicAdd(&a.st->scan_ticket, 1) == (int)gridDim.x - 1;
     }
     __syncthreads();
-    // new counts: right-movers of c-1, stayers of c, left-movers of c+1
-    for (int c = threadIdx.x; c < M; c += blockDim.x)
-        ncount[c] = tot[imod(c - 1, M) * 3 + 2] + tot[c * 3 + 1] + tot[imod(c + 1, M) * 3 + 0];
-    __syncthreads();
-    scan_cells(ncount, nstart, M, lds);
-    __syncthreads();
-    // destination of each cell's first mover of each kind (an item adds its
-    // prefix within the cell, a wave its prefix within the item)
-    for (int c = threadIdx.x; c < M; c += blockDim.x) {
-        const int cm = imod(c - 1, M), cp = imod(c + 1, M), cmm = imod(c - 2, M);
-        a.cbase[c * 3 + 0] = nstart[cm] + tot[cmm * 3 + 2] + tot[cm * 3 + 1];
-        a.cbase[c * 3 + 1] = nstart[c] + tot[cm * 3 + 2];
-        a.cbase[c * 3 + 2] = nstart[cp];
+    if (!lastb) return;
+    __threadfence();
+    int n_next = M;
+    if (atomicOr(&a.st->scan_multi, 0)) {
+        n_next = build_items(a.nstart + (M + 1), a.nstart, M, a.chunk, a.N, a.items_next, lds);
+    } else if (t == 0) {
+        a.items_next.cell_first[M] = M;
+        a.items_next.begin[M] = (int)a.N;
+        a.items_next.n_items[0] = M;
+        a.items_next.n_items[1] = 1;
     }
-    __syncthreads();
-    const int n_next = build_items(ncount, nstart, M, a.chunk, a.N, a.items_next, lds);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         a.st->n_items_next = n_next;
+        a.st->scan_ticket = 0;
+        a.st->scan_multi = 0;
         a.st->committed = 1;
     }
 }
@@ -888,10 +969,10 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
-    const size_t lds = a.scan_in_lds ? sizeof(int32_t) * (5 * (size_t)a.M + 1) : 0;
+    const int gscan = (a.M + SCAN_CELLS - 1) / SCAN_CELLS;
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
-        launch_k((k_commit_scan<PP>), dim3(1), dim3(1024), lds, s, a);                 \
+        launch_k((k_commit_scan<PP>), dim3(gscan), dim3(SCAN_CELLS), 0, s, a);         \
         if (a.rec.stride > 0)                                                                    \
             launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
         else                                                                                     \
