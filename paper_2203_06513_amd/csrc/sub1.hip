@@ -459,6 +459,41 @@ __device__ __forceinline__ void cell_partials_I(const ItemList &it, bool one_eac
     }
 }
 
+// cell_partials_I with one item per cell and WPI waves per item: unit c * WPI + w,
+// all loads issued before any is used.
+template <int P, int WPI>
+__device__ __forceinline__ void cell_partials_one(const double *part, int c, double (&v)[P + 2], double &rx,
+                                                  int &flags) {
+    constexpr int N = UnitI<P>::N;
+    double u[WPI][N];
+#pragma unroll
+    for (int w = 0; w < WPI; ++w)
+#pragma unroll
+        for (int q = 0; q < N; ++q) u[w][q] = part[((size_t)c * WPI + w) * N + q];
+#pragma unroll
+    for (int q = 0; q < P + 2; ++q) {
+        v[q] = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPI; ++w) v[q] += u[w][q];
+    }
+#pragma unroll
+    for (int w = 0; w < WPI; ++w) {
+        rx = fmax(rx, u[w][P + 2]);
+        flags |= (int)u[w][P + 3];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void cell_partials_one(const double *part, int c, int wpi, double (&v)[P + 2],
+                                                  double &rx, int &flags) {
+    switch (wpi) {
+        case 1: cell_partials_one<P, 1>(part, c, v, rx, flags); break;
+        case 2: cell_partials_one<P, 2>(part, c, v, rx, flags); break;
+        case 3: cell_partials_one<P, 3>(part, c, v, rx, flags); break;
+        default: cell_partials_one<P, 4>(part, c, v, rx, flags); break;
+    }
+}
+
 // Field update of sweep k and the E-records of the next ebar.  Block b
 // computes e^(k+1) on the FIELD_OUT cells starting at b * TILE - (P - 1) (the
 // first P - 1 only to form the records of cells b * TILE .. b * TILE + TILE - 1).
@@ -491,19 +526,42 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     double *enl = tp + a.ntaps;
     double *enw = enl + FIELD_OUT;   // e_x^n on the block's cells
     const double *ek = k == 0 ? a.en : ((k & 1) ? a.ek1 : a.ek0);
-    // loads that do not depend on the partials: this quad's output cell
+    // One memory round trip before the status test: this quad's output cell,
+    // the first taps, e_x^n on the block's cells and the first round of
+    // partials, loaded as if item c were cell c (in bounds whatever the list
+    // holds) and kept if it is (a list with several items per cell is followed
+    // only after the test).  The empty asm keeps the loads above the branch.
     const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
     const int jq = j0 + quad, jqm = imod(jq, M);
+    const int t0 = threadIdx.x;
     const double en_q = a.en[jqm + HALO];
     const double ek_q = ek[jqm + HALO];
-    for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
-    if (threadIdx.x < FIELD_OUT) enw[threadIdx.x] = a.en[imod(j0 + (int)threadIdx.x, M) + HALO];
+    const double tap0 = a.taps[min(t0, a.ntaps - 1)];
+    const double enw0 = a.en[imod(j0 + min(t0, FIELD_OUT - 1), M) + HALO];
+    double rx0 = 0.0, v0[NS];
+    int fl0 = 0;
+    cell_partials_one<P>(a.part, imod(clo + min(t0, clen - 1), M), a.wpi, v0, rx0, fl0);
+    asm volatile("" ::"v"(en_q), "v"(ek_q), "v"(tap0), "v"(enw0), "v"(rx0), "v"(fl0));
+#pragma unroll
+    for (int q = 0; q < NS; ++q) asm volatile("" ::"v"(v0[q]));
     if (!sgate | sflags | (skconv >= 0)) return;
+    if (t0 < a.ntaps) tp[t0] = tap0;
+    for (int t = t0 + blockDim.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
+    if (t0 < FIELD_OUT) enw[t0] = enw0;
     double rx = 0.0;
     int flags = 0;
+    if (one_each && t0 < clen) {
+        rx = rx0;
+        flags = fl0;
+    }
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         double v[NS];
-        cell_partials_I<P>(a.items, one_each, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
+        if (one_each && t == t0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) v[q] = v0[q];
+        } else {
+            cell_partials_I<P>(a.items, one_each, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
+        }
 #pragma unroll
         for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
     }
@@ -520,15 +578,18 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     double re = 0.0;
     {
         // S_{j - m} for m = mlo + i sits at S[quad + mhi - m] = S[quad + ntaps - 1 - i]
+        // (four chains per lane, so that several LDS reads are in flight)
         const double *Sq = S + quad + a.ntaps - 1;
-        double acc0 = 0.0, acc1 = 0.0;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
         int i = ql;
-        for (; i + 4 < a.ntaps; i += 8) {
+        for (; i + 12 < a.ntaps; i += 16) {
             acc0 = fma(tp[i], Sq[-i], acc0);
             acc1 = fma(tp[i + 4], Sq[-i - 4], acc1);
+            acc2 = fma(tp[i + 8], Sq[-i - 8], acc2);
+            acc3 = fma(tp[i + 12], Sq[-i - 12], acc3);
         }
-        if (i < a.ntaps) acc0 = fma(tp[i], Sq[-i], acc0);
-        double conv = acc0 + acc1;
+        for (; i < a.ntaps; i += 4) acc0 = fma(tp[i], Sq[-i], acc0);
+        double conv = (acc0 + acc1) + (acc2 + acc3);
         conv += dpp_d<0xB1>(conv);   // quad_perm [1,0,3,2]
         conv += dpp_d<0x4E>(conv);   // quad_perm [2,3,0,1]
         const double enew = en_q - a.w * conv;

@@ -160,6 +160,33 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
 // (every fourth tap each, combined in a fixed order).
 constexpr int FIELD2_OUT = 64;
 
+// Sum over the WPI wave partials of cell c when item c is cell c, all loads
+// issued before any is used.
+template <int NS, int WPI>
+__device__ __forceinline__ void cell_partials_one2(const double *part, int c, double (&v)[NS]) {
+    double u[WPI][NS];
+#pragma unroll
+    for (int w = 0; w < WPI; ++w)
+#pragma unroll
+        for (int q = 0; q < NS; ++q) u[w][q] = part[((size_t)c * WPI + w) * NS + q];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        v[q] = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPI; ++w) v[q] += u[w][q];
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ void cell_partials_one2(const double *part, int c, int wpi, double (&v)[NS]) {
+    switch (wpi) {
+        case 1: cell_partials_one2<NS, 1>(part, c, v); break;
+        case 2: cell_partials_one2<NS, 2>(part, c, v); break;
+        case 3: cell_partials_one2<NS, 3>(part, c, v); break;
+        default: cell_partials_one2<NS, 4>(part, c, v); break;
+    }
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     extern __shared__ double smem[];
@@ -188,20 +215,40 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     double *baz = bay + FIELD2_OUT;
     const double *eyk = k == 0 ? a.eyn : ((k & 1) ? a.ey1 : a.ey0);
     const double *ezk = k == 0 ? a.ezn : ((k & 1) ? a.ez1 : a.ez0);
+    // One memory round trip before the status test: this quad's output cell,
+    // the first taps, a^n and e^n on the block's cells and the first round of
+    // partials, loaded as if item c were cell c (in bounds whatever the list
+    // holds) and kept if it is (a list with several items per cell is followed
+    // only after the test).  The empty asm keeps the loads above the branch.
     const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
     const int jq = j0 + quad, jqm = imod(jq, M);
+    const int t0 = threadIdx.x;
     const double E0y_q = a.E0y[jqm], E0z_q = a.E0z[jqm];
     const double eyk_q = eyk[jqm + HALO], ezk_q = ezk[jqm + HALO];
-    for (int t = threadIdx.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
-    if (threadIdx.x < FIELD2_OUT) {
-        const int jm = imod(j0 + (int)threadIdx.x, M) + HALO;
-        bay[threadIdx.x] = a.ayn[jm] - a.half_dt * a.eyn[jm];
-        baz[threadIdx.x] = a.azn[jm] - a.half_dt * a.ezn[jm];
-    }
+    const double tap0 = a.taps[min(t0, a.ntaps - 1)];
+    const int jm0 = imod(j0 + min(t0, FIELD2_OUT - 1), M) + HALO;
+    const double ay0 = a.ayn[jm0], ey0 = a.eyn[jm0], az0 = a.azn[jm0], ez0 = a.ezn[jm0];
+    double v0[NS];
+    cell_partials_one2<NS>(a.part, imod(clo + min(t0, clen - 1), M), a.wpi, v0);
+    asm volatile("" ::"v"(E0y_q), "v"(E0z_q), "v"(eyk_q), "v"(ezk_q), "v"(tap0));
+    asm volatile("" ::"v"(ay0), "v"(ey0), "v"(az0), "v"(ez0));
+#pragma unroll
+    for (int q = 0; q < NS; ++q) asm volatile("" ::"v"(v0[q]));
     if (!sgate | sflags | (skconv >= 0)) return;
+    if (t0 < a.ntaps) tp[t0] = tap0;
+    for (int t = t0 + blockDim.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
+    if (t0 < FIELD2_OUT) {
+        bay[t0] = ay0 - a.half_dt * ey0;
+        baz[t0] = az0 - a.half_dt * ez0;
+    }
     for (int t = threadIdx.x; t < clen; t += blockDim.x) {
         const int c = imod(clo + t, M);
         double v[NS];
+        if (one_each && t == t0) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) cp[t * NS + q] = v0[q];
+            continue;
+        }
 #pragma unroll
         for (int q = 0; q < NS; ++q) v[q] = 0.0;
         const int u0 = (one_each ? c : a.items.cell_first[c]) * a.wpi;
@@ -232,20 +279,24 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     int flags = 0;
     {
         const double *Syq = Sy + quad + a.ntaps - 1, *Szq = Sz + quad + a.ntaps - 1;
-        double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0;
+        double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0, cy2 = 0.0, cz2 = 0.0, cy3 = 0.0, cz3 = 0.0;
         int i = ql;
-        for (; i + 4 < a.ntaps; i += 8) {
+        for (; i + 12 < a.ntaps; i += 16) {   // four chains per component
             cy = fma(tp[i], Syq[-i], cy);
             cz = fma(tp[i], Szq[-i], cz);
             cy1 = fma(tp[i + 4], Syq[-i - 4], cy1);
             cz1 = fma(tp[i + 4], Szq[-i - 4], cz1);
+            cy2 = fma(tp[i + 8], Syq[-i - 8], cy2);
+            cz2 = fma(tp[i + 8], Szq[-i - 8], cz2);
+            cy3 = fma(tp[i + 12], Syq[-i - 12], cy3);
+            cz3 = fma(tp[i + 12], Szq[-i - 12], cz3);
         }
-        if (i < a.ntaps) {
+        for (; i < a.ntaps; i += 4) {
             cy = fma(tp[i], Syq[-i], cy);
             cz = fma(tp[i], Szq[-i], cz);
         }
-        cy += cy1;
-        cz += cz1;
+        cy = (cy + cy1) + (cy2 + cy3);
+        cz = (cz + cz1) + (cz2 + cz3);
         cy += dpp_d<0xB1>(cy);
         cz += dpp_d<0xB1>(cz);
         cy += dpp_d<0x4E>(cy);
