@@ -367,7 +367,9 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
                                                     double *coefAk0, int do_II, Stencil m0, Stencil kk, double r2,
                                                     double ck, const double *taps, int ntaps, int mlo, int M,
                                                     double *E0y, double *E0z) {
-    extern __shared__ double R[];   // [2][FIELD2_OUT + ntaps - 1] + taps
+    // LDS: Ry, Rz [len], taps [ntaps], the window of a_y, a_z, e_y, e_z [wlen]
+    // each and e_x on cells j0 - P .. j0 + FIELD2_OUT - 1
+    extern __shared__ double R[];
     // a step enqueued behind another runs only if that one committed
     const bool go = gate_src ? (gate_src->committed && gate_src->flags == 0) : true;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -376,39 +378,61 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
     }
     const int j0 = blockIdx.x * FIELD2_OUT;
     const int mhi = mlo + ntaps - 1;
-    const int len = FIELD2_OUT + ntaps - 1;
+    const int len = FIELD2_OUT + ntaps - 1;   // R on cells j0 - mhi .. j0 - mhi + len - 1
+    const int wlo = j0 - mhi - P;             // the window: every cell the stencil and the records read
+    const int wlen = len + 2 * P;
+    constexpr int XL = FIELD2_OUT + P;
     double *Ry = R, *Rz = R + len, *tp = Rz + len;
-    if (do_II) {
-        for (int t = threadIdx.x; t < ntaps; t += blockDim.x) tp[t] = taps[t];
-        for (int idx = threadIdx.x; idx < len; idx += blockDim.x) {
-            const int j = imod(j0 - mhi + idx, M);
+    double *Way = tp + ntaps, *Waz = Way + wlen, *Wey = Waz + wlen, *Wez = Wey + wlen, *Wex = Wez + wlen;
+    // one memory round trip: the first round of the window, taps and e_x (none
+    // of it depends on the gate; nothing is written before it)
+    const int t = threadIdx.x;
+    const int jw = imod(wlo + min(t, wlen - 1), M) + HALO;
+    const double w_ay = ayn[jw], w_az = azn[jw], w_ey = eyn[jw], w_ez = ezn[jw];
+    const double w_tp = ntaps > 0 ? taps[min(t, ntaps - 1)] : 0.0;
+    const double w_ex = exn ? exn[imod(j0 - P + min(t, XL - 1), M) + HALO] : 0.0;
+    asm volatile("" ::"v"(w_ay), "v"(w_az), "v"(w_ey), "v"(w_ez), "v"(w_tp), "v"(w_ex));
+    if (!go) return;
+    if (t < wlen) { Way[t] = w_ay; Waz[t] = w_az; Wey[t] = w_ey; Wez[t] = w_ez; }
+    for (int idx = t + blockDim.x; idx < wlen; idx += blockDim.x) {
+        const int j = imod(wlo + idx, M) + HALO;
+        Way[idx] = ayn[j]; Waz[idx] = azn[j]; Wey[idx] = eyn[j]; Wez[idx] = ezn[j];
+    }
+    if (t < ntaps) tp[t] = w_tp;
+    for (int idx = t + blockDim.x; idx < ntaps; idx += blockDim.x) tp[idx] = taps[idx];
+    if (t < XL) Wex[t] = w_ex;
+    __syncthreads();
+    if (do_II) {   // R = (M0 - r^2 K) e^n + ck K a^n on the cells the convolution reads
+        for (int idx = t; idx < len; idx += blockDim.x) {
             double sy = 0.0, sz = 0.0;
-            for (int q = -m0.half; q <= m0.half; ++q) {
-                const double cm = m0.v[q + m0.half] - r2 * kk.v[q + kk.half];
-                const double ka = ck * kk.v[q + kk.half];
-                const int jq = imod(j + q, M) + HALO;
-                sy += cm * eyn[jq] + ka * ayn[jq];
-                sz += cm * ezn[jq] + ka * azn[jq];
+#pragma unroll
+            for (int q = -P; q <= P; ++q) {
+                const double cm = m0.v[q + P] - r2 * kk.v[q + P];
+                const double ka = ck * kk.v[q + P];
+                const int u = idx + P + q;
+                sy += cm * Wey[u] + ka * Way[u];
+                sz += cm * Wez[u] + ka * Waz[u];
             }
             Ry[idx] = sy;
             Rz[idx] = sz;
         }
     }
-    // (the loads above do not depend on the gate; nothing is written before it)
-    if (!go) return;
     {
-        const int c = j0 + (int)threadIdx.x;
-        if ((int)threadIdx.x < FIELD2_OUT && c < M) {
+        const int c = j0 + t;
+        if (t < FIELD2_OUT && c < M) {
             constexpr Pieces<P> B{};
             constexpr int NA = RecA<P>::N;
+            const int u0 = c - wlo;   // window index of cell c
+#pragma unroll
             for (int i = 0; i <= P; ++i) {
                 double ny = 0.0, nz = 0.0, ky = 0.0, kz = 0.0;
+#pragma unroll
                 for (int m = 0; m <= P; ++m) {
-                    const int j = c - m + HALO;
-                    ny += ayn[j] * B.c[m][i];
-                    nz += azn[j] * B.c[m][i];
-                    ky += (ayn[j] - dt * eyn[j]) * B.c[m][i];
-                    kz += (azn[j] - dt * ezn[j]) * B.c[m][i];
+                    const int u = u0 - m;
+                    ny += Way[u] * B.c[m][i];
+                    nz += Waz[u] * B.c[m][i];
+                    ky += (Way[u] - dt * Wey[u]) * B.c[m][i];
+                    kz += (Waz[u] - dt * Wez[u]) * B.c[m][i];
                 }
                 store_record(coefA, M, c, NA, i, ny);
                 store_record(coefA, M, c, NA, P + 1 + i, nz);
@@ -419,20 +443,29 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
             }
             if (coefE0) {
                 double r[P];
-                make_recE<P>([&](int jj) { return exn[jj + HALO]; }, c, r);
+                make_recE<P>([&](int jj) { return Wex[jj - (j0 - P)]; }, c, r);
                 for (int i = 0; i < P; ++i) store_record(coefE0, M, c, RecE<P>::N, i, r[i]);
             }
         }
     }
     if (!do_II) return;
     __syncthreads();
-    const int quad = threadIdx.x >> 2, ql = threadIdx.x & 3;
+    const int quad = t >> 2, ql = t & 3;
     const double *Ryq = Ry + quad + ntaps - 1, *Rzq = Rz + quad + ntaps - 1;
-    double cy = 0.0, cz = 0.0;
-    for (int i = ql; i < ntaps; i += 4) {
+    double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0;
+    int i = ql;
+    for (; i + 4 < ntaps; i += 8) {   // two chains per component
+        cy = fma(tp[i], Ryq[-i], cy);
+        cz = fma(tp[i], Rzq[-i], cz);
+        cy1 = fma(tp[i + 4], Ryq[-i - 4], cy1);
+        cz1 = fma(tp[i + 4], Rzq[-i - 4], cz1);
+    }
+    if (i < ntaps) {
         cy = fma(tp[i], Ryq[-i], cy);
         cz = fma(tp[i], Rzq[-i], cz);
     }
+    cy += cy1;
+    cz += cz1;
     cy += dpp_d<0xB1>(cy);
     cz += dpp_d<0xB1>(cz);
     cy += dpp_d<0x4E>(cy);
@@ -463,23 +496,30 @@ __global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const DevStatu
                                                    const double *ez0, const double *ez1, double *ey_next,
                                                    double *ez_next, double *ay_next, double *az_next, double half_dt,
                                                    int M, int nsweeps, double tol) {
-    int kc = -1;
-    if (st->gate && !st->flags) {
-        kc = st->kconv;
-        if (kc < 0 && prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0, st->re_bits[(nsweeps - 1) & 1]))
-            kc = nsweeps - 1;
-    }
+    // one memory round trip: the status words, the last residual and this
+    // cell's fields, with both candidates for e^(kc+1) (which one depends only
+    // on the parity of kc)
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const unsigned long long reb = st->re_bits[(nsweeps - 1) & 1];
+    asm volatile("" ::"s"(sgate), "s"(sflags), "s"(skconv), "s"(reb));
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jj = min(j, M - 1) + HALO;
+    const double y0 = ey0[jj], y1 = ey1[jj], z0 = ez0[jj], z1 = ez1[jj];
+    const double ay = ayn[jj], az = azn[jj], ey = eyn[jj], ez = ezn[jj];
+    int kc = -1;
+    if (sgate && !sflags) {
+        kc = skconv;
+        if (kc < 0 && prev_converged2(st, nsweeps, tol, blockIdx.x == 0 && threadIdx.x == 0, reb)) kc = nsweeps - 1;
+    }
     if (kc >= 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0) st->committed = 1;
         if (j < M) {
-            const double *eya = ((kc + 1) & 1) ? ey1 : ey0;
-            const double *eza = ((kc + 1) & 1) ? ez1 : ez0;
-            const double ny = eya[j + HALO], nz = eza[j + HALO];
+            const bool odd = ((kc + 1) & 1) != 0;
+            const double ny = odd ? y1 : y0, nz = odd ? z1 : z0;
             store_padded(ey_next, M, j, ny);
             store_padded(ez_next, M, j, nz);
-            store_padded(ay_next, M, j, ayn[j + HALO] - half_dt * (eyn[j + HALO] + ny));
-            store_padded(az_next, M, j, azn[j + HALO] - half_dt * (ezn[j + HALO] + nz));
+            store_padded(ay_next, M, j, ay - half_dt * (ey + ny));
+            store_padded(az_next, M, j, az - half_dt * (ez + nz));
         }
     }
     if (mirror && blockIdx.x == 0) {
@@ -520,7 +560,8 @@ void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *ga
     a.half = P; b.half = P;
     for (int q = 0; q <= 2 * P; ++q) { a.v[q] = m0[q]; b.v[q] = kr[q]; }
     const int grid = (M + FIELD2_OUT - 1) / FIELD2_OUT;
-    const size_t lds = do_II ? sizeof(double) * (2 * (FIELD2_OUT + ntaps - 1) + ntaps) : 0;
+    const int len = FIELD2_OUT + ntaps - 1;
+    const size_t lds = sizeof(double) * (2 * len + ntaps + 4 * (len + 2 * P) + FIELD2_OUT + P);
 #define ECPIC_B2(PP)                                                                                          \
     case PP:                                                                                                  \
         launch_k((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn,  \
