@@ -35,6 +35,13 @@ void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *ga
                        const double *eyn, const double *ezn, const double *exn, double dt, double *coefA,
                        double *coefE0, double *coefAk0, int do_II, const double *m0, const double *kr, double r2,
                        double ck, const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z);
+void launch_step_join(int P, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
+                      DevStatus *stI_next, const double *eyn, const double *ezn, const double *ayn, const double *azn,
+                      const double *ey0, const double *ey1, const double *ez0, const double *ez1, double *ey_next,
+                      double *ez_next, double *ay_next, double *az_next, int nsweeps, double tol,
+                      const double *exn_next, double dt, double *coefA, double *coefE0, double *coefAk0,
+                      const double *m0, const double *kr, double r2, double ck, const double *taps, int ntaps,
+                      int mlo, int M, double *E0y, double *E0z);
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
                  double alpha, int M);
 void launch_commit_II(int grid, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
@@ -496,7 +503,17 @@ int flags_to_status(int32_t f) {
     return ECPIC_OK;
 }
 
-// Finish Subsystem I (more sweeps / commit) after a status read.
+// The predictor's tables of the learned warm start (when it is on), from this
+// step's a_perp^n and e_x^n.
+void enqueue_ws_table(ecpic_ctx *c) {
+    if (!c->ws_on) return;
+    WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
+    timed(c, "ws_table", [&] {
+        launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc],
+                        c->M, c->ws_table);
+    });
+}
+
 // Start of a step (do_I and do_II), or of one substep: statuses, the records
 // of a^n (both substeps), of e_x^n (Subsystem I) and of a^(0), and E0
 // (Subsystem II).  In a full step the Subsystem I commit resets the Subsystem
@@ -512,13 +529,7 @@ void enqueue_begin(ecpic_ctx *c, bool do_I, bool do_II, const DevStatus *gate_sr
                           do_I ? c->coefE[0] : nullptr, c->coefAk[0], do_II ? 1 : 0, c->m0row.data(), c->krow.data(),
                           r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y, c->E0z);
     });
-    if (do_I && c->ws_on) {   // the predictor's tables, from this step's a_perp^n and e_x^n
-        WsNet net{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
-        timed(c, "ws_table", [&] {
-            launch_ws_table(c->P, c->stream, net, c->ws_w2b, c->coefA, c->ay[c->trc], c->az[c->trc], c->ex[c->exc],
-                            c->M, c->ws_table);
-        });
-    }
+    if (do_I) enqueue_ws_table(c);
 }
 
 // Slots of the training pairs advance after every committed Subsystem I step.
@@ -528,6 +539,7 @@ void advance_records(ecpic_ctx *c) {
     c->ws_phase = (c->ws_phase + 1) % c->ws_stride;
 }
 
+// Finish Subsystem I (more sweeps / commit) after a status read.
 int finish_I(ecpic_ctx *c, bool *recommitted) {
     *recommitted = false;
     while (true) {
@@ -1048,6 +1060,30 @@ void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII)
     }
 }
 
+// The Subsystem II commit of the step in slot j joined to the start of the
+// step in slot j + 1 (one kernel instead of a commit and a start); the
+// buffers advance in between, as after a separate commit.
+void enqueue_join(ecpic_ctx *c, int j) {
+    const int t = c->trc, n = t ^ 1;
+    DevStatus *st = c->stII;
+    const DevStatus *stI = c->stI;
+    DevStatus *mirror = c->hdev;
+    const int nsw = c->kII;
+    advance(c);
+    set_slot(c, j + 1);
+    c->kI = 0;
+    c->kII = 0;
+    const double r = c->dt / (2.0 * c->dx);
+    timed(c, "join", [&] {
+        launch_step_join(c->P, c->stream, st, stI, mirror, c->stI, c->ey[t], c->ez[t], c->ay[t], c->az[t], c->eyk[0],
+                         c->eyk[1], c->ezk[0], c->ezk[1], c->ey[n], c->ez[n], c->ay[n], c->az[n], nsw, c->tol,
+                         c->ex[c->exc], c->dt, c->coefA, c->coefE[0], c->coefAk[0], c->m0row.data(),
+                         c->krow.data(), r * r, c->dt / (c->dx * c->dx), c->tapsA, c->ntA, c->mloA, c->M, c->E0y,
+                         c->E0z);
+    });
+    enqueue_ws_table(c);
+}
+
 }  // namespace
 
 int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII, int32_t *steps_done) {
@@ -1067,15 +1103,21 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
         for (int j = 0; j < K; ++j) {
             snaps[j] = snap(c);
             set_slot(c, j);
-            enqueue_begin(c, true, true, j == 0 ? nullptr : c->st_ring + 2 * (j - 1) + 1);
+            if (j == 0) enqueue_begin(c, true, true);   // later steps are started by the join before them
             enqueue_sweeps_I(c, gI);
             enqueue_commit_I(c);   // also resets the Subsystem II status, gated on the commit
             // Subsystem II runs on the order the commit just made, whose item
             // count only the device knows: launch for the largest count
             IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
             enqueue_iters_II(c, v, gII);
-            enqueue_commit_II(c);   // writes this step's statuses into the host mirror
-            advance(c);
+            // the commit writes this step's statuses into the host mirror; the
+            // next step's start, gated on it, runs in the same kernel
+            if (j + 1 < K) {
+                enqueue_join(c, j);
+            } else {
+                enqueue_commit_II(c);
+                advance(c);
+            }
             c->exact_items = false;   // the item count of the next step is only known on the device
         }
         int rc = sync(c);

@@ -347,6 +347,105 @@ struct Stencil {
     int half;
 };
 
+// The step-start work of one block from its window in LDS (a^n, e^n on cells
+// wlo .., e_x^n on cells j0 - P ..): the A-records of a^n and of
+// a^(0) = a^n - dt e^n, the E-records of e_x^n, and with do_II the stencil
+// R = (M0 - r^2 K) e^n + ck K a^n and E0 = (M0 + r^2 K)^{-1} R on the block's
+// cells.  Every thread of the block calls it.
+struct StepStart {
+    double *coefA, *coefE0, *coefAk0, *E0y, *E0z;
+    Stencil m0, kk;
+    double dt, r2, ck;
+    int do_II, ntaps, mlo, M;
+};
+
+template <int P>
+__device__ __forceinline__ void step_start_body(const StepStart &a, int j0, int wlo, int len, const double *Way,
+                                                const double *Waz, const double *Wey, const double *Wez,
+                                                const double *Wex, const double *tp, double *Ry, double *Rz) {
+    const int t = threadIdx.x, M = a.M, ntaps = a.ntaps;
+    if (a.do_II) {
+        for (int idx = t; idx < len; idx += blockDim.x) {
+            double sy = 0.0, sz = 0.0;
+#pragma unroll
+            for (int q = -P; q <= P; ++q) {
+                const double cm = a.m0.v[q + P] - a.r2 * a.kk.v[q + P];
+                const double ka = a.ck * a.kk.v[q + P];
+                const int u = idx + P + q;
+                sy += cm * Wey[u] + ka * Way[u];
+                sz += cm * Wez[u] + ka * Waz[u];
+            }
+            Ry[idx] = sy;
+            Rz[idx] = sz;
+        }
+    }
+    {
+        const int c = j0 + t;
+        if (t < FIELD2_OUT && c < M) {
+            constexpr Pieces<P> B{};
+            constexpr int NA = RecA<P>::N;
+            const int u0 = c - wlo;   // window index of cell c
+#pragma unroll
+            for (int i = 0; i <= P; ++i) {
+                double ny = 0.0, nz = 0.0, ky = 0.0, kz = 0.0;
+#pragma unroll
+                for (int m = 0; m <= P; ++m) {
+                    const int u = u0 - m;
+                    ny += Way[u] * B.c[m][i];
+                    nz += Waz[u] * B.c[m][i];
+                    ky += (Way[u] - a.dt * Wey[u]) * B.c[m][i];
+                    kz += (Waz[u] - a.dt * Wez[u]) * B.c[m][i];
+                }
+                store_record(a.coefA, M, c, NA, i, ny);
+                store_record(a.coefA, M, c, NA, P + 1 + i, nz);
+                if (a.do_II) {
+                    store_record(a.coefAk0, M, c, NA, i, ky);
+                    store_record(a.coefAk0, M, c, NA, P + 1 + i, kz);
+                }
+            }
+            if (a.coefE0) {
+                double r[P];
+                make_recE<P>([&](int jj) { return Wex[jj - (j0 - P)]; }, c, r);
+                for (int i = 0; i < P; ++i) store_record(a.coefE0, M, c, RecE<P>::N, i, r[i]);
+            }
+        }
+    }
+    if (!a.do_II) return;
+    __syncthreads();
+    const int quad = t >> 2, ql = t & 3;
+    const double *Ryq = Ry + quad + ntaps - 1, *Rzq = Rz + quad + ntaps - 1;
+    double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0;
+    int i = ql;
+    for (; i + 4 < ntaps; i += 8) {   // two chains per component
+        cy = fma(tp[i], Ryq[-i], cy);
+        cz = fma(tp[i], Rzq[-i], cz);
+        cy1 = fma(tp[i + 4], Ryq[-i - 4], cy1);
+        cz1 = fma(tp[i + 4], Rzq[-i - 4], cz1);
+    }
+    if (i < ntaps) {
+        cy = fma(tp[i], Ryq[-i], cy);
+        cz = fma(tp[i], Rzq[-i], cz);
+    }
+    cy += cy1;
+    cz += cz1;
+    cy += dpp_d<0xB1>(cy);
+    cz += dpp_d<0xB1>(cz);
+    cy += dpp_d<0x4E>(cy);
+    cz += dpp_d<0x4E>(cz);
+    const int j = j0 + quad;
+    if (ql == 0 && j < M) {
+        a.E0y[j] = cy;
+        a.E0z[j] = cz;
+    }
+}
+
+// LDS of a step start: Ry, Rz [len], taps [ntaps], the window of a_y, a_z,
+// e_y, e_z [len + 2 P] each and e_x on cells j0 - P .. j0 + FIELD2_OUT - 1.
+__host__ __device__ constexpr size_t step_start_lds(int P, int ntaps) {
+    return sizeof(double) * (2 * (size_t)(FIELD2_OUT + ntaps - 1) + (size_t)ntaps +
+                             4 * (size_t)(FIELD2_OUT + ntaps - 1 + 2 * P) + FIELD2_OUT + P);
+}
+
 // Start of a step (or of one substep).  Block 0 resets the statuses it is
 // given (stI for Subsystem I, gated on gate_src, the Subsystem II status of the
 // step before when it was enqueued ahead; stII for a Subsystem II run on its
@@ -361,14 +460,9 @@ struct Stencil {
 // four lanes per output.
 template <int P>
 __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevStatus *gate_src, DevStatus *stII,
-                                                    const double *ayn,
-                                                    const double *azn, const double *eyn, const double *ezn,
-                                                    const double *exn, double dt, double *coefA, double *coefE0,
-                                                    double *coefAk0, int do_II, Stencil m0, Stencil kk, double r2,
-                                                    double ck, const double *taps, int ntaps, int mlo, int M,
-                                                    double *E0y, double *E0z) {
-    // LDS: Ry, Rz [len], taps [ntaps], the window of a_y, a_z, e_y, e_z [wlen]
-    // each and e_x on cells j0 - P .. j0 + FIELD2_OUT - 1
+                                                    const double *ayn, const double *azn, const double *eyn,
+                                                    const double *ezn, const double *exn, const double *taps,
+                                                    StepStart a) {
     extern __shared__ double R[];
     // a step enqueued behind another runs only if that one committed
     const bool go = gate_src ? (gate_src->committed && gate_src->flags == 0) : true;
@@ -376,8 +470,9 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
         if (stI) init_status(stI, gate_src);
         if (stII) init_status(stII, nullptr);
     }
+    const int M = a.M, ntaps = a.ntaps;
     const int j0 = blockIdx.x * FIELD2_OUT;
-    const int mhi = mlo + ntaps - 1;
+    const int mhi = a.mlo + ntaps - 1;
     const int len = FIELD2_OUT + ntaps - 1;   // R on cells j0 - mhi .. j0 - mhi + len - 1
     const int wlo = j0 - mhi - P;             // the window: every cell the stencil and the records read
     const int wlen = len + 2 * P;
@@ -402,80 +497,100 @@ __global__ void __launch_bounds__(256) k_begin_step(DevStatus *stI, const DevSta
     for (int idx = t + blockDim.x; idx < ntaps; idx += blockDim.x) tp[idx] = taps[idx];
     if (t < XL) Wex[t] = w_ex;
     __syncthreads();
-    if (do_II) {   // R = (M0 - r^2 K) e^n + ck K a^n on the cells the convolution reads
-        for (int idx = t; idx < len; idx += blockDim.x) {
-            double sy = 0.0, sz = 0.0;
-#pragma unroll
-            for (int q = -P; q <= P; ++q) {
-                const double cm = m0.v[q + P] - r2 * kk.v[q + P];
-                const double ka = ck * kk.v[q + P];
-                const int u = idx + P + q;
-                sy += cm * Wey[u] + ka * Way[u];
-                sz += cm * Wez[u] + ka * Waz[u];
-            }
-            Ry[idx] = sy;
-            Rz[idx] = sz;
-        }
-    }
-    {
-        const int c = j0 + t;
-        if (t < FIELD2_OUT && c < M) {
-            constexpr Pieces<P> B{};
-            constexpr int NA = RecA<P>::N;
-            const int u0 = c - wlo;   // window index of cell c
-#pragma unroll
-            for (int i = 0; i <= P; ++i) {
-                double ny = 0.0, nz = 0.0, ky = 0.0, kz = 0.0;
-#pragma unroll
-                for (int m = 0; m <= P; ++m) {
-                    const int u = u0 - m;
-                    ny += Way[u] * B.c[m][i];
-                    nz += Waz[u] * B.c[m][i];
-                    ky += (Way[u] - dt * Wey[u]) * B.c[m][i];
-                    kz += (Waz[u] - dt * Wez[u]) * B.c[m][i];
-                }
-                store_record(coefA, M, c, NA, i, ny);
-                store_record(coefA, M, c, NA, P + 1 + i, nz);
-                if (do_II) {
-                    store_record(coefAk0, M, c, NA, i, ky);
-                    store_record(coefAk0, M, c, NA, P + 1 + i, kz);
-                }
-            }
-            if (coefE0) {
-                double r[P];
-                make_recE<P>([&](int jj) { return Wex[jj - (j0 - P)]; }, c, r);
-                for (int i = 0; i < P; ++i) store_record(coefE0, M, c, RecE<P>::N, i, r[i]);
-            }
-        }
-    }
-    if (!do_II) return;
-    __syncthreads();
-    const int quad = t >> 2, ql = t & 3;
-    const double *Ryq = Ry + quad + ntaps - 1, *Rzq = Rz + quad + ntaps - 1;
-    double cy = 0.0, cz = 0.0, cy1 = 0.0, cz1 = 0.0;
-    int i = ql;
-    for (; i + 4 < ntaps; i += 8) {   // two chains per component
-        cy = fma(tp[i], Ryq[-i], cy);
-        cz = fma(tp[i], Rzq[-i], cz);
-        cy1 = fma(tp[i + 4], Ryq[-i - 4], cy1);
-        cz1 = fma(tp[i + 4], Rzq[-i - 4], cz1);
-    }
-    if (i < ntaps) {
-        cy = fma(tp[i], Ryq[-i], cy);
-        cz = fma(tp[i], Rzq[-i], cz);
-    }
-    cy += cy1;
-    cz += cz1;
-    cy += dpp_d<0xB1>(cy);
-    cz += dpp_d<0xB1>(cz);
-    cy += dpp_d<0x4E>(cy);
-    cz += dpp_d<0x4E>(cz);
-    const int j = j0 + quad;
-    if (ql == 0 && j < M) {
-        E0y[j] = cy;
-        E0z[j] = cz;
-    }
+    step_start_body<P>(a, j0, wlo, len, Way, Waz, Wey, Wez, Wex, tp, Ry, Rz);
 }
+
+// The Subsystem II commit of one step joined to the start of the next (steps
+// enqueued back to back).  Every block settles the convergence test of step n
+// on its own (same answer); block 0 records it, mirrors both statuses of step
+// n to the host and resets the Subsystem I status of step n+1, gated on the
+// commit.  Each block forms the committed e_perp^{n+1} = e^(kc+1) and
+// a^{n+1} = a^n - dt/2 (e^n + e^{n+1}) on its whole window from the iterates
+// (one memory round trip, both parity candidates loaded), writes them on its
+// own cells, and does the step-start work of step n+1 from that window.
+struct JoinArgs {
+    DevStatus *st;                         // Subsystem II status of step n
+    const DevStatus *stI;                  // Subsystem I status of step n (mirrored)
+    DevStatus *mirror;                     // host mirror of step n's statuses, or null
+    DevStatus *stI_next;                   // Subsystem I status of step n+1
+    const double *eyn, *ezn, *ayn, *azn;   // fields of step n
+    const double *ey0, *ey1, *ez0, *ez1;   // Subsystem II iterates, by parity
+    double *ey_next, *ez_next, *ay_next, *az_next;
+    const double *exn;                     // e_x^{n+1} (Subsystem I commit of step n)
+    const double *taps;
+    double half_dt, tol;
+    int nsweeps;
+};
+
+template <int P>
+__global__ void __launch_bounds__(256) k_step_join(JoinArgs g, StepStart a) {
+    extern __shared__ double R[];
+    DevStatus *st = g.st;
+    const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
+    const unsigned long long reb = st->re_bits[(g.nsweeps - 1) & 1];
+    asm volatile("" ::"s"(sgate), "s"(sflags), "s"(skconv), "s"(reb));
+    const int M = a.M, ntaps = a.ntaps;
+    const int j0 = blockIdx.x * FIELD2_OUT;
+    const int mhi = a.mlo + ntaps - 1;
+    const int len = FIELD2_OUT + ntaps - 1;
+    const int wlo = j0 - mhi - P;
+    const int wlen = len + 2 * P;
+    constexpr int XL = FIELD2_OUT + P;
+    double *Ry = R, *Rz = R + len, *tp = Rz + len;
+    double *Way = tp + ntaps, *Waz = Way + wlen, *Wey = Waz + wlen, *Wez = Wey + wlen, *Wex = Wez + wlen;
+    const int t = threadIdx.x;
+    const int jw = imod(wlo + min(t, wlen - 1), M) + HALO;
+    const double w_ay = g.ayn[jw], w_az = g.azn[jw], w_ey = g.eyn[jw], w_ez = g.ezn[jw];
+    const double w_y0 = g.ey0[jw], w_y1 = g.ey1[jw], w_z0 = g.ez0[jw], w_z1 = g.ez1[jw];
+    const double w_tp = ntaps > 0 ? g.taps[min(t, ntaps - 1)] : 0.0;
+    const double w_ex = g.exn[imod(j0 - P + min(t, XL - 1), M) + HALO];
+    asm volatile("" ::"v"(w_ay), "v"(w_az), "v"(w_ey), "v"(w_ez), "v"(w_tp), "v"(w_ex));
+    asm volatile("" ::"v"(w_y0), "v"(w_y1), "v"(w_z0), "v"(w_z1));
+    int kc = -1;
+    if (sgate && !sflags) {
+        kc = skconv;
+        if (kc < 0 && prev_converged2(st, g.nsweeps, g.tol, blockIdx.x == 0 && t == 0, reb)) kc = g.nsweeps - 1;
+    }
+    if (blockIdx.x == 0) {
+        if (t == 0 && kc >= 0) st->committed = 1;
+        if (g.mirror) {   // the words before the residual history of both statuses
+            __syncthreads();
+            constexpr int W = (int)(offsetof(DevStatus, res_hist) / sizeof(int32_t));
+            if (t < 2 * W) {
+                const int32_t *src = reinterpret_cast<const int32_t *>(t < W ? g.stI : st);
+                int32_t *dst = reinterpret_cast<int32_t *>(g.mirror + (t < W ? 0 : 1));
+                dst[t % W] = src[t % W];
+            }
+        }
+        if (t == 0) init_status(g.stI_next, st);
+    }
+    if (kc < 0) return;
+    const bool odd = ((kc + 1) & 1) != 0;
+    auto commit_cell = [&](int idx, double ay, double az, double ey, double ez, double y0, double y1, double z0,
+                           double z1) {
+        const double ny = odd ? y1 : y0, nz = odd ? z1 : z0;
+        const double na_y = fma(-g.half_dt, ey + ny, ay), na_z = fma(-g.half_dt, ez + nz, az);
+        Way[idx] = na_y; Waz[idx] = na_z; Wey[idx] = ny; Wez[idx] = nz;
+        const int q = idx - (mhi + P);   // own cell j0 + q
+        if (q >= 0 && q < FIELD2_OUT && j0 + q < M) {
+            store_padded(g.ey_next, M, j0 + q, ny);
+            store_padded(g.ez_next, M, j0 + q, nz);
+            store_padded(g.ay_next, M, j0 + q, na_y);
+            store_padded(g.az_next, M, j0 + q, na_z);
+        }
+    };
+    if (t < wlen) commit_cell(t, w_ay, w_az, w_ey, w_ez, w_y0, w_y1, w_z0, w_z1);
+    for (int idx = t + blockDim.x; idx < wlen; idx += blockDim.x) {
+        const int j = imod(wlo + idx, M) + HALO;
+        commit_cell(idx, g.ayn[j], g.azn[j], g.eyn[j], g.ezn[j], g.ey0[j], g.ey1[j], g.ez0[j], g.ez1[j]);
+    }
+    if (t < ntaps) tp[t] = w_tp;
+    for (int idx = t + blockDim.x; idx < ntaps; idx += blockDim.x) tp[idx] = g.taps[idx];
+    if (t < XL) Wex[t] = w_ex;
+    __syncthreads();
+    step_start_body<P>(a, j0, wlo, len, Way, Waz, Wey, Wez, Wex, tp, Ry, Rz);
+}
+
 
 // out_j = alpha * sum_i taps[i] in[(j - mlo - i) mod M]  (in, out unpadded)
 __global__ void __launch_bounds__(256) k_conv(const double *in, double *out, const double *taps, int ntaps, int mlo,
@@ -518,8 +633,8 @@ __global__ void __launch_bounds__(256) k_commit_II(DevStatus *st, const DevStatu
             const double ny = odd ? y1 : y0, nz = odd ? z1 : z0;
             store_padded(ey_next, M, j, ny);
             store_padded(ez_next, M, j, nz);
-            store_padded(ay_next, M, j, ay - half_dt * (ey + ny));
-            store_padded(az_next, M, j, az - half_dt * (ez + nz));
+            store_padded(ay_next, M, j, fma(-half_dt, ey + ny, ay));
+            store_padded(az_next, M, j, fma(-half_dt, ez + nz, az));
         }
     }
     if (mirror && blockIdx.x == 0) {
@@ -556,20 +671,41 @@ void launch_begin_step(int P, hipStream_t s, DevStatus *stI, const DevStatus *ga
                        const double *eyn, const double *ezn, const double *exn, double dt, double *coefA,
                        double *coefE0, double *coefAk0, int do_II, const double *m0, const double *kr, double r2,
                        double ck, const double *taps, int ntaps, int mlo, int M, double *E0y, double *E0z) {
-    Stencil a{}, b{};
-    a.half = P; b.half = P;
-    for (int q = 0; q <= 2 * P; ++q) { a.v[q] = m0[q]; b.v[q] = kr[q]; }
+    StepStart a{};
+    a.coefA = coefA; a.coefE0 = coefE0; a.coefAk0 = coefAk0; a.E0y = E0y; a.E0z = E0z;
+    a.m0.half = P; a.kk.half = P;
+    for (int q = 0; q <= 2 * P; ++q) { a.m0.v[q] = m0[q]; a.kk.v[q] = kr[q]; }
+    a.dt = dt; a.r2 = r2; a.ck = ck; a.do_II = do_II; a.ntaps = ntaps; a.mlo = mlo; a.M = M;
     const int grid = (M + FIELD2_OUT - 1) / FIELD2_OUT;
-    const int len = FIELD2_OUT + ntaps - 1;
-    const size_t lds = sizeof(double) * (2 * len + ntaps + 4 * (len + 2 * P) + FIELD2_OUT + P);
+    const size_t lds = step_start_lds(P, ntaps);
 #define ECPIC_B2(PP)                                                                                          \
     case PP:                                                                                                  \
-        launch_k((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn,  \
-                           ezn, exn, dt, coefA, coefE0, coefAk0, do_II, a, b, r2, ck, taps, ntaps, mlo, M, E0y,   \
-                           E0z);                                                                              \
+        launch_k((k_begin_step<PP>), dim3(grid), dim3(256), lds, s, stI, gate_src, stII, ayn, azn, eyn, ezn, \
+                 exn, taps, a);                                                                               \
         break;
     switch (P) { ECPIC_B2(2) ECPIC_B2(3) ECPIC_B2(4) ECPIC_B2(5) }
 #undef ECPIC_B2
+}
+
+void launch_step_join(int P, hipStream_t s, DevStatus *st, const DevStatus *stI, DevStatus *mirror,
+                      DevStatus *stI_next, const double *eyn, const double *ezn, const double *ayn, const double *azn,
+                      const double *ey0, const double *ey1, const double *ez0, const double *ez1, double *ey_next,
+                      double *ez_next, double *ay_next, double *az_next, int nsweeps, double tol,
+                      const double *exn_next, double dt, double *coefA, double *coefE0, double *coefAk0,
+                      const double *m0, const double *kr, double r2, double ck, const double *taps, int ntaps,
+                      int mlo, int M, double *E0y, double *E0z) {
+    JoinArgs g{st, stI, mirror, stI_next, eyn, ezn, ayn, azn, ey0, ey1, ez0, ez1, ey_next, ez_next, ay_next,
+               az_next, exn_next, taps, 0.5 * dt, tol, nsweeps};
+    StepStart a{};
+    a.coefA = coefA; a.coefE0 = coefE0; a.coefAk0 = coefAk0; a.E0y = E0y; a.E0z = E0z;
+    a.m0.half = P; a.kk.half = P;
+    for (int q = 0; q <= 2 * P; ++q) { a.m0.v[q] = m0[q]; a.kk.v[q] = kr[q]; }
+    a.dt = dt; a.r2 = r2; a.ck = ck; a.do_II = 1; a.ntaps = ntaps; a.mlo = mlo; a.M = M;
+    const int grid = (M + FIELD2_OUT - 1) / FIELD2_OUT;
+    const size_t lds = step_start_lds(P, ntaps);
+#define ECPIC_J(PP) case PP: launch_k((k_step_join<PP>), dim3(grid), dim3(256), lds, s, g, a); break;
+    switch (P) { ECPIC_J(2) ECPIC_J(3) ECPIC_J(4) ECPIC_J(5) }
+#undef ECPIC_J
 }
 
 void launch_conv(int grid, hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo,
