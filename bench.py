@@ -144,7 +144,7 @@ def main():
     arr = workloads.generate(w)
     N = w.n_particles
     names = ("ws_table", "ws_predict", "sweep_I32", "sweep_I", "field_I", "commit_I", "sweep_II", "field_II",
-             "begin", "commit_II")
+             "begin", "commit_II", "join")
 
     # ---- plain FP64 ---------------------------------------------------------
     plain = ec.Context.from_workload(w, map=ec.MAP_SEIDEL)
