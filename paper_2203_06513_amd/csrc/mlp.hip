@@ -351,7 +351,9 @@ __global__ void __launch_bounds__(64 * WS_CELLS) k_ws_table(WsNet net, const uns
 // its cell's (t, p) table of network outputs (k_ws_table, same substep), and
 // the current of that increment deposited like a sweep's, so that the field
 // kernel after it makes e^(1) consistent with delta^(1).  The Picard sweeps
-// start from both.
+// start from both.  The increment is stored in the precision of the sweep that
+// follows: single precision in the precision form (whose first FP64 sweep
+// starts from the last single-precision one), else double.
 constexpr int PRED_BATCH = 4;
 
 template <int P>
@@ -430,9 +432,9 @@ __device__ __forceinline__ void ws_predict_item(const SweepIArgs &a, int item) {
             int s;
             end_point(xi0, d, c, t1, s, flags);
             stage_deposit<P, double>(mo, __ballot(s != 0) != 0, t0, t1, s, valid ? 1.0 : 0.0);
-            if (valid) {
-                a.d1[ia] = d;
+            if (valid) {   // the sweep after it reads one of the two copies
                 if (a.f1) a.f1[ia] = (float)d;
+                else a.d1[ia] = d;
             }
         }
     }
