@@ -563,13 +563,13 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
             cell_partials_I<P>(a.items, one_each, a.part, imod(clo + t, M), a.wpi, v, rx, flags);
         }
 #pragma unroll
-        for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
+        for (int q = 0; q < NS; ++q) cp[q * clen + t] = v[q];   // slot-major: consecutive cells, banks
     }
     __syncthreads();
     for (int t = threadIdx.x; t < slen; t += blockDim.x) {
         double sum = 0.0;
 #pragma unroll
-        for (int r = 0; r < NS; ++r) sum += cp[(t + r) * NS + (P + 1 - r)];   // cell (j-1+r): slot P+1-r
+        for (int r = 0; r < NS; ++r) sum += cp[(P + 1 - r) * clen + t + r];   // cell (j-1+r): slot P+1-r
         S[t] = sum;
     }
     __syncthreads();

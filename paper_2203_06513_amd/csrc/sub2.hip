@@ -246,7 +246,7 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
         double v[NS];
         if (one_each && t == t0) {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) cp[t * NS + q] = v0[q];
+            for (int q = 0; q < NS; ++q) cp[q * clen + t] = v0[q];
             continue;
         }
 #pragma unroll
@@ -258,15 +258,15 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
             for (int q = 0; q < NS; ++q) v[q] += a.part[(size_t)u * NS + q];
         }
 #pragma unroll
-        for (int q = 0; q < NS; ++q) cp[t * NS + q] = v[q];
+        for (int q = 0; q < NS; ++q) cp[q * clen + t] = v[q];   // slot-major: consecutive cells, banks
     }
     __syncthreads();
     for (int t = threadIdx.x; t < slen; t += blockDim.x) {
         double sy = 0.0, sz = 0.0;
 #pragma unroll
         for (int r = 0; r <= P; ++r) {   // cell j + r: slot P - r
-            sy += cp[(t + r) * NS + (P - r)];
-            sz += cp[(t + r) * NS + P + 1 + (P - r)];
+            sy += cp[(P - r) * clen + t + r];
+            sz += cp[(P + 1 + (P - r)) * clen + t + r];
         }
         Sy[t] = sy;
         Sz[t] = sz;
