@@ -127,7 +127,6 @@ __device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate
     st->committed = 0;
     st->flags = 0;
     st->fp32_sweeps = 0;
-    st->scan_ticket = 0;
     st->scan_multi = 0;
     st->res = 0.0;
     st->gate = gate_src ? (gate_src->committed && gate_src->flags == 0) : 1;

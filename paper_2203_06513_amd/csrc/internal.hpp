@@ -44,8 +44,7 @@ struct DevStatus {
     int32_t gate;                    // substep allowed to run (Subsystem II waits on I)
     int32_t fp32_sweeps;             // sweeps done in FP32 (precision form)
     int32_t n_items_next;            // item count of the re-sorted particles (Subsystem I commit)
-    int32_t scan_ticket;             // blocks of the commit scan done (the last one resets it)
-    int32_t scan_multi;              // the new order has a cell with other than one item
+    int32_t scan_multi;              // a field kernel of the substep saw a cell with other than one item
     double res;                      // residual of sweep kconv (length / field units)
     double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
@@ -123,6 +122,17 @@ struct FieldIArgs {
     int32_t M;
     int32_t k;
     int32_t wpi;                   // waves per item of the sweep (partials per item)
+    // what a commit after this sweep needs (FP64 sweeps, k >= first64): the
+    // destinations of each cell's movers, the new counts and starts, the new
+    // item list if it has one item per cell, and e_x^{n+1}
+    int32_t first64;
+    const int32_t *wcnt;           // the sweep's per-wave mover counts
+    int32_t *cbase;                // [M][3]
+    int32_t *nstart;               // [2M + 1]: new start of each cell, N, new count of each cell
+    int32_t *base;                 // [max_items][3] (only when some cell has several items)
+    ItemList items_next;
+    double *ex_next;               // padded
+    int32_t chunk;
 };
 
 struct CommitIArgs {
@@ -143,6 +153,7 @@ struct CommitIArgs {
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
+    int32_t list_kernel;           // a separate kernel builds a new item list with several items per cell
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     int64_t N;
 };

@@ -353,10 +353,18 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.w = c->w;
     f.M = c->M;
     f.wpi = c->block / 64;
+    f.wcnt = c->wcnt;
+    f.cbase = c->cbase;
+    f.nstart = c->nstart;
+    f.base = c->base;
+    f.items_next = c->items[c->icur ^ 1];
+    f.ex_next = c->ex[c->exc ^ 1];
+    f.chunk = c->chunk;
     const int gridp = particle_grid(c, c->exact_items);
     const int mlp = c->ws_on ? 1 : 0;
     const int first64 = mlp + c->k32;
     a.first64 = first64;
+    f.first64 = first64;
     a.explicit_start = !mlp;
     a.ws = WsNet{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
     a.ws_table = c->ws_table;
@@ -415,6 +423,8 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
     a.first64 = (c->ws_on ? 1 : 0) + c->k32;
+    // the last known order decides where a list with several items per cell is built
+    a.list_kernel = c->n_items_host != c->M ? 1 : 0;
     if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
         a.rec.feat = c->ws_feat;
         a.rec.targ = c->ws_targ;

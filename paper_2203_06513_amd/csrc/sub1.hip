@@ -494,6 +494,44 @@ __device__ __forceinline__ void cell_partials_one(const double *part, int c, int
     }
 }
 
+// The commit's destinations need no scan over the cells.  A particle moves at
+// most one cell, so the particles that end in cells [0, c) are those that
+// started there, plus the left-movers of cell c and the right-movers of cell
+// M-1 (periodic), minus the right-movers of cell c-1 and the left-movers of
+// cell 0:
+//   nstart[c] = start[c] + L_c - R_{c-1} + R_{M-1} - L_0,   nstart[0] = 0,
+// with start[c] the first particle of cell c in the current order and L, S, R
+// a cell's left-movers, stayers and right-movers.  Each cell's value (and its
+// new count R_{c-1} + S_c + L_{c+1}) is local, so the field kernel after each
+// FP64 sweep forms them for its cells from the sweep's mover counts: the last
+// field kernel to run is that of the sweep the commit takes.  Only an item
+// list with other than one item per cell needs a prefix over the cells; the
+// commit builds it.
+
+// L, S, R of cell c and its first particle in the current order.  With one
+// item per cell only the cell index addresses the loads; otherwise they follow
+// the list, and base gets each item's movers before it in its cell.
+__device__ __forceinline__ void cell_movers(const ItemList &it, const int32_t *wcnt, int wpi, int32_t *base,
+                                            bool one_each, int c, bool write_base, int (&t)[3], int &start) {
+    if (one_each) {
+        start = it.begin[c];
+        const int32_t *q = wcnt + (size_t)c * wpi * 3;   // the cell's wpi triples, contiguous
+        t[0] = t[1] = t[2] = 0;
+        for (int w = 0; w < wpi; ++w) { t[0] += q[3 * w]; t[1] += q[3 * w + 1]; t[2] += q[3 * w + 2]; }
+        return;
+    }
+    const int lo = it.cell_first[c], hi = it.cell_first[c + 1];
+    start = it.begin[lo];   // an empty cell starts where the next item does
+    t[0] = t[1] = t[2] = 0;
+    for (int i = lo; i < hi; ++i) {
+        if (write_base) { base[i * 3 + 0] = t[0]; base[i * 3 + 1] = t[1]; base[i * 3 + 2] = t[2]; }
+        for (int w = 0; w < wpi; ++w) {
+            const int32_t *q = wcnt + ((size_t)i * wpi + w) * 3;
+            t[0] += q[0]; t[1] += q[1]; t[2] += q[2];
+        }
+    }
+}
+
 // Field update of sweep k and the E-records of the next ebar.  Block b
 // computes e^(k+1) on the FIELD_OUT cells starting at b * TILE - (P - 1) (the
 // first P - 1 only to form the records of cells b * TILE .. b * TILE + TILE - 1).
@@ -509,6 +547,12 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     __shared__ int ldsf[MAX_WAVES];
     constexpr int NS = P + 2;
     constexpr int TILE = FIELD_OUT - (P - 1);
+    // commit data: L, S, R of cells cb0-2 .. cb0+TILE, the current start of
+    // cells cb0-1 .. cb0+TILE (both mod M), L, S, R of cells 0 and M-1
+    __shared__ int tl[TILE + 3][3];
+    __shared__ int sl[TILE + 2];
+    __shared__ int ends[2][3];
+    __shared__ int notone_s;
     DevStatus *st = a.st;
     // the status is tested once the loads that do not depend on it are issued
     const int sgate = st->gate, sflags = st->flags, skconv = st->kconv;
@@ -545,6 +589,29 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
 #pragma unroll
     for (int q = 0; q < NS; ++q) asm volatile("" ::"v"(v0[q]));
     if (!sgate | sflags | (skconv >= 0)) return;
+    // commit data (FP64 sweeps): thread t < TILE + 3 takes the movers of cell
+    // cb0 - 2 + t and the start of cell cb0 - 1 + t, threads 254 and 255 those
+    // of cells 0 and M - 1.  Their loads are issued here and used once the
+    // partials are summed.
+    const bool cw = k >= a.first64;
+    const int cb0 = blockIdx.x * TILE;
+    const int mcell = t0 >= 254 ? (t0 == 254 ? 0 : M - 1) : imod(cb0 - 2 + min(t0, TILE + 2), M);
+    const int scell = imod(cb0 - 1 + min(t0, TILE + 1), M);
+    const bool mload = cw && (t0 < TILE + 3 || t0 >= 254), sload = cw && t0 < TILE + 2;
+    const bool own = t0 >= 2 && t0 < TILE + 2 && cb0 - 2 + t0 < M;   // base for the block's own cells
+    // Read as if item c were cell c (in bounds for any list), with no branch
+    // but the lane's own predicate, so that nothing waits for them before use;
+    // a list with several items per cell is followed where they are used.
+    int raw[MAX_WAVES][3] = {}, st0 = 0;
+    if (mload) {
+        const int32_t *q = a.wcnt + (size_t)mcell * a.wpi * 3;   // the cell's wpi triples, contiguous
+#pragma unroll
+        for (int w = 0; w < MAX_WAVES; ++w) {
+            const int ww = min(w, a.wpi - 1);
+            raw[w][0] = q[3 * ww]; raw[w][1] = q[3 * ww + 1]; raw[w][2] = q[3 * ww + 2];
+        }
+    }
+    if (sload) st0 = a.items.begin[scell];
     if (t0 < a.ntaps) tp[t0] = tap0;
     for (int t = t0 + blockDim.x; t < a.ntaps; t += blockDim.x) tp[t] = a.taps[t];
     if (t0 < FIELD_OUT) enw[t0] = enw0;
@@ -572,7 +639,50 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         for (int r = 0; r < NS; ++r) sum += cp[(P + 1 - r) * clen + t + r];   // cell (j-1+r): slot P+1-r
         S[t] = sum;
     }
+    if (cw) {
+        int mv[3] = {0, 0, 0};
+        if (one_each) {
+#pragma unroll
+            for (int w = 0; w < MAX_WAVES; ++w) {
+                const int u = w < a.wpi ? 1 : 0;
+                mv[0] += u * raw[w][0]; mv[1] += u * raw[w][1]; mv[2] += u * raw[w][2];
+            }
+        } else {   // through the item list; base for the block's own cells
+            int dummy;
+            if (mload) cell_movers(a.items, a.wcnt, a.wpi, a.base, false, mcell, own, mv, dummy);
+            if (sload) st0 = a.items.begin[a.items.cell_first[scell]];   // an empty cell starts where the next item does
+        }
+        if (t0 < TILE + 3) { tl[t0][0] = mv[0]; tl[t0][1] = mv[1]; tl[t0][2] = mv[2]; }
+        if (t0 >= 254) { ends[t0 - 254][0] = mv[0]; ends[t0 - 254][1] = mv[1]; ends[t0 - 254][2] = mv[2]; }
+        if (t0 < TILE + 2) sl[t0] = st0;
+        if (t0 == 0) notone_s = 0;
+    }
     __syncthreads();
+    // the commit data of the block's cells, stored before the convolution so
+    // that the stores complete behind it
+    if (cw && t0 < TILE && cb0 + t0 < M) {
+        // new start of cell cb0 + q (mod M), q in [-1, TILE]: slots q + 1 of sl
+        // and q + 2 of tl (L of the cell), q + 1 of tl (R of the cell before)
+        const int c = cb0 + t0;
+        const int wrap = ends[1][2] - ends[0][0];   // R_{M-1} - L_0
+        auto nstart_of = [&](int q) {
+            const int cq = cb0 + q;
+            return (cq == 0 || cq == M) ? 0 : sl[q + 1] + tl[q + 2][0] - tl[q + 1][2] + wrap;
+        };
+        const int ns = nstart_of(t0), nsm = nstart_of(t0 - 1), nsp = nstart_of(t0 + 1);
+        const int Rm = tl[t0 + 1][2], Sm = tl[t0 + 1][1], Rmm = tl[t0][2];
+        const int Lp = c == M - 1 ? ends[0][0] : tl[t0 + 3][0];
+        const int cnt = Rm + tl[t0 + 2][1] + Lp;   // R_{c-1} + S_c + L_{c+1}
+        a.cbase[c * 3 + 0] = nsm + Rmm + Sm;      // left-movers: after R_{c-2} and S_{c-1} in cell c-1
+        a.cbase[c * 3 + 1] = ns + Rm;             // stayers: after R_{c-1}
+        a.cbase[c * 3 + 2] = nsp;                 // right-movers: first in cell c+1
+        a.nstart[c] = ns;
+        a.nstart[M + 1 + c] = cnt;
+        a.items_next.cell[c] = c;                 // the list if every cell has one item
+        a.items_next.begin[c] = ns;
+        a.items_next.cell_first[c] = c;
+        if (items_of(cnt, a.chunk) != 1) notone_s = 1;
+    }
     double *eout = (k & 1) ? a.ek0 : a.ek1;
     double *Eout = ((k + 1) & 1) ? a.coefE1 : a.coefE0;
     double re = 0.0;
@@ -597,6 +707,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
             enl[quad] = enew;
             if (quad >= P - 1 && jq < M) {
                 store_padded(eout, M, jqm, enew);
+                if (cw) store_padded(a.ex_next, M, jqm, enew);   // e_x^{n+1} if this sweep is committed
                 re = fabs(enew - ek_q);
                 if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
             }
@@ -629,6 +740,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         atomicMax(&st->re_bits[k & 1], bitsd(re));
         atomicMax(&st->rx_bits[k & 1], bitsd(rx));
         if (flags) atomicOr(&st->flags, flags);
+        if (cw && notone_s) atomicOr(&st->scan_multi, 1);
         if (blockIdx.x == 0) {   // clear the slots field kernel k+1 accumulates into
             st->rx_bits[(k + 1) & 1] = 0ull;
             st->re_bits[(k + 1) & 1] = 0ull;
@@ -680,191 +792,6 @@ __device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a, int kc) 
     return r;
 }
 
-// Converged sweep index for the commit, making the test of the last enqueued
-// sweep if no later sweep made it; -1 if the commit must not run.
-__device__ __forceinline__ int settle_last(DevStatus *st, int nsweeps, int first64, double dx, double tol,
-                                           bool writer) {
-    if (!st->gate || st->flags || st->committed) return -1;
-    if (st->kconv >= 0) return st->kconv;
-    return prev_converged(st, nsweeps, first64, dx, tol, writer) ? nsweeps - 1 : -1;
-}
-
-// The commit's destinations need no scan over the cells.  A particle moves at
-// most one cell, so the particles that end in cells [0, c) are those that
-// started there, plus the left-movers of cell c and the right-movers of cell
-// M-1 (periodic), minus the right-movers of cell c-1 and the left-movers of
-// cell 0:
-//   nstart[c] = start[c] + L_c - R_{c-1} + R_{M-1} - L_0,   nstart[0] = 0,
-// with start[c] the first particle of cell c in the current order and L, S, R
-// a cell's left-movers, stayers and right-movers.  Each cell's value (and its
-// new count R_{c-1} + S_c + L_{c+1}) is local, so the commit scan runs one
-// cell per thread over many blocks; only an item list with other than one item
-// per cell needs a prefix over the cells, built by the last block to finish.
-constexpr int SCAN_CELLS = 256;   // cells (threads) per block
-
-// L, S, R of cell c and its first particle in the current order; with several
-// items in the cell, base gets each item's movers before it in the cell.
-__device__ __forceinline__ void cell_movers(const CommitIArgs &a, bool one_each, int c, bool write_base,
-                                            int (&t)[3], int &start) {
-    const int wpi = a.wpi;
-    if (one_each) {   // item c is cell c: no dependent load
-        start = a.items.begin[c];
-        int n[MAX_WAVES][3];
-#pragma unroll
-        for (int w = 0; w < MAX_WAVES; ++w) {
-            const int32_t *q = a.wcnt + (size_t)(c * wpi + min(w, wpi - 1)) * 3;
-            n[w][0] = q[0]; n[w][1] = q[1]; n[w][2] = q[2];
-        }
-        t[0] = t[1] = t[2] = 0;
-#pragma unroll
-        for (int w = 0; w < MAX_WAVES; ++w)
-            if (w < wpi) { t[0] += n[w][0]; t[1] += n[w][1]; t[2] += n[w][2]; }
-        return;
-    }
-    const int lo = a.items.cell_first[c], hi = a.items.cell_first[c + 1];
-    start = a.items.begin[lo];   // an empty cell starts where the next item does
-    t[0] = t[1] = t[2] = 0;
-    for (int i = lo; i < hi; ++i) {
-        if (write_base) { a.base[i * 3 + 0] = t[0]; a.base[i * 3 + 1] = t[1]; a.base[i * 3 + 2] = t[2]; }
-        for (int w = 0; w < wpi; ++w) {
-            const int32_t *q = a.wcnt + ((size_t)i * wpi + w) * 3;
-            t[0] += q[0]; t[1] += q[1]; t[2] += q[2];
-        }
-    }
-}
-
-// Settles the convergence test (block 0 records it) and resets the Subsystem
-// II status; then, for the cells of this block: e_x^{n+1}, the destinations of
-// each cell's first mover of each kind (an item adds its prefix within the
-// cell, a wave its prefix within the item), the new counts and starts, and the
-// entries of the new item list if it has one item per cell.  The last block
-// to finish completes the list (or builds it whole when some cell has other
-// than one item) and marks the substep committed.
-template <int P>
-__global__ void __launch_bounds__(SCAN_CELLS) k_commit_scan(CommitIArgs a) {
-    __shared__ int tl[SCAN_CELLS + 3][3];   // L, S, R of cells b0-2 .. b0+SCAN_CELLS (mod M)
-    __shared__ int sl[SCAN_CELLS + 2];      // current start of cells b0-1 .. b0+SCAN_CELLS (mod M)
-    __shared__ int ends[2][3];              // L, S, R of cells 0 and M-1
-    __shared__ int lds[16];
-    __shared__ int kcs, lastb;
-    const int M = a.M;
-    const int b0 = blockIdx.x * SCAN_CELLS, t = threadIdx.x;
-    const int c = b0 + t;
-    const bool live = c < M;
-    const bool one_each = a.items.n_items[1] != 0;
-    const int nex = M + 2 * HALO, nstride = gridDim.x * SCAN_CELLS;
-    // the movers and starts of this block's cells and of its halo cells b0-2,
-    // b0-1, b0+SCAN_CELLS and the end cells 0, M-1, into LDS
-    auto load_movers = [&]() {
-        int tm[3], sm;
-        cell_movers(a, one_each, live ? c : M - 1, live, tm, sm);
-        tl[t + 2][0] = tm[0]; tl[t + 2][1] = tm[1]; tl[t + 2][2] = tm[2];
-        sl[t + 1] = sm;
-        if (t < 5) {
-            const int hc = t == 0 ? imod(b0 - 2, M)
-                         : t == 1 ? imod(b0 - 1, M)
-                         : t == 2 ? imod(b0 + SCAN_CELLS, M)
-                         : t == 3 ? 0 : M - 1;
-            int th[3], sh;
-            cell_movers(a, one_each, hc, false, th, sh);
-            int *dst = t == 0 ? tl[0] : t == 1 ? tl[1] : t == 2 ? tl[SCAN_CELLS + 2] : ends[t - 3];
-            dst[0] = th[0]; dst[1] = th[1]; dst[2] = th[2];
-            if (t == 1) sl[0] = sh;
-            if (t == 2) sl[SCAN_CELLS + 1] = sh;
-        }
-    };
-    // loads first: both candidates for e_x^{n+1} (which one is e^(kc+1)
-    // depends only on the parity of kc) and, with one item per cell, the
-    // movers, whose addresses depend on the cell index only.  A list with
-    // several items per cell is followed only once the test has passed: the
-    // list of a substep that will not commit may be one no commit has written.
-    double e0[2], e1[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int idx = min(c + u * nstride, nex - 1);
-        e0[u] = a.ek0[idx];
-        e1[u] = a.ek1[idx];
-    }
-    if (one_each) load_movers();
-    if (t == 0) {
-        kcs = settle_last(a.st, a.nsweeps, a.first64, a.dx, a.tol, blockIdx.x == 0);
-        if (a.stII && blockIdx.x == 0) {   // Subsystem II may run only after this commit
-            init_status(a.stII, nullptr);
-            a.stII->gate = kcs >= 0 ? 1 : 0;
-        }
-    }
-    __syncthreads();
-    const int kc = kcs;
-    if (kc < 0) return;
-    if (!one_each) {
-        load_movers();
-        __syncthreads();
-    }
-    {   // e_x^{n+1} = e^(kc+1)
-        const bool odd = ((kc + 1) & 1) != 0;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int idx = c + u * nstride;
-            if (idx < nex) a.ex_next[idx] = odd ? e1[u] : e0[u];
-        }
-        const double *enew = odd ? a.ek1 : a.ek0;
-        for (int idx = c + 2 * nstride; idx < nex; idx += nstride) a.ex_next[idx] = enew[idx];
-    }
-    // new start of cell b0 + q (mod M), q in [-1, SCAN_CELLS]: slots q + 1 of
-    // sl and q + 2 of tl (L of the cell), q + 1 of tl (R of the cell before)
-    const int wrap = ends[1][2] - ends[0][0];   // R_{M-1} - L_0
-    auto nstart_of = [&](int q) {
-        const int cq = b0 + q;
-        return (cq == 0 || cq == M) ? 0 : sl[q + 1] + tl[q + 2][0] - tl[q + 1][2] + wrap;
-    };
-    int notone = 0;
-    if (live) {
-        const int ns = nstart_of(t), nsm = nstart_of(t - 1), nsp = nstart_of(t + 1);
-        const int Rm = tl[t + 1][2], Sm = tl[t + 1][1], Rmm = tl[t][2];
-        const int Lp = c == M - 1 ? ends[0][0] : tl[t + 3][0];
-        const int cnt = Rm + tl[t + 2][1] + Lp;   // R_{c-1} + S_c + L_{c+1}
-        a.cbase[c * 3 + 0] = nsm + Rmm + Sm;      // left-movers: after R_{c-2} and S_{c-1} in cell c-1
-        a.cbase[c * 3 + 1] = ns + Rm;             // stayers: after R_{c-1}
-        a.cbase[c * 3 + 2] = nsp;                 // right-movers: first in cell c+1
-        int32_t *ncount = a.nstart + (M + 1);
-        a.nstart[c] = ns;
-        ncount[c] = cnt;
-        notone = items_of(cnt, a.chunk) != 1;
-        a.items_next.cell[c] = c;                 // the list if every cell has one item
-        a.items_next.begin[c] = ns;
-        a.items_next.cell_first[c] = c;
-    }
-    // this block's writes are made visible device-wide before it takes its
-    // ticket; the last block sees every block's (fence after the ticket)
-    __threadfence();
-    notone = __syncthreads_or(notone);
-    if (t == 0) {
-        if (notone) {
-            atomicOr(&a.st->scan_multi, 1);
-            __threadfence();
-        }
-        lastb = atomicAdd(&a.st->scan_ticket, 1) == (int)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!lastb) return;
-    __threadfence();
-    int n_next = M;
-    if (atomicOr(&a.st->scan_multi, 0)) {
-        n_next = build_items(a.nstart + (M + 1), a.nstart, M, a.chunk, a.N, a.items_next, lds);
-    } else if (t == 0) {
-        a.items_next.cell_first[M] = M;
-        a.items_next.begin[M] = (int)a.N;
-        a.items_next.n_items[0] = M;
-        a.items_next.n_items[1] = 1;
-    }
-    if (t == 0) {
-        a.st->n_items_next = n_next;
-        a.st->scan_ticket = 0;
-        a.st->scan_multi = 0;
-        a.st->committed = 1;
-    }
-}
-
 // One training pair of the learned warm start: the particle's features at the
 // step start and the converged increments (see mlp.hip for the definitions).
 template <int P>
@@ -890,6 +817,51 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, d
     a.rec.targ[slot * 2 + 1] = (float)((p1 - p0) / a.dt);
 }
 
+// Block 0 of the commit: the Subsystem II status, reset and gated on the commit,
+// and, when the commit happens, the new item list completed (or built whole
+// when some cell of the new order has other than one item), its count and the
+// commit mark.  Every thread of the block calls it.
+__device__ __forceinline__ void commit_finish(const CommitIArgs &a, int kc, int multi, int *lds) {
+    if (threadIdx.x == 0 && a.stII) {   // Subsystem II may run only after this commit
+        init_status(a.stII, nullptr);
+        a.stII->gate = kc >= 0 ? 1 : 0;
+    }
+    if (kc < 0) return;
+    const int M = a.M;
+    if (multi && a.list_kernel) {   // k_commit_list builds the list
+        if (threadIdx.x == 0) a.st->committed = 1;
+        return;
+    }
+    int n_next = M;
+    if (multi) {
+        n_next = build_items(a.nstart + (M + 1), a.nstart, M, a.chunk, a.N, a.items_next, lds);
+    } else if (threadIdx.x == 0) {
+        a.items_next.cell_first[M] = M;
+        a.items_next.begin[M] = (int)a.N;
+        a.items_next.n_items[0] = M;
+        a.items_next.n_items[1] = 1;
+    }
+    if (threadIdx.x == 0) {
+        a.st->n_items_next = n_next;
+        a.st->scan_multi = 0;
+        a.st->committed = 1;
+    }
+}
+
+// The new item list when some cell of the new order has other than one item,
+// built by one 1024-thread block after the scatter (launched when the current
+// order has such cells; otherwise block 0 of the scatter builds it).
+__global__ void __launch_bounds__(1024) k_commit_list(CommitIArgs a) {
+    __shared__ int lds[16];
+    const int committed = a.st->committed, multi = a.st->scan_multi;
+    if (!committed || !multi) return;
+    const int n_next = build_items(a.nstart + (a.M + 1), a.nstart, a.M, a.chunk, a.N, a.items_next, lds);
+    if (threadIdx.x == 0) {
+        a.st->n_items_next = n_next;
+        a.st->scan_multi = 0;
+    }
+}
+
 // Moves every particle to its place in the new cell order, with the committed
 // momentum re-evaluated.  Each wave handles the same run of rows as in the
 // sweep, so its movers of each kind are consecutive from the base the scan
@@ -897,16 +869,27 @@ __device__ __forceinline__ void record_pair(const CommitIArgs &a, const Own<P, d
 template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
-    // item count, status words and item description in one memory round trip
+    __shared__ int lds[16];
+    // item count, status words, the residual slots of the last sweep and the
+    // item description in one memory round trip
     const int n_items = a.items.n_items[0], one_each = a.items.n_items[1];
-    const int sgate = a.st->gate, sflags = a.st->flags, skconv = a.st->kconv;
+    const int sgate = a.st->gate, sflags = a.st->flags, skconv = a.st->kconv, smulti = a.st->scan_multi;
+    const unsigned long long rxb = a.st->rx_bits[(a.nsweeps - 1) & 1], reb = a.st->re_bits[(a.nsweeps - 1) & 1];
     const int c = a.items.cell[item];
     const int beg = a.items.begin[item], end = a.items.begin[item + 1];
-    asm volatile("" ::"s"(n_items), "s"(one_each), "s"(sgate), "s"(sflags), "s"(skconv), "s"(c), "s"(beg),
-                 "s"(end));
-    if (item >= n_items) return;
-    if (!(sgate && skconv >= 0 && sflags == 0)) return;   // the commit runs on a converged, unflagged substep
-    const CommitPick pk = commit_pick(a, skconv);
+    asm volatile("" ::"s"(n_items), "s"(one_each), "s"(sgate), "s"(sflags), "s"(skconv), "s"(smulti), "s"(rxb),
+                 "s"(reb), "s"(c), "s"(beg), "s"(end));
+    // the converged sweep: recorded by an earlier sweep's start, else the test
+    // of the last enqueued sweep, made here by every block (block 0 records it)
+    int kc = -1;
+    if (sgate && !sflags) {
+        kc = skconv;
+        if (kc < 0 && prev_converged(a.st, a.nsweeps, a.first64, a.dx, a.tol, item == 0 && threadIdx.x == 0, rxb, reb))
+            kc = a.nsweeps - 1;
+    }
+    if (item == 0) commit_finish(a, kc, smulti, lds);
+    if (item >= n_items || kc < 0) return;   // the commit runs on a converged, unflagged substep
+    const CommitPick pk = commit_pick(a, kc);
     const int M = a.M;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
@@ -1030,10 +1013,8 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
-    const int gscan = (a.M + SCAN_CELLS - 1) / SCAN_CELLS;
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
-        launch_k((k_commit_scan<PP>), dim3(gscan), dim3(SCAN_CELLS), 0, s, a);         \
         if (a.rec.stride > 0)                                                                    \
             launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
         else                                                                                     \
@@ -1041,6 +1022,7 @@ void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArg
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C
+    if (a.list_kernel) launch_k(k_commit_list, dim3(1), dim3(1024), 0, s, a);
 }
 
 
