@@ -140,8 +140,6 @@ struct CommitIArgs {
     const double *d0, *d1;
     ItemList items, items_next;
     const double *coefA, *coefE0, *coefE1;
-    const double *ek0, *ek1;
-    double *ex_next;               // padded e_x^{n+1}
     DevStatus *stII;               // reset here, gated on this commit (null: leave it)
     const int32_t *wcnt;           // per-wave mover counts of the converged sweep (see SweepIArgs)
     int32_t *base;                 // [max_items][3] each item's movers of each kind before it in its cell

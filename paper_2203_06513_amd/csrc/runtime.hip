@@ -403,9 +403,6 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.coefA = c->coefA;
     a.coefE0 = c->coefE[0];
     a.coefE1 = c->coefE[1];
-    a.ek0 = c->ek[0];
-    a.ek1 = c->ek[1];
-    a.ex_next = c->ex[c->exc ^ 1];
     a.stII = c->stII;
     a.wcnt = c->wcnt;
     a.base = c->base;

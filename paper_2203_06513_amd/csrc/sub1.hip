@@ -776,12 +776,10 @@ __global__ void __launch_bounds__(256) k_prep_records(DevStatus *st_init, const 
 struct CommitPick {
     const double *d;       // increment to commit
     const double *coefE;   // ebar records for the committed momentum
-    const double *enew;    // e_x^{n+1}
 };
 
 __device__ __forceinline__ CommitPick commit_pick(const CommitIArgs &a, int kc) {
     CommitPick r;
-    r.enew = ((kc + 1) & 1) ? a.ek1 : a.ek0;   // e^(kc+1)
     if (a.seidel) {
         r.d = ((kc + 1) & 1) ? a.d1 : a.d0;     // delta^(kc+1)
         r.coefE = ((kc + 1) & 1) ? a.coefE1 : a.coefE0;
@@ -864,8 +862,10 @@ __global__ void __launch_bounds__(1024) k_commit_list(CommitIArgs a) {
 
 // Moves every particle to its place in the new cell order, with the committed
 // momentum re-evaluated.  Each wave handles the same run of rows as in the
-// sweep, so its movers of each kind are consecutive from the base the scan
-// gave it; ballots rank them within a row.
+// sweep, so its movers of each kind are consecutive from its cell's base (the
+// field kernel of the committed sweep formed it; an item adds the movers of
+// the cell's earlier items, a wave those of the item's earlier waves); ballots
+// rank them within a row.
 template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
