@@ -337,15 +337,20 @@ def _items_per_step(o, s, w, nsteps, chunk=2048):
     return counts
 
 
-@pytest.mark.parametrize("case", ["sparse", "sparse-guess1", "dense"])
+@pytest.mark.parametrize("case", ["sparse", "sparse-guess1", "dense", "edge", "edge-guess1"])
 def test_item_count_changes_within_steps(case):
     """Steps during which the number of work items changes (particles entering empty cells;
     a cell's count crossing the item size): Subsystem II runs on the new order, whose item
     count is only known on the device, and must cover every item.  With one sweep enqueued
-    ahead (sparse-guess1) every batch fails its first test, so the commits of the steps
-    behind it run gated on an order that no commit has written yet."""
+    ahead (-guess1) every batch fails its first test, so the commits of the steps behind it
+    run gated on an order that no commit has written yet.  The edge cases start with one
+    item per cell and cross the item size both ways (item counts 6, 7, 6, .. on 6 cells):
+    batched, the commit's block 0 builds the lists with two items in a cell; with the steps
+    finished one by one the host knows the current count and a separate kernel builds them."""
     if case.startswith("sparse"):
         w = workloads.small("sparse", M=64, L=8.0, n=48, dt=0.05, sigma=0.6, amplitude=0.3)
+    elif case.startswith("edge"):
+        w = workloads.small("edge", M=6, L=1.5, n=12000, dt=0.05, sigma=0.3, amplitude=0.3, seed=7)
     else:
         w = workloads.small("dense", M=8, L=2.0, n=16384, dt=0.05, sigma=0.3, amplitude=0.3)
     arr = workloads.generate(w)
@@ -354,9 +359,11 @@ def test_item_count_changes_within_steps(case):
     s = initial_state(o, arr)
     items = _items_per_step(o, {k: v.copy() for k, v in s.items()}, w, nsteps)
     assert max(items[1:]) > items[0] or len(set(items)) > 1, items   # the case is exercised
+    if case.startswith("edge"):
+        assert items[0] == w.M and max(items) > w.M and items.count(w.M) > 1, items
     st, kI, kII, E = o.step(s, nsteps, energies=True)
     assert st == 0
-    kw = {"sweep_guess": 1} if case == "sparse-guess1" else {}
+    kw = {"sweep_guess": 1} if case.endswith("guess1") else {}
     with gpu_ctx(w, map=ec.MAP_SEIDEL, **kw) as c:
         c.load(arr)
         H0 = c.energy()[4]
