@@ -126,7 +126,6 @@ struct FieldIArgs {
     // destinations of each cell's movers, the new counts and starts, the new
     // item list if it has one item per cell, and e_x^{n+1}
     int32_t first64;
-    double dx, tol;                // the convergence test (a block whose residual exceeds tol skips the commit data)
     const int32_t *wcnt;           // the sweep's per-wave mover counts
     int32_t *cbase;                // [M][3]
     int32_t *nstart;               // [2M + 1]: new start of each cell, N, new count of each cell

@@ -360,8 +360,6 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.items_next = c->items[c->icur ^ 1];
     f.ex_next = c->ex[c->exc ^ 1];
     f.chunk = c->chunk;
-    f.dx = c->dx;
-    f.tol = c->tol;
     const int gridp = particle_grid(c, c->exact_items);
     const int mlp = c->ws_on ? 1 : 0;
     const int first64 = mlp + c->k32;

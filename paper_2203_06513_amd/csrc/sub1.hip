@@ -632,16 +632,14 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
 #pragma unroll
         for (int q = 0; q < NS; ++q) cp[q * clen + t] = v[q];   // slot-major: consecutive cells, banks
     }
-    // A sweep is committed only if its residual meets the test everywhere, so
-    // a block that sees a larger increment change skips the commit data.
-    const bool cwc = cw && !__syncthreads_or(cw && rx * a.dx > a.tol);
+    __syncthreads();
     for (int t = threadIdx.x; t < slen; t += blockDim.x) {
         double sum = 0.0;
 #pragma unroll
         for (int r = 0; r < NS; ++r) sum += cp[(P + 1 - r) * clen + t + r];   // cell (j-1+r): slot P+1-r
         S[t] = sum;
     }
-    if (cwc) {
+    if (cw) {
         int mv[3] = {0, 0, 0};
         if (one_each) {
 #pragma unroll
@@ -662,7 +660,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     __syncthreads();
     // the commit data of the block's cells, stored before the convolution so
     // that the stores complete behind it
-    if (cwc && t0 < TILE && cb0 + t0 < M) {
+    if (cw && t0 < TILE && cb0 + t0 < M) {
         // new start of cell cb0 + q (mod M), q in [-1, TILE]: slots q + 1 of sl
         // and q + 2 of tl (L of the cell), q + 1 of tl (R of the cell before)
         const int c = cb0 + t0;
@@ -709,7 +707,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
             enl[quad] = enew;
             if (quad >= P - 1 && jq < M) {
                 store_padded(eout, M, jqm, enew);
-                if (cwc) store_padded(a.ex_next, M, jqm, enew);   // e_x^{n+1} if this sweep is committed
+                if (cw) store_padded(a.ex_next, M, jqm, enew);   // e_x^{n+1} if this sweep is committed
                 re = fabs(enew - ek_q);
                 if (!(fabs(enew) < 1.0e300)) flags |= FLAG_NONFINITE;
             }
@@ -742,7 +740,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         atomicMax(&st->re_bits[k & 1], bitsd(re));
         atomicMax(&st->rx_bits[k & 1], bitsd(rx));
         if (flags) atomicOr(&st->flags, flags);
-        if (cwc && notone_s) atomicOr(&st->scan_multi, 1);
+        if (cw && notone_s) atomicOr(&st->scan_multi, 1);
         if (blockIdx.x == 0) {   // clear the slots field kernel k+1 accumulates into
             st->rx_bits[(k + 1) & 1] = 0ull;
             st->re_bits[(k + 1) & 1] = 0ull;
