@@ -121,6 +121,23 @@ __device__ __forceinline__ double fsqrt(double q) {   // q >= 1
 }
 #endif
 
+// One particle of a Subsystem II iterate (Section 4.2): the deposit
+// coefficients c = (A^(k) + A^n)/(gamma^n + gamma^(k)) at local coordinate t0
+// with momentum p0; any, anz (ak*) are the cell's polynomial coefficients of
+// a^n (of a^(k)).
+template <int P>
+__device__ __forceinline__ void sub2_coef(const double *any, const double *anz, const double *aky, const double *akz,
+                                          double t0, double p0, double &cy, double &cz) {
+    const double Any = horner<P + 1>(any, t0), Anz = horner<P + 1>(anz, t0);
+    const double Aky = horner<P + 1>(aky, t0), Akz = horner<P + 1>(akz, t0);
+    const double q = fma(p0, p0, 1.0);
+    const double gn = fsqrt(q + Any * Any + Anz * Anz);
+    const double gk = fsqrt(q + Aky * Aky + Akz * Akz);
+    const double inv = frcp(gn + gk);
+    cy = (Aky + Any) * inv;
+    cz = (Akz + Anz) * inv;
+}
+
 // Single precision: the hardware square root and reciprocal (about 1 ulp).
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float fsqrt(float q) { return __builtin_amdgcn_sqrtf(q); }

@@ -152,6 +152,9 @@ struct CommitIArgs {
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
     int32_t list_kernel;           // a separate kernel builds a new item list with several items per cell
+    // the first Subsystem II deposit at the committed positions (part2 null: not formed)
+    const double *coefAk0;         // A-records of a^(0) = a^n - dt e^n
+    double *part2;                 // [items][waves per item][2 (deg+3)], by the current item list
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     int64_t N;
 };
@@ -183,6 +186,8 @@ struct FieldIIArgs {
     int32_t M;
     int32_t k;
     int32_t wpi;                              // waves per item of the particle pass
+    int32_t wide;                             // iterate 0 from the commit's partials: items is the list
+                                              // of the order before the commit, 2 (deg+3) per wave
 };
 
 // Kernel launches go through launch_k.  When a profiled launch has set the

@@ -244,6 +244,9 @@ struct ecpic_ctx {
     bool have_particles = false;
     int guessI = 4, guessII = 4;
     bool exact_items = true;   // n_items_host is the item count of the step being enqueued
+    // inside ecpic_step: the Subsystem I commit forms the particle deposit of
+    // the first Subsystem II iterate, which then has no particle pass of its own
+    bool fuse_II = false;
     int kI = 0, kII = 0;   // sweeps / iterations enqueued in the current substeps
     Prof prof;
 };
@@ -422,6 +425,10 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.first64 = (c->ws_on ? 1 : 0) + c->k32;
     // the last known order decides where a list with several items per cell is built
     a.list_kernel = c->n_items_host != c->M ? 1 : 0;
+    if (c->fuse_II) {
+        a.coefAk0 = c->coefAk[0];   // a^(0), formed by the step's start
+        a.part2 = c->part;
+    }
     if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
         a.rec.feat = c->ws_feat;
         a.rec.targ = c->ws_targ;
@@ -442,6 +449,8 @@ struct IIView {
     const double *xi, *p;
     ItemList items;
     bool exact;
+    bool fused;            // iterate 0's deposit comes from the commit just enqueued ...
+    ItemList items_commit; // ... indexed by the item list of the order it left
 };
 
 void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
@@ -481,6 +490,13 @@ void enqueue_iters_II(ecpic_ctx *c, const IIView &v, int count) {
     const int gridp = particle_grid(c, v.exact);
     for (int i = 0; i < count; ++i) {
         a.k = f.k = c->kII++;
+        if (a.k == 0 && v.fused) {
+            FieldIIArgs f0 = f;
+            f0.items = v.items_commit;
+            f0.wide = 1;
+            timed(c, "field_II", [&] { launch_field_II(c->P, c->M, c->stream, f0); });
+            continue;
+        }
         timed(c, "sweep_II", [&] { launch_sweep_II(c->P, gridp, c->block, c->stream, a); });
         timed(c, "field_II", [&] { launch_field_II(c->P, c->M, c->stream, f); });
     }
@@ -656,7 +672,7 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->wcnt, (size_t)c->max_items * (c->block / 64) * 3);
     rc |= dalloc(&c->nstart, (size_t)2 * M + 1);
     // per item and wave: Subsystem I P+4 values, Subsystem II 2 (P+1)
-    rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 1), c->P + 4));
+    rc |= dalloc(&c->part, (size_t)c->max_items * (c->block / 64) * std::max(2 * (c->P + 3), c->P + 4));
     rc |= dalloc(&c->E0y, M); rc |= dalloc(&c->E0z, M);
     const size_t nrec = (size_t)(M + 2);
     rc |= dalloc(&c->coefA, nrec * 2 * (c->P + 1));
@@ -1014,7 +1030,7 @@ int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
     enqueue_begin(c, false, true);
-    IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true};
+    IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true, false, {}};
     enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
     enqueue_commit_II(c);
     int rc = read_status(c, true);
@@ -1098,6 +1114,11 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
     if (steps_done) *steps_done = 0;
+    struct FuseII {   // every commit of a step feeds the step's first Subsystem II iterate
+        ecpic_ctx *c;
+        explicit FuseII(ecpic_ctx *x) : c(x) { c->fuse_II = true; }
+        ~FuseII() { c->fuse_II = false; }
+    } fuse(c);
     int done = 0;
     while (done < nsteps) {
         // Enqueue a batch of steps, each gated on the one before having
@@ -1115,7 +1136,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             enqueue_commit_I(c);   // also resets the Subsystem II status, gated on the commit
             // Subsystem II runs on the order the commit just made, whose item
             // count only the device knows: launch for the largest count
-            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
+            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false, true, c->items[c->icur]};
             enqueue_iters_II(c, v, gII);
             // the commit writes this step's statuses into the host mirror; the
             // next step's start, gated on it, runs in the same kernel
@@ -1156,7 +1177,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
             restore(c, snaps[j]);
             c->exact_items = true;
             if (j > 0) c->n_items_host = c->h_ring[j - 1].I.n_items_next;
-            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false};
+            IIView v{c->pb[c->cur ^ 1].xi, c->pb[c->cur ^ 1].p, c->items[c->icur ^ 1], false, true, c->items[c->icur]};
             bool again = false;
             rc = finish_I(c, &again);
             if (!rc && again) {   // Subsystem I needed extra sweeps: run II now

@@ -65,10 +65,17 @@ __device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, dou
     else end_point(L.t0, L.d, L.t1, L.s, flags);
 }
 
+// A and gamma at the step's end with the new momentum (for the commit).
+template <typename T>
+struct PushEnd {
+    T A1y, A1z, g11;
+};
+
 // Momentum update and next increment; anycross is wave-uniform.
 template <int P, typename T>
 __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
-                                           const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags) {
+                                           const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags,
+                                           PushEnd<T> *pe = nullptr) {
     const T zero = (T)0, one = (T)1;
     const T t1c = fmin(fmax(L.t1, zero), one);
     T h[P];
@@ -102,6 +109,11 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
     p1 = fma(dt, F, L.p0);
     const T g11 = fsqrt(fma(p1, p1, one) + qa1);
     dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
+    if (pe) {
+        pe->A1y = A1y;
+        pe->A1z = A1z;
+        pe->g11 = g11;
+    }
     const T big = sizeof(T) == 8 ? (T)1.0e300 : (T)1.0e30f;
     wave_flag(flags, !(fabs(dn) < big), FLAG_NONFINITE);
     wave_flag(flags, !(fabs(p1) < big), FLAG_NONFINITE);
@@ -860,16 +872,59 @@ __global__ void __launch_bounds__(1024) k_commit_list(CommitIArgs a) {
     }
 }
 
+// Totals over the lanes of a wave of NV values per lane held in LDS, value u
+// of lane i at col[u * stride + i]; lane u < NV returns total u.  A lane sums
+// one value over a run of lanes (staggered, so that the lanes of a run read
+// different banks), the runs' parts go to row 0 and lane u adds its value's
+// parts, all in a fixed order.  Every thread of the block calls it (barriers);
+// the caller has made the values visible.
+template <int NV>
+__device__ __forceinline__ double wave_totals_lds(double *col, int stride, int lane) {
+    constexpr int G = WAVE / NV, S = (WAVE + G - 1) / G;   // runs per value, lanes per run
+    const int u = lane % NV, g = lane / NV;
+    double part = 0.0;
+    if (g < G) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int src = g * S + (i + u) % S;
+            if (src < WAVE) part += col[u * stride + src];
+        }
+    }
+    __syncthreads();   // every run is read before row 0 is overwritten
+    if (g < G) col[g * NV + u] = part;
+    __syncthreads();
+    double t = 0.0;
+    if (lane < NV)
+#pragma unroll
+        for (int k = 0; k < G; ++k) t += col[k * NV + lane];
+    return t;
+}
+
 // Moves every particle to its place in the new cell order, with the committed
 // momentum re-evaluated.  Each wave handles the same run of rows as in the
 // sweep, so its movers of each kind are consecutive from its cell's base (the
 // field kernel of the committed sweep formed it; an item adds the movers of
 // the cell's earlier items, a wave those of the item's earlier waves); ballots
 // rank them within a row.
+//
+// With part2 set the commit also forms the particle deposit of the first
+// Subsystem II iterate.  That iterate needs only the committed (x, p) and the
+// records of a^n and a^(0) = a^n - dt e^n, all fixed before Subsystem I
+// starts, so the particle pass of iterate 0 is done here, on values already in
+// registers, instead of by a pass of its own over the new order.  Each particle
+// adds c_y t^j, c_z t^j (t its coordinate in the cell it lands in) to the
+// moments of that cell: its own (in registers), or the neighbour a mover
+// enters (per-lane slots in dynamic LDS, lane-major, so that the rare movers
+// cost no registers across the loop).  A^n and gamma^n at the end point are
+// those the push evaluated.  A wave writes 2 (P+3) slots, V0 indices
+// c-P-1 .. c+1 for each component.
 template <int P, bool RECORD>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
+    constexpr int NA = RecA<P>::N;
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
+    __shared__ double rk[3][NA];           // a^(0) records of cells c-1, c, c+1 (part2)
     __shared__ int lds[16];
+    extern __shared__ double mvl[];        // part2: per wave [left, right][y, z][P+1][64 lanes] mover moments
     // item count, status words, the residual slots of the last sweep and the
     // item description in one memory round trip
     const int n_items = a.items.n_items[0], one_each = a.items.n_items[1];
@@ -896,6 +951,10 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
     int wb, we;
     wave_range(beg, end, wid, nw, wb, we);
     stage_records<P, double>(rec, a.coefA, pk.coefE, c);
+    const bool dep2 = a.part2 != nullptr;
+    if (dep2)
+        for (int t = threadIdx.x; t < 3 * NA; t += blockDim.x)
+            (&rk[0][0])[t] = a.coefAk0[(size_t)(rec_index(c) - 1) * NA + t];
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     const int32_t *cb = a.cbase + (size_t)c * 3;
     int run0 = cb[0], run1 = cb[1], run2 = cb[2];
@@ -911,6 +970,16 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
     __syncthreads();
     Own<P, double> o1;
     own_from_lds<P, double>(rec, o1);
+    double my[P + 1], mz[P + 1];               // moments of the particles that stay in cell c
+#pragma unroll
+    for (int j = 0; j <= P; ++j) { my[j] = 0.0; mz[j] = 0.0; }
+    // the wave's mover slots: value u of lane l at col[u * WAVE + l] (a constant
+    // stride, so the slots of one lane provably differ)
+    constexpr int NM = 4 * (P + 1);
+    double *const col = mvl + (size_t)wid * NM * WAVE;
+    if (dep2)
+#pragma unroll
+        for (int u = 0; u < NM; ++u) col[u * WAVE + lane] = 0.0;
     // the next row's loads are issued before the current row is computed
     double nx = 0.0, np = 0.0, nd = 0.0;
     int32_t nid = 0;
@@ -940,7 +1009,9 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         La.d = d;
         stage_gather<P, double, false>(o1, La, xi0, c, a.dt_dx, flags);
         double p1, dn;
-        stage_push<P, double>(o1, rec, __ballot(La.s != 0) != 0, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags);
+        const bool anymove = __ballot(La.s != 0) != 0;
+        PushEnd<double> pe;
+        stage_push<P, double>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags, &pe);
         const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
         double xin = xi0 + d;
         if (xin >= (double)M) xin -= (double)M;
@@ -950,6 +1021,55 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         }
         if constexpr (RECORD)
             if (valid && pid % a.rec.stride == a.rec.phase) record_pair<P>(a, o1, c, pid, xi0, p0, d, p1);
+        if (dep2) {
+            // the cell the particle lands in and its coordinate there, as the
+            // particle pass over the new order would take them
+            int dc = c + La.s;
+            dc = dc < 0 ? dc + M : (dc >= M ? dc - M : dc);
+            double tn = xin - (double)dc;
+            wave_flag(flags, !(tn >= 0.0), FLAG_ORDER);
+            wave_flag(flags, !(tn < 1.0), FLAG_ORDER);
+            tn = fmin(fmax(tn, 0.0), 1.0);
+            // a^(0) of the destination cell (per lane if the row has a mover)
+            const double *ky = rk[anymove ? La.s + 1 : 1];
+            const double Aky = horner<P + 1>(ky, tn), Akz = horner<P + 1>(ky + P + 1, tn);
+            const double gk = fsqrt(fma(p1, p1, 1.0) + Aky * Aky + Akz * Akz);
+            const double inv = (valid ? 1.0 : 0.0) * frcp(pe.g11 + gk);
+            const double cy = (Aky + pe.A1y) * inv, cz = (Akz + pe.A1z) * inv;
+            if (anymove) {
+                const double ws = La.s == 0 ? 1.0 : 0.0;
+                double tp = 1.0;
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    my[j] = fma(cy * ws, tp, my[j]);
+                    mz[j] = fma(cz * ws, tp, mz[j]);
+                    tp *= tn;
+                }
+                if (La.s != 0) {   // all loads, then all stores: one LDS round trip
+                    double *mq = col + (La.s > 0 ? 2 * (P + 1) : 0) * WAVE + lane;
+                    double v[2 * (P + 1)];
+#pragma unroll
+                    for (int u = 0; u < 2 * (P + 1); ++u) v[u] = mq[u * WAVE];
+                    tp = 1.0;
+#pragma unroll
+                    for (int j = 0; j <= P; ++j) {
+                        v[j] = fma(cy, tp, v[j]);
+                        v[P + 1 + j] = fma(cz, tp, v[P + 1 + j]);
+                        tp *= tn;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 2 * (P + 1); ++u) mq[u * WAVE] = v[u];
+                }
+            } else {
+                double tp = 1.0;
+#pragma unroll
+                for (int j = 0; j <= P; ++j) {
+                    my[j] = fma(cy, tp, my[j]);
+                    mz[j] = fma(cz, tp, mz[j]);
+                    tp *= tn;
+                }
+            }
+        }
         const unsigned long long b0 = __ballot(t == 0), b1 = __ballot(t == 1), b2 = __ballot(t == 2);
         if (valid) {
             int dest;
@@ -963,6 +1083,48 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         run0 += __popcll(b0);
         run1 += __popcll(b1);
         run2 += __popcll(b2);
+    }
+    if (dep2) {   // block-uniform: every wave of the block takes part in the barriers
+        // wave totals of the moments (movers from their LDS slots; then the
+        // stayers, through the same slots), and lane q < 2 (P+3) forms slot q
+        constexpr int NS1 = 2 * (P + 1);
+        __syncthreads();   // the mover slots are complete
+        const double tm = wave_totals_lds<NM>(col, WAVE, lane);
+        double ty[3][P + 1], tz[3][P + 1];
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            ty[0][j] = readlane_d(tm, j);
+            tz[0][j] = readlane_d(tm, P + 1 + j);
+            ty[2][j] = readlane_d(tm, NS1 + j);
+            tz[2][j] = readlane_d(tm, NS1 + P + 1 + j);
+        }
+        __syncthreads();   // row 0 of the slots (the parts) is read
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            col[j * WAVE + lane] = my[j];
+            col[(P + 1 + j) * WAVE + lane] = mz[j];
+        }
+        __syncthreads();
+        const double ts = wave_totals_lds<NS1>(col, WAVE, lane);
+#pragma unroll
+        for (int j = 0; j <= P; ++j) {
+            ty[1][j] = readlane_d(ts, j);
+            tz[1][j] = readlane_d(ts, P + 1 + j);
+        }
+        constexpr Pieces<P> Bp{};
+        constexpr int NW = P + 3;
+        const int comp = lane / NW, qq = lane % NW;
+        double out = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            // destination c - 1 + d: its slot q (V0 index c - 1 + d - P + q) is slot qq = q + d here
+            const int q = qq - d, m = P - q;
+            const bool in = q >= 0 && q <= P;
+            const int mm = in ? m : 0;
+#pragma unroll
+            for (int j = 0; j <= P; ++j) out += in ? Bp.c[mm][j] * (comp == 0 ? ty[d][j] : tz[d][j]) : 0.0;
+        }
+        if (lane < 2 * NW) a.part2[((size_t)item * nw + wid) * 2 * NW + lane] = out;
     }
     if (flags && lane == 0) atomicOr(&a.st->flags, flags);   // flags is wave-uniform (wave_flag)
 }
@@ -1013,12 +1175,13 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 }
 
 void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
+    const size_t lds = a.part2 ? sizeof(double) * 4 * (P + 1) * (size_t)block : 0;   // mover moments
 #define ECPIC_C(PP)                                                                              \
     case PP:                                                                                     \
         if (a.rec.stride > 0)                                                                    \
-            launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), 0, s, a);  \
+            launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), lds, s, a);  \
         else                                                                                     \
-            launch_k((k_commit_scatter<PP, false>), dim3(grid), dim3(block), 0, s, a); \
+            launch_k((k_commit_scatter<PP, false>), dim3(grid), dim3(block), lds, s, a); \
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C

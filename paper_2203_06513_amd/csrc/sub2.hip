@@ -30,21 +30,6 @@ __device__ __forceinline__ bool prev_converged2(DevStatus *st, int k, double tol
     return false;
 }
 
-// One particle of a Subsystem II iteration: the deposit coefficients
-// c = (A^(k) + A^n)/(gamma^n + gamma^(k)) and its local coordinate.
-template <int P>
-__device__ __forceinline__ void sub2_coef(const double *cn, const double *ck, double t0, double p0, double &cy,
-                                          double &cz) {
-    const double Any = horner<P + 1>(cn, t0), Anz = horner<P + 1>(cn + P + 1, t0);
-    const double Aky = horner<P + 1>(ck, t0), Akz = horner<P + 1>(ck + P + 1, t0);
-    const double q = fma(p0, p0, 1.0);
-    const double gn = fsqrt(q + Any * Any + Anz * Anz);
-    const double gk = fsqrt(q + Aky * Aky + Akz * Akz);
-    const double inv = frcp(gn + gk);
-    cy = (Aky + Any) * inv;
-    cz = (Akz + Anz) * inv;
-}
-
 constexpr int SUB2_BATCH = 4;
 
 // The particle pass.  Each wave takes every nw-th row of 64 particles of the
@@ -116,7 +101,7 @@ __device__ __forceinline__ void sweep_II_item(const SweepIIArgs &a, int item) {
             wave_flag(flags, !(t < 1.0), FLAG_ORDER);
             t = fmin(fmax(t, 0.0), 1.0);
             double cy, cz;
-            sub2_coef<P>(cn, ck, t, pc[b], cy, cz);
+            sub2_coef<P>(cn, cn + P + 1, ck, ck + P + 1, t, pc[b], cy, cz);
             const double wv = valid ? 1.0 : 0.0;
             cy *= wv;
             cz *= wv;
@@ -157,7 +142,9 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_II(SweepIIArgs a) {
 // to form the records of cells b * TILE .. b * TILE + TILE - 1).  The item
 // partials are summed per cell into LDS, the two deposits assembled, and the
 // inverse of (M0^ + r^2 K^) applied as a convolution by four lanes per output
-// (every fourth tap each, combined in a fixed order).
+// (every fourth tap each, combined in a fixed order).  WIDE: iterate 0 from
+// the partials the Subsystem I commit formed (items of the order before the
+// commit; a cell's partial spans V0 indices c-P-1 .. c+1, P+3 per component).
 constexpr int FIELD2_OUT = 64;
 
 // Sum over the WPI wave partials of cell c when item c is cell c, all loads
@@ -187,12 +174,14 @@ __device__ __forceinline__ void cell_partials_one2(const double *part, int c, in
     }
 }
 
-template <int P>
+template <int P, bool WIDE>
 __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     extern __shared__ double smem[];
     __shared__ double ldsm[MAX_WAVES];
     __shared__ int ldsf[MAX_WAVES];
-    constexpr int NA = RecA<P>::N, NS = 2 * (P + 1);
+    constexpr int RL = WIDE ? 1 : 0;           // cells a partial reaches to the right of its V0 range
+    constexpr int NC = P + 1 + 2 * RL;         // slots per component
+    constexpr int NA = RecA<P>::N, NS = 2 * NC;
     constexpr int TILE = FIELD2_OUT - P;
     DevStatus *st = a.st;
     // the status is tested once the loads that do not depend on it are issued
@@ -203,8 +192,8 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     const int j0 = blockIdx.x * TILE - P;
     const int mhi = a.mlo + a.ntaps - 1;
     const int slen = FIELD2_OUT + a.ntaps - 1;   // b on cells [j0 - mhi, j0 - mhi + slen)
-    const int clo = j0 - mhi;                    // b_j needs the partials of cells j .. j+P
-    const int clen = slen + P;
+    const int clo = j0 - mhi - RL;               // b_j needs the partials of cells j-RL .. j+P+RL
+    const int clen = slen + P + 2 * RL;
     double *cp = smem;
     double *Sy = cp + (size_t)clen * NS;
     double *Sz = Sy + slen;
@@ -264,9 +253,9 @@ __global__ void __launch_bounds__(256) k_field_II(FieldIIArgs a) {
     for (int t = threadIdx.x; t < slen; t += blockDim.x) {
         double sy = 0.0, sz = 0.0;
 #pragma unroll
-        for (int r = 0; r <= P; ++r) {   // cell j + r: slot P - r
-            sy += cp[(P - r) * clen + t + r];
-            sz += cp[(P + 1 + (P - r)) * clen + t + r];
+        for (int r = 0; r <= P + 2 * RL; ++r) {   // cell j - RL + r: slot P + 2 RL - r
+            sy += cp[(P + 2 * RL - r) * clen + t + r];
+            sz += cp[(NC + P + 2 * RL - r) * clen + t + r];
         }
         Sy[t] = sy;
         Sz[t] = sz;
@@ -660,8 +649,14 @@ void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArg
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a) {
     const int grid = (M + FIELD2_OUT - P - 1) / (FIELD2_OUT - P);
     const int slen = FIELD2_OUT + a.ntaps - 1;
-    const size_t lds = sizeof(double) * ((size_t)(slen + P) * 2 * (P + 1) + 2 * slen + a.ntaps + 4 * FIELD2_OUT);
-#define ECPIC_F2(PP) case PP: launch_k((k_field_II<PP>), dim3(grid), dim3(256), lds, s, a); break;
+    const int rl = a.wide ? 1 : 0;
+    const size_t lds =
+        sizeof(double) * ((size_t)(slen + P + 2 * rl) * 2 * (P + 1 + 2 * rl) + 2 * slen + a.ntaps + 4 * FIELD2_OUT);
+#define ECPIC_F2(PP)                                                                          \
+    case PP:                                                                                  \
+        if (a.wide) launch_k((k_field_II<PP, true>), dim3(grid), dim3(256), lds, s, a);       \
+        else launch_k((k_field_II<PP, false>), dim3(grid), dim3(256), lds, s, a);             \
+        break;
     switch (P) { ECPIC_F2(2) ECPIC_F2(3) ECPIC_F2(4) ECPIC_F2(5) }
 #undef ECPIC_F2
 }
