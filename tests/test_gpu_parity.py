@@ -375,6 +375,38 @@ def test_item_count_changes_within_steps(case):
     assert abs(H - H0) / H0 <= 1e-12
 
 
+@pytest.mark.parametrize("case", ["dense", "sparse", "quintic"])
+def test_fused_first_field_iterate_matches_separate_pass(case):
+    """Inside ecpic_step the Subsystem I commit forms the particle deposit of the first
+    Subsystem II iterate, each particle into the cell it lands in, and the first field
+    kernel maps cells to it through the item list of the order before the commit; the
+    substep calls run that iterate as a particle pass of its own over the new order.  Both
+    give the same iteration counts and the same state to round-off: with one item per
+    cell, on a sparse order with empty cells (the general item list), and at degree 5."""
+    if case == "sparse":
+        w = workloads.small("sparse", M=64, L=8.0, n=48, dt=0.05, sigma=0.6, amplitude=0.3)
+    elif case == "quintic":
+        w = workloads.get("langmuir64").scaled(degree=5, n_particles=3000, M=32)
+    else:
+        w = workloads.small("dense", M=8, L=2.0, n=16384, dt=0.05, sigma=0.3, amplitude=0.3)
+    arr = workloads.generate(w)
+    nsteps = 3
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        rc, done, gI, gII, _ = c.step(nsteps)
+        fused = c.state()
+    assert rc == 0 and done == nsteps
+    kI, kII = [], []
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(arr)
+        for _ in range(nsteps):
+            kI.append(c.substep_particles()[0])
+            kII.append(c.substep_fields()[0])
+        sep = c.state()
+    assert gI.tolist() == kI and gII.tolist() == kII
+    assert_state_close(fused, sep, w.L, tol=1e-12)
+
+
 def test_not_converged_rolls_back():
     w = workloads.get("langmuir64").scaled(n_particles=2000, kmax=2)
     arr = workloads.generate(w)
