@@ -126,7 +126,7 @@ def test_subsystem_II_one_call(name):
 
 
 @pytest.mark.parametrize("seidel", [0, 1])
-@pytest.mark.parametrize("p", [2, 5])
+@pytest.mark.parametrize("p", [2, 4, 5])
 def test_other_degrees_one_step(p, seidel):
     w = workloads.get("langmuir64").scaled(degree=p, n_particles=3000, M=32)
     arr = workloads.generate(w)
