@@ -11,7 +11,10 @@
 // where b^ is the deposit without the weight.  The particle kernel evaluates
 // A^n and A^(k) as per-cell polynomials (coef.hpp) and accumulates the deposit
 // as moments sum_a c_a t_a^i, turned into the P+1 V0 coefficients once per
-// block.
+// block.  Within a full step the deposit of iterate 0 is formed by the
+// Subsystem I commit (sub1.hip), which holds the new positions and momenta,
+// and the first field kernel reads it (WIDE); the particle kernel then runs
+// from iterate 1 on.
 #include <cstddef>
 
 #include "coef.hpp"
