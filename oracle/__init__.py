@@ -32,7 +32,8 @@ def build(force: bool = True) -> str:
 class Cfg(C.Structure):
     _fields_ = [("L", C.c_double), ("M", C.c_int32), ("p", C.c_int32), ("n", C.c_int64),
                 ("w", C.c_double), ("dt", C.c_double), ("tol", C.c_double),
-                ("kmax", C.c_int32), ("commit_unconverged", C.c_int32), ("seidel", C.c_int32)]
+                ("kmax", C.c_int32), ("commit_unconverged", C.c_int32), ("seidel", C.c_int32),
+                ("splitting", C.c_int32), ("warm_previous", C.c_int32)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -76,13 +77,22 @@ def lib() -> C.CDLL:
         L.orc_particle_map.restype = None
         L.orc_particle_map.argtypes = [P, C.c_double, C.c_double, C.c_double, _D, _D, _D, _D, _D,
                                        _D, _D, C.POINTER(C.c_long), C.POINTER(C.c_int), _D]
+        I32 = C.POINTER(C.c_int32)
         L.orc_substep_I.restype = C.c_int
-        L.orc_substep_I.argtypes = [P, _D, _D, _D, _D, _D, C.POINTER(C.c_int32), _D]
+        L.orc_substep_I.argtypes = [P, _D, _D, _D, _D, _D, I32, _D]
+        L.orc_substep_I_h.restype = C.c_int
+        L.orc_substep_I_h.argtypes = [P, C.c_double, _D, _D, _D, _D, _D, _D, _D, I32, _D]
+        L.orc_substep_I_adjoint.restype = C.c_int
+        L.orc_substep_I_adjoint.argtypes = [P, C.c_double, _D, _D, _D, _D, _D, _D, I32, _D]
+        L.orc_particle_map_adjoint.restype = None
+        L.orc_particle_map_adjoint.argtypes = [P, C.c_double, C.c_double, C.c_double, _D, _D, _D, _D, _D,
+                                               _D, _D, _D]
         L.orc_substep_II.restype = C.c_int
-        L.orc_substep_II.argtypes = [P, _D, _D, _D, _D, _D, _D, C.POINTER(C.c_int32), _D]
+        L.orc_substep_II.argtypes = [P, _D, _D, _D, _D, _D, _D, I32, _D]
+        L.orc_substep_II_h.restype = C.c_int
+        L.orc_substep_II_h.argtypes = [P, C.c_double, _D, _D, _D, _D, _D, _D, I32, _D]
         L.orc_step.restype = C.c_int
-        L.orc_step.argtypes = [P, C.c_int32, _D, _D, _D, _D, _D, _D, _D,
-                               C.POINTER(C.c_int32), C.POINTER(C.c_int32), _D]
+        L.orc_step.argtypes = [P, C.c_int32, _D, _D, _D, _D, _D, _D, _D, I32, I32, I32, _D]
         _lib = L
     return _lib
 
@@ -102,12 +112,12 @@ class Oracle:
     """The oracle bound to one configuration (L, M, p, n, w, dt, tol, kmax)."""
 
     def __init__(self, L, M, p, n, w=None, dt=0.05, tol=1e-13, kmax=50, commit_unconverged=False,
-                 seidel=False):
+                 seidel=False, splitting=0, warm_previous=False):
         if w is None:
             w = L / n if n > 0 else 0.0
         self.cfg = Cfg(float(L), int(M), int(p), int(n), float(w),
                        float(dt), float(tol), int(kmax), int(bool(commit_unconverged)),
-                       int(bool(seidel)))
+                       int(bool(seidel)), int(splitting), int(bool(warm_previous)))
         self._c = C.byref(self.cfg)
 
     @classmethod
@@ -205,26 +215,51 @@ class Oracle:
         lib().orc_solve_gauss(self._c, _ptr(x), _ptr(ex))
         return ex
 
-    def substep_I(self, s):
-        """In place on state dict s (x, p, ex, ay, az). Returns (status, sweeps, residual)."""
+    def substep_I(self, s, h=None, dstart=None, dcommit=None):
+        """In place on state dict s (x, p, ex, ay, az), over time step h (the configured dt
+        if None), from the increments dstart if given (else the explicit start); dcommit
+        (array of n) receives the committed increments.  Returns (status, sweeps, residual)."""
         k = C.c_int32(0); r = C.c_double(0)
-        st = lib().orc_substep_I(self._c, _ptr(s["x"]), _ptr(s["p"]), _ptr(s["ex"]), _ptr(s["ay"]),
-                                 _ptr(s["az"]), C.byref(k), C.byref(r))
+        h = self.cfg.dt if h is None else float(h)
+        ds = None if dstart is None else _f64(dstart)
+        st = lib().orc_substep_I_h(self._c, h, _ptr(s["x"]), _ptr(s["p"]), _ptr(s["ex"]), _ptr(s["ay"]),
+                                   _ptr(s["az"]), _ptr(ds), _ptr(dcommit), C.byref(k), C.byref(r))
         return st, k.value, r.value
 
-    def substep_II(self, s):
+    def substep_I_adjoint(self, s, h=None, dcommit=None):
+        """The adjoint Subsystem I scheme over h, in place.  Returns (status, sweeps, residual)."""
         k = C.c_int32(0); r = C.c_double(0)
-        st = lib().orc_substep_II(self._c, _ptr(s["x"]), _ptr(s["p"]), _ptr(s["ey"]), _ptr(s["ez"]),
-                                  _ptr(s["ay"]), _ptr(s["az"]), C.byref(k), C.byref(r))
+        h = self.cfg.dt if h is None else float(h)
+        st = lib().orc_substep_I_adjoint(self._c, h, _ptr(s["x"]), _ptr(s["p"]), _ptr(s["ex"]), _ptr(s["ay"]),
+                                         _ptr(s["az"]), _ptr(dcommit), C.byref(k), C.byref(r))
+        return st, k.value, r.value
+
+    def particle_map_adjoint(self, x0, p0, P, ay, az, gy, gz, ebar):
+        """One evaluation of the adjoint map: (delta of P, new momentum, its delta)."""
+        arrs = [_f64(a) for a in (ay, az, gy, gz, ebar)]
+        d = C.c_double(0); Pn = C.c_double(0); dn = C.c_double(0)
+        lib().orc_particle_map_adjoint(self._c, float(x0), float(p0), float(P), *[_ptr(a) for a in arrs],
+                                       C.byref(d), C.byref(Pn), C.byref(dn))
+        return d.value, Pn.value, dn.value
+
+    def substep_II(self, s, h=None):
+        k = C.c_int32(0); r = C.c_double(0)
+        h = self.cfg.dt if h is None else float(h)
+        st = lib().orc_substep_II_h(self._c, h, _ptr(s["x"]), _ptr(s["p"]), _ptr(s["ey"]), _ptr(s["ez"]),
+                                    _ptr(s["ay"]), _ptr(s["az"]), C.byref(k), C.byref(r))
         return st, k.value, r.value
 
     def step(self, s, nsteps=1, energies=False):
-        """Lie-Trotter steps in place.  Returns (status, sweeps_I, iters_II, energy[nsteps+1,5])."""
+        """Steps in place (Lie-Trotter, or the symmetric composition with splitting=1).
+        Returns (status, sweeps_I, iters_II, energy[nsteps+1,5]); with splitting=1 the
+        sweeps of the adjoint substeps are kept in self.last_sweeps_I2."""
+        I32 = C.POINTER(C.c_int32)
         kI = np.zeros(nsteps, dtype=np.int32); kII = np.zeros(nsteps, dtype=np.int32)
+        kI2 = np.zeros(nsteps, dtype=np.int32)
         E = np.zeros((nsteps + 1, 5)) if energies else None
         st = lib().orc_step(self._c, int(nsteps), *[_ptr(s[k]) for k in ("x", "p", "ex", "ey", "ez", "ay", "az")],
-                            kI.ctypes.data_as(C.POINTER(C.c_int32)), kII.ctypes.data_as(C.POINTER(C.c_int32)),
-                            _ptr(E))
+                            kI.ctypes.data_as(I32), kII.ctypes.data_as(I32), kI2.ctypes.data_as(I32), _ptr(E))
+        self.last_sweeps_I2 = kI2
         return st, kI, kII, E
 
 

@@ -37,7 +37,19 @@
  *     it has just produced, delta^(k+1), instead of delta^(k); the fixed point is
  *     the same, the contraction per sweep is the square of Jacobi's, and the
  *     commit is x^n + delta^(k+1), e^(k+1) and the momentum re-evaluated from
- *     (delta^(k+1), e^(k+1)).
+ *     (delta^(k+1), e^(k+1));
+ *   - optionally (warm_previous = 1) the iteration of a Subsystem I substep
+ *     starts from the increments the previous substep of the run committed
+ *     (explicit start on the first); the fixed point does not change;
+ *   - the adjoint of the Subsystem I scheme (Section 4.1: the discrete gradient
+ *     with the two coordinates varied in the opposite order, p first at x^n,
+ *     then x at p^{n+1}) is iterated on the new momentum P: each sweep forms the
+ *     increment of P, the new momentum, and the increment of the new momentum,
+ *     deposits the current of that last increment and commits it together with
+ *     the new momentum and e^(k+1);
+ *   - optionally (splitting = 1) a step is the symmetric composition
+ *     Subsystem I over dt/2, Subsystem II over dt, adjoint Subsystem I over dt/2
+ *     (second order in dt); splitting = 0 is the Lie-Trotter step of Section 5.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,6 +67,8 @@ typedef struct {
     int32_t kmax;               /* Picard iteration cap */
     int32_t commit_unconverged; /* test hook: commit after kmax sweeps anyway */
     int32_t seidel;             /* 0: Jacobi map, 1: current from the fresh increment */
+    int32_t splitting;          /* 0: Lie-Trotter (I then II), 1: I(dt/2), II(dt), adjoint I(dt/2) */
+    int32_t warm_previous;      /* 1: Subsystem I starts from the last committed increments */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_ENOTCONV = -3, ORC_ENOMEM = -2 };
@@ -429,10 +443,15 @@ void orc_particle_map(const orc_cfg *c, double x0, double p0, double delta,
     *delta_out = c->dt * (p0 + p1) / (g01 + g11);
 }
 
-/* Solve Subsystem I by Picard iteration; on success x, p, ex hold the new state. */
-int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const double *ay,
-                  const double *az, int32_t *sweeps, double *res)
+/* Solve Subsystem I over the time step h by Picard iteration; on success x, p, ex
+ * hold the new state.  dstart (nullable): initial increments instead of the
+ * explicit h p / gamma; dcommit (nullable): receives the committed increments. */
+int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                    const double *az, const double *dstart, double *dcommit, int32_t *sweeps, double *res)
 {
+    orc_cfg ch = *cfg;
+    ch.dt = h;
+    const orc_cfg *c = &ch;
     int M = c->M;
     int64_t n = c->n;
     double *d = malloc(sizeof(double) * n), *dn = malloc(sizeof(double) * n),
@@ -446,7 +465,7 @@ int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const doub
     orc_apply_G(c, az, gz);
     for (int64_t a = 0; a < n; ++a) {
         double Ay = orc_field0(c, ay, x[a]), Az = orc_field0(c, az, x[a]);
-        d[a] = c->dt * p[a] / sqrt(1.0 + p[a] * p[a] + Ay * Ay + Az * Az);
+        d[a] = dstart ? dstart[a] : c->dt * p[a] / sqrt(1.0 + p[a] * p[a] + Ay * Ay + Az * Az);
     }
     memcpy(ek, ex, sizeof(double) * M);
     int status = ORC_ENOTCONV;
@@ -486,11 +505,13 @@ int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const doub
                     int nj;
                     double lbar[16], pc, dc;
                     orc_particle_map(c, x[a], p[a], dn[a], ay, az, gy, gz, ebar, &pc, &dc, &jlo, &nj, lbar);
+                    if (dcommit) dcommit[a] = dn[a];
                     x[a] = wrap(c, x[a] + dn[a]);
                     p[a] = pc;
                 }
             } else {
                 for (int64_t a = 0; a < n; ++a) {
+                    if (dcommit) dcommit[a] = d[a];
                     x[a] = wrap(c, x[a] + d[a]);
                     p[a] = p1[a];
                 }
@@ -509,6 +530,137 @@ int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const doub
     return status;
 }
 
+/* Subsystem I over the configured step, explicit start. */
+int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const double *ay,
+                  const double *az, int32_t *sweeps, double *res)
+{
+    return orc_substep_I_h(c, c->dt, x, p, ex, ay, az, NULL, NULL, sweeps, res);
+}
+
+/* ------------------------------------------------------------------ */
+/* The adjoint of the Subsystem I scheme (Section 4.1 discrete gradient  */
+/* with the coordinates taken in the other order).                       */
+/* ------------------------------------------------------------------ */
+
+/* The Subsystem I scheme varies x first (at p^n) and then p (at x^{n+1}).  Its
+ * adjoint varies p first, at x^n, then x, at p^{n+1}:
+ *   grad_p H = (gamma(x^n, p^{n+1}) - gamma(x^n, p^n)) / (p^{n+1} - p^n)
+ *            = (p^n + p^{n+1}) / (gamma(x^n, p^n) + gamma(x^n, p^{n+1})),
+ *   grad_x H = (gamma(x^{n+1}, p^{n+1}) - gamma(x^n, p^{n+1})) / (x^{n+1} - x^n)
+ *            = (A(x^{n+1}) + A(x^n)).(A(x^{n+1}) - A(x^n)) / (x^{n+1} - x^n)
+ *              / (gamma(x^n, p^{n+1}) + gamma(x^{n+1}, p^{n+1})),
+ * and the step is delta / h = grad_p H, (p^{n+1} - p^n) / h = lbar.ebar - grad_x H,
+ * with the same line means and field equation as the scheme.  Both gradients
+ * still satisfy the discrete-gradient identity, so energy is conserved exactly
+ * at the fixed point.  Given the iterate P of p^{n+1}, the increment follows
+ * explicitly from the first equation; this evaluates the map once:
+ *   delta = h (p0 + P) / (g(x0, p0) + g(x0, P)),  x1 = x0 + delta,
+ *   P'    = p0 + h [lbar(x0, x1).ebar - (A0 + A1).DA / (g(x0, P) + g(x1, P))],
+ *   delta' = h (p0 + P') / (g(x0, p0) + g(x0, P')),
+ * where DA = (A1 - A0)/(x1 - x0) = sum_j (G a)_j lbar_j. */
+void orc_particle_map_adjoint(const orc_cfg *c, double x0, double p0, double P,
+                              const double *ay, const double *az, const double *gy, const double *gz,
+                              const double *ebar, double *delta_out, double *P_out, double *delta_next)
+{
+    double A0y = orc_field0(c, ay, x0), A0z = orc_field0(c, az, x0);
+    double qa0 = A0y * A0y + A0z * A0z;
+    double g00 = sqrt(1.0 + p0 * p0 + qa0);
+    double g10 = sqrt(1.0 + P * P + qa0);
+    double delta = c->dt * (p0 + P) / (g00 + g10);
+    double x1 = x0 + delta;
+    double A1y = orc_field0(c, ay, x1), A1z = orc_field0(c, az, x1);
+    double g11 = sqrt(1.0 + P * P + A1y * A1y + A1z * A1z);
+    long jlo;
+    double lbar[16];
+    int nj = orc_line_mean(c, x0, x1, &jlo, lbar);
+    double LE = 0.0, LGy = 0.0, LGz = 0.0;
+    for (int k = 0; k < nj; ++k) {
+        long j = imod(jlo + k, c->M);
+        LE += lbar[k] * ebar[j];
+        LGy += lbar[k] * gy[j];
+        LGz += lbar[k] * gz[j];
+    }
+    double F = LE - ((A0y + A1y) * LGy + (A0z + A1z) * LGz) / (g10 + g11);
+    double Pn = p0 + c->dt * F;
+    double g10n = sqrt(1.0 + Pn * Pn + qa0);
+    *delta_out = delta;
+    *P_out = Pn;
+    *delta_next = c->dt * (p0 + Pn) / (g00 + g10n);
+}
+
+/* The adjoint Subsystem I scheme over the time step h, by Picard iteration on
+ * (P, e_x) from P = p^n, e = e_x^n.  Sweep k forms P^(k+1) from (P^(k), e^(k)),
+ * the increment delta^(k+1) of P^(k+1), and deposits the current of
+ * delta^(k+1); e^(k+1) = e_x^n - M1^{-1} J.  The test is the max norm of the
+ * change of the increment and of e; the commit is x^n + delta^(k+1), P^(k+1),
+ * e^(k+1) (position and deposit from one increment: Gauss's law holds
+ * exactly).  dcommit (nullable) receives the committed increments. */
+int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                          const double *az, double *dcommit, int32_t *sweeps, double *res)
+{
+    orc_cfg ch = *cfg;
+    ch.dt = h;
+    const orc_cfg *c = &ch;
+    int M = c->M;
+    int64_t n = c->n;
+    double *P = malloc(sizeof(double) * (n > 0 ? n : 1)), *Pn = malloc(sizeof(double) * (n > 0 ? n : 1)),
+           *dn = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *ek = malloc(sizeof(double) * M), *enew = malloc(sizeof(double) * M),
+           *ebar = malloc(sizeof(double) * M), *J = malloc(sizeof(double) * M),
+           *MJ = malloc(sizeof(double) * M), *gy = malloc(sizeof(double) * M),
+           *gz = malloc(sizeof(double) * M);
+    if (!P || !Pn || !dn || !ek || !enew || !ebar || !J || !MJ || !gy || !gz) return ORC_ENOMEM;
+    orc_apply_G(c, ay, gy);
+    orc_apply_G(c, az, gz);
+    for (int64_t a = 0; a < n; ++a) P[a] = p[a];
+    memcpy(ek, ex, sizeof(double) * M);
+    int status = ORC_ENOTCONV;
+    double r = 0.0;
+    int k;
+    for (k = 0; k < c->kmax; ++k) {
+        for (int j = 0; j < M; ++j) ebar[j] = 0.5 * (ex[j] + ek[j]);
+        memset(J, 0, sizeof(double) * M);
+        double rx = 0.0;
+        for (int64_t a = 0; a < n; ++a) {
+            double dk;
+            orc_particle_map_adjoint(c, x[a], p[a], P[a], ay, az, gy, gz, ebar, &dk, &Pn[a], &dn[a]);
+            long jlo;
+            double lbar[16];
+            int nj = orc_line_mean(c, x[a], x[a] + dn[a], &jlo, lbar);
+            double inc = (x[a] + dn[a]) - x[a];
+            for (int q = 0; q < nj; ++q) J[imod(jlo + q, M)] += c->w * inc * lbar[q];
+            double dd = fabs(dn[a] - dk);
+            if (dd > rx) rx = dd;
+        }
+        orc_solve_M1(c, J, MJ);
+        double re = 0.0;
+        for (int j = 0; j < M; ++j) {
+            enew[j] = ex[j] - MJ[j];
+            double de = fabs(enew[j] - ek[j]);
+            if (de > re) re = de;
+        }
+        r = rx > re ? rx : re;
+        int last = (k == c->kmax - 1);
+        if (r <= c->tol || (last && c->commit_unconverged)) {
+            for (int64_t a = 0; a < n; ++a) {
+                if (dcommit) dcommit[a] = dn[a];
+                x[a] = wrap(c, x[a] + dn[a]);
+                p[a] = Pn[a];
+            }
+            memcpy(ex, enew, sizeof(double) * M);
+            status = (r <= c->tol) ? ORC_OK : ORC_ENOTCONV;
+            ++k;
+            break;
+        }
+        double *t = P; P = Pn; Pn = t;
+        memcpy(ek, enew, sizeof(double) * M);
+    }
+    if (sweeps) *sweeps = k;
+    if (res) *res = r;
+    free(P); free(Pn); free(dn); free(ek); free(enew); free(ebar); free(J); free(MJ); free(gy); free(gz);
+    return status;
+}
+
 /* ------------------------------------------------------------------ */
 /* Subsystem II (Section 4.2): (e_y, e_z, a_y, a_z) with particles fixed. */
 /* ------------------------------------------------------------------ */
@@ -518,9 +670,12 @@ int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const doub
  *   b = sum_a w (A^{n+1}(x_a) + A^n(x_a)) Lambda0(x_a) / (g^n_a + g^{n+1}_a),
  *   a^{n+1} = a^n - dt/2 (e^n + e^{n+1}),
  * with the particle term lagged one iteration and the matrix inverted exactly. */
-int orc_substep_II(const orc_cfg *c, const double *x, const double *p, double *ey, double *ez,
-                   double *ay, double *az, int32_t *iters, double *res)
+int orc_substep_II_h(const orc_cfg *cfg, double h, const double *x, const double *p, double *ey, double *ez,
+                     double *ay, double *az, int32_t *iters, double *res)
 {
+    orc_cfg ch = *cfg;
+    ch.dt = h;
+    const orc_cfg *c = &ch;
     int M = c->M;
     int64_t n = c->n;
     double *Any = malloc(sizeof(double) * n), *Anz = malloc(sizeof(double) * n),
@@ -598,20 +753,33 @@ int orc_substep_II(const orc_cfg *c, const double *x, const double *p, double *e
     return status;
 }
 
+/* Subsystem II over the configured step. */
+int orc_substep_II(const orc_cfg *c, const double *x, const double *p, double *ey, double *ez,
+                   double *ay, double *az, int32_t *iters, double *res)
+{
+    return orc_substep_II_h(c, c->dt, x, p, ey, ez, ay, az, iters, res);
+}
+
 /* ------------------------------------------------------------------ */
-/* One time step: Lie-Trotter composition, Subsystem I then II (Section */
-/* 5); Subsystem III is the identity without spin.  On failure the      */
-/* state is restored to the start of the failing step.                  */
+/* One time step.  splitting = 0: the Lie-Trotter composition of        */
+/* Section 5, Subsystem I then II.  splitting = 1: the symmetric        */
+/* composition Subsystem I over dt/2, II over dt, adjoint I over dt/2.  */
+/* Subsystem III is the identity without spin.  On failure the state   */
+/* is restored to the start of the failing step.  sweeps_I2 (nullable)  */
+/* receives the sweeps of the adjoint substep.                          */
 /* ------------------------------------------------------------------ */
 int orc_step(const orc_cfg *c, int32_t nsteps, double *x, double *p, double *ex, double *ey,
              double *ez, double *ay, double *az, int32_t *sweeps_I, int32_t *iters_II,
-             double *energy_per_step /* nsteps+1 x 5, nullable */)
+             int32_t *sweeps_I2, double *energy_per_step /* nsteps+1 x 5, nullable */)
 {
     int M = c->M;
     int64_t n = c->n;
-    double *sx = malloc(sizeof(double) * n), *sp = malloc(sizeof(double) * n);
+    double *sx = malloc(sizeof(double) * (n > 0 ? n : 1)), *sp = malloc(sizeof(double) * (n > 0 ? n : 1));
     double *sf = malloc(sizeof(double) * 5 * M);
+    double *dprev = c->warm_previous ? malloc(sizeof(double) * (n > 0 ? n : 1)) : NULL;
+    int have_prev = 0;
     int status = ORC_OK;
+    double h = c->splitting ? 0.5 * c->dt : c->dt;
     if (energy_per_step) orc_energy(c, x, p, ex, ey, ez, ay, az, energy_per_step);
     for (int s = 0; s < nsteps; ++s) {
         memcpy(sx, x, sizeof(double) * n);
@@ -619,11 +787,13 @@ int orc_step(const orc_cfg *c, int32_t nsteps, double *x, double *p, double *ex,
         memcpy(sf, ex, sizeof(double) * M); memcpy(sf + M, ey, sizeof(double) * M);
         memcpy(sf + 2 * M, ez, sizeof(double) * M); memcpy(sf + 3 * M, ay, sizeof(double) * M);
         memcpy(sf + 4 * M, az, sizeof(double) * M);
-        int32_t k1 = 0, k2 = 0;
-        int st = orc_substep_I(c, x, p, ex, ay, az, &k1, NULL);
-        if (st == ORC_OK) st = orc_substep_II(c, x, p, ey, ez, ay, az, &k2, NULL);
+        int32_t k1 = 0, k2 = 0, k3 = 0;
+        int st = orc_substep_I_h(c, h, x, p, ex, ay, az, have_prev ? dprev : NULL, dprev, &k1, NULL);
+        if (st == ORC_OK) st = orc_substep_II_h(c, c->dt, x, p, ey, ez, ay, az, &k2, NULL);
+        if (st == ORC_OK && c->splitting) st = orc_substep_I_adjoint(c, h, x, p, ex, ay, az, dprev, &k3, NULL);
         if (sweeps_I) sweeps_I[s] = k1;
         if (iters_II) iters_II[s] = k2;
+        if (sweeps_I2) sweeps_I2[s] = k3;
         if (st != ORC_OK) {
             memcpy(x, sx, sizeof(double) * n);
             memcpy(p, sp, sizeof(double) * n);
@@ -633,8 +803,9 @@ int orc_step(const orc_cfg *c, int32_t nsteps, double *x, double *p, double *ex,
             status = st;
             break;
         }
+        have_prev = dprev != NULL;
         if (energy_per_step) orc_energy(c, x, p, ex, ey, ez, ay, az, energy_per_step + 5 * (s + 1));
     }
-    free(sx); free(sp); free(sf);
+    free(sx); free(sp); free(sf); free(dprev);
     return status;
 }
