@@ -19,6 +19,14 @@
  * All computation of the step runs in HIP kernels on the GPU; there is no CPU
  * fallback, and ecpic_create fails with ECPIC_EDEVICE when no gfx950 device
  * is usable.
+ *
+ * Two choices a particle code usually exposes are fixed here:
+ *   - the particles are re-sorted by cell at every Subsystem I commit (a
+ *     stable three-way merge, since a particle moves at most one cell per
+ *     step), so there is no sort interval to set;
+ *   - every deposit is deterministic (per-wave partial sums assembled per cell
+ *     in a fixed order, no floating-point atomics on the step's path), so two
+ *     runs from one state agree bit for bit.
  */
 #ifndef ECPIC_H
 #define ECPIC_H
@@ -53,6 +61,8 @@ typedef enum {
 /* Initial Picard iterate of Subsystem I. */
 typedef enum {
     ECPIC_WS_EXPLICIT = 0, /* delta^(0) = dt p / gamma(x^n, p^n), e^(0) = e_x^n */
+    ECPIC_WS_PREVIOUS = 1, /* delta^(0) = the increment the previous Subsystem I substep committed
+                              for the same particle (explicit after set_particles), e^(0) = e_x^n */
     ECPIC_WS_MLP = 2       /* delta^(0) from the learned predictor (see ecpic_ws_*) */
 } ecpic_warmstart;
 
@@ -66,6 +76,15 @@ typedef enum {
                              has just produced; commit x^n + delta^(k+1), e^(k+1) and the
                              momentum re-evaluated from both */
 } ecpic_map;
+
+/* Composition of the substeps into a time step. */
+typedef enum {
+    ECPIC_LIE_TROTTER = 0, /* Subsystem I over dt, then II over dt (Section 5; first order) */
+    ECPIC_SYMMETRIC = 1    /* Subsystem I over dt/2, II over dt, then the adjoint of Subsystem I
+                              over dt/2 (ecpic_substep_particles_adjoint): a map composed with
+                              its adjoint around the symmetric Subsystem II, second order; each
+                              substep conserves the discrete energy as in Section 4.1 */
+} ecpic_splitting;
 
 typedef struct {
     double L;                 /* domain length; grid x_j = j L/M (Section 3.1) */
@@ -85,12 +104,22 @@ typedef struct {
                                  before the FP64 ones; 0 => 2.  Ignored for ECPIC_FP64. */
     int32_t sweep_guess;      /* sweeps / iterations enqueued per substep before the first status
                                  read of a step; later steps use what earlier ones needed; 0 => 4 */
+    int32_t waves_per_item;   /* launch shape of the particle passes: 64-lane waves per work item
+                                 (a cell or a slice of at most 2048 of its particles), 1..4;
+                                 0 => chosen from the item count (about four waves per SIMD).
+                                 Results do not depend on it beyond rounding order. */
+    int32_t splitting;        /* ecpic_splitting */
 } ecpic_config;
 
 typedef struct {
     int32_t sweeps;   /* Picard sweeps (Subsystem I) or iterations (Subsystem II) */
     int32_t fp32_sweeps; /* of which in FP32 (precision form) */
     double residual;  /* last max-norm increment (length / field units) */
+    int32_t crossing_queue; /* Subsystem I: nonzero if some sweep redid the particles whose step
+                               crosses a cell boundary through its per-wave queue (degree >= 4 and
+                               at least 1024 particles per wave); 0 for Subsystem II */
+    int32_t sweeps_adjoint; /* ecpic_step with ECPIC_SYMMETRIC, Subsystem I entries: sweeps of the
+                               step's closing adjoint substep (sweeps is the opening one's); else 0 */
 } ecpic_iter_stats;
 
 typedef struct {
@@ -134,23 +163,47 @@ int ecpic_get_fields(ecpic_ctx *ctx, double *ex, double *ey, double *ez, double 
 int ecpic_solve_gauss(ecpic_ctx *ctx);
 
 /* Subsystem I (Section 4.2): solve the implicit discrete-gradient update of
- * (x, p, e_x) with a_perp frozen, by Picard sweeps to picard_tol.  stats may be
- * NULL.  ENOTCONV rolls back to the state before the call. */
-int ecpic_substep_particles(ecpic_ctx *ctx, ecpic_iter_stats *stats);
+ * (x, p, e_x) over time step dt with a_perp frozen, by Picard sweeps to
+ * picard_tol.  0 < dt < L/M (EINVAL otherwise); the configured dt is not
+ * changed.  stats may be NULL.  ENOTCONV rolls back to the state before the
+ * call; ENONFINITE / ECFL leave the state as before the call as well (nothing
+ * is committed), but the caller should set it again before going on. */
+int ecpic_substep_particles(ecpic_ctx *ctx, double dt, ecpic_iter_stats *stats);
 
-/* Subsystem II (Section 4.2): solve the update of (e_y, e_z, a_y, a_z) with the
- * particles frozen, by fixed-point iteration on e_perp with the matrix
- * M0 + dt^2 K / 4 inverted exactly and the particle term lagged.  ENOTCONV
- * rolls back. */
-int ecpic_substep_fields(ecpic_ctx *ctx, ecpic_iter_stats *stats);
+/* The adjoint of the Subsystem I scheme over dt.  The scheme's discrete
+ * gradient (Section 4.1, as used for Subsystem I in Section 4.2) varies x first,
+ * at p^n, then p, at x^{n+1}; the adjoint varies p first, at x^n, then x, at
+ * p^{n+1}:
+ *   delta / dt = (p^n + p^{n+1}) / (gamma(x^n, p^n) + gamma(x^n, p^{n+1})),
+ *   (p^{n+1} - p^n) / dt = lbar.ebar - (A(x^{n+1}) + A(x^n)).DA
+ *                          / (gamma(x^n, p^{n+1}) + gamma(x^{n+1}, p^{n+1})),
+ * with the same line means lbar, difference quotient DA and e_x equation.  It
+ * is the scheme run backwards: ecpic_substep_particles over -dt would undo it.
+ * Iterated on delta (p^{n+1} follows from delta in closed form) by FP64 sweeps
+ * from delta^(0) = dt p / gamma, each depositing the current of the increment
+ * it produces; it commits x^n + delta^(k+1), the momentum that increment stands
+ * for, and e^(k+1), so Gauss's law holds exactly and energy to the tolerance.
+ * Precision form, learned and previous-step starts do not apply; the increment
+ * it commits is kept for a following ECPIC_WS_PREVIOUS start.  Errors as for
+ * ecpic_substep_particles. */
+int ecpic_substep_particles_adjoint(ecpic_ctx *ctx, double dt, ecpic_iter_stats *stats);
 
-/* nsteps Lie-Trotter steps, Subsystem I then II (Section 5; Subsystem III is the
+/* Subsystem II (Section 4.2): solve the update of (e_y, e_z, a_y, a_z) over time
+ * step dt with the particles frozen, by fixed-point iteration on e_perp with the
+ * matrix M0 + dt^2 K / 4 inverted exactly and the particle term lagged.  The
+ * inverse for a dt not seen before is computed once (host DFT, O(M^2)) and kept.
+ * 0 < dt < L/M.  ENOTCONV rolls back. */
+int ecpic_substep_fields(ecpic_ctx *ctx, double dt, ecpic_iter_stats *stats);
+
+/* nsteps time steps composed as cfg.splitting says (Subsystem III is the
  * identity without spin).  per_step_I / per_step_II: arrays of nsteps entries
  * or NULL.  On ENOTCONV the failing step is rolled back and *steps_done (if
- * not NULL) tells how many steps completed.  Steps are enqueued in batches of
- * up to 16, each gated on the device on the one before having committed; a
- * step that needs more sweeps than were enqueued is finished alone and the
- * batch resumes after it, so the result does not depend on the batching. */
+ * not NULL) tells how many steps completed.  Lie-Trotter steps are enqueued in
+ * batches of up to 16, each gated on the device on the one before having
+ * committed; a step that needs more sweeps than were enqueued is finished
+ * alone and the batch resumes after it, so the result does not depend on the
+ * batching.  Symmetric steps run their three substeps one after the other,
+ * with a status read after each. */
 int ecpic_step(ecpic_ctx *ctx, int32_t nsteps, ecpic_iter_stats *per_step_I,
                ecpic_iter_stats *per_step_II, int32_t *steps_done);
 

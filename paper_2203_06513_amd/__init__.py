@@ -5,4 +5,5 @@ The computation lives in the HIP library ``libecpic.so`` (C-ABI in
 ``include/ecpic.h``); this package only builds and binds it.
 """
 from ._lib import (Context, EcpicError, EXPORTS, FP32_MIXED, FP64, MAP_JACOBI, MAP_SEIDEL,  # noqa: F401
-                   WS_EXPLICIT, WS_MLP, LIB_PATH, load)
+                   WS_EXPLICIT, WS_MLP, WS_PREVIOUS, LIE_TROTTER, SYMMETRIC, LIB_PATH, load,
+                   OK, EINVAL, ENOMEM, ENOTCONV, EDEVICE, ENONFINITE, ECFL, ESTATE)

@@ -16,14 +16,16 @@ LIB_PATH = os.environ.get("ECPIC_LIB") or os.path.join(_HERE, "libecpic.so")
 
 OK, EINVAL, ENOMEM, ENOTCONV, EDEVICE, ENONFINITE, ECFL, ESTATE = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
-WS_EXPLICIT, WS_MLP = 0, 2
+WS_EXPLICIT, WS_PREVIOUS, WS_MLP = 0, 1, 2
 MAP_JACOBI, MAP_SEIDEL = 0, 1
+LIE_TROTTER, SYMMETRIC = 0, 1
 
 # Every symbol include/ecpic.h declares.
 EXPORTS = (
     "ecpic_create", "ecpic_destroy", "ecpic_set_particles", "ecpic_get_particles",
     "ecpic_set_particles_dev", "ecpic_get_particles_dev", "ecpic_set_fields", "ecpic_get_fields",
-    "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_fields", "ecpic_step",
+    "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_particles_adjoint", "ecpic_substep_fields",
+    "ecpic_step",
     "ecpic_deposit_current", "ecpic_deposit_charge", "ecpic_energy", "ecpic_gauss_residual",
     "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_bandwidth_probe", "ecpic_strerror",
     "ecpic_ws_record", "ecpic_ws_records", "ecpic_ws_get_records", "ecpic_ws_train", "ecpic_ws_n_params",
@@ -42,11 +44,12 @@ class Config(C.Structure):
                 ("weight", C.c_double), ("dt", C.c_double), ("picard_tol", C.c_double),
                 ("picard_max_iter", C.c_int32), ("precision", C.c_int32), ("warmstart", C.c_int32),
                 ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32),
-                ("sweep_guess", C.c_int32)]
+                ("sweep_guess", C.c_int32), ("waves_per_item", C.c_int32), ("splitting", C.c_int32)]
 
 
 class IterStats(C.Structure):
-    _fields_ = [("sweeps", C.c_int32), ("fp32_sweeps", C.c_int32), ("residual", C.c_double)]
+    _fields_ = [("sweeps", C.c_int32), ("fp32_sweeps", C.c_int32), ("residual", C.c_double),
+                ("crossing_queue", C.c_int32), ("sweeps_adjoint", C.c_int32)]
 
 
 class WsTrainConfig(C.Structure):
@@ -62,6 +65,18 @@ _lib: Optional[C.CDLL] = None
 _D = C.POINTER(C.c_double)
 
 
+def _one_hip_runtime():
+    """PyTorch for ROCm ships its own HIP runtime library under a name that does not match
+    the one the library links; loaded after the library, it would be a second runtime in
+    the process, whose streams and allocations the library's runtime does not know.  When
+    torch is installed it is therefore imported first, so the library binds to the
+    runtime torch already holds and a torch stream or tensor can be handed over."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
 def load() -> C.CDLL:
     """Load the in-tree HIP library; raise if it has not been built."""
     global _lib
@@ -69,6 +84,7 @@ def load() -> C.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2203_06513_amd/build.py "
                                "(or __graft_entry__.build())")
+        _one_hip_runtime()
         L = C.CDLL(LIB_PATH)
         V = C.c_void_p
         L.ecpic_create.argtypes = [C.POINTER(Config), C.POINTER(V)]
@@ -79,8 +95,9 @@ def load() -> C.CDLL:
         L.ecpic_set_fields.argtypes = [V, V, V, V, V, V]
         L.ecpic_get_fields.argtypes = [V, V, V, V, V, V]
         L.ecpic_solve_gauss.argtypes = [V]
-        L.ecpic_substep_particles.argtypes = [V, C.POINTER(IterStats)]
-        L.ecpic_substep_fields.argtypes = [V, C.POINTER(IterStats)]
+        L.ecpic_substep_particles.argtypes = [V, C.c_double, C.POINTER(IterStats)]
+        L.ecpic_substep_particles_adjoint.argtypes = [V, C.c_double, C.POINTER(IterStats)]
+        L.ecpic_substep_fields.argtypes = [V, C.c_double, C.POINTER(IterStats)]
         L.ecpic_step.argtypes = [V, C.c_int32, C.POINTER(IterStats), C.POINTER(IterStats), C.POINTER(C.c_int32)]
         L.ecpic_deposit_current.argtypes = [V, V, V, C.c_int64, V]
         L.ecpic_deposit_charge.argtypes = [V, V]
@@ -137,11 +154,14 @@ class Context:
     def __init__(self, L: float, M: int, degree: int, n_particles: int, dt: float, tol: float,
                  weight: float = 0.0, max_iter: int = 0, precision: int = FP64,
                  warmstart: int = WS_EXPLICIT, map: int = MAP_JACOBI, device: int = 0,
-                 stream: Optional[int] = None, fp32_sweeps: int = 0, sweep_guess: int = 0):
+                 stream: Optional[int] = None, fp32_sweeps: int = 0, sweep_guess: int = 0,
+                 waves_per_item: int = 0, splitting: int = LIE_TROTTER):
         self._lib = load()
         self.cfg = Config(float(L), int(M), int(degree), int(n_particles), float(weight), float(dt),
                           float(tol), int(max_iter), int(precision), int(warmstart), int(map), int(device),
-                          C.c_void_p(stream) if stream else None, int(fp32_sweeps), int(sweep_guess))
+                          C.c_void_p(stream) if stream else None, int(fp32_sweeps), int(sweep_guess),
+                          int(waves_per_item), int(splitting))
+        self.dt = float(dt)
         self.M = int(M)
         self.N = int(n_particles)
         h = C.c_void_p()
@@ -217,17 +237,29 @@ class Context:
     def solve_gauss(self):
         _ck(self._lib.ecpic_solve_gauss(self._h), "solve_gauss")
 
-    def substep_particles(self):
-        """Returns (sweeps, residual); last_stats_I keeps (sweeps, fp32_sweeps, residual)."""
+    def substep_particles(self, dt: Optional[float] = None, check: bool = True):
+        """Subsystem I over dt (the configured step if None).  Returns (sweeps, residual);
+        last_stats_I keeps (sweeps, fp32_sweeps, residual, crossing_queue, status)."""
         st = IterStats()
-        rc = self._lib.ecpic_substep_particles(self._h, C.byref(st))
-        _ck(rc, "substep_particles")
-        self.last_stats_I = (st.sweeps, st.fp32_sweeps, st.residual)
+        rc = self._lib.ecpic_substep_particles(self._h, self.dt if dt is None else float(dt), C.byref(st))
+        self.last_stats_I = (st.sweeps, st.fp32_sweeps, st.residual, st.crossing_queue, rc)
+        if check:
+            _ck(rc, "substep_particles")
         return st.sweeps, st.residual
 
-    def substep_fields(self):
+    def substep_particles_adjoint(self, dt: Optional[float] = None, check: bool = True):
+        """The adjoint Subsystem I scheme over dt.  Returns (sweeps, residual)."""
         st = IterStats()
-        rc = self._lib.ecpic_substep_fields(self._h, C.byref(st))
+        rc = self._lib.ecpic_substep_particles_adjoint(self._h, self.dt if dt is None else float(dt),
+                                                       C.byref(st))
+        self.last_stats_I = (st.sweeps, st.fp32_sweeps, st.residual, st.crossing_queue, rc)
+        if check:
+            _ck(rc, "substep_particles_adjoint")
+        return st.sweeps, st.residual
+
+    def substep_fields(self, dt: Optional[float] = None):
+        st = IterStats()
+        rc = self._lib.ecpic_substep_fields(self._h, self.dt if dt is None else float(dt), C.byref(st))
         _ck(rc, "substep_fields")
         return st.sweeps, st.residual
 
@@ -242,6 +274,8 @@ class Context:
         kI = np.array([sI[i].sweeps for i in range(nsteps)], dtype=np.int32)
         kII = np.array([sII[i].sweeps for i in range(nsteps)], dtype=np.int32)
         k32 = np.array([sI[i].fp32_sweeps for i in range(nsteps)], dtype=np.int32)
+        self.last_queue_I = np.array([sI[i].crossing_queue for i in range(nsteps)], dtype=np.int32)
+        self.last_sweeps_I2 = np.array([sI[i].sweeps_adjoint for i in range(nsteps)], dtype=np.int32)
         return rc, done.value, kI, kII, k32
 
     # -- diagnostics ------------------------------------------------------------

@@ -6,6 +6,15 @@
 
 #include "internal.hpp"
 
+// Instantiate CALL(P) for the spline degrees the library is built for.
+#define ECPIC_DISPATCH(P, CALL) \
+    switch (P) {                \
+        case 2: CALL(2); break; \
+        case 3: CALL(3); break; \
+        case 4: CALL(4); break; \
+        case 5: CALL(5); break; \
+    }
+
 namespace ecpic {
 
 constexpr int WAVE = 64;
@@ -128,6 +137,7 @@ __device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate
     st->flags = 0;
     st->fp32_sweeps = 0;
     st->scan_multi = 0;
+    st->queued = 0;
     st->res = 0.0;
     st->gate = gate_src ? (gate_src->committed && gate_src->flags == 0) : 1;
 }

@@ -27,6 +27,10 @@ constexpr int MAX_CHUNK = 2048;   // particles of one work item (one cell or a p
 
 // Error bits raised by kernels.
 enum : int32_t { FLAG_NONFINITE = 1, FLAG_CFL = 2, FLAG_ORDER = 4 };
+// Not an error: a sweep's wave partials carry it when the wave redid crossing
+// lanes through its queue; the field kernel moves it into DevStatus::queued.
+constexpr int32_t FLAG_QUEUED = 8;
+constexpr int32_t FLAG_ERRORS = FLAG_NONFINITE | FLAG_CFL | FLAG_ORDER;
 
 // Picard bookkeeping of one substep, device-resident.  The host enqueues
 // sweeps with their index k; sweep k first decides whether sweep k-1 already met
@@ -45,6 +49,7 @@ struct DevStatus {
     int32_t fp32_sweeps;             // sweeps done in FP32 (precision form)
     int32_t n_items_next;            // item count of the re-sorted particles (Subsystem I commit)
     int32_t scan_multi;              // a field kernel of the substep saw a cell with other than one item
+    int32_t queued;                  // some sweep of the substep redid crossing lanes through its queue
     double res;                      // residual of sweep kconv (length / field units)
     double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
@@ -101,7 +106,9 @@ struct SweepIArgs {
                                    // of the increment a commit after this sweep would take
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
+    double dx_dt;                  // 1 / dt_dx (the adjoint scheme's velocity from an increment)
     int32_t explicit_start;        // 1: d^(0) = dt p / gamma; 0: d^(0) read from d0
+    const double *dprev;           // non-null: d^(0) is the increment the last commit took (same order)
     int32_t k;                     // sweep index
     int32_t first64;               // index of the first FP64 sweep (0 for the plain method)
     // predictor pass of the learned warm start
@@ -148,6 +155,7 @@ struct CommitIArgs {
     int32_t *nstart;               // [2M + 1]: new start of each cell, N, new count of each cell
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
+    double dx_dt;                  // 1 / dt_dx
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
     int32_t first64;               // index of the first FP64 sweep
@@ -156,6 +164,7 @@ struct CommitIArgs {
     const double *coefAk0;         // A-records of a^(0) = a^n - dt e^n
     double *part2;                 // [items][waves per item][2 (deg+3)], by the current item list
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
+    double *dprev_out;             // non-null: the committed increment, in the new order
     int64_t N;
 };
 

@@ -316,6 +316,16 @@ __global__ void __launch_bounds__(256) k_count_cells(const int32_t *key, int64_t
     if (i < n) atomicAdd(&count[key[i]], 1);
 }
 
+// Particles per cell of a cell-sorted order (xi in [0, M)), for an item list
+// rebuilt from the particles alone.
+__global__ void __launch_bounds__(256) k_count_cells_xi(const double *xi, int64_t n, int M, int32_t *count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = xi[i];
+    const int c = v >= 0.0 && v < (double)M ? (int)v : 0;
+    atomicAdd(&count[c], 1);
+}
+
 __global__ void __launch_bounds__(1024) k_items_from_counts(const int32_t *count, int32_t *start, int M, int chunk,
                                                             int64_t N, ItemList out) {
     __shared__ int lds[40];
@@ -363,14 +373,6 @@ __global__ void __launch_bounds__(256) k_copy(const double2 *in, double2 *out, i
 }
 
 // ---- launchers ------------------------------------------------------------
-#define ECPIC_DISPATCH(P, CALL) \
-    switch (P) {                \
-        case 2: CALL(2); break; \
-        case 3: CALL(3); break; \
-        case 4: CALL(4); break; \
-        case 5: CALL(5); break; \
-    }
-
 void launch_energy(int P, int grid, int block, hipStream_t s, const double *xi, const double *p, ItemList items,
                    const double *ay, const double *az, double *part) {
 #define CALL(PP) launch_k((k_energy_part<PP>), dim3(grid), dim3(block), 0, s, xi, p, items, ay, az, part)
@@ -452,6 +454,11 @@ void launch_gather_sorted(hipStream_t s, const int32_t *val, const double *xi_t,
 void launch_count_cells(hipStream_t s, const int32_t *key, int64_t n, int32_t *count) {
     if (n > 0)
         launch_k(k_count_cells, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, key, n, count);
+}
+
+void launch_count_cells_xi(hipStream_t s, const double *xi, int64_t n, int M, int32_t *count) {
+    if (n > 0)
+        launch_k(k_count_cells_xi, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, xi, n, M, count);
 }
 
 void launch_items_from_counts(hipStream_t s, const int32_t *count, int32_t *start, int M, int chunk, int64_t N,

@@ -23,9 +23,10 @@
 #include "internal.hpp"
 
 namespace ecpic {
-void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a);
+void launch_sweep_I(int P, bool seidel, bool fp32, bool adj, int grid, int block, hipStream_t s,
+                    const SweepIArgs &a);
 void launch_field_I(int P, int M, hipStream_t s, const FieldIArgs &a);
-void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a);
+void launch_commit_I(int P, bool adj, int grid, int block, hipStream_t s, const CommitIArgs &a);
 void launch_sweep_II(int P, int grid, int block, hipStream_t s, const SweepIIArgs &a);
 void launch_field_II(int P, int M, hipStream_t s, const FieldIIArgs &a);
 void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, const double *az,
@@ -68,6 +69,7 @@ void radix_sort(hipStream_t s, int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v
 void launch_gather_sorted(hipStream_t s, const int32_t *val, const double *xi_t, const double *p_t, int64_t n,
                           double *xi, double *p, int32_t *id);
 void launch_count_cells(hipStream_t s, const int32_t *key, int64_t n, int32_t *count);
+void launch_count_cells_xi(hipStream_t s, const double *xi, int64_t n, int M, int32_t *count);
 void launch_items_from_counts(hipStream_t s, const int32_t *count, int32_t *start, int M, int chunk, int64_t N,
                               ItemList out);
 void launch_unpermute(hipStream_t s, const double *xi, const double *p, const int32_t *id, int64_t n, double dx,
@@ -176,6 +178,7 @@ struct Prof {
 
 namespace ecpic {
 constexpr int STEP_BATCH = 16;   // steps enqueued before the host reads their statuses
+constexpr int MAX_WAVES_PER_ITEM = 4;
 thread_local LaunchEvents g_launch_events;
 }
 
@@ -223,6 +226,13 @@ struct ecpic_ctx {
     double *coefA = nullptr, *coefE[2]{}, *coefAk[2]{};
     double *taps1 = nullptr, *tapsA = nullptr;
     int nt1 = 0, mlo1 = 0, ntA = 0, mloA = 0;
+    // (M0 + dt^2 K / 4)^{-1} taps of every time step Subsystem II has run with
+    // (tapsA, ntA, mloA point at those of the current dt)
+    struct Taps {
+        double *dev;
+        int n, mlo;
+    };
+    std::map<double, Taps> tapsA_by_dt;
     std::vector<double> m0row, m1row, krow;
 
     // Statuses of up to STEP_BATCH steps enqueued ahead, pair by pair (Subsystem
@@ -239,14 +249,23 @@ struct ecpic_ctx {
     static_assert(offsetof(HostMirror, II) == sizeof(DevStatus), "statuses are copied as one block");
 
     double *rho = nullptr, *rvec = nullptr, *uvec = nullptr, *out5 = nullptr, *part_e = nullptr;
+    double *ex_save = nullptr;   // e_x at the start of a symmetric step (its rollback)
+    bool symmetric = false;      // steps are I(dt/2), II(dt), adjoint I(dt/2)
     unsigned long long *maxbits = nullptr;
     int32_t *count = nullptr;
     bool have_particles = false;
-    int guessI = 4, guessII = 4;
+    // previous-step warm start: the increment each commit took, in the new order
+    bool ws_prev = false;
+    double *dprev = nullptr;
+    bool have_prev = false;   // dprev holds the increments of the current order
+    int guessI = 4, guessII = 4, guessIadj = 4;
     bool exact_items = true;   // n_items_host is the item count of the step being enqueued
     // inside ecpic_step: the Subsystem I commit forms the particle deposit of
     // the first Subsystem II iterate, which then has no particle pass of its own
     bool fuse_II = false;
+    // the Subsystem I substep being enqueued is the adjoint scheme (FP64 sweeps
+    // from the explicit start, Seidel map)
+    bool adjoint = false;
     int kI = 0, kII = 0;   // sweeps / iterations enqueued in the current substeps
     Prof prof;
 };
@@ -332,12 +351,18 @@ SweepIArgs sweep_args(ecpic_ctx *c) {
     a.st = c->stI;
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
+    a.dx_dt = c->dx / c->dt;
     a.inv_dx = c->inv_dx;
     a.dx = c->dx;
     a.tol = c->tol;
     a.explicit_start = 1;
     return a;
 }
+
+// Index of the first FP64 sweep of a Subsystem I substep: after the predictor
+// pass (learned warm start) and the FP32 sweeps (precision form); the adjoint
+// substep has neither.
+int first64_of(const ecpic_ctx *c) { return c->adjoint ? 0 : (c->ws_on ? 1 : 0) + c->k32; }
 
 void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     SweepIArgs a = sweep_args(c);
@@ -364,11 +389,12 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
     f.ex_next = c->ex[c->exc ^ 1];
     f.chunk = c->chunk;
     const int gridp = particle_grid(c, c->exact_items);
-    const int mlp = c->ws_on ? 1 : 0;
-    const int first64 = mlp + c->k32;
+    const int mlp = (c->ws_on && !c->adjoint) ? 1 : 0;
+    const int first64 = first64_of(c);
     a.first64 = first64;
     f.first64 = first64;
-    a.explicit_start = !mlp;
+    a.dprev = (!mlp && !c->adjoint && c->ws_prev && c->have_prev) ? c->dprev : nullptr;
+    a.explicit_start = !mlp && !a.dprev;
     a.ws = WsNet{c->ws_theta, c->ws_norm, c->ws_norm + (c->wsD + 2), c->ws_norm + 2 * (c->wsD + 2)};
     a.ws_table = c->ws_table;
     for (int i = 0; i < count; ++i) {
@@ -377,9 +403,10 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
             timed(c, "ws_predict", [&] { launch_ws_predict(c->P, gridp, c->block, c->stream, a); });
         } else {
             const bool fp32 = a.k < first64;
-            a.d32in = (c->k32 > 0 && a.k == first64) ? c->fbuf[first64 & 1] : nullptr;
-            timed(c, fp32 ? "sweep_I32" : "sweep_I",
-                  [&] { launch_sweep_I(c->P, c->seidel, fp32, gridp, c->block, c->stream, a); });
+            a.d32in = (c->k32 > 0 && !c->adjoint && a.k == first64) ? c->fbuf[first64 & 1] : nullptr;
+            timed(c, c->adjoint ? "sweep_I_adj" : (fp32 ? "sweep_I32" : "sweep_I"), [&] {
+                launch_sweep_I(c->P, c->seidel || c->adjoint, fp32, c->adjoint, gridp, c->block, c->stream, a);
+            });
         }
         timed(c, "field_I", [&] { launch_field_I(c->P, c->M, c->stream, f); });
     }
@@ -389,9 +416,10 @@ void enqueue_sweeps_I(ecpic_ctx *c, int count) {
 // counted) and how many of them ran in FP32.
 int sweeps_done_I(const ecpic_ctx *c) {
     const int n = c->h->I.kconv >= 0 ? c->h->I.kconv + 1 : c->kI;
-    return c->ws_on ? n - 1 : n;
+    return (c->ws_on && !c->adjoint) ? n - 1 : n;
 }
 int fp32_sweeps_done_I(const ecpic_ctx *c) {
+    if (c->adjoint) return 0;
     return std::min(std::max(c->kI - (c->ws_on ? 1 : 0), 0), c->k32);
 }
 
@@ -414,22 +442,23 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.st = c->stI;
     a.dt = c->dt;
     a.dt_dx = c->dt / c->dx;
+    a.dx_dt = c->dx / c->dt;
     a.inv_dx = c->inv_dx;
     a.dx = c->dx;
     a.tol = c->tol;
     a.M = c->M;
     a.chunk = c->chunk;
-    a.seidel = c->seidel;
+    a.seidel = c->seidel || c->adjoint;
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
-    a.first64 = (c->ws_on ? 1 : 0) + c->k32;
+    a.first64 = first64_of(c);
     // the last known order decides where a list with several items per cell is built
     a.list_kernel = c->n_items_host != c->M ? 1 : 0;
-    if (c->fuse_II) {
+    if (c->fuse_II && !c->adjoint) {
         a.coefAk0 = c->coefAk[0];   // a^(0), formed by the step's start
         a.part2 = c->part;
     }
-    if (c->ws_stride > 0 && c->ws_feat) {   // record training pairs of this step
+    if (c->ws_stride > 0 && c->ws_feat && !c->adjoint) {   // record training pairs of this step
         a.rec.feat = c->ws_feat;
         a.rec.targ = c->ws_targ;
         a.rec.cap = c->ws_cap;
@@ -441,7 +470,12 @@ void enqueue_commit_I(ecpic_ctx *c) {
         a.rec.ex = c->ex[c->exc];
     }
     a.N = c->N;
-    timed(c, "commit_I", [&] { launch_commit_I(c->P, particle_grid(c, c->exact_items), c->block, c->stream, a); });
+    if (c->ws_prev) {   // the next substep starts from this commit's increments
+        a.dprev_out = c->dprev;
+        c->have_prev = true;
+    }
+    timed(c, c->adjoint ? "commit_I_adj" : "commit_I",
+          [&] { launch_commit_I(c->P, c->adjoint, particle_grid(c, c->exact_items), c->block, c->stream, a); });
 }
 
 // ---- Subsystem II ---------------------------------------------------------
@@ -596,6 +630,63 @@ int finish_II(ecpic_ctx *c, const IIView &v) {
     }
 }
 
+// A substep call with its own time step: dt (and with Subsystem II the
+// matrix taps of that step) hold for the call, the configured ones after it.
+struct DtScope {
+    ecpic_ctx *c;
+    double dt;
+    double *taps;
+    int n, mlo;
+    explicit DtScope(ecpic_ctx *x) : c(x), dt(x->dt), taps(x->tapsA), n(x->ntA), mlo(x->mloA) {}
+    ~DtScope() {
+        c->dt = dt;
+        c->tapsA = taps;
+        c->ntA = n;
+        c->mloA = mlo;
+    }
+};
+
+// One Subsystem I substep over dt on its own (the scheme, or its adjoint):
+// start, the expected number of sweeps, commit, one status read, more sweeps if
+// needed.  Nothing is committed on failure.
+int substep_I(ecpic_ctx *c, double dt, ecpic_iter_stats *stats, bool adjoint) {
+    if (!c || !(dt > 0.0) || !(dt < c->dx)) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    DtScope scope(c);
+    c->dt = dt;
+    struct Adj {
+        ecpic_ctx *c;
+        Adj(ecpic_ctx *x, bool on) : c(x) { c->adjoint = on; }
+        ~Adj() { c->adjoint = false; }
+    } adj(c, adjoint);
+    const bool had_prev = c->have_prev;
+    int &guess = adjoint ? c->guessIadj : c->guessI;
+    enqueue_begin(c, true, false);
+    enqueue_sweeps_I(c, std::min(guess, c->kmax));
+    enqueue_commit_I(c);
+    int rc = read_status(c, false);
+    bool again = false;
+    if (!rc) rc = finish_I(c, &again);
+    if (stats) {
+        stats->sweeps = sweeps_done_I(c);
+        stats->fp32_sweeps = fp32_sweeps_done_I(c);
+        stats->residual = c->h->I.res;
+        stats->crossing_queue = c->h->I.queued;
+    }
+    if (rc) {
+        c->have_prev = had_prev;   // no commit: the increments are those of before
+        return rc;
+    }
+    guess = std::max(1, c->h->I.kconv + 1);
+    c->cur ^= 1;
+    c->icur ^= 1;
+    c->exc ^= 1;
+    c->n_items_host = c->h->I.n_items_next;
+    if (!adjoint) advance_records(c);
+    return ECPIC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -641,16 +732,44 @@ void free_all(ecpic_ctx *c) {
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
     F(c->wcnt); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
-    F(c->E0y); F(c->E0z); F(c->taps1); F(c->tapsA);
+    F(c->E0y); F(c->E0z); F(c->taps1); F(c->dprev);
+    for (auto &t : c->tapsA_by_dt) F(t.second.dev);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
     F(c->ws_theta); F(c->ws_m); F(c->ws_v); F(c->ws_norm); F(c->ws_table); F(c->ws_feat); F(c->ws_targ);
     F(c->ws_pgrad); F(c->ws_ploss); F(c->ws_loss); F(c->ws_w2b);
-    F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count);
+    F(c->rho); F(c->rvec); F(c->uvec); F(c->out5); F(c->part_e); F(c->maxbits); F(c->count); F(c->ex_save);
     if (c->h_ring) hipHostFree(c->h_ring);
     for (auto &e : c->prof.pool) hipEventDestroy(e);
     for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
     if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+}
+
+// The first row of (M0^ + r^2 K^)^{-1}, r = dt / (2 dx), the Subsystem II
+// matrix of time step dt, made current; computed once per time step and kept
+// for the context's lifetime.
+int select_tapsA(ecpic_ctx *c, double dt) {
+    auto it = c->tapsA_by_dt.find(dt);
+    if (it == c->tapsA_by_dt.end()) {
+        std::vector<double> tA, arow(2 * c->P + 1);
+        const double r = dt / (2.0 * c->dx);
+        for (int k = 0; k <= 2 * c->P; ++k) arow[k] = c->m0row[k] + r * r * c->krow[k];
+        int mlo = 0;
+        inverse_taps(arow, c->M, 1e-18, tA, mlo);
+        double *d = nullptr;
+        if (dalloc(&d, tA.size())) return ECPIC_ENOMEM;
+        if (hipMemcpyAsync(d, tA.data(), sizeof(double) * tA.size(), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            hipFree(d);
+            return ECPIC_EDEVICE;
+        }
+        it = c->tapsA_by_dt.emplace(dt, ecpic_ctx::Taps{d, (int)tA.size(), mlo}).first;
+    }
+    c->tapsA = it->second.dev;
+    c->ntA = it->second.n;
+    c->mloA = it->second.mlo;
+    return ECPIC_OK;
 }
 
 int alloc_all(ecpic_ctx *c) {
@@ -679,6 +798,7 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->coefAk[0], nrec * 2 * (c->P + 1)); rc |= dalloc(&c->coefAk[1], nrec * 2 * (c->P + 1));
     rc |= dalloc(&c->coefE[0], nrec * c->P); rc |= dalloc(&c->coefE[1], nrec * c->P);
     rc |= dalloc(&c->st_ring, 2 * STEP_BATCH);
+    if (c->ws_prev) rc |= dalloc(&c->dprev, N);
     c->wsD = ws_d(c->P);
     c->wsNP = ws_nparams(c->wsD);
     rc |= dalloc(&c->ws_theta, c->wsNP); rc |= dalloc(&c->ws_m, c->wsNP); rc |= dalloc(&c->ws_v, c->wsNP);
@@ -688,6 +808,7 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
     rc |= dalloc(&c->count, M);
+    if (c->symmetric) rc |= dalloc(&c->ex_save, MP);
     if (rc) return ECPIC_ENOMEM;
     if (hipHostMalloc((void **)&c->h_ring, sizeof(*c->h_ring) * STEP_BATCH, hipHostMallocMapped) != hipSuccess)
         return ECPIC_ENOMEM;
@@ -710,17 +831,14 @@ int alloc_all(ecpic_ctx *c) {
         auto m = [&](int q) { return (q >= -(c->P - 1) && q <= c->P - 1) ? c->m1row[q + c->P - 1] : 0.0; };
         c->krow[k + c->P] = 2.0 * m(k) - m(k - 1) - m(k + 1);
     }
-    std::vector<double> t1, tA, arow(2 * c->P + 1);
+    std::vector<double> t1;
     inverse_taps(c->m1row, M, 1e-18, t1, c->mlo1);
-    const double r = c->dt / (2.0 * c->dx);
-    for (int k = 0; k <= 2 * c->P; ++k) arow[k] = c->m0row[k] + r * r * c->krow[k];
-    inverse_taps(arow, M, 1e-18, tA, c->mloA);
     c->nt1 = (int)t1.size();
-    c->ntA = (int)tA.size();
-    if (dalloc(&c->taps1, t1.size()) || dalloc(&c->tapsA, tA.size())) return ECPIC_ENOMEM;
+    if (dalloc(&c->taps1, t1.size())) return ECPIC_ENOMEM;
     HIPCHK(hipMemcpyAsync(c->taps1, t1.data(), sizeof(double) * t1.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipMemcpyAsync(c->tapsA, tA.data(), sizeof(double) * tA.size(), hipMemcpyHostToDevice, c->stream));
-    return sync(c);
+    rc = sync(c);
+    if (rc) return rc;
+    return select_tapsA(c, c->dt);
 }
 
 int upload_padded(ecpic_ctx *c, const double *host, double *dev_pad) {
@@ -771,6 +889,7 @@ int load_particles_dev(ecpic_ctx *c, const double *x, const double *p) {
     for (void *q : {(void *)k0, (void *)v0, (void *)k1, (void *)v1, (void *)hist, (void *)xt, (void *)pt})
         if (q) hipFree(q);
     if (rc == ECPIC_OK) c->have_particles = true;
+    c->have_prev = false;   // a new order: no previous increments
     return rc;
 }
 
@@ -787,7 +906,9 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
         g.picard_max_iter < 0 || (g.precision != ECPIC_FP64 && g.precision != ECPIC_FP32_MIXED) ||
         g.fp32_sweeps < 0 || g.fp32_sweeps > 16 || g.sweep_guess < 0 ||
         (g.map != ECPIC_MAP_JACOBI && g.map != ECPIC_MAP_SEIDEL) ||
-        (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_MLP) || g.weight < 0.0)
+        (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_PREVIOUS && g.warmstart != ECPIC_WS_MLP) ||
+        g.weight < 0.0 || g.waves_per_item < 0 || g.waves_per_item > MAX_WAVES_PER_ITEM ||
+        (g.splitting != ECPIC_LIE_TROTTER && g.splitting != ECPIC_SYMMETRIC))
         return ECPIC_EINVAL;
     int rc = check_device(g.device);
     if (rc) return rc;
@@ -808,13 +929,17 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->seidel = g.map == ECPIC_MAP_SEIDEL;
     c->k32 = g.precision == ECPIC_FP32_MIXED ? (g.fp32_sweeps > 0 ? g.fp32_sweeps : 2) : 0;
     c->guessI = c->guessII = g.sweep_guess > 0 ? g.sweep_guess : 4;
+    c->ws_prev = g.warmstart == ECPIC_WS_PREVIOUS;
+    c->symmetric = g.splitting == ECPIC_SYMMETRIC;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
     c->chunk = MAX_CHUNK;
     // Waves per work item: enough items x waves to give every SIMD (1024 on the
     // chip) about four waves, and otherwise as few waves per item as possible,
     // so each wave streams many rows of particles (measured best on the pump
     // and Langmuir workloads).
-    {
+    if (g.waves_per_item > 0) {
+        c->block = 64 * g.waves_per_item;
+    } else {
         const double items = (double)g.M * std::max(1.0, std::ceil(ppc / c->chunk));
         const int wpi = (int)std::min(4.0, std::max(1.0, std::ceil(4096.0 / items)));
         c->block = 64 * wpi;
@@ -1000,35 +1125,22 @@ int ecpic_deposit_current(ecpic_ctx *c, const double *x0, const double *x1, int6
 }
 
 // ---- substeps and steps -------------------------------------------------------
-int ecpic_substep_particles(ecpic_ctx *c, ecpic_iter_stats *stats) {
-    if (!c) return ECPIC_EINVAL;
-    if (!c->have_particles) return ECPIC_ESTATE;
-    hipSetDevice(c->device);
-    enqueue_begin(c, true, false);
-    enqueue_sweeps_I(c, std::min(c->guessI, c->kmax));
-    enqueue_commit_I(c);
-    int rc = read_status(c, false);
-    bool again = false;
-    if (!rc) rc = finish_I(c, &again);
-    if (stats) {
-        stats->sweeps = sweeps_done_I(c);
-        stats->fp32_sweeps = fp32_sweeps_done_I(c);
-        stats->residual = c->h->I.res;
-    }
-    if (rc) return rc;
-    c->guessI = std::max(1, c->h->I.kconv + 1);
-    c->cur ^= 1;
-    c->icur ^= 1;
-    c->exc ^= 1;
-    c->n_items_host = c->h->I.n_items_next;
-    advance_records(c);
-    return ECPIC_OK;
+int ecpic_substep_particles(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
+    return substep_I(c, dt, stats, false);
 }
 
-int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
-    if (!c) return ECPIC_EINVAL;
+int ecpic_substep_particles_adjoint(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
+    return substep_I(c, dt, stats, true);
+}
+
+int ecpic_substep_fields(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
+    if (!c || !(dt > 0.0) || !(dt < c->dx)) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
+    DtScope scope(c);
+    int rc0 = select_tapsA(c, dt);
+    if (rc0) return rc0;
+    c->dt = dt;
     enqueue_begin(c, false, true);
     IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true, false, {}};
     enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
@@ -1039,6 +1151,7 @@ int ecpic_substep_fields(ecpic_ctx *c, ecpic_iter_stats *stats) {
         stats->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
         stats->fp32_sweeps = 0;
         stats->residual = c->h->II.res;
+        stats->crossing_queue = 0;
     }
     if (rc) return rc;
     c->guessII = std::max(1, c->h->II.kconv + 1);
@@ -1053,16 +1166,17 @@ struct StepSnap {
     int cur, icur, exc, trc, n_items;
     int64_t ws_base;
     int ws_phase;
-    bool exact;
+    bool exact, have_prev;
 };
 
 StepSnap snap(const ecpic_ctx *c) {
-    return {c->cur, c->icur, c->exc, c->trc, c->n_items_host, c->ws_base, c->ws_phase, c->exact_items};
+    return {c->cur, c->icur, c->exc, c->trc, c->n_items_host, c->ws_base, c->ws_phase, c->exact_items, c->have_prev};
 }
 
 void restore(ecpic_ctx *c, const StepSnap &q) {
     c->cur = q.cur; c->icur = q.icur; c->exc = q.exc; c->trc = q.trc;
     c->n_items_host = q.n_items; c->ws_base = q.ws_base; c->ws_phase = q.ws_phase; c->exact_items = q.exact;
+    c->have_prev = q.have_prev;
 }
 
 // Buffers swap after a committed step.
@@ -1075,12 +1189,65 @@ void advance(ecpic_ctx *c) {
 }
 
 void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII) {
-    if (sI) { sI->sweeps = sweeps_done_I(c); sI->fp32_sweeps = fp32_sweeps_done_I(c); sI->residual = c->h->I.res; }
+    if (sI) {
+        sI->sweeps = sweeps_done_I(c);
+        sI->fp32_sweeps = fp32_sweeps_done_I(c);
+        sI->residual = c->h->I.res;
+        sI->crossing_queue = c->h->I.queued;
+        sI->sweeps_adjoint = 0;
+    }
     if (sII) {
         sII->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
         sII->fp32_sweeps = 0;
         sII->residual = c->h->II.res;
+        sII->crossing_queue = 0;
+        sII->sweeps_adjoint = 0;
     }
+}
+
+// Steps of the symmetric composition, Subsystem I over dt/2, II over dt, the
+// adjoint Subsystem I over dt/2, each substep run on its own.  A failed step
+// is rolled back: a substep commits nothing on failure, and the buffers the
+// committed substeps of the step left behind still hold the step's start,
+// except e_x and the item list, which the closing substep's field kernels
+// overwrite while iterating (they are the spare buffers of that substep): e_x
+// is saved before it and the list rebuilt from the particles on failure.
+int step_symmetric(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII,
+                   int32_t *steps_done) {
+    const double dt = c->dt, h = 0.5 * c->dt;
+    for (int n = 0; n < nsteps; ++n) {
+        const StepSnap q = snap(c);
+        ecpic_iter_stats a{}, b{}, d{};
+        int rc = substep_I(c, h, &a, false);
+        bool closing = false;
+        if (!rc) rc = ecpic_substep_fields(c, dt, &b);
+        if (!rc) {
+            HIPCHK(hipMemcpyAsync(c->ex_save, c->ex[q.exc], sizeof(double) * (c->M + 2 * HALO),
+                                  hipMemcpyDeviceToDevice, c->stream));
+            closing = true;
+            rc = substep_I(c, h, &d, true);
+        }
+        if (sI) { sI[n] = a; sI[n].sweeps_adjoint = d.sweeps; }
+        if (sII) sII[n] = b;
+        if (rc) {
+            const bool committed = c->cur != q.cur || c->trc != q.trc;
+            restore(c, q);
+            if (committed) c->have_prev = false;   // the increments kept are of an order undone
+            if (closing) {   // e_x and the item list of the step's start, as they were
+                HIPCHK(hipMemcpyAsync(c->ex[c->exc], c->ex_save, sizeof(double) * (c->M + 2 * HALO),
+                                      hipMemcpyDeviceToDevice, c->stream));
+                HIPCHK(hipMemsetAsync(c->count, 0, sizeof(int32_t) * c->M, c->stream));
+                launch_count_cells_xi(c->stream, c->pb[c->cur].xi, c->N, c->M, c->count);
+                launch_items_from_counts(c->stream, c->count, c->nstart, c->M, c->chunk, c->N, c->items[c->icur]);
+                const int rs = sync(c);
+                if (rs) return rs;
+            }
+            if (steps_done) *steps_done = n;
+            return rc;
+        }
+        if (steps_done) *steps_done = n + 1;
+    }
+    return ECPIC_OK;
 }
 
 // The Subsystem II commit of the step in slot j joined to the start of the
@@ -1114,6 +1281,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
     if (steps_done) *steps_done = 0;
+    if (c->symmetric) return step_symmetric(c, nsteps, sI, sII, steps_done);
     struct FuseII {   // every commit of a step feeds the step's first Subsystem II iterate
         ecpic_ctx *c;
         explicit FuseII(ecpic_ctx *x) : c(x) { c->fuse_II = true; }

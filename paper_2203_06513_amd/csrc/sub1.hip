@@ -44,14 +44,32 @@ template <typename T>
 struct Lane {
     T t0, p0, d, t1, q0, A0y, A0z, g00;
     int s;
+    // adjoint scheme: |A0|^2, the momentum iterate P = p^{n+1} the increment
+    // stands for, and gamma(x^n, P)
+    T qa0, P, g10;
 };
+
+// The adjoint scheme (the discrete gradient with p varied first, at x^n, then
+// x, at p^{n+1}) has delta = dt (p0 + P) / (gamma(x0, p0) + gamma(x0, P)); for
+// a given delta this is solved for P in closed form.  With v = delta / dt,
+// m^2 = 1 + |A0|^2 and b = p0 - v gamma(x0, p0), squaring
+// v gamma(x0, P) = P + b gives (1 - v^2) P^2 + 2 b P + b^2 - v^2 m^2 = 0, and
+// the root with P + b of the sign of v is
+//   P = (v R - b) / (1 - v^2),   R = sqrt(b^2 + (1 - v^2) m^2).
+template <typename T>
+__device__ __forceinline__ T adjoint_momentum(T v, T p0, T g00, T m2) {
+    const T b = fma(-v, g00, p0);
+    const T om = fma(-v, v, (T)1);
+    const T R = fsqrt(fma(b, b, om * m2));
+    return fma(v, R, -b) * frcp(om);
+}
 
 // Gather at the step start, gamma there, the explicit first increment if asked,
 // and the end point of the current increment.  xi0 - c is exact in FP64; the
 // single precision sweeps round it once.
-template <int P, typename T, bool EXPL>
+template <int P, typename T, bool EXPL, bool ADJ = false>
 __device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, double xi0, int c, T dt_dx,
-                                             int &flags) {
+                                             int &flags, T dx_dt = (T)0) {
     const double t0 = xi0 - (double)c;
     wave_flag(flags, !(t0 >= 0.0), FLAG_ORDER);
     wave_flag(flags, !(t0 < 1.0), FLAG_ORDER);
@@ -59,8 +77,22 @@ __device__ __forceinline__ void stage_gather(const Own<P, T> &o, Lane<T> &L, dou
     L.A0y = horner<P + 1>(o.ay, L.t0);
     L.A0z = horner<P + 1>(o.az, L.t0);
     L.q0 = fma(L.p0, L.p0, (T)1);
-    L.g00 = fsqrt(L.q0 + L.A0y * L.A0y + L.A0z * L.A0z);
-    if constexpr (EXPL) L.d = dt_dx * L.p0 * frcp(L.g00);
+    if constexpr (ADJ) {
+        L.qa0 = fma(L.A0y, L.A0y, L.A0z * L.A0z);
+        L.g00 = fsqrt(L.q0 + L.qa0);
+        if constexpr (EXPL) {   // P^(0) = p^n
+            L.d = dt_dx * L.p0 * frcp(L.g00);
+            L.P = L.p0;
+            L.g10 = L.g00;
+        } else {
+            const T m2 = (T)1 + L.qa0;
+            L.P = adjoint_momentum<T>(L.d * dx_dt, L.p0, L.g00, m2);
+            L.g10 = fsqrt(fma(L.P, L.P, m2));
+        }
+    } else {
+        L.g00 = fsqrt(L.q0 + L.A0y * L.A0y + L.A0z * L.A0z);
+    }
+    if constexpr (EXPL && !ADJ) L.d = dt_dx * L.p0 * frcp(L.g00);
     if constexpr (sizeof(T) == 8) end_point(xi0, L.d, c, L.t1, L.s, flags);
     else end_point(L.t0, L.d, L.t1, L.s, flags);
 }
@@ -71,8 +103,11 @@ struct PushEnd {
     T A1y, A1z, g11;
 };
 
-// Momentum update and next increment; anycross is wave-uniform.
-template <int P, typename T>
+// Momentum update and next increment; anycross is wave-uniform.  ADJ: the
+// adjoint scheme, whose force divides by gamma(x0, P) + gamma(x1, P) and whose
+// next increment is that of the new momentum (dt (p0 + p1) / (gamma(x0, p0) +
+// gamma(x0, p1))).
+template <int P, typename T, bool ADJ = false>
 __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
                                            const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags,
                                            PushEnd<T> *pe = nullptr) {
@@ -104,11 +139,20 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
         A1z = horner<P + 1>(o.az, L.t1);
     }
     const T qa1 = A1y * A1y + A1z * A1z;
-    const T g01 = fsqrt(L.q0 + qa1);
-    const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
-    p1 = fma(dt, F, L.p0);
-    const T g11 = fsqrt(fma(p1, p1, one) + qa1);
-    dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
+    T g11;
+    if constexpr (ADJ) {
+        g11 = fsqrt(fma(L.P, L.P, one) + qa1);
+        const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g10 + g11);
+        p1 = fma(dt, F, L.p0);
+        const T g10n = fsqrt(fma(p1, p1, one) + L.qa0);
+        dn = dt_dx * (L.p0 + p1) * frcp(L.g00 + g10n);
+    } else {
+        const T g01 = fsqrt(L.q0 + qa1);
+        const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
+        p1 = fma(dt, F, L.p0);
+        g11 = fsqrt(fma(p1, p1, one) + qa1);
+        dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
+    }
     if (pe) {
         pe->A1y = A1y;
         pe->A1z = A1z;
@@ -189,7 +233,10 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 // float increments (d32in).
 // Where d^(k) comes from: computed explicitly (first sweep), read back from the
 // previous FP64 sweep, or read from the last float sweep of the precision form.
-enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2 };
+// START_PREV: the first sweep of a substep reads d^(0) from the increment the
+// last commit took (the previous step's converged displacement, kept in the
+// current order by that commit).
+enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2, START_PREV = 3 };
 
 // Rows a wave must hold for the sweep to queue its crossing lanes (degree >= 4).
 constexpr int QUEUE_MIN_ROWS = 16;
@@ -200,8 +247,9 @@ constexpr int QUEUE_MIN_ROWS = 16;
 constexpr int QCAP = 2 * WAVE;
 inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * sizeof(int); }
 
-template <int P, bool SEIDEL, typename T, int START>
+template <int P, bool SEIDEL, typename T, int START, bool ADJ>
 __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsRec<P, T> *rec, int *queue) {
+    static_assert(!ADJ || SEIDEL, "the adjoint scheme deposits the increment it has just produced");
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
     DevStatus *st = a.st;
@@ -231,6 +279,10 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     const double *coefE = (k & 1) ? a.coefE1 : a.coefE0;
     constexpr bool explicit_start = START == START_EXPLICIT;
     constexpr bool from_float = F64 && START == START_FLOAT;
+    constexpr bool from_prev = START == START_PREV;
+    const double *dprev = a.dprev;
+    // d^(0) is kept in FP64 where a Jacobi commit may take it
+    constexpr bool keep_start = F64 && !SEIDEL && (explicit_start || from_float || from_prev);
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const int nw = blockDim.x / WAVE;
     int wb, we;
@@ -246,6 +298,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
         nx = a.xi[il];
         np = a.p[il];
         if constexpr (from_float) nf = d32in[il];
+        else if constexpr (from_prev) nd = (T)dprev[il];
         else if constexpr (!explicit_start) nd = din[il];
     }
     stage_records<P, T>(rec, a.coefA, coefE, c);
@@ -256,7 +309,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     // the loop's memory waits only ever concern the loop's own loads and stores.
     __builtin_amdgcn_s_waitcnt(0);
     MO mo{};
-    const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx;
+    const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx, dx_dt = (T)a.dx_dt;
     T rmax = (T)0;
     int flags = 0;
     int nleft = 0, nstay = 0, nright = 0;
@@ -280,14 +333,15 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
         const double xq = a.xi[qi];
         Lq.p0 = (T)a.p[qi];
         if constexpr (from_float) Lq.d = (T)d32in[qi];
+        else if constexpr (from_prev) Lq.d = (T)dprev[qi];
         else if constexpr (!explicit_start) Lq.d = din[qi];
-        stage_gather<P, T, explicit_start>(o1, Lq, xq, c, dt_dx, flags);
+        stage_gather<P, T, explicit_start, ADJ>(o1, Lq, xq, c, dt_dx, flags, dx_dt);
         const bool cr = __ballot(Lq.s != 0) != 0;
         T pq, dq;
-        stage_push<P, T>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
+        stage_push<P, T, ADJ>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
+        flags |= FLAG_QUEUED;
         if (qv) {
-            if constexpr (F64)
-                if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[qi] = Lq.d;
+            if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[qi] = Lq.d;
             dout[qi] = dq;
             rmax = fmax(rmax, fabs(dq - Lq.d));
         }
@@ -326,13 +380,14 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 nx = a.xi[il];
                 np = a.p[il];
                 if constexpr (from_float) nf = d32in[il];
+                else if constexpr (from_prev) nd = (T)dprev[il];
                 else if constexpr (!explicit_start) nd = din[il];
             }
-            stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
+            stage_gather<P, T, explicit_start, ADJ>(o1, La, xi0, c, dt_dx, flags, dx_dt);
             // own-cell terms for every lane; a crossing lane's result is discarded
             // (it stays finite: its end point is clamped into (-1, 2) and |d| < dt/dx < 1)
             T pa, dna;
-            stage_push<P, T>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
             bool cross = La.s != 0;
             T ta = La.t1;
             if constexpr (SEIDEL) {
@@ -343,9 +398,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             }
             const bool live = valid && !cross;
             if (live) {
-                // keep d^(k) in FP64 where a Jacobi commit may take it
-                if constexpr (F64)
-                    if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
+                if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
                 rmax = fmax(rmax, fabs(dna - La.d));
             }
             pend = dna;
@@ -384,16 +437,15 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 nx = a.xi[il];
                 np = a.p[il];
                 if constexpr (from_float) nf = d32in[il];
+                else if constexpr (from_prev) nd = (T)dprev[il];
                 else if constexpr (!explicit_start) nd = din[il];
             }
-            stage_gather<P, T, explicit_start>(o1, La, xi0, c, dt_dx, flags);
+            stage_gather<P, T, explicit_start, ADJ>(o1, La, xi0, c, dt_dx, flags, dx_dt);
             const bool cross1 = __ballot(La.s != 0) != 0;
             T pa, dna;
-            stage_push<P, T>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
             if (valid) {
-                // keep d^(k) in FP64 where a Jacobi commit may take it
-                if constexpr (F64)
-                    if (!SEIDEL && (explicit_start || from_float)) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
+                if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
                 rmax = fmax(rmax, fabs(dna - La.d));
             }
             pend = dna;
@@ -435,21 +487,28 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
 
 // One block per work item; the grid may exceed the item count (the count of a
 // step enqueued ahead is only known on the device) and the extra blocks exit.
-template <int P, bool SEIDEL, typename T>
+// ADJ: the adjoint scheme (FP64, Seidel map, explicit start only).
+template <int P, bool SEIDEL, typename T, bool ADJ>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     extern __shared__ int queue[];    // the waves' queues (degree >= 4)
     if (a.k == 0 && a.explicit_start) {
-        sweep_I_item<P, SEIDEL, T, START_EXPLICIT>(a, blockIdx.x, rec, queue);
+        sweep_I_item<P, SEIDEL, T, START_EXPLICIT, ADJ>(a, blockIdx.x, rec, queue);
         return;
     }
-    if constexpr (sizeof(T) == 8) {
-        if (a.d32in) {
-            sweep_I_item<P, SEIDEL, T, START_FLOAT>(a, blockIdx.x, rec, queue);
+    if constexpr (!ADJ) {
+        if (a.k == 0 && a.dprev) {
+            sweep_I_item<P, SEIDEL, T, START_PREV, ADJ>(a, blockIdx.x, rec, queue);
             return;
         }
+        if constexpr (sizeof(T) == 8) {
+            if (a.d32in) {
+                sweep_I_item<P, SEIDEL, T, START_FLOAT, ADJ>(a, blockIdx.x, rec, queue);
+                return;
+            }
+        }
     }
-    sweep_I_item<P, SEIDEL, T, START_READ>(a, blockIdx.x, rec, queue);
+    sweep_I_item<P, SEIDEL, T, START_READ, ADJ>(a, blockIdx.x, rec, queue);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -737,7 +796,7 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
     }
     re = wave_max_dpp(re);
     rx = wave_max_dpp(rx);
-    flags = wave_or_bits(flags);
+    flags = wave_or_bits<4>(flags);
     {
         const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
         if (lane == 0) { ldsm[wid] = re; ldsx[wid] = rx; ldsf[wid] = flags; }
@@ -751,7 +810,8 @@ __global__ void __launch_bounds__(256) k_field_I(FieldIArgs a) {
         }
         atomicMax(&st->re_bits[k & 1], bitsd(re));
         atomicMax(&st->rx_bits[k & 1], bitsd(rx));
-        if (flags) atomicOr(&st->flags, flags);
+        if (flags & FLAG_ERRORS) atomicOr(&st->flags, flags & FLAG_ERRORS);
+        if (flags & FLAG_QUEUED) atomicOr(&st->queued, 1);
         if (cw && notone_s) atomicOr(&st->scan_multi, 1);
         if (blockIdx.x == 0) {   // clear the slots field kernel k+1 accumulates into
             st->rx_bits[(k + 1) & 1] = 0ull;
@@ -918,8 +978,14 @@ __device__ __forceinline__ double wave_totals_lds(double *col, int stride, int l
 // cost no registers across the loop).  A^n and gamma^n at the end point are
 // those the push evaluated.  A wave writes 2 (P+3) slots, V0 indices
 // c-P-1 .. c+1 for each component.
-template <int P, bool RECORD>
+//
+// ADJ: the commit of the adjoint scheme.  The committed increment is the
+// sweep's delta^(kc+1); the momentum is the P that increment stands for (the
+// closed form of adjoint_momentum), so no push is evaluated again.  It forms no
+// Subsystem II deposit (the adjoint substep closes a step) and records nothing.
+template <int P, bool RECORD, bool ADJ>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
+    static_assert(!(ADJ && RECORD), "pairs are recorded from the scheme's own commit");
     constexpr int NA = RecA<P>::N;
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
     __shared__ double rk[3][NA];           // a^(0) records of cells c-1, c, c+1 (part2)
@@ -1004,14 +1070,20 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             nid = a.cur.id[il];
         }
         // the committed momentum: the map evaluated at the committed increment
+        // (adjoint: the momentum that increment stands for)
         Lane<double> La;
         La.p0 = p0;
         La.d = d;
-        stage_gather<P, double, false>(o1, La, xi0, c, a.dt_dx, flags);
         double p1, dn;
+        PushEnd<double> pe{0.0, 0.0, 0.0};
+        stage_gather<P, double, false, ADJ>(o1, La, xi0, c, a.dt_dx, flags, a.dx_dt);
         const bool anymove = __ballot(La.s != 0) != 0;
-        PushEnd<double> pe;
-        stage_push<P, double>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags, &pe);
+        if constexpr (ADJ) {
+            p1 = La.P;
+            wave_flag(flags, !(fabs(p1) < 1.0e300), FLAG_NONFINITE);
+        } else {
+            stage_push<P, double>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags, &pe);
+        }
         const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
         double xin = xi0 + d;
         if (xin >= (double)M) xin -= (double)M;
@@ -1021,7 +1093,7 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         }
         if constexpr (RECORD)
             if (valid && pid % a.rec.stride == a.rec.phase) record_pair<P>(a, o1, c, pid, xi0, p0, d, p1);
-        if (dep2) {
+        if (!ADJ && dep2) {
             // the cell the particle lands in and its coordinate there, as the
             // particle pass over the new order would take them
             int dc = c + La.s;
@@ -1079,12 +1151,13 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             a.nxt.xi[dest] = xin;
             a.nxt.p[dest] = p1;
             a.nxt.id[dest] = pid;
+            if (a.dprev_out) a.dprev_out[dest] = d;
         }
         run0 += __popcll(b0);
         run1 += __popcll(b1);
         run2 += __popcll(b2);
     }
-    if (dep2) {   // block-uniform: every wave of the block takes part in the barriers
+    if (!ADJ && dep2) {   // block-uniform: every wave of the block takes part in the barriers
         // wave totals of the moments (movers from their LDS slots; then the
         // stayers, through the same slots), and lane q < 2 (P+3) forms slot q
         constexpr int NS1 = 2 * (P + 1);
@@ -1133,24 +1206,27 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 // RECORD: the step also writes training pairs of the learned warm start (a
 // kernel of its own, so the plain one keeps its registers).
-template <int P, bool RECORD>
+template <int P, bool RECORD, bool ADJ>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
-    commit_scatter_item<P, RECORD>(a, blockIdx.x);
+    commit_scatter_item<P, RECORD, ADJ>(a, blockIdx.x);
 }
 
 
 // ---- launchers ------------------------------------------------------------
-void launch_sweep_I(int P, bool seidel, bool fp32, int grid, int block, hipStream_t s, const SweepIArgs &a) {
+void launch_sweep_I(int P, bool seidel, bool fp32, bool adj, int grid, int block, hipStream_t s,
+                    const SweepIArgs &a) {
     const size_t lds = P >= 4 ? queue_lds_bytes(block) : 0;   // the queue is used from degree 4 on
-#define ECPIC_SW(PP)                                                                                         \
-    case PP:                                                                                                 \
-        if (fp32) {                                                                                          \
-            if (seidel) launch_k((k_sweep_I<PP, true, float>), dim3(grid), dim3(block), lds, s, a);  \
-            else launch_k((k_sweep_I<PP, false, float>), dim3(grid), dim3(block), lds, s, a);        \
-        } else {                                                                                             \
-            if (seidel) launch_k((k_sweep_I<PP, true, double>), dim3(grid), dim3(block), lds, s, a); \
-            else launch_k((k_sweep_I<PP, false, double>), dim3(grid), dim3(block), lds, s, a);       \
-        }                                                                                                    \
+#define ECPIC_SW(PP)                                                                                          \
+    case PP:                                                                                                  \
+        if (adj) {                                                                                            \
+            launch_k((k_sweep_I<PP, true, double, true>), dim3(grid), dim3(block), lds, s, a);                \
+        } else if (fp32) {                                                                                    \
+            if (seidel) launch_k((k_sweep_I<PP, true, float, false>), dim3(grid), dim3(block), lds, s, a);    \
+            else launch_k((k_sweep_I<PP, false, float, false>), dim3(grid), dim3(block), lds, s, a);          \
+        } else {                                                                                              \
+            if (seidel) launch_k((k_sweep_I<PP, true, double, false>), dim3(grid), dim3(block), lds, s, a);   \
+            else launch_k((k_sweep_I<PP, false, double, false>), dim3(grid), dim3(block), lds, s, a);         \
+        }                                                                                                     \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW
@@ -1174,14 +1250,16 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 #undef ECPIC_PR
 }
 
-void launch_commit_I(int P, int grid, int block, hipStream_t s, const CommitIArgs &a) {
-    const size_t lds = a.part2 ? sizeof(double) * 4 * (P + 1) * (size_t)block : 0;   // mover moments
-#define ECPIC_C(PP)                                                                              \
-    case PP:                                                                                     \
-        if (a.rec.stride > 0)                                                                    \
-            launch_k((k_commit_scatter<PP, true>), dim3(grid), dim3(block), lds, s, a);  \
-        else                                                                                     \
-            launch_k((k_commit_scatter<PP, false>), dim3(grid), dim3(block), lds, s, a); \
+void launch_commit_I(int P, bool adj, int grid, int block, hipStream_t s, const CommitIArgs &a) {
+    const size_t lds = (a.part2 && !adj) ? sizeof(double) * 4 * (P + 1) * (size_t)block : 0;   // mover moments
+#define ECPIC_C(PP)                                                                                     \
+    case PP:                                                                                            \
+        if (adj)                                                                                        \
+            launch_k((k_commit_scatter<PP, false, true>), dim3(grid), dim3(block), lds, s, a);          \
+        else if (a.rec.stride > 0)                                                                      \
+            launch_k((k_commit_scatter<PP, true, false>), dim3(grid), dim3(block), lds, s, a);          \
+        else                                                                                            \
+            launch_k((k_commit_scatter<PP, false, false>), dim3(grid), dim3(block), lds, s, a);         \
         break;
     switch (P) { ECPIC_C(2) ECPIC_C(3) ECPIC_C(4) ECPIC_C(5) }
 #undef ECPIC_C

@@ -246,6 +246,60 @@ def test_pump2048_full_size_step_properties():
     assert on.gauss_residual(s1["x"], s1["ex"]) <= 1e-13
 
 
+def test_pump2048_full_size_two_steps_elementwise():
+    """Two Lie-Trotter steps of the full pump2048 workload (2e6 particles, 2048 cells) in
+    the launch configuration the benchmark times (ecpic_step: steps enqueued as one batch,
+    Seidel map, the first Subsystem II deposit formed by the commit, the join of a step's
+    Subsystem II commit with the next step's start) against the oracle's two steps from the
+    identical state: every particle and every field coefficient at 1e-12, equal sweep and
+    iteration counts."""
+    w = workloads.get("pump2048")
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=1)
+    s = initial_state(o, arr)
+    start = dict(arr, ex=s["ex"].copy())
+    st, kI, kII, E = o.step(s, 2, energies=True)
+    assert st == 0
+    with gpu_ctx(w, map=ec.MAP_SEIDEL) as c:
+        c.load(start, solve_gauss=False)
+        rc, done, gI, gII, _ = c.step(2)
+        g = c.state()
+        H = c.energy()[4]
+    assert rc == 0 and done == 2
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L)
+    assert abs(H - E[-1, 4]) / E[0, 4] <= 1e-12
+
+
+@pytest.mark.parametrize("p,seidel", [(4, 1), (5, 0), (5, 1)])
+def test_crossing_queue_elementwise(p, seidel):
+    """From degree 4 on, a wave that holds at least 1024 particles computes every row with
+    the own-cell terms and queues the particles whose step crosses a cell boundary, redoing
+    them a row at a time with every term.  One wave per item and 1500 particles per cell
+    make every wave take that path (more than 64 crossings each, so both the full-row and
+    the final partial redo run); two steps against the oracle element by element."""
+    w = workloads.get("langmuir64").scaled(degree=p, M=32, n_particles=48000, sigma=0.5)
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=seidel)
+    s = initial_state(o, arr)
+    start = dict(arr, ex=s["ex"].copy())
+    st, kI, kII, _ = o.step(s, 2)
+    assert st == 0
+    with gpu_ctx(w, map=seidel, waves_per_item=1) as c:
+        c.load(start, solve_gauss=False)
+        rc, done, gI, gII, _ = c.step(2)
+        queued = c.last_queue_I.copy()
+        g = c.state()
+    assert queued.all(), queued
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L)
+    # the default launch shape (four waves per item here) does not queue
+    with gpu_ctx(w, map=seidel) as c:
+        c.load(start, solve_gauss=False)
+        c.step(1)
+        assert not c.last_queue_I.any()
+
+
 def test_stress16384_full_size_step_properties():
     """The quintic stress workload at full size (1.28e8 particles, 16384 cells): one step
     in the launch configuration the benchmark uses.  The oracle cannot sum over all
