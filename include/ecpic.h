@@ -214,6 +214,22 @@ int ecpic_step(ecpic_ctx *ctx, int32_t nsteps, ecpic_iter_stats *per_step_I,
 int ecpic_deposit_current(ecpic_ctx *ctx, const double *x0, const double *x1, int64_t n,
                           double *J);
 
+/* The current of ecpic_deposit_current for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  x0, x1: device arrays of n doubles, J: device array of M
+ * doubles (overwritten), flags: device int32 or NULL, all on the context's
+ * device.  The call only enqueues two kernels on the context's stream and
+ * returns: it allocates nothing, copies nothing to the host and does not wait,
+ * so J and *flags are ready when the stream reaches that point.  *flags gets 2
+ * (the ECPIC_ECFL cause) if some segment ends outside the neighbour cells of its
+ * start (that segment is left out), else 0.  Per-block partial currents live in
+ * a fixed static device buffer of 64 x 16384 doubles (8 MiB per device, held
+ * until the process ends), shared by every call on that device: calls that
+ * overlap on one device race.  EINVAL if M > 16384 (the buffer's limit) or for a
+ * bad argument; EDEVICE if the buffer could not be located on this device. */
+int ecpic_deposit_current_noalloc(ecpic_ctx *ctx, const double *x0, const double *x1, int64_t n, double *J,
+                                  int32_t *flags);
+
 /* Charge rho = Lambda0(X)^T W 1 of the current particles (second remark of
  * Section 4.2); rho: host array of length M. */
 int ecpic_deposit_charge(ecpic_ctx *ctx, double *rho);

@@ -26,7 +26,8 @@ EXPORTS = (
     "ecpic_set_particles_dev", "ecpic_get_particles_dev", "ecpic_set_fields", "ecpic_get_fields",
     "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_particles_adjoint", "ecpic_substep_fields",
     "ecpic_step",
-    "ecpic_deposit_current", "ecpic_deposit_charge", "ecpic_energy", "ecpic_gauss_residual",
+    "ecpic_deposit_current", "ecpic_deposit_current_noalloc", "ecpic_deposit_charge", "ecpic_energy",
+    "ecpic_gauss_residual",
     "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_bandwidth_probe", "ecpic_strerror",
     "ecpic_ws_record", "ecpic_ws_records", "ecpic_ws_get_records", "ecpic_ws_train", "ecpic_ws_n_params",
     "ecpic_ws_get_weights", "ecpic_ws_set_weights", "ecpic_ws_enable", "ecpic_ws_grad", "ecpic_ws_table",
@@ -100,6 +101,7 @@ def load() -> C.CDLL:
         L.ecpic_substep_fields.argtypes = [V, C.c_double, C.POINTER(IterStats)]
         L.ecpic_step.argtypes = [V, C.c_int32, C.POINTER(IterStats), C.POINTER(IterStats), C.POINTER(C.c_int32)]
         L.ecpic_deposit_current.argtypes = [V, V, V, C.c_int64, V]
+        L.ecpic_deposit_current_noalloc.argtypes = [V, V, V, C.c_int64, V, V]
         L.ecpic_deposit_charge.argtypes = [V, V]
         L.ecpic_energy.argtypes = [V, C.POINTER(EnergyParts)]
         L.ecpic_gauss_residual.argtypes = [V, C.POINTER(C.c_double), V]
@@ -301,6 +303,11 @@ class Context:
         _ck(self._lib.ecpic_deposit_current(self._h, x0.ctypes.data, x1.ctypes.data, len(x0), J.ctypes.data),
             "deposit_current")
         return J
+
+    def deposit_current_noalloc(self, x0_ptr: int, x1_ptr: int, n: int, J_ptr: int, flags_ptr: int = 0) -> int:
+        """Device pointers in and out; enqueued on the context's stream, nothing allocated,
+        not waited for.  Returns the status (not raised: the caller may be capturing)."""
+        return self._lib.ecpic_deposit_current_noalloc(self._h, x0_ptr, x1_ptr, int(n), J_ptr, flags_ptr or None)
 
     # -- learned warm start -----------------------------------------------------
     def ws_record(self, stride: int, capacity: int = 0):

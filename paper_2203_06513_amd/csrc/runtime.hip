@@ -77,6 +77,11 @@ void launch_unpermute(hipStream_t s, const double *xi, const double *p, const in
 void launch_deposit_segments(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
                              double dx, double w, int M, double *J, int *flags);
 void launch_copy(hipStream_t s, const double *in, double *out, int64_t n);
+int noalloc_init(int dev);
+double *noalloc_scratch(int dev);
+int noalloc_max_cells();
+void launch_deposit_noalloc(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
+                            double dx, double w, int M, double *scr, double *J, int32_t *flags);
 void launch_ws_predict(int P, int grid, int block, hipStream_t s, const SweepIArgs &a);
 void launch_ws_init(int P, hipStream_t s, float *theta, uint64_t seed);
 void launch_ws_stats(hipStream_t s, const float *feat, const float *targ, int64_t n, int D, float *mu, float *sd,
@@ -913,6 +918,9 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     int rc = check_device(g.device);
     if (rc) return rc;
     if (hipSetDevice(g.device) != hipSuccess) return ECPIC_EDEVICE;
+    // the fixed scratch of ecpic_deposit_current_noalloc on this device (if its
+    // address cannot be taken, only that call fails, with EDEVICE)
+    noalloc_init(g.device);
     ecpic_ctx *c = new ecpic_ctx();
     c->cfg = g;
     c->device = g.device;
@@ -1122,6 +1130,23 @@ int ecpic_deposit_current(ecpic_ctx *c, const double *x0, const double *x1, int6
     if (!rc && hf) rc = ECPIC_ECFL;
     for (void *q : {(void *)a, (void *)b, (void *)dJ, (void *)fl}) hipFree(q);
     return rc;
+}
+
+// Asynchronous, allocation-free variant of ecpic_deposit_current (device
+// arrays, fixed scratch; see noalloc.hip).
+int ecpic_deposit_current_noalloc(ecpic_ctx *c, const double *x0, const double *x1, int64_t n, double *J,
+                                  int32_t *flags) {
+    if (!c || !J || n < 0 || (n > 0 && (!x0 || !x1))) return ECPIC_EINVAL;
+    if (c->M > noalloc_max_cells()) {
+        std::fprintf(stderr, "ecpic_deposit_current_noalloc: %d cells exceed the %d of its fixed scratch\n", c->M,
+                     noalloc_max_cells());
+        return ECPIC_EINVAL;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return ECPIC_EDEVICE;
+    double *scr = noalloc_scratch(c->device);
+    if (!scr) return ECPIC_EDEVICE;
+    launch_deposit_noalloc(c->P, c->stream, x0, x1, n, c->inv_dx, c->dx, c->w, c->M, scr, J, flags);
+    return hipGetLastError() == hipSuccess ? ECPIC_OK : ECPIC_EDEVICE;
 }
 
 // ---- substeps and steps -------------------------------------------------------
