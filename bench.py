@@ -1,21 +1,28 @@
 """Benchmark: converged particle-steps/s of full Lie-Trotter steps (Subsystem I
-+ II, every step converged to the Picard tolerance) on the pump2048 workload
-(L = 64 pi, 2048 cells, cubic splines, 2e6 particles, dt = 0.02, tol 1e-12) on
-one MI355X, for the two forms the metric compares:
++ II, every step converged to the Picard tolerance) on one MI355X, for the two
+forms the metric compares:
 
 * plain FP64: every Picard sweep in FP64 from the explicit initial iterate;
 * FP32 + learned warm start: a predictor pass from the network (trained first on
   pairs the method produced, training time reported apart), then FP32 sweeps,
   then FP64 sweeps to the same tolerance.
 
-Prints ONE JSON line.  `value` is the throughput of the second form (the
-whole hot path: network tables, predictor, FP32 and FP64 sweeps, field
-solves, commit, Subsystem II); the plain form's throughput, sweep counts and
-energy drift sit beside it.  Inputs are resident in HBM before each timed
-region.  A separate pass with per-kernel HIP events (on the library's stream)
-gives the average duration of the dominant kernel, the FP64 Subsystem I sweep,
-for the roofline object; the CPU baseline is the FP64 oracle timed on a bounded
-sample of the same workload.
+The headline workload is pump2048 (L = 64 pi, 2048 cells, cubic splines, 2e6
+particles, dt = 0.02, tol 1e-12).  Its particle arrays (~64 MB per sweep) fit
+in the 256 MB last-level cache, so the HBM roofline is graded on the two
+workloads whose sweeps do not: langmuir4096 (1.6e7 particles, cubic) and
+stress16384 (1.28e8 particles, quintic).  Both forms run on each of them too
+("graded": ms/step, mean sweeps, energy drift, per-kernel averages and the HBM
+fraction of the FP64 sweep and of the commit), and the line's `roofline`
+object is the FP64 sweep of the plain form at stress16384.
+
+Prints ONE JSON line.  `value` is the throughput of the learned form on the
+headline workload (the whole hot path: network tables, predictor, FP32 and
+FP64 sweeps, field solves, commit, Subsystem II); the plain form's throughput
+sits beside it.  Inputs are resident in HBM before each timed region.  Kernel
+averages come from a separate pass with per-kernel HIP events that the
+kernels' dispatch packets record, on the library's stream.  The CPU baseline
+is the FP64 oracle timed on a bounded sample of the headline workload.
 """
 from __future__ import annotations
 
@@ -33,9 +40,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "converged particle-steps/s, plain FP64 vs FP32+learned warm start at equal |ΔH|/H"
 HBM_PEAK_GBS = 8000.0
-# A Subsystem I sweep reads xi, p and (after the first sweep of a substep) delta^(k),
-# and writes delta^(k+1): 24 B/particle on the first sweep, 32 B on the others.
-PMC_SUMMARY = os.path.join(ROOT, "profiles", "sweep_I_pump2048_pmc.txt")
+KERNELS = ("ws_table", "ws_predict", "sweep_I32", "sweep_I", "field_I", "commit_I", "sweep_II", "field_II",
+           "begin", "commit_II", "join")
+# Algorithmic bytes per particle.  A Subsystem I sweep reads xi, p and (after the
+# first sweep of a substep) delta^(k), and writes delta^(k+1): 24 B on the first
+# sweep, 32 B on the others.  The commit reads xi, p, delta and the id (28 B) and
+# writes xi, p and the id in the new order (20 B).
+COMMIT_BYTES = 48.0
+
+
+def sweep_bytes(S: float) -> float:
+    return (24.0 + 32.0 * (S - 1.0)) / S
 
 
 def kernel_source_hash() -> str:
@@ -45,12 +60,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_particles: int):
-    """HBM bytes per sweep launch from committed PMC counters, if they are current."""
-    if not os.path.exists(PMC_SUMMARY):
+def traffic_from_profile(workload: str, n_particles: int):
+    """HBM bytes per FP64 sweep launch from committed PMC counters, if they were taken
+    from the current kernel sources on this workload."""
+    path = os.path.join(ROOT, "profiles", f"sweep_I_{workload}_pmc.txt")
+    if not os.path.exists(path):
         return None
     d = {}
-    for line in open(PMC_SUMMARY):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             d[k.strip()] = v.strip()
@@ -75,14 +92,15 @@ def cpu_baseline(w, n_sample: int, steps: int):
     dt = time.perf_counter() - t0
     assert st == 0
     return {"value": n_sample * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"pump2048 grid/fields/dt/tol with the first {n_sample} of its {w.n_particles} particles, "
+            "sample": f"{w.name} grid/fields/dt/tol with the first {n_sample} of its {w.n_particles} particles, "
                       f"{steps} Lie-Trotter steps (plain FP64, Seidel map), {dt:.1f} s single-threaded",
             "mean_sweeps_I": float(np.mean(kI)), "mean_iters_II": float(np.mean(kII))}
 
 
 def _device_sync():
-    """ecpic_step returns after its own stream is synchronised; this also drains
-    every other stream of the device around the timed region."""
+    """ecpic_step returns after its own stream is synchronised; this also drains every
+    other stream of the device around the timed region (torch holds the process's one
+    HIP runtime, see the binding)."""
     import torch
     if torch.cuda.is_available():
         torch.cuda.synchronize()
@@ -105,16 +123,76 @@ def timed_run(ctx, steps: int):
             "gauss": float(np.abs(r1 - r0).max())}
 
 
-def kernel_profile(ctx, steps: int, names):
+def kernel_profile(ctx, steps: int):
     ctx.profile(True)
     ctx.step(steps)
     out = {}
-    for name in names:
+    for name in KERNELS:
         ms, n = ctx.kernel_time(name)
         if n:
             out[name] = {"ms_total": ms, "launches": n, "us_avg": 1e3 * ms / n}
     ctx.profile(False)
     return out
+
+
+def run_form(ec, w, arr, learned: bool, steps: int, warmup: int, profile_steps: int, fp32_sweeps: int,
+             record_steps: int, train_steps: int):
+    """One form on one workload: load, (record and train), warm up, time, profile."""
+    N = w.n_particles
+    kw = dict(map=ec.MAP_SEIDEL)
+    if learned:
+        kw.update(precision=ec.FP32_MIXED, fp32_sweeps=fp32_sweeps)
+    out = {}
+    with ec.Context.from_workload(w, **kw) as ctx:
+        ctx.load(arr)
+        if learned:
+            stride = max(1, N // 100_000)
+            per_step = (N + stride - 1) // stride
+            ctx.ws_record(stride, record_steps * per_step)
+            t0 = time.perf_counter()
+            ctx.step(record_steps)
+            n_pairs = ctx.ws_records()
+            ctx.ws_record(0)
+            t1 = time.perf_counter()
+            loss = ctx.ws_train(steps=train_steps, batch=1024, lr=2e-3, seed=5)
+            t2 = time.perf_counter()
+            ctx.ws_enable(True)
+            out["training"] = {"pairs": int(n_pairs), "record_steps": record_steps, "record_s": t1 - t0,
+                               "train_steps": train_steps, "train_s": t2 - t1, "final_loss": loss}
+        ctx.step(warmup)
+        r = timed_run(ctx, steps)
+        k = kernel_profile(ctx, profile_steps)
+    out.update(r)
+    out["kernels"] = k
+    return out
+
+
+def summarize(w, r):
+    N = w.n_particles
+    S = float(np.mean(r["kI"]))
+    k = r["kernels"]
+    d = {"value": N * len(r["kI"]) / r["elapsed"], "ms_per_step": 1e3 * r["elapsed"] / len(r["kI"]),
+         "mean_sweeps_I": S, "mean_fp32_sweeps_I": float(np.mean(r["k32"])),
+         "mean_iters_II": float(np.mean(r["kII"])), "rel_energy_drift": r["drift"],
+         "gauss_change_linf": r["gauss"], "kernels_us": {n: round(v["us_avg"], 2) for n, v in k.items()}}
+    if "sweep_I" in k:
+        S64 = S - d["mean_fp32_sweeps_I"]
+        if d["mean_fp32_sweeps_I"] == 0 and "ws_predict" not in k:
+            b = sweep_bytes(S)
+        else:   # after FP32 sweeps the first FP64 sweep reads a 4-byte increment: 28 B, then 32 B
+            b = (28.0 + 32.0 * (S64 - 1.0)) / S64
+        d["sweep_I_hbm_frac"] = N * b / (k["sweep_I"]["us_avg"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+        d["sweep_I_bytes_per_particle"] = b
+    if "commit_I" in k:
+        d["commit_I_hbm_frac"] = N * COMMIT_BYTES / (k["commit_I"]["us_avg"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+    if "training" in r:
+        d["training"] = r["training"]
+    return d
+
+
+def describe(w):
+    return (f"{w.name}: L={w.L / np.pi:g}pi, M={w.M}, degree {w.degree}, N={w.n_particles}, dt={w.dt}, "
+            f"tol={w.tol}, wave={w.wave} a0={w.amplitude} mode {w.wave_mode}, sigma={w.sigma}")
 
 
 def main():
@@ -127,6 +205,13 @@ def main():
     ap.add_argument("--record-steps", type=int, default=100)
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--graded", default="langmuir4096,stress16384",
+                    help="workloads that grade the HBM roofline (comma separated, empty for none)")
+    ap.add_argument("--graded-steps", type=int, default=10)
+    ap.add_argument("--graded-warmup", type=int, default=3)
+    ap.add_argument("--graded-profile-steps", type=int, default=4)
+    ap.add_argument("--graded-record-steps", type=int, default=20)
+    ap.add_argument("--forms", default="plain,learned", help="forms to run on the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -140,87 +225,89 @@ def main():
     import paper_2203_06513_amd as ec
     import workloads
 
+    # ---- headline workload, both forms ---------------------------------------
     w = workloads.get(args.workload)
     arr = workloads.generate(w)
     N = w.n_particles
-    names = ("ws_table", "ws_predict", "sweep_I32", "sweep_I", "field_I", "commit_I", "sweep_II", "field_II",
-             "begin", "commit_II", "join")
-
-    # ---- plain FP64 ---------------------------------------------------------
-    plain = ec.Context.from_workload(w, map=ec.MAP_SEIDEL)
-    plain.load(arr)
-    plain.step(args.warmup)
-    rp = timed_run(plain, args.steps)
-    kp = kernel_profile(plain, args.profile_steps, names)
-    copy_bytes = 1 << 30
-    copy_ms = plain.bandwidth_probe(copy_bytes, reps=10)
-    plain.close()
-
-    # ---- FP32 + learned warm start -----------------------------------------
-    lw = ec.Context.from_workload(w, map=ec.MAP_SEIDEL, precision=ec.FP32_MIXED, fp32_sweeps=args.fp32_sweeps)
-    lw.load(arr)
-    stride = max(1, N // 100_000)
-    per_step = (N + stride - 1) // stride
-    capacity = args.record_steps * per_step
-    lw.ws_record(stride, capacity)
-    t0 = time.perf_counter()
-    lw.step(args.record_steps)
-    n_pairs = lw.ws_records()
-    lw.ws_record(0)
-    t1 = time.perf_counter()
-    loss = lw.ws_train(steps=args.train_steps, batch=1024, lr=2e-3, seed=5)
-    t2 = time.perf_counter()
-    lw.ws_enable(True)
-    lw.step(args.warmup)
-    rl = timed_run(lw, args.steps)
-    kl = kernel_profile(lw, args.profile_steps, names)
-    lw.close()
-
-    value = N * args.steps / rl["elapsed"]
-    value_plain = N * args.steps / rp["elapsed"]
-
-    # roofline of the dominant kernel, the FP64 Subsystem I sweep, in the plain form
-    S = float(np.mean(rp["kI"]))
-    sweep_us = kp["sweep_I"]["us_avg"]
-    alg_bytes = N * (24.0 + 32.0 * (S - 1.0)) / S
-    achieved = alg_bytes / (sweep_us * 1e-6) / 1e9
+    forms = args.forms.split(",")
+    rp = run_form(ec, w, arr, False, args.steps, args.warmup, args.profile_steps, args.fp32_sweeps,
+                  args.record_steps, args.train_steps)
+    rl = rp if "learned" not in forms else run_form(ec, w, arr, True, args.steps, args.warmup, args.profile_steps,
+                                                    args.fp32_sweeps, args.record_steps, args.train_steps)
+    with ec.Context.from_workload(w) as c:
+        copy_bytes = 1 << 30
+        copy_ms = c.bandwidth_probe(copy_bytes, reps=10)
     copy_gbs = 2 * copy_bytes / (copy_ms * 1e-3) / 1e9
+    del arr
+    sp, sl = summarize(w, rp), summarize(w, rl)
+    print(f"bench: {w.name} plain {sp['ms_per_step']:.4f} ms/step, learned {sl['ms_per_step']:.4f} ms/step",
+          file=sys.stderr, flush=True)
+
+    # ---- graded workloads (working sets beyond the last-level cache) ----------
+    graded = {}
+    for name in [g for g in args.graded.split(",") if g]:
+        wg = workloads.get(name)
+        ag = workloads.generate(wg)
+        gp = summarize(wg, run_form(ec, wg, ag, False, args.graded_steps, args.graded_warmup,
+                                    args.graded_profile_steps, args.fp32_sweeps, 0, 0))
+        gl = summarize(wg, run_form(ec, wg, ag, True, args.graded_steps, args.graded_warmup,
+                                    args.graded_profile_steps, args.fp32_sweeps, args.graded_record_steps,
+                                    args.train_steps))
+        del ag
+        graded[name] = {"config": describe(wg), "steps": args.graded_steps, "plain_fp64": gp,
+                        "fp32_learned": gl, "speedup_learned_vs_plain": gl["value"] / gp["value"]}
+        print(f"bench: {name} plain {gp['ms_per_step']:.3f} ms/step (sweep {gp.get('sweep_I_hbm_frac', 0):.3f} "
+              f"of HBM), learned {gl['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel, the FP64 Subsystem I sweep of the plain form, on
+    # the largest graded workload (else the headline one)
+    if "stress16384" in graded:
+        rw, rk = workloads.get("stress16384"), graded["stress16384"]["plain_fp64"]
+    elif graded:
+        last = list(graded)[-1]
+        rw, rk = workloads.get(last), graded[last]["plain_fp64"]
+    else:
+        rw, rk = w, sp
+    S = rk["mean_sweeps_I"]
+    sweep_us = rk["kernels_us"]["sweep_I"]
+    alg_bytes = rw.n_particles * sweep_bytes(S)
+    achieved = alg_bytes / (sweep_us * 1e-6) / 1e9
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": sl["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * rl["elapsed"] / args.steps,
+        "ms_per_step": sl["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+f32+bf16",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: L={w.L / np.pi:g}pi, M={w.M}, degree {w.degree}, N={N}, "
-                               f"dt={w.dt}, tol={w.tol}, wave={w.wave} a0={w.amplitude} mode {w.wave_mode}, "
-                               f"sigma={w.sigma}",
+        "config": {"workload": describe(w),
                    "form": f"FP32+learned warm start ({args.fp32_sweeps} FP32 sweep(s), then FP64 to tol)",
                    "picard_map": "seidel",
-                   "mean_sweeps_I": float(np.mean(rl["kI"])), "mean_fp32_sweeps_I": float(np.mean(rl["k32"])),
-                   "predictor_passes_per_step": 1, "mean_iters_II": float(np.mean(rl["kII"])),
-                   "rel_energy_drift": rl["drift"], "gauss_change_linf": rl["gauss"],
-                   "training": {"pairs": int(n_pairs),
-                                "record_steps": args.record_steps, "record_s": t1 - t0,
-                                "train_steps": args.train_steps, "train_s": t2 - t1, "final_loss": loss},
-                   "plain_fp64": {"value": value_plain, "ms_per_step": 1e3 * rp["elapsed"] / args.steps,
-                                  "mean_sweeps_I": S, "mean_iters_II": float(np.mean(rp["kII"])),
-                                  "rel_energy_drift": rp["drift"], "gauss_change_linf": rp["gauss"]},
-                   "speedup_vs_plain_fp64": value / value_plain},
+                   "mean_sweeps_I": sl["mean_sweeps_I"], "mean_fp32_sweeps_I": sl["mean_fp32_sweeps_I"],
+                   "predictor_passes_per_step": 1, "mean_iters_II": sl["mean_iters_II"],
+                   "rel_energy_drift": sl["rel_energy_drift"], "gauss_change_linf": sl["gauss_change_linf"],
+                   "training": sl.get("training"),
+                   "plain_fp64": {k: sp[k] for k in ("value", "ms_per_step", "mean_sweeps_I", "mean_iters_II",
+                                                     "rel_energy_drift", "gauss_change_linf")},
+                   "speedup_vs_plain_fp64": sl["value"] / sp["value"],
+                   "cache_note": f"{w.name} moves {N * sweep_bytes(sp['mean_sweeps_I']) / 1e6:.0f} MB per sweep, "
+                                 "inside the 256 MB last-level cache: its sweep fraction "
+                                 f"({sp.get('sweep_I_hbm_frac', 0):.3f}) is not an HBM figure"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(N),
-                     "kernel": f"k_sweep_I<{w.degree},true,double> (FP64 Subsystem I sweep, plain form)",
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": sweep_us, "copy_probe_GBs": copy_gbs},
-        "kernels_plain": {k: round(v["us_avg"], 2) for k, v in kp.items()},
-        "kernels_learned": {k: round(v["us_avg"], 2) for k, v in kl.items()},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(rw.name, rw.n_particles),
+                     "kernel": f"k_sweep_I<{rw.degree},true,double,false> (FP64 Subsystem I sweep, plain form)",
+                     "workload": rw.name,
+                     "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": sweep_us,
+                     "copy_probe_GBs": copy_gbs},
+        "graded": graded,
+        "kernels_plain": sp["kernels_us"],
+        "kernels_learned": sl["kernels_us"],
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, args.cpu_steps)

@@ -115,9 +115,11 @@ def _positions(w: Workload, rng: np.random.Generator, n: int) -> np.ndarray:
         eps = w.density_ripple
         target = u * w.L
         x = target.copy()
-        for _ in range(60):
+        for _ in range(60):   # Newton; quadratic, so a few steps reach round-off
             f = x + (eps / k) * np.sin(k * x) - target
             x = x - f / (1.0 + eps * np.cos(k * x))
+            if np.abs(f).max(initial=0.0) <= 1e-15 * w.L:
+                break
         x = np.mod(x, w.L)
     x[x >= w.L] = 0.0
     return x
