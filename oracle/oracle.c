@@ -36,8 +36,8 @@
  *   - optionally (seidel = 1) each sweep deposits the current of the increment
  *     it has just produced, delta^(k+1), instead of delta^(k); the fixed point is
  *     the same, the contraction per sweep is the square of Jacobi's, and the
- *     commit is x^n + delta^(k+1), e^(k+1) and the momentum p^(k+1) the
- *     converged sweep computed (the one delta^(k+1) was formed from);
+ *     commit is x^n + delta^(k+1), e^(k+1) and the momentum re-evaluated from
+ *     (delta^(k+1), e^(k+1));
  *   - optionally (warm_previous = 1) the iteration of a Subsystem I substep
  *     starts from the increments the previous substep of the run committed
  *     (explicit start on the first); the fixed point does not change;
@@ -499,10 +499,15 @@ int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *
         int last = (k == c->kmax - 1);
         if (r <= c->tol || (last && c->commit_unconverged)) {
             if (c->seidel) {
+                for (int j = 0; j < M; ++j) ebar[j] = 0.5 * (ex[j] + enew[j]);
                 for (int64_t a = 0; a < n; ++a) {
+                    long jlo;
+                    int nj;
+                    double lbar[16], pc, dc;
+                    orc_particle_map(c, x[a], p[a], dn[a], ay, az, gy, gz, ebar, &pc, &dc, &jlo, &nj, lbar);
                     if (dcommit) dcommit[a] = dn[a];
                     x[a] = wrap(c, x[a] + dn[a]);
-                    p[a] = p1[a];
+                    p[a] = pc;
                 }
             } else {
                 for (int64_t a = 0; a < n; ++a) {
