@@ -116,8 +116,8 @@ typedef struct {
     int32_t fp32_sweeps; /* of which in FP32 (precision form) */
     double residual;  /* last max-norm increment (length / field units) */
     int32_t crossing_queue; /* Subsystem I: nonzero if some sweep redid the particles whose step
-                               crosses a cell boundary through its per-wave queue (degree >= 4 and
-                               at least 1024 particles per wave); 0 for Subsystem II */
+                               crosses a cell boundary through its per-wave queue (degree >= 4,
+                               when some step crosses); 0 for Subsystem II */
     int32_t sweeps_adjoint; /* ecpic_step with ECPIC_SYMMETRIC, Subsystem I entries: sweeps of the
                                step's closing adjoint substep (sweeps is the opening one's); else 0 */
 } ecpic_iter_stats;

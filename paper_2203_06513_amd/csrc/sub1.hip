@@ -183,7 +183,10 @@ __device__ __forceinline__ void stage_records(LdsRec<P, T> *rec, const double *c
 
 // The block's own cell (record 1) from LDS into registers.  Reading them from
 // LDS rather than global memory keeps the particle loop's memory waits
-// counting only its own row loads and stores.
+// counting only its own row loads and stores.  (Moving them to scalar
+// registers, since they are wave-uniform, took the quintic sweep from three to
+// four waves per SIMD but did not make it faster, and made the cubic one 12 %
+// slower.)
 template <int P, typename T>
 __device__ __forceinline__ void own_from_lds(const LdsRec<P, T> *rec, Own<P, T> &o1) {
 #pragma unroll
@@ -238,13 +241,11 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 // current order by that commit).
 enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2, START_PREV = 3 };
 
-// Rows a wave must hold for the sweep to queue its crossing lanes (degree >= 4).
-constexpr int QUEUE_MIN_ROWS = 16;
-
-// The queue of crossing lanes (see the sweep loop): per wave, in dynamic LDS,
-// the indices of the particles to redo.  (Keeping their position, momentum
-// and increment there instead of reloading them was measured slower.)
-constexpr int QCAP = 2 * WAVE;
+// The queue of crossing lanes (see the sweep loop, degree >= 4): per wave, in
+// dynamic LDS, the indices of the particles to redo, room for every particle
+// of the wave.  (Keeping their position, momentum and increment there instead
+// of reloading them was measured slower.)
+constexpr int QCAP = MAX_CHUNK;
 inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * sizeof(int); }
 
 template <int P, bool SEIDEL, typename T, int START, bool ADJ>
@@ -322,13 +323,15 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     // from d^(k+1) for the Seidel deposit) need the neighbour-cell terms; they
     // are few, so the row is computed with the own-cell terms only, and such a
     // lane's particle is queued (its index, in LDS) and redone with the full
-    // terms once a whole row of them has gathered.  Without the queue every row
-    // holding one crossing lane would run the neighbour code for all 64 lanes.
+    // terms, a row of 64 at a time, after the wave's last row (the loop then
+    // holds none of the neighbour code's registers).  Without the queue every
+    // row holding one crossing lane would run the neighbour code for all 64
+    // lanes.
     int *const q = queue + (size_t)wid * QCAP;
     int qn = 0;   // queued particles (wave-uniform)
-    auto redo = [&](int n) {   // the first n queued particles, with every term
+    auto redo = [&](int qb, int n) {   // queued particles qb .. qb + n - 1, with every term
         const bool qv = lane < n;
-        const int qi = q[qv ? lane : 0];
+        const int qi = q[qb + (qv ? lane : 0)];
         Lane<T> Lq;
         const double xq = a.xi[qi];
         Lq.p0 = (T)a.p[qi];
@@ -363,11 +366,10 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             nstay += __popcll(__builtin_amdgcn_ballot_w64(sc == 0) & qmask);
         }
     };
-    // The queue pays for itself on long runs of rows and at high degree (the
-    // neighbour terms cost more there; measured: 11 % faster at degree 5, 10 %
-    // slower at degree 3).  Otherwise a row with a crossing lane computes the
-    // neighbour terms for all its lanes.
-    if (P >= 4 && we - wb >= QUEUE_MIN_ROWS * WAVE) {
+    // The queue pays at high degree, where the neighbour terms cost more
+    // (measured: 11 % faster at degree 5, 10 % slower at degree 3).  At degree
+    // 3 a row with a crossing lane computes the neighbour terms for all lanes.
+    if constexpr (P >= 4) {
         for (int row = wb; row < we; row += WAVE, ia += WAVE) {
             Lane<T> La;
             const double xi0 = nx;
@@ -412,17 +414,9 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
                 if (valid && cross) q[qn + __popcll(dmask & below)] = ia;
                 qn += __popcll(dmask);
-                if (qn >= WAVE) {
-                    redo(WAVE);
-                    qn -= WAVE;
-                    if (lane < qn) {   // move the rest to the front
-                        const int v = q[WAVE + lane];
-                        q[lane] = v;
-                    }
-                }
             }
         }
-        if (qn > 0) redo(qn);
+        for (int qb = 0; qb < qn; qb += WAVE) redo(qb, min(WAVE, qn - qb));
     } else {
         for (int row = wb; row < we; row += WAVE, ia += WAVE) {
             Lane<T> La;
@@ -487,28 +481,14 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
 
 // One block per work item; the grid may exceed the item count (the count of a
 // step enqueued ahead is only known on the device) and the extra blocks exit.
-// ADJ: the adjoint scheme (FP64, Seidel map, explicit start only).
-template <int P, bool SEIDEL, typename T, bool ADJ>
+// One kernel per start mode (the host knows it), so that each is allocated the
+// registers it needs rather than the most any mode needs.  ADJ: the adjoint
+// scheme (FP64, Seidel map, explicit start or read).
+template <int P, bool SEIDEL, typename T, int START, bool ADJ>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     extern __shared__ int queue[];    // the waves' queues (degree >= 4)
-    if (a.k == 0 && a.explicit_start) {
-        sweep_I_item<P, SEIDEL, T, START_EXPLICIT, ADJ>(a, blockIdx.x, rec, queue);
-        return;
-    }
-    if constexpr (!ADJ) {
-        if (a.k == 0 && a.dprev) {
-            sweep_I_item<P, SEIDEL, T, START_PREV, ADJ>(a, blockIdx.x, rec, queue);
-            return;
-        }
-        if constexpr (sizeof(T) == 8) {
-            if (a.d32in) {
-                sweep_I_item<P, SEIDEL, T, START_FLOAT, ADJ>(a, blockIdx.x, rec, queue);
-                return;
-            }
-        }
-    }
-    sweep_I_item<P, SEIDEL, T, START_READ, ADJ>(a, blockIdx.x, rec, queue);
+    sweep_I_item<P, SEIDEL, T, START, ADJ>(a, blockIdx.x, rec, queue);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -1213,20 +1193,31 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
 
 
 // ---- launchers ------------------------------------------------------------
+template <int P, bool SEIDEL, typename T, bool ADJ>
+void launch_sweep_mode(const SweepIArgs &a, int grid, int block, size_t lds, hipStream_t s) {
+    if (a.k == 0 && a.explicit_start)
+        launch_k((k_sweep_I<P, SEIDEL, T, START_EXPLICIT, ADJ>), dim3(grid), dim3(block), lds, s, a);
+    else if (!ADJ && a.k == 0 && a.dprev)
+        launch_k((k_sweep_I<P, SEIDEL, T, START_PREV, ADJ>), dim3(grid), dim3(block), lds, s, a);
+    else if (!ADJ && sizeof(T) == 8 && a.d32in)
+        launch_k((k_sweep_I<P, SEIDEL, T, START_FLOAT, ADJ>), dim3(grid), dim3(block), lds, s, a);
+    else
+        launch_k((k_sweep_I<P, SEIDEL, T, START_READ, ADJ>), dim3(grid), dim3(block), lds, s, a);
+}
+
 void launch_sweep_I(int P, bool seidel, bool fp32, bool adj, int grid, int block, hipStream_t s,
                     const SweepIArgs &a) {
     const size_t lds = P >= 4 ? queue_lds_bytes(block) : 0;   // the queue is used from degree 4 on
-#define ECPIC_SW(PP)                                                                                          \
-    case PP:                                                                                                  \
-        if (adj) {                                                                                            \
-            launch_k((k_sweep_I<PP, true, double, true>), dim3(grid), dim3(block), lds, s, a);                \
-        } else if (fp32) {                                                                                    \
-            if (seidel) launch_k((k_sweep_I<PP, true, float, false>), dim3(grid), dim3(block), lds, s, a);    \
-            else launch_k((k_sweep_I<PP, false, float, false>), dim3(grid), dim3(block), lds, s, a);          \
-        } else {                                                                                              \
-            if (seidel) launch_k((k_sweep_I<PP, true, double, false>), dim3(grid), dim3(block), lds, s, a);   \
-            else launch_k((k_sweep_I<PP, false, double, false>), dim3(grid), dim3(block), lds, s, a);         \
-        }                                                                                                     \
+#define ECPIC_SW(PP)                                                                             \
+    case PP:                                                                                     \
+        if (adj) launch_sweep_mode<PP, true, double, true>(a, grid, block, lds, s);              \
+        else if (fp32) {                                                                         \
+            if (seidel) launch_sweep_mode<PP, true, float, false>(a, grid, block, lds, s);       \
+            else launch_sweep_mode<PP, false, float, false>(a, grid, block, lds, s);             \
+        } else {                                                                                 \
+            if (seidel) launch_sweep_mode<PP, true, double, false>(a, grid, block, lds, s);      \
+            else launch_sweep_mode<PP, false, double, false>(a, grid, block, lds, s);            \
+        }                                                                                        \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW

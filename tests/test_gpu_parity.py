@@ -273,11 +273,11 @@ def test_pump2048_full_size_two_steps_elementwise():
 
 @pytest.mark.parametrize("p,seidel", [(4, 1), (5, 0), (5, 1)])
 def test_crossing_queue_elementwise(p, seidel):
-    """From degree 4 on, a wave that holds at least 1024 particles computes every row with
-    the own-cell terms and queues the particles whose step crosses a cell boundary, redoing
-    them a row at a time with every term.  One wave per item and 1500 particles per cell
-    make every wave take that path (more than 64 crossings each, so both the full-row and
-    the final partial redo run); two steps against the oracle element by element."""
+    """From degree 4 on, a wave computes every row with the own-cell terms and queues the
+    particles whose step crosses a cell boundary, redoing them with every term, 64 at a
+    time, after its last row.  One wave per item and 1500 particles per cell give every
+    wave more than 64 crossings (full and partial redo rows); two steps against the oracle
+    element by element, in this launch shape and in the default one."""
     w = workloads.get("langmuir64").scaled(degree=p, M=32, n_particles=48000, sigma=0.5)
     arr = workloads.generate(w)
     o = Oracle.from_workload(w, seidel=seidel)
@@ -293,11 +293,14 @@ def test_crossing_queue_elementwise(p, seidel):
     assert queued.all(), queued
     assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
     assert_state_close(g, s, w.L)
-    # the default launch shape (four waves per item here) does not queue
-    with gpu_ctx(w, map=seidel) as c:
+    with gpu_ctx(w, map=seidel) as c:   # four waves per item here
         c.load(start, solve_gauss=False)
-        c.step(1)
-        assert not c.last_queue_I.any()
+        rc, done, gI, gII, _ = c.step(2)
+        queued = c.last_queue_I.copy()
+        g = c.state()
+    assert queued.all(), queued
+    assert gI.tolist() == kI.tolist() and gII.tolist() == kII.tolist()
+    assert_state_close(g, s, w.L)
 
 
 def test_stress16384_full_size_step_properties():
