@@ -109,6 +109,10 @@ typedef struct {
                                  0 => chosen from the item count (about four waves per SIMD).
                                  Results do not depend on it beyond rounding order. */
     int32_t splitting;        /* ecpic_splitting */
+    int32_t item_particles;   /* launch shape: at most this many particles of one cell per work item
+                                 (a power of two in [2048, 16384]); 0 => twice the mean particles per
+                                 cell, so that cells normally hold one item.  Results do not depend
+                                 on it beyond rounding order. */
 } ecpic_config;
 
 typedef struct {

@@ -45,7 +45,8 @@ class Config(C.Structure):
                 ("weight", C.c_double), ("dt", C.c_double), ("picard_tol", C.c_double),
                 ("picard_max_iter", C.c_int32), ("precision", C.c_int32), ("warmstart", C.c_int32),
                 ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32),
-                ("sweep_guess", C.c_int32), ("waves_per_item", C.c_int32), ("splitting", C.c_int32)]
+                ("sweep_guess", C.c_int32), ("waves_per_item", C.c_int32), ("splitting", C.c_int32),
+                ("item_particles", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -157,12 +158,12 @@ class Context:
                  weight: float = 0.0, max_iter: int = 0, precision: int = FP64,
                  warmstart: int = WS_EXPLICIT, map: int = MAP_JACOBI, device: int = 0,
                  stream: Optional[int] = None, fp32_sweeps: int = 0, sweep_guess: int = 0,
-                 waves_per_item: int = 0, splitting: int = LIE_TROTTER):
+                 waves_per_item: int = 0, splitting: int = LIE_TROTTER, item_particles: int = 0):
         self._lib = load()
         self.cfg = Config(float(L), int(M), int(degree), int(n_particles), float(weight), float(dt),
                           float(tol), int(max_iter), int(precision), int(warmstart), int(map), int(device),
                           C.c_void_p(stream) if stream else None, int(fp32_sweeps), int(sweep_guess),
-                          int(waves_per_item), int(splitting))
+                          int(waves_per_item), int(splitting), int(item_particles))
         self.dt = float(dt)
         self.M = int(M)
         self.N = int(n_particles)

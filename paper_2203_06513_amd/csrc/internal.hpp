@@ -23,7 +23,11 @@ namespace ecpic {
 constexpr int HALO = 8;
 constexpr int MAX_DEG = 5;
 constexpr int MAX_HIST = 128;
-constexpr int MAX_CHUNK = 2048;   // particles of one work item (one cell or a part of it)
+// Particles of one work item (a cell, or a part of a cell holding more): at least
+// MIN_CHUNK, raised to twice the mean particles per cell (a power of two, at most
+// MAX_CHUNK) so that cells normally hold one item each.
+constexpr int MIN_CHUNK = 2048;
+constexpr int MAX_CHUNK = 16384;
 
 // Error bits raised by kernels.
 enum : int32_t { FLAG_NONFINITE = 1, FLAG_CFL = 2, FLAG_ORDER = 4 };

@@ -913,7 +913,9 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
         (g.map != ECPIC_MAP_JACOBI && g.map != ECPIC_MAP_SEIDEL) ||
         (g.warmstart != ECPIC_WS_EXPLICIT && g.warmstart != ECPIC_WS_PREVIOUS && g.warmstart != ECPIC_WS_MLP) ||
         g.weight < 0.0 || g.waves_per_item < 0 || g.waves_per_item > MAX_WAVES_PER_ITEM ||
-        (g.splitting != ECPIC_LIE_TROTTER && g.splitting != ECPIC_SYMMETRIC))
+        (g.splitting != ECPIC_LIE_TROTTER && g.splitting != ECPIC_SYMMETRIC) ||
+        (g.item_particles != 0 && (g.item_particles < MIN_CHUNK || g.item_particles > MAX_CHUNK ||
+                                   (g.item_particles & (g.item_particles - 1)) != 0)))
         return ECPIC_EINVAL;
     int rc = check_device(g.device);
     if (rc) return rc;
@@ -940,7 +942,12 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->ws_prev = g.warmstart == ECPIC_WS_PREVIOUS;
     c->symmetric = g.splitting == ECPIC_SYMMETRIC;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
-    c->chunk = MAX_CHUNK;
+    // One work item per cell where the cells allow (the item list is then the
+    // cell index, and the commit needs no list-building pass): items hold up to
+    // twice the mean count, from MIN_CHUNK to MAX_CHUNK particles.
+    c->chunk = MIN_CHUNK;
+    if (g.item_particles > 0) c->chunk = g.item_particles;
+    else while (c->chunk < MAX_CHUNK && c->chunk < 2.0 * ppc) c->chunk *= 2;
     // Waves per work item: enough items x waves to give every SIMD (1024 on the
     // chip) about four waves, and otherwise as few waves per item as possible,
     // so each wave streams many rows of particles (measured best on the pump

@@ -242,10 +242,9 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2, START_PREV = 3 };
 
 // The queue of crossing lanes (see the sweep loop, degree >= 4): per wave, in
-// dynamic LDS, the indices of the particles to redo, room for every particle
-// of the wave.  (Keeping their position, momentum and increment there instead
-// of reloading them was measured slower.)
-constexpr int QCAP = MAX_CHUNK;
+// dynamic LDS, the indices of the particles to redo.  (Keeping their position,
+// momentum and increment there instead of reloading them was measured slower.)
+constexpr int QCAP = 2 * WAVE;
 inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * sizeof(int); }
 
 template <int P, bool SEIDEL, typename T, int START, bool ADJ>
@@ -323,10 +322,9 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     // from d^(k+1) for the Seidel deposit) need the neighbour-cell terms; they
     // are few, so the row is computed with the own-cell terms only, and such a
     // lane's particle is queued (its index, in LDS) and redone with the full
-    // terms, a row of 64 at a time, after the wave's last row (the loop then
-    // holds none of the neighbour code's registers).  Without the queue every
-    // row holding one crossing lane would run the neighbour code for all 64
-    // lanes.
+    // terms once a whole row of them has gathered (the rest after the wave's
+    // last row).  Without the queue every row holding one crossing lane would
+    // run the neighbour code for all 64 lanes.
     int *const q = queue + (size_t)wid * QCAP;
     int qn = 0;   // queued particles (wave-uniform)
     auto redo = [&](int qb, int n) {   // queued particles qb .. qb + n - 1, with every term
@@ -414,9 +412,17 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
                 if (valid && cross) q[qn + __popcll(dmask & below)] = ia;
                 qn += __popcll(dmask);
+                if (qn >= WAVE) {
+                    redo(0, WAVE);
+                    qn -= WAVE;
+                    if (lane < qn) {   // move the rest to the front
+                        const int v = q[WAVE + lane];
+                        q[lane] = v;
+                    }
+                }
             }
         }
-        for (int qb = 0; qb < qn; qb += WAVE) redo(qb, min(WAVE, qn - qb));
+        if (qn > 0) redo(0, qn);
     } else {
         for (int row = wb; row < we; row += WAVE, ia += WAVE) {
             Lane<T> La;

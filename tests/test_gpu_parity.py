@@ -421,7 +421,7 @@ def test_item_count_changes_within_steps(case):
     st, kI, kII, E = o.step(s, nsteps, energies=True)
     assert st == 0
     kw = {"sweep_guess": 1} if case.endswith("guess1") else {}
-    with gpu_ctx(w, map=ec.MAP_SEIDEL, **kw) as c:
+    with gpu_ctx(w, map=ec.MAP_SEIDEL, item_particles=2048, **kw) as c:
         c.load(arr)
         H0 = c.energy()[4]
         rc, done, gI, gII, _ = c.step(nsteps)
