@@ -311,19 +311,35 @@ __global__ void __launch_bounds__(256) k_gather_sorted(const int32_t *val, const
     id[i] = v;
 }
 
-__global__ void __launch_bounds__(256) k_count_cells(const int32_t *key, int64_t n, int32_t *count) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicAdd(&count[key[i]], 1);
-}
-
-// Particles per cell of a cell-sorted order (xi in [0, M)), for an item list
-// rebuilt from the particles alone.
-__global__ void __launch_bounds__(256) k_count_cells_xi(const double *xi, int64_t n, int M, int32_t *count) {
+// Particles per cell of a cell-grouped order (each cell's particles contiguous,
+// cells ascending), from the ends of the runs: the first particle of cell c's run
+// adds -i and the last adds i + 1, two atomics per occupied cell whatever its
+// count (one atomic per particle serialised on the cell's address: 69 ms for
+// 1.28e8 particles in 16384 cells).  count must be zero on entry.
+template <class CellOf>
+__device__ __forceinline__ void count_runs(CellOf cell_of, int64_t n, int32_t *count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double v = xi[i];
-    const int c = v >= 0.0 && v < (double)M ? (int)v : 0;
-    atomicAdd(&count[c], 1);
+    const int c = cell_of(i);
+    const bool first = i == 0 || cell_of(i - 1) != c;
+    const bool last = i == n - 1 || cell_of(i + 1) != c;
+    const int add = (first ? -(int)i : 0) + (last ? (int)(i + 1) : 0);
+    if (first || last) atomicAdd(&count[c], add);
+}
+
+__global__ void __launch_bounds__(256) k_count_cells(const int32_t *key, int64_t n, int32_t *count) {
+    count_runs([=](int64_t j) { return key[j]; }, n, count);
+}
+
+// The same from the particles' positions (xi in [0, M), cell-grouped), for an
+// item list rebuilt from the particles alone.
+__global__ void __launch_bounds__(256) k_count_cells_xi(const double *xi, int64_t n, int M, int32_t *count) {
+    count_runs(
+        [=](int64_t j) {
+            const double v = xi[j];
+            return v >= 0.0 && v < (double)M ? (int)v : 0;
+        },
+        n, count);
 }
 
 __global__ void __launch_bounds__(1024) k_items_from_counts(const int32_t *count, int32_t *start, int M, int chunk,

@@ -106,8 +106,10 @@ struct PushEnd {
 // Momentum update and next increment; anycross is wave-uniform.  ADJ: the
 // adjoint scheme, whose force divides by gamma(x0, P) + gamma(x1, P) and whose
 // next increment is that of the new momentum (dt (p0 + p1) / (gamma(x0, p0) +
-// gamma(x0, p1))).
-template <int P, typename T, bool ADJ = false>
+// gamma(x0, p1))).  MOM: p1 is wanted (the commit); a sweep needs only the
+// increment, which it then forms with one reciprocal instead of two (p1 and
+// the flags' finiteness test take N = p1 (g00 + g01) in its place).
+template <int P, typename T, bool ADJ = false, bool MOM = true>
 __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
                                            const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags,
                                            PushEnd<T> *pe = nullptr) {
@@ -135,8 +137,12 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
             DAz = (sA * DAz + sB * divdiff<P>(nb.az, hb)) * inv;
         }
     } else {
-        A1y = horner<P + 1>(o.ay, L.t1);
-        A1z = horner<P + 1>(o.az, L.t1);
+        // A at the end point from the divided difference: A1 = A0 + (t1 - t0) DA
+        // (the same value as evaluating A there, in two operations instead of
+        // 2P; and (A0 + A1).DA (t1 - t0) = |A1|^2 - |A0|^2 then holds to rounding)
+        const T dt1 = L.t1 - L.t0;
+        A1y = fma(dt1, DAy, L.A0y);
+        A1z = fma(dt1, DAz, L.A0z);
     }
     const T qa1 = A1y * A1y + A1z * A1z;
     T g11;
@@ -146,12 +152,24 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
         p1 = fma(dt, F, L.p0);
         const T g10n = fsqrt(fma(p1, p1, one) + L.qa0);
         dn = dt_dx * (L.p0 + p1) * frcp(L.g00 + g10n);
-    } else {
+    } else if constexpr (MOM) {
         const T g01 = fsqrt(L.q0 + qa1);
         const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
         p1 = fma(dt, F, L.p0);
         g11 = fsqrt(fma(p1, p1, one) + qa1);
         dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
+    } else {
+        // with U = g00 + g01 and N = p1 U = p0 U + dt (LE U - X):
+        //   gamma(p1, A1) = sqrt(U^2 (1 + |A1|^2) + N^2) / U, so
+        //   d^(k+1) = (dt/dx) (p0 U + N) / (g01 U + sqrt(U^2 (1 + |A1|^2) + N^2))
+        const T g01 = fsqrt(L.q0 + qa1);
+        const T U = L.g00 + g01;
+        const T X = ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx;
+        const T N = fma(dt, fma(LE, U, -X), L.p0 * U);
+        const T W = fma(N, N, U * U * (one + qa1));
+        dn = dt_dx * fma(L.p0, U, N) * frcp(fma(g01, U, fsqrt(W)));
+        p1 = N;
+        g11 = (T)0;
     }
     if (pe) {
         pe->A1y = A1y;
@@ -242,13 +260,23 @@ __device__ __forceinline__ void to_double(const Moments32<P> &m, Moments<P> &o) 
 enum : int { START_READ = 0, START_EXPLICIT = 1, START_FLOAT = 2, START_PREV = 3 };
 
 // The queue of crossing lanes (see the sweep loop, degree >= 4): per wave, in
-// dynamic LDS, the indices of the particles to redo.  (Keeping their position,
-// momentum and increment there instead of reloading them was measured slower.)
+// dynamic LDS, the particles to redo: position, momentum and increment as
+// loaded, and the index.  (Reloading them from memory instead, when a row of
+// them has gathered some 30 rows later, fetched whole lines again for 8 bytes
+// each: 5 bytes per particle and sweep more HBM traffic at degree 5.)
 constexpr int QCAP = 2 * WAVE;
-inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * sizeof(int); }
+struct QueueW {
+    double *x, *p, *d;
+    int *i;
+};
+inline size_t queue_lds_bytes(int block) { return (size_t)(block / WAVE) * QCAP * (3 * sizeof(double) + sizeof(int)); }
+__device__ __forceinline__ QueueW queue_of_wave(double *base, int wid) {
+    double *w = base + (size_t)wid * QCAP * 7 / 2;   // 3 doubles and an int per slot (QCAP even)
+    return QueueW{w, w + QCAP, w + 2 * QCAP, reinterpret_cast<int *>(w + 3 * QCAP)};
+}
 
 template <int P, bool SEIDEL, typename T, int START, bool ADJ>
-__device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsRec<P, T> *rec, int *queue) {
+__device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsRec<P, T> *rec, double *queue) {
     static_assert(!ADJ || SEIDEL, "the adjoint scheme deposits the increment it has just produced");
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
@@ -325,21 +353,20 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     // terms once a whole row of them has gathered (the rest after the wave's
     // last row).  Without the queue every row holding one crossing lane would
     // run the neighbour code for all 64 lanes.
-    int *const q = queue + (size_t)wid * QCAP;
+    const QueueW q = queue_of_wave(queue, wid);
     int qn = 0;   // queued particles (wave-uniform)
     auto redo = [&](int qb, int n) {   // queued particles qb .. qb + n - 1, with every term
         const bool qv = lane < n;
-        const int qi = q[qb + (qv ? lane : 0)];
+        const int qs = qb + (qv ? lane : 0);
+        const int qi = q.i[qs];
         Lane<T> Lq;
-        const double xq = a.xi[qi];
-        Lq.p0 = (T)a.p[qi];
-        if constexpr (from_float) Lq.d = (T)d32in[qi];
-        else if constexpr (from_prev) Lq.d = (T)dprev[qi];
-        else if constexpr (!explicit_start) Lq.d = din[qi];
+        const double xq = q.x[qs];
+        Lq.p0 = (T)q.p[qs];
+        if constexpr (!explicit_start) Lq.d = (T)q.d[qs];
         stage_gather<P, T, explicit_start, ADJ>(o1, Lq, xq, c, dt_dx, flags, dx_dt);
         const bool cr = __ballot(Lq.s != 0) != 0;
         T pq, dq;
-        stage_push<P, T, ADJ>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
+        stage_push<P, T, ADJ, false>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
         flags |= FLAG_QUEUED;
         if (qv) {
             if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[qi] = Lq.d;
@@ -387,7 +414,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             // own-cell terms for every lane; a crossing lane's result is discarded
             // (it stays finite: its end point is clamped into (-1, 2) and |d| < dt/dx < 1)
             T pa, dna;
-            stage_push<P, T, ADJ>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ, false>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
             bool cross = La.s != 0;
             T ta = La.t1;
             if constexpr (SEIDEL) {
@@ -410,14 +437,24 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             const uint64_t dmask = __builtin_amdgcn_ballot_w64(valid && cross);
             if (dmask) {
                 const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));
-                if (valid && cross) q[qn + __popcll(dmask & below)] = ia;
+                if (valid && cross) {
+                    const int qs = qn + __popcll(dmask & below);
+                    q.i[qs] = ia;
+                    q.x[qs] = xi0;
+                    q.p[qs] = (double)La.p0;
+                    q.d[qs] = (double)La.d;
+                }
                 qn += __popcll(dmask);
                 if (qn >= WAVE) {
                     redo(0, WAVE);
                     qn -= WAVE;
                     if (lane < qn) {   // move the rest to the front
-                        const int v = q[WAVE + lane];
-                        q[lane] = v;
+                        const int vi = q.i[WAVE + lane];
+                        const double vx = q.x[WAVE + lane], vp = q.p[WAVE + lane], vd = q.d[WAVE + lane];
+                        q.i[lane] = vi;
+                        q.x[lane] = vx;
+                        q.p[lane] = vp;
+                        q.d[lane] = vd;
                     }
                 }
             }
@@ -443,7 +480,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             stage_gather<P, T, explicit_start, ADJ>(o1, La, xi0, c, dt_dx, flags, dx_dt);
             const bool cross1 = __ballot(La.s != 0) != 0;
             T pa, dna;
-            stage_push<P, T, ADJ>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ, false>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
             if (valid) {
                 if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
                 rmax = fmax(rmax, fabs(dna - La.d));
@@ -493,7 +530,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
 template <int P, bool SEIDEL, typename T, int START, bool ADJ>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
-    extern __shared__ int queue[];    // the waves' queues (degree >= 4)
+    extern __shared__ double queue[];   // the waves' queues (degree >= 4)
     sweep_I_item<P, SEIDEL, T, START, ADJ>(a, blockIdx.x, rec, queue);
 }
 
