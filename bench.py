@@ -146,24 +146,63 @@ def run_form(ec, w, arr, learned: bool, steps: int, warmup: int, profile_steps: 
     with ec.Context.from_workload(w, **kw) as ctx:
         ctx.load(arr)
         if learned:
-            stride = max(1, N // 100_000)
-            per_step = (N + stride - 1) // stride
-            ctx.ws_record(stride, record_steps * per_step)
-            t0 = time.perf_counter()
-            ctx.step(record_steps)
-            n_pairs = ctx.ws_records()
-            ctx.ws_record(0)
-            t1 = time.perf_counter()
-            loss = ctx.ws_train(steps=train_steps, batch=1024, lr=2e-3, seed=5)
-            t2 = time.perf_counter()
-            ctx.ws_enable(True)
-            out["training"] = {"pairs": int(n_pairs), "record_steps": record_steps, "record_s": t1 - t0,
-                               "train_steps": train_steps, "train_s": t2 - t1, "final_loss": loss}
+            out["training"] = train_learned(ctx, N, record_steps, train_steps)
         ctx.step(warmup)
         r = timed_run(ctx, steps)
         k = kernel_profile(ctx, profile_steps)
     out.update(r)
     out["kernels"] = k
+    return out
+
+
+def train_learned(ctx, N: int, record_steps: int, train_steps: int):
+    """Record (features, converged increment) pairs over record_steps steps of the method
+    itself, train the network on them and switch the predictor on."""
+    stride = max(1, N // 100_000)
+    per_step = (N + stride - 1) // stride
+    ctx.ws_record(stride, record_steps * per_step)
+    t0 = time.perf_counter()
+    ctx.step(record_steps)
+    n_pairs = ctx.ws_records()
+    ctx.ws_record(0)
+    t1 = time.perf_counter()
+    loss = ctx.ws_train(steps=train_steps, batch=1024, lr=2e-3, seed=5)
+    t2 = time.perf_counter()
+    ctx.ws_enable(True)
+    return {"pairs": int(n_pairs), "record_steps": record_steps, "record_s": t1 - t0,
+            "train_steps": train_steps, "train_s": t2 - t1, "final_loss": loss}
+
+
+AB_FORMS = ("explicit", "previous", "learned_fp64", "learned_fp32")
+
+
+def warm_start_ab(ec, w, arr, steps: int, warmup: int, record_steps: int, train_steps: int, fp32_sweeps: int):
+    """The starting iterates of Subsystem I side by side over the same steps: the explicit
+    increment dt p / gamma, the previous step's converged increment, the network's
+    prediction followed by FP64 sweeps, and the network's prediction followed by FP32
+    then FP64 sweeps.  Per form: ms/step, mean sweeps (FP64 and FP32), the median over
+    steps of the residuals of the first four FP64 sweeps (each within a factor 1 +- rho
+    of the error of the iterate that sweep started from) and the energy drift over the
+    run."""
+    out = {}
+    for kind in AB_FORMS:
+        kw = dict(map=ec.MAP_SEIDEL)
+        if kind == "previous":
+            kw["warmstart"] = ec.WS_PREVIOUS
+        if kind == "learned_fp32":
+            kw.update(precision=ec.FP32_MIXED, fp32_sweeps=fp32_sweeps)
+        with ec.Context.from_workload(w, **kw) as ctx:
+            ctx.load(arr)
+            if kind.startswith("learned"):
+                train_learned(ctx, w.n_particles, record_steps, train_steps)
+            ctx.step(warmup)
+            r = timed_run(ctx, steps)
+            rh = ctx.last_res_hist_I
+        k32 = float(np.mean(r["k32"]))
+        out[kind] = {"ms_per_step": 1e3 * r["elapsed"] / steps, "mean_sweeps_I_fp64": float(np.mean(r["kI"])) - k32,
+                     "mean_sweeps_I_fp32": k32,
+                     "median_fp64_residuals": [float(np.median(rh[:, i])) for i in range(4)],
+                     "rel_energy_drift": r["drift"]}
     return out
 
 
@@ -190,6 +229,14 @@ def summarize(w, r):
     return d
 
 
+def cache_note(name: str, sweep_bytes_total: float, frac: float) -> str:
+    mb = sweep_bytes_total / 1e6
+    if mb < 256.0:
+        return (f"{name} moves {mb:.0f} MB per sweep, inside the 256 MB last-level cache: its sweep fraction "
+                f"({frac:.3f}) is not an HBM figure")
+    return f"{name} moves {mb:.0f} MB per sweep, beyond the 256 MB last-level cache"
+
+
 def describe(w):
     return (f"{w.name}: L={w.L / np.pi:g}pi, M={w.M}, degree {w.degree}, N={w.n_particles}, dt={w.dt}, "
             f"tol={w.tol}, wave={w.wave} a0={w.amplitude} mode {w.wave_mode}, sigma={w.sigma}")
@@ -212,6 +259,9 @@ def main():
     ap.add_argument("--graded-profile-steps", type=int, default=4)
     ap.add_argument("--graded-record-steps", type=int, default=20)
     ap.add_argument("--forms", default="plain,learned", help="forms to run on the headline workload")
+    ap.add_argument("--ab", default="stress16384,langmuir4096",
+                    help="workloads of the warm-start comparison (comma separated, empty for none)")
+    ap.add_argument("--ab-steps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -259,6 +309,18 @@ def main():
         print(f"bench: {name} plain {gp['ms_per_step']:.3f} ms/step (sweep {gp.get('sweep_I_hbm_frac', 0):.3f} "
               f"of HBM), learned {gl['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
 
+    # ---- starting iterates of Subsystem I, side by side ------------------------
+    ab = {}
+    for name in [g for g in args.ab.split(",") if g]:
+        wa = workloads.get(name)
+        aa = workloads.generate(wa)
+        ab[name] = warm_start_ab(ec, wa, aa, args.ab_steps, args.graded_warmup, args.graded_record_steps,
+                                 args.train_steps, args.fp32_sweeps)
+        del aa
+        print(f"bench: {name} warm starts, ms/step: " +
+              ", ".join(f"{k} {v['ms_per_step']:.3f} ({v['mean_sweeps_I_fp64']:.2f} FP64 sweeps)"
+                        for k, v in ab[name].items()), file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel, the FP64 Subsystem I sweep of the plain form, on
     # the largest graded workload (else the headline one)
     if "stress16384" in graded:
@@ -296,9 +358,8 @@ def main():
                    "plain_fp64": {k: sp[k] for k in ("value", "ms_per_step", "mean_sweeps_I", "mean_iters_II",
                                                      "rel_energy_drift", "gauss_change_linf")},
                    "speedup_vs_plain_fp64": sl["value"] / sp["value"],
-                   "cache_note": f"{w.name} moves {N * sweep_bytes(sp['mean_sweeps_I']) / 1e6:.0f} MB per sweep, "
-                                 "inside the 256 MB last-level cache: its sweep fraction "
-                                 f"({sp.get('sweep_I_hbm_frac', 0):.3f}) is not an HBM figure"},
+                   "cache_note": cache_note(w.name, N * sweep_bytes(sp["mean_sweeps_I"]),
+                                            sp.get("sweep_I_hbm_frac", 0))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(rw.name, rw.n_particles),
                      "kernel": f"k_sweep_I<{rw.degree},true,double,false> (FP64 Subsystem I sweep, plain form)",
@@ -306,6 +367,7 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_us": sweep_us,
                      "copy_probe_GBs": copy_gbs},
         "graded": graded,
+        "warm_start_ab": {"steps": args.ab_steps, "workloads": ab},
         "kernels_plain": sp["kernels_us"],
         "kernels_learned": sl["kernels_us"],
     }

@@ -124,6 +124,12 @@ typedef struct {
                                when some step crosses); 0 for Subsystem II */
     int32_t sweeps_adjoint; /* ecpic_step with ECPIC_SYMMETRIC, Subsystem I entries: sweeps of the
                                step's closing adjoint substep (sweeps is the opening one's); else 0 */
+    double residual_hist[4];  /* Subsystem I: residuals of the substep's first four FP64 sweeps (the
+                                 max-norm change each made to the iterate it started from,
+                                 increments in length units or the field, whichever is larger;
+                                 0 past the last sweep): how far each iterate was from the fixed
+                                 point, to a factor 1 +- rho, rho the contraction of the map.
+                                 Zero for Subsystem II. */
 } ecpic_iter_stats;
 
 typedef struct {

@@ -51,7 +51,7 @@ class Config(C.Structure):
 
 class IterStats(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("fp32_sweeps", C.c_int32), ("residual", C.c_double),
-                ("crossing_queue", C.c_int32), ("sweeps_adjoint", C.c_int32)]
+                ("crossing_queue", C.c_int32), ("sweeps_adjoint", C.c_int32), ("residual_hist", C.c_double * 4)]
 
 
 class WsTrainConfig(C.Structure):
@@ -246,6 +246,7 @@ class Context:
         st = IterStats()
         rc = self._lib.ecpic_substep_particles(self._h, self.dt if dt is None else float(dt), C.byref(st))
         self.last_stats_I = (st.sweeps, st.fp32_sweeps, st.residual, st.crossing_queue, rc)
+        self.last_res_hist_I = np.array(st.residual_hist[:])
         if check:
             _ck(rc, "substep_particles")
         return st.sweeps, st.residual
@@ -279,6 +280,7 @@ class Context:
         k32 = np.array([sI[i].fp32_sweeps for i in range(nsteps)], dtype=np.int32)
         self.last_queue_I = np.array([sI[i].crossing_queue for i in range(nsteps)], dtype=np.int32)
         self.last_sweeps_I2 = np.array([sI[i].sweeps_adjoint for i in range(nsteps)], dtype=np.int32)
+        self.last_res_hist_I = np.array([sI[i].residual_hist[:] for i in range(nsteps)]).reshape(nsteps, 4)
         return rc, done.value, kI, kII, k32
 
     # -- diagnostics ------------------------------------------------------------

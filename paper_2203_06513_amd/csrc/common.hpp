@@ -139,6 +139,7 @@ __device__ __forceinline__ void init_status(DevStatus *st, const DevStatus *gate
     st->scan_multi = 0;
     st->queued = 0;
     st->res = 0.0;
+    for (int i = 0; i < 4; ++i) st->res_first[i] = 0.0;
     st->gate = gate_src ? (gate_src->committed && gate_src->flags == 0) : 1;
 }
 

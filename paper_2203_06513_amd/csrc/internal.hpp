@@ -55,6 +55,7 @@ struct DevStatus {
     int32_t scan_multi;              // a field kernel of the substep saw a cell with other than one item
     int32_t queued;                  // some sweep of the substep redid crossing lanes through its queue
     double res;                      // residual of sweep kconv (length / field units)
+    double res_first[4];             // residuals of the first four FP64 sweeps (0 if not run)
     double res_hist[MAX_HIST];       // residual of each evaluated sweep
 };
 

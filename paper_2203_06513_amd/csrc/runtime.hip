@@ -428,6 +428,12 @@ int fp32_sweeps_done_I(const ecpic_ctx *c) {
     return std::min(std::max(c->kI - (c->ws_on ? 1 : 0), 0), c->k32);
 }
 
+// Residuals of the last Subsystem I substep's first FP64 sweeps (each recorded
+// by the convergence test that follows the sweep; 0 past the last).
+void first_residuals_I(const ecpic_ctx *c, double *r) {
+    for (int i = 0; i < 4; ++i) r[i] = c->h->I.res_first[i];
+}
+
 void enqueue_commit_I(ecpic_ctx *c) {
     CommitIArgs a{};
     a.cur = c->pb[c->cur];
@@ -678,6 +684,7 @@ int substep_I(ecpic_ctx *c, double dt, ecpic_iter_stats *stats, bool adjoint) {
         stats->fp32_sweeps = fp32_sweeps_done_I(c);
         stats->residual = c->h->I.res;
         stats->crossing_queue = c->h->I.queued;
+        first_residuals_I(c, stats->residual_hist);
     }
     if (rc) {
         c->have_prev = had_prev;   // no commit: the increments are those of before
@@ -1184,6 +1191,7 @@ int ecpic_substep_fields(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
         stats->fp32_sweeps = 0;
         stats->residual = c->h->II.res;
         stats->crossing_queue = 0;
+        for (double &r : stats->residual_hist) r = 0.0;
     }
     if (rc) return rc;
     c->guessII = std::max(1, c->h->II.kconv + 1);
@@ -1227,6 +1235,7 @@ void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII)
         sI->residual = c->h->I.res;
         sI->crossing_queue = c->h->I.queued;
         sI->sweeps_adjoint = 0;
+        first_residuals_I(c, sI->residual_hist);
     }
     if (sII) {
         sII->sweeps = c->h->II.kconv >= 0 ? c->h->II.kconv + 1 : c->kII;
@@ -1234,6 +1243,7 @@ void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII)
         sII->residual = c->h->II.res;
         sII->crossing_queue = 0;
         sII->sweeps_adjoint = 0;
+        for (double &r : sII->residual_hist) r = 0.0;
     }
 }
 

@@ -221,6 +221,7 @@ __device__ __forceinline__ bool prev_converged(DevStatus *st, int k, int first64
     if (k <= first64) return false;
     const double r = fmax(dbits(rxb) * dx, dbits(reb));
     if (writer && k - 1 < MAX_HIST) st->res_hist[k - 1] = r;
+    if (writer && k - 1 - first64 < 4) st->res_first[k - 1 - first64] = r;
     if (r <= tol) {
         if (writer) { st->kconv = k - 1; st->res = r; }
         return true;

@@ -101,6 +101,38 @@ def test_previous_step_start_in_single_steps_and_after_a_new_state():
         np.testing.assert_array_equal(s1[k], s2[k])
 
 
+@pytest.mark.parametrize("warm", ["explicit", "previous"])
+def test_residual_history_matches_oracle(warm):
+    """The residuals the step reports for its first FP64 sweeps equal the oracle's: the
+    residual of sweep k is what a substep limited to k + 1 sweeps ends with (run on a copy
+    of the state at the step's start, from the same starting increments)."""
+    w = workloads.get("langmuir64").scaled(n_particles=4000)
+    arr = workloads.generate(w)
+    o = Oracle.from_workload(w, seidel=1)
+    short = [Oracle.from_workload(w, seidel=1, kmax=k) for k in (1, 2, 3)]
+    s = initial_state(o, arr)
+    nsteps, ref, dprev = 5, [], None
+    for j in range(nsteps):
+        ds = dprev if warm == "previous" else None
+        r = []
+        for ok in short:
+            s1 = {k: v.copy() for k, v in s.items()}
+            r.append(ok.substep_I(s1, None, dstart=ds)[2])
+        ref.append(r)
+        dc = np.zeros(w.n_particles)
+        assert o.substep_I(s, None, dstart=ds, dcommit=dc)[0] == 0
+        assert o.substep_II(s)[0] == 0
+        dprev = dc
+    ref = np.array(ref)
+    kw = {"warmstart": ec.WS_PREVIOUS} if warm == "previous" else {}
+    with ec.Context.from_workload(w, map=ec.MAP_SEIDEL, **kw) as c:
+        c.load(arr)
+        c.step(nsteps)
+        got = c.last_res_hist_I
+    assert ref.min() > 1e-11   # the three sweeps compared are far from the tolerance
+    np.testing.assert_allclose(got[:, :3], ref, rtol=1e-6, atol=0)
+
+
 # --------------------------------------------------------------------------
 # device memory and a stream from PyTorch
 # --------------------------------------------------------------------------
