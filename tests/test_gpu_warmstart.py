@@ -102,7 +102,10 @@ def test_ws_tables_vs_fp64_forward():
     err = np.abs(tab - ref).max()
     spread = np.abs(ref - mu[D]).max()
     print(f"\ntable vs FP64 forward: max error {err:.3e}, output spread {spread:.3e}")
-    assert err <= 3e-2 * spread
+    # BF16 keeps 8 significant bits (unit roundoff 2^-9); the products of layer 2
+    # round their inputs so, and the 64-term sums partly cancel the errors.  Measured
+    # 3.6e-3 of the spread; the bar is three times that.
+    assert err <= 1.2e-2 * spread
 
 
 @pytest.fixture(scope="module")
