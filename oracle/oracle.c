@@ -50,6 +50,21 @@
  *   - optionally (splitting = 1) a step is the symmetric composition
  *     Subsystem I over dt/2, Subsystem II over dt, adjoint Subsystem I over dt/2
  *     (second order in dt); splitting = 0 is the Lie-Trotter step of Section 5.
+ * With spin (the *_s functions; hbar = the normalised Planck constant):
+ *   - the Zeeman energy of eq. discrete_H, hbar sum_a w (s_y dA_z/dx - s_z dA_y/dx)
+ *     at x_a, enters Subsystem I through the divided difference of dA/dx along
+ *     the step, evaluated as sum_j (G G a)_j times the line mean of the degree
+ *     p-2 splines Lambda2_j (d/dx Lambda1_j = (Lambda2_j - Lambda2_{j+1}) / dx),
+ *     the same 0/0-free identity one degree down; the sign is the one the
+ *     gradient of that energy gives (the printed discrete gradient drops a sign
+ *     and a weight), and it matches the printed momentum update;
+ *   - Subsystem II gains the constant source -/+ hbar G^T Lambda1(X)^T W S_{z/y},
+ *     multiplied by dt in the combined (M0 + dt^2 K/4) system (the M0^{-1}
+ *     printed there is a slip: the e_y scheme multiplied by M0 has none);
+ *   - Subsystem III rotates every spin exactly about r = (0, Z, -Y),
+ *     Y = dA_y/dx(x_a), Z = dA_z/dx(x_a), by Rodrigues' formula;
+ *   - a Lie-Trotter step with spin is I, II, III; the symmetric one
+ *     I(dt/2), III(dt/2), II(dt), III(dt/2), adjoint I(dt/2).
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,6 +84,7 @@ typedef struct {
     int32_t seidel;             /* 0: Jacobi map, 1: current from the fresh increment */
     int32_t splitting;          /* 0: Lie-Trotter (I then II), 1: I(dt/2), II(dt), adjoint I(dt/2) */
     int32_t warm_previous;      /* 1: Subsystem I starts from the last committed increments */
+    double hbar;                /* spin coupling (the *_s functions) */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_ENOTCONV = -3, ORC_ENOMEM = -2 };
@@ -265,23 +281,23 @@ void orc_solve_cn(const orc_cfg *c, const double *b, double *x) { solve(c, orc_a
 /* Line integrals along the straight trajectory (Subsystem I scheme).    */
 /* ------------------------------------------------------------------ */
 
-/* Mean of Lambda1_j over the segment between x0 and x1 (unwrapped positions):
- * lbar_j = (1/dt) int Lambda1_j(x(tau)) dtau = (1/(x1-x0)) int_{x0}^{x1} Lambda1_j.
- * The segment is cut at the knots and each piece integrated by Gauss-Legendre
- * (exact for degree p-1); piece means are combined with weights len/total, so
- * no 0/0 arises; for x1 == x0 the mean is Lambda1_j(x0).  Returns the number of
- * entries written to vals for the unwrapped indices *jlo, *jlo+1, ... */
-int orc_line_mean(const orc_cfg *c, double x0, double x1, long *jlo, double *vals)
+/* Mean of the degree-d splines B_d((x - x_j)/dx) over the segment between x0 and
+ * x1 (unwrapped positions): (1/(x1-x0)) int_{x0}^{x1} B_d((x - x_j)/dx) dx.  The
+ * segment is cut at the knots and each piece integrated by Gauss-Legendre
+ * (exact for degree d <= 11); piece means are combined with weights len/total,
+ * so no 0/0 arises; for x1 == x0 the mean is the value at x0.  Returns the
+ * number of entries written to vals for the unwrapped indices *jlo, *jlo+1, ... */
+static int line_mean_deg(const orc_cfg *c, int d, double x0, double x1, long *jlo, double *vals)
 {
     double dx = dx_of(c);
     double lo = x0 < x1 ? x0 : x1, hi = x0 < x1 ? x1 : x0;
     long ilo = cell_of(c, lo), ihi = cell_of(c, hi);
-    long j0 = ilo - c->p + 1;
-    int nj = (int)(ihi - ilo) + c->p;
+    long j0 = ilo - d;
+    int nj = (int)(ihi - ilo) + d + 1;
     *jlo = j0;
     for (int k = 0; k < nj; ++k) vals[k] = 0.0;
     if (hi == lo) {
-        for (long j = j0; j <= ihi; ++j) vals[j - j0] = orc_lambda1(c, j, lo);
+        for (long j = j0; j <= ihi; ++j) vals[j - j0] = orc_bspline(d, lo / dx - (double)j);
         return nj;
     }
     double total = hi - lo;
@@ -292,11 +308,27 @@ int orc_line_mean(const orc_cfg *c, double x0, double x1, long *jlo, double *val
         double frac = (e - s) / total;
         for (int q = 0; q < 6; ++q) {
             double xq = 0.5 * (s + e) + 0.5 * (e - s) * GL_X[q];
-            for (long j = cell - c->p + 1; j <= cell; ++j)
-                vals[j - j0] += frac * 0.5 * GL_W[q] * orc_lambda1(c, j, xq);
+            for (long j = cell - d; j <= cell; ++j)
+                vals[j - j0] += frac * 0.5 * GL_W[q] * orc_bspline(d, xq / dx - (double)j);
         }
     }
     return nj;
+}
+
+/* Mean of Lambda1_j over the segment (the time average of the basis along the
+ * straight trajectory of the Subsystem I scheme): lbar_j = (1/dt) int
+ * Lambda1_j(x(tau)) dtau = (1/(x1-x0)) int_{x0}^{x1} Lambda1_j. */
+int orc_line_mean(const orc_cfg *c, double x0, double x1, long *jlo, double *vals)
+{
+    return line_mean_deg(c, c->p - 1, x0, x1, jlo, vals);
+}
+
+/* Mean of Lambda2_j = B_{p-2}((x - x_j)/dx) over the segment: the divided
+ * difference of a V1 field phi = sum c_j Lambda1_j along the step is
+ * sum_j (G c)_j times these means (spin force of Subsystem I). */
+int orc_line_mean2(const orc_cfg *c, double x0, double x1, long *jlo, double *vals)
+{
+    return line_mean_deg(c, c->p - 2, x0, x1, jlo, vals);
 }
 
 /* Current deposit J_j = sum_a w int_{x0_a}^{x1_a} Lambda1_j (length units), the
@@ -410,18 +442,38 @@ static double wrap(const orc_cfg *c, double x)
     return x;
 }
 
+/* Spin force of the Subsystem I scheme on one particle stepping from x0 to x1:
+ * hbar [s_z (dA_y/dx(x1) - dA_y/dx(x0)) - s_y (dA_z/dx(x1) - dA_z/dx(x0))] / (x1 - x0),
+ * the divided differences taken as sum_j (G G a)_j mean_j(Lambda2) (hy = G G a_y,
+ * hz = G G a_z). */
+static double spin_force(const orc_cfg *c, double x0, double x1, double sy, double sz, const double *hy,
+                         const double *hz)
+{
+    long jlo;
+    double m2[16];
+    int nj = orc_line_mean2(c, x0, x1, &jlo, m2);
+    double DDy = 0.0, DDz = 0.0;
+    for (int k = 0; k < nj; ++k) {
+        long j = imod(jlo + k, c->M);
+        DDy += m2[k] * hy[j];
+        DDz += m2[k] * hz[j];
+    }
+    return c->hbar * (sz * DDy - sy * DDz);
+}
+
 /* One particle of one Picard sweep.  Inputs: start x0, p0, iterate delta, field
- * coefficients a_y, a_z, gy = G a_y, gz = G a_z and ebar = (e^n + e^(k))/2.
- * Outputs: p1 (the momentum update), the next delta and the line-mean vector
- * (for the current).  The discrete gradients are those of the Subsystem I
- * scheme with hbar = 0:
- *   p1 = p0 + dt [ lbar.ebar - (A0 + A1).DA / (g(p0,A0) + g(p0,A1)) ],
+ * coefficients a_y, a_z, gy = G a_y, gz = G a_z and ebar = (e^n + e^(k))/2; with
+ * spin also the particle's s_y, s_z and hy = G G a_y, hz = G G a_z (NULL: no
+ * spin term).  Outputs: p1 (the momentum update), the next delta and the
+ * line-mean vector (for the current).  The discrete gradients are those of the
+ * Subsystem I scheme:
+ *   p1 = p0 + dt [ lbar.ebar - (A0 + A1).DA / (g(p0,A0) + g(p0,A1)) + spin force ],
  *   delta' = dt (p0 + p1) / (g(p0,A1) + g(p1,A1)),
  * with DA = (A1 - A0)/(x1 - x0) = sum_j (G a)_j lbar_j. */
-void orc_particle_map(const orc_cfg *c, double x0, double p0, double delta,
-                      const double *ay, const double *az, const double *gy, const double *gz,
-                      const double *ebar, double *p1_out, double *delta_out,
-                      long *jlo, int *nj, double *lbar)
+static void particle_map_s(const orc_cfg *c, double x0, double p0, double delta, double sy, double sz,
+                           const double *ay, const double *az, const double *gy, const double *gz,
+                           const double *hy, const double *hz, const double *ebar, double *p1_out,
+                           double *delta_out, long *jlo, int *nj, double *lbar)
 {
     double x1 = x0 + delta;
     double A0y = orc_field0(c, ay, x0), A0z = orc_field0(c, az, x0);
@@ -437,17 +489,40 @@ void orc_particle_map(const orc_cfg *c, double x0, double p0, double delta,
         LGz += lbar[k] * gz[j];
     }
     double F = LE - ((A0y + A1y) * LGy + (A0z + A1z) * LGz) / (g00 + g01);
+    if (hy) F += spin_force(c, x0, x1, sy, sz, hy, hz);
     double p1 = p0 + c->dt * F;
     double g11 = sqrt(1.0 + p1 * p1 + A1y * A1y + A1z * A1z);
     *p1_out = p1;
     *delta_out = c->dt * (p0 + p1) / (g01 + g11);
 }
 
+void orc_particle_map(const orc_cfg *c, double x0, double p0, double delta,
+                      const double *ay, const double *az, const double *gy, const double *gz,
+                      const double *ebar, double *p1_out, double *delta_out,
+                      long *jlo, int *nj, double *lbar)
+{
+    particle_map_s(c, x0, p0, delta, 0.0, 0.0, ay, az, gy, gz, NULL, NULL, ebar, p1_out, delta_out, jlo, nj,
+                   lbar);
+}
+
+/* The same with the spin term (hy = G G a_y, hz = G G a_z). */
+void orc_particle_map_spin(const orc_cfg *c, double x0, double p0, double delta, double sy, double sz,
+                           const double *ay, const double *az, const double *gy, const double *gz,
+                           const double *hy, const double *hz, const double *ebar, double *p1_out,
+                           double *delta_out)
+{
+    long jlo;
+    int nj;
+    double lbar[16];
+    particle_map_s(c, x0, p0, delta, sy, sz, ay, az, gy, gz, hy, hz, ebar, p1_out, delta_out, &jlo, &nj, lbar);
+}
+
 /* Solve Subsystem I over the time step h by Picard iteration; on success x, p, ex
  * hold the new state.  dstart (nullable): initial increments instead of the
  * explicit h p / gamma; dcommit (nullable): receives the committed increments. */
-int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
-                    const double *az, const double *dstart, double *dcommit, int32_t *sweeps, double *res)
+int orc_substep_I_hs(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                     const double *az, const double *sy, const double *sz, const double *dstart,
+                     double *dcommit, int32_t *sweeps, double *res)
 {
     orc_cfg ch = *cfg;
     ch.dt = h;
@@ -463,6 +538,13 @@ int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *
     if (!d || !dn || !p1 || !ek || !enew || !ebar || !J || !MJ || !gy || !gz) return ORC_ENOMEM;
     orc_apply_G(c, ay, gy);
     orc_apply_G(c, az, gz);
+    /* spin: second differences G G a for the divided differences of dA/dx */
+    const int spin = sy != NULL;
+    double *hy = spin ? malloc(sizeof(double) * M) : NULL, *hz = spin ? malloc(sizeof(double) * M) : NULL;
+    if (spin) {
+        orc_apply_G(c, gy, hy);
+        orc_apply_G(c, gz, hz);
+    }
     for (int64_t a = 0; a < n; ++a) {
         double Ay = orc_field0(c, ay, x[a]), Az = orc_field0(c, az, x[a]);
         d[a] = dstart ? dstart[a] : c->dt * p[a] / sqrt(1.0 + p[a] * p[a] + Ay * Ay + Az * Az);
@@ -479,7 +561,8 @@ int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *
             long jlo;
             int nj;
             double lbar[16];
-            orc_particle_map(c, x[a], p[a], d[a], ay, az, gy, gz, ebar, &p1[a], &dn[a], &jlo, &nj, lbar);
+            particle_map_s(c, x[a], p[a], d[a], spin ? sy[a] : 0.0, spin ? sz[a] : 0.0, ay, az, gy, gz, hy, hz,
+                           ebar, &p1[a], &dn[a], &jlo, &nj, lbar);
             double step = c->seidel ? dn[a] : d[a];
             if (c->seidel) nj = orc_line_mean(c, x[a], x[a] + step, &jlo, lbar);
             double inc = (x[a] + step) - x[a];
@@ -504,7 +587,8 @@ int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *
                     long jlo;
                     int nj;
                     double lbar[16], pc, dc;
-                    orc_particle_map(c, x[a], p[a], dn[a], ay, az, gy, gz, ebar, &pc, &dc, &jlo, &nj, lbar);
+                    particle_map_s(c, x[a], p[a], dn[a], spin ? sy[a] : 0.0, spin ? sz[a] : 0.0, ay, az, gy, gz,
+                                   hy, hz, ebar, &pc, &dc, &jlo, &nj, lbar);
                     if (dcommit) dcommit[a] = dn[a];
                     x[a] = wrap(c, x[a] + dn[a]);
                     p[a] = pc;
@@ -527,7 +611,15 @@ int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *
     if (sweeps) *sweeps = k;
     if (res) *res = r;
     free(d); free(dn); free(p1); free(ek); free(enew); free(ebar); free(J); free(MJ); free(gy); free(gz);
+    free(hy); free(hz);
     return status;
+}
+
+/* Subsystem I over the time step h without spin. */
+int orc_substep_I_h(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                    const double *az, const double *dstart, double *dcommit, int32_t *sweeps, double *res)
+{
+    return orc_substep_I_hs(cfg, h, x, p, ex, ay, az, NULL, NULL, dstart, dcommit, sweeps, res);
 }
 
 /* Subsystem I over the configured step, explicit start. */
@@ -558,9 +650,10 @@ int orc_substep_I(const orc_cfg *c, double *x, double *p, double *ex, const doub
  *   P'    = p0 + h [lbar(x0, x1).ebar - (A0 + A1).DA / (g(x0, P) + g(x1, P))],
  *   delta' = h (p0 + P') / (g(x0, p0) + g(x0, P')),
  * where DA = (A1 - A0)/(x1 - x0) = sum_j (G a)_j lbar_j. */
-void orc_particle_map_adjoint(const orc_cfg *c, double x0, double p0, double P,
-                              const double *ay, const double *az, const double *gy, const double *gz,
-                              const double *ebar, double *delta_out, double *P_out, double *delta_next)
+static void adjoint_map_s(const orc_cfg *c, double x0, double p0, double P, double sy, double sz,
+                          const double *ay, const double *az, const double *gy, const double *gz,
+                          const double *hy, const double *hz, const double *ebar, double *delta_out,
+                          double *P_out, double *delta_next)
 {
     double A0y = orc_field0(c, ay, x0), A0z = orc_field0(c, az, x0);
     double qa0 = A0y * A0y + A0z * A0z;
@@ -581,11 +674,19 @@ void orc_particle_map_adjoint(const orc_cfg *c, double x0, double p0, double P,
         LGz += lbar[k] * gz[j];
     }
     double F = LE - ((A0y + A1y) * LGy + (A0z + A1z) * LGz) / (g10 + g11);
+    if (hy) F += spin_force(c, x0, x1, sy, sz, hy, hz);   /* independent of p: the same in both orders */
     double Pn = p0 + c->dt * F;
     double g10n = sqrt(1.0 + Pn * Pn + qa0);
     *delta_out = delta;
     *P_out = Pn;
     *delta_next = c->dt * (p0 + Pn) / (g00 + g10n);
+}
+
+void orc_particle_map_adjoint(const orc_cfg *c, double x0, double p0, double P,
+                              const double *ay, const double *az, const double *gy, const double *gz,
+                              const double *ebar, double *delta_out, double *P_out, double *delta_next)
+{
+    adjoint_map_s(c, x0, p0, P, 0.0, 0.0, ay, az, gy, gz, NULL, NULL, ebar, delta_out, P_out, delta_next);
 }
 
 /* The adjoint Subsystem I scheme over the time step h, by Picard iteration on
@@ -595,8 +696,9 @@ void orc_particle_map_adjoint(const orc_cfg *c, double x0, double p0, double P,
  * change of the increment and of e; the commit is x^n + delta^(k+1), P^(k+1),
  * e^(k+1) (position and deposit from one increment: Gauss's law holds
  * exactly).  dcommit (nullable) receives the committed increments. */
-int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
-                          const double *az, double *dcommit, int32_t *sweeps, double *res)
+int orc_substep_I_adjoint_s(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                            const double *az, const double *sy, const double *sz, double *dcommit,
+                            int32_t *sweeps, double *res)
 {
     orc_cfg ch = *cfg;
     ch.dt = h;
@@ -612,6 +714,12 @@ int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, do
     if (!P || !Pn || !dn || !ek || !enew || !ebar || !J || !MJ || !gy || !gz) return ORC_ENOMEM;
     orc_apply_G(c, ay, gy);
     orc_apply_G(c, az, gz);
+    const int spin = sy != NULL;
+    double *hy = spin ? malloc(sizeof(double) * M) : NULL, *hz = spin ? malloc(sizeof(double) * M) : NULL;
+    if (spin) {
+        orc_apply_G(c, gy, hy);
+        orc_apply_G(c, gz, hz);
+    }
     for (int64_t a = 0; a < n; ++a) P[a] = p[a];
     memcpy(ek, ex, sizeof(double) * M);
     int status = ORC_ENOTCONV;
@@ -623,7 +731,8 @@ int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, do
         double rx = 0.0;
         for (int64_t a = 0; a < n; ++a) {
             double dk;
-            orc_particle_map_adjoint(c, x[a], p[a], P[a], ay, az, gy, gz, ebar, &dk, &Pn[a], &dn[a]);
+            adjoint_map_s(c, x[a], p[a], P[a], spin ? sy[a] : 0.0, spin ? sz[a] : 0.0, ay, az, gy, gz, hy, hz,
+                          ebar, &dk, &Pn[a], &dn[a]);
             long jlo;
             double lbar[16];
             int nj = orc_line_mean(c, x[a], x[a] + dn[a], &jlo, lbar);
@@ -658,7 +767,14 @@ int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, do
     if (sweeps) *sweeps = k;
     if (res) *res = r;
     free(P); free(Pn); free(dn); free(ek); free(enew); free(ebar); free(J); free(MJ); free(gy); free(gz);
+    free(hy); free(hz);
     return status;
+}
+
+int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, double *ex, const double *ay,
+                          const double *az, double *dcommit, int32_t *sweeps, double *res)
+{
+    return orc_substep_I_adjoint_s(cfg, h, x, p, ex, ay, az, NULL, NULL, dcommit, sweeps, res);
 }
 
 /* ------------------------------------------------------------------ */
@@ -670,8 +786,20 @@ int orc_substep_I_adjoint(const orc_cfg *cfg, double h, double *x, double *p, do
  *   b = sum_a w (A^{n+1}(x_a) + A^n(x_a)) Lambda0(x_a) / (g^n_a + g^{n+1}_a),
  *   a^{n+1} = a^n - dt/2 (e^n + e^{n+1}),
  * with the particle term lagged one iteration and the matrix inverted exactly. */
-int orc_substep_II_h(const orc_cfg *cfg, double h, const double *x, const double *p, double *ey, double *ez,
-                     double *ay, double *az, int32_t *iters, double *res)
+/* V1 deposit of the spins, u_j = sum_a w s_a Lambda1_j(x_a) (the vector
+ * Lambda1(X)^T W S of the Subsystem II spin source). */
+static void deposit_spin_v1(const orc_cfg *c, const double *x, const double *s, double *u)
+{
+    memset(u, 0, sizeof(double) * c->M);
+    for (int64_t a = 0; a < c->n; ++a) {
+        long i = cell_of(c, x[a]);
+        for (long j = i - c->p + 1; j <= i; ++j) u[imod(j, c->M)] += c->w * s[a] * orc_lambda1(c, j, x[a]);
+    }
+}
+
+int orc_substep_II_hs(const orc_cfg *cfg, double h, const double *x, const double *p, const double *sy,
+                      const double *sz, double *ey, double *ez, double *ay, double *az, int32_t *iters,
+                      double *res)
 {
     orc_cfg ch = *cfg;
     ch.dt = h;
@@ -698,6 +826,17 @@ int orc_substep_II_h(const orc_cfg *cfg, double h, const double *x, const double
     orc_apply_cn_minus(c, ez, rhs_z);
     orc_apply_K(c, az, t);
     for (int j = 0; j < M; ++j) rhs_z[j] += c->dt * t[j];
+    if (sy) {
+        /* spin source: e_y gains -hbar G^T Lambda1^T W S_z, e_z gains +hbar G^T Lambda1^T W S_y */
+        double *u = malloc(sizeof(double) * M);
+        deposit_spin_v1(c, x, sz, u);
+        orc_apply_GT(c, u, t);
+        for (int j = 0; j < M; ++j) rhs_y[j] -= c->dt * c->hbar * t[j];
+        deposit_spin_v1(c, x, sy, u);
+        orc_apply_GT(c, u, t);
+        for (int j = 0; j < M; ++j) rhs_z[j] += c->dt * c->hbar * t[j];
+        free(u);
+    }
 
     memcpy(eky, ey, sizeof(double) * M);
     memcpy(ekz, ez, sizeof(double) * M);
@@ -753,11 +892,138 @@ int orc_substep_II_h(const orc_cfg *cfg, double h, const double *x, const double
     return status;
 }
 
+int orc_substep_II_h(const orc_cfg *cfg, double h, const double *x, const double *p, double *ey, double *ez,
+                     double *ay, double *az, int32_t *iters, double *res)
+{
+    return orc_substep_II_hs(cfg, h, x, p, NULL, NULL, ey, ez, ay, az, iters, res);
+}
+
 /* Subsystem II over the configured step. */
 int orc_substep_II(const orc_cfg *c, const double *x, const double *p, double *ey, double *ez,
                    double *ay, double *az, int32_t *iters, double *res)
 {
     return orc_substep_II_h(c, c->dt, x, p, ey, ez, ay, az, iters, res);
+}
+
+/* ------------------------------------------------------------------ */
+/* Subsystem III (Section 4.2): the spins, everything else fixed.        */
+/* ------------------------------------------------------------------ */
+
+/* Each spin obeys ds/dt = rhat s with
+ *   rhat = [[0, Y, Z], [-Y, 0, 0], [-Z, 0, 0]],  Y = dA_y/dx(x_a), Z = dA_z/dx(x_a),
+ * a constant matrix over the substep (x and a_perp are fixed), i.e. ds/dt =
+ * r x s with r = (0, Z, -Y).  The exact solution over h is the rotation of
+ * eq. spin_rodrigue:
+ *   s^{n+1} = (I + sin(h|r|)/|r| rhat + 1/2 (sin(h|r|/2)/(|r|/2))^2 rhat^2) s^n,
+ * written here with the matrix rhat and its square as printed (|r| = 0: the
+ * identity). */
+void orc_substep_III_h(const orc_cfg *c, double h, const double *x, const double *ay, const double *az,
+                       double *sx, double *sy, double *sz)
+{
+    int M = c->M;
+    double *gy = malloc(sizeof(double) * M), *gz = malloc(sizeof(double) * M);
+    orc_apply_G(c, ay, gy);
+    orc_apply_G(c, az, gz);
+    for (int64_t a = 0; a < c->n; ++a) {
+        double Y = orc_field1(c, gy, x[a]), Z = orc_field1(c, gz, x[a]);
+        double R[3][3] = {{0.0, Y, Z}, {-Y, 0.0, 0.0}, {-Z, 0.0, 0.0}};
+        double R2[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                R2[i][j] = 0.0;
+                for (int k = 0; k < 3; ++k) R2[i][j] += R[i][k] * R[k][j];
+            }
+        double nr = sqrt(Y * Y + Z * Z);
+        if (nr == 0.0) continue;
+        double c1 = sin(h * nr) / nr;
+        double hs = sin(0.5 * h * nr) / (0.5 * nr);
+        double c2 = 0.5 * hs * hs;
+        double s0[3] = {sx[a], sy[a], sz[a]}, s1[3];
+        for (int i = 0; i < 3; ++i) {
+            s1[i] = s0[i];
+            for (int j = 0; j < 3; ++j) s1[i] += (c1 * R[i][j] + c2 * R2[i][j]) * s0[j];
+        }
+        sx[a] = s1[0]; sy[a] = s1[1]; sz[a] = s1[2];
+    }
+    free(gy); free(gz);
+}
+
+/* Discrete Hamiltonian with the Zeeman term of eq. discrete_H:
+ * parts = {kinetic, 1/2 ex^T M1 ex, 1/2 sum e_c^T M0 e_c, 1/2 sum a_c^T K a_c,
+ *          hbar sum_a w (s_y dA_z/dx - s_z dA_y/dx)(x_a), H}. */
+void orc_energy_s(const orc_cfg *c, const double *x, const double *p, const double *sy, const double *sz,
+                  const double *ex, const double *ey, const double *ez, const double *ay, const double *az,
+                  double *parts)
+{
+    double five[5];
+    orc_energy(c, x, p, ex, ey, ez, ay, az, five);
+    int M = c->M;
+    double *gy = malloc(sizeof(double) * M), *gz = malloc(sizeof(double) * M);
+    orc_apply_G(c, ay, gy);
+    orc_apply_G(c, az, gz);
+    double zee = 0.0;
+    for (int64_t a = 0; a < c->n; ++a)
+        zee += c->w * (sy[a] * orc_field1(c, gz, x[a]) - sz[a] * orc_field1(c, gy, x[a]));
+    zee *= c->hbar;
+    for (int i = 0; i < 4; ++i) parts[i] = five[i];
+    parts[4] = zee;
+    parts[5] = five[4] + zee;
+    free(gy); free(gz);
+}
+
+/* Steps with spin.  splitting = 0: Lie-Trotter I, II, III.  splitting = 1: the
+ * symmetric composition I(dt/2), III(dt/2), II(dt), III(dt/2), adjoint I(dt/2)
+ * (Subsystems II and III are self-adjoint: the discrete gradient of II is
+ * symmetric in the two time levels, III is an exact flow).  On failure the state
+ * (spins included) is restored to the start of the failing step.  energy rows
+ * hold the six parts of orc_energy_s. */
+int orc_step_s(const orc_cfg *c, int32_t nsteps, double *x, double *p, double *sx, double *sy, double *sz,
+               double *ex, double *ey, double *ez, double *ay, double *az, int32_t *sweeps_I,
+               int32_t *iters_II, int32_t *sweeps_I2, double *energy_per_step /* nsteps+1 x 6, nullable */)
+{
+    int M = c->M;
+    int64_t n = c->n;
+    size_t nb = sizeof(double) * (n > 0 ? n : 1);
+    double *save = malloc(nb * 5), *sf = malloc(sizeof(double) * 5 * M);
+    double *dprev = c->warm_previous ? malloc(nb) : NULL;
+    int have_prev = 0;
+    int status = ORC_OK;
+    double h = c->splitting ? 0.5 * c->dt : c->dt;
+    if (energy_per_step) orc_energy_s(c, x, p, sy, sz, ex, ey, ez, ay, az, energy_per_step);
+    for (int s = 0; s < nsteps; ++s) {
+        memcpy(save, x, sizeof(double) * n); memcpy(save + n, p, sizeof(double) * n);
+        memcpy(save + 2 * n, sx, sizeof(double) * n); memcpy(save + 3 * n, sy, sizeof(double) * n);
+        memcpy(save + 4 * n, sz, sizeof(double) * n);
+        memcpy(sf, ex, sizeof(double) * M); memcpy(sf + M, ey, sizeof(double) * M);
+        memcpy(sf + 2 * M, ez, sizeof(double) * M); memcpy(sf + 3 * M, ay, sizeof(double) * M);
+        memcpy(sf + 4 * M, az, sizeof(double) * M);
+        int32_t k1 = 0, k2 = 0, k3 = 0;
+        int st = orc_substep_I_hs(c, h, x, p, ex, ay, az, sy, sz, have_prev ? dprev : NULL, dprev, &k1, NULL);
+        if (st == ORC_OK) {
+            if (c->splitting) orc_substep_III_h(c, h, x, ay, az, sx, sy, sz);
+            st = orc_substep_II_hs(c, c->dt, x, p, sy, sz, ey, ez, ay, az, &k2, NULL);
+        }
+        if (st == ORC_OK) orc_substep_III_h(c, h, x, ay, az, sx, sy, sz);
+        if (st == ORC_OK && c->splitting)
+            st = orc_substep_I_adjoint_s(c, h, x, p, ex, ay, az, sy, sz, dprev, &k3, NULL);
+        if (sweeps_I) sweeps_I[s] = k1;
+        if (iters_II) iters_II[s] = k2;
+        if (sweeps_I2) sweeps_I2[s] = k3;
+        if (st != ORC_OK) {
+            memcpy(x, save, sizeof(double) * n); memcpy(p, save + n, sizeof(double) * n);
+            memcpy(sx, save + 2 * n, sizeof(double) * n); memcpy(sy, save + 3 * n, sizeof(double) * n);
+            memcpy(sz, save + 4 * n, sizeof(double) * n);
+            memcpy(ex, sf, sizeof(double) * M); memcpy(ey, sf + M, sizeof(double) * M);
+            memcpy(ez, sf + 2 * M, sizeof(double) * M); memcpy(ay, sf + 3 * M, sizeof(double) * M);
+            memcpy(az, sf + 4 * M, sizeof(double) * M);
+            status = st;
+            break;
+        }
+        have_prev = dprev != NULL;
+        if (energy_per_step) orc_energy_s(c, x, p, sy, sz, ex, ey, ez, ay, az, energy_per_step + 6 * (s + 1));
+    }
+    free(save); free(sf); free(dprev);
+    return status;
 }
 
 /* ------------------------------------------------------------------ */

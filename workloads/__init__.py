@@ -19,6 +19,15 @@ spin term switched off, and the parametric-instability setup of Section 5.1):
   1.6e7 particles (the FP32 precision form is run on it).
 * ``stress16384`` -- L = 256 pi, 16384 cells, quintic splines, 1.28e8
   particles, pump a0 = 0.3 at k0 = 1, sigma = 0.1, dt = 0.01, tol 1e-12.
+* ``paper52`` -- the paper's run with spin (Section 5.2): the ``paper51``
+  setup with 1e4 particles, hbar = 0.1 and every spin (0, 0, 1).
+* ``spin4096`` -- the spin model at scale: the ``paper51`` physics (pump
+  E0 = sqrt 3 at k = 1/sqrt 2, T = 3/511) on 32 wavelengths, 4096 cells,
+  1.6e7 particles, hbar = 0.1, spins uniform on the unit sphere, dt = 0.02,
+  tol 1e-12.
+
+Spins are drawn after every other array, so a workload without spin draws
+exactly what it drew before spins existed.
 
 Field coefficients are sampled at the Greville abscissae x_j + (p+1) dx / 2 of
 the degree-p basis (Schoenberg's variation-diminishing quasi-interpolant); the
@@ -55,6 +64,8 @@ class Workload:
     coef_noise: float = 0.0      # std of N(0, s^2) added to a_y, a_z coefficients
     seed: int = 0
     kmax: int = 50
+    hbar: float = 0.0            # spin coupling (Section 2.1)
+    spin: str = "none"           # "none" | "z" (every spin (0, 0, 1)) | "sphere" (uniform)
 
     @property
     def dx(self) -> float:
@@ -75,8 +86,18 @@ def _paper51() -> Workload:
                     wave="paper", amplitude=math.sqrt(3.0), wave_mode=1, seed=511)
 
 
+def _spin4096() -> Workload:
+    k = 1.0 / math.sqrt(2.0)
+    return Workload(name="spin4096", L=32 * 2.0 * math.pi / k, M=4096, degree=3, n_particles=16_000_000,
+                    dt=0.02, steps=1000, tol=1e-12, sigma=math.sqrt(3.0 / 511.0), wave="paper",
+                    amplitude=math.sqrt(3.0), wave_mode=32, seed=5232, hbar=0.1, spin="sphere")
+
+
 WORKLOADS: Dict[str, Workload] = {
     "paper51": _paper51(),
+    "paper52": dataclasses.replace(_paper51(), name="paper52", n_particles=10_000, steps=10_000, seed=512,
+                                   hbar=0.1, spin="z"),
+    "spin4096": _spin4096(),
     "langmuir64": Workload(name="langmuir64", L=4.0 * math.pi, M=64, degree=3, n_particles=10_000,
                            dt=0.05, steps=100, tol=1e-13, sigma=0.1, density_ripple=0.01,
                            ripple_mode=1, wave="linear_y", amplitude=0.05, wave_mode=1, seed=101),
@@ -160,13 +181,22 @@ def _fields(w: Workload, rng: np.random.Generator):
 def generate(w: Workload, n: Optional[int] = None, seed: Optional[int] = None) -> dict:
     """Initial state arrays for workload ``w`` (float64, host).
 
-    Returns a dict with x, p (length n) and ey, ez, ay, az (length M); e_x is
-    left to the discrete Poisson solve of each implementation.
+    Returns a dict with x, p (length n) and ey, ez, ay, az (length M), and with
+    spin sx, sy, sz (length n); e_x is left to the discrete Poisson solve of each
+    implementation.
     """
     n = w.n_particles if n is None else int(n)
     rng = np.random.Generator(np.random.PCG64(w.seed if seed is None else seed))
     x = _positions(w, rng, n)
     p = rng.normal(0.0, w.sigma, n)
     ey, ez, ay, az = _fields(w, rng)
-    return {"x": x.astype(np.float64), "p": p.astype(np.float64),
-            "ey": ey, "ez": ez, "ay": ay, "az": az}
+    out = {"x": x.astype(np.float64), "p": p.astype(np.float64), "ey": ey, "ez": ez, "ay": ay, "az": az}
+    if w.spin == "z":
+        out.update(sx=np.zeros(n), sy=np.zeros(n), sz=np.ones(n))
+    elif w.spin == "sphere":
+        # uniform on the unit sphere: cos(theta) uniform in [-1, 1], azimuth uniform
+        u = rng.uniform(-1.0, 1.0, n)
+        phi = rng.uniform(0.0, 2.0 * math.pi, n)
+        r = np.sqrt(1.0 - u * u)
+        out.update(sx=r * np.cos(phi), sy=r * np.sin(phi), sz=u)
+    return out
