@@ -113,6 +113,14 @@ typedef struct {
                                  (a power of two in [2048, 16384]); 0 => twice the mean particles per
                                  cell, so that cells normally hold one item.  Results do not depend
                                  on it beyond rounding order. */
+    int32_t spin;             /* 1: the particles carry spins s_a (Section 2.1; ecpic_set_spins) and
+                                 a step is Subsystems I, II, III (symmetric: I(dt/2), III(dt/2),
+                                 II(dt), III(dt/2), adjoint I(dt/2)); 0: no spin.  Spin runs the
+                                 plain FP64 sweeps: ECPIC_FP32_MIXED and ECPIC_WS_MLP are EINVAL. */
+    double hbar;              /* normalised Planck constant of the Zeeman energy
+                                 hbar sum_a w (s_y dA_z/dx - s_z dA_y/dx)(x_a) (eq. discrete_H);
+                                 must be 0 without spin.  With hbar = 0 the spins still precess
+                                 (Subsystem III) but act on nothing. */
 } ecpic_config;
 
 typedef struct {
@@ -137,7 +145,8 @@ typedef struct {
     double e_long;    /* 1/2 e_x^T M1 e_x */
     double e_trans;   /* 1/2 (e_y^T M0 e_y + e_z^T M0 e_z) */
     double b_trans;   /* 1/2 (a_y^T K a_y + a_z^T K a_z), K = G^T M1 G */
-    double total;     /* discrete Hamiltonian H (eq. discrete_H, spin term off) */
+    double total;     /* discrete Hamiltonian H (eq. discrete_H), the Zeeman term included */
+    double zeeman;    /* hbar sum_a w (s_y dA_z/dx - s_z dA_y/dx)(x_a) (0 without spin) */
 } ecpic_energy_parts;
 
 /* Create a context on cfg->device; allocates every device buffer it needs for
@@ -159,6 +168,13 @@ int ecpic_get_particles(ecpic_ctx *ctx, double *x, double *p, int64_t n);
 /* Same, with device arrays of length n (float64). */
 int ecpic_set_particles_dev(ecpic_ctx *ctx, const double *x, const double *p, int64_t n);
 int ecpic_get_particles_dev(ecpic_ctx *ctx, double *x, double *p, int64_t n);
+
+/* Spins s_a = (s_x, s_y, s_z) of the particles (eq. f_dirac; needs cfg.spin),
+ * host arrays of n = n_particles entries each, in the order of set_particles
+ * (copied).  set_particles sets every spin to zero.  get_spins returns them in
+ * that order.  EINVAL without spin or if n differs; ESTATE before set_particles. */
+int ecpic_set_spins(ecpic_ctx *ctx, const double *sx, const double *sy, const double *sz, int64_t n);
+int ecpic_get_spins(ecpic_ctx *ctx, double *sx, double *sy, double *sz, int64_t n);
 
 /* Field coefficients (eqs. fem_e, fem_a), host arrays of length M; a NULL input
  * sets that field to zero, a NULL output skips it. */
@@ -205,15 +221,24 @@ int ecpic_substep_particles_adjoint(ecpic_ctx *ctx, double dt, ecpic_iter_stats 
  * 0 < dt < L/M.  ENOTCONV rolls back. */
 int ecpic_substep_fields(ecpic_ctx *ctx, double dt, ecpic_iter_stats *stats);
 
-/* nsteps time steps composed as cfg.splitting says (Subsystem III is the
- * identity without spin).  per_step_I / per_step_II: arrays of nsteps entries
+/* Subsystem III over dt (Section 4.2, eq. spin_rodrigue; needs cfg.spin): every
+ * spin turns about r_a = (0, dA_z/dx, -dA_y/dx)(x_a) by the exact rotation
+ * exp(dt rhat_a); positions, momenta and fields do not change, and neither do
+ * |s_a| nor the energy.  dt may be any real (negative undoes a positive one).
+ * With hbar != 0, ecpic_substep_fields also applies the spin source of
+ * Subsystem II, -/+ hbar G^T Lambda1(X)^T W S_{z/y}, and ecpic_substep_particles
+ * the spin force. */
+int ecpic_substep_spin(ecpic_ctx *ctx, double dt);
+
+/* nsteps time steps composed as cfg.splitting says (with cfg.spin the
+ * Subsystem III substeps too; without it Subsystem III is the identity).  per_step_I / per_step_II: arrays of nsteps entries
  * or NULL.  On ENOTCONV the failing step is rolled back and *steps_done (if
  * not NULL) tells how many steps completed.  Lie-Trotter steps are enqueued in
  * batches of up to 16, each gated on the device on the one before having
  * committed; a step that needs more sweeps than were enqueued is finished
  * alone and the batch resumes after it, so the result does not depend on the
- * batching.  Symmetric steps run their three substeps one after the other,
- * with a status read after each. */
+ * batching.  Symmetric steps and steps with spin run their substeps one after
+ * the other, with a status read after each. */
 int ecpic_step(ecpic_ctx *ctx, int32_t nsteps, ecpic_iter_stats *per_step_I,
                ecpic_iter_stats *per_step_II, int32_t *steps_done);
 
@@ -244,7 +269,8 @@ int ecpic_deposit_current_noalloc(ecpic_ctx *ctx, const double *x0, const double
  * Section 4.2); rho: host array of length M. */
 int ecpic_deposit_charge(ecpic_ctx *ctx, double *rho);
 
-/* Discrete Hamiltonian (eq. discrete_H with the spin term off). */
+/* Discrete Hamiltonian (eq. discrete_H), with the Zeeman term when cfg.spin is set
+ * (its value also in out->zeeman). */
 int ecpic_energy(ecpic_ctx *ctx, ecpic_energy_parts *out);
 
 /* Gauss-law residual r = G^T M1 e_x + Lambda0(X)^T W 1 - dx 1 (second remark of

@@ -25,7 +25,7 @@ EXPORTS = (
     "ecpic_create", "ecpic_destroy", "ecpic_set_particles", "ecpic_get_particles",
     "ecpic_set_particles_dev", "ecpic_get_particles_dev", "ecpic_set_fields", "ecpic_get_fields",
     "ecpic_solve_gauss", "ecpic_substep_particles", "ecpic_substep_particles_adjoint", "ecpic_substep_fields",
-    "ecpic_step",
+    "ecpic_step", "ecpic_set_spins", "ecpic_get_spins", "ecpic_substep_spin",
     "ecpic_deposit_current", "ecpic_deposit_current_noalloc", "ecpic_deposit_charge", "ecpic_energy",
     "ecpic_gauss_residual",
     "ecpic_profile_enable", "ecpic_kernel_time", "ecpic_bandwidth_probe", "ecpic_strerror",
@@ -46,7 +46,7 @@ class Config(C.Structure):
                 ("picard_max_iter", C.c_int32), ("precision", C.c_int32), ("warmstart", C.c_int32),
                 ("map", C.c_int32), ("device", C.c_int32), ("stream", C.c_void_p), ("fp32_sweeps", C.c_int32),
                 ("sweep_guess", C.c_int32), ("waves_per_item", C.c_int32), ("splitting", C.c_int32),
-                ("item_particles", C.c_int32)]
+                ("item_particles", C.c_int32), ("spin", C.c_int32), ("hbar", C.c_double)]
 
 
 class IterStats(C.Structure):
@@ -60,7 +60,7 @@ class WsTrainConfig(C.Structure):
 
 class EnergyParts(C.Structure):
     _fields_ = [("kinetic", C.c_double), ("e_long", C.c_double), ("e_trans", C.c_double),
-                ("b_trans", C.c_double), ("total", C.c_double)]
+                ("b_trans", C.c_double), ("total", C.c_double), ("zeeman", C.c_double)]
 
 
 _lib: Optional[C.CDLL] = None
@@ -101,6 +101,9 @@ def load() -> C.CDLL:
         L.ecpic_substep_particles_adjoint.argtypes = [V, C.c_double, C.POINTER(IterStats)]
         L.ecpic_substep_fields.argtypes = [V, C.c_double, C.POINTER(IterStats)]
         L.ecpic_step.argtypes = [V, C.c_int32, C.POINTER(IterStats), C.POINTER(IterStats), C.POINTER(C.c_int32)]
+        L.ecpic_set_spins.argtypes = [V, V, V, V, C.c_int64]
+        L.ecpic_get_spins.argtypes = [V, V, V, V, C.c_int64]
+        L.ecpic_substep_spin.argtypes = [V, C.c_double]
         L.ecpic_deposit_current.argtypes = [V, V, V, C.c_int64, V]
         L.ecpic_deposit_current_noalloc.argtypes = [V, V, V, C.c_int64, V, V]
         L.ecpic_deposit_charge.argtypes = [V, V]
@@ -158,12 +161,15 @@ class Context:
                  weight: float = 0.0, max_iter: int = 0, precision: int = FP64,
                  warmstart: int = WS_EXPLICIT, map: int = MAP_JACOBI, device: int = 0,
                  stream: Optional[int] = None, fp32_sweeps: int = 0, sweep_guess: int = 0,
-                 waves_per_item: int = 0, splitting: int = LIE_TROTTER, item_particles: int = 0):
+                 waves_per_item: int = 0, splitting: int = LIE_TROTTER, item_particles: int = 0,
+                 spin: bool = False, hbar: float = 0.0):
         self._lib = load()
         self.cfg = Config(float(L), int(M), int(degree), int(n_particles), float(weight), float(dt),
                           float(tol), int(max_iter), int(precision), int(warmstart), int(map), int(device),
                           C.c_void_p(stream) if stream else None, int(fp32_sweeps), int(sweep_guess),
-                          int(waves_per_item), int(splitting), int(item_particles))
+                          int(waves_per_item), int(splitting), int(item_particles), int(bool(spin)),
+                          float(hbar))
+        self.spin = bool(spin)
         self.dt = float(dt)
         self.M = int(M)
         self.N = int(n_particles)
@@ -175,6 +181,8 @@ class Context:
     def from_workload(cls, w, n: Optional[int] = None, **kw):
         n = w.n_particles if n is None else n
         args = dict(L=w.L, M=w.M, degree=w.degree, n_particles=n, dt=w.dt, tol=w.tol, max_iter=w.kmax)
+        if getattr(w, "spin", "none") != "none":
+            args.update(spin=True, hbar=w.hbar)
         args.update(kw)
         return cls(**args)
 
@@ -222,9 +230,25 @@ class Context:
             "get_fields")
         return out
 
+    def set_spins(self, sx, sy, sz):
+        a = [_arr(v, self.N) for v in (sx, sy, sz)]
+        _ck(self._lib.ecpic_set_spins(self._h, *[v.ctypes.data for v in a], self.N), "set_spins")
+
+    def get_spins(self):
+        out = [np.empty(self.N) for _ in range(3)]
+        _ck(self._lib.ecpic_get_spins(self._h, *[v.ctypes.data for v in out], self.N), "get_spins")
+        return tuple(out)
+
+    def substep_spin(self, dt: Optional[float] = None):
+        """Subsystem III (the spins' exact rotation) over dt (the configured step if None)."""
+        _ck(self._lib.ecpic_substep_spin(self._h, self.dt if dt is None else float(dt)), "substep_spin")
+
     def load(self, arrays: dict, solve_gauss: bool = True):
-        """Particles and transverse fields from a workload dict; e_x from the Poisson solve."""
+        """Particles, spins (if the dict has them) and transverse fields from a workload
+        dict; e_x from the Poisson solve."""
         self.set_particles(arrays["x"], arrays["p"])
+        if self.spin and "sx" in arrays:
+            self.set_spins(arrays["sx"], arrays["sy"], arrays["sz"])
         self.set_fields(arrays.get("ex"), arrays["ey"], arrays["ez"], arrays["ay"], arrays["az"])
         if solve_gauss:
             self.solve_gauss()
@@ -234,6 +258,8 @@ class Context:
         s = self.get_fields()
         s["x"] = x
         s["p"] = p
+        if self.spin:
+            s["sx"], s["sy"], s["sz"] = self.get_spins()
         return s
 
     # -- the method -------------------------------------------------------------
@@ -287,6 +313,7 @@ class Context:
     def energy(self) -> np.ndarray:
         e = EnergyParts()
         _ck(self._lib.ecpic_energy(self._h, C.byref(e)), "energy")
+        self.last_zeeman = e.zeeman
         return np.array([e.kinetic, e.e_long, e.e_trans, e.b_trans, e.total])
 
     def gauss_residual(self, vec: bool = False):

@@ -86,6 +86,16 @@ __device__ __forceinline__ T divdiff(const T *c, const T (&h)[P]) {
     return v;
 }
 
+// (A'(b) - A'(a))/(b - a) for A = sum_{i=0}^{P} c_i t^i, A' = dA/dt, given h_0..h_{P-1}
+// of (a, b): sum_{i=2}^{P} i c_i h_{i-2}.
+template <int P, typename T>
+__device__ __forceinline__ T divdiff2(const T *c, const T (&h)[P]) {
+    T v = (T)2 * c[2];
+#pragma unroll
+    for (int i = 3; i <= P; ++i) v = fma((T)i * c[i], h[i - 2], v);
+    return v;
+}
+
 template <int P, typename T>
 __device__ __forceinline__ T pmean(const T *w, const T (&h)[P]) {
     T v = w[0];

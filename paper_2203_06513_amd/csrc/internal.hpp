@@ -71,6 +71,7 @@ struct Particles {
     double *xi;
     double *p;
     int32_t *id;
+    double *sx, *sy, *sz;   // spins (null without spin); Subsystem I carries them with the sort
 };
 
 // ---- learned warm start ----------------------------------------------------
@@ -119,6 +120,9 @@ struct SweepIArgs {
     // predictor pass of the learned warm start
     WsNet ws;
     const float *ws_table;         // [M][WS_NT * WS_NP] network outputs of this substep
+    // spin force (sweeps compiled with it): s_y, s_z and hbar / dx^2
+    const double *sy, *sz;
+    double hbar_dx2;
 };
 
 struct FieldIArgs {
@@ -160,6 +164,7 @@ struct CommitIArgs {
     int32_t *nstart;               // [2M + 1]: new start of each cell, N, new count of each cell
     DevStatus *st;
     double dt, dt_dx, inv_dx, dx, tol;
+    double hbar_dx2;               // spin force (commits compiled with it; cur/nxt carry the spins)
     double dx_dt;                  // 1 / dt_dx
     int32_t M, chunk, seidel, wpi;
     int32_t nsweeps;               // sweeps enqueued so far (the last one may still need its test)
@@ -171,6 +176,18 @@ struct CommitIArgs {
     WsRecord rec;                  // training pairs to record (rec.stride 0: none)
     double *dprev_out;             // non-null: the committed increment, in the new order
     int64_t N;
+};
+
+// ---- spin (Subsystem III, the Subsystem II source, the Zeeman energy) -------
+struct SpinArgs {
+    const double *xi;
+    double *sx, *sy, *sz;
+    ItemList items;
+    const double *ay, *az;   // padded a_perp (current)
+    double inv_dx;
+    double h;                // rotation time (Subsystem III)
+    double *spart;           // [items][2 deg] V1 sums of (s_y, s_z) per item (deposit pass)
+    double *epart;           // [items] Zeeman sum per item (energy pass)
 };
 
 // ---- Subsystem II --------------------------------------------------------

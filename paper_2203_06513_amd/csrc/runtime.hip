@@ -78,6 +78,16 @@ void launch_deposit_segments(int P, hipStream_t s, const double *x0, const doubl
                              double dx, double w, int M, double *J, int *flags);
 void launch_copy(hipStream_t s, const double *in, double *out, int64_t n);
 int noalloc_init(int dev);
+void launch_spin_rotate(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
+void launch_spin_deposit(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
+void launch_spin_source(int P, hipStream_t s, const double *spart, const ItemList &items, int M, double coef,
+                        double *by, double *bz);
+void launch_conv_add(hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo, int M);
+void launch_spin_energy(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
+void launch_spin_in(hipStream_t s, const double *ix, const double *iy, const double *iz, const int32_t *id,
+                    int64_t n, double *sx, double *sy, double *sz);
+void launch_spin_out(hipStream_t s, const double *sx, const double *sy, const double *sz, const int32_t *id,
+                     int64_t n, double *ox, double *oy, double *oz);
 double *noalloc_scratch(int dev);
 int noalloc_max_cells();
 void launch_deposit_noalloc(int P, hipStream_t s, const double *x0, const double *x1, int64_t n, double inv_dx,
@@ -272,6 +282,13 @@ struct ecpic_ctx {
     // from the explicit start, Seidel map)
     bool adjoint = false;
     int kI = 0, kII = 0;   // sweeps / iterations enqueued in the current substeps
+    // spin: the particles carry spins (both buffers), hbar couples them
+    bool spin = false;
+    double hbar = 0.0;
+    double *spart = nullptr;        // [max_items][2 deg] spin deposit per item (Subsystem II source)
+    double *sby = nullptr, *sbz = nullptr;   // [M] the source's load vectors
+    double *epart = nullptr;        // [max_items] Zeeman sum per item
+    std::vector<double> h_epart;
     Prof prof;
 };
 
@@ -361,6 +378,11 @@ SweepIArgs sweep_args(ecpic_ctx *c) {
     a.dx = c->dx;
     a.tol = c->tol;
     a.explicit_start = 1;
+    if (c->spin && c->hbar != 0.0) {   // the spin force (hbar = 0: the plain sweeps, spins untouched)
+        a.sy = c->pb[c->cur].sy;
+        a.sz = c->pb[c->cur].sz;
+        a.hbar_dx2 = c->hbar / (c->dx * c->dx);
+    }
     return a;
 }
 
@@ -459,6 +481,7 @@ void enqueue_commit_I(ecpic_ctx *c) {
     a.tol = c->tol;
     a.M = c->M;
     a.chunk = c->chunk;
+    a.hbar_dx2 = c->hbar / (c->dx * c->dx);   // cur / nxt carry the spins when there are any
     a.seidel = c->seidel || c->adjoint;
     a.wpi = c->block / 64;
     a.nsweeps = c->kI;
@@ -657,6 +680,47 @@ struct DtScope {
     }
 };
 
+// ---- spin ------------------------------------------------------------------
+SpinArgs spin_args(ecpic_ctx *c) {
+    SpinArgs a{};
+    const Particles &d = c->pb[c->cur];
+    a.xi = d.xi;
+    a.sx = d.sx;
+    a.sy = d.sy;
+    a.sz = d.sz;
+    a.items = c->items[c->icur];
+    a.ay = c->ay[c->trc];
+    a.az = c->az[c->trc];
+    a.inv_dx = c->inv_dx;
+    a.spart = c->spart;
+    a.epart = c->epart;
+    return a;
+}
+
+// The spin source of Subsystem II over the current dt, added to the constant
+// part E0 of its iteration (after the start kernel formed E0): the deposit of
+// (s_y, s_z) on V1, -/+ hbar G^T of it, times dt, through (M0 + dt^2 K/4)^{-1}.
+void enqueue_spin_source(ecpic_ctx *c) {
+    if (!c->spin || c->hbar == 0.0 || c->N == 0) return;
+    const SpinArgs a = spin_args(c);
+    timed(c, "spin_deposit", [&] { launch_spin_deposit(c->P, std::max(1, c->n_items_host), c->stream, a, c->M); });
+    const double coef = c->hbar * c->dt * c->w / (c->dx * c->dx);   // G^T's 1/dx, the taps' 1/dx
+    timed(c, "spin_source", [&] {
+        launch_spin_source(c->P, c->stream, c->spart, c->items[c->icur], c->M, coef, c->sby, c->sbz);
+        launch_conv_add(c->stream, c->sby, c->E0y, c->tapsA, c->ntA, c->mloA, c->M);
+        launch_conv_add(c->stream, c->sbz, c->E0z, c->tapsA, c->ntA, c->mloA, c->M);
+    });
+}
+
+// Subsystem III over h (any sign): one pass over the current order.
+int substep_spin(ecpic_ctx *c, double h) {
+    if (c->N == 0) return ECPIC_OK;
+    SpinArgs a = spin_args(c);
+    a.h = h;
+    timed(c, "spin_rotate", [&] { launch_spin_rotate(c->P, std::max(1, c->n_items_host), c->stream, a, c->M); });
+    return sync(c);
+}
+
 // One Subsystem I substep over dt on its own (the scheme, or its adjoint):
 // start, the expected number of sweeps, commit, one status read, more sweeps if
 // needed.  Nothing is committed on failure.
@@ -739,12 +803,14 @@ void free_all(ecpic_ctx *c) {
     auto F = [](void *p) { if (p) hipFree(p); };
     for (int b = 0; b < 2; ++b) {
         F(c->pb[b].xi); F(c->pb[b].p); F(c->pb[b].id); F(c->dbuf[b]); F(c->fbuf[b]);
+        F(c->pb[b].sx); F(c->pb[b].sy); F(c->pb[b].sz);
         F(c->items[b].cell); F(c->items[b].begin); F(c->items[b].cell_first); F(c->items[b].n_items);
         F(c->ex[b]); F(c->ey[b]); F(c->ez[b]); F(c->ay[b]); F(c->az[b]);
         F(c->ek[b]); F(c->eyk[b]); F(c->ezk[b]);
     }
     F(c->wcnt); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->dprev);
+    F(c->spart); F(c->sby); F(c->sbz); F(c->epart);
     for (auto &t : c->tapsA_by_dt) F(t.second.dev);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
@@ -790,6 +856,7 @@ int alloc_all(ecpic_ctx *c) {
     int rc = 0;
     for (int b = 0; b < 2; ++b) {
         rc |= dalloc(&c->pb[b].xi, N); rc |= dalloc(&c->pb[b].p, N); rc |= dalloc(&c->pb[b].id, N);
+        if (c->spin) { rc |= dalloc(&c->pb[b].sx, N); rc |= dalloc(&c->pb[b].sy, N); rc |= dalloc(&c->pb[b].sz, N); }
         rc |= dalloc(&c->dbuf[b], N);
         if (c->k32 > 0) rc |= dalloc(&c->fbuf[b], N);
         rc |= dalloc(&c->items[b].cell, c->max_items); rc |= dalloc(&c->items[b].begin, c->max_items + 1);
@@ -820,7 +887,12 @@ int alloc_all(ecpic_ctx *c) {
     rc |= dalloc(&c->rho, M); rc |= dalloc(&c->rvec, M); rc |= dalloc(&c->uvec, M);
     rc |= dalloc(&c->out5, 8); rc |= dalloc(&c->part_e, c->max_items); rc |= dalloc(&c->maxbits, 1);
     rc |= dalloc(&c->count, M);
-    if (c->symmetric) rc |= dalloc(&c->ex_save, MP);
+    if (c->symmetric || c->spin) rc |= dalloc(&c->ex_save, MP);
+    if (c->spin) {
+        rc |= dalloc(&c->spart, (size_t)c->max_items * 2 * c->P);
+        rc |= dalloc(&c->sby, M); rc |= dalloc(&c->sbz, M);
+        rc |= dalloc(&c->epart, c->max_items);
+    }
     if (rc) return ECPIC_ENOMEM;
     if (hipHostMalloc((void **)&c->h_ring, sizeof(*c->h_ring) * STEP_BATCH, hipHostMallocMapped) != hipSuccess)
         return ECPIC_ENOMEM;
@@ -900,6 +972,12 @@ int load_particles_dev(ecpic_ctx *c, const double *x, const double *p) {
     }
     for (void *q : {(void *)k0, (void *)v0, (void *)k1, (void *)v1, (void *)hist, (void *)xt, (void *)pt})
         if (q) hipFree(q);
+    if (rc == ECPIC_OK && c->spin && N > 0) {   // a new state: spins zero until set_spins
+        const Particles &d = c->pb[c->cur];
+        for (double *q : {d.sx, d.sy, d.sz})
+            if (hipMemsetAsync(q, 0, sizeof(double) * N, c->stream) != hipSuccess) rc = ECPIC_EDEVICE;
+        if (rc == ECPIC_OK) rc = sync(c);
+    }
     if (rc == ECPIC_OK) c->have_particles = true;
     c->have_prev = false;   // a new order: no previous increments
     return rc;
@@ -922,7 +1000,9 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
         g.weight < 0.0 || g.waves_per_item < 0 || g.waves_per_item > MAX_WAVES_PER_ITEM ||
         (g.splitting != ECPIC_LIE_TROTTER && g.splitting != ECPIC_SYMMETRIC) ||
         (g.item_particles != 0 && (g.item_particles < MIN_CHUNK || g.item_particles > MAX_CHUNK ||
-                                   (g.item_particles & (g.item_particles - 1)) != 0)))
+                                   (g.item_particles & (g.item_particles - 1)) != 0)) ||
+        (g.spin != 0 && g.spin != 1) || !std::isfinite(g.hbar) || (!g.spin && g.hbar != 0.0) ||
+        (g.spin && (g.precision != ECPIC_FP64 || g.warmstart == ECPIC_WS_MLP)))
         return ECPIC_EINVAL;
     int rc = check_device(g.device);
     if (rc) return rc;
@@ -948,6 +1028,8 @@ int ecpic_create(const ecpic_config *cfg, ecpic_ctx **out) {
     c->guessI = c->guessII = g.sweep_guess > 0 ? g.sweep_guess : 4;
     c->ws_prev = g.warmstart == ECPIC_WS_PREVIOUS;
     c->symmetric = g.splitting == ECPIC_SYMMETRIC;
+    c->spin = g.spin != 0;
+    c->hbar = g.hbar;
     const double ppc = g.M > 0 ? (double)g.n_particles / g.M : 0.0;
     // One work item per cell where the cells allow (the item list is then the
     // cell index, and the commit needs no list-building pass): items hold up to
@@ -1041,6 +1123,50 @@ int ecpic_get_particles(ecpic_ctx *c, double *x, double *p, int64_t n) {
     return rc;
 }
 
+int ecpic_set_spins(ecpic_ctx *c, const double *sx, const double *sy, const double *sz, int64_t n) {
+    if (!c || !c->spin || n != c->N || (n > 0 && (!sx || !sy || !sz))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    if (n == 0) return ECPIC_OK;
+    double *t[3] = {nullptr, nullptr, nullptr};
+    if (dalloc(&t[0], n) || dalloc(&t[1], n) || dalloc(&t[2], n)) {
+        for (double *q : t) if (q) hipFree(q);
+        return ECPIC_ENOMEM;
+    }
+    int rc = ECPIC_OK;
+    const double *in[3] = {sx, sy, sz};
+    for (int k = 0; k < 3 && rc == ECPIC_OK; ++k)
+        if (hipMemcpyAsync(t[k], in[k], sizeof(double) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            rc = ECPIC_EDEVICE;
+    const Particles &d = c->pb[c->cur];
+    if (rc == ECPIC_OK) launch_spin_in(c->stream, t[0], t[1], t[2], d.id, n, d.sx, d.sy, d.sz);
+    if (rc == ECPIC_OK) rc = sync(c);
+    for (double *q : t) hipFree(q);
+    return rc;
+}
+
+int ecpic_get_spins(ecpic_ctx *c, double *sx, double *sy, double *sz, int64_t n) {
+    if (!c || !c->spin || n != c->N || (n > 0 && (!sx || !sy || !sz))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    if (n == 0) return ECPIC_OK;
+    double *t[3] = {nullptr, nullptr, nullptr};
+    if (dalloc(&t[0], n) || dalloc(&t[1], n) || dalloc(&t[2], n)) {
+        for (double *q : t) if (q) hipFree(q);
+        return ECPIC_ENOMEM;
+    }
+    const Particles &d = c->pb[c->cur];
+    launch_spin_out(c->stream, d.sx, d.sy, d.sz, d.id, n, t[0], t[1], t[2]);
+    int rc = ECPIC_OK;
+    double *out[3] = {sx, sy, sz};
+    for (int k = 0; k < 3 && rc == ECPIC_OK; ++k)
+        if (hipMemcpyAsync(out[k], t[k], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            rc = ECPIC_EDEVICE;
+    if (rc == ECPIC_OK) rc = sync(c);
+    for (double *q : t) hipFree(q);
+    return rc;
+}
+
 int ecpic_set_fields(ecpic_ctx *c, const double *ex, const double *ey, const double *ez, const double *ay,
                      const double *az) {
     if (!c) return ECPIC_EINVAL;
@@ -1115,8 +1241,21 @@ int ecpic_energy(ecpic_ctx *c, ecpic_energy_parts *out) {
                         c->krow.data(), c->P, c->M, c->dx, c->out5);
     double h5[5];
     HIPCHK(hipMemcpyAsync(h5, c->out5, sizeof(h5), hipMemcpyDeviceToHost, c->stream));
+    double zee = 0.0;
+    const int ni = c->n_items_host;
+    if (c->spin && c->hbar != 0.0 && c->N > 0 && ni > 0) {   // per-item sums, added here in item order
+        launch_spin_energy(c->P, ni, c->stream, spin_args(c), c->M);
+        c->h_epart.resize(ni);
+        HIPCHK(hipMemcpyAsync(c->h_epart.data(), c->epart, sizeof(double) * ni, hipMemcpyDeviceToHost, c->stream));
+    }
     int rc = sync(c);
-    out->kinetic = h5[0]; out->e_long = h5[1]; out->e_trans = h5[2]; out->b_trans = h5[3]; out->total = h5[4];
+    if (c->spin && c->hbar != 0.0 && c->N > 0 && ni > 0) {
+        for (int i = 0; i < ni; ++i) zee += c->h_epart[i];
+        zee *= c->hbar * c->w;
+    }
+    out->kinetic = h5[0]; out->e_long = h5[1]; out->e_trans = h5[2]; out->b_trans = h5[3];
+    out->total = h5[4] + zee;
+    out->zeeman = zee;
     return rc;
 }
 
@@ -1172,6 +1311,13 @@ int ecpic_substep_particles_adjoint(ecpic_ctx *c, double dt, ecpic_iter_stats *s
     return substep_I(c, dt, stats, true);
 }
 
+int ecpic_substep_spin(ecpic_ctx *c, double dt) {
+    if (!c || !c->spin || !std::isfinite(dt)) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    return substep_spin(c, dt);
+}
+
 int ecpic_substep_fields(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
     if (!c || !(dt > 0.0) || !(dt < c->dx)) return ECPIC_EINVAL;
     if (!c->have_particles) return ECPIC_ESTATE;
@@ -1181,6 +1327,7 @@ int ecpic_substep_fields(ecpic_ctx *c, double dt, ecpic_iter_stats *stats) {
     if (rc0) return rc0;
     c->dt = dt;
     enqueue_begin(c, false, true);
+    enqueue_spin_source(c);
     IIView v{c->pb[c->cur].xi, c->pb[c->cur].p, c->items[c->icur], true, false, {}};
     enqueue_iters_II(c, v, std::min(c->guessII, c->kmax));
     enqueue_commit_II(c);
@@ -1247,23 +1394,29 @@ void step_stats(const ecpic_ctx *c, ecpic_iter_stats *sI, ecpic_iter_stats *sII)
     }
 }
 
-// Steps of the symmetric composition, Subsystem I over dt/2, II over dt, the
-// adjoint Subsystem I over dt/2, each substep run on its own.  A failed step
-// is rolled back: a substep commits nothing on failure, and the buffers the
-// committed substeps of the step left behind still hold the step's start,
-// except e_x and the item list, which the closing substep's field kernels
-// overwrite while iterating (they are the spare buffers of that substep): e_x
-// is saved before it and the list rebuilt from the particles on failure.
-int step_symmetric(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII,
+// Steps run substep by substep: the symmetric composition (Subsystem I over
+// dt/2, II over dt, the adjoint Subsystem I over dt/2) and steps with spin
+// (Lie-Trotter I, II, III; symmetric I(dt/2), III(dt/2), II(dt), III(dt/2),
+// adjoint I(dt/2)).  A failed step is rolled back: a substep commits nothing on
+// failure, and the buffers the committed substeps of the step left behind still
+// hold the step's start (Subsystem III turns the spins of the order Subsystem I
+// has just written, never those of the step's start), except e_x and the item
+// list, which the closing adjoint substep's field kernels overwrite while
+// iterating (they are the spare buffers of that substep): e_x is saved before
+// it and the list rebuilt from the particles on failure.
+int step_unbatched(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_stats *sII,
                    int32_t *steps_done) {
-    const double dt = c->dt, h = 0.5 * c->dt;
+    const bool sym = c->symmetric, spin = c->spin;
+    const double dt = c->dt, h = sym ? 0.5 * c->dt : c->dt;
     for (int n = 0; n < nsteps; ++n) {
         const StepSnap q = snap(c);
         ecpic_iter_stats a{}, b{}, d{};
         int rc = substep_I(c, h, &a, false);
-        bool closing = false;
+        if (!rc && sym && spin) rc = substep_spin(c, h);
         if (!rc) rc = ecpic_substep_fields(c, dt, &b);
-        if (!rc) {
+        if (!rc && spin) rc = substep_spin(c, h);
+        bool closing = false;
+        if (!rc && sym) {
             HIPCHK(hipMemcpyAsync(c->ex_save, c->ex[q.exc], sizeof(double) * (c->M + 2 * HALO),
                                   hipMemcpyDeviceToDevice, c->stream));
             closing = true;
@@ -1323,7 +1476,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
     if (!c->have_particles) return ECPIC_ESTATE;
     hipSetDevice(c->device);
     if (steps_done) *steps_done = 0;
-    if (c->symmetric) return step_symmetric(c, nsteps, sI, sII, steps_done);
+    if (c->symmetric || c->spin) return step_unbatched(c, nsteps, sI, sII, steps_done);
     struct FuseII {   // every commit of a step feeds the step's first Subsystem II iterate
         ecpic_ctx *c;
         explicit FuseII(ecpic_ctx *x) : c(x) { c->fuse_II = true; }
@@ -1422,6 +1575,7 @@ int ecpic_step(ecpic_ctx *c, int32_t nsteps, ecpic_iter_stats *sI, ecpic_iter_st
 // ---- learned warm start ------------------------------------------------------
 int ecpic_ws_record(ecpic_ctx *c, int32_t stride, int64_t capacity) {
     if (!c || stride < 0 || (stride > 0 && capacity <= 0)) return ECPIC_EINVAL;
+    if (stride > 0 && c->spin) return ECPIC_EINVAL;   // the learned start runs without spin
     hipSetDevice(c->device);
     if (sync(c)) return ECPIC_EDEVICE;
     if (stride == 0) { c->ws_stride = 0; return ECPIC_OK; }

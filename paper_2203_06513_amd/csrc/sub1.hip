@@ -43,6 +43,7 @@ struct LdsRec {   // one cell's coefficients in LDS
 template <typename T>
 struct Lane {
     T t0, p0, d, t1, q0, A0y, A0z, g00;
+    T sy, sz;   // the particle's spin (spin force only)
     int s;
     // adjoint scheme: |A0|^2, the momentum iterate P = p^{n+1} the increment
     // stands for, and gamma(x^n, P)
@@ -109,16 +110,25 @@ struct PushEnd {
 // gamma(x0, p1))).  MOM: p1 is wanted (the commit); a sweep needs only the
 // increment, which it then forms with one reciprocal instead of two (p1 and
 // the flags' finiteness test take N = p1 (g00 + g01) in its place).
-template <int P, typename T, bool ADJ = false, bool MOM = true>
+// SPIN: the force of the Zeeman energy, hbar (s_z DD_y - s_y DD_z) with DD the
+// divided difference of dA/dx along the step (per cell, (A'(t1) - A'(t0))/(t1 -
+// t0) / dx^2 with A' = dA/dt, from the same h_i); hbar_dx2 = hbar / dx^2.  It
+// does not depend on p, so the adjoint takes it unchanged.
+template <int P, typename T, bool ADJ = false, bool MOM = true, bool SPIN = false>
 __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
                                            const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags,
-                                           PushEnd<T> *pe = nullptr) {
+                                           PushEnd<T> *pe = nullptr, T hbar_dx2 = (T)0) {
     const T zero = (T)0, one = (T)1;
     const T t1c = fmin(fmax(L.t1, zero), one);
     T h[P];
     homog<P - 1>(fmin(L.t0, t1c), fmax(L.t0, t1c), h);
     T LE = pmean<P>(o.eb, h);
     T DAy = divdiff<P>(o.ay, h), DAz = divdiff<P>(o.az, h);
+    T DDy = (T)0, DDz = (T)0;
+    if constexpr (SPIN) {
+        DDy = divdiff2<P>(o.ay, h);
+        DDz = divdiff2<P>(o.az, h);
+    }
     T A1y, A1z;
     if (anycross) {
         // record of the cell holding t1 (s = floor(t1) in {-1, 0, 1})
@@ -135,6 +145,10 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
             LE = (sA * LE + sB * pmean<P>(nb.eb, hb)) * inv;
             DAy = (sA * DAy + sB * divdiff<P>(nb.ay, hb)) * inv;
             DAz = (sA * DAz + sB * divdiff<P>(nb.az, hb)) * inv;
+            if constexpr (SPIN) {   // dA/dx is continuous at the knot (degree >= 2)
+                DDy = (sA * DDy + sB * divdiff2<P>(nb.ay, hb)) * inv;
+                DDz = (sA * DDz + sB * divdiff2<P>(nb.az, hb)) * inv;
+            }
         }
     } else {
         // A at the end point from the divided difference: A1 = A0 + (t1 - t0) DA
@@ -144,6 +158,7 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
         A1y = fma(dt1, DAy, L.A0y);
         A1z = fma(dt1, DAz, L.A0z);
     }
+    if constexpr (SPIN) LE = fma(hbar_dx2, fma(L.sz, DDy, -L.sy * DDz), LE);
     const T qa1 = A1y * A1y + A1z * A1z;
     T g11;
     if constexpr (ADJ) {
@@ -276,9 +291,10 @@ __device__ __forceinline__ QueueW queue_of_wave(double *base, int wid) {
     return QueueW{w, w + QCAP, w + 2 * QCAP, reinterpret_cast<int *>(w + 3 * QCAP)};
 }
 
-template <int P, bool SEIDEL, typename T, int START, bool ADJ>
+template <int P, bool SEIDEL, typename T, int START, bool ADJ, bool SPIN>
 __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsRec<P, T> *rec, double *queue) {
     static_assert(!ADJ || SEIDEL, "the adjoint scheme deposits the increment it has just produced");
+    static_assert(!SPIN || (sizeof(T) == 8 && START != START_FLOAT), "spin runs the plain FP64 sweeps");
     constexpr bool F64 = sizeof(T) == 8;
     using MO = typename std::conditional<F64, Moments<P>, Moments32<P>>::type;
     DevStatus *st = a.st;
@@ -322,6 +338,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     double nx = 0.0, np = 0.0;
     T nd = (T)0;
     float nf = 0.0f;   // the float increment (from_float; converted at use)
+    double nsy = 0.0, nsz = 0.0;   // spin (SPIN)
     if (wb < we) {
         const int il = min(ia, we - 1);
         nx = a.xi[il];
@@ -329,6 +346,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
         if constexpr (from_float) nf = d32in[il];
         else if constexpr (from_prev) nd = (T)dprev[il];
         else if constexpr (!explicit_start) nd = din[il];
+        if constexpr (SPIN) { nsy = a.sy[il]; nsz = a.sz[il]; }
     }
     stage_records<P, T>(rec, a.coefA, coefE, c);
     __syncthreads();
@@ -339,6 +357,7 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
     __builtin_amdgcn_s_waitcnt(0);
     MO mo{};
     const T dt = (T)a.dt, dt_dx = (T)a.dt_dx, inv_dx = (T)a.inv_dx, dx_dt = (T)a.dx_dt;
+    const T hbar_dx2 = (T)a.hbar_dx2;
     T rmax = (T)0;
     int flags = 0;
     int nleft = 0, nstay = 0, nright = 0;
@@ -364,10 +383,11 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
         const double xq = q.x[qs];
         Lq.p0 = (T)q.p[qs];
         if constexpr (!explicit_start) Lq.d = (T)q.d[qs];
+        if constexpr (SPIN) { Lq.sy = a.sy[qi]; Lq.sz = a.sz[qi]; }
         stage_gather<P, T, explicit_start, ADJ>(o1, Lq, xq, c, dt_dx, flags, dx_dt);
         const bool cr = __ballot(Lq.s != 0) != 0;
         T pq, dq;
-        stage_push<P, T, ADJ, false>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags);
+        stage_push<P, T, ADJ, false, SPIN>(o1, rec, cr, Lq, dt, dt_dx, inv_dx, pq, dq, flags, nullptr, hbar_dx2);
         flags |= FLAG_QUEUED;
         if (qv) {
             if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[qi] = Lq.d;
@@ -401,6 +421,8 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             const double xi0 = nx;
             La.p0 = (T)np;
             La.d = from_float ? (T)nf : nd;
+            La.sy = (T)nsy;
+            La.sz = (T)nsz;
             const bool valid = ia < we;
             if (pend_i >= 0) dout[pend_i] = pend;
             {   // prefetch the next row (unconditionally: the last row reloads its last particle)
@@ -410,12 +432,14 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 if constexpr (from_float) nf = d32in[il];
                 else if constexpr (from_prev) nd = (T)dprev[il];
                 else if constexpr (!explicit_start) nd = din[il];
+                if constexpr (SPIN) { nsy = a.sy[il]; nsz = a.sz[il]; }
             }
             stage_gather<P, T, explicit_start, ADJ>(o1, La, xi0, c, dt_dx, flags, dx_dt);
             // own-cell terms for every lane; a crossing lane's result is discarded
             // (it stays finite: its end point is clamped into (-1, 2) and |d| < dt/dx < 1)
             T pa, dna;
-            stage_push<P, T, ADJ, false>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ, false, SPIN>(o1, rec, false, La, dt, dt_dx, inv_dx, pa, dna, flags, nullptr,
+                                               hbar_dx2);
             bool cross = La.s != 0;
             T ta = La.t1;
             if constexpr (SEIDEL) {
@@ -467,6 +491,8 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
             const double xi0 = nx;
             La.p0 = (T)np;
             La.d = from_float ? (T)nf : nd;
+            La.sy = (T)nsy;
+            La.sz = (T)nsz;
             const bool valid = ia < we;
             const uint64_t vmask = __builtin_amdgcn_ballot_w64(valid);
             if (pend_i >= 0) dout[pend_i] = pend;
@@ -477,11 +503,13 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
                 if constexpr (from_float) nf = d32in[il];
                 else if constexpr (from_prev) nd = (T)dprev[il];
                 else if constexpr (!explicit_start) nd = din[il];
+                if constexpr (SPIN) { nsy = a.sy[il]; nsz = a.sz[il]; }
             }
             stage_gather<P, T, explicit_start, ADJ>(o1, La, xi0, c, dt_dx, flags, dx_dt);
             const bool cross1 = __ballot(La.s != 0) != 0;
             T pa, dna;
-            stage_push<P, T, ADJ, false>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags);
+            stage_push<P, T, ADJ, false, SPIN>(o1, rec, cross1, La, dt, dt_dx, inv_dx, pa, dna, flags, nullptr,
+                                               hbar_dx2);
             if (valid) {
                 if constexpr (keep_start) ((k & 1) ? a.d1 : a.d0)[ia] = La.d;
                 rmax = fmax(rmax, fabs(dna - La.d));
@@ -528,11 +556,11 @@ __device__ __forceinline__ void sweep_I_item(const SweepIArgs &a, int item, LdsR
 // One kernel per start mode (the host knows it), so that each is allocated the
 // registers it needs rather than the most any mode needs.  ADJ: the adjoint
 // scheme (FP64, Seidel map, explicit start or read).
-template <int P, bool SEIDEL, typename T, int START, bool ADJ>
+template <int P, bool SEIDEL, typename T, int START, bool ADJ, bool SPIN = false>
 __global__ void __launch_bounds__(MAX_BLOCK) k_sweep_I(SweepIArgs a) {
     __shared__ LdsRec<P, T> rec[3];   // cells c-1, c, c+1
     extern __shared__ double queue[];   // the waves' queues (degree >= 4)
-    sweep_I_item<P, SEIDEL, T, START, ADJ>(a, blockIdx.x, rec, queue);
+    sweep_I_item<P, SEIDEL, T, START, ADJ, SPIN>(a, blockIdx.x, rec, queue);
 }
 
 // Sum of the wave partials of cell c (its items times wpi waves each): the P+2
@@ -1007,9 +1035,10 @@ __device__ __forceinline__ double wave_totals_lds(double *col, int stride, int l
 // sweep's delta^(kc+1); the momentum is the P that increment stands for (the
 // closed form of adjoint_momentum), so no push is evaluated again.  It forms no
 // Subsystem II deposit (the adjoint substep closes a step) and records nothing.
-template <int P, bool RECORD, bool ADJ>
+template <int P, bool RECORD, bool ADJ, bool SPIN>
 __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int item) {
     static_assert(!(ADJ && RECORD), "pairs are recorded from the scheme's own commit");
+    static_assert(!(SPIN && RECORD), "the learned warm start runs without spin");
     constexpr int NA = RecA<P>::N;
     __shared__ LdsRec<P, double> rec[3];   // cells c-1, c, c+1
     __shared__ double rk[3][NA];           // a^(0) records of cells c-1, c, c+1 (part2)
@@ -1072,6 +1101,7 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         for (int u = 0; u < NM; ++u) col[u * WAVE + lane] = 0.0;
     // the next row's loads are issued before the current row is computed
     double nx = 0.0, np = 0.0, nd = 0.0;
+    double nsy = 0.0, nsz = 0.0;   // spin (SPIN)
     int32_t nid = 0;
     if (wb < we) {
         const int il = min(wb + lane, we - 1);
@@ -1079,12 +1109,14 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
         np = a.cur.p[il];
         nd = pk.d[il];
         nid = a.cur.id[il];
+        if constexpr (SPIN) { nsy = a.cur.sy[il]; nsz = a.cur.sz[il]; }
     }
     __builtin_amdgcn_s_waitcnt(0);
     for (int r0 = wb; r0 < we; r0 += WAVE) {
         const int i = r0 + lane;
         const bool valid = i < we;
         const double xi0 = nx, p0 = np, d = nd;
+        const double sy0 = nsy, sz0 = nsz;
         const int32_t pid = nid;
         {
             const int il = min(i + WAVE, we - 1);
@@ -1092,12 +1124,15 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             np = a.cur.p[il];
             nd = pk.d[il];
             nid = a.cur.id[il];
+            if constexpr (SPIN) { nsy = a.cur.sy[il]; nsz = a.cur.sz[il]; }
         }
         // the committed momentum: the map evaluated at the committed increment
         // (adjoint: the momentum that increment stands for)
         Lane<double> La;
         La.p0 = p0;
         La.d = d;
+        La.sy = sy0;
+        La.sz = sz0;
         double p1, dn;
         PushEnd<double> pe{0.0, 0.0, 0.0};
         stage_gather<P, double, false, ADJ>(o1, La, xi0, c, a.dt_dx, flags, a.dx_dt);
@@ -1106,7 +1141,8 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             p1 = La.P;
             wave_flag(flags, !(fabs(p1) < 1.0e300), FLAG_NONFINITE);
         } else {
-            stage_push<P, double>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags, &pe);
+            stage_push<P, double, false, true, SPIN>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags,
+                                                     &pe, a.hbar_dx2);
         }
         const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
         double xin = xi0 + d;
@@ -1176,6 +1212,11 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             a.nxt.p[dest] = p1;
             a.nxt.id[dest] = pid;
             if (a.dprev_out) a.dprev_out[dest] = d;
+            if constexpr (SPIN) {   // Subsystem I leaves the spins as they are
+                a.nxt.sx[dest] = a.cur.sx[i];
+                a.nxt.sy[dest] = sy0;
+                a.nxt.sz[dest] = sz0;
+            }
         }
         run0 += __popcll(b0);
         run1 += __popcll(b1);
@@ -1230,38 +1271,49 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
 // step enqueued ahead is only known on the device) and the extra blocks exit.
 // RECORD: the step also writes training pairs of the learned warm start (a
 // kernel of its own, so the plain one keeps its registers).
-template <int P, bool RECORD, bool ADJ>
+template <int P, bool RECORD, bool ADJ, bool SPIN = false>
 __global__ void __launch_bounds__(MAX_BLOCK) k_commit_scatter(CommitIArgs a) {
-    commit_scatter_item<P, RECORD, ADJ>(a, blockIdx.x);
+    commit_scatter_item<P, RECORD, ADJ, SPIN>(a, blockIdx.x);
 }
 
 
 // ---- launchers ------------------------------------------------------------
-template <int P, bool SEIDEL, typename T, bool ADJ>
+template <int P, bool SEIDEL, typename T, bool ADJ, bool SPIN>
 void launch_sweep_mode(const SweepIArgs &a, int grid, int block, size_t lds, hipStream_t s) {
     if (a.k == 0 && a.explicit_start)
-        launch_k((k_sweep_I<P, SEIDEL, T, START_EXPLICIT, ADJ>), dim3(grid), dim3(block), lds, s, a);
+        launch_k((k_sweep_I<P, SEIDEL, T, START_EXPLICIT, ADJ, SPIN>), dim3(grid), dim3(block), lds, s, a);
     else if (!ADJ && a.k == 0 && a.dprev)
-        launch_k((k_sweep_I<P, SEIDEL, T, START_PREV, ADJ>), dim3(grid), dim3(block), lds, s, a);
-    else if (!ADJ && sizeof(T) == 8 && a.d32in)
-        launch_k((k_sweep_I<P, SEIDEL, T, START_FLOAT, ADJ>), dim3(grid), dim3(block), lds, s, a);
-    else
-        launch_k((k_sweep_I<P, SEIDEL, T, START_READ, ADJ>), dim3(grid), dim3(block), lds, s, a);
+        launch_k((k_sweep_I<P, SEIDEL, T, START_PREV, ADJ, SPIN>), dim3(grid), dim3(block), lds, s, a);
+    else if constexpr (!SPIN && !ADJ && sizeof(T) == 8) {
+        if (a.d32in)
+            launch_k((k_sweep_I<P, SEIDEL, T, START_FLOAT, ADJ>), dim3(grid), dim3(block), lds, s, a);
+        else
+            launch_k((k_sweep_I<P, SEIDEL, T, START_READ, ADJ>), dim3(grid), dim3(block), lds, s, a);
+    } else
+        launch_k((k_sweep_I<P, SEIDEL, T, START_READ, ADJ, SPIN>), dim3(grid), dim3(block), lds, s, a);
 }
 
+// spin (a.sy non-null) runs the FP64 sweeps only; the host refuses the
+// precision form and the learned start with spin
 void launch_sweep_I(int P, bool seidel, bool fp32, bool adj, int grid, int block, hipStream_t s,
                     const SweepIArgs &a) {
     const size_t lds = P >= 4 ? queue_lds_bytes(block) : 0;   // the queue is used from degree 4 on
-#define ECPIC_SW(PP)                                                                             \
-    case PP:                                                                                     \
-        if (adj) launch_sweep_mode<PP, true, double, true>(a, grid, block, lds, s);              \
-        else if (fp32) {                                                                         \
-            if (seidel) launch_sweep_mode<PP, true, float, false>(a, grid, block, lds, s);       \
-            else launch_sweep_mode<PP, false, float, false>(a, grid, block, lds, s);             \
-        } else {                                                                                 \
-            if (seidel) launch_sweep_mode<PP, true, double, false>(a, grid, block, lds, s);      \
-            else launch_sweep_mode<PP, false, double, false>(a, grid, block, lds, s);            \
-        }                                                                                        \
+    const bool spin = a.sy != nullptr;
+#define ECPIC_SW(PP)                                                                                  \
+    case PP:                                                                                          \
+        if (adj) {                                                                                    \
+            if (spin) launch_sweep_mode<PP, true, double, true, true>(a, grid, block, lds, s);        \
+            else launch_sweep_mode<PP, true, double, true, false>(a, grid, block, lds, s);            \
+        } else if (fp32) {                                                                            \
+            if (seidel) launch_sweep_mode<PP, true, float, false, false>(a, grid, block, lds, s);     \
+            else launch_sweep_mode<PP, false, float, false, false>(a, grid, block, lds, s);           \
+        } else if (spin) {                                                                            \
+            if (seidel) launch_sweep_mode<PP, true, double, false, true>(a, grid, block, lds, s);     \
+            else launch_sweep_mode<PP, false, double, false, true>(a, grid, block, lds, s);           \
+        } else {                                                                                      \
+            if (seidel) launch_sweep_mode<PP, true, double, false, false>(a, grid, block, lds, s);    \
+            else launch_sweep_mode<PP, false, double, false, false>(a, grid, block, lds, s);          \
+        }                                                                                             \
         break;
     switch (P) { ECPIC_SW(2) ECPIC_SW(3) ECPIC_SW(4) ECPIC_SW(5) }
 #undef ECPIC_SW
@@ -1287,10 +1339,14 @@ void launch_prep_records(int P, hipStream_t s, DevStatus *st, const double *ay, 
 
 void launch_commit_I(int P, bool adj, int grid, int block, hipStream_t s, const CommitIArgs &a) {
     const size_t lds = (a.part2 && !adj) ? sizeof(double) * 4 * (P + 1) * (size_t)block : 0;   // mover moments
+    const bool spin = a.cur.sx != nullptr;
 #define ECPIC_C(PP)                                                                                     \
     case PP:                                                                                            \
-        if (adj)                                                                                        \
-            launch_k((k_commit_scatter<PP, false, true>), dim3(grid), dim3(block), lds, s, a);          \
+        if (adj) {                                                                                      \
+            if (spin) launch_k((k_commit_scatter<PP, false, true, true>), dim3(grid), dim3(block), lds, s, a); \
+            else launch_k((k_commit_scatter<PP, false, true>), dim3(grid), dim3(block), lds, s, a);     \
+        } else if (spin)                                                                                \
+            launch_k((k_commit_scatter<PP, false, false, true>), dim3(grid), dim3(block), lds, s, a);   \
         else if (a.rec.stride > 0)                                                                      \
             launch_k((k_commit_scatter<PP, true, false>), dim3(grid), dim3(block), lds, s, a);          \
         else                                                                                            \

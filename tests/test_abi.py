@@ -35,7 +35,9 @@ def test_strerror_and_invalid_config_without_device():
     assert b"converge" in lib.ecpic_strerror(-3)
     # invalid configurations are rejected before any device is touched
     bad = [dict(degree=1), dict(degree=6), dict(M=4), dict(dt=1.0), dict(tol=0.0), dict(n_particles=-1),
-           dict(waves_per_item=5), dict(splitting=2), dict(item_particles=3000), dict(item_particles=32768)]
+           dict(waves_per_item=5), dict(splitting=2), dict(item_particles=3000), dict(item_particles=32768),
+           dict(hbar=0.1), dict(spin=True, precision=1), dict(spin=True, warmstart=2),
+           dict(spin=True, hbar=float("nan"))]
     for b in bad:
         args = dict(L=8.0, M=16, degree=3, n_particles=10, dt=0.05, tol=1e-12)
         args.update(b)
