@@ -16,6 +16,13 @@ stress16384 (1.28e8 particles, quintic).  Both forms run on each of them too
 fraction of the FP64 sweep and of the commit), and the line's `roofline`
 object is the FP64 sweep of the plain form at stress16384.
 
+Two more studies ride along: the Subsystem I starting iterates side by side
+over 200 steps ("warm_start_ab": explicit, previous increment, network then
+FP64, network then FP32 and FP64; sweeps, residuals of the first FP64 sweeps,
+ms/step, drift), and the spin model ("spin": Lie-Trotter steps I, II, III on
+spin4096, 1.6e7 particles with spins, per-kernel averages and HBM fractions of
+the particle passes).
+
 Prints ONE JSON line.  `value` is the throughput of the learned form on the
 headline workload (the whole hot path: network tables, predictor, FP32 and
 FP64 sweeps, field solves, commit, Subsystem II); the plain form's throughput
@@ -41,12 +48,18 @@ sys.path.insert(0, ROOT)
 METRIC = "converged particle-steps/s, plain FP64 vs FP32+learned warm start at equal |ΔH|/H"
 HBM_PEAK_GBS = 8000.0
 KERNELS = ("ws_table", "ws_predict", "sweep_I32", "sweep_I", "field_I", "commit_I", "sweep_II", "field_II",
-           "begin", "commit_II", "join")
+           "begin", "commit_II", "join", "spin_rotate", "spin_deposit", "spin_source")
+
 # Algorithmic bytes per particle.  A Subsystem I sweep reads xi, p and (after the
 # first sweep of a substep) delta^(k), and writes delta^(k+1): 24 B on the first
 # sweep, 32 B on the others.  The commit reads xi, p, delta and the id (28 B) and
 # writes xi, p and the id in the new order (20 B).
 COMMIT_BYTES = 48.0
+# With spin, per particle: the FP64 sweep also reads s_y, s_z (16 B); the commit moves
+# the three spin components too (24 B read, 24 B written: 96 B); Subsystem III reads xi
+# and the spin and writes the spin (56 B); the source's deposit reads xi, s_y, s_z (24 B).
+SPIN_SWEEP_EXTRA = 16.0
+SPIN_BYTES = {"commit_I": COMMIT_BYTES + 48.0, "spin_rotate": 56.0, "spin_deposit": 24.0}
 
 
 def sweep_bytes(S: float) -> float:
@@ -206,6 +219,39 @@ def warm_start_ab(ec, w, arr, steps: int, warmup: int, record_steps: int, train_
     return out
 
 
+def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
+    """Lie-Trotter steps with spin (Subsystems I, II, III, plain FP64, Seidel map) on
+    workload w: ms/step, sweeps, energy drift (the Zeeman term included), per-kernel
+    averages and the HBM fractions of the particle passes."""
+    arr = workloads_generate(w)
+    with ec.Context.from_workload(w, map=ec.MAP_SEIDEL) as ctx:
+        ctx.load(arr)
+        del arr
+        ctx.step(warmup)
+        r = timed_run(ctx, steps)
+        k = kernel_profile(ctx, profile_steps)
+        zee = ctx.last_zeeman
+    N = w.n_particles
+    S = float(np.mean(r["kI"]))
+    us = {n: round(v["us_avg"], 2) for n, v in k.items()}
+    frac = {}
+    if "sweep_I" in us:
+        frac["sweep_I"] = N * (sweep_bytes(S) + SPIN_SWEEP_EXTRA) / (us["sweep_I"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+    for name, b in SPIN_BYTES.items():
+        if name in us:
+            frac[name] = N * b / (us[name] * 1e-6) / 1e9 / HBM_PEAK_GBS
+    return {"config": describe(w) + f", hbar={w.hbar}, spins {w.spin}", "steps": steps,
+            "value": N * steps / r["elapsed"], "ms_per_step": 1e3 * r["elapsed"] / steps,
+            "mean_sweeps_I": S, "mean_iters_II": float(np.mean(r["kII"])), "rel_energy_drift": r["drift"],
+            "gauss_change_linf": r["gauss"], "zeeman_energy": zee, "kernels_us": us,
+            "hbm_frac": {n: round(v, 4) for n, v in frac.items()}}
+
+
+def workloads_generate(w):
+    import workloads
+    return workloads.generate(w)
+
+
 def summarize(w, r):
     N = w.n_particles
     S = float(np.mean(r["kI"]))
@@ -262,6 +308,8 @@ def main():
     ap.add_argument("--ab", default="stress16384,langmuir4096",
                     help="workloads of the warm-start comparison (comma separated, empty for none)")
     ap.add_argument("--ab-steps", type=int, default=200)
+    ap.add_argument("--spin", default="spin4096", help="spin workload (empty for none)")
+    ap.add_argument("--spin-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -321,6 +369,13 @@ def main():
               ", ".join(f"{k} {v['ms_per_step']:.3f} ({v['mean_sweeps_I_fp64']:.2f} FP64 sweeps)"
                         for k, v in ab[name].items()), file=sys.stderr, flush=True)
 
+    # ---- the spin model (Subsystem III and the spin terms) ----------------------
+    spin = None
+    if args.spin:
+        spin = spin_run(ec, workloads.get(args.spin), args.spin_steps, args.graded_warmup, args.graded_profile_steps)
+        print(f"bench: {args.spin} with spin {spin['ms_per_step']:.3f} ms/step, "
+              f"HBM fractions {spin['hbm_frac']}", file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel, the FP64 Subsystem I sweep of the plain form, on
     # the largest graded workload (else the headline one)
     if "stress16384" in graded:
@@ -368,6 +423,7 @@ def main():
                      "copy_probe_GBs": copy_gbs},
         "graded": graded,
         "warm_start_ab": {"steps": args.ab_steps, "workloads": ab},
+        "spin": spin,
         "kernels_plain": sp["kernels_us"],
         "kernels_learned": sl["kernels_us"],
     }

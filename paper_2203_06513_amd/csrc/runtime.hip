@@ -81,8 +81,7 @@ int noalloc_init(int dev);
 void launch_spin_rotate(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
 void launch_spin_deposit(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
 void launch_spin_source(int P, hipStream_t s, const double *spart, const ItemList &items, int M, double coef,
-                        double *by, double *bz);
-void launch_conv_add(hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo, int M);
+                        const double *taps, int ntaps, int mlo, double *E0y, double *E0z);
 void launch_spin_energy(int P, int grid, hipStream_t s, const SpinArgs &a, int M);
 void launch_spin_in(hipStream_t s, const double *ix, const double *iy, const double *iz, const int32_t *id,
                     int64_t n, double *sx, double *sy, double *sz);
@@ -286,7 +285,6 @@ struct ecpic_ctx {
     bool spin = false;
     double hbar = 0.0;
     double *spart = nullptr;        // [max_items][2 deg] spin deposit per item (Subsystem II source)
-    double *sby = nullptr, *sbz = nullptr;   // [M] the source's load vectors
     double *epart = nullptr;        // [max_items] Zeeman sum per item
     std::vector<double> h_epart;
     Prof prof;
@@ -706,9 +704,8 @@ void enqueue_spin_source(ecpic_ctx *c) {
     timed(c, "spin_deposit", [&] { launch_spin_deposit(c->P, std::max(1, c->n_items_host), c->stream, a, c->M); });
     const double coef = c->hbar * c->dt * c->w / (c->dx * c->dx);   // G^T's 1/dx, the taps' 1/dx
     timed(c, "spin_source", [&] {
-        launch_spin_source(c->P, c->stream, c->spart, c->items[c->icur], c->M, coef, c->sby, c->sbz);
-        launch_conv_add(c->stream, c->sby, c->E0y, c->tapsA, c->ntA, c->mloA, c->M);
-        launch_conv_add(c->stream, c->sbz, c->E0z, c->tapsA, c->ntA, c->mloA, c->M);
+        launch_spin_source(c->P, c->stream, c->spart, c->items[c->icur], c->M, coef, c->tapsA, c->ntA, c->mloA,
+                           c->E0y, c->E0z);
     });
 }
 
@@ -810,7 +807,7 @@ void free_all(ecpic_ctx *c) {
     }
     F(c->wcnt); F(c->base); F(c->cbase); F(c->nstart); F(c->part);
     F(c->E0y); F(c->E0z); F(c->taps1); F(c->dprev);
-    F(c->spart); F(c->sby); F(c->sbz); F(c->epart);
+    F(c->spart); F(c->epart);
     for (auto &t : c->tapsA_by_dt) F(t.second.dev);
     F(c->coefA); F(c->coefE[0]); F(c->coefE[1]); F(c->coefAk[0]); F(c->coefAk[1]);
     F(c->st_ring);
@@ -890,7 +887,6 @@ int alloc_all(ecpic_ctx *c) {
     if (c->symmetric || c->spin) rc |= dalloc(&c->ex_save, MP);
     if (c->spin) {
         rc |= dalloc(&c->spart, (size_t)c->max_items * 2 * c->P);
-        rc |= dalloc(&c->sby, M); rc |= dalloc(&c->sbz, M);
         rc |= dalloc(&c->epart, c->max_items);
     }
     if (rc) return ECPIC_ENOMEM;

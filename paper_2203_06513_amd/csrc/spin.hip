@@ -71,6 +71,7 @@ template <int P>
 __global__ void __launch_bounds__(256) k_spin_rotate(SpinArgs a, int M) {
     CellDiff<P> d;
     if (!cell_diff<P>(a, blockIdx.x, M, d)) return;
+#pragma unroll 2
     for (int i = d.beg + (int)threadIdx.x; i < d.end; i += blockDim.x) {
         const double t = local_t(a.xi[i], d.c);
         double Y, Z;
@@ -78,10 +79,11 @@ __global__ void __launch_bounds__(256) k_spin_rotate(SpinArgs a, int M) {
         const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
         const double nr2 = fma(Y, Y, Z * Z);
         double c1 = a.h, c2 = 0.5 * a.h * a.h;
-        if (nr2 > 0.0) {
+        if (nr2 > 0.0) {   // sin(h|r|) = 2 sin(h|r|/2) cos(h|r|/2): one sincos
             const double nr = sqrt(nr2);
-            const double sh = sin(0.5 * a.h * nr);
-            c1 = sin(a.h * nr) / nr;
+            double sh, ch;
+            sincos(0.5 * a.h * nr, &sh, &ch);
+            c1 = 2.0 * sh * ch / nr;
             c2 = 2.0 * sh * sh / nr2;
         }
         // u = rhat s, v = rhat u (rhat = [[0, Y, Z], [-Y, 0, 0], [-Z, 0, 0]])
@@ -104,6 +106,7 @@ __global__ void __launch_bounds__(256) k_spin_deposit(SpinArgs a, int M) {
     double vy[P], vz[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) { vy[m] = 0.0; vz[m] = 0.0; }
+#pragma unroll 4
     for (int i = d.beg + (int)threadIdx.x; i < d.end; i += blockDim.x) {
         double B[P];
         basis_values<P - 1, double>(local_t(a.xi[i], d.c), B);
@@ -128,42 +131,53 @@ __global__ void __launch_bounds__(256) k_spin_deposit(SpinArgs a, int M) {
     }
 }
 
-// The source of Subsystem II on V0 index j, times dt, added to E0 through the
-// matrix inverse: first b (here), then E0 += taps * b (k_conv_add).
-//   u_j = w sum over items of cells c = j .. j+P-1 of their (V1 index c - m = j) sums,
-//   b_y,j = -hbar dt (u^z_j - u^z_{j+1}) / dx,   b_z,j = +hbar dt (u^y_j - u^y_{j+1}) / dx.
+// The source of Subsystem II, times dt, added to the iteration's constant part
+// E0 through the matrix inverse (E0 += taps * b, the taps of (M0 + dt^2 K/4)
+// scaled by dx), one block per 256 outputs with its window of u and b in LDS:
+//   u_k = w sum over items of cells c = k .. k+P-1 of their (V1 index c - m = k) sums,
+//   b_y,k = -hbar dt (u^z_k - u^z_{k+1}) / dx,   b_z,k = +hbar dt (u^y_k - u^y_{k+1}) / dx
+// (coef = hbar dt w / dx^2 takes the w, the 1/dx of G^T and that of the taps).
 template <int P>
 __global__ void __launch_bounds__(256) k_spin_source(const double *spart, ItemList items, int M, double coef,
-                                                     double *by, double *bz) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= M) return;
+                                                     const double *taps, int ntaps, int mlo, double *E0y,
+                                                     double *E0z) {
+    extern __shared__ double sh[];
+    const int len = blockDim.x + ntaps - 1;            // b indices lo .. lo + len - 1
+    const int j0 = blockIdx.x * blockDim.x;
+    const int lo = j0 - mlo - (ntaps - 1);
+    double *uy = sh, *uz = uy + (len + 1), *by = uz + (len + 1), *bz = by + len;
     const int one_each = items.n_items[1];
-    double u[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   // [j, j+1][y, z]
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int q = threadIdx.x; q < len + 1; q += blockDim.x) {
+        double vy = 0.0, vz = 0.0;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
-            const int c = imod(j + r + m, M);
+            const int c = imod(lo + q + m, M);
             const int i0 = one_each ? c : items.cell_first[c];
             const int i1 = one_each ? c + 1 : items.cell_first[c + 1];
             for (int it = i0; it < i1; ++it) {
-                u[r][0] += spart[(size_t)it * 2 * P + m];
-                u[r][1] += spart[(size_t)it * 2 * P + P + m];
+                vy += spart[(size_t)it * 2 * P + m];
+                vz += spart[(size_t)it * 2 * P + P + m];
             }
         }
+        uy[q] = vy;
+        uz[q] = vz;
     }
-    by[j] = -coef * (u[0][1] - u[1][1]);
-    bz[j] = coef * (u[0][0] - u[1][0]);
-}
-
-// out_j += sum_i taps[i] in[(j - mlo - i) mod M]  (in, out unpadded)
-__global__ void __launch_bounds__(256) k_conv_add(const double *in, double *out, const double *taps, int ntaps,
-                                                  int mlo, int M) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    __syncthreads();
+    for (int q = threadIdx.x; q < len; q += blockDim.x) {
+        by[q] = -coef * (uz[q] - uz[q + 1]);
+        bz[q] = coef * (uy[q] - uy[q + 1]);
+    }
+    __syncthreads();
+    const int j = j0 + threadIdx.x;
     if (j >= M) return;
-    double s = 0.0;
-    for (int i = 0; i < ntaps; ++i) s += taps[i] * in[imod(j - mlo - i, M)];
-    out[j] += s;
+    double sy = 0.0, sz = 0.0;
+    for (int i = 0; i < ntaps; ++i) {   // b index j - mlo - i, at q = threadIdx.x + ntaps - 1 - i
+        const int q = threadIdx.x + ntaps - 1 - i;
+        sy = fma(taps[i], by[q], sy);
+        sz = fma(taps[i], bz[q], sz);
+    }
+    E0y[j] += sy;
+    E0z[j] += sz;
 }
 
 // Per item: sum over its particles of s_y dA_z/dx - s_z dA_y/dx (the Zeeman
@@ -229,12 +243,10 @@ void launch_spin_deposit(int P, int grid, hipStream_t s, const SpinArgs &a, int 
 }
 
 void launch_spin_source(int P, hipStream_t s, const double *spart, const ItemList &items, int M, double coef,
-                        double *by, double *bz) {
-    ECPIC_SPIN_P(k_spin_source, dim3((M + 255) / 256), dim3(256), 0, s, spart, items, M, coef, by, bz)
-}
-
-void launch_conv_add(hipStream_t s, const double *in, double *out, const double *taps, int ntaps, int mlo, int M) {
-    launch_k(k_conv_add, dim3((M + 255) / 256), dim3(256), 0, s, in, out, taps, ntaps, mlo, M);
+                        const double *taps, int ntaps, int mlo, double *E0y, double *E0z) {
+    const size_t lds = sizeof(double) * (4 * (size_t)(256 + ntaps - 1) + 2);
+    ECPIC_SPIN_P(k_spin_source, dim3((M + 255) / 256), dim3(256), lds, s, spart, items, M, coef, taps, ntaps, mlo,
+                 E0y, E0z)
 }
 
 void launch_spin_energy(int P, int grid, hipStream_t s, const SpinArgs &a, int M) {
