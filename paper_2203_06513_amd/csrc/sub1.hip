@@ -113,8 +113,10 @@ struct PushEnd {
 // SPIN: the force of the Zeeman energy, hbar (s_z DD_y - s_y DD_z) with DD the
 // divided difference of dA/dx along the step (per cell, (A'(t1) - A'(t0))/(t1 -
 // t0) / dx^2 with A' = dA/dt, from the same h_i); hbar_dx2 = hbar / dx^2.  It
-// does not depend on p, so the adjoint takes it unchanged.
-template <int P, typename T, bool ADJ = false, bool MOM = true, bool SPIN = false>
+// does not depend on p, so the adjoint takes it unchanged.  DN = false: only the
+// momentum is wanted (the commit), so the next increment and its reciprocal are
+// not formed (dn is left unset).
+template <int P, typename T, bool ADJ = false, bool MOM = true, bool SPIN = false, bool DN = true>
 __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T> *rec, bool anycross,
                                            const Lane<T> &L, T dt, T dt_dx, T inv_dx, T &p1, T &dn, int &flags,
                                            PushEnd<T> *pe = nullptr, T hbar_dx2 = (T)0) {
@@ -172,7 +174,7 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
         const T F = LE - ((L.A0y + A1y) * DAy + (L.A0z + A1z) * DAz) * inv_dx * frcp(L.g00 + g01);
         p1 = fma(dt, F, L.p0);
         g11 = fsqrt(fma(p1, p1, one) + qa1);
-        dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
+        if constexpr (DN) dn = dt_dx * (L.p0 + p1) * frcp(g01 + g11);
     } else {
         // with U = g00 + g01 and N = p1 U = p0 U + dt (LE U - X):
         //   gamma(p1, A1) = sqrt(U^2 (1 + |A1|^2) + N^2) / U, so
@@ -192,7 +194,7 @@ __device__ __forceinline__ void stage_push(const Own<P, T> &o, const LdsRec<P, T
         pe->g11 = g11;
     }
     const T big = sizeof(T) == 8 ? (T)1.0e300 : (T)1.0e30f;
-    wave_flag(flags, !(fabs(dn) < big), FLAG_NONFINITE);
+    if constexpr (DN) wave_flag(flags, !(fabs(dn) < big), FLAG_NONFINITE);
     wave_flag(flags, !(fabs(p1) < big), FLAG_NONFINITE);
 }
 
@@ -1141,8 +1143,8 @@ __device__ __forceinline__ void commit_scatter_item(const CommitIArgs &a, int it
             p1 = La.P;
             wave_flag(flags, !(fabs(p1) < 1.0e300), FLAG_NONFINITE);
         } else {
-            stage_push<P, double, false, true, SPIN>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn, flags,
-                                                     &pe, a.hbar_dx2);
+            stage_push<P, double, false, true, SPIN, false>(o1, rec, anymove, La, a.dt, a.dt_dx, a.inv_dx, p1, dn,
+                                                            flags, &pe, a.hbar_dx2);
         }
         const int t = valid ? La.s + 1 : -1;   // 0 left, 1 stay, 2 right
         double xin = xi0 + d;
