@@ -16,15 +16,16 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
+SRC2D_PATH = os.path.join(_HERE, "oracle2d.c")
 
 OK, ENOTCONV = 0, -3
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (strict IEEE: no contraction, no fast-math)."""
+    """Compile the oracle (1D and 2D) with gcc (strict IEEE: no contraction, no fast-math)."""
     if force or not os.path.exists(LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-o", LIB_PATH, SRC_PATH, "-lm"]
+               "-fno-fast-math", "-Wall", "-o", LIB_PATH, SRC_PATH, SRC2D_PATH, "-lm"]
         subprocess.run(cmd, check=True)
     return LIB_PATH
 
