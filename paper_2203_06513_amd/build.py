@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libecpic.so")
-SOURCES = ["sub1.hip", "sub2.hip", "misc.hip", "mlp.hip", "noalloc.hip", "spin.hip", "runtime.hip"]
+SOURCES = ["sub1.hip", "sub2.hip", "misc.hip", "mlp.hip", "noalloc.hip", "spin.hip", "twod.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result",

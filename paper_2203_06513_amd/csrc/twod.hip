@@ -1,0 +1,1597 @@
+// Reduced 2D model (Sections 2.2, 3.2 and 4.3), hbar = 0: kernels, spectral
+// solves and the C ABI of include/ecpic2d.h.
+//
+// Data layout in HBM (one context):
+//   particles  SoA, sorted by cell c = floor(xi1) M2 + floor(xi2), double
+//              buffered: xi_k = x_k / dx_k in [0, M_k) (f64), p1, p2 (f64),
+//              id (i32, the index given at set_particles).  The Picard iterate
+//              d = x^{n+1} - x^n (physical units) and p^{k+1} live in more
+//              buffers.  start[c] is the first particle of cell c.
+//   fields     row-major M1 x M2 coefficient grids, index i1 M2 + i2 (no halo;
+//              the tile kernels wrap indices while staging).
+//   spectra    M1 x M2 complex grids for the linear solves.
+//
+// Tiles.  A tile is TW consecutive cells of one row (x1 fixed); its particles
+// are contiguous in the sorted order.  One thread block per tile stages the
+// field coefficients the tile's particles can touch (rows r-p-1 .. r+1, columns
+// c0-p-1 .. c0+TW, enough for a step of less than one cell) in LDS, gathers
+// from there, accumulates its deposits in LDS with atomics, and adds the patch
+// to the global grid with atomics at the end.
+//
+// Linear solves.  Every linear operator of the 2D scheme is a sum of tensor
+// products of circulants (periodic B-spline mass matrices and differences), so
+// the 2D discrete Fourier transform diagonalises it: M1, M0 + dt^2 K/4 and the
+// Maxwell system are solved exactly by a forward transform, a division by the
+// symbol and an inverse transform.  The transforms are radix-2 Stockham FFTs in
+// LDS (rows in one kernel, columns with the spectral step fused in the next).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ecpic2d.h"
+#include "spline.hpp"
+
+namespace ecpic2d {
+
+using ecpic::basis_values;
+using ecpic::line_mean_v1;
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int TWMAX = 16;        // tile width (cells along x2)
+constexpr int MAXM = 512;        // largest grid size per direction (LDS of the transforms)
+constexpr int MAXK = 64;         // residual slots per substep (Picard cap)
+constexpr int FLAG_NONFINITE = 1, FLAG_CFL = 2;
+
+__device__ __forceinline__ int wrapi(int j, int M) {
+    const int w = j < 0 ? j + M : (j >= M ? j - M : j);
+    if (w >= 0 && w < M) return w;
+    const int r = j % M;
+    return r < 0 ? r + M : r;
+}
+
+__device__ __forceinline__ unsigned long long bitsd(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+// Max of v >= 0 over the block, then one atomic max (as bits) into *slot.
+__device__ __forceinline__ void block_max_to(double v, unsigned long long *slot) {
+    __shared__ double red[BLOCK / WAVE];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x / WAVE); ++w) m = fmax(m, red[w]);
+        if (m > 0.0) atomicMax(slot, bitsd(m));
+    }
+}
+
+// Sum over the block in a fixed order; thread 0 writes it to *out.
+__device__ __forceinline__ void block_sum_to(double v, double *out) {
+    __shared__ double red[BLOCK / WAVE];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) s += red[w];
+        *out = s;
+    }
+}
+
+// Block -> tile, keeping each XCD (blocks are dealt to the 8 XCDs round robin)
+// on a contiguous band of rows so neighbouring tiles share its L2.
+__device__ __forceinline__ int tile_of_block() {
+    const int b = blockIdx.x, n = gridDim.x;
+    if (n % 8 != 0) return b;
+    return (b % 8) * (n / 8) + b / 8;
+}
+
+// Gauss-Legendre rule with P points on [0, 1] (exact to degree 2P - 1, the degree
+// of a product of a degree-P and a degree-(P-1) spline along a straight path).
+template <int P>
+struct GL;
+template <> struct GL<2> {
+    static constexpr double x[2] = {0.21132486540518713, 0.7886751345948129};
+    static constexpr double w[2] = {0.5, 0.5};
+};
+template <> struct GL<3> {
+    static constexpr double x[3] = {0.1127016653792583, 0.5, 0.8872983346207417};
+    static constexpr double w[3] = {0.27777777777777785, 0.4444444444444444, 0.27777777777777785};
+};
+template <> struct GL<4> {
+    static constexpr double x[4] = {0.06943184420297371, 0.33000947820757187, 0.6699905217924281,
+                                    0.9305681557970262};
+    static constexpr double w[4] = {0.17392742256872684, 0.3260725774312731, 0.3260725774312731,
+                                    0.17392742256872684};
+};
+template <> struct GL<5> {
+    static constexpr double x[5] = {0.04691007703066802, 0.23076534494715845, 0.5, 0.7692346550528415,
+                                    0.9530899229693319};
+    static constexpr double w[5] = {0.11846344252809471, 0.2393143352496831, 0.2844444444444445,
+                                    0.2393143352496831, 0.11846344252809471};
+};
+
+// Window vector of the degree-D splines alive at a point of cell m + o (o in
+// {0, 1}) over the D + 2 indices m - D .. m + 1: v[j] is the spline of index
+// m - D + j, B[k] the value of the spline of index (m + o) - k.
+template <int D>
+__device__ __forceinline__ void window(const double (&B)[D + 1], int o, double (&v)[D + 2]) {
+#pragma unroll
+    for (int j = 0; j < D + 2; ++j) {
+        const double lo = (j <= D) ? B[(D - j) < 0 ? 0 : (D - j)] : 0.0;           // o = 0: index m - D + j = m - k
+        const double hi = (j >= 1) ? B[(D + 1 - j) > D ? D : (D + 1 - j)] : 0.0;  // o = 1
+        v[j] = o ? hi : lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small grid and particle kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k2_fill(double *a, int64_t n, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__global__ void k2_fill_u64(unsigned long long *a, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0ull;
+}
+
+__global__ void k2_fill_i32(int32_t *a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+__global__ void k2_copy(double *__restrict__ dst, const double *__restrict__ src, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// (G a)_1 = (a_{i1,i2} - a_{i1-1,i2}) / dx1, (G a)_2 = (a_{i1,i2} - a_{i1,i2-1}) / dx2.
+__global__ void k2_grad(const double *__restrict__ a, double *__restrict__ g1, double *__restrict__ g2, int M1,
+                        int M2, double inv_dx1, double inv_dx2) {
+    const int N = M1 * M2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int i1 = i / M2, i2 = i - i1 * M2;
+        const double v = a[i];
+        g1[i] = (v - a[wrapi(i1 - 1, M1) * M2 + i2]) * inv_dx1;
+        g2[i] = (v - a[i1 * M2 + wrapi(i2 - 1, M2)]) * inv_dx2;
+    }
+}
+
+// Positions of new particles: wrap into [0, M) (cell units), record the cell and
+// count it.
+__global__ __launch_bounds__(BLOCK) void k2_bin_new(const double *__restrict__ x1, const double *__restrict__ x2, double *__restrict__ xi1,
+                           double *__restrict__ xi2, int32_t *__restrict__ cell, int32_t *__restrict__ count,
+                           int64_t n, int M1, int M2, double inv_dx1, double inv_dx2, int *flags) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double u1 = x1[i] * inv_dx1, u2 = x2[i] * inv_dx2;
+        if (!isfinite(u1) || !isfinite(u2)) { atomicOr(flags, FLAG_NONFINITE); u1 = 0.0; u2 = 0.0; }
+        u1 = fmod(u1, (double)M1);
+        u2 = fmod(u2, (double)M2);
+        if (u1 < 0.0) u1 += (double)M1;
+        if (u2 < 0.0) u2 += (double)M2;
+        if (u1 >= (double)M1) u1 = 0.0;
+        if (u2 >= (double)M2) u2 = 0.0;
+        xi1[i] = u1;
+        xi2[i] = u2;
+        const int c = (int)u1 * M2 + (int)u2;
+        cell[i] = c;
+        atomicAdd(&count[c], 1);
+    }
+}
+
+// Exclusive scan of count[0..Nc) into start[0..Nc] and count <- 0 (one block of
+// 1024 threads, each owning a contiguous run of cells).
+__global__ void k2_scan(int32_t *__restrict__ count, int32_t *__restrict__ start, int Nc) {
+    __shared__ int wsum[1024 / WAVE];
+    const int per = (Nc + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * per;
+    int local = 0;
+    for (int c = c0; c < c0 + per && c < Nc; ++c) local += count[c];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    int x = local;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    if (lane == WAVE - 1) wsum[wid] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) {
+        pre += w < wid ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    int off = pre + x - local;
+    for (int c = c0; c < c0 + per && c < Nc; ++c) {
+        const int k = count[c];
+        start[c] = off;
+        off += k;
+        count[c] = 0;
+    }
+    if (threadIdx.x == 0) start[Nc] = tot;
+}
+
+// Move every particle to its cell's range of the destination buffers.
+__global__ __launch_bounds__(BLOCK) void k2_scatter(const double *__restrict__ s1, const double *__restrict__ s2,
+                           const double *__restrict__ q1, const double *__restrict__ q2,
+                           const int32_t *__restrict__ sid, double *__restrict__ d1, double *__restrict__ d2,
+                           double *__restrict__ r1, double *__restrict__ r2, int32_t *__restrict__ did,
+                           const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
+                           int32_t *__restrict__ cursor, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = cell[i];
+        const int j = start[c] + atomicAdd(&cursor[c], 1);
+        d1[j] = s1[i];
+        d2[j] = s2[i];
+        r1[j] = q1[i];
+        r2[j] = q2[i];
+        did[j] = sid[i];
+    }
+}
+
+// out[id[i]] = v[i] (positions back to physical units when scale != 1).
+__global__ void k2_unsort(const double *__restrict__ v, const int32_t *__restrict__ id, double *__restrict__ out,
+                          int64_t n, double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[id[i]] = v[i] * scale;
+}
+
+__global__ void k2_iota(int32_t *id, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        id[i] = (int32_t)i;
+}
+
+// Value of the degree (P, P) field at a point in cell (c1, c2), local (t1, t2),
+// from the global grid.
+template <int P>
+__device__ __forceinline__ double gather00(const double *__restrict__ f, int M1, int M2, int c1, int c2, double t1,
+                                           double t2) {
+    double b1[P + 1], b2[P + 1];
+    basis_values<P>(t1, b1);
+    basis_values<P>(t2, b2);
+    double s = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 <= P; ++m1) {
+        const double *row = f + wrapi(c1 - m1, M1) * M2;
+        double t = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 <= P; ++m2) t += b2[m2] * row[wrapi(c2 - m2, M2)];
+        s += b1[m1] * t;
+    }
+    return s;
+}
+
+// Explicit start of the Picard iteration: d = dt p / gamma(x^n, p^n).
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_init_I(const double *__restrict__ xi1, const double *__restrict__ xi2,
+                          const double *__restrict__ p1, const double *__restrict__ p2,
+                          const double *__restrict__ az, double *__restrict__ d1, double *__restrict__ d2, int64_t n,
+                          int M1, int M2, double dt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c1 = (int)u1, c2 = (int)u2;
+        const double A = gather00<P>(az, M1, M2, c1, c2, u1 - c1, u2 - c2);
+        const double q1 = p1[i], q2 = p2[i];
+        const double s = dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+        d1[i] = q1 * s;
+        d2[i] = q2 * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Subsystem I sweep (Section 4.3): gather, push, deposit, one tile per block
+// ---------------------------------------------------------------------------
+struct SweepArgs {
+    const double *xi1, *xi2, *p1, *p2;   // sorted particles
+    const double *d1, *d2;               // increment d^(k) (physical)
+    double *dn1, *dn2;                   // increment d^(k+1)
+    double *pk1, *pk2;                   // momentum p^(k+1)
+    const int32_t *start;
+    const double *eb1, *eb2;             // (e^n + e^(k)) / 2
+    const double *az, *g1a, *g2a;        // a_z and G a_z
+    double *J1, *J2;                     // current of d^(k) (accumulated, zero on entry)
+    unsigned long long *res;             // max |d^(k+1) - d^(k)|, as bits
+    int *flags;
+    int M1, M2, TW;
+    double inv_dx1, inv_dx2, dt, w;
+};
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
+    constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
+    __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
+    const int nseg = a.M2 / a.TW;
+    const int tile = tile_of_block();
+    const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
+    const int PC = a.TW + P + 2;
+    const int R0 = r - P - 1, C0 = c0 - P - 1;
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
+        sE1[t] = a.eb1[g];
+        sE2[t] = a.eb2[g];
+        sA[t] = a.az[g];
+        sG1[t] = a.g1a[g];
+        sG2[t] = a.g2a[g];
+        sJ1[t] = 0.0;
+        sJ2[t] = 0.0;
+    }
+    __syncthreads();
+    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
+    double rmax = 0.0;
+    int flags = 0;
+    for (int base = begin; base < end; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        const bool live = i < end;
+        const int ii = live ? i : begin;
+        const double x1 = a.xi1[ii], x2 = a.xi2[ii];
+        const double q1 = a.p1[ii], q2 = a.p2[ii];
+        const double D1 = live ? a.d1[ii] : 0.0, D2 = live ? a.d2[ii] : 0.0;
+        const double s1 = D1 * a.inv_dx1, s2 = D2 * a.inv_dx2;   // increment in cell units
+        const double y1 = x1 + s1, y2 = x2 + s2;
+        const int ca1 = r, ca2 = (int)x2;
+        int cb1 = (int)floor(y1), cb2 = (int)floor(y2);
+        if (cb1 < ca1 - 1 || cb1 > ca1 + 1 || cb2 < ca2 - 1 || cb2 > ca2 + 1 || !isfinite(s1 + s2)) {
+            flags |= isfinite(s1 + s2) ? FLAG_CFL : FLAG_NONFINITE;
+            cb1 = ca1;
+            cb2 = ca2;
+        }
+        const int mn1 = min(ca1, cb1), mn2 = min(ca2, cb2);
+        // breakpoints of the straight path where it crosses a grid line
+        const double bA = cb1 != ca1 ? ((double)max(ca1, cb1) - x1) / s1 : 1.0;
+        const double bB = cb2 != ca2 ? ((double)max(ca2, cb2) - x2) / s2 : 1.0;
+        const double lo = fmin(bA, bB), hi = fmax(bA, bB);
+        // path means of the V1 basis: W1 over rows mn1-(P-1).., cols mn2-P..; W2 over rows mn1-P.., cols mn2-(P-1)..
+        double W1[P + 1][P + 2], W2[P + 2][P + 1];
+#pragma unroll
+        for (int u = 0; u < P + 1; ++u)
+#pragma unroll
+            for (int v = 0; v < P + 2; ++v) { W1[u][v] = 0.0; W2[v][u] = 0.0; }
+#pragma unroll 1
+        for (int piece = 0; piece < 3; ++piece) {
+            const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
+            const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
+            const double len = live ? sb - sa : 0.0;
+            if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
+            const double sm = 0.5 * (sa + sb);
+            const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
+            const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
+            const int o1 = k1 - mn1, o2 = k2 - mn2;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const double s = sa + len * GL<P>::x[q];
+                const double g = len * GL<P>::w[q];
+                const double t1 = x1 + s * s1 - k1, t2 = x2 + s * s2 - k2;
+                double b0x[P + 1], b1x[P], b0y[P + 1], b1y[P];
+                basis_values<P>(t1, b0x);
+                basis_values<P - 1>(t1, b1x);
+                basis_values<P>(t2, b0y);
+                basis_values<P - 1>(t2, b1y);
+                double v0x[P + 2], v1x[P + 1], v0y[P + 2], v1y[P + 1];
+                window<P>(b0x, o1, v0x);
+                window<P - 1>(b1x, o1, v1x);
+                window<P>(b0y, o2, v0y);
+                window<P - 1>(b1y, o2, v1y);
+#pragma unroll
+                for (int u = 0; u < P + 1; ++u) {
+                    const double gx = g * v1x[u], gy = g * v1y[u];
+#pragma unroll
+                    for (int v = 0; v < P + 2; ++v) {
+                        W1[u][v] += gx * v0y[v];
+                        W2[v][u] += gy * v0x[v];
+                    }
+                }
+            }
+        }
+        // gathers: Ebar along the path, A at both ends, means of dA/dx2 (vertical leg
+        // at x1^n) and dA/dx1 (horizontal leg at x2^{n+1})
+        const int rW1 = mn1 - (P - 1) - R0, cW1 = mn2 - P - C0;
+        const int rW2 = mn1 - P - R0, cW2 = mn2 - (P - 1) - C0;
+        double E1 = 0.0, E2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < P + 1; ++u)
+#pragma unroll
+            for (int v = 0; v < P + 2; ++v) {
+                E1 += W1[u][v] * sE1[(rW1 + u) * PC + cW1 + v];
+                E2 += W2[v][u] * sE2[(rW2 + v) * PC + cW2 + u];
+            }
+        double ba1[P + 1], ba2[P + 1], bb1[P + 1], bb2[P + 1];
+        basis_values<P>(x1 - ca1, ba1);
+        basis_values<P>(x2 - ca2, ba2);
+        basis_values<P>(y1 - cb1, bb1);
+        basis_values<P>(y2 - cb2, bb2);
+        double Aa = 0.0, Ab = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            double ta = 0.0, tb = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) {
+                ta += ba2[m2] * sA[(ca1 - m1 - R0) * PC + ca2 - m2 - C0];
+                tb += bb2[m2] * sA[(cb1 - m1 - R0) * PC + cb2 - m2 - C0];
+            }
+            Aa += ba1[m1] * ta;
+            Ab += bb1[m1] * tb;
+        }
+        double lm2[P + 2], lm1[P + 2];
+        line_mean_v1<P>(x2 - ca2, y2 - ca2, cb2 - ca2, lm2);   // indices ca2 - P + k
+        line_mean_v1<P>(x1 - ca1, y1 - ca1, cb1 - ca1, lm1);   // indices ca1 - P + k
+        double Dv = 0.0, Dh = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < P + 2; ++k) t += lm2[k] * sG2[(ca1 - m1 - R0) * PC + ca2 - P + k - C0];
+            Dv += ba1[m1] * t;
+        }
+#pragma unroll
+        for (int k = 0; k < P + 2; ++k) {
+            double t = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) t += bb2[m2] * sG1[(ca1 - P + k - R0) * PC + cb2 - m2 - C0];
+            Dh += lm1[k] * t;
+        }
+        // push (Subsystem I scheme)
+        const double pp = q1 * q1 + q2 * q2;
+        const double gA = sqrt(1.0 + pp + Aa * Aa), gB = sqrt(1.0 + pp + Ab * Ab);
+        const double f = -(Aa + Ab) / (gA + gB);
+        const double n1 = q1 + a.dt * (E1 + f * Dh), n2 = q2 + a.dt * (E2 + f * Dv);
+        const double gC = sqrt(1.0 + n1 * n1 + n2 * n2 + Ab * Ab);
+        const double sc = a.dt / (gB + gC);
+        const double e1 = (q1 + n1) * sc, e2 = (q2 + n2) * sc;
+        if (live) {
+            if (!isfinite(e1 + e2 + n1 + n2)) flags |= FLAG_NONFINITE;
+            a.dn1[i] = e1;
+            a.dn2[i] = e2;
+            a.pk1[i] = n1;
+            a.pk2[i] = n2;
+            rmax = fmax(rmax, fmax(fabs(e1 - D1), fabs(e2 - D2)));
+            // current of d^(k): w d times the path means of the V1 basis
+            const double j1 = a.w * D1, j2 = a.w * D2;
+#pragma unroll
+            for (int u = 0; u < P + 1; ++u)
+#pragma unroll
+                for (int v = 0; v < P + 2; ++v) {
+                    atomicAdd(&sJ1[(rW1 + u) * PC + cW1 + v], j1 * W1[u][v]);
+                    atomicAdd(&sJ2[(rW2 + v) * PC + cW2 + u], j2 * W2[v][u]);
+                }
+        }
+    }
+    if (flags) atomicOr(a.flags, flags);
+    block_max_to(rmax, a.res);
+    __syncthreads();
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
+        if (sJ1[t] != 0.0) atomicAdd(&a.J1[g], sJ1[t]);
+        if (sJ2[t] != 0.0) atomicAdd(&a.J2[g], sJ2[t]);
+    }
+}
+
+// Commit x^n + d^(k), p^(k+1) and bin the particles by their new cells.
+__global__ __launch_bounds__(BLOCK) void k2_commit_I(double *__restrict__ xi1, double *__restrict__ xi2, double *__restrict__ p1,
+                            double *__restrict__ p2, const double *__restrict__ d1, const double *__restrict__ d2,
+                            const double *__restrict__ pk1, const double *__restrict__ pk2,
+                            int32_t *__restrict__ cell, int32_t *__restrict__ count, int64_t n, int M1, int M2,
+                            double inv_dx1, double inv_dx2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
+        if (u1 < 0.0) u1 += (double)M1;
+        if (u1 >= (double)M1) u1 -= (double)M1;
+        if (u2 < 0.0) u2 += (double)M2;
+        if (u2 >= (double)M2) u2 -= (double)M2;
+        if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
+        if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
+        xi1[i] = u1;
+        xi2[i] = u2;
+        p1[i] = pk1[i];
+        p2[i] = pk2[i];
+        const int c = (int)u1 * M2 + (int)u2;
+        cell[i] = c;
+        atomicAdd(&count[c], 1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Subsystem II: rotation of p by B_z
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_rotate_II(const double *__restrict__ xi1, const double *__restrict__ xi2,
+                             double *__restrict__ p1, double *__restrict__ p2, const double *__restrict__ bz,
+                             const double *__restrict__ az, int64_t n, int M1, int M2, double dt) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c1 = (int)u1, c2 = (int)u2;
+        const double t1 = u1 - c1, t2 = u2 - c2;
+        double a1[P + 1], a2[P + 1], b1[P], b2[P];
+        basis_values<P>(t1, a1);
+        basis_values<P>(t2, a2);
+        basis_values<P - 1>(t1, b1);
+        basis_values<P - 1>(t2, b2);
+        double A = 0.0, B = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            const int row = wrapi(c1 - m1, M1) * M2;
+            double ta = 0.0, tb = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) {
+                const int col = wrapi(c2 - m2, M2);
+                ta += a2[m2] * az[row + col];
+                if (m1 < P && m2 < P) tb += b2[m2] * bz[row + col];
+            }
+            A += a1[m1] * ta;
+            if (m1 < P) B += b1[m1] * tb;
+        }
+        const double q1 = p1[i], q2 = p2[i];
+        const double th = B * dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        p1[i] = q1 * cs + q2 * sn;
+        p2[i] = -q1 * sn + q2 * cs;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Subsystem III particle term and the charge deposit (tiles, no motion)
+// ---------------------------------------------------------------------------
+struct DepArgs {
+    const double *xi1, *xi2, *p1, *p2;
+    const int32_t *start;
+    const double *an;    // a_z^n                     (III)
+    const double *ezn;   // e_z^n                     (III)
+    const double *ezk;   // e_z^(k)                   (III)
+    double *S;           // deposit target (zero on entry)
+    int M1, M2, TW;
+    double dt, w;
+    int mode;            // 0: charge w Lambda0; 1: Subsystem III source
+};
+
+// mode 1: S += w (A^n + A^(k)) / (gamma(p, A^n) + gamma(p, A^(k))) Lambda0(x_a),
+// with A^(k) the field of a^(k) = a^n - dt (e^n + e^(k)) / 2.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
+    constexpr int PR = P + 1, PCM = TWMAX + P, PS = PR * PCM;
+    __shared__ double sAn[PS], sAk[PS], sS[PS];
+    const int nseg = a.M2 / a.TW;
+    const int tile = tile_of_block();
+    const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
+    const int PC = a.TW + P;
+    const int R0 = r - P, C0 = c0 - P;
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
+        if (a.mode == 1) {
+            const double an = a.an[g];
+            sAn[t] = an;
+            sAk[t] = an - 0.5 * a.dt * (a.ezn[g] + a.ezk[g]);
+        }
+        sS[t] = 0.0;
+    }
+    __syncthreads();
+    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
+    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        const double u1 = a.xi1[i], u2 = a.xi2[i];
+        const int c2 = (int)u2;
+        double b1[P + 1], b2[P + 1];
+        basis_values<P>(u1 - r, b1);
+        basis_values<P>(u2 - c2, b2);
+        double q = a.w;
+        if (a.mode == 1) {
+            double An = 0.0, Ak = 0.0;
+#pragma unroll
+            for (int m1 = 0; m1 <= P; ++m1) {
+                double tn = 0.0, tk = 0.0;
+#pragma unroll
+                for (int m2 = 0; m2 <= P; ++m2) {
+                    const int s = (r - m1 - R0) * PC + c2 - m2 - C0;
+                    tn += b2[m2] * sAn[s];
+                    tk += b2[m2] * sAk[s];
+                }
+                An += b1[m1] * tn;
+                Ak += b1[m1] * tk;
+            }
+            const double q1 = a.p1[i], q2 = a.p2[i], pp = 1.0 + q1 * q1 + q2 * q2;
+            q = a.w * (An + Ak) / (sqrt(pp + An * An) + sqrt(pp + Ak * Ak));
+        }
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            const double qb = q * b1[m1];
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) atomicAdd(&sS[(r - m1 - R0) * PC + c2 - m2 - C0], qb * b2[m2]);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
+        if (sS[t] != 0.0) atomicAdd(&a.S[g], sS[t]);
+    }
+}
+
+// a^{n+1} = a^n - dt (e^n + e^{n+1}) / 2, e_z = e^{n+1}.
+__global__ void k2_finish_III(double *__restrict__ az, double *__restrict__ ez, const double *__restrict__ ezn,
+                              const double *__restrict__ ezk, int N, double dt) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        az[i] -= 0.5 * dt * (ezn[i] + ezk[i]);
+        ez[i] = ezk[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: kinetic energy, quadratic forms, Gauss residual
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_kinetic(const double *__restrict__ xi1, const double *__restrict__ xi2,
+                           const double *__restrict__ p1, const double *__restrict__ p2,
+                           const double *__restrict__ az, int64_t n, int M1, int M2, double w,
+                           double *__restrict__ partial) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c1 = (int)u1, c2 = (int)u2;
+        const double A = gather00<P>(az, M1, M2, c1, c2, u1 - c1, u2 - c2);
+        const double q1 = p1[i], q2 = p2[i];
+        const double pp = q1 * q1 + q2 * q2 + A * A;
+        s += w * pp / (sqrt(1.0 + pp) + 1.0);   // gamma - 1 without cancellation
+    }
+    block_sum_to(s, &partial[blockIdx.x]);
+}
+
+struct MassRows {
+    double r1[11], r2[11];   // rows of the 1D mass matrices (dimensionless), 2d+1 entries
+    int d1, d2;
+    double scale;            // dx1 dx2
+};
+
+// y = (Mass_{d1} (x) Mass_{d2}) x on the periodic grid.
+__global__ __launch_bounds__(BLOCK) void k2_mass(const double *__restrict__ x, double *__restrict__ y, int M1, int M2, MassRows m) {
+    const int N = M1 * M2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int i1 = i / M2, i2 = i - i1 * M2;
+        double s = 0.0;
+        for (int k1 = -m.d1; k1 <= m.d1; ++k1) {
+            const double *row = x + wrapi(i1 + k1, M1) * M2;
+            double t = 0.0;
+            for (int k2 = -m.d2; k2 <= m.d2; ++k2) t += m.r2[k2 + m.d2] * row[wrapi(i2 + k2, M2)];
+            s += m.r1[k1 + m.d1] * t;
+        }
+        y[i] = m.scale * s;
+    }
+}
+
+// partial[block] = sum of x_i y_i over the block's nodes.
+__global__ void k2_dot(const double *__restrict__ x, const double *__restrict__ y, int N, double *partial) {
+    double s = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) s += x[i] * y[i];
+    block_sum_to(s, &partial[blockIdx.x]);
+}
+
+// out = sum of partial[0..n) in order (one block).
+__global__ void k2_sum(const double *__restrict__ partial, int n, double *out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += partial[i];
+    block_sum_to(s, out);
+}
+
+// r = G^T u + rho - dx1 dx2 with u = M1 e (two components); max |r| into *res.
+__global__ __launch_bounds__(BLOCK) void k2_gauss(const double *__restrict__ u1, const double *__restrict__ u2,
+                         const double *__restrict__ rho, double *__restrict__ r, int M1, int M2, double inv_dx1,
+                         double inv_dx2, double cell_area, unsigned long long *res) {
+    const int N = M1 * M2;
+    double m = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int i1 = i / M2, i2 = i - i1 * M2;
+        const double v = (u1[i] - u1[wrapi(i1 + 1, M1) * M2 + i2]) * inv_dx1 +
+                         (u2[i] - u2[i1 * M2 + wrapi(i2 + 1, M2)]) * inv_dx2 + rho[i] - cell_area;
+        r[i] = v;
+        m = fmax(m, fabs(v));
+    }
+    block_max_to(m, res);
+}
+
+// ---------------------------------------------------------------------------
+// Spectral solves: 2D FFT (rows, then columns with the spectral step fused)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Radix-2 Stockham FFT of n = 2^k points held in LDS at a (t: scratch of n);
+// tw[j] = exp(-2 pi i j / n), j < n/2; INV uses the conjugate twiddles (no
+// scaling).  Returns the buffer that holds the result (a or t).
+template <bool INV>
+__device__ double2 *fft_lds(double2 *a, double2 *t, int n, const double2 *__restrict__ tw) {
+    const int h = n >> 1;
+    for (int Ns = 1; Ns < n; Ns <<= 1) {
+        const int stride = h / Ns;
+        for (int j = threadIdx.x; j < h; j += blockDim.x) {
+            const int k = j & (Ns - 1);
+            const double2 v0 = a[j];
+            double2 w = tw[k * stride];
+            if (INV) w.y = -w.y;
+            const double2 v1 = cmul(a[j + h], w);
+            const int idx = ((j - k) << 1) + k;
+            t[idx] = make_double2(v0.x + v1.x, v0.y + v1.y);
+            t[idx + Ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+        }
+        __syncthreads();
+        double2 *s = a;
+        a = t;
+        t = s;
+    }
+    return a;
+}
+
+template <int NB>
+struct Ptrs {
+    double *p[NB];
+};
+
+// Forward transform along x2 of NB real grids (blockIdx.y picks the grid);
+// zero[b] != 0 zeroes grid b after it is read (the accumulators of the next
+// deposit).
+template <int NB>
+__global__ __launch_bounds__(BLOCK) void k2_fft_rows_fwd(Ptrs<NB> src, int zero_mask, double2 *__restrict__ Z,
+                                                         int M1, int M2, const double2 *__restrict__ tw2) {
+    __shared__ double2 buf[2 * MAXM];
+    const int row = blockIdx.x, b = blockIdx.y;
+    double *s = src.p[0];
+#pragma unroll
+    for (int q = 1; q < NB; ++q)
+        if (b == q) s = src.p[q];
+    s += (size_t)row * M2;
+    for (int j = threadIdx.x; j < M2; j += blockDim.x) {
+        buf[j] = make_double2(s[j], 0.0);
+        if ((zero_mask >> b) & 1) s[j] = 0.0;
+    }
+    __syncthreads();
+    const double2 *res = fft_lds<false>(buf, buf + M2, M2, tw2);
+    double2 *z = Z + (size_t)b * M1 * M2 + (size_t)row * M2;
+    for (int j = threadIdx.x; j < M2; j += blockDim.x) z[j] = res[j];
+}
+
+// 1D symbols of the spectral step, per direction (length M1 and M2): the mass
+// matrices' eigenvalues m0, m1 (dx included) and the backward difference
+// (1 - exp(-i theta)) / dx as (cr, ci).
+struct Sym {
+    const double *m0a, *m1a, *cra, *cia;
+    const double *m0b, *m1b, *crb, *cib;
+};
+
+// Along x1 for NB grids of the same column: forward transform, the spectral
+// step op(k1, k2, v) on every frequency, then (if op.INVERSE) the inverse
+// transform, written back to Z.
+template <int NB, class Op>
+__global__ __launch_bounds__(BLOCK) void k2_fft_cols(double2 *__restrict__ Z, int M1, int M2,
+                                                     const double2 *__restrict__ tw1, Op op) {
+    __shared__ double2 buf[(NB + 1) * MAXM];
+    const int col = blockIdx.x;
+    const size_t N = (size_t)M1 * M2;
+    double2 *scratch = buf + NB * M1;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = Z[b * N + (size_t)i * M2 + col];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        double2 *res = fft_lds<false>(buf + b * M1, scratch, M1, tw1);
+        if (res != buf + b * M1) {
+            for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = res[i];
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < M1; i += blockDim.x) {
+        double2 v[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[b] = buf[b * M1 + i];
+        op(i, col, v);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) buf[b * M1 + i] = v[b];
+    }
+    __syncthreads();
+    if (!Op::INVERSE) return;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        double2 *res = fft_lds<true>(buf + b * M1, scratch, M1, tw1);
+        if (res != buf + b * M1) {
+            for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = res[i];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        for (int i = threadIdx.x; i < M1; i += blockDim.x) Z[b * N + (size_t)i * M2 + col] = buf[b * M1 + i];
+}
+
+// Inverse transform along x2 of NB grids, scaled by 1/(M1 M2); the real part of
+// entry g of grid b goes to epi(b, g, v), whose return values are max-reduced
+// into epi.res (if set).
+template <int NB, class Epi>
+__global__ __launch_bounds__(BLOCK) void k2_fft_rows_inv(const double2 *__restrict__ Z, int M1, int M2,
+                                                         const double2 *__restrict__ tw2, double invN, Epi epi) {
+    __shared__ double2 buf[2 * MAXM];
+    const int row = blockIdx.x, b = blockIdx.y;
+    const double2 *z = Z + (size_t)b * M1 * M2 + (size_t)row * M2;
+    for (int j = threadIdx.x; j < M2; j += blockDim.x) buf[j] = z[j];
+    __syncthreads();
+    const double2 *res = fft_lds<true>(buf, buf + M2, M2, tw2);
+    double m = 0.0;
+    for (int j = threadIdx.x; j < M2; j += blockDim.x) m = fmax(m, epi(b, row * M2 + j, res[j].x * invN));
+    if (epi.res) block_max_to(m, epi.res);
+}
+
+// ---- spectral steps -------------------------------------------------------
+// M1^{-1} on the current (Subsystem I): component 1 has symbol m1(t1) m0(t2),
+// component 2 m0(t1) m1(t2).
+struct OpM1inv {
+    static constexpr bool INVERSE = true;
+    Sym s;
+    __device__ void operator()(int k1, int k2, double2 (&v)[2]) const {
+        const double d1 = 1.0 / (s.m1a[k1] * s.m0b[k2]), d2 = 1.0 / (s.m0a[k1] * s.m1b[k2]);
+        v[0].x *= d1; v[0].y *= d1;
+        v[1].x *= d2; v[1].y *= d2;
+    }
+};
+
+// e^{(k+1)} = e^n - M1^{-1} J; residual |e^{(k+1)} - e^{(k)}|; ebar = (e^n + e^{(k+1)})/2.
+struct EpiI {
+    const double *en1, *en2;
+    double *ek1, *ek2, *eb1, *eb2;
+    unsigned long long *res;
+    __device__ double operator()(int b, int g, double v) const {
+        const double en = b ? en2[g] : en1[g];
+        double *ek = b ? ek2 : ek1;
+        double *eb = b ? eb2 : eb1;
+        const double e = en - v;
+        const double d = fabs(e - ek[g]);
+        ek[g] = e;
+        eb[g] = 0.5 * (en + e);
+        return d;
+    }
+};
+
+__device__ __forceinline__ double kappa(const Sym &s, int k1, int k2) {   // symbol of K = G^T M1 G
+    const double c1 = s.cra[k1] * s.cra[k1] + s.cia[k1] * s.cia[k1];
+    const double c2 = s.crb[k2] * s.crb[k2] + s.cib[k2] * s.cib[k2];
+    return c1 * s.m1a[k1] * s.m0b[k2] + c2 * s.m0a[k1] * s.m1b[k2];
+}
+
+// Subsystem III constant part: R = (M0 - q K) e^n + dt K a^n (q = dt^2/4), kept in Fourier space.
+struct OpIIIrhs {
+    static constexpr bool INVERSE = false;
+    Sym s;
+    double2 *R;
+    int M2;
+    double dt;
+    __device__ void operator()(int k1, int k2, double2 (&v)[2]) const {
+        const double kp = kappa(s, k1, k2), m0 = s.m0a[k1] * s.m0b[k2];
+        const double ce = m0 - 0.25 * dt * dt * kp, ca = dt * kp;
+        R[(size_t)k1 * M2 + k2] = make_double2(ce * v[0].x + ca * v[1].x, ce * v[0].y + ca * v[1].y);
+    }
+};
+
+// Subsystem III solve: e = (R + dt S) / (M0 + q K).
+struct OpIII {
+    static constexpr bool INVERSE = true;
+    Sym s;
+    const double2 *R;
+    int M2;
+    double dt;
+    __device__ void operator()(int k1, int k2, double2 (&v)[1]) const {
+        const double lam = s.m0a[k1] * s.m0b[k2] + 0.25 * dt * dt * kappa(s, k1, k2);
+        const double2 r = R[(size_t)k1 * M2 + k2];
+        v[0] = make_double2((r.x + dt * v[0].x) / lam, (r.y + dt * v[0].y) / lam);
+    }
+};
+
+struct EpiIII {
+    double *ezk;
+    unsigned long long *res;
+    __device__ double operator()(int, int g, double v) const {
+        const double d = fabs(v - ezk[g]);
+        ezk[g] = v;
+        return d;
+    }
+};
+
+// Subsystem IV in Fourier space (v = e1, e2, b): with c_k = (1 - exp(-i t_k))/dx_k and
+// sigma = |c1|^2 m1a/m0a + |c2|^2 m1b/m0b the symbol of C M1^{-1} C^T M2,
+//   b' = ((1 - q sigma) b - dt (c1 e2 - c2 e1)) / (1 + q sigma),
+//   e1' = e1 - dt conj(c2) (m1b/m0b) (b + b')/2,  e2' = e2 + dt conj(c1) (m1a/m0a) (b + b')/2,
+// the implicit midpoint step of the Maxwell subsystem eliminated for b.
+struct OpIV {
+    static constexpr bool INVERSE = true;
+    Sym s;
+    double dt;
+    __device__ void operator()(int k1, int k2, double2 (&v)[3]) const {
+        const double2 c1 = make_double2(s.cra[k1], s.cia[k1]), c2 = make_double2(s.crb[k2], s.cib[k2]);
+        const double ra = s.m1a[k1] / s.m0a[k1], rb = s.m1b[k2] / s.m0b[k2];
+        const double sig = (c1.x * c1.x + c1.y * c1.y) * ra + (c2.x * c2.x + c2.y * c2.y) * rb;
+        const double q = 0.25 * dt * dt;
+        const double2 t1 = cmul(c1, v[1]), t2 = cmul(c2, v[0]);
+        const double2 ce = make_double2(t1.x - t2.x, t1.y - t2.y);
+        const double den = 1.0 / (1.0 + q * sig), num = 1.0 - q * sig;
+        const double2 bn = make_double2((num * v[2].x - dt * ce.x) * den, (num * v[2].y - dt * ce.y) * den);
+        const double2 bm = make_double2(0.5 * (v[2].x + bn.x), 0.5 * (v[2].y + bn.y));
+        const double2 u1 = cmul(make_double2(c2.x, -c2.y), bm), u2 = cmul(make_double2(c1.x, -c1.y), bm);
+        v[0] = make_double2(v[0].x - dt * rb * u1.x, v[0].y - dt * rb * u1.y);
+        v[1] = make_double2(v[1].x + dt * ra * u2.x, v[1].y + dt * ra * u2.y);
+        v[2] = bn;
+    }
+};
+
+// Gauss-law correction (v = e1, e2, rho): r = G^T M1 e + rho (the constant part
+// lives in the mean, which phi does not see), phi = r / kappa, e -= G phi.
+struct OpPoisson {
+    static constexpr bool INVERSE = true;
+    Sym s;
+    __device__ void operator()(int k1, int k2, double2 (&v)[3]) const {
+        if (k1 == 0 && k2 == 0) return;
+        const double2 c1 = make_double2(s.cra[k1], s.cia[k1]), c2 = make_double2(s.crb[k2], s.cib[k2]);
+        const double w1 = s.m1a[k1] * s.m0b[k2], w2 = s.m0a[k1] * s.m1b[k2];
+        const double2 a = cmul(make_double2(c1.x, -c1.y), v[0]), b = cmul(make_double2(c2.x, -c2.y), v[1]);
+        const double kp = kappa(s, k1, k2);
+        const double2 phi = make_double2((w1 * a.x + w2 * b.x + v[2].x) / kp, (w1 * a.y + w2 * b.y + v[2].y) / kp);
+        const double2 g1 = cmul(c1, phi), g2 = cmul(c2, phi);
+        v[0] = make_double2(v[0].x - g1.x, v[0].y - g1.y);
+        v[1] = make_double2(v[1].x - g2.x, v[1].y - g2.y);
+    }
+};
+
+template <int NB>
+struct EpiStore {
+    Ptrs<NB> out;
+    unsigned long long *res;
+    __device__ double operator()(int b, int g, double v) const {
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (b == q) out.p[q][g] = v;
+        return 0.0;
+    }
+};
+
+}  // namespace ecpic2d
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+using namespace ecpic2d;
+
+namespace {
+
+int64_t eulerian2(int n, int k) {   // A(n, k) = sum_j (-1)^j C(n+1, j) (k+1-j)^n
+    int64_t s = 0;
+    for (int j = 0; j <= k; ++j) {
+        int64_t b = 1;
+        for (int q = 1; q <= j; ++q) b = b * (n + 1 - j + q) / q;
+        int64_t pw = 1;
+        for (int q = 0; q < n; ++q) pw *= (k + 1 - j);
+        s += (j % 2 == 0) ? b * pw : -b * pw;
+    }
+    return s;
+}
+
+// Row of the degree-d B-spline mass matrix with dx = 1: the cardinal B-spline of
+// degree 2d+1 at the integers, A(2d+1, k) / (2d+1)!.
+std::vector<double> mass_row2(int d) {
+    const int n = 2 * d + 1;
+    double f = 1.0;
+    for (int q = 2; q <= n; ++q) f *= q;
+    std::vector<double> r(n);
+    for (int k = 0; k < n; ++k) r[k] = (double)eulerian2(n, k) / f;
+    return r;
+}
+
+struct Prof2 {
+    bool on = false;
+    std::map<std::string, std::pair<double, int64_t>> acc;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+};
+
+constexpr int RED_BLOCKS = 1024;
+
+}  // namespace
+
+struct ecpic2d_ctx {
+    ecpic2d_config cfg{};
+    int P = 3, M1 = 0, M2 = 0, Nc = 0, TW = 16, kmax = 50, device = 0;
+    int64_t N = 0;
+    double dx1 = 0, dx2 = 0, w = 0, tol = 0;
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    double *xi1[2] = {}, *xi2[2] = {}, *p1[2] = {}, *p2[2] = {};
+    int32_t *id[2] = {};
+    double *d1[2] = {}, *d2[2] = {}, *pk1 = nullptr, *pk2 = nullptr;
+    int32_t *cell = nullptr, *count = nullptr, *start = nullptr;
+    double *e1 = nullptr, *e2 = nullptr, *bz = nullptr, *ez = nullptr, *az = nullptr;
+    double *en1 = nullptr, *en2 = nullptr, *ek1 = nullptr, *ek2 = nullptr, *eb1 = nullptr, *eb2 = nullptr;
+    double *J1 = nullptr, *J2 = nullptr, *g1a = nullptr, *g2a = nullptr, *ezn = nullptr, *ezk = nullptr,
+           *S = nullptr, *tmp = nullptr;
+    double2 *Z = nullptr, *R = nullptr, *tw1 = nullptr, *tw2 = nullptr;
+    double *sym = nullptr;        // m0a m1a cra cia (M1 each) m0b m1b crb cib (M2 each)
+    double *partial = nullptr;    // RED_BLOCKS + 8
+    unsigned long long *res = nullptr;   // 3 * MAXK + 4 slots
+    int *flags = nullptr;
+    bool have_particles = false;
+    std::vector<double> m0row, m1row;
+    Prof2 prof;
+    std::vector<void *> allocs;
+};
+
+namespace {
+
+template <typename T>
+int dalloc(ecpic2d_ctx *c, T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc((void **)p, n * sizeof(T)) != hipSuccess) { *p = nullptr; return ECPIC_ENOMEM; }
+    c->allocs.push_back((void *)*p);
+    return ECPIC_OK;
+}
+
+int sync2(ecpic2d_ctx *c) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return ECPIC_EDEVICE;
+    if (c->prof.on) {
+        for (auto &pe : c->prof.pending) {
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, pe.second.first, pe.second.second);
+            auto &a = c->prof.acc[pe.first];
+            a.first += ms;
+            a.second += 1;
+            hipEventDestroy(pe.second.first);
+            hipEventDestroy(pe.second.second);
+        }
+        c->prof.pending.clear();
+    }
+    return hipGetLastError() == hipSuccess ? ECPIC_OK : ECPIC_EDEVICE;
+}
+
+// Launch with HIP events around it when profiling.
+template <class F>
+void timed(ecpic2d_ctx *c, const char *name, F launch) {
+    if (!c->prof.on) { launch(); return; }
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    hipEventRecord(a, c->stream);
+    launch();
+    hipEventRecord(b, c->stream);
+    c->prof.pending.push_back({name, {a, b}});
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + BLOCK - 1) / BLOCK;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 8192));
+}
+
+Sym sym_of(ecpic2d_ctx *c) {
+    const double *s = c->sym;
+    const int M1 = c->M1, M2 = c->M2;
+    return Sym{s, s + M1, s + 2 * M1, s + 3 * M1, s + 4 * M1, s + 4 * M1 + M2, s + 4 * M1 + 2 * M2,
+               s + 4 * M1 + 3 * M2};
+}
+
+int n_tiles(ecpic2d_ctx *c) { return c->M1 * (c->M2 / c->TW); }
+
+// Re-sort after positions changed: counts are in c->count, cells in c->cell.
+void sort_particles(ecpic2d_ctx *c) {
+    const int A = c->cur, B = 1 - c->cur;
+    timed(c, "sort", [&] {
+        k2_scan<<<1, 1024, 0, c->stream>>>(c->count, c->start, c->Nc);
+        k2_scatter<<<grid_for(c->N), BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A],
+                                                           c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
+                                                           c->cell, c->start, c->count, c->N);
+        k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->count, c->Nc);
+    });
+    c->cur = B;
+}
+
+// Forward rows -> columns with op -> inverse rows with epi, over NB grids.
+template <int NB, class Op, class Epi>
+void spectral(ecpic2d_ctx *c, const char *name, Ptrs<NB> src, int zero_mask, Op op, Epi epi) {
+    timed(c, name, [&] {
+        k2_fft_rows_fwd<NB><<<dim3(c->M1, NB), BLOCK, 0, c->stream>>>(src, zero_mask, c->Z, c->M1, c->M2, c->tw2);
+        k2_fft_cols<NB, Op><<<c->M2, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw1, op);
+        if (Op::INVERSE)
+            k2_fft_rows_inv<NB, Epi><<<dim3(c->M1, NB), BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw2,
+                                                                              1.0 / (double)c->Nc, epi);
+    });
+}
+
+int flags_status(ecpic2d_ctx *c) {
+    int f = 0;
+    if (hipMemcpyAsync(&f, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess) return ECPIC_EDEVICE;
+    int rc = sync2(c);
+    if (rc) return rc;
+    if (f & FLAG_NONFINITE) return ECPIC_ENONFINITE;
+    if (f & FLAG_CFL) return ECPIC_ECFL;
+    return ECPIC_OK;
+}
+
+double read_res(ecpic2d_ctx *c, int slot, int *rc) {
+    unsigned long long b = 0;
+    if (hipMemcpyAsync(&b, c->res + slot, sizeof(b), hipMemcpyDeviceToHost, c->stream) != hipSuccess) {
+        *rc = ECPIC_EDEVICE;
+        return 0.0;
+    }
+    *rc = sync2(c);
+    double v;
+    std::memcpy(&v, &b, sizeof(v));
+    return v;
+}
+
+#define LAUNCH_P(P, ...)                                      \
+    switch (P) {                                              \
+        case 2: { constexpr int PP = 2; __VA_ARGS__; } break; \
+        case 3: { constexpr int PP = 3; __VA_ARGS__; } break; \
+        case 4: { constexpr int PP = 4; __VA_ARGS__; } break; \
+        case 5: { constexpr int PP = 5; __VA_ARGS__; } break; \
+    }
+
+int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
+    const int A = c->cur, Nc = c->Nc, gN = grid_for(c->N), gC = grid_for(Nc);
+    hipStream_t s = c->stream;
+    k2_fill_u64<<<1, 2 * MAXK, 0, s>>>(c->res, 2 * MAXK);
+    k2_fill_i32<<<1, 1, 0, s>>>(c->flags, 1);
+    k2_grad<<<gC, BLOCK, 0, s>>>(c->az, c->g1a, c->g2a, c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->en1, c->e1, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->en2, c->e2, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->ek1, c->e1, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->ek2, c->e2, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->eb1, c->e1, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->eb2, c->e2, Nc);
+    k2_fill<<<gC, BLOCK, 0, s>>>(c->J1, Nc, 0.0);
+    k2_fill<<<gC, BLOCK, 0, s>>>(c->J2, Nc, 0.0);
+    int di = 0;
+    LAUNCH_P(c->P, k2_init_I<PP><<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->az, c->d1[0],
+                                                       c->d2[0], c->N, c->M1, c->M2, dt));
+    const Sym sy = sym_of(c);
+    double r = 0.0;
+    int k;
+    for (k = 0; k < c->kmax; ++k) {
+        SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
+                    c->pk1, c->pk2, c->start, c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
+                    c->res + k, c->flags, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
+        timed(c, "sweep_I", [&] { LAUNCH_P(c->P, k2_sweep_I<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
+        spectral<2>(c, "solve_I", Ptrs<2>{{c->J1, c->J2}}, 3, OpM1inv{sy},
+                    EpiI{c->en1, c->en2, c->ek1, c->ek2, c->eb1, c->eb2, c->res + MAXK + k});
+        unsigned long long b[2];
+        hipMemcpyAsync(&b[0], c->res + k, sizeof(b[0]), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(&b[1], c->res + MAXK + k, sizeof(b[1]), hipMemcpyDeviceToHost, s);
+        int rc = flags_status(c);
+        if (rc) return rc;
+        double rx, re;
+        std::memcpy(&rx, &b[0], sizeof(rx));
+        std::memcpy(&re, &b[1], sizeof(re));
+        r = std::max(rx, re);
+        if (r <= c->tol) break;
+        di = 1 - di;
+    }
+    if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
+    if (k == c->kmax) return ECPIC_ENOTCONV;
+    // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1), then re-sort
+    timed(c, "commit_I", [&] {
+        k2_commit_I<<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->pk1,
+                                         c->pk2, c->cell, c->count, c->N, c->M1, c->M2, 1.0 / c->dx1,
+                                         1.0 / c->dx2);
+    });
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->e1, c->ek1, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->e2, c->ek2, Nc);
+    sort_particles(c);
+    return sync2(c);
+}
+
+int substep_II(ecpic2d_ctx *c, double dt) {
+    const int A = c->cur;
+    timed(c, "rotate_II", [&] {
+        LAUNCH_P(c->P, k2_rotate_II<PP><<<grid_for(c->N), BLOCK, 0, c->stream>>>(
+                           c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->bz, c->az, c->N, c->M1, c->M2, dt));
+    });
+    return ECPIC_OK;
+}
+
+int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
+    const int A = c->cur, Nc = c->Nc, gC = grid_for(Nc);
+    hipStream_t s = c->stream;
+    k2_fill_u64<<<1, MAXK, 0, s>>>(c->res + 2 * MAXK, MAXK);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->ezn, c->ez, Nc);
+    k2_copy<<<gC, BLOCK, 0, s>>>(c->ezk, c->ez, Nc);
+    k2_fill<<<gC, BLOCK, 0, s>>>(c->S, Nc, 0.0);
+    const Sym sy = sym_of(c);
+    // constant part in Fourier space
+    spectral<2>(c, "solve_III", Ptrs<2>{{c->ezn, c->az}}, 0, OpIIIrhs{sy, c->R, c->M2, dt},
+                EpiStore<2>{Ptrs<2>{{nullptr, nullptr}}, nullptr});
+    double r = 0.0;
+    int k;
+    for (k = 0; k < c->kmax; ++k) {
+        DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->start, c->az, c->ezn, c->ezk, c->S,
+                  c->M1, c->M2, c->TW, dt, c->w, 1};
+        timed(c, "deposit_III", [&] { LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
+        spectral<1>(c, "solve_III", Ptrs<1>{{c->S}}, 1, OpIII{sy, c->R, c->M2, dt},
+                    EpiIII{c->ezk, c->res + 2 * MAXK + k});
+        int rc = 0;
+        r = read_res(c, 2 * MAXK + k, &rc);
+        if (rc) return rc;
+        if (!std::isfinite(r)) return ECPIC_ENONFINITE;
+        if (r <= c->tol) break;
+    }
+    if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
+    if (k == c->kmax) return ECPIC_ENOTCONV;
+    k2_finish_III<<<gC, BLOCK, 0, s>>>(c->az, c->ez, c->ezn, c->ezk, Nc, dt);
+    return ECPIC_OK;
+}
+
+int substep_IV(ecpic2d_ctx *c, double dt) {
+    spectral<3>(c, "maxwell_IV", Ptrs<3>{{c->e1, c->e2, c->bz}}, 0, OpIV{sym_of(c), dt},
+                EpiStore<3>{Ptrs<3>{{c->e1, c->e2, c->bz}}, nullptr});
+    return ECPIC_OK;
+}
+
+void deposit_rho(ecpic2d_ctx *c, double *rho) {
+    const int A = c->cur;
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(rho, c->Nc, 0.0);
+    DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->start, nullptr, nullptr, nullptr, rho,
+              c->M1, c->M2, c->TW, 0.0, c->w, 0};
+    LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(a));
+}
+
+MassRows rows_of(ecpic2d_ctx *c, int d1, int d2) {
+    MassRows m{};
+    const std::vector<double> &a = d1 == c->P ? c->m0row : c->m1row, &b = d2 == c->P ? c->m0row : c->m1row;
+    for (size_t i = 0; i < a.size(); ++i) m.r1[i] = a[i];
+    for (size_t i = 0; i < b.size(); ++i) m.r2[i] = b[i];
+    m.d1 = d1;
+    m.d2 = d2;
+    m.scale = c->dx1 * c->dx2;
+    return m;
+}
+
+// x^T Mass x for a grid (result left in partial[RED_BLOCKS + slot]).
+void quad(ecpic2d_ctx *c, const double *x, int d1, int d2, int slot) {
+    const int gC = std::min(grid_for(c->Nc), RED_BLOCKS);
+    k2_mass<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(x, c->tmp, c->M1, c->M2, rows_of(c, d1, d2));
+    k2_dot<<<gC, BLOCK, 0, c->stream>>>(x, c->tmp, c->Nc, c->partial);
+    k2_sum<<<1, BLOCK, 0, c->stream>>>(c->partial, gC, c->partial + RED_BLOCKS + slot);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
+    if (!cfg || !out) return ECPIC_EINVAL;
+    *out = nullptr;
+    const ecpic2d_config g = *cfg;
+    auto pow2 = [](int m) { return m >= 8 && m <= MAXM && (m & (m - 1)) == 0; };
+    const double dx1 = g.L1 / g.M1, dx2 = g.L2 / g.M2;
+    if (!(g.L1 > 0) || !(g.L2 > 0) || !pow2(g.M1) || !pow2(g.M2) || g.degree < 2 || g.degree > 5 ||
+        g.n_particles < 0 || g.n_particles > INT32_MAX || !(g.picard_tol > 0) || g.picard_max_iter < 0 ||
+        g.picard_max_iter > MAXK || !(g.dt > 0) || !(g.dt < std::min(dx1, dx2)) || g.weight < 0 ||
+        !std::isfinite(g.weight) || g.reserved != 0)
+        return ECPIC_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return ECPIC_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, g.device) != hipSuccess) return ECPIC_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return ECPIC_EDEVICE;
+    if (hipSetDevice(g.device) != hipSuccess) return ECPIC_EDEVICE;
+    ecpic2d_ctx *c = new ecpic2d_ctx();
+    c->cfg = g;
+    c->device = g.device;
+    c->P = g.degree;
+    c->M1 = g.M1;
+    c->M2 = g.M2;
+    c->Nc = g.M1 * g.M2;
+    c->TW = std::min(TWMAX, g.M2);
+    c->kmax = g.picard_max_iter ? g.picard_max_iter : 50;
+    c->N = g.n_particles;
+    c->dx1 = dx1;
+    c->dx2 = dx2;
+    c->w = g.weight > 0 ? g.weight : (c->N > 0 ? g.L1 * g.L2 / (double)c->N : 0.0);
+    c->tol = g.picard_tol;
+    c->m0row = mass_row2(c->P);
+    c->m1row = mass_row2(c->P - 1);
+    if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return ECPIC_EDEVICE; }
+    const size_t N = (size_t)c->N, Nc = (size_t)c->Nc;
+    int rc = 0;
+    for (int b = 0; b < 2; ++b) {
+        rc |= dalloc(c, &c->xi1[b], N) | dalloc(c, &c->xi2[b], N) | dalloc(c, &c->p1[b], N) |
+              dalloc(c, &c->p2[b], N) | dalloc(c, &c->id[b], N) | dalloc(c, &c->d1[b], N) |
+              dalloc(c, &c->d2[b], N);
+    }
+    rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->count, Nc) |
+          dalloc(c, &c->start, Nc + 1);
+    double **grids[] = {&c->e1, &c->e2, &c->bz, &c->ez, &c->az, &c->en1, &c->en2, &c->ek1, &c->ek2, &c->eb1,
+                        &c->eb2, &c->J1, &c->J2, &c->g1a, &c->g2a, &c->ezn, &c->ezk, &c->S, &c->tmp};
+    for (double **gp : grids) rc |= dalloc(c, gp, Nc);
+    rc |= dalloc(c, &c->Z, 3 * Nc) | dalloc(c, &c->R, Nc) | dalloc(c, &c->tw1, (size_t)c->M1 / 2) |
+          dalloc(c, &c->tw2, (size_t)c->M2 / 2) | dalloc(c, &c->sym, 4 * (size_t)(c->M1 + c->M2)) |
+          dalloc(c, &c->partial, RED_BLOCKS + 16) | dalloc(c, &c->res, 3 * MAXK + 4) | dalloc(c, &c->flags, 1);
+    if (rc) { ecpic2d_destroy(c); return ECPIC_ENOMEM; }
+    // twiddles and 1D symbols (host, long double)
+    const long double PI = 3.14159265358979323846264338327950288L;
+    std::vector<double2> t1(c->M1 / 2), t2(c->M2 / 2);
+    for (int j = 0; j < c->M1 / 2; ++j)
+        t1[j] = make_double2((double)cosl(2 * PI * j / c->M1), (double)-sinl(2 * PI * j / c->M1));
+    for (int j = 0; j < c->M2 / 2; ++j)
+        t2[j] = make_double2((double)cosl(2 * PI * j / c->M2), (double)-sinl(2 * PI * j / c->M2));
+    std::vector<double> sy(4 * (size_t)(c->M1 + c->M2));
+    auto fill_dir = [&](int M, double dx, double *m0, double *m1, double *cr, double *ci) {
+        const int p = c->P;
+        for (int k = 0; k < M; ++k) {
+            const long double th = 2 * PI * k / M;
+            long double s0 = 0, s1 = 0;
+            for (int q = -p; q <= p; ++q) s0 += (long double)c->m0row[q + p] * cosl(q * th);
+            for (int q = -(p - 1); q <= p - 1; ++q) s1 += (long double)c->m1row[q + p - 1] * cosl(q * th);
+            m0[k] = (double)(s0 * dx);
+            m1[k] = (double)(s1 * dx);
+            cr[k] = (double)((1 - cosl(th)) / dx);
+            ci[k] = (double)(sinl(th) / dx);
+        }
+    };
+    const int M1 = c->M1, M2 = c->M2;
+    fill_dir(M1, dx1, &sy[0], &sy[M1], &sy[2 * M1], &sy[3 * M1]);
+    fill_dir(M2, dx2, &sy[4 * M1], &sy[4 * M1 + M2], &sy[4 * M1 + 2 * M2], &sy[4 * M1 + 3 * M2]);
+    bool ok = hipMemcpy(c->tw1, t1.data(), sizeof(double2) * t1.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->tw2, t2.data(), sizeof(double2) * t2.size(), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->sym, sy.data(), sizeof(double) * sy.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) { ecpic2d_destroy(c); return ECPIC_EDEVICE; }
+    for (double **gp : grids) k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(*gp, c->Nc, 0.0);
+    k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->count, c->Nc);
+    k2_fill_i32<<<1, 1, 0, c->stream>>>(c->flags, 1);
+    if (sync2(c)) { ecpic2d_destroy(c); return ECPIC_EDEVICE; }
+    *out = c;
+    return ECPIC_OK;
+}
+
+int ecpic2d_destroy(ecpic2d_ctx *c) {
+    if (!c) return ECPIC_OK;
+    hipSetDevice(c->device);
+    if (c->stream) hipStreamSynchronize(c->stream);
+    for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
+    for (void *p : c->allocs) hipFree(p);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+    return ECPIC_OK;
+}
+
+int ecpic2d_set_particles(ecpic2d_ctx *c, const double *x1, const double *x2, const double *p1, const double *p2,
+                          int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x1 || !x2 || !p1 || !p2))) return ECPIC_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(x1[i]) || !std::isfinite(x2[i]) || !std::isfinite(p1[i]) || !std::isfinite(p2[i]))
+            return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    const int B = 1 - c->cur, A = c->cur;
+    const size_t bytes = sizeof(double) * (size_t)n;
+    hipStream_t s = c->stream;
+    // raw positions into the B buffers, momenta into A (scatter moves A -> B)
+    if (n > 0) {
+        if (hipMemcpyAsync(c->d1[0], x1, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(c->d2[0], x2, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(c->p1[A], p1, bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(c->p2[A], p2, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+            return ECPIC_EDEVICE;
+    }
+    (void)B;
+    k2_fill_i32<<<1, 1, 0, s>>>(c->flags, 1);
+    k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->count, c->Nc);
+    k2_iota<<<grid_for(n), BLOCK, 0, s>>>(c->id[A], n);
+    k2_bin_new<<<grid_for(n), BLOCK, 0, s>>>(c->d1[0], c->d2[0], c->xi1[A], c->xi2[A], c->cell, c->count, n,
+                                             c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2, c->flags);
+    sort_particles(c);
+    int rc = flags_status(c);
+    if (rc) return rc == ECPIC_ENONFINITE ? ECPIC_EINVAL : rc;
+    c->have_particles = true;
+    return ECPIC_OK;
+}
+
+int ecpic2d_get_particles(ecpic2d_ctx *c, double *x1, double *x2, double *p1, double *p2, int64_t n) {
+    if (!c || n != c->N || (n > 0 && (!x1 || !x2 || !p1 || !p2))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int A = c->cur;
+    const size_t bytes = sizeof(double) * (size_t)n;
+    double *outs[4] = {x1, x2, p1, p2};
+    const double *srcs[4] = {c->xi1[A], c->xi2[A], c->p1[A], c->p2[A]};
+    const double scales[4] = {c->dx1, c->dx2, 1.0, 1.0};
+    for (int q = 0; q < 4; ++q) {
+        if (n == 0) break;
+        k2_unsort<<<grid_for(n), BLOCK, 0, c->stream>>>(srcs[q], c->id[A], c->pk1, n, scales[q]);
+        if (hipMemcpyAsync(outs[q], c->pk1, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            return ECPIC_EDEVICE;
+        int rc = sync2(c);
+        if (rc) return rc;
+    }
+    return sync2(c);
+}
+
+int ecpic2d_set_fields(ecpic2d_ctx *c, const double *e1, const double *e2, const double *bz, const double *ez,
+                       const double *az) {
+    if (!c) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    const double *src[5] = {e1, e2, bz, ez, az};
+    double *dst[5] = {c->e1, c->e2, c->bz, c->ez, c->az};
+    for (int q = 0; q < 5; ++q) {
+        if (src[q]) {
+            if (hipMemcpyAsync(dst[q], src[q], sizeof(double) * c->Nc, hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess)
+                return ECPIC_EDEVICE;
+        } else {
+            k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(dst[q], c->Nc, 0.0);
+        }
+    }
+    return sync2(c);
+}
+
+int ecpic2d_get_fields(ecpic2d_ctx *c, double *e1, double *e2, double *bz, double *ez, double *az) {
+    if (!c) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    double *dst[5] = {e1, e2, bz, ez, az};
+    const double *src[5] = {c->e1, c->e2, c->bz, c->ez, c->az};
+    for (int q = 0; q < 5; ++q)
+        if (dst[q] &&
+            hipMemcpyAsync(dst[q], src[q], sizeof(double) * c->Nc, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            return ECPIC_EDEVICE;
+    return sync2(c);
+}
+
+int ecpic2d_solve_gauss(ecpic2d_ctx *c) {
+    if (!c) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    deposit_rho(c, c->S);
+    spectral<3>(c, "poisson", Ptrs<3>{{c->e1, c->e2, c->S}}, 4, OpPoisson{sym_of(c)},
+                EpiStore<3>{Ptrs<3>{{c->e1, c->e2, c->S}}, nullptr});
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->S, c->Nc, 0.0);
+    return sync2(c);
+}
+
+int ecpic2d_substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
+    if (!c || !(dt > 0) || !(dt < std::min(c->dx1, c->dx2))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    return substep_I(c, dt, st);
+}
+
+int ecpic2d_substep_II(ecpic2d_ctx *c, double dt) {
+    if (!c || !std::isfinite(dt)) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    substep_II(c, dt);
+    return sync2(c);
+}
+
+int ecpic2d_substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
+    if (!c || !(dt > 0) || !std::isfinite(dt)) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    int rc = substep_III(c, dt, st);
+    if (rc) return rc;
+    return sync2(c);
+}
+
+int ecpic2d_substep_IV(ecpic2d_ctx *c, double dt) {
+    if (!c || !std::isfinite(dt)) return ECPIC_EINVAL;
+    hipSetDevice(c->device);
+    substep_IV(c, dt);
+    return sync2(c);
+}
+
+int ecpic2d_step(ecpic2d_ctx *c, int32_t nsteps, int32_t *sweeps_I, int32_t *iters_III) {
+    if (!c || nsteps < 0) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const double dt = c->cfg.dt;
+    for (int s = 0; s < nsteps; ++s) {
+        ecpic2d_iter_stats a{}, b{};
+        int rc = substep_I(c, dt, &a);
+        if (sweeps_I) sweeps_I[s] = a.sweeps;
+        if (rc) return rc;
+        substep_II(c, dt);
+        rc = substep_III(c, dt, &b);
+        if (iters_III) iters_III[s] = b.sweeps;
+        if (rc) return rc;
+        substep_IV(c, dt);
+    }
+    return sync2(c);
+}
+
+int ecpic2d_energy(ecpic2d_ctx *c, ecpic2d_energy_parts *out) {
+    if (!c || !out) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int A = c->cur, P = c->P;
+    hipStream_t s = c->stream;
+    const int gN = std::min(grid_for(c->N), RED_BLOCKS);
+    k2_fill<<<1, BLOCK, 0, s>>>(c->partial, RED_BLOCKS + 16, 0.0);
+    LAUNCH_P(P, k2_kinetic<PP><<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->az, c->N, c->M1,
+                                                     c->M2, c->w, c->partial));
+    k2_sum<<<1, BLOCK, 0, s>>>(c->partial, gN, c->partial + RED_BLOCKS + 0);
+    quad(c, c->e1, P - 1, P, 1);
+    quad(c, c->e2, P, P - 1, 2);
+    quad(c, c->bz, P - 1, P - 1, 3);
+    quad(c, c->ez, P, P, 4);
+    k2_grad<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->az, c->g1a, c->g2a, c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2);
+    quad(c, c->g1a, P - 1, P, 5);
+    quad(c, c->g2a, P, P - 1, 6);
+    double v[7];
+    if (hipMemcpyAsync(v, c->partial + RED_BLOCKS, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return ECPIC_EDEVICE;
+    int rc = sync2(c);
+    if (rc) return rc;
+    out->kinetic = v[0];
+    out->e_xy = 0.5 * (v[1] + v[2]);
+    out->b_z = 0.5 * v[3];
+    out->e_z = 0.5 * v[4];
+    out->a_z = 0.5 * (v[5] + v[6]);
+    out->total = out->kinetic + out->e_xy + out->b_z + out->e_z + out->a_z;
+    return ECPIC_OK;
+}
+
+int ecpic2d_deposit_charge(ecpic2d_ctx *c, double *rho) {
+    if (!c || !rho) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    deposit_rho(c, c->S);
+    if (hipMemcpyAsync(rho, c->S, sizeof(double) * c->Nc, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        return ECPIC_EDEVICE;
+    int rc = sync2(c);
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->S, c->Nc, 0.0);
+    return rc ? rc : sync2(c);
+}
+
+int ecpic2d_gauss_residual(ecpic2d_ctx *c, double *linf, double *vec) {
+    if (!c || !linf) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    hipStream_t s = c->stream;
+    const int P = c->P;
+    deposit_rho(c, c->S);
+    k2_mass<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->e1, c->J1, c->M1, c->M2, rows_of(c, P - 1, P));
+    k2_mass<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->e2, c->J2, c->M1, c->M2, rows_of(c, P, P - 1));
+    k2_fill_u64<<<1, 1, 0, s>>>(c->res + 3 * MAXK, 1);
+    k2_gauss<<<std::min(grid_for(c->Nc), RED_BLOCKS), BLOCK, 0, s>>>(c->J1, c->J2, c->S, c->tmp, c->M1, c->M2,
+                                                                     1.0 / c->dx1, 1.0 / c->dx2, c->dx1 * c->dx2,
+                                                                     c->res + 3 * MAXK);
+    int rc = 0;
+    *linf = read_res(c, 3 * MAXK, &rc);
+    if (!rc && vec &&
+        hipMemcpyAsync(vec, c->tmp, sizeof(double) * c->Nc, hipMemcpyDeviceToHost, s) != hipSuccess)
+        rc = ECPIC_EDEVICE;
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->S, c->Nc, 0.0);
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->J1, c->Nc, 0.0);
+    k2_fill<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->J2, c->Nc, 0.0);
+    int rc2 = sync2(c);
+    return rc ? rc : rc2;
+}
+
+int ecpic2d_profile_enable(ecpic2d_ctx *c, int32_t enable) {
+    if (!c) return ECPIC_EINVAL;
+    sync2(c);
+    c->prof.on = enable != 0;
+    if (c->prof.on) c->prof.acc.clear();
+    return ECPIC_OK;
+}
+
+int ecpic2d_kernel_time(ecpic2d_ctx *c, const char *name, double *ms, int64_t *launches) {
+    if (!c || !name || !ms || !launches) return ECPIC_EINVAL;
+    sync2(c);
+    auto it = c->prof.acc.find(name);
+    *ms = it == c->prof.acc.end() ? 0.0 : it->second.first;
+    *launches = it == c->prof.acc.end() ? 0 : it->second.second;
+    return ECPIC_OK;
+}
+
+}  // extern "C"

@@ -9,24 +9,39 @@ import paper_2203_06513_amd as ec
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ecpic.h")
+HEADER2D = os.path.join(ROOT, "include", "ecpic2d.h")
 
 
-def declared_symbols():
-    text = open(HEADER).read()
+def declared_symbols(header=HEADER, prefix="ecpic_"):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(ecpic_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_0-9A-Z]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():
     assert declared_symbols() == sorted(ec.EXPORTS)
+    assert declared_symbols(HEADER2D, "ecpic2d_") == sorted(ec.EXPORTS_2D)
 
 
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(ec.LIB_PATH):
         pytest.fail("libecpic.so not built (run __graft_entry__.build())")
     lib = ctypes.CDLL(ec.LIB_PATH)
-    for name in declared_symbols():
+    for name in declared_symbols() + declared_symbols(HEADER2D, "ecpic2d_"):
         assert hasattr(lib, name), name
+
+
+def test_2d_invalid_config_without_device():
+    """2D configurations outside the documented ranges are rejected before any
+    device is touched."""
+    bad = [dict(M1=12), dict(M2=4), dict(M1=1024), dict(degree=1), dict(degree=6), dict(dt=0.8),
+           dict(tol=0.0), dict(n_particles=-1), dict(kmax=65), dict(L1=-1.0), dict(weight=float("nan"))]
+    for b in bad:
+        args = dict(L1=8.0, L2=8.0, M1=16, M2=16, degree=3, n_particles=10, dt=0.05, tol=1e-12)
+        args.update(b)
+        with pytest.raises(ec.EcpicError) as e:
+            ec.Context2D(**args)
+        assert e.value.status == -1, b
 
 
 def test_strerror_and_invalid_config_without_device():

@@ -1,0 +1,233 @@
+"""GPU parity of the 2D path (include/ecpic2d.h) against the 2D FP64 oracle.
+
+Every test calls the HIP library through the C-ABI binding and compares with the
+oracle on the same seeded inputs: element by element at sizes the oracle
+finishes in seconds (several tiles per row, both spline degrees the small
+workloads use, a rectangular grid), and at the 512 x 512, 2^24-particle size of
+the bench on sampled particles and on properties that hold at any size.
+
+Tolerances: both sides stop their fixed points at the same absolute tolerance
+(1e-13 small, 1e-12 large) on the same maps, so states agree to a few times the
+tolerance; the linear substeps (II, IV) agree to rounding (1e-13 relative).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2203_06513_amd as ec
+from oracle.twod import Oracle2D, initial_state2d
+from workloads.twod import generate2d, get2d
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(name, n=None, **kw):
+    w = get2d(name)
+    if n is not None:
+        w = w.scaled(n_particles=n)
+    w = w.scaled(**kw) if kw else w
+    arr = generate2d(w)
+    o = Oracle2D.from_workload(w)
+    s = initial_state2d(o, arr)
+    ctx = ec.Context2D.from_workload(w)
+    ctx.load(arr)
+    return w, o, s, ctx
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300)
+
+
+def compare(w, g, s, bar):
+    """Max relative differences of every state array (positions modulo the period)."""
+    out = {}
+    for k, L in (("x1", w.L1), ("x2", w.L2)):
+        d = np.mod(g[k] - s[k] + L / 2, L) - L / 2
+        out[k] = np.abs(d).max() / L
+    for k in ("p1", "p2", "e", "bz", "ez", "az"):
+        out[k] = rel(g[k], s[k]) if np.abs(s[k]).max() > 0 else np.abs(g[k]).max()
+    bad = {k: v for k, v in out.items() if not v <= bar}
+    assert not bad, (bad, out)
+    return out
+
+
+@pytest.mark.parametrize("name", ["twod16", "twod8x16"])
+def test_gauss_solve_and_charge_match_oracle(name):
+    w, o, s, ctx = setup(name)
+    with ctx:
+        g = ctx.state()
+        assert rel(g["e"], s["e"]) < 1e-13
+        assert rel(ctx.deposit_charge(), o.deposit_charge(s)) < 1e-14
+        m, r = ctx.gauss_residual(vec=True)
+        assert m < 1e-13
+        mo, ro = o.gauss_residual(s, vec=True)
+        assert np.abs(r - ro).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["twod16", "twod8x16"])
+def test_substep_I_matches_oracle(name):
+    w, o, s, ctx = setup(name)
+    with ctx:
+        kg, rg = ctx.substep_I()
+        st, ko, ro = o.substep_I(s)
+        assert st == 0 and abs(kg - ko) <= 1, (kg, ko)
+        compare(w, ctx.state(), s, 1e-11)
+        assert ctx.gauss_residual() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["twod16", "twod8x16"])
+def test_substep_II_matches_oracle(name):
+    w, o, s, ctx = setup(name)
+    with ctx:
+        ctx.substep_II()
+        o.substep_II(s)
+        compare(w, ctx.state(), s, 1e-13)
+
+
+@pytest.mark.parametrize("name", ["twod16", "twod8x16"])
+def test_substep_III_matches_oracle(name):
+    w, o, s, ctx = setup(name)
+    with ctx:
+        kg, _ = ctx.substep_III()
+        st, ko, _ = o.substep_III(s)
+        assert st == 0 and abs(kg - ko) <= 1, (kg, ko)
+        compare(w, ctx.state(), s, 1e-12)
+
+
+@pytest.mark.parametrize("name", ["twod16", "twod8x16"])
+def test_substep_IV_matches_oracle(name):
+    w, o, s, ctx = setup(name)
+    with ctx:
+        ctx.substep_IV()
+        o.substep_IV(s)
+        compare(w, ctx.state(), s, 1e-13)
+        assert ctx.gauss_residual() < 1e-13
+
+
+def test_lie_steps_match_oracle_and_conserve():
+    w, o, s, ctx = setup("twod16", n=1500)
+    with ctx:
+        H0 = ctx.energy()
+        np.testing.assert_allclose(H0, o.energy(s), rtol=1e-13, atol=1e-15)
+        kg, kIIIg = ctx.step(3)
+        st, ko, kIIIo = o.step(s, 3)
+        assert st == 0
+        assert np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
+        compare(w, ctx.state(), s, 3e-11)
+        H1 = ctx.energy()
+        np.testing.assert_allclose(H1, o.energy(s), rtol=1e-11, atol=1e-14)
+        assert abs(H1[5] - H0[5]) <= 1e-12 * H0[5]
+        assert ctx.gauss_residual() < 1e-13
+
+
+def test_edge_positions_and_order():
+    """Particles on and just inside the domain boundary, negative and beyond-L
+    positions (wrapped), returned in input order."""
+    w = get2d("twod8x16").scaled(n_particles=8)
+    arr = generate2d(w)
+    eps = 1e-15
+    arr["x1"][:4] = [0.0, w.L1 - eps, -0.25 * w.L1, 1.5 * w.L1]
+    arr["x2"][:4] = [w.L2 - eps, 0.0, 2.25 * w.L2, -eps]
+    o = Oracle2D.from_workload(w)
+    wrapped = dict(arr)
+    wrapped["x1"] = np.mod(arr["x1"], w.L1)
+    wrapped["x2"] = np.mod(arr["x2"], w.L2)
+    s = initial_state2d(o, wrapped)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        g = ctx.get_particles()
+        for k, L in (("x1", w.L1), ("x2", w.L2)):
+            assert np.all((g[k] >= 0) & (g[k] < L))
+            d = np.mod(g[k] - s[k] + L / 2, L) - L / 2
+            assert np.abs(d).max() < 1e-12 * L
+        np.testing.assert_array_equal(g["p1"], arr["p1"])
+        ctx.substep_I()
+        o.substep_I(s)
+        compare(w, ctx.state(), s, 1e-11)
+
+
+def test_no_particles_and_rollback():
+    w = get2d("twod16")
+    arr = generate2d(w, n=0)
+    with ec.Context2D.from_workload(w, n=0) as ctx:
+        ctx.load(arr)
+        k, _ = ctx.substep_I()
+        assert k == 1
+        ctx.step(2)
+        # without particles nothing neutralises the background: r = -dx1 dx2 everywhere
+        m, r = ctx.gauss_residual(vec=True)
+        assert np.abs(r + w.dx1 * w.dx2).max() < 1e-13
+    w, o, s, ctx = setup("twod16", n=500)
+    ctx.close()
+    with ec.Context2D.from_workload(w, kmax=1) as ctx:
+        ctx.load(generate2d(w))
+        before = ctx.state()
+        with pytest.raises(ec.EcpicError) as e:
+            ctx.substep_I()
+        assert e.value.status == ec.ENOTCONV
+        after = ctx.state()
+        for k in before:
+            np.testing.assert_array_equal(after[k], before[k])
+        with pytest.raises(ec.EcpicError) as e:
+            ctx.substep_III()
+        assert e.value.status == ec.ENOTCONV
+        after = ctx.state()
+        for k in before:
+            np.testing.assert_array_equal(after[k], before[k])
+
+
+# --------------------------------------------------------------------------
+# Full size (512 x 512 cells, 2^24 particles): sampled particles and invariants
+# --------------------------------------------------------------------------
+
+def test_full_size_step_properties():
+    w = get2d("twod512")
+    arr = generate2d(w)
+    o = Oracle2D.from_workload(w)
+    rng = np.random.default_rng(3)
+    idx = rng.choice(w.n_particles, 64, replace=False)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        assert ctx.gauss_residual() < 1e-12
+        s0 = ctx.state()
+        H0 = ctx.energy()[5]
+        # Subsystem I: the committed state satisfies the scheme at sampled particles
+        k, r = ctx.substep_I()
+        s1 = ctx.state()
+        H1 = ctx.energy()[5]
+        assert abs(H1 - H0) <= 1e-12 * H0
+        assert ctx.gauss_residual() < 1e-12
+        ebar = 0.5 * (s0["e"] + s1["e"])
+        ga = o.G(s0["az"])
+        for a in idx:
+            x = (s0["x1"][a], s0["x2"][a])
+            d = [np.mod(s1[k_][a] - s0[k_][a] + L / 2, L) - L / 2 for k_, L in (("x1", w.L1), ("x2", w.L2))]
+            pn, dn = o.particle_map(x, (s0["p1"][a], s0["p2"][a]), d, ebar, s0["az"], ga)
+            assert abs(pn[0] - s1["p1"][a]) < 1e-10 and abs(pn[1] - s1["p2"][a]) < 1e-10
+            assert abs(dn[0] - d[0]) < 1e-10 and abs(dn[1] - d[1]) < 1e-10
+        # Subsystem II: sampled particles against the oracle's rotation of the same particles
+        ctx.substep_II()
+        s2 = ctx.state()
+        osub = Oracle2D.from_workload(w, n=len(idx))
+        sub = {"x1": s1["x1"][idx].copy(), "x2": s1["x2"][idx].copy(), "p1": s1["p1"][idx].copy(),
+               "p2": s1["p2"][idx].copy(), "bz": s1["bz"], "az": s1["az"]}
+        osub.substep_II(sub)
+        assert rel(s2["p1"][idx], sub["p1"]) < 1e-13 and rel(s2["p2"][idx], sub["p2"]) < 1e-13
+        H2 = ctx.energy()[5]
+        assert abs(H2 - H1) <= 1e-13 * H1
+        # Subsystem III: midpoint relation on the grid, energy
+        ctx.substep_III()
+        s3 = ctx.state()
+        np.testing.assert_allclose((s3["az"] - s2["az"]) / w.dt, -0.5 * (s2["ez"] + s3["ez"]), atol=1e-12)
+        H3 = ctx.energy()[5]
+        assert abs(H3 - H2) <= 1e-12 * H2
+        # Subsystem IV: energy, Gauss, reversibility
+        ctx.substep_IV()
+        H4 = ctx.energy()[5]
+        assert abs(H4 - H3) <= 1e-13 * H3
+        assert ctx.gauss_residual() < 1e-12
+        ctx.substep_IV(-w.dt)
+        s5 = ctx.state()
+        assert rel(s5["e"], s3["e"]) < 1e-12 and rel(s5["bz"], s3["bz"]) < 1e-12
+        assert k >= 2 and math.isfinite(r)
