@@ -19,9 +19,11 @@ object is the FP64 sweep of the plain form at stress16384.
 Two more studies ride along: the Subsystem I starting iterates side by side
 over 200 steps ("warm_start_ab": explicit, previous increment, network then
 FP64, network then FP32 and FP64; sweeps, residuals of the first FP64 sweeps,
-ms/step, drift), and the spin model ("spin": Lie-Trotter steps I, II, III on
+ms/step, drift), the spin model ("spin": Lie-Trotter steps I, II, III on
 spin4096, 1.6e7 particles with spins, per-kernel averages and HBM fractions of
-the particle passes).
+the particle passes), and the 2D model ("twod": Lie-Trotter steps I-IV on
+twod512, 512 x 512 cells and 2^24 particles, per-kernel times per step and HBM
+fractions of the particle passes).
 
 Prints ONE JSON line.  `value` is the throughput of the learned form on the
 headline workload (the whole hot path: network tables, predictor, FP32 and
@@ -247,6 +249,46 @@ def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
             "hbm_frac": {n: round(v, 4) for n, v in frac.items()}}
 
 
+# 2D model, per particle: a Subsystem I sweep reads x1, x2, p1, p2 and d^(k) (48 B) and
+# writes d^(k+1) and p^(k+1) (32 B); the commit reads x, p, d, p^(k+1) (64 B) and writes
+# x, p and the cell (36 B); the sort reads x, p, id, cell and writes x, p, id (60 B);
+# Subsystem II reads x, p and writes p (48 B); the III source reads x, p (32 B).
+TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 100.0, "sort": 60.0, "rotate_II": 48.0, "deposit_III": 32.0}
+TWOD_KERNELS = ("sweep_I", "solve_I", "commit_I", "sort", "rotate_II", "deposit_III", "solve_III", "maxwell_IV")
+
+
+def twod_run(ec, w, steps: int, warmup: int, profile_steps: int):
+    """Lie-Trotter steps I, II, III, IV of the 2D model on workload w: ms/step, sweeps,
+    energy drift, Gauss residual, per-kernel averages (HIP events on the library's
+    stream) and the HBM fractions of the particle passes."""
+    from workloads.twod import generate2d
+    arr = generate2d(w)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        del arr
+        ctx.step(warmup)
+        H0 = ctx.energy()[5]
+        t0 = time.perf_counter()
+        kI, kIII = ctx.step(steps)
+        elapsed = time.perf_counter() - t0
+        H1 = ctx.energy()[5]
+        gauss = ctx.gauss_residual()
+        ctx.profile(True)
+        kIp, kIIIp = ctx.step(profile_steps)
+        times = {n: ctx.kernel_time(n) for n in TWOD_KERNELS}
+        ctx.profile(False)
+    N = w.n_particles
+    us = {n: round(1e3 * ms / cnt, 2) for n, (ms, cnt) in times.items() if cnt}
+    frac = {n: round(N * b / (us[n] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for n, b in TWOD_BYTES.items() if n in us}
+    per_step = {n: round(1e3 * ms / profile_steps, 1) for n, (ms, cnt) in times.items() if cnt}
+    return {"config": f"{w.name}: {w.L1:.4g} x {w.L2:.4g}, {w.M1} x {w.M2} cells, degree {w.degree}, "
+                      f"{N} particles, dt={w.dt}, tol={w.tol}", "steps": steps,
+            "value": N * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
+            "mean_sweeps_I": float(np.mean(kI)), "mean_iters_III": float(np.mean(kIII)),
+            "rel_energy_drift": abs(H1 - H0) / abs(H0), "gauss_linf": gauss, "kernels_us": us,
+            "kernels_us_per_step": per_step, "profiled_sweeps": int(np.sum(kIp)), "hbm_frac": frac}
+
+
 def workloads_generate(w):
     import workloads
     return workloads.generate(w)
@@ -310,6 +352,8 @@ def main():
     ap.add_argument("--ab-steps", type=int, default=200)
     ap.add_argument("--spin", default="spin4096", help="spin workload (empty for none)")
     ap.add_argument("--spin-steps", type=int, default=20)
+    ap.add_argument("--twod", default="twod512", help="2D workload (empty for none)")
+    ap.add_argument("--twod-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -376,6 +420,15 @@ def main():
         print(f"bench: {args.spin} with spin {spin['ms_per_step']:.3f} ms/step, "
               f"HBM fractions {spin['hbm_frac']}", file=sys.stderr, flush=True)
 
+    # ---- the 2D model (Subsystems I-IV) ------------------------------------------
+    twod = None
+    if args.twod:
+        from workloads.twod import get2d
+        twod = twod_run(ec, get2d(args.twod), args.twod_steps, args.graded_warmup, args.graded_profile_steps)
+        print(f"bench: {args.twod} {twod['ms_per_step']:.3f} ms/step, {twod['mean_sweeps_I']:.2f} sweeps, "
+              f"kernels us/step {twod['kernels_us_per_step']}, HBM fractions {twod['hbm_frac']}",
+              file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel, the FP64 Subsystem I sweep of the plain form, on
     # the largest graded workload (else the headline one)
     if "stress16384" in graded:
@@ -424,6 +477,7 @@ def main():
         "graded": graded,
         "warm_start_ab": {"steps": args.ab_steps, "workloads": ab},
         "spin": spin,
+        "twod": twod,
         "kernels_plain": sp["kernels_us"],
         "kernels_learned": sl["kernels_us"],
     }
