@@ -35,16 +35,18 @@
 #include <vector>
 
 #include "../../include/ecpic2d.h"
+#include "common.hpp"
 #include "spline.hpp"
 
 namespace ecpic2d {
 
 using ecpic::basis_values;
 using ecpic::line_mean_v1;
+using ecpic::wave_sum_dpp;
 
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
-constexpr int TWMAX = 16;        // tile width (cells along x2)
+constexpr int TWMAX = 64;        // tile width (cells along x2)
 constexpr int MAXM = 512;        // largest grid size per direction (LDS of the transforms)
 constexpr int MAXK = 64;         // residual slots per substep (Picard cap)
 constexpr int FLAG_NONFINITE = 1, FLAG_CFL = 2;
@@ -94,6 +96,52 @@ __device__ __forceinline__ int tile_of_block() {
     const int b = blockIdx.x, n = gridDim.x;
     if (n % 8 != 0) return b;
     return (b % 8) * (n / 8) + b / 8;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+// Number of lanes below this one set in mask.
+__device__ __forceinline__ int rank_in(unsigned long long mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Lane-strided walk over a tile's particles: lane l of a wave owns the contiguous
+// run [l Q, (l+1) Q) of the tile (Q = ceil(count / 64)) and the block's waves
+// interleave within each run, so the lanes of one wave sit in different cells
+// (cells hold about count / TW particles each) and their LDS deposits rarely hit
+// the same address; the round count is uniform over the block.
+struct Stride {
+    int begin, end, Q, rounds;
+    __device__ Stride(int b, int e) : begin(b), end(e) {
+        Q = (e - b + WAVE - 1) / WAVE;
+        const int nw = blockDim.x / WAVE;
+        rounds = (Q + nw - 1) / nw;
+    }
+    // particle of this thread in round k (valid if < end)
+    __device__ int at(int k) const {
+        const int nw = blockDim.x / WAVE, j = k * nw + (int)(threadIdx.x / WAVE);
+        return j < Q ? begin + (int)(threadIdx.x & (WAVE - 1)) * Q + j : end;
+    }
+};
+
+// Slot of this lane in the range of its cell: one atomic per distinct cell of the
+// wave on cursor[c], ranks within the wave by mbcnt.  Every lane must execute this.
+__device__ __forceinline__ int claim_slot(int c, bool live, int32_t *cursor) {
+    const int lane = lane_id();
+    unsigned long long pend = __builtin_amdgcn_ballot_w64(live);
+    int slot = 0;
+    while (pend) {
+        const int lead = __builtin_ctzll(pend);
+        const int lc = __builtin_amdgcn_readlane(c, lead);
+        const bool mine = ((pend >> lane) & 1ull) && c == lc;
+        const unsigned long long mask = __builtin_amdgcn_ballot_w64(mine);
+        int b = 0;
+        if (lane == lead) b = atomicAdd(&cursor[lc], __builtin_popcountll(mask));
+        b = __builtin_amdgcn_readlane(b, lead);
+        if (mine) slot = b + rank_in(mask);
+        pend &= ~mask;
+    }
+    return slot;
 }
 
 // Gauss-Legendre rule with P points on [0, 1] (exact to degree 2P - 1, the degree
@@ -171,36 +219,41 @@ __global__ void k2_grad(const double *__restrict__ a, double *__restrict__ g1, d
 
 // Positions of new particles: wrap into [0, M) (cell units), record the cell and
 // count it.
-__global__ __launch_bounds__(BLOCK) void k2_bin_new(const double *__restrict__ x1, const double *__restrict__ x2, double *__restrict__ xi1,
-                           double *__restrict__ xi2, int32_t *__restrict__ cell, int32_t *__restrict__ count,
-                           int64_t n, int M1, int M2, double inv_dx1, double inv_dx2, int *flags) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double u1 = x1[i] * inv_dx1, u2 = x2[i] * inv_dx2;
-        if (!isfinite(u1) || !isfinite(u2)) { atomicOr(flags, FLAG_NONFINITE); u1 = 0.0; u2 = 0.0; }
-        u1 = fmod(u1, (double)M1);
-        u2 = fmod(u2, (double)M2);
-        if (u1 < 0.0) u1 += (double)M1;
-        if (u2 < 0.0) u2 += (double)M2;
-        if (u1 >= (double)M1) u1 = 0.0;
-        if (u2 >= (double)M2) u2 = 0.0;
-        xi1[i] = u1;
-        xi2[i] = u2;
-        const int c = (int)u1 * M2 + (int)u2;
-        cell[i] = c;
-        atomicAdd(&count[c], 1);
+__global__ __launch_bounds__(BLOCK) void k2_bin_new(const double *__restrict__ x1, const double *__restrict__ x2,
+                                                    double *__restrict__ xi1, double *__restrict__ xi2,
+                                                    int32_t *__restrict__ cell, int32_t *__restrict__ count, int64_t n,
+                                                    int M1, int M2, double inv_dx1, double inv_dx2, int *flags) {
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < n;
+        int c = 0;
+        if (live) {
+            double u1 = x1[i] * inv_dx1, u2 = x2[i] * inv_dx2;
+            if (!isfinite(u1) || !isfinite(u2)) { atomicOr(flags, FLAG_NONFINITE); u1 = 0.0; u2 = 0.0; }
+            u1 = fmod(u1, (double)M1);
+            u2 = fmod(u2, (double)M2);
+            if (u1 < 0.0) u1 += (double)M1;
+            if (u2 < 0.0) u2 += (double)M2;
+            if (u1 >= (double)M1) u1 = 0.0;
+            if (u2 >= (double)M2) u2 = 0.0;
+            xi1[i] = u1;
+            xi2[i] = u2;
+            c = (int)u1 * M2 + (int)u2;
+            cell[i] = c;
+        }
+        claim_slot(c, live, count);
     }
 }
 
-// Exclusive scan of count[0..Nc) into start[0..Nc] and count <- 0 (one block of
-// 1024 threads, each owning a contiguous run of cells).
-__global__ void k2_scan(int32_t *__restrict__ count, int32_t *__restrict__ start, int Nc) {
-    __shared__ int wsum[1024 / WAVE];
-    const int per = (Nc + blockDim.x - 1) / blockDim.x;
-    const int c0 = threadIdx.x * per;
-    int local = 0;
-    for (int c = c0; c < c0 + per && c < Nc; ++c) local += count[c];
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
-    int x = local;
+// Exclusive scan of count[0..Nc) into start[0..Nc], count <- 0, in three passes:
+// block sums (SCAN_TILE cells per block), a scan of the block sums (one block),
+// and the block-local scans plus their offsets.
+constexpr int SCAN_THREADS = 1024, SCAN_PER = 4, SCAN_TILE = SCAN_THREADS * SCAN_PER;
+
+__device__ __forceinline__ int block_exscan1024(int v, int *total) {
+    __shared__ int wsum[SCAN_THREADS / WAVE];
+    const int lane = lane_id(), wid = threadIdx.x / WAVE;
+    int x = v;
 #pragma unroll
     for (int o = 1; o < WAVE; o <<= 1) {
         const int y = __shfl_up(x, o, WAVE);
@@ -213,31 +266,72 @@ __global__ void k2_scan(int32_t *__restrict__ count, int32_t *__restrict__ start
         pre += w < wid ? wsum[w] : 0;
         tot += wsum[w];
     }
-    int off = pre + x - local;
-    for (int c = c0; c < c0 + per && c < Nc; ++c) {
-        const int k = count[c];
-        start[c] = off;
-        off += k;
-        count[c] = 0;
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k2_scan_sums(const int32_t *__restrict__ count, int32_t *bsum,
+                                                             int Nc) {
+    const int c0 = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER;
+    int v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) v += c0 + q < Nc ? count[c0 + q] : 0;
+    int tot;
+    block_exscan1024(v, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k2_scan_top(int32_t *bsum, int nb, int32_t *start_end) {
+    // nb <= SCAN_THREADS (Nc <= 512 * 512 = 64 tiles)
+    const int v = (int)threadIdx.x < nb ? bsum[threadIdx.x] : 0;
+    int tot;
+    const int pre = block_exscan1024(v, &tot);
+    if ((int)threadIdx.x < nb) bsum[threadIdx.x] = pre;
+    if (threadIdx.x == 0) *start_end = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k2_scan_apply(int32_t *__restrict__ count, int32_t *__restrict__ start,
+                                                              const int32_t *__restrict__ bsum, int Nc) {
+    const int c0 = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_PER;
+    int k[SCAN_PER], v = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q) {
+        k[q] = c0 + q < Nc ? count[c0 + q] : 0;
+        v += k[q];
     }
-    if (threadIdx.x == 0) start[Nc] = tot;
+    int tot;
+    int off = bsum[blockIdx.x] + block_exscan1024(v, &tot);
+#pragma unroll
+    for (int q = 0; q < SCAN_PER; ++q)
+        if (c0 + q < Nc) {
+            start[c0 + q] = off;
+            off += k[q];
+            count[c0 + q] = 0;
+        }
 }
 
 // Move every particle to its cell's range of the destination buffers.
 __global__ __launch_bounds__(BLOCK) void k2_scatter(const double *__restrict__ s1, const double *__restrict__ s2,
-                           const double *__restrict__ q1, const double *__restrict__ q2,
-                           const int32_t *__restrict__ sid, double *__restrict__ d1, double *__restrict__ d2,
-                           double *__restrict__ r1, double *__restrict__ r2, int32_t *__restrict__ did,
-                           const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
-                           int32_t *__restrict__ cursor, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int c = cell[i];
-        const int j = start[c] + atomicAdd(&cursor[c], 1);
-        d1[j] = s1[i];
-        d2[j] = s2[i];
-        r1[j] = q1[i];
-        r2[j] = q2[i];
-        did[j] = sid[i];
+                                                    const double *__restrict__ q1, const double *__restrict__ q2,
+                                                    const int32_t *__restrict__ sid, double *__restrict__ d1,
+                                                    double *__restrict__ d2, double *__restrict__ r1,
+                                                    double *__restrict__ r2, int32_t *__restrict__ did,
+                                                    const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
+                                                    int32_t *__restrict__ cursor, int64_t n) {
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < n;
+        const int c = live ? cell[i] : 0;
+        const int slot = claim_slot(c, live, cursor);
+        if (live) {
+            const int j = start[c] + slot;
+            d1[j] = s1[i];
+            d2[j] = s2[i];
+            r1[j] = q1[i];
+            r2[j] = q2[i];
+            did[j] = sid[i];
+        }
     }
 }
 
@@ -308,6 +402,46 @@ struct SweepArgs {
     double inv_dx1, inv_dx2, dt, w;
 };
 
+// Path means along the straight step of one V1 component: DA is the degree (P-1
+// or P) of the basis in x1, DB in x2; W[u][v] is the mean of the basis function
+// of index (mn1 - DA + u, mn2 - DB + v) over the path, summed piece by piece
+// (pieces between the grid-line crossings, P-point Gauss-Legendre on each).
+template <int P, int DA, int DB>
+__device__ __forceinline__ void path_means(double x1, double x2, double s1, double s2, int mn1, int mn2, double lo,
+                                           double hi, bool live, double (&W)[DA + 2][DB + 2]) {
+#pragma unroll
+    for (int u = 0; u < DA + 2; ++u)
+#pragma unroll
+        for (int v = 0; v < DB + 2; ++v) W[u][v] = 0.0;
+#pragma unroll 1
+    for (int piece = 0; piece < 3; ++piece) {
+        const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
+        const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
+        const double len = live ? sb - sa : 0.0;
+        if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
+        const double sm = 0.5 * (sa + sb);
+        const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
+        const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
+        const int o1 = k1 - mn1, o2 = k2 - mn2;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const double s = sa + len * GL<P>::x[q];
+            const double g = len * GL<P>::w[q];
+            double ba[DA + 1], bb[DB + 1], va[DA + 2], vb[DB + 2];
+            basis_values<DA>(x1 + s * s1 - k1, ba);
+            basis_values<DB>(x2 + s * s2 - k2, bb);
+            window<DA>(ba, o1, va);
+            window<DB>(bb, o2, vb);
+#pragma unroll
+            for (int u = 0; u < DA + 2; ++u) {
+                const double gu = g * va[u];
+#pragma unroll
+                for (int v = 0; v < DB + 2; ++v) W[u][v] += gu * vb[v];
+            }
+        }
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
@@ -332,8 +466,9 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
     double rmax = 0.0;
     int flags = 0;
-    for (int base = begin; base < end; base += blockDim.x) {
-        const int i = base + threadIdx.x;
+    const Stride st(begin, end);
+    for (int k = 0; k < st.rounds; ++k) {
+        const int i = st.at(k);
         const bool live = i < end;
         const int ii = live ? i : begin;
         const double x1 = a.xi1[ii], x2 = a.xi2[ii];
@@ -353,60 +488,44 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         const double bA = cb1 != ca1 ? ((double)max(ca1, cb1) - x1) / s1 : 1.0;
         const double bB = cb2 != ca2 ? ((double)max(ca2, cb2) - x2) / s2 : 1.0;
         const double lo = fmin(bA, bB), hi = fmax(bA, bB);
-        // path means of the V1 basis: W1 over rows mn1-(P-1).., cols mn2-P..; W2 over rows mn1-P.., cols mn2-(P-1)..
-        double W1[P + 1][P + 2], W2[P + 2][P + 1];
+        // component 1 (degree P-1 in x1, P in x2): mean field along the path, current of d^(k)
+        const int rW1 = mn1 - (P - 1) - R0, cW1 = mn2 - P - C0;
+        double E1 = 0.0;
+        {
+            double W[P + 1][P + 2];
+            path_means<P, P - 1, P>(x1, x2, s1, s2, mn1, mn2, lo, hi, live, W);
 #pragma unroll
-        for (int u = 0; u < P + 1; ++u)
+            for (int u = 0; u < P + 1; ++u)
 #pragma unroll
-            for (int v = 0; v < P + 2; ++v) { W1[u][v] = 0.0; W2[v][u] = 0.0; }
-#pragma unroll 1
-        for (int piece = 0; piece < 3; ++piece) {
-            const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
-            const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
-            const double len = live ? sb - sa : 0.0;
-            if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
-            const double sm = 0.5 * (sa + sb);
-            const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
-            const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
-            const int o1 = k1 - mn1, o2 = k2 - mn2;
+                for (int v = 0; v < P + 2; ++v) E1 += W[u][v] * sE1[(rW1 + u) * PC + cW1 + v];
+            if (live) {
+                const double j = a.w * D1;
 #pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const double s = sa + len * GL<P>::x[q];
-                const double g = len * GL<P>::w[q];
-                const double t1 = x1 + s * s1 - k1, t2 = x2 + s * s2 - k2;
-                double b0x[P + 1], b1x[P], b0y[P + 1], b1y[P];
-                basis_values<P>(t1, b0x);
-                basis_values<P - 1>(t1, b1x);
-                basis_values<P>(t2, b0y);
-                basis_values<P - 1>(t2, b1y);
-                double v0x[P + 2], v1x[P + 1], v0y[P + 2], v1y[P + 1];
-                window<P>(b0x, o1, v0x);
-                window<P - 1>(b1x, o1, v1x);
-                window<P>(b0y, o2, v0y);
-                window<P - 1>(b1y, o2, v1y);
+                for (int u = 0; u < P + 1; ++u)
 #pragma unroll
-                for (int u = 0; u < P + 1; ++u) {
-                    const double gx = g * v1x[u], gy = g * v1y[u];
-#pragma unroll
-                    for (int v = 0; v < P + 2; ++v) {
-                        W1[u][v] += gx * v0y[v];
-                        W2[v][u] += gy * v0x[v];
-                    }
-                }
+                    for (int v = 0; v < P + 2; ++v) atomicAdd(&sJ1[(rW1 + u) * PC + cW1 + v], j * W[u][v]);
             }
         }
-        // gathers: Ebar along the path, A at both ends, means of dA/dx2 (vertical leg
-        // at x1^n) and dA/dx1 (horizontal leg at x2^{n+1})
-        const int rW1 = mn1 - (P - 1) - R0, cW1 = mn2 - P - C0;
+        // component 2 (degree P in x1, P-1 in x2)
         const int rW2 = mn1 - P - R0, cW2 = mn2 - (P - 1) - C0;
-        double E1 = 0.0, E2 = 0.0;
+        double E2 = 0.0;
+        {
+            double W[P + 2][P + 1];
+            path_means<P, P, P - 1>(x1, x2, s1, s2, mn1, mn2, lo, hi, live, W);
 #pragma unroll
-        for (int u = 0; u < P + 1; ++u)
+            for (int u = 0; u < P + 2; ++u)
 #pragma unroll
-            for (int v = 0; v < P + 2; ++v) {
-                E1 += W1[u][v] * sE1[(rW1 + u) * PC + cW1 + v];
-                E2 += W2[v][u] * sE2[(rW2 + v) * PC + cW2 + u];
+                for (int v = 0; v < P + 1; ++v) E2 += W[u][v] * sE2[(rW2 + u) * PC + cW2 + v];
+            if (live) {
+                const double j = a.w * D2;
+#pragma unroll
+                for (int u = 0; u < P + 2; ++u)
+#pragma unroll
+                    for (int v = 0; v < P + 1; ++v) atomicAdd(&sJ2[(rW2 + u) * PC + cW2 + v], j * W[u][v]);
             }
+        }
+        // A at both ends, means of dA/dx2 (vertical leg at x1^n) and dA/dx1 (horizontal
+        // leg at x2^{n+1})
         double ba1[P + 1], ba2[P + 1], bb1[P + 1], bb2[P + 1];
         basis_values<P>(x1 - ca1, ba1);
         basis_values<P>(x2 - ca2, ba2);
@@ -457,15 +576,6 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
             a.pk1[i] = n1;
             a.pk2[i] = n2;
             rmax = fmax(rmax, fmax(fabs(e1 - D1), fabs(e2 - D2)));
-            // current of d^(k): w d times the path means of the V1 basis
-            const double j1 = a.w * D1, j2 = a.w * D2;
-#pragma unroll
-            for (int u = 0; u < P + 1; ++u)
-#pragma unroll
-                for (int v = 0; v < P + 2; ++v) {
-                    atomicAdd(&sJ1[(rW1 + u) * PC + cW1 + v], j1 * W1[u][v]);
-                    atomicAdd(&sJ2[(rW2 + v) * PC + cW2 + u], j2 * W2[v][u]);
-                }
         }
     }
     if (flags) atomicOr(a.flags, flags);
@@ -480,26 +590,32 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
 }
 
 // Commit x^n + d^(k), p^(k+1) and bin the particles by their new cells.
-__global__ __launch_bounds__(BLOCK) void k2_commit_I(double *__restrict__ xi1, double *__restrict__ xi2, double *__restrict__ p1,
-                            double *__restrict__ p2, const double *__restrict__ d1, const double *__restrict__ d2,
-                            const double *__restrict__ pk1, const double *__restrict__ pk2,
-                            int32_t *__restrict__ cell, int32_t *__restrict__ count, int64_t n, int M1, int M2,
-                            double inv_dx1, double inv_dx2) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
-        if (u1 < 0.0) u1 += (double)M1;
-        if (u1 >= (double)M1) u1 -= (double)M1;
-        if (u2 < 0.0) u2 += (double)M2;
-        if (u2 >= (double)M2) u2 -= (double)M2;
-        if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
-        if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
-        xi1[i] = u1;
-        xi2[i] = u2;
-        p1[i] = pk1[i];
-        p2[i] = pk2[i];
-        const int c = (int)u1 * M2 + (int)u2;
-        cell[i] = c;
-        atomicAdd(&count[c], 1);
+__global__ __launch_bounds__(BLOCK) void k2_commit_I(double *__restrict__ xi1, double *__restrict__ xi2,
+                                                     double *__restrict__ p1, double *__restrict__ p2,
+                                                     const double *__restrict__ d1, const double *__restrict__ d2,
+                                                     const double *__restrict__ pk1, const double *__restrict__ pk2,
+                                                     int32_t *__restrict__ cell, int32_t *__restrict__ count,
+                                                     int64_t n, int M1, int M2, double inv_dx1, double inv_dx2) {
+    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool live = i < n;
+        int c = 0;
+        if (live) {
+            double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
+            if (u1 < 0.0) u1 += (double)M1;
+            if (u1 >= (double)M1) u1 -= (double)M1;
+            if (u2 < 0.0) u2 += (double)M2;
+            if (u2 >= (double)M2) u2 -= (double)M2;
+            if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
+            if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
+            xi1[i] = u1;
+            xi2[i] = u2;
+            p1[i] = pk1[i];
+            p2[i] = pk2[i];
+            c = (int)u1 * M2 + (int)u2;
+            cell[i] = c;
+        }
+        claim_slot(c, live, count);
     }
 }
 
@@ -580,8 +696,12 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
     }
     __syncthreads();
     const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
-    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
-        const double u1 = a.xi1[i], u2 = a.xi2[i];
+    const Stride st(begin, end);
+    for (int k = 0; k < st.rounds; ++k) {
+        const int i = st.at(k);
+        const bool live = i < end;
+        const int ii = live ? i : begin;
+        const double u1 = a.xi1[ii], u2 = a.xi2[ii];
         const int c2 = (int)u2;
         double b1[P + 1], b2[P + 1];
         basis_values<P>(u1 - r, b1);
@@ -601,14 +721,16 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
                 An += b1[m1] * tn;
                 Ak += b1[m1] * tk;
             }
-            const double q1 = a.p1[i], q2 = a.p2[i], pp = 1.0 + q1 * q1 + q2 * q2;
+            const double q1 = a.p1[ii], q2 = a.p2[ii], pp = 1.0 + q1 * q1 + q2 * q2;
             q = a.w * (An + Ak) / (sqrt(pp + An * An) + sqrt(pp + Ak * Ak));
         }
+        if (live) {
 #pragma unroll
-        for (int m1 = 0; m1 <= P; ++m1) {
-            const double qb = q * b1[m1];
+            for (int m1 = 0; m1 <= P; ++m1) {
+                const double qb = q * b1[m1];
 #pragma unroll
-            for (int m2 = 0; m2 <= P; ++m2) atomicAdd(&sS[(r - m1 - R0) * PC + c2 - m2 - C0], qb * b2[m2]);
+                for (int m2 = 0; m2 <= P; ++m2) atomicAdd(&sS[(r - m1 - R0) * PC + c2 - m2 - C0], qb * b2[m2]);
+            }
         }
     }
     __syncthreads();
@@ -1013,7 +1135,7 @@ struct ecpic2d_ctx {
     double *xi1[2] = {}, *xi2[2] = {}, *p1[2] = {}, *p2[2] = {};
     int32_t *id[2] = {};
     double *d1[2] = {}, *d2[2] = {}, *pk1 = nullptr, *pk2 = nullptr;
-    int32_t *cell = nullptr, *count = nullptr, *start = nullptr;
+    int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *bsum = nullptr;
     double *e1 = nullptr, *e2 = nullptr, *bz = nullptr, *ez = nullptr, *az = nullptr;
     double *en1 = nullptr, *en2 = nullptr, *ek1 = nullptr, *ek2 = nullptr, *eb1 = nullptr, *eb2 = nullptr;
     double *J1 = nullptr, *J2 = nullptr, *g1a = nullptr, *g2a = nullptr, *ezn = nullptr, *ezk = nullptr,
@@ -1088,7 +1210,10 @@ int n_tiles(ecpic2d_ctx *c) { return c->M1 * (c->M2 / c->TW); }
 void sort_particles(ecpic2d_ctx *c) {
     const int A = c->cur, B = 1 - c->cur;
     timed(c, "sort", [&] {
-        k2_scan<<<1, 1024, 0, c->stream>>>(c->count, c->start, c->Nc);
+        const int nb = (c->Nc + SCAN_TILE - 1) / SCAN_TILE;
+        k2_scan_sums<<<nb, SCAN_THREADS, 0, c->stream>>>(c->count, c->bsum, c->Nc);
+        k2_scan_top<<<1, SCAN_THREADS, 0, c->stream>>>(c->bsum, nb, c->start + c->Nc);
+        k2_scan_apply<<<nb, SCAN_THREADS, 0, c->stream>>>(c->count, c->start, c->bsum, c->Nc);
         k2_scatter<<<grid_for(c->N), BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A],
                                                            c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
                                                            c->cell, c->start, c->count, c->N);
@@ -1311,7 +1436,8 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
               dalloc(c, &c->d2[b], N);
     }
     rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->count, Nc) |
-          dalloc(c, &c->start, Nc + 1);
+          dalloc(c, &c->start, Nc + 1) |
+          dalloc(c, &c->bsum, Nc / SCAN_TILE + 2);
     double **grids[] = {&c->e1, &c->e2, &c->bz, &c->ez, &c->az, &c->en1, &c->en2, &c->ek1, &c->ek2, &c->eb1,
                         &c->eb2, &c->J1, &c->J2, &c->g1a, &c->g2a, &c->ezn, &c->ezk, &c->S, &c->tmp};
     for (double **gp : grids) rc |= dalloc(c, gp, Nc);
