@@ -2,11 +2,15 @@
 // solves and the C ABI of include/ecpic2d.h.
 //
 // Data layout in HBM (one context):
-//   particles  SoA, sorted by cell c = floor(xi1) M2 + floor(xi2), double
-//              buffered: xi_k = x_k / dx_k in [0, M_k) (f64), p1, p2 (f64),
-//              id (i32, the index given at set_particles).  The Picard iterate
-//              d = x^{n+1} - x^n (physical units) and p^{k+1} live in more
-//              buffers.  start[c] is the first particle of cell c.
+//   particles  SoA, grouped by tile (TW cells of one row) in tile order, double
+//              buffered: xi_k = x_k / dx_k in [0, M_k) (f64), p1, p2 (f64), id
+//              (i32, the index given at set_particles).  Inside a tile the
+//              cell-sorted sequence is stored transposed (see tile_pos), so a
+//              coalesced read hands the lanes of a wave particles of different
+//              cells.  start[c] is where cell c's share of its tile begins in the
+//              sorted count (start[first cell of a tile] is the tile's offset).
+//              The Picard iterate d = x^{n+1} - x^n (physical units) and p^{k+1}
+//              live in more buffers.
 //   fields     row-major M1 x M2 coefficient grids, index i1 M2 + i2 (no halo;
 //              the tile kernels wrap indices while staging).
 //   spectra    M1 x M2 complex grids for the linear solves.
@@ -105,43 +109,38 @@ __device__ __forceinline__ int rank_in(unsigned long long mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// Lane-strided walk over a tile's particles: lane l of a wave owns the contiguous
-// run [l Q, (l+1) Q) of the tile (Q = ceil(count / 64)) and the block's waves
-// interleave within each run, so the lanes of one wave sit in different cells
-// (cells hold about count / TW particles each) and their LDS deposits rarely hit
-// the same address; the round count is uniform over the block.
-struct Stride {
-    int begin, end, Q, rounds;
-    __device__ Stride(int b, int e) : begin(b), end(e) {
-        Q = (e - b + WAVE - 1) / WAVE;
-        const int nw = blockDim.x / WAVE;
-        rounds = (Q + nw - 1) / nw;
-    }
-    // particle of this thread in round k (valid if < end)
-    __device__ int at(int k) const {
-        const int nw = blockDim.x / WAVE, j = k * nw + (int)(threadIdx.x / WAVE);
-        return j < Q ? begin + (int)(threadIdx.x & (WAVE - 1)) * Q + j : end;
-    }
-};
+// Walk over a tile's particles.  The sort stores each tile transposed: with
+// cnt = 64 Q + R particles, the particle of rank t = l Q + j (t < 64 Q) in the
+// cell-sorted order sits at position j 64 + l, the last R in order.  Reading
+// position j 64 + lane is then coalesced, while lane l works through the run of
+// ranks [l Q, (l+1) Q), so the lanes of one wave sit in different cells and
+// their LDS deposits rarely hit the same address.  Waves take j = wave, wave +
+// waves, ... while j 64 < cnt (the last pass holds the R remaining particles).
+__device__ __forceinline__ int tile_pos(int t, int cnt) {
+    const int Q = cnt / WAVE;
+    return t < WAVE * Q ? (t % Q) * WAVE + t / Q : t;
+}
 
-// Slot of this lane in the range of its cell: one atomic per distinct cell of the
-// wave on cursor[c], ranks within the wave by mbcnt.  Every lane must execute this.
+// Slot of this lane in the range of its cell, one atomic per run of equal
+// consecutive cells: the first lane of a run adds the run's length to
+// cursor[c] and hands the old value to the run (ds_bpermute).  Live lanes must be
+// a prefix of the wave; every lane must execute this.
 __device__ __forceinline__ int claim_slot(int c, bool live, int32_t *cursor) {
     const int lane = lane_id();
-    unsigned long long pend = __builtin_amdgcn_ballot_w64(live);
-    int slot = 0;
-    while (pend) {
-        const int lead = __builtin_ctzll(pend);
-        const int lc = __builtin_amdgcn_readlane(c, lead);
-        const bool mine = ((pend >> lane) & 1ull) && c == lc;
-        const unsigned long long mask = __builtin_amdgcn_ballot_w64(mine);
-        int b = 0;
-        if (lane == lead) b = atomicAdd(&cursor[lc], __builtin_popcountll(mask));
-        b = __builtin_amdgcn_readlane(b, lead);
-        if (mine) slot = b + rank_in(mask);
-        pend &= ~mask;
+    const int prev = __shfl_up(c, 1, WAVE);
+    const bool head = live && (lane == 0 || prev != c);
+    const unsigned long long heads = __builtin_amdgcn_ballot_w64(head);
+    const unsigned long long lives = __builtin_amdgcn_ballot_w64(live);
+    const unsigned long long upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1ull);   // lanes <= this one
+    const int leader = WAVE - 1 - __builtin_clzll((heads & upto) | 1ull);
+    int b = 0;
+    if (head) {
+        const unsigned long long later = (heads & ~upto) | ~lives;   // next head or first dead lane
+        const int next = later ? __builtin_ctzll(later) : WAVE;
+        b = atomicAdd(&cursor[c], next - lane);
     }
-    return slot;
+    b = __builtin_amdgcn_ds_bpermute(leader << 2, b);
+    return b + lane - leader;
 }
 
 // Gauss-Legendre rule with P points on [0, 1] (exact to degree 2P - 1, the degree
@@ -168,19 +167,6 @@ template <> struct GL<5> {
     static constexpr double w[5] = {0.11846344252809471, 0.2393143352496831, 0.2844444444444445,
                                     0.2393143352496831, 0.11846344252809471};
 };
-
-// Window vector of the degree-D splines alive at a point of cell m + o (o in
-// {0, 1}) over the D + 2 indices m - D .. m + 1: v[j] is the spline of index
-// m - D + j, B[k] the value of the spline of index (m + o) - k.
-template <int D>
-__device__ __forceinline__ void window(const double (&B)[D + 1], int o, double (&v)[D + 2]) {
-#pragma unroll
-    for (int j = 0; j < D + 2; ++j) {
-        const double lo = (j <= D) ? B[(D - j) < 0 ? 0 : (D - j)] : 0.0;           // o = 0: index m - D + j = m - k
-        const double hi = (j >= 1) ? B[(D + 1 - j) > D ? D : (D + 1 - j)] : 0.0;  // o = 1
-        v[j] = o ? hi : lo;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Small grid and particle kernels
@@ -318,14 +304,16 @@ __global__ __launch_bounds__(BLOCK) void k2_scatter(const double *__restrict__ s
                                                     double *__restrict__ d2, double *__restrict__ r1,
                                                     double *__restrict__ r2, int32_t *__restrict__ did,
                                                     const int32_t *__restrict__ cell, const int32_t *__restrict__ start,
-                                                    int32_t *__restrict__ cursor, int64_t n) {
+                                                    int32_t *__restrict__ cursor, int64_t n, int M2, int TW) {
     for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = base + threadIdx.x;
         const bool live = i < n;
         const int c = live ? cell[i] : 0;
         const int slot = claim_slot(c, live, cursor);
         if (live) {
-            const int j = start[c] + slot;
+            const int r = c / M2, first = r * M2 + ((c - r * M2) / TW) * TW;   // tile's first cell
+            const int tb = start[first], cnt = start[first + TW] - tb;
+            const int j = tb + tile_pos(start[c] - tb + slot, cnt);
             d1[j] = s1[i];
             d2[j] = s2[i];
             r1[j] = q1[i];
@@ -402,41 +390,36 @@ struct SweepArgs {
     double inv_dx1, inv_dx2, dt, w;
 };
 
-// Path means along the straight step of one V1 component: DA is the degree (P-1
-// or P) of the basis in x1, DB in x2; W[u][v] is the mean of the basis function
-// of index (mn1 - DA + u, mn2 - DB + v) over the path, summed piece by piece
-// (pieces between the grid-line crossings, P-point Gauss-Legendre on each).
-template <int P, int DA, int DB>
-__device__ __forceinline__ void path_means(double x1, double x2, double s1, double s2, int mn1, int mn2, double lo,
-                                           double hi, bool live, double (&W)[DA + 2][DB + 2]) {
+// Path integrals of the V1 basis on one piece of the straight step (between two
+// grid-line crossings, inside cell (k1, k2)), both components, by the P-point
+// Gauss-Legendre rule in the piece's own frame: W1[u][v] is the integral over
+// the piece (parameter length len) of N^{P-1}_{k1-(P-1)+u}(x1) N^P_{k2-P+v}(x2),
+// W2[u][v] that of N^P_{k1-P+u}(x1) N^{P-1}_{k2-(P-1)+v}(x2).
+template <int P>
+__device__ __forceinline__ void piece_integrals(double x1, double x2, double s1, double s2, int k1, int k2,
+                                                double sa, double len, double (&W1)[P][P + 1],
+                                                double (&W2)[P + 1][P]) {
 #pragma unroll
-    for (int u = 0; u < DA + 2; ++u)
+    for (int u = 0; u < P; ++u)
 #pragma unroll
-        for (int v = 0; v < DB + 2; ++v) W[u][v] = 0.0;
-#pragma unroll 1
-    for (int piece = 0; piece < 3; ++piece) {
-        const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
-        const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
-        const double len = live ? sb - sa : 0.0;
-        if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
-        const double sm = 0.5 * (sa + sb);
-        const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
-        const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
-        const int o1 = k1 - mn1, o2 = k2 - mn2;
+        for (int v = 0; v < P + 1; ++v) { W1[u][v] = 0.0; W2[v][u] = 0.0; }
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-            const double s = sa + len * GL<P>::x[q];
-            const double g = len * GL<P>::w[q];
-            double ba[DA + 1], bb[DB + 1], va[DA + 2], vb[DB + 2];
-            basis_values<DA>(x1 + s * s1 - k1, ba);
-            basis_values<DB>(x2 + s * s2 - k2, bb);
-            window<DA>(ba, o1, va);
-            window<DB>(bb, o2, vb);
+    for (int q = 0; q < P; ++q) {
+        const double s = sa + len * GL<P>::x[q];
+        const double g = len * GL<P>::w[q];
+        const double t1 = x1 + s * s1 - k1, t2 = x2 + s * s2 - k2;
+        double b0x[P + 1], b1x[P], b0y[P + 1], b1y[P];
+        basis_values<P>(t1, b0x);       // b0x[m]: N^P_{k1-m}
+        basis_values<P - 1>(t1, b1x);   // b1x[m]: N^{P-1}_{k1-m}
+        basis_values<P>(t2, b0y);
+        basis_values<P - 1>(t2, b1y);
 #pragma unroll
-            for (int u = 0; u < DA + 2; ++u) {
-                const double gu = g * va[u];
+        for (int u = 0; u < P; ++u) {
+            const double gx = g * b1x[P - 1 - u], gy = g * b1y[P - 1 - u];
 #pragma unroll
-                for (int v = 0; v < DB + 2; ++v) W[u][v] += gu * vb[v];
+            for (int v = 0; v < P + 1; ++v) {
+                W1[u][v] += gx * b0y[P - v];
+                W2[v][u] += gy * b0x[P - v];
             }
         }
     }
@@ -466,9 +449,9 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
     double rmax = 0.0;
     int flags = 0;
-    const Stride st(begin, end);
-    for (int k = 0; k < st.rounds; ++k) {
-        const int i = st.at(k);
+    const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
+    for (int jr = threadIdx.x / WAVE; jr < passes; jr += nw) {
+        const int i = begin + jr * WAVE + lane_id();
         const bool live = i < end;
         const int ii = live ? i : begin;
         const double x1 = a.xi1[ii], x2 = a.xi2[ii];
@@ -479,7 +462,7 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         const int ca1 = r, ca2 = (int)x2;
         int cb1 = (int)floor(y1), cb2 = (int)floor(y2);
         if (cb1 < ca1 - 1 || cb1 > ca1 + 1 || cb2 < ca2 - 1 || cb2 > ca2 + 1 || !isfinite(s1 + s2)) {
-            flags |= isfinite(s1 + s2) ? FLAG_CFL : FLAG_NONFINITE;
+            if (live) flags |= isfinite(s1 + s2) ? FLAG_CFL : FLAG_NONFINITE;
             cb1 = ca1;
             cb2 = ca2;
         }
@@ -488,40 +471,38 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         const double bA = cb1 != ca1 ? ((double)max(ca1, cb1) - x1) / s1 : 1.0;
         const double bB = cb2 != ca2 ? ((double)max(ca2, cb2) - x2) / s2 : 1.0;
         const double lo = fmin(bA, bB), hi = fmax(bA, bB);
-        // component 1 (degree P-1 in x1, P in x2): mean field along the path, current of d^(k)
-        const int rW1 = mn1 - (P - 1) - R0, cW1 = mn2 - P - C0;
-        double E1 = 0.0;
-        {
-            double W[P + 1][P + 2];
-            path_means<P, P - 1, P>(x1, x2, s1, s2, mn1, mn2, lo, hi, live, W);
+        // mean field along the path and the current of d^(k), piece by piece in each
+        // piece's cell (pieces no lane of the wave needs are skipped)
+        double E1 = 0.0, E2 = 0.0;
+        const double j1 = a.w * D1, j2 = a.w * D2;
+#pragma unroll 1
+        for (int piece = 0; piece < 3; ++piece) {
+            const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
+            const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
+            const double len = live ? sb - sa : 0.0;
+            if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
+            const double sm = 0.5 * (sa + sb);
+            const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
+            const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
+            double W1[P][P + 1], W2[P + 1][P];
+            piece_integrals<P>(x1, x2, s1, s2, k1, k2, sa, len, W1, W2);
+            const int o1 = (k1 - (P - 1) - R0) * PC + k2 - P - C0;   // W1[0][0] in the patch
+            const int o2 = (k1 - P - R0) * PC + k2 - (P - 1) - C0;   // W2[0][0]
 #pragma unroll
-            for (int u = 0; u < P + 1; ++u)
+            for (int u = 0; u < P; ++u)
 #pragma unroll
-                for (int v = 0; v < P + 2; ++v) E1 += W[u][v] * sE1[(rW1 + u) * PC + cW1 + v];
-            if (live) {
-                const double j = a.w * D1;
+                for (int v = 0; v < P + 1; ++v) {
+                    E1 += W1[u][v] * sE1[o1 + u * PC + v];
+                    E2 += W2[v][u] * sE2[o2 + v * PC + u];
+                }
+            if (len > 0.0) {
 #pragma unroll
-                for (int u = 0; u < P + 1; ++u)
+                for (int u = 0; u < P; ++u)
 #pragma unroll
-                    for (int v = 0; v < P + 2; ++v) atomicAdd(&sJ1[(rW1 + u) * PC + cW1 + v], j * W[u][v]);
-            }
-        }
-        // component 2 (degree P in x1, P-1 in x2)
-        const int rW2 = mn1 - P - R0, cW2 = mn2 - (P - 1) - C0;
-        double E2 = 0.0;
-        {
-            double W[P + 2][P + 1];
-            path_means<P, P, P - 1>(x1, x2, s1, s2, mn1, mn2, lo, hi, live, W);
-#pragma unroll
-            for (int u = 0; u < P + 2; ++u)
-#pragma unroll
-                for (int v = 0; v < P + 1; ++v) E2 += W[u][v] * sE2[(rW2 + u) * PC + cW2 + v];
-            if (live) {
-                const double j = a.w * D2;
-#pragma unroll
-                for (int u = 0; u < P + 2; ++u)
-#pragma unroll
-                    for (int v = 0; v < P + 1; ++v) atomicAdd(&sJ2[(rW2 + u) * PC + cW2 + v], j * W[u][v]);
+                    for (int v = 0; v < P + 1; ++v) {
+                        atomicAdd(&sJ1[o1 + u * PC + v], j1 * W1[u][v]);
+                        atomicAdd(&sJ2[o2 + v * PC + u], j2 * W2[v][u]);
+                    }
             }
         }
         // A at both ends, means of dA/dx2 (vertical leg at x1^n) and dA/dx1 (horizontal
@@ -696,9 +677,9 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
     }
     __syncthreads();
     const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
-    const Stride st(begin, end);
-    for (int k = 0; k < st.rounds; ++k) {
-        const int i = st.at(k);
+    const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
+    for (int jr = threadIdx.x / WAVE; jr < passes; jr += nw) {
+        const int i = begin + jr * WAVE + lane_id();
         const bool live = i < end;
         const int ii = live ? i : begin;
         const double u1 = a.xi1[ii], u2 = a.xi2[ii];
@@ -1216,7 +1197,7 @@ void sort_particles(ecpic2d_ctx *c) {
         k2_scan_apply<<<nb, SCAN_THREADS, 0, c->stream>>>(c->count, c->start, c->bsum, c->Nc);
         k2_scatter<<<grid_for(c->N), BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A],
                                                            c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
-                                                           c->cell, c->start, c->count, c->N);
+                                                           c->cell, c->start, c->count, c->N, c->M2, c->TW);
         k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->count, c->Nc);
     });
     c->cur = B;
