@@ -255,6 +255,45 @@ def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
 # Subsystem II reads x, p and writes p (48 B); the III source reads x, p (32 B).
 TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 100.0, "sort": 60.0, "rotate_II": 48.0, "deposit_III": 32.0}
 TWOD_KERNELS = ("sweep_I", "solve_I", "commit_I", "sort", "rotate_II", "deposit_III", "solve_III", "maxwell_IV")
+FP64_PEAK_TFLOPS = 78.6
+
+
+def twod_sweep_flops(P: int) -> float:
+    """Algorithmic FP64 operations (an FMA counts 2) per particle of one 2D Subsystem I
+    sweep, for a step that stays in its cell (one piece), degree P:
+      path integrals of both V1 components, P Gauss points, each: the degree P and
+        P-1 splines in both coordinates by Horner (2 P(P+1) + 2 P(P-1) FMA), two
+        outer products (2 P(P+1) FMA), the weights (2 P): 12 P^2 + 6 P per point;
+      mean field gather and current deposit: 2 P(P+1) FMA and 2 P(P+1) mul+add;
+      A_z at both ends: basis 4 P(P+1) FMA, contraction 2 (P+1)(P+2) FMA;
+      the two leg means of grad A_z: P^2 FMA for the piece means and (P+1)(P+2) +
+        (P+1) FMA for the contraction, each;
+      the push (three gammas, the update): 30."""
+    return (P * (12 * P * P + 6 * P) + 4 * P * (P + 1) + 4 * P * (P + 1) + 8 * P * (P + 1) + 4 * (P + 1) * (P + 2)
+            + 2 * (2 * P * P + 2 * (P + 1) * (P + 2) + 2 * (P + 1)) + 30)
+
+
+def twod_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("twod.hip", "spline.hpp", "common.hpp", "internal.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2203_06513_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def twod_traffic_from_profile(workload: str, n_particles: int):
+    """HBM bytes per 2D sweep launch from committed PMC counters taken from the current
+    2D kernel sources on this workload, else None."""
+    path = os.path.join(ROOT, "profiles", f"sweep_I_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    d = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            d[k.strip()] = v.strip()
+    if d.get("kernel_source_hash") != twod_source_hash() or int(d.get("n_particles", -1)) != n_particles:
+        return None
+    return float(d["bytes_per_launch"]) if "bytes_per_launch" in d else None
 
 
 def twod_run(ec, w, steps: int, warmup: int, profile_steps: int):
@@ -281,12 +320,23 @@ def twod_run(ec, w, steps: int, warmup: int, profile_steps: int):
     us = {n: round(1e3 * ms / cnt, 2) for n, (ms, cnt) in times.items() if cnt}
     frac = {n: round(N * b / (us[n] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for n, b in TWOD_BYTES.items() if n in us}
     per_step = {n: round(1e3 * ms / profile_steps, 1) for n, (ms, cnt) in times.items() if cnt}
+    roof = None
+    if "sweep_I" in us:
+        fl = twod_sweep_flops(w.degree)
+        achieved = N * fl / (us["sweep_I"] * 1e-6) / 1e12
+        traffic = twod_traffic_from_profile(w.name, N)
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": f"k2_sweep_I<{w.degree}> (2D Subsystem I Picard sweep)",
+                "algorithmic_flops_per_particle": fl, "avg_launch_us": us["sweep_I"],
+                "algorithmic_bytes_per_particle": TWOD_BYTES["sweep_I"], "hbm_frac": frac.get("sweep_I")}
     return {"config": f"{w.name}: {w.L1:.4g} x {w.L2:.4g}, {w.M1} x {w.M2} cells, degree {w.degree}, "
                       f"{N} particles, dt={w.dt}, tol={w.tol}", "steps": steps,
             "value": N * steps / elapsed, "ms_per_step": 1e3 * elapsed / steps,
             "mean_sweeps_I": float(np.mean(kI)), "mean_iters_III": float(np.mean(kIII)),
             "rel_energy_drift": abs(H1 - H0) / abs(H0), "gauss_linf": gauss, "kernels_us": us,
-            "kernels_us_per_step": per_step, "profiled_sweeps": int(np.sum(kIp)), "hbm_frac": frac}
+            "kernels_us_per_step": per_step, "profiled_sweeps": int(np.sum(kIp)), "hbm_frac": frac,
+            "roofline_sweep_I": roof}
 
 
 def workloads_generate(w):
