@@ -425,148 +425,229 @@ __device__ __forceinline__ void piece_integrals(double x1, double x2, double s1,
     }
 }
 
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
-    constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
-    __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
-    const int nseg = a.M2 / a.TW;
-    const int tile = tile_of_block();
-    const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
-    const int PC = a.TW + P + 2;
-    const int R0 = r - P - 1, C0 = c0 - P - 1;
-    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
-        const int i = t / PC, j = t - i * PC;
-        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
-        sE1[t] = a.eb1[g];
-        sE2[t] = a.eb2[g];
-        sA[t] = a.az[g];
-        sG1[t] = a.g1a[g];
-        sG2[t] = a.g2a[g];
-        sJ1[t] = 0.0;
-        sJ2[t] = 0.0;
+// The field patch of a tile in LDS (rows r-P-1 .. r+1, columns c0-P-1 .. c0+TW).
+struct Patch {
+    double *E1, *E2, *A, *G1, *G2, *J1, *J2;
+    int PC, R0, C0, r;
+};
+
+// One particle's step geometry (cell units): start x, increment s, end y, the
+// start/end cells, the lower-left cell of the step and the path parameters lo <=
+// hi of its grid-line crossings (1 when there is none).
+struct Geo {
+    double x1, x2, q1, q2, D1, D2, s1, s2, y1, y2, lo, hi;
+    int ca2, cb1, cb2, mn1, mn2;
+};
+
+__device__ __forceinline__ Geo geometry(const SweepArgs &a, int ii, bool live, int r, int &flags) {
+    Geo g;
+    g.x1 = a.xi1[ii];
+    g.x2 = a.xi2[ii];
+    g.q1 = a.p1[ii];
+    g.q2 = a.p2[ii];
+    g.D1 = live ? a.d1[ii] : 0.0;
+    g.D2 = live ? a.d2[ii] : 0.0;
+    g.s1 = g.D1 * a.inv_dx1;
+    g.s2 = g.D2 * a.inv_dx2;
+    g.y1 = g.x1 + g.s1;
+    g.y2 = g.x2 + g.s2;
+    const int ca1 = r;
+    g.ca2 = (int)g.x2;
+    g.cb1 = (int)floor(g.y1);
+    g.cb2 = (int)floor(g.y2);
+    if (g.cb1 < ca1 - 1 || g.cb1 > ca1 + 1 || g.cb2 < g.ca2 - 1 || g.cb2 > g.ca2 + 1 || !isfinite(g.s1 + g.s2)) {
+        if (live) flags |= isfinite(g.s1 + g.s2) ? FLAG_CFL : FLAG_NONFINITE;
+        g.cb1 = ca1;
+        g.cb2 = g.ca2;
     }
-    __syncthreads();
-    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
-    double rmax = 0.0;
-    int flags = 0;
-    const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
-    for (int jr = threadIdx.x / WAVE; jr < passes; jr += nw) {
-        const int i = begin + jr * WAVE + lane_id();
-        const bool live = i < end;
-        const int ii = live ? i : begin;
-        const double x1 = a.xi1[ii], x2 = a.xi2[ii];
-        const double q1 = a.p1[ii], q2 = a.p2[ii];
-        const double D1 = live ? a.d1[ii] : 0.0, D2 = live ? a.d2[ii] : 0.0;
-        const double s1 = D1 * a.inv_dx1, s2 = D2 * a.inv_dx2;   // increment in cell units
-        const double y1 = x1 + s1, y2 = x2 + s2;
-        const int ca1 = r, ca2 = (int)x2;
-        int cb1 = (int)floor(y1), cb2 = (int)floor(y2);
-        if (cb1 < ca1 - 1 || cb1 > ca1 + 1 || cb2 < ca2 - 1 || cb2 > ca2 + 1 || !isfinite(s1 + s2)) {
-            if (live) flags |= isfinite(s1 + s2) ? FLAG_CFL : FLAG_NONFINITE;
-            cb1 = ca1;
-            cb2 = ca2;
-        }
-        const int mn1 = min(ca1, cb1), mn2 = min(ca2, cb2);
-        // breakpoints of the straight path where it crosses a grid line
-        const double bA = cb1 != ca1 ? ((double)max(ca1, cb1) - x1) / s1 : 1.0;
-        const double bB = cb2 != ca2 ? ((double)max(ca2, cb2) - x2) / s2 : 1.0;
-        const double lo = fmin(bA, bB), hi = fmax(bA, bB);
-        // mean field along the path and the current of d^(k), piece by piece in each
-        // piece's cell (pieces no lane of the wave needs are skipped)
-        double E1 = 0.0, E2 = 0.0;
-        const double j1 = a.w * D1, j2 = a.w * D2;
+    g.mn1 = min(ca1, g.cb1);
+    g.mn2 = min(g.ca2, g.cb2);
+    const double bA = g.cb1 != ca1 ? ((double)max(ca1, g.cb1) - g.x1) / g.s1 : 1.0;
+    const double bB = g.cb2 != g.ca2 ? ((double)max(g.ca2, g.cb2) - g.x2) / g.s2 : 1.0;
+    g.lo = fmin(bA, bB);
+    g.hi = fmax(bA, bB);
+    return g;
+}
+
+// Pieces first..last of the path (0: [0, lo], 1: [lo, hi], 2: [hi, 1]): the mean
+// field is accumulated into E1, E2 and w d times the path integrals of the V1 basis
+// are added to the current patch.  Pieces no lane of the wave needs are skipped.
+template <int P>
+__device__ __forceinline__ void pieces(const Geo &g, bool live, int first, int last, const Patch &t, double w,
+                                       double &E1, double &E2) {
+    const double j1 = w * g.D1, j2 = w * g.D2;
+    const int PC = t.PC;
 #pragma unroll 1
-        for (int piece = 0; piece < 3; ++piece) {
-            const double sa = piece == 0 ? 0.0 : (piece == 1 ? lo : hi);
-            const double sb = piece == 0 ? lo : (piece == 1 ? hi : 1.0);
-            const double len = live ? sb - sa : 0.0;
-            if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
-            const double sm = 0.5 * (sa + sb);
-            const int k1 = min(max((int)floor(x1 + sm * s1), mn1), mn1 + 1);
-            const int k2 = min(max((int)floor(x2 + sm * s2), mn2), mn2 + 1);
-            double W1[P][P + 1], W2[P + 1][P];
-            piece_integrals<P>(x1, x2, s1, s2, k1, k2, sa, len, W1, W2);
-            const int o1 = (k1 - (P - 1) - R0) * PC + k2 - P - C0;   // W1[0][0] in the patch
-            const int o2 = (k1 - P - R0) * PC + k2 - (P - 1) - C0;   // W2[0][0]
+    for (int piece = first; piece <= last; ++piece) {
+        const double sa = piece == 0 ? 0.0 : (piece == 1 ? g.lo : g.hi);
+        const double sb = piece == 0 ? g.lo : (piece == 1 ? g.hi : 1.0);
+        const double len = live ? sb - sa : 0.0;
+        if (!__builtin_amdgcn_ballot_w64(len > 0.0)) continue;
+        const double sm = 0.5 * (sa + sb);
+        const int k1 = min(max((int)floor(g.x1 + sm * g.s1), g.mn1), g.mn1 + 1);
+        const int k2 = min(max((int)floor(g.x2 + sm * g.s2), g.mn2), g.mn2 + 1);
+        double W1[P][P + 1], W2[P + 1][P];
+        piece_integrals<P>(g.x1, g.x2, g.s1, g.s2, k1, k2, sa, len, W1, W2);
+        const int o1 = (k1 - (P - 1) - t.R0) * PC + k2 - P - t.C0;   // W1[0][0] in the patch
+        const int o2 = (k1 - P - t.R0) * PC + k2 - (P - 1) - t.C0;   // W2[0][0]
+#pragma unroll
+        for (int u = 0; u < P; ++u)
+#pragma unroll
+            for (int v = 0; v < P + 1; ++v) {
+                E1 += W1[u][v] * t.E1[o1 + u * PC + v];
+                E2 += W2[v][u] * t.E2[o2 + v * PC + u];
+            }
+        if (len > 0.0) {
 #pragma unroll
             for (int u = 0; u < P; ++u)
 #pragma unroll
                 for (int v = 0; v < P + 1; ++v) {
-                    E1 += W1[u][v] * sE1[o1 + u * PC + v];
-                    E2 += W2[v][u] * sE2[o2 + v * PC + u];
+                    atomicAdd(&t.J1[o1 + u * PC + v], j1 * W1[u][v]);
+                    atomicAdd(&t.J2[o2 + v * PC + u], j2 * W2[v][u]);
                 }
-            if (len > 0.0) {
-#pragma unroll
-                for (int u = 0; u < P; ++u)
-#pragma unroll
-                    for (int v = 0; v < P + 1; ++v) {
-                        atomicAdd(&sJ1[o1 + u * PC + v], j1 * W1[u][v]);
-                        atomicAdd(&sJ2[o2 + v * PC + u], j2 * W2[v][u]);
-                    }
-            }
-        }
-        // A at both ends, means of dA/dx2 (vertical leg at x1^n) and dA/dx1 (horizontal
-        // leg at x2^{n+1})
-        double ba1[P + 1], ba2[P + 1], bb1[P + 1], bb2[P + 1];
-        basis_values<P>(x1 - ca1, ba1);
-        basis_values<P>(x2 - ca2, ba2);
-        basis_values<P>(y1 - cb1, bb1);
-        basis_values<P>(y2 - cb2, bb2);
-        double Aa = 0.0, Ab = 0.0;
-#pragma unroll
-        for (int m1 = 0; m1 <= P; ++m1) {
-            double ta = 0.0, tb = 0.0;
-#pragma unroll
-            for (int m2 = 0; m2 <= P; ++m2) {
-                ta += ba2[m2] * sA[(ca1 - m1 - R0) * PC + ca2 - m2 - C0];
-                tb += bb2[m2] * sA[(cb1 - m1 - R0) * PC + cb2 - m2 - C0];
-            }
-            Aa += ba1[m1] * ta;
-            Ab += bb1[m1] * tb;
-        }
-        double lm2[P + 2], lm1[P + 2];
-        line_mean_v1<P>(x2 - ca2, y2 - ca2, cb2 - ca2, lm2);   // indices ca2 - P + k
-        line_mean_v1<P>(x1 - ca1, y1 - ca1, cb1 - ca1, lm1);   // indices ca1 - P + k
-        double Dv = 0.0, Dh = 0.0;
-#pragma unroll
-        for (int m1 = 0; m1 <= P; ++m1) {
-            double t = 0.0;
-#pragma unroll
-            for (int k = 0; k < P + 2; ++k) t += lm2[k] * sG2[(ca1 - m1 - R0) * PC + ca2 - P + k - C0];
-            Dv += ba1[m1] * t;
-        }
-#pragma unroll
-        for (int k = 0; k < P + 2; ++k) {
-            double t = 0.0;
-#pragma unroll
-            for (int m2 = 0; m2 <= P; ++m2) t += bb2[m2] * sG1[(ca1 - P + k - R0) * PC + cb2 - m2 - C0];
-            Dh += lm1[k] * t;
-        }
-        // push (Subsystem I scheme)
-        const double pp = q1 * q1 + q2 * q2;
-        const double gA = sqrt(1.0 + pp + Aa * Aa), gB = sqrt(1.0 + pp + Ab * Ab);
-        const double f = -(Aa + Ab) / (gA + gB);
-        const double n1 = q1 + a.dt * (E1 + f * Dh), n2 = q2 + a.dt * (E2 + f * Dv);
-        const double gC = sqrt(1.0 + n1 * n1 + n2 * n2 + Ab * Ab);
-        const double sc = a.dt / (gB + gC);
-        const double e1 = (q1 + n1) * sc, e2 = (q2 + n2) * sc;
-        if (live) {
-            if (!isfinite(e1 + e2 + n1 + n2)) flags |= FLAG_NONFINITE;
-            a.dn1[i] = e1;
-            a.dn2[i] = e2;
-            a.pk1[i] = n1;
-            a.pk2[i] = n2;
-            rmax = fmax(rmax, fmax(fabs(e1 - D1), fabs(e2 - D2)));
         }
     }
+}
+
+// A_z at both ends, the means of dA_z/dx2 along the vertical leg (at x1^n) and of
+// dA_z/dx1 along the horizontal leg (at x2^{n+1}), the push of the Subsystem I
+// scheme, and the stores of particle i.
+template <int P>
+__device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1, double E2, const Patch &t,
+                                       const SweepArgs &a, double &rmax, int &flags) {
+    const int PC = t.PC, R0 = t.R0, C0 = t.C0, ca1 = t.r, ca2 = g.ca2, cb1 = g.cb1, cb2 = g.cb2;
+    double ba1[P + 1], ba2[P + 1], bb1[P + 1], bb2[P + 1];
+    basis_values<P>(g.x1 - ca1, ba1);
+    basis_values<P>(g.x2 - ca2, ba2);
+    basis_values<P>(g.y1 - cb1, bb1);
+    basis_values<P>(g.y2 - cb2, bb2);
+    double Aa = 0.0, Ab = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 <= P; ++m1) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 <= P; ++m2) {
+            ta += ba2[m2] * t.A[(ca1 - m1 - R0) * PC + ca2 - m2 - C0];
+            tb += bb2[m2] * t.A[(cb1 - m1 - R0) * PC + cb2 - m2 - C0];
+        }
+        Aa += ba1[m1] * ta;
+        Ab += bb1[m1] * tb;
+    }
+    double lm2[P + 2], lm1[P + 2];
+    line_mean_v1<P>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, lm2);   // indices ca2 - P + k
+    line_mean_v1<P>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, lm1);   // indices ca1 - P + k
+    double Dv = 0.0, Dh = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 <= P; ++m1) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < P + 2; ++k) s += lm2[k] * t.G2[(ca1 - m1 - R0) * PC + ca2 - P + k - C0];
+        Dv += ba1[m1] * s;
+    }
+#pragma unroll
+    for (int k = 0; k < P + 2; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 <= P; ++m2) s += bb2[m2] * t.G1[(ca1 - P + k - R0) * PC + cb2 - m2 - C0];
+        Dh += lm1[k] * s;
+    }
+    const double q1 = g.q1, q2 = g.q2, pp = q1 * q1 + q2 * q2;
+    const double gA = sqrt(1.0 + pp + Aa * Aa), gB = sqrt(1.0 + pp + Ab * Ab);
+    const double f = -(Aa + Ab) / (gA + gB);
+    const double n1 = q1 + a.dt * (E1 + f * Dh), n2 = q2 + a.dt * (E2 + f * Dv);
+    const double gC = sqrt(1.0 + n1 * n1 + n2 * n2 + Ab * Ab);
+    const double sc = a.dt / (gB + gC);
+    const double e1 = (q1 + n1) * sc, e2 = (q2 + n2) * sc;
+    if (live) {
+        if (!isfinite(e1 + e2 + n1 + n2)) flags |= FLAG_NONFINITE;
+        a.dn1[i] = e1;
+        a.dn2[i] = e2;
+        a.pk1[i] = n1;
+        a.pk2[i] = n2;
+        rmax = fmax(rmax, fmax(fabs(e1 - g.D1), fabs(e2 - g.D2)));
+    }
+}
+
+// One sweep over a tile.  Every particle integrates the first piece of its path
+// inline; a step that crosses a grid line needs one or two more pieces, and such
+// particles (about one in ten) are parked in a per-wave LDS queue with their
+// partial mean field and finished 64 at a time, so that the waves do not run the
+// extra pieces for lanes that have none.
+constexpr int QCAP = 2 * WAVE;
+
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
+    constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
+    __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
+    __shared__ int qI[BLOCK / WAVE][QCAP];
+    __shared__ double qE1[BLOCK / WAVE][QCAP], qE2[BLOCK / WAVE][QCAP];
+    const int nseg = a.M2 / a.TW;
+    const int tile = tile_of_block();
+    const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
+    const int PC = a.TW + P + 2;
+    const Patch t{sE1, sE2, sA, sG1, sG2, sJ1, sJ2, PC, r - P - 1, c0 - P - 1, r};
+    for (int k = threadIdx.x; k < PR * PC; k += blockDim.x) {
+        const int i = k / PC, j = k - i * PC;
+        const int g = wrapi(t.R0 + i, a.M1) * a.M2 + wrapi(t.C0 + j, a.M2);
+        sE1[k] = a.eb1[g];
+        sE2[k] = a.eb2[g];
+        sA[k] = a.az[g];
+        sG1[k] = a.g1a[g];
+        sG2[k] = a.g2a[g];
+        sJ1[k] = 0.0;
+        sJ2[k] = 0.0;
+    }
+    __syncthreads();
+    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
+    const int wid = threadIdx.x / WAVE, lane = lane_id();
+    int *const qi = qI[wid];
+    double *const qe1 = qE1[wid], *const qe2 = qE2[wid];
+    double rmax = 0.0;
+    int flags = 0;
+    int head = 0, tail = 0;   // queue of this wave (uniform)
+    // finish the n oldest queued particles, one per lane
+    auto drain = [&](int n) {
+        const bool valid = lane < n;
+        const int slot = (head + lane) & (QCAP - 1);
+        const int i = valid ? qi[slot] : begin;
+        double E1 = valid ? qe1[slot] : 0.0, E2 = valid ? qe2[slot] : 0.0;
+        const Geo g = geometry(a, i, valid, r, flags);
+        pieces<P>(g, valid, 1, 2, t, a.w, E1, E2);
+        finish<P>(g, valid, i, E1, E2, t, a, rmax, flags);
+        head += n;
+    };
+    const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
+    for (int jr = wid; jr < passes; jr += nw) {
+        const int i = begin + jr * WAVE + lane;
+        const bool live = i < end;
+        const int ii = live ? i : begin;
+        const Geo g = geometry(a, ii, live, r, flags);
+        double E1 = 0.0, E2 = 0.0;
+        pieces<P>(g, live, 0, 0, t, a.w, E1, E2);
+        const bool cross = live && g.lo < 1.0;
+        const unsigned long long cm = __builtin_amdgcn_ballot_w64(cross);
+        if (cross) {
+            const int slot = (tail + rank_in(cm)) & (QCAP - 1);
+            qi[slot] = i;
+            qe1[slot] = E1;
+            qe2[slot] = E2;
+        }
+        tail += __builtin_popcountll(cm);
+        if (live && !cross) finish<P>(g, live, i, E1, E2, t, a, rmax, flags);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tail - head >= WAVE) drain(WAVE);
+    }
+    if (tail > head) drain(tail - head);
     if (flags) atomicOr(a.flags, flags);
     block_max_to(rmax, a.res);
     __syncthreads();
-    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
-        const int i = t / PC, j = t - i * PC;
-        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
-        if (sJ1[t] != 0.0) atomicAdd(&a.J1[g], sJ1[t]);
-        if (sJ2[t] != 0.0) atomicAdd(&a.J2[g], sJ2[t]);
+    for (int k = threadIdx.x; k < PR * PC; k += blockDim.x) {
+        const int i = k / PC, j = k - i * PC;
+        const int g = wrapi(t.R0 + i, a.M1) * a.M2 + wrapi(t.C0 + j, a.M2);
+        if (sJ1[k] != 0.0) atomicAdd(&a.J1[g], sJ1[k]);
+        if (sJ2[k] != 0.0) atomicAdd(&a.J2[g], sJ2[k]);
     }
 }
 
