@@ -439,14 +439,15 @@ struct Geo {
     int ca2, cb1, cb2, mn1, mn2;
 };
 
-__device__ __forceinline__ Geo geometry(const SweepArgs &a, int ii, bool live, int r, int &flags) {
+__device__ __forceinline__ Geo geometry(const SweepArgs &a, double x1, double x2, double q1, double q2, double D1,
+                                        double D2, bool live, int r, int &flags) {
     Geo g;
-    g.x1 = a.xi1[ii];
-    g.x2 = a.xi2[ii];
-    g.q1 = a.p1[ii];
-    g.q2 = a.p2[ii];
-    g.D1 = live ? a.d1[ii] : 0.0;
-    g.D2 = live ? a.d2[ii] : 0.0;
+    g.x1 = x1;
+    g.x2 = x2;
+    g.q1 = q1;
+    g.q2 = q2;
+    g.D1 = live ? D1 : 0.0;
+    g.D2 = live ? D2 : 0.0;
     g.s1 = g.D1 * a.inv_dx1;
     g.s2 = g.D2 * a.inv_dx2;
     g.y1 = g.x1 + g.s1;
@@ -570,17 +571,19 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
 
 // One sweep over a tile.  Every particle integrates the first piece of its path
 // inline; a step that crosses a grid line needs one or two more pieces, and such
-// particles (about one in ten) are parked in a per-wave LDS queue with their
-// partial mean field and finished 64 at a time, so that the waves do not run the
-// extra pieces for lanes that have none.
+// particles (about one in ten) are parked, with their position, increment and
+// partial mean field, in a per-wave LDS queue and finished 64 at a time, so that
+// the waves do not run the extra pieces for lanes that have none (only the
+// momentum is read again).
 constexpr int QCAP = 2 * WAVE;
+constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
     __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
     __shared__ int qI[BLOCK / WAVE][QCAP];
-    __shared__ double qE1[BLOCK / WAVE][QCAP], qE2[BLOCK / WAVE][QCAP];
+    __shared__ double qV[BLOCK / WAVE][QV][QCAP];
     const int nseg = a.M2 / a.TW;
     const int tile = tile_of_block();
     const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
@@ -601,17 +604,21 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
     const int wid = threadIdx.x / WAVE, lane = lane_id();
     int *const qi = qI[wid];
-    double *const qe1 = qE1[wid], *const qe2 = qE2[wid];
+    double(*const qv)[QCAP] = qV[wid];
     double rmax = 0.0;
     int flags = 0;
     int head = 0, tail = 0;   // queue of this wave (uniform)
-    // finish the n oldest queued particles, one per lane
+    // finish the n <= 64 oldest queued particles, one per lane
     auto drain = [&](int n) {
         const bool valid = lane < n;
         const int slot = (head + lane) & (QCAP - 1);
+        double v[QV];
+#pragma unroll
+        for (int q = 0; q < QV; ++q) v[q] = valid ? qv[q][slot] : 0.0;
         const int i = valid ? qi[slot] : begin;
-        double E1 = valid ? qe1[slot] : 0.0, E2 = valid ? qe2[slot] : 0.0;
-        const Geo g = geometry(a, i, valid, r, flags);
+        if (!valid) v[0] = (double)r, v[1] = (double)c0;   // any point of the tile
+        double E1 = v[4], E2 = v[5];
+        const Geo g = geometry(a, v[0], v[1], a.p1[i], a.p2[i], v[2], v[3], valid, r, flags);
         pieces<P>(g, valid, 1, 2, t, a.w, E1, E2);
         finish<P>(g, valid, i, E1, E2, t, a, rmax, flags);
         head += n;
@@ -621,7 +628,8 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         const int i = begin + jr * WAVE + lane;
         const bool live = i < end;
         const int ii = live ? i : begin;
-        const Geo g = geometry(a, ii, live, r, flags);
+        const double x1 = a.xi1[ii], x2 = a.xi2[ii], q1 = a.p1[ii], q2 = a.p2[ii], D1 = a.d1[ii], D2 = a.d2[ii];
+        const Geo g = geometry(a, x1, x2, q1, q2, D1, D2, live, r, flags);
         double E1 = 0.0, E2 = 0.0;
         pieces<P>(g, live, 0, 0, t, a.w, E1, E2);
         const bool cross = live && g.lo < 1.0;
@@ -629,8 +637,12 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         if (cross) {
             const int slot = (tail + rank_in(cm)) & (QCAP - 1);
             qi[slot] = i;
-            qe1[slot] = E1;
-            qe2[slot] = E2;
+            qv[0][slot] = x1;
+            qv[1][slot] = x2;
+            qv[2][slot] = D1;
+            qv[3][slot] = D2;
+            qv[4][slot] = E1;
+            qv[5][slot] = E2;
         }
         tail += __builtin_popcountll(cm);
         if (live && !cross) finish<P>(g, live, i, E1, E2, t, a, rmax, flags);
