@@ -380,7 +380,7 @@ struct SweepArgs {
     const double *d1, *d2;               // increment d^(k) (physical)
     double *dn1, *dn2;                   // increment d^(k+1)
     double *pk1, *pk2;                   // momentum p^(k+1)
-    const int32_t *start;
+    const int32_t *start;                // first particle of each tile (ntiles + 1)
     const double *eb1, *eb2;             // (e^n + e^(k)) / 2
     const double *az, *g1a, *g2a;        // a_z and G a_z
     double *J1, *J2;                     // current of d^(k) (accumulated, zero on entry)
@@ -601,7 +601,7 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         sJ2[k] = 0.0;
     }
     __syncthreads();
-    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
+    const int begin = a.start[tile], end = a.start[tile + 1];
     const int wid = threadIdx.x / WAVE, lane = lane_id();
     int *const qi = qI[wid];
     double(*const qv)[QCAP] = qV[wid];
@@ -663,33 +663,168 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
     }
 }
 
-// Commit x^n + d^(k), p^(k+1) and bin the particles by their new cells.
-__global__ __launch_bounds__(BLOCK) void k2_commit_I(double *__restrict__ xi1, double *__restrict__ xi2,
-                                                     double *__restrict__ p1, double *__restrict__ p2,
-                                                     const double *__restrict__ d1, const double *__restrict__ d2,
-                                                     const double *__restrict__ pk1, const double *__restrict__ pk2,
-                                                     int32_t *__restrict__ cell, int32_t *__restrict__ count,
-                                                     int64_t n, int M1, int M2, double inv_dx1, double inv_dx2) {
-    for (int64_t base = blockIdx.x * (int64_t)blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool live = i < n;
-        int c = 0;
-        if (live) {
-            double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
-            if (u1 < 0.0) u1 += (double)M1;
-            if (u1 >= (double)M1) u1 -= (double)M1;
-            if (u2 < 0.0) u2 += (double)M2;
-            if (u2 >= (double)M2) u2 -= (double)M2;
-            if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
-            if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
-            xi1[i] = u1;
-            xi2[i] = u2;
-            p1[i] = pk1[i];
-            p2[i] = pk2[i];
-            c = (int)u1 * M2 + (int)u2;
-            cell[i] = c;
+// Tile starts from cell starts (after the full cell sort of set_particles): the
+// first cell of tile T is (T / nseg) M2 + (T % nseg) TW.
+__global__ void k2_tiles_from_cells(const int32_t *__restrict__ start, int32_t *__restrict__ tstart, int ntiles,
+                                    int nseg, int M2, int TW, int Nc) {
+    for (int T = blockIdx.x * blockDim.x + threadIdx.x; T <= ntiles; T += gridDim.x * blockDim.x)
+        tstart[T] = T == ntiles ? start[Nc] : start[(T / nseg) * M2 + (T - (T / nseg) * nseg) * TW];
+}
+
+// Commit of Subsystem I, one block per tile: x^n + d^(k) and p^(k+1) in place, the
+// particle's new tile, the count of the tile's particles that stay in it and, per
+// destination, the count of those that arrive.
+__global__ __launch_bounds__(BLOCK) void k2_commit_tiles(double *__restrict__ xi1, double *__restrict__ xi2,
+                                                         double *__restrict__ p1, double *__restrict__ p2,
+                                                         const double *__restrict__ d1, const double *__restrict__ d2,
+                                                         const double *__restrict__ pk1,
+                                                         const double *__restrict__ pk2, int32_t *__restrict__ tile,
+                                                         const int32_t *__restrict__ tstart, int32_t *__restrict__ tstay,
+                                                         int32_t *__restrict__ tarr, int M1, int M2, int TW,
+                                                         double inv_dx1, double inv_dx2) {
+    __shared__ int red[BLOCK / WAVE];
+    const int T = blockIdx.x, nseg = M2 / TW;
+    const int begin = tstart[T], end = tstart[T + 1];
+    int stay = 0;
+    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
+        if (u1 < 0.0) u1 += (double)M1;
+        if (u1 >= (double)M1) u1 -= (double)M1;
+        if (u2 < 0.0) u2 += (double)M2;
+        if (u2 >= (double)M2) u2 -= (double)M2;
+        if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
+        if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
+        xi1[i] = u1;
+        xi2[i] = u2;
+        p1[i] = pk1[i];
+        p2[i] = pk2[i];
+        const int Tn = (int)u1 * nseg + (int)u2 / TW;
+        tile[i] = Tn;
+        if (Tn == T) ++stay;
+        else atomicAdd(&tarr[Tn], 1);
+    }
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, WAVE);
+    if (lane_id() == 0) red[threadIdx.x / WAVE] = stay;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x / WAVE); ++w) t += red[w];
+        tstay[T] = t;
+    }
+}
+
+// count[T] = stay[T] + arrivals[T]; the arrival counts and cursors start at zero again.
+__global__ void k2_tile_counts(const int32_t *__restrict__ tstay, int32_t *__restrict__ tarr,
+                               int32_t *__restrict__ tcnt, int32_t *__restrict__ tcur, int ntiles) {
+    for (int T = blockIdx.x * blockDim.x + threadIdx.x; T < ntiles; T += gridDim.x * blockDim.x) {
+        tcnt[T] = tstay[T] + tarr[T];
+        tarr[T] = 0;
+        tcur[T] = 0;
+    }
+}
+
+// Re-sort by tile, one block per old tile: the particles that stay keep their
+// order (positions from a block prefix, so their writes are contiguous); the few
+// that leave go after the stayers of their new tile, by an atomic cursor.
+__global__ __launch_bounds__(BLOCK) void k2_scatter_tiles(const double *__restrict__ s1, const double *__restrict__ s2,
+                                                          const double *__restrict__ q1, const double *__restrict__ q2,
+                                                          const int32_t *__restrict__ sid, double *__restrict__ d1,
+                                                          double *__restrict__ d2, double *__restrict__ r1,
+                                                          double *__restrict__ r2, int32_t *__restrict__ did,
+                                                          const int32_t *__restrict__ tile,
+                                                          const int32_t *__restrict__ told,
+                                                          const int32_t *__restrict__ tnew,
+                                                          const int32_t *__restrict__ tstay, int32_t *__restrict__ tcur) {
+    __shared__ int wtot[BLOCK / WAVE];
+    const int T = blockIdx.x, wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
+    const int begin = told[T], end = told[T + 1], base0 = tnew[T];
+    int run = 0;   // stayers placed so far (uniform over the block)
+    for (int base = begin; base < end; base += blockDim.x) {   // uniform over the block
+        const int i = base + threadIdx.x;
+        const bool live = i < end;
+        const int Tn = live ? tile[i] : -1;
+        const bool stay = live && Tn == T;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(stay);
+        if (lane_id() == 0) wtot[wid] = __builtin_popcountll(m);
+        __syncthreads();
+        int pre = 0, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            pre += w < wid ? wtot[w] : 0;
+            tot += wtot[w];
         }
-        claim_slot(c, live, count);
+        __syncthreads();
+        int pos = -1;
+        if (stay) pos = base0 + run + pre + rank_in(m);
+        else if (live) pos = tnew[Tn] + tstay[Tn] + atomicAdd(&tcur[Tn], 1);
+        if (live) {
+            d1[pos] = s1[i];
+            d2[pos] = s2[i];
+            r1[pos] = q1[i];
+            r2[pos] = q2[i];
+            did[pos] = sid[i];
+        }
+        run += tot;
+    }
+}
+
+// Cell sort inside each tile (one block per tile, after the tile scatter): an LDS
+// histogram of the tile's cells and its prefix give every particle its rank in the
+// cell-sorted order, and the tile is written in the transposed layout (tile_pos),
+// so that a coalesced read hands the lanes of a wave particles of different cells
+// again.  Up to INVCAP particles per tile the source of every rank is kept in LDS
+// and the output is written in position order (coalesced stores, reads scattered
+// inside the tile); a fuller tile writes each particle to its position directly.
+constexpr int INVCAP = 8192;
+
+__device__ __forceinline__ int tile_rank(int p, int cnt) {   // inverse of tile_pos
+    const int Q = cnt / WAVE;
+    return p < WAVE * Q ? (p % WAVE) * Q + p / WAVE : p;
+}
+
+__global__ __launch_bounds__(BLOCK) void k2_tile_cellsort(const double *__restrict__ s1, const double *__restrict__ s2,
+                                                          const double *__restrict__ q1, const double *__restrict__ q2,
+                                                          const int32_t *__restrict__ sid, double *__restrict__ d1,
+                                                          double *__restrict__ d2, double *__restrict__ r1,
+                                                          double *__restrict__ r2, int32_t *__restrict__ did,
+                                                          const int32_t *__restrict__ tstart, int M2, int TW) {
+    __shared__ int hist[TWMAX], cur[TWMAX];
+    __shared__ int inv[INVCAP];
+    const int T = blockIdx.x, nseg = M2 / TW, c0 = (T - (T / nseg) * nseg) * TW;
+    const int begin = tstart[T], end = tstart[T + 1], cnt = end - begin;
+    for (int k = threadIdx.x; k < TW; k += blockDim.x) hist[k] = 0;
+    __syncthreads();
+    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&hist[(int)s2[i] - c0], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {   // TW <= 64 entries
+        int run = 0;
+        for (int k = 0; k < TW; ++k) {
+            cur[k] = run;
+            run += hist[k];
+        }
+    }
+    __syncthreads();
+    if (cnt <= INVCAP) {
+        for (int i = begin + threadIdx.x; i < end; i += blockDim.x) inv[atomicAdd(&cur[(int)s2[i] - c0], 1)] = i;
+        __syncthreads();
+        for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
+            const int i = inv[tile_rank(p, cnt)], j = begin + p;
+            d1[j] = s1[i];
+            d2[j] = s2[i];
+            r1[j] = q1[i];
+            r2[j] = q2[i];
+            did[j] = sid[i];
+        }
+    } else {
+        for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
+            const double x2 = s2[i];
+            const int j = begin + tile_pos(atomicAdd(&cur[(int)x2 - c0], 1), cnt);
+            d1[j] = s1[i];
+            d2[j] = x2;
+            r1[j] = q1[i];
+            r2[j] = q2[i];
+            did[j] = sid[i];
+        }
     }
 }
 
@@ -737,7 +872,7 @@ __global__ __launch_bounds__(BLOCK) void k2_rotate_II(const double *__restrict__
 // ---------------------------------------------------------------------------
 struct DepArgs {
     const double *xi1, *xi2, *p1, *p2;
-    const int32_t *start;
+    const int32_t *start;   // first particle of each tile (ntiles + 1)
     const double *an;    // a_z^n                     (III)
     const double *ezn;   // e_z^n                     (III)
     const double *ezk;   // e_z^(k)                   (III)
@@ -769,7 +904,7 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
         sS[t] = 0.0;
     }
     __syncthreads();
-    const int begin = a.start[r * a.M2 + c0], end = a.start[r * a.M2 + c0 + a.TW];
+    const int begin = a.start[tile], end = a.start[tile + 1];
     const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
     for (int jr = threadIdx.x / WAVE; jr < passes; jr += nw) {
         const int i = begin + jr * WAVE + lane_id();
@@ -1209,7 +1344,9 @@ struct ecpic2d_ctx {
     double *xi1[2] = {}, *xi2[2] = {}, *p1[2] = {}, *p2[2] = {};
     int32_t *id[2] = {};
     double *d1[2] = {}, *d2[2] = {}, *pk1 = nullptr, *pk2 = nullptr;
-    int32_t *cell = nullptr, *count = nullptr, *start = nullptr, *bsum = nullptr;
+    int32_t *cell = nullptr /* new cell (set_particles) or new tile (commit) */, *count = nullptr, *start = nullptr, *bsum = nullptr;
+    int32_t *tstart[2] = {}, *tstay = nullptr, *tarr = nullptr, *tcnt = nullptr, *tcur = nullptr;
+    int ts = 0, ntiles = 0;   // tstart[ts]: first particle of each tile
     double *e1 = nullptr, *e2 = nullptr, *bz = nullptr, *ez = nullptr, *az = nullptr;
     double *en1 = nullptr, *en2 = nullptr, *ek1 = nullptr, *ek2 = nullptr, *eb1 = nullptr, *eb2 = nullptr;
     double *J1 = nullptr, *J2 = nullptr, *g1a = nullptr, *g2a = nullptr, *ezn = nullptr, *ezk = nullptr,
@@ -1280,7 +1417,8 @@ Sym sym_of(ecpic2d_ctx *c) {
 
 int n_tiles(ecpic2d_ctx *c) { return c->M1 * (c->M2 / c->TW); }
 
-// Re-sort after positions changed: counts are in c->count, cells in c->cell.
+// Full cell sort (set_particles): counts in c->count, cells in c->cell; each tile
+// is stored transposed (tile_pos), and the tile starts are taken from the cell starts.
 void sort_particles(ecpic2d_ctx *c) {
     const int A = c->cur, B = 1 - c->cur;
     timed(c, "sort", [&] {
@@ -1292,8 +1430,32 @@ void sort_particles(ecpic2d_ctx *c) {
                                                            c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
                                                            c->cell, c->start, c->count, c->N, c->M2, c->TW);
         k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->count, c->Nc);
+        k2_tiles_from_cells<<<grid_for(c->ntiles + 1), BLOCK, 0, c->stream>>>(
+            c->start, c->tstart[c->ts], c->ntiles, c->M2 / c->TW, c->M2, c->TW, c->Nc);
     });
     c->cur = B;
+}
+
+// Re-sort after a Subsystem I commit (new tiles in c->cell, stay and arrival
+// counts from the commit): move the particles to their new tiles (those that
+// stay keep their order, the arrivals follow), then sort each tile by cell into
+// the transposed layout.
+void sort_tiles(ecpic2d_ctx *c) {
+    const int A = c->cur, B = 1 - c->cur, T0 = c->ts, T1 = 1 - c->ts;
+    timed(c, "sort", [&] {
+        const int nt = c->ntiles, nb = (nt + SCAN_TILE - 1) / SCAN_TILE;
+        k2_tile_counts<<<grid_for(nt), BLOCK, 0, c->stream>>>(c->tstay, c->tarr, c->tcnt, c->tcur, nt);
+        k2_scan_sums<<<nb, SCAN_THREADS, 0, c->stream>>>(c->tcnt, c->bsum, nt);
+        k2_scan_top<<<1, SCAN_THREADS, 0, c->stream>>>(c->bsum, nb, c->tstart[T1] + nt);
+        k2_scan_apply<<<nb, SCAN_THREADS, 0, c->stream>>>(c->tcnt, c->tstart[T1], c->bsum, nt);
+        k2_scatter_tiles<<<nt, BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->xi1[B],
+                                                     c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->cell,
+                                                     c->tstart[T0], c->tstart[T1], c->tstay, c->tcur);
+        k2_tile_cellsort<<<nt, BLOCK, 0, c->stream>>>(c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->xi1[A],
+                                                     c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->tstart[T1], c->M2,
+                                                     c->TW);
+    });
+    c->ts = T1;   // the particles are back in buffer A
 }
 
 // Forward rows -> columns with op -> inverse rows with epi, over NB grids.
@@ -1360,7 +1522,7 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     int k;
     for (k = 0; k < c->kmax; ++k) {
         SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
-                    c->pk1, c->pk2, c->start, c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
+                    c->pk1, c->pk2, c->tstart[c->ts], c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
                     c->res + k, c->flags, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
         timed(c, "sweep_I", [&] { LAUNCH_P(c->P, k2_sweep_I<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
         spectral<2>(c, "solve_I", Ptrs<2>{{c->J1, c->J2}}, 3, OpM1inv{sy},
@@ -1379,15 +1541,15 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     }
     if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
     if (k == c->kmax) return ECPIC_ENOTCONV;
-    // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1), then re-sort
+    // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1), then re-sort by tile
     timed(c, "commit_I", [&] {
-        k2_commit_I<<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->pk1,
-                                         c->pk2, c->cell, c->count, c->N, c->M1, c->M2, 1.0 / c->dx1,
-                                         1.0 / c->dx2);
+        k2_commit_tiles<<<c->ntiles, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di],
+                                                    c->pk1, c->pk2, c->cell, c->tstart[c->ts], c->tstay, c->tarr,
+                                                    c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2);
     });
     k2_copy<<<gC, BLOCK, 0, s>>>(c->e1, c->ek1, Nc);
     k2_copy<<<gC, BLOCK, 0, s>>>(c->e2, c->ek2, Nc);
-    sort_particles(c);
+    sort_tiles(c);
     return sync2(c);
 }
 
@@ -1414,7 +1576,7 @@ int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     double r = 0.0;
     int k;
     for (k = 0; k < c->kmax; ++k) {
-        DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->start, c->az, c->ezn, c->ezk, c->S,
+        DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->az, c->ezn, c->ezk, c->S,
                   c->M1, c->M2, c->TW, dt, c->w, 1};
         timed(c, "deposit_III", [&] { LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
         spectral<1>(c, "solve_III", Ptrs<1>{{c->S}}, 1, OpIII{sy, c->R, c->M2, dt},
@@ -1440,7 +1602,7 @@ int substep_IV(ecpic2d_ctx *c, double dt) {
 void deposit_rho(ecpic2d_ctx *c, double *rho) {
     const int A = c->cur;
     k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(rho, c->Nc, 0.0);
-    DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->start, nullptr, nullptr, nullptr, rho,
+    DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], nullptr, nullptr, nullptr, rho,
               c->M1, c->M2, c->TW, 0.0, c->w, 0};
     LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(a));
 }
@@ -1512,6 +1674,10 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->count, Nc) |
           dalloc(c, &c->start, Nc + 1) |
           dalloc(c, &c->bsum, Nc / SCAN_TILE + 2);
+    c->ntiles = c->M1 * (c->M2 / c->TW);
+    rc |= dalloc(c, &c->tstart[0], (size_t)c->ntiles + 1) | dalloc(c, &c->tstart[1], (size_t)c->ntiles + 1) |
+          dalloc(c, &c->tstay, (size_t)c->ntiles) | dalloc(c, &c->tarr, (size_t)c->ntiles) |
+          dalloc(c, &c->tcnt, (size_t)c->ntiles) | dalloc(c, &c->tcur, (size_t)c->ntiles);
     double **grids[] = {&c->e1, &c->e2, &c->bz, &c->ez, &c->az, &c->en1, &c->en2, &c->ek1, &c->ek2, &c->eb1,
                         &c->eb2, &c->J1, &c->J2, &c->g1a, &c->g2a, &c->ezn, &c->ezk, &c->S, &c->tmp};
     for (double **gp : grids) rc |= dalloc(c, gp, Nc);
@@ -1549,6 +1715,9 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     if (!ok) { ecpic2d_destroy(c); return ECPIC_EDEVICE; }
     for (double **gp : grids) k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(*gp, c->Nc, 0.0);
     k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->count, c->Nc);
+    // the commit accumulates arrivals per tile: every tile counter starts at zero
+    for (int32_t *tp : {c->tstay, c->tarr, c->tcnt, c->tcur})
+        k2_fill_i32<<<grid_for(c->ntiles), BLOCK, 0, c->stream>>>(tp, c->ntiles);
     k2_fill_i32<<<1, 1, 0, c->stream>>>(c->flags, 1);
     if (sync2(c)) { ecpic2d_destroy(c); return ECPIC_EDEVICE; }
     *out = c;
@@ -1587,6 +1756,8 @@ int ecpic2d_set_particles(ecpic2d_ctx *c, const double *x1, const double *x2, co
     (void)B;
     k2_fill_i32<<<1, 1, 0, s>>>(c->flags, 1);
     k2_fill_i32<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->count, c->Nc);
+    for (int32_t *tp : {c->tstay, c->tarr, c->tcnt, c->tcur})
+        k2_fill_i32<<<grid_for(c->ntiles), BLOCK, 0, s>>>(tp, c->ntiles);
     k2_iota<<<grid_for(n), BLOCK, 0, s>>>(c->id[A], n);
     k2_bin_new<<<grid_for(n), BLOCK, 0, s>>>(c->d1[0], c->d2[0], c->xi1[A], c->xi2[A], c->cell, c->count, n,
                                              c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2, c->flags);
