@@ -782,7 +782,9 @@ __device__ __forceinline__ int tile_rank(int p, int cnt) {   // inverse of tile_
     return p < WAVE * Q ? (p % WAVE) * Q + p / WAVE : p;
 }
 
-__global__ __launch_bounds__(BLOCK) void k2_tile_cellsort(const double *__restrict__ s1, const double *__restrict__ s2,
+constexpr int SORT_THREADS = 1024;
+
+__global__ __launch_bounds__(SORT_THREADS) void k2_tile_cellsort(const double *__restrict__ s1, const double *__restrict__ s2,
                                                           const double *__restrict__ q1, const double *__restrict__ q2,
                                                           const int32_t *__restrict__ sid, double *__restrict__ d1,
                                                           double *__restrict__ d2, double *__restrict__ r1,
@@ -1451,7 +1453,7 @@ void sort_tiles(ecpic2d_ctx *c) {
         k2_scatter_tiles<<<nt, BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->xi1[B],
                                                      c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->cell,
                                                      c->tstart[T0], c->tstart[T1], c->tstay, c->tcur);
-        k2_tile_cellsort<<<nt, BLOCK, 0, c->stream>>>(c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->xi1[A],
+        k2_tile_cellsort<<<nt, SORT_THREADS, 0, c->stream>>>(c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->xi1[A],
                                                      c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->tstart[T1], c->M2,
                                                      c->TW);
     });
