@@ -311,7 +311,9 @@ static void cg2_core(const orc2_cfg *c, orc2_op A, double prm, long n, int zero_
             double rn = dot2(n, r, r);
             if (rn < best_rr) { best_rr = rn; stall = 0; memcpy(best, x, sizeof(double) * n); }
             else ++stall;
-            if (rn <= 1e-36 * bb || stall >= 8) break;
+            /* the residual norm of CG is not monotone on ill-conditioned systems (the
+             * quintic mass matrices): allow a full 2n iterations without a new best */
+            if (rn <= 1e-36 * bb || stall >= 2 * n + 50) break;
             double beta = rn / rr;
             for (long i = 0; i < n; ++i) d[i] = r[i] + beta * d[i];
             rr = rn;

@@ -249,3 +249,30 @@ def test_fresh_context_after_destroyed_one():
         ctx.substep_I()
         assert o.substep_I(s)[0] == 0
         compare(w, ctx.state(), s, 1e-11)
+
+
+@pytest.mark.parametrize("degree", [4, 5])
+def test_high_degree_substeps_and_step(degree):
+    """Degrees 4 and 5 (the sweep at its register limits): Subsystem I and a whole Lie
+    step against the oracle element by element."""
+    w = get2d("twod16").scaled(degree=degree, n_particles=1200 if degree == 4 else 500)
+    arr = generate2d(w)
+    o = Oracle2D.from_workload(w)
+    s = initial_state2d(o, arr)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        assert rel(ctx.state()["e"], s["e"]) < 1e-12
+        kg, _ = ctx.substep_I()
+        st, ko, _ = o.substep_I(s)
+        assert st == 0 and abs(kg - ko) <= 1
+        compare(w, ctx.state(), s, 1e-11)
+        ctx.substep_II()
+        o.substep_II(s)
+        ctx.substep_III()
+        assert o.substep_III(s)[0] == 0
+        ctx.substep_IV()
+        o.substep_IV(s)
+        ctx.step(1)
+        assert o.step(s, 1)[0] == 0
+        compare(w, ctx.state(), s, 3e-11)
+        assert ctx.gauss_residual() < 1e-13

@@ -425,3 +425,29 @@ def test_gauss_law_is_exact_at_a_loose_tolerance():
     st, k, r = o.substep_I(s)
     assert st == 0 and k <= 6 and r > 1e-10
     assert o.gauss_residual(s) < 1e-14
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_linear_solves_reach_their_solution(p):
+    """Every linear system of the 2D scheme is solved, at every degree (the quintic mass
+    matrices are the worst conditioned): M1 x = b, the Gauss correction (residual at
+    round-off), Subsystem IV (energy kept, reversible) and Subsystem III's midpoint
+    relation."""
+    o = Oracle2D(L1=4 * math.pi, L2=2 * math.pi, M1=16, M2=8, p=p, n=1)
+    rng = np.random.default_rng(40 + p)
+    b = rng.normal(size=2 * o.N)
+    assert np.abs(o.M1(o.solve_M1(b)) - b).max() <= 1e-12 * np.abs(b).max()
+    w = get2d("twod16").scaled(degree=p, n_particles=200, M2=8, L2=2 * math.pi)
+    o2 = Oracle2D.from_workload(w)
+    s = initial_state2d(o2, generate2d(w))
+    assert o2.gauss_residual(s) < 1e-13
+    W = lambda s: 0.5 * s["e"] @ o2.M1(s["e"]) + 0.5 * s["bz"] @ o2.M2(s["bz"])   # noqa: E731
+    e0, b0, W0 = s["e"].copy(), s["bz"].copy(), W(s)
+    o2.substep_IV(s, 0.3)
+    assert abs(W(s) - W0) < 1e-13 * W0
+    o2.substep_IV(s, -0.3)
+    np.testing.assert_allclose(s["e"], e0, atol=1e-12)
+    np.testing.assert_allclose(s["bz"], b0, atol=1e-12)
+    a0, ez0 = s["az"].copy(), s["ez"].copy()
+    assert o2.substep_III(s)[0] == 0
+    np.testing.assert_allclose((s["az"] - a0) / w.dt, -0.5 * (ez0 + s["ez"]), atol=1e-12)
