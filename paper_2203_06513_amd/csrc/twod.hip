@@ -831,45 +831,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k2_tile_cellsort(const double *_
 }
 
 // ---------------------------------------------------------------------------
-// Subsystem II: rotation of p by B_z
-// ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k2_rotate_II(const double *__restrict__ xi1, const double *__restrict__ xi2,
-                             double *__restrict__ p1, double *__restrict__ p2, const double *__restrict__ bz,
-                             const double *__restrict__ az, int64_t n, int M1, int M2, double dt) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double u1 = xi1[i], u2 = xi2[i];
-        const int c1 = (int)u1, c2 = (int)u2;
-        const double t1 = u1 - c1, t2 = u2 - c2;
-        double a1[P + 1], a2[P + 1], b1[P], b2[P];
-        basis_values<P>(t1, a1);
-        basis_values<P>(t2, a2);
-        basis_values<P - 1>(t1, b1);
-        basis_values<P - 1>(t2, b2);
-        double A = 0.0, B = 0.0;
-#pragma unroll
-        for (int m1 = 0; m1 <= P; ++m1) {
-            const int row = wrapi(c1 - m1, M1) * M2;
-            double ta = 0.0, tb = 0.0;
-#pragma unroll
-            for (int m2 = 0; m2 <= P; ++m2) {
-                const int col = wrapi(c2 - m2, M2);
-                ta += a2[m2] * az[row + col];
-                if (m1 < P && m2 < P) tb += b2[m2] * bz[row + col];
-            }
-            A += a1[m1] * ta;
-            if (m1 < P) B += b1[m1] * tb;
-        }
-        const double q1 = p1[i], q2 = p2[i];
-        const double th = B * dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
-        double sn, cs;
-        sincos(th, &sn, &cs);
-        p1[i] = q1 * cs + q2 * sn;
-        p2[i] = -q1 * sn + q2 * cs;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Subsystem III particle term and the charge deposit (tiles, no motion)
 // ---------------------------------------------------------------------------
 struct DepArgs {
@@ -879,9 +840,11 @@ struct DepArgs {
     const double *ezn;   // e_z^n                     (III)
     const double *ezk;   // e_z^(k)                   (III)
     double *S;           // deposit target (zero on entry)
+    double *anp;         // A^n at each particle (III): written on the first iteration, read after
     int M1, M2, TW;
     double dt, w;
     int mode;            // 0: charge w Lambda0; 1: Subsystem III source
+    int first;           // III: first iteration of the substep
 };
 
 // mode 1: S += w (A^n + A^(k)) / (gamma(p, A^n) + gamma(p, A^(k))) Lambda0(x_a),
@@ -900,7 +863,7 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
         const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
         if (a.mode == 1) {
             const double an = a.an[g];
-            sAn[t] = an;
+            if (a.first) sAn[t] = an;
             sAk[t] = an - 0.5 * a.dt * (a.ezn[g] + a.ezk[g]);
         }
         sS[t] = 0.0;
@@ -926,11 +889,16 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
 #pragma unroll
                 for (int m2 = 0; m2 <= P; ++m2) {
                     const int s = (r - m1 - R0) * PC + c2 - m2 - C0;
-                    tn += b2[m2] * sAn[s];
+                    if (a.first) tn += b2[m2] * sAn[s];
                     tk += b2[m2] * sAk[s];
                 }
                 An += b1[m1] * tn;
                 Ak += b1[m1] * tk;
+            }
+            if (a.first) {
+                if (live) a.anp[i] = An;
+            } else {
+                An = a.anp[ii];
             }
             const double q1 = a.p1[ii], q2 = a.p2[ii], pp = 1.0 + q1 * q1 + q2 * q2;
             q = a.w * (An + Ak) / (sqrt(pp + An * An) + sqrt(pp + Ak * Ak));
@@ -949,6 +917,60 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
         const int i = t / PC, j = t - i * PC;
         const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
         if (sS[t] != 0.0) atomicAdd(&a.S[g], sS[t]);
+    }
+}
+
+// Subsystem II over tiles: B_z (V2) and A_z (V0) gathered from the tile's LDS
+// patch, every momentum turned by the angle B_z dt / gamma.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_rotate_tiles(const double *__restrict__ xi1,
+                                                         const double *__restrict__ xi2, double *__restrict__ p1,
+                                                         double *__restrict__ p2, const int32_t *__restrict__ start,
+                                                         const double *__restrict__ bz, const double *__restrict__ az,
+                                                         int M1, int M2, int TW, double dt) {
+    constexpr int PR = P + 1, PCM = TWMAX + P, PS = PR * PCM;
+    __shared__ double sA[PS], sB[PS];
+    const int nseg = M2 / TW;
+    const int tile = tile_of_block();
+    const int r = tile / nseg, c0 = (tile - r * nseg) * TW;
+    const int PC = TW + P;
+    const int R0 = r - P, C0 = c0 - P;
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, M1) * M2 + wrapi(C0 + j, M2);
+        sA[t] = az[g];
+        sB[t] = bz[g];
+    }
+    __syncthreads();
+    const int begin = start[tile], end = start[tile + 1];
+    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c2 = (int)u2;
+        const double t1 = u1 - r, t2 = u2 - c2;
+        double a1[P + 1], a2[P + 1], b1[P], b2[P];
+        basis_values<P>(t1, a1);
+        basis_values<P>(t2, a2);
+        basis_values<P - 1>(t1, b1);
+        basis_values<P - 1>(t2, b2);
+        double A = 0.0, B = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            double ta = 0.0, tb = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) {
+                const int s = (r - m1 - R0) * PC + c2 - m2 - C0;
+                ta += a2[m2] * sA[s];
+                if (m1 < P && m2 < P) tb += b2[m2] * sB[s];
+            }
+            A += a1[m1] * ta;
+            if (m1 < P) B += b1[m1] * tb;
+        }
+        const double q1 = p1[i], q2 = p2[i];
+        const double th = B * dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        p1[i] = q1 * cs + q2 * sn;
+        p2[i] = -q1 * sn + q2 * cs;
     }
 }
 
@@ -1558,8 +1580,9 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
 int substep_II(ecpic2d_ctx *c, double dt) {
     const int A = c->cur;
     timed(c, "rotate_II", [&] {
-        LAUNCH_P(c->P, k2_rotate_II<PP><<<grid_for(c->N), BLOCK, 0, c->stream>>>(
-                           c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->bz, c->az, c->N, c->M1, c->M2, dt));
+        LAUNCH_P(c->P, k2_rotate_tiles<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(
+                           c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->bz, c->az, c->M1, c->M2,
+                           c->TW, dt));
     });
     return ECPIC_OK;
 }
@@ -1579,7 +1602,7 @@ int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     int k;
     for (k = 0; k < c->kmax; ++k) {
         DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->az, c->ezn, c->ezk, c->S,
-                  c->M1, c->M2, c->TW, dt, c->w, 1};
+                  c->pk1, c->M1, c->M2, c->TW, dt, c->w, 1, k == 0};
         timed(c, "deposit_III", [&] { LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
         spectral<1>(c, "solve_III", Ptrs<1>{{c->S}}, 1, OpIII{sy, c->R, c->M2, dt},
                     EpiIII{c->ezk, c->res + 2 * MAXK + k});
@@ -1605,7 +1628,7 @@ void deposit_rho(ecpic2d_ctx *c, double *rho) {
     const int A = c->cur;
     k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(rho, c->Nc, 0.0);
     DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], nullptr, nullptr, nullptr, rho,
-              c->M1, c->M2, c->TW, 0.0, c->w, 0};
+              nullptr, c->M1, c->M2, c->TW, 0.0, c->w, 0, 0};
     LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(a));
 }
 
