@@ -143,6 +143,26 @@ __device__ __forceinline__ int claim_slot(int c, bool live, int32_t *cursor) {
     return b + lane - leader;
 }
 
+// Slot of this lane in counter[key] for the lanes with flag set, one atomic per
+// distinct key among them (the lowest such lane adds the key's lane count and
+// hands the old value on); lanes without flag get an unspecified value.
+__device__ __forceinline__ int wave_claim(int32_t *counter, int key, bool flag) {
+    unsigned long long rem = __builtin_amdgcn_ballot_w64(flag);
+    int slot = 0;
+    while (rem) {
+        const int leader = __builtin_ctzll(rem);
+        const int lk = __shfl(key, leader, WAVE);
+        const bool mine = flag && key == lk;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(mine);
+        int b = 0;
+        if (lane_id() == leader) b = atomicAdd(&counter[lk], __builtin_popcountll(m));
+        b = __shfl(b, leader, WAVE);
+        if (mine) slot = b + rank_in(m);
+        rem &= ~m;
+    }
+    return slot;
+}
+
 // Gauss-Legendre rule with P points on [0, 1] (exact to degree 2P - 1, the degree
 // of a product of a degree-P and a degree-(P-1) spline along a straight path).
 template <int P>
@@ -671,14 +691,24 @@ __global__ void k2_tiles_from_cells(const int32_t *__restrict__ start, int32_t *
         tstart[T] = T == ntiles ? start[Nc] : start[(T / nseg) * M2 + (T - (T / nseg) * nseg) * TW];
 }
 
-// Commit of Subsystem I, one block per tile: x^n + d^(k) and p^(k+1) in place, the
-// particle's new tile, the count of the tile's particles that stay in it and, per
-// destination, the count of those that arrive.
-__global__ __launch_bounds__(BLOCK) void k2_commit_tiles(double *__restrict__ xi1, double *__restrict__ xi2,
-                                                         double *__restrict__ p1, double *__restrict__ p2,
+// New cell coordinate of a particle from its committed increment, wrapped into
+// [0, M); the commit and the re-sort form it with the same operations.
+__device__ __forceinline__ double new_coord(double u, double d, double inv_dx, int M) {
+    double v = fma(d, inv_dx, u);
+    if (v < 0.0) v += (double)M;
+    if (v >= (double)M) v -= (double)M;
+    if (!(v < (double)M) || v < 0.0) v = 0.0;   // -tiny + M rounded to M
+    return v;
+}
+
+// Subsystem I commit, first half (one block per tile): the new tile Tn and the
+// column c of every particle inside it, packed as Tn 64 + c in word[i]; per
+// tile the particles that stay and (by atomics) those that arrive.  The new
+// positions and momenta are written by the re-sort.
+__global__ __launch_bounds__(BLOCK) void k2_commit_tiles(const double *__restrict__ xi1,
+                                                         const double *__restrict__ xi2,
                                                          const double *__restrict__ d1, const double *__restrict__ d2,
-                                                         const double *__restrict__ pk1,
-                                                         const double *__restrict__ pk2, int32_t *__restrict__ tile,
+                                                         int32_t *__restrict__ word,
                                                          const int32_t *__restrict__ tstart, int32_t *__restrict__ tstay,
                                                          int32_t *__restrict__ tarr, int M1, int M2, int TW,
                                                          double inv_dx1, double inv_dx2) {
@@ -687,21 +717,12 @@ __global__ __launch_bounds__(BLOCK) void k2_commit_tiles(double *__restrict__ xi
     const int begin = tstart[T], end = tstart[T + 1];
     int stay = 0;
     for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
-        double u1 = xi1[i] + d1[i] * inv_dx1, u2 = xi2[i] + d2[i] * inv_dx2;
-        if (u1 < 0.0) u1 += (double)M1;
-        if (u1 >= (double)M1) u1 -= (double)M1;
-        if (u2 < 0.0) u2 += (double)M2;
-        if (u2 >= (double)M2) u2 -= (double)M2;
-        if (!(u1 < (double)M1) || u1 < 0.0) u1 = 0.0;   // -tiny + M rounded to M
-        if (!(u2 < (double)M2) || u2 < 0.0) u2 = 0.0;
-        xi1[i] = u1;
-        xi2[i] = u2;
-        p1[i] = pk1[i];
-        p2[i] = pk2[i];
-        const int Tn = (int)u1 * nseg + (int)u2 / TW;
-        tile[i] = Tn;
+        const double u1 = new_coord(xi1[i], d1[i], inv_dx1, M1), u2 = new_coord(xi2[i], d2[i], inv_dx2, M2);
+        const int c2 = (int)u2, sg = c2 / TW;
+        const int Tn = (int)u1 * nseg + sg;
+        word[i] = (Tn << 6) | (c2 - sg * TW);
         if (Tn == T) ++stay;
-        else atomicAdd(&tarr[Tn], 1);
+        wave_claim(tarr, Tn, Tn != T);
     }
 #pragma unroll
     for (int o = WAVE / 2; o > 0; o >>= 1) stay += __shfl_xor(stay, o, WAVE);
@@ -724,108 +745,173 @@ __global__ void k2_tile_counts(const int32_t *__restrict__ tstay, int32_t *__res
     }
 }
 
-// Re-sort by tile, one block per old tile: the particles that stay keep their
-// order (positions from a block prefix, so their writes are contiguous); the few
-// that leave go after the stayers of their new tile, by an atomic cursor.
-__global__ __launch_bounds__(BLOCK) void k2_scatter_tiles(const double *__restrict__ s1, const double *__restrict__ s2,
-                                                          const double *__restrict__ q1, const double *__restrict__ q2,
-                                                          const int32_t *__restrict__ sid, double *__restrict__ d1,
-                                                          double *__restrict__ d2, double *__restrict__ r1,
-                                                          double *__restrict__ r2, int32_t *__restrict__ did,
-                                                          const int32_t *__restrict__ tile,
+// Arrivals listed per new tile: a particle of old tile T whose new tile Tn
+// differs puts its index at mig[tnew[Tn] + tstay[Tn] + k], k from Tn's cursor
+// (the slots after Tn's stayers in the new order).
+__global__ __launch_bounds__(BLOCK) void k2_list_arrivals(const int32_t *__restrict__ word,
                                                           const int32_t *__restrict__ told,
                                                           const int32_t *__restrict__ tnew,
-                                                          const int32_t *__restrict__ tstay, int32_t *__restrict__ tcur) {
-    __shared__ int wtot[BLOCK / WAVE];
-    const int T = blockIdx.x, wid = threadIdx.x / WAVE, nw = blockDim.x / WAVE;
-    const int begin = told[T], end = told[T + 1], base0 = tnew[T];
-    int run = 0;   // stayers placed so far (uniform over the block)
-    for (int base = begin; base < end; base += blockDim.x) {   // uniform over the block
-        const int i = base + threadIdx.x;
-        const bool live = i < end;
-        const int Tn = live ? tile[i] : -1;
-        const bool stay = live && Tn == T;
-        const unsigned long long m = __builtin_amdgcn_ballot_w64(stay);
-        if (lane_id() == 0) wtot[wid] = __builtin_popcountll(m);
-        __syncthreads();
-        int pre = 0, tot = 0;
-        for (int w = 0; w < nw; ++w) {
-            pre += w < wid ? wtot[w] : 0;
-            tot += wtot[w];
-        }
-        __syncthreads();
-        int pos = -1;
-        if (stay) pos = base0 + run + pre + rank_in(m);
-        else if (live) pos = tnew[Tn] + tstay[Tn] + atomicAdd(&tcur[Tn], 1);
-        if (live) {
-            d1[pos] = s1[i];
-            d2[pos] = s2[i];
-            r1[pos] = q1[i];
-            r2[pos] = q2[i];
-            did[pos] = sid[i];
-        }
-        run += tot;
+                                                          const int32_t *__restrict__ tstay, int32_t *__restrict__ tcur,
+                                                          int32_t *__restrict__ mig) {
+    const int T = blockIdx.x;
+    for (int i = told[T] + threadIdx.x; i < told[T + 1]; i += blockDim.x) {
+        const int Tn = word[i] >> 6;
+        const int k = wave_claim(tcur, Tn, Tn != T);
+        if (Tn != T) mig[tnew[Tn] + tstay[Tn] + k] = i;
     }
 }
 
-// Cell sort inside each tile (one block per tile, after the tile scatter): an LDS
-// histogram of the tile's cells and its prefix give every particle its rank in the
-// cell-sorted order, and the tile is written in the transposed layout (tile_pos),
-// so that a coalesced read hands the lanes of a wave particles of different cells
-// again.  Up to INVCAP particles per tile the source of every rank is kept in LDS
-// and the output is written in position order (coalesced stores, reads scattered
-// inside the tile); a fuller tile writes each particle to its position directly.
-constexpr int INVCAP = 8192;
+// Subsystem I commit, second half, and the re-sort in one pass (one block per
+// new tile): the tile's particles are the stayers of its old range and its
+// listed arrivals; an LDS histogram of their new columns and its prefix give
+// each its rank in the cell-sorted order, and the tile is written in the
+// transposed layout (tile_pos), so that a coalesced read hands the lanes of a
+// wave particles of different cells.  Each particle is written with its new
+// position (formed again from x^n and the increment), its momentum p^(k+1)
+// and its id.  When the tile's sources and particles fit INVCAP, every output
+// array passes through LDS (sources read in order, values placed at their new
+// positions, the tile written in order); a fuller tile writes each particle to
+// its position directly.
+constexpr int INVCAP = 6144;
 
-__device__ __forceinline__ int tile_rank(int p, int cnt) {   // inverse of tile_pos
-    const int Q = cnt / WAVE;
-    return p < WAVE * Q ? (p % WAVE) * Q + p / WAVE : p;
-}
+constexpr int SORT_THREADS = 512;
 
-constexpr int SORT_THREADS = 1024;
+struct Resort {
+    const double *xi1, *xi2, *d1, *d2, *pk1, *pk2;
+    const int32_t *sid, *word, *mig, *told, *tnew, *tstay;
+    double *o1, *o2, *r1, *r2;
+    int32_t *did;
+    int M1, M2;
+    double inv_dx1, inv_dx2;
+    __device__ __forceinline__ void put(int j, int i) const {
+        o1[j] = new_coord(xi1[i], d1[i], inv_dx1, M1);
+        o2[j] = new_coord(xi2[i], d2[i], inv_dx2, M2);
+        r1[j] = pk1[i];
+        r2[j] = pk2[i];
+        did[j] = sid[i];
+    }
+};
 
-__global__ __launch_bounds__(SORT_THREADS) void k2_tile_cellsort(const double *__restrict__ s1, const double *__restrict__ s2,
-                                                          const double *__restrict__ q1, const double *__restrict__ q2,
-                                                          const int32_t *__restrict__ sid, double *__restrict__ d1,
-                                                          double *__restrict__ d2, double *__restrict__ r1,
-                                                          double *__restrict__ r2, int32_t *__restrict__ did,
-                                                          const int32_t *__restrict__ tstart, int M2, int TW) {
-    __shared__ int hist[TWMAX], cur[TWMAX];
-    __shared__ int inv[INVCAP];
-    const int T = blockIdx.x, nseg = M2 / TW, c0 = (T - (T / nseg) * nseg) * TW;
-    const int begin = tstart[T], end = tstart[T + 1], cnt = end - begin;
-    for (int k = threadIdx.x; k < TW; k += blockDim.x) hist[k] = 0;
+// Particles per thread whose loads the re-sort issues together.
+constexpr int RB = 4;
+
+__global__ __launch_bounds__(SORT_THREADS) void k2_tile_resort(Resort a) {
+    constexpr int NW = SORT_THREADS / WAVE;
+    __shared__ int hist[WAVE], cur[WAVE];
+    __shared__ int wcnt[NW][WAVE], woff[NW][WAVE];
+    __shared__ int pos[INVCAP];      // new position in the tile of source q (-1: it left)
+    __shared__ double val[INVCAP];   // one output array of the tile, by new position
+    const int T = tile_of_block();
+    const int ob = a.told[T], nold = a.told[T + 1] - ob;
+    const int base = a.tnew[T], cnt = a.tnew[T + 1] - base, arr0 = base + a.tstay[T];
+    const int nsrc = nold + cnt - a.tstay[T];
+    const int nt = blockDim.x, wv = threadIdx.x / WAVE;
+    // source q < nold: old position q of the tile; q >= nold: listed arrival
+    auto source = [&](int q) { return q < nold ? ob + q : a.mig[arr0 + q - nold]; };
+    if (threadIdx.x < WAVE) hist[threadIdx.x] = 0;
+    for (int k = threadIdx.x; k < NW * WAVE; k += nt) wcnt[k / WAVE][k % WAVE] = 0;
     __syncthreads();
-    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) atomicAdd(&hist[(int)s2[i] - c0], 1);
-    __syncthreads();
-    if (threadIdx.x == 0) {   // TW <= 64 entries
-        int run = 0;
-        for (int k = 0; k < TW; ++k) {
-            cur[k] = run;
-            run += hist[k];
-        }
+    // column counts (any order)
+    for (int q0 = threadIdx.x; q0 < nsrc; q0 += RB * nt) {
+        int w[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) w[k] = q0 + k * nt < nsrc ? a.word[source(q0 + k * nt)] : -1;
+#pragma unroll
+        for (int k = 0; k < RB; ++k)
+            if (w[k] >= 0 && (w[k] >> 6) == T) atomicAdd(&hist[w[k] & 63], 1);
     }
     __syncthreads();
-    if (cnt <= INVCAP) {
-        for (int i = begin + threadIdx.x; i < end; i += blockDim.x) inv[atomicAdd(&cur[(int)s2[i] - c0], 1)] = i;
-        __syncthreads();
-        for (int p = threadIdx.x; p < cnt; p += blockDim.x) {
-            const int i = inv[tile_rank(p, cnt)], j = begin + p;
-            d1[j] = s1[i];
-            d2[j] = s2[i];
-            r1[j] = q1[i];
-            r2[j] = q2[i];
-            did[j] = sid[i];
+    if (threadIdx.x < WAVE) {   // exclusive prefix over the 64 columns
+        const int v = hist[threadIdx.x];
+        int inc = v;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int u = __shfl_up(inc, o, WAVE);
+            if ((int)threadIdx.x >= o) inc += u;
         }
-    } else {
-        for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
-            const double x2 = s2[i];
-            const int j = begin + tile_pos(atomicAdd(&cur[(int)x2 - c0], 1), cnt);
-            d1[j] = s1[i];
-            d2[j] = x2;
-            r1[j] = q1[i];
-            r2[j] = q2[i];
-            did[j] = sid[i];
+        cur[threadIdx.x] = inc - v;
+    }
+    __syncthreads();
+    // Stable ranks: the sources in the old cell-sorted order (old rank t at
+    // position tile_pos(t)), then the arrivals, a block of them at a time;
+    // inside a wave the lanes of one column count the lower lanes of that
+    // column, across waves a per-column prefix.  Rank r goes to position
+    // tile_pos(r) of the new tile.
+    const bool direct = cnt > INVCAP || nsrc > INVCAP;
+    for (int t0 = 0; t0 < nsrc; t0 += nt) {   // uniform over the block
+        const int t = t0 + threadIdx.x;
+        int q = -1, key = -1;
+        if (t < nsrc) {
+            q = t < nold ? tile_pos(t, nold) : t;
+            const int w = a.word[source(q)];
+            if ((w >> 6) == T) key = w & 63;
+        }
+        unsigned long long rem = __builtin_amdgcn_ballot_w64(key >= 0);
+        int wr = 0;
+        while (rem) {
+            const int leader = __builtin_ctzll(rem);
+            const int lk = __shfl(key, leader, WAVE);
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(key == lk);
+            if (key == lk) wr = rank_in(m);
+            if (lane_id() == leader) wcnt[wv][lk] = __builtin_popcountll(m);
+            rem &= ~m;
+        }
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            int run = cur[threadIdx.x];
+            for (int v = 0; v < NW; ++v) {
+                const int c = wcnt[v][threadIdx.x];
+                wcnt[v][threadIdx.x] = 0;
+                woff[v][threadIdx.x] = run;
+                run += c;
+            }
+            cur[threadIdx.x] = run;
+        }
+        __syncthreads();
+        if (q >= 0) {
+            const int p = key >= 0 ? tile_pos(woff[wv][key] + wr, cnt) : -1;
+            if (direct) {
+                if (p >= 0) a.put(base + p, source(q));
+            } else {
+                pos[q] = p;
+            }
+        }
+    }
+    if (direct) return;   // uniform over the block
+    // One output array at a time: the old tile read in order (and the
+    // arrivals), each value placed in LDS at its new position, the tile written
+    // in order.
+    for (int f = 0; f < 5; ++f) {
+        __syncthreads();
+        for (int q0 = threadIdx.x; q0 < nsrc; q0 += RB * nt) {
+            int i[RB], p[RB];
+            double v[RB];
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                const int q = q0 + k * nt;
+                p[k] = q < nsrc ? pos[q] : -1;
+                i[k] = p[k] >= 0 ? source(q) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < RB; ++k) {
+                if (i[k] < 0) continue;
+                switch (f) {
+                    case 0: v[k] = new_coord(a.xi1[i[k]], a.d1[i[k]], a.inv_dx1, a.M1); break;
+                    case 1: v[k] = new_coord(a.xi2[i[k]], a.d2[i[k]], a.inv_dx2, a.M2); break;
+                    case 2: v[k] = a.pk1[i[k]]; break;
+                    case 3: v[k] = a.pk2[i[k]]; break;
+                    default: v[k] = (double)a.sid[i[k]]; break;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < RB; ++k)
+                if (i[k] >= 0) val[p[k]] = v[k];
+        }
+        __syncthreads();
+        double *out = f == 0 ? a.o1 : f == 1 ? a.o2 : f == 2 ? a.r1 : a.r2;
+        for (int p = threadIdx.x; p < cnt; p += nt) {
+            if (f < 4) out[base + p] = val[p];
+            else a.did[base + p] = (int32_t)val[p];
         }
     }
 }
@@ -1062,30 +1148,105 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Radix-2 Stockham FFT of n = 2^k points held in LDS at a (t: scratch of n);
-// tw[j] = exp(-2 pi i j / n), j < n/2; INV uses the conjugate twiddles (no
-// scaling).  Returns the buffer that holds the result (a or t).
 template <bool INV>
-__device__ double2 *fft_lds(double2 *a, double2 *t, int n, const double2 *__restrict__ tw) {
-    const int h = n >> 1;
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        const int stride = h / Ns;
-        for (int j = threadIdx.x; j < h; j += blockDim.x) {
-            const int k = j & (Ns - 1);
-            const double2 v0 = a[j];
-            double2 w = tw[k * stride];
-            if (INV) w.y = -w.y;
-            const double2 v1 = cmul(a[j + h], w);
-            const int idx = ((j - k) << 1) + k;
-            t[idx] = make_double2(v0.x + v1.x, v0.y + v1.y);
-            t[idx + Ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+__device__ __forceinline__ double2 mul_i(double2 a) {   // a exp(-+ i pi / 2): -i a forward, +i a inverse
+    return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// DFT of R = 2, 4 or 8 points in registers: X_q = sum_r v_r exp(-+ 2 pi i r q / R)
+// (the + sign for INV).
+template <int R, bool INV>
+__device__ __forceinline__ void dft_reg(double2 (&v)[R]) {
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = make_double2(a.x + b.x, a.y + b.y);
+        v[1] = make_double2(a.x - b.x, a.y - b.y);
+    } else if constexpr (R == 4) {
+        const double2 s02 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y);
+        const double2 d02 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+        const double2 s13 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y);
+        const double2 d13 = mul_i<INV>(make_double2(v[1].x - v[3].x, v[1].y - v[3].y));
+        v[0] = make_double2(s02.x + s13.x, s02.y + s13.y);
+        v[2] = make_double2(s02.x - s13.x, s02.y - s13.y);
+        v[1] = make_double2(d02.x + d13.x, d02.y + d13.y);
+        v[3] = make_double2(d02.x - d13.x, d02.y - d13.y);
+    } else {
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft_reg<4, INV>(e);
+        dft_reg<4, INV>(o);
+        constexpr double c = 0.70710678118654752440;
+        o[1] = cmul(o[1], make_double2(c, INV ? c : -c));
+        o[2] = mul_i<INV>(o[2]);
+        o[3] = cmul(o[3], make_double2(-c, INV ? c : -c));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = make_double2(e[q].x + o[q].x, e[q].y + o[q].y);
+            v[q + 4] = make_double2(e[q].x - o[q].x, e[q].y - o[q].y);
         }
-        __syncthreads();
-        double2 *s = a;
-        a = t;
-        t = s;
     }
-    return a;
+}
+
+// FFT of n = 2^k points (8 <= n <= MAXM), Stockham autosort with radix-8
+// stages and one final radix-2 or radix-4 stage when k is not a multiple of 3.
+// A transform is spread over T = n / 8 threads; thread t holds the 8 values at
+// positions t + m T (m < 8) in x, before and after.  In a stage of radix R
+// after Ns points have been combined, butterfly j = t + q T (q < 8 / R) takes
+// the inputs j + r n / R (x[q + r 8/R]), multiplies input r by
+// w^(r (j mod Ns) n / (Ns R)) with w = exp(-+ 2 pi i / n), and sends output r
+// to (j - j mod Ns) R + j mod Ns + r Ns.  Between stages the values pass
+// through LDS (position p of this transform at lds[base + p sp]); the last
+// stage's outputs are this thread's own positions, so they stay in registers.
+// stw holds w^m for m < n / 2.  Every thread of the block takes part (the
+// stages synchronise the block).
+template <int R, bool INV>
+__device__ __forceinline__ void fft_stage(double2 (&x)[8], int t, int T, int n, int Ns, bool last, double2 *lds,
+                                          int sp, int base, const double2 *stw) {
+    constexpr int Q = 8 / R;
+    const int step = n / (Ns * R), h = n >> 1;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = t + q * T, k = j & (Ns - 1);
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double2 a = x[q + r * Q];
+            if (r > 0) {
+                const int m = r * k * step;
+                double2 w = m < h ? stw[m] : make_double2(-stw[m - h].x, -stw[m - h].y);
+                if (INV) w.y = -w.y;
+                a = cmul(a, w);
+            }
+            v[r] = a;
+        }
+        dft_reg<R, INV>(v);
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (last)
+                x[q + r * Q] = v[r];
+            else
+                lds[base + (o + r * Ns) * sp] = v[r];
+        }
+    }
+    if (!last) {
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = lds[base + (t + m * T) * sp];
+        __syncthreads();
+    }
+}
+
+template <bool INV>
+__device__ void fft8(double2 (&x)[8], int t, int n, double2 *lds, int sp, int base, const double2 *stw) {
+    const int T = n >> 3;
+    const int e = 31 - __clz(n), n8 = e / 3, rem = e % 3;
+    int Ns = 1;
+    for (int s = 0; s < n8; ++s) {
+        fft_stage<8, INV>(x, t, T, n, Ns, s == n8 - 1 && rem == 0, lds, sp, base, stw);
+        Ns <<= 3;
+    }
+    if (rem == 1) fft_stage<2, INV>(x, t, T, n, Ns, true, lds, sp, base, stw);
+    if (rem == 2) fft_stage<4, INV>(x, t, T, n, Ns, true, lds, sp, base, stw);
 }
 
 template <int NB>
@@ -1093,27 +1254,37 @@ struct Ptrs {
     double *p[NB];
 };
 
-// Forward transform along x2 of NB real grids (blockIdx.y picks the grid);
-// zero[b] != 0 zeroes grid b after it is read (the accumulators of the next
-// deposit).
+// Forward transform along x2 of NB real grids, one transform per (grid, row)
+// over M2 / 8 threads; bit b of zero_mask zeroes grid b after it is read (the
+// accumulators of the next deposit).
 template <int NB>
 __global__ __launch_bounds__(BLOCK) void k2_fft_rows_fwd(Ptrs<NB> src, int zero_mask, double2 *__restrict__ Z,
                                                          int M1, int M2, const double2 *__restrict__ tw2) {
-    __shared__ double2 buf[2 * MAXM];
-    const int row = blockIdx.x, b = blockIdx.y;
+    __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
+    const int n = M2, T = n >> 3, per = BLOCK / T;
+    const int fl = threadIdx.x / T, t = threadIdx.x - fl * T, f = blockIdx.x * per + fl;
+    const bool act = f < NB * M1;
+    const int b = act ? f / M1 : 0, row = act ? f - b * M1 : 0;
+    for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) stw[i] = tw2[i];
     double *s = src.p[0];
 #pragma unroll
     for (int q = 1; q < NB; ++q)
         if (b == q) s = src.p[q];
     s += (size_t)row * M2;
-    for (int j = threadIdx.x; j < M2; j += blockDim.x) {
-        buf[j] = make_double2(s[j], 0.0);
-        if ((zero_mask >> b) & 1) s[j] = 0.0;
+    const bool zero = (zero_mask >> b) & 1;
+    double2 x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        x[m] = make_double2(act ? s[t + m * T] : 0.0, 0.0);
+        if (act && zero) s[t + m * T] = 0.0;
     }
     __syncthreads();
-    const double2 *res = fft_lds<false>(buf, buf + M2, M2, tw2);
-    double2 *z = Z + (size_t)b * M1 * M2 + (size_t)row * M2;
-    for (int j = threadIdx.x; j < M2; j += blockDim.x) z[j] = res[j];
+    fft8<false>(x, t, n, lds, 1, fl * n, stw);
+    if (act) {
+        double2 *z = Z + (size_t)b * M1 * M2 + (size_t)row * M2;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) z[t + m * T] = x[m];
+    }
 }
 
 // 1D symbols of the spectral step, per direction (length M1 and M2): the mass
@@ -1124,49 +1295,52 @@ struct Sym {
     const double *m0b, *m1b, *crb, *cib;
 };
 
-// Along x1 for NB grids of the same column: forward transform, the spectral
-// step op(k1, k2, v) on every frequency, then (if op.INVERSE) the inverse
-// transform, written back to Z.
+// Along x1 for NB grids: forward transform of each grid's column, the spectral
+// step op(k1, k2, v) on every frequency (all NB grids at once, in registers),
+// then (if op.INVERSE) the inverse transforms, written back to Z.  The block's
+// BLOCK / (M1 / 8) columns are adjacent and consecutive threads take
+// consecutive columns, so every row access is contiguous; adjacent column
+// groups go to blocks on the same XCD.
 template <int NB, class Op>
 __global__ __launch_bounds__(BLOCK) void k2_fft_cols(double2 *__restrict__ Z, int M1, int M2,
                                                      const double2 *__restrict__ tw1, Op op) {
-    __shared__ double2 buf[(NB + 1) * MAXM];
-    const int col = blockIdx.x;
+    __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
+    const int n = M1, T = n >> 3, per = BLOCK / T;
+    const int c = threadIdx.x % per, t = threadIdx.x / per;
+    const int col = tile_of_block() * per + c;
+    const bool act = col < M2;
     const size_t N = (size_t)M1 * M2;
-    double2 *scratch = buf + NB * M1;
+    for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) stw[i] = tw1[i];
+    double2 x[NB][8];
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-        for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = Z[b * N + (size_t)i * M2 + col];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            x[b][m] = act ? Z[b * N + (size_t)(t + m * T) * M2 + col] : make_double2(0.0, 0.0);
     __syncthreads();
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        double2 *res = fft_lds<false>(buf + b * M1, scratch, M1, tw1);
-        if (res != buf + b * M1) {
-            for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = res[i];
-            __syncthreads();
+    for (int b = 0; b < NB; ++b) fft8<false>(x[b], t, n, lds, per, c, stw);
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            double2 v[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) v[b] = x[b][m];
+            op(t + m * T, col, v);
+#pragma unroll
+            for (int b = 0; b < NB; ++b) x[b][m] = v[b];
         }
     }
-    for (int i = threadIdx.x; i < M1; i += blockDim.x) {
-        double2 v[NB];
+    if constexpr (Op::INVERSE) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) v[b] = buf[b * M1 + i];
-        op(i, col, v);
+        for (int b = 0; b < NB; ++b) fft8<true>(x[b], t, n, lds, per, c, stw);
+        if (act) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) buf[b * M1 + i] = v[b];
-    }
-    __syncthreads();
-    if (!Op::INVERSE) return;
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        double2 *res = fft_lds<true>(buf + b * M1, scratch, M1, tw1);
-        if (res != buf + b * M1) {
-            for (int i = threadIdx.x; i < M1; i += blockDim.x) buf[b * M1 + i] = res[i];
-            __syncthreads();
+                for (int m = 0; m < 8; ++m) Z[b * N + (size_t)(t + m * T) * M2 + col] = x[b][m];
         }
     }
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-        for (int i = threadIdx.x; i < M1; i += blockDim.x) Z[b * N + (size_t)i * M2 + col] = buf[b * M1 + i];
 }
 
 // Inverse transform along x2 of NB grids, scaled by 1/(M1 M2); the real part of
@@ -1175,15 +1349,24 @@ __global__ __launch_bounds__(BLOCK) void k2_fft_cols(double2 *__restrict__ Z, in
 template <int NB, class Epi>
 __global__ __launch_bounds__(BLOCK) void k2_fft_rows_inv(const double2 *__restrict__ Z, int M1, int M2,
                                                          const double2 *__restrict__ tw2, double invN, Epi epi) {
-    __shared__ double2 buf[2 * MAXM];
-    const int row = blockIdx.x, b = blockIdx.y;
+    __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
+    const int n = M2, T = n >> 3, per = BLOCK / T;
+    const int fl = threadIdx.x / T, t = threadIdx.x - fl * T, f = blockIdx.x * per + fl;
+    const bool act = f < NB * M1;
+    const int b = act ? f / M1 : 0, row = act ? f - b * M1 : 0;
+    for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) stw[i] = tw2[i];
     const double2 *z = Z + (size_t)b * M1 * M2 + (size_t)row * M2;
-    for (int j = threadIdx.x; j < M2; j += blockDim.x) buf[j] = z[j];
+    double2 x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) x[m] = act ? z[t + m * T] : make_double2(0.0, 0.0);
     __syncthreads();
-    const double2 *res = fft_lds<true>(buf, buf + M2, M2, tw2);
-    double m = 0.0;
-    for (int j = threadIdx.x; j < M2; j += blockDim.x) m = fmax(m, epi(b, row * M2 + j, res[j].x * invN));
-    if (epi.res) block_max_to(m, epi.res);
+    fft8<true>(x, t, n, lds, 1, fl * n, stw);
+    double mx = 0.0;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) mx = fmax(mx, epi(b, row * M2 + t + m * T, x[m].x * invN));
+    }
+    if (epi.res) block_max_to(mx, epi.res);
 }
 
 // ---- spectral steps -------------------------------------------------------
@@ -1368,7 +1551,9 @@ struct ecpic2d_ctx {
     double *xi1[2] = {}, *xi2[2] = {}, *p1[2] = {}, *p2[2] = {};
     int32_t *id[2] = {};
     double *d1[2] = {}, *d2[2] = {}, *pk1 = nullptr, *pk2 = nullptr;
-    int32_t *cell = nullptr /* new cell (set_particles) or new tile (commit) */, *count = nullptr, *start = nullptr, *bsum = nullptr;
+    int32_t *cell = nullptr /* new cell (set_particles) or packed new tile and column (commit) */, *count = nullptr,
+            *start = nullptr, *bsum = nullptr;
+    int32_t *mig = nullptr;   // arrivals per new tile, after the stayers' slots
     int32_t *tstart[2] = {}, *tstay = nullptr, *tarr = nullptr, *tcnt = nullptr, *tcur = nullptr;
     int ts = 0, ntiles = 0;   // tstart[ts]: first particle of each tile
     double *e1 = nullptr, *e2 = nullptr, *bz = nullptr, *ez = nullptr, *az = nullptr;
@@ -1460,11 +1645,11 @@ void sort_particles(ecpic2d_ctx *c) {
     c->cur = B;
 }
 
-// Re-sort after a Subsystem I commit (new tiles in c->cell, stay and arrival
-// counts from the commit): move the particles to their new tiles (those that
-// stay keep their order, the arrivals follow), then sort each tile by cell into
-// the transposed layout.
-void sort_tiles(ecpic2d_ctx *c) {
+// Re-sort after the first half of a Subsystem I commit (packed new tile and
+// column in c->cell, stay and arrival counts per tile; increment in buffer di):
+// new tile starts, the arrival lists, then each new tile formed and sorted by
+// cell into the transposed layout in the other particle buffer.
+void sort_tiles(ecpic2d_ctx *c, int di) {
     const int A = c->cur, B = 1 - c->cur, T0 = c->ts, T1 = 1 - c->ts;
     timed(c, "sort", [&] {
         const int nt = c->ntiles, nb = (nt + SCAN_TILE - 1) / SCAN_TILE;
@@ -1472,25 +1657,29 @@ void sort_tiles(ecpic2d_ctx *c) {
         k2_scan_sums<<<nb, SCAN_THREADS, 0, c->stream>>>(c->tcnt, c->bsum, nt);
         k2_scan_top<<<1, SCAN_THREADS, 0, c->stream>>>(c->bsum, nb, c->tstart[T1] + nt);
         k2_scan_apply<<<nb, SCAN_THREADS, 0, c->stream>>>(c->tcnt, c->tstart[T1], c->bsum, nt);
-        k2_scatter_tiles<<<nt, BLOCK, 0, c->stream>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->xi1[B],
-                                                     c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->cell,
-                                                     c->tstart[T0], c->tstart[T1], c->tstay, c->tcur);
-        k2_tile_cellsort<<<nt, SORT_THREADS, 0, c->stream>>>(c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B], c->xi1[A],
-                                                     c->xi2[A], c->p1[A], c->p2[A], c->id[A], c->tstart[T1], c->M2,
-                                                     c->TW);
+        k2_list_arrivals<<<nt, BLOCK, 0, c->stream>>>(c->cell, c->tstart[T0], c->tstart[T1], c->tstay, c->tcur,
+                                                     c->mig);
+        const Resort r{c->xi1[A], c->xi2[A], c->d1[di], c->d2[di], c->pk1, c->pk2, c->id[A], c->cell, c->mig,
+                       c->tstart[T0], c->tstart[T1], c->tstay, c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
+                       c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2};
+        k2_tile_resort<<<nt, SORT_THREADS, 0, c->stream>>>(r);
     });
-    c->ts = T1;   // the particles are back in buffer A
+    c->cur = B;
+    c->ts = T1;
 }
 
 // Forward rows -> columns with op -> inverse rows with epi, over NB grids.
 template <int NB, class Op, class Epi>
 void spectral(ecpic2d_ctx *c, const char *name, Ptrs<NB> src, int zero_mask, Op op, Epi epi) {
     timed(c, name, [&] {
-        k2_fft_rows_fwd<NB><<<dim3(c->M1, NB), BLOCK, 0, c->stream>>>(src, zero_mask, c->Z, c->M1, c->M2, c->tw2);
-        k2_fft_cols<NB, Op><<<c->M2, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw1, op);
+        // transforms per block: BLOCK / (n / 8) for n points
+        const int rows = NB * c->M1, per_row = BLOCK / (c->M2 / 8), per_col = BLOCK / (c->M1 / 8);
+        const int grow = (rows + per_row - 1) / per_row, gcol = (c->M2 + per_col - 1) / per_col;
+        k2_fft_rows_fwd<NB><<<grow, BLOCK, 0, c->stream>>>(src, zero_mask, c->Z, c->M1, c->M2, c->tw2);
+        k2_fft_cols<NB, Op><<<gcol, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw1, op);
         if (Op::INVERSE)
-            k2_fft_rows_inv<NB, Epi><<<dim3(c->M1, NB), BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw2,
-                                                                              1.0 / (double)c->Nc, epi);
+            k2_fft_rows_inv<NB, Epi><<<grow, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw2, 1.0 / (double)c->Nc,
+                                                                  epi);
     });
 }
 
@@ -1565,15 +1754,16 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     }
     if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
     if (k == c->kmax) return ECPIC_ENOTCONV;
-    // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1), then re-sort by tile
+    // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1): new tiles and counts, the
+    // fields, then the re-sort writes the particles in their new order
     timed(c, "commit_I", [&] {
-        k2_commit_tiles<<<c->ntiles, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di],
-                                                    c->pk1, c->pk2, c->cell, c->tstart[c->ts], c->tstay, c->tarr,
-                                                    c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2);
+        k2_commit_tiles<<<c->ntiles, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->d1[di], c->d2[di], c->cell,
+                                                    c->tstart[c->ts], c->tstay, c->tarr, c->M1, c->M2, c->TW,
+                                                    1.0 / c->dx1, 1.0 / c->dx2);
     });
     k2_copy<<<gC, BLOCK, 0, s>>>(c->e1, c->ek1, Nc);
     k2_copy<<<gC, BLOCK, 0, s>>>(c->e2, c->ek2, Nc);
-    sort_tiles(c);
+    sort_tiles(c, di);
     return sync2(c);
 }
 
@@ -1696,9 +1886,8 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
               dalloc(c, &c->p2[b], N) | dalloc(c, &c->id[b], N) | dalloc(c, &c->d1[b], N) |
               dalloc(c, &c->d2[b], N);
     }
-    rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->count, Nc) |
-          dalloc(c, &c->start, Nc + 1) |
-          dalloc(c, &c->bsum, Nc / SCAN_TILE + 2);
+    rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->mig, N) |
+          dalloc(c, &c->count, Nc) | dalloc(c, &c->start, Nc + 1) | dalloc(c, &c->bsum, Nc / SCAN_TILE + 2);
     c->ntiles = c->M1 * (c->M2 / c->TW);
     rc |= dalloc(c, &c->tstart[0], (size_t)c->ntiles + 1) | dalloc(c, &c->tstart[1], (size_t)c->ntiles + 1) |
           dalloc(c, &c->tstay, (size_t)c->ntiles) | dalloc(c, &c->tarr, (size_t)c->ntiles) |

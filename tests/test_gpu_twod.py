@@ -105,6 +105,54 @@ def test_substep_IV_matches_oracle(name):
         assert ctx.gauss_residual() < 1e-13
 
 
+def _min_image(d, L):
+    return np.mod(d + L / 2, L) - L / 2
+
+
+@pytest.mark.parametrize("M1,M2,degree", [(32, 64, 2), (128, 256, 3), (256, 8, 3)])
+def test_spectral_solves_at_other_transform_lengths(M1, M2, degree):
+    """Grids whose FFT lengths take the radix-8 stages with a radix-4 or radix-2
+    last stage (32, 128, 256) and a single block of columns (M2 = 8).  The
+    oracle's own solves take minutes here, so the GPU state is checked against
+    the scheme's relations through the oracle's operators: the Gauss law after
+    the load, M1 (e^{n+1} - e^n) = -J(path) after Subsystem I, the Subsystem III
+    pair (a and e_z, particle term evaluated at the particles), the implicit
+    midpoint pair of Subsystem IV."""
+    w = get2d("twod16").scaled(M1=M1, M2=M2, degree=degree, n_particles=600, L1=0.6 * M1, L2=0.6 * M2)
+    o = Oracle2D.from_workload(w)
+    p, N, dt, wt = degree, o.N, w.dt, o.cfg.w
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(generate2d(w))
+        s0 = ctx.state()
+        assert o.gauss_residual(s0) < 1e-12 * w.dx1 * w.dx2
+        ctx.substep_I()
+        s1 = ctx.state()
+        J = np.zeros(2 * N)
+        for a in range(w.n_particles):
+            xa = np.array([s0["x1"][a], s0["x2"][a]])
+            d = np.array([_min_image(s1["x1"][a] - xa[0], w.L1), _min_image(s1["x2"][a] - xa[1], w.L2)])
+            o.line_deposit(p - 1, p, xa, xa + d, wt * d[0], J[:N])
+            o.line_deposit(p, p - 1, xa, xa + d, wt * d[1], J[N:])
+        assert np.abs(o.M1(s1["e"] - s0["e"]) + J).max() < 1e-11 * np.abs(J).max()
+        ctx.substep_II()
+        s2 = ctx.state()
+        ctx.substep_III()
+        s3 = ctx.state()
+        assert rel((s3["az"] - s2["az"]) / dt, -0.5 * (s2["ez"] + s3["ez"])) < 1e-12
+        S = np.zeros(N)
+        for a in range(w.n_particles):
+            x = (s2["x1"][a], s2["x2"][a])
+            An, A1 = o.eval(s2["az"], p, p, *x), o.eval(s3["az"], p, p, *x)
+            q2 = 1 + s2["p1"][a] ** 2 + s2["p2"][a] ** 2
+            o.line_deposit(p, p, x, x, wt * (An + A1) / (math.sqrt(q2 + An * An) + math.sqrt(q2 + A1 * A1)), S)
+        assert rel(o.M0(s3["ez"] - s2["ez"]) / dt, o.K(0.5 * (s2["az"] + s3["az"])) + S) < 1e-11
+        ctx.substep_IV()
+        s4 = ctx.state()
+        assert rel(o.M1(s4["e"] - s3["e"]) / dt, o.CT(o.M2(0.5 * (s3["bz"] + s4["bz"])))) < 1e-11
+        assert rel((s4["bz"] - s3["bz"]) / dt, -o.C(0.5 * (s3["e"] + s4["e"]))) < 1e-11
+        assert o.gauss_residual(s4) < 1e-12 * w.dx1 * w.dx2
+
+
 def test_lie_steps_match_oracle_and_conserve():
     w, o, s, ctx = setup("twod16", n=1500)
     with ctx:
@@ -118,6 +166,19 @@ def test_lie_steps_match_oracle_and_conserve():
         H1 = ctx.energy()
         np.testing.assert_allclose(H1, o.energy(s), rtol=1e-11, atol=1e-14)
         assert abs(H1[5] - H0[5]) <= 1e-12 * H0[5]
+        assert ctx.gauss_residual() < 1e-13
+
+
+def test_dense_tiles_take_the_direct_resort():
+    """About 10^4 particles per tile (8 x 16 cells, one 16-cell tile per row):
+    more than the re-sort keeps in LDS, so every tile is written by the direct
+    path; one Lie step against the oracle and the tile order afterwards."""
+    w, o, s, ctx = setup("twod8x16", n=80000)
+    with ctx:
+        kg, kIIIg = ctx.step(1)
+        st, ko, kIIIo = o.step(s, 1)
+        assert st == 0 and np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
+        compare(w, ctx.state(), s, 1e-11)
         assert ctx.gauss_residual() < 1e-13
 
 
