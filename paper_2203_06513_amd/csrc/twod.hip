@@ -375,29 +375,12 @@ __device__ __forceinline__ double gather00(const double *__restrict__ f, int M1,
     return s;
 }
 
-// Explicit start of the Picard iteration: d = dt p / gamma(x^n, p^n).
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k2_init_I(const double *__restrict__ xi1, const double *__restrict__ xi2,
-                          const double *__restrict__ p1, const double *__restrict__ p2,
-                          const double *__restrict__ az, double *__restrict__ d1, double *__restrict__ d2, int64_t n,
-                          int M1, int M2, double dt) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const double u1 = xi1[i], u2 = xi2[i];
-        const int c1 = (int)u1, c2 = (int)u2;
-        const double A = gather00<P>(az, M1, M2, c1, c2, u1 - c1, u2 - c2);
-        const double q1 = p1[i], q2 = p2[i];
-        const double s = dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
-        d1[i] = q1 * s;
-        d2[i] = q2 * s;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Subsystem I sweep (Section 4.3): gather, push, deposit, one tile per block
 // ---------------------------------------------------------------------------
 struct SweepArgs {
     const double *xi1, *xi2, *p1, *p2;   // sorted particles
-    const double *d1, *d2;               // increment d^(k) (physical)
+    double *d1, *d2;                     // increment d^(k) (physical); formed and stored by sweep 0
     double *dn1, *dn2;                   // increment d^(k+1)
     double *pk1, *pk2;                   // momentum p^(k+1)
     const int32_t *start;                // first particle of each tile (ntiles + 1)
@@ -598,8 +581,12 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
 constexpr int QCAP = 2 * WAVE;
 constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
+// FIRST (sweep 0): the increment is the explicit start d^(0) = dt p^n /
+// gamma(x^n, p^n), formed from A_z on the patch and stored; that variant is held
+// to three waves per SIMD (168 VGPRs) at p = 3, like the others.
+template <int P, bool FIRST>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && P == 3 ? 3 : 1))) void k2_sweep_I(
+    SweepArgs a) {
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
     __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
     __shared__ int qI[BLOCK / WAVE][QCAP];
@@ -648,7 +635,32 @@ __global__ __launch_bounds__(BLOCK) void k2_sweep_I(SweepArgs a) {
         const int i = begin + jr * WAVE + lane;
         const bool live = i < end;
         const int ii = live ? i : begin;
-        const double x1 = a.xi1[ii], x2 = a.xi2[ii], q1 = a.p1[ii], q2 = a.p2[ii], D1 = a.d1[ii], D2 = a.d2[ii];
+        const double x1 = a.xi1[ii], x2 = a.xi2[ii], q1 = a.p1[ii], q2 = a.p2[ii];
+        double D1, D2;
+        if constexpr (FIRST) {
+            const int c2 = (int)x2;
+            double b1[P + 1], b2[P + 1];
+            basis_values<P>(x1 - r, b1);
+            basis_values<P>(x2 - c2, b2);
+            double A = 0.0;
+#pragma unroll
+            for (int m1 = 0; m1 <= P; ++m1) {
+                double ta = 0.0;
+#pragma unroll
+                for (int m2 = 0; m2 <= P; ++m2) ta += b2[m2] * t.A[(r - m1 - t.R0) * PC + c2 - m2 - t.C0];
+                A += b1[m1] * ta;
+            }
+            const double sc = a.dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+            D1 = q1 * sc;
+            D2 = q2 * sc;
+            if (live) {
+                a.d1[i] = D1;
+                a.d2[i] = D2;
+            }
+        } else {
+            D1 = a.d1[ii];
+            D2 = a.d2[ii];
+        }
         const Geo g = geometry(a, x1, x2, q1, q2, D1, D2, live, r, flags);
         double E1 = 0.0, E2 = 0.0;
         pieces<P>(g, live, 0, 0, t, a.w, E1, E2);
@@ -1714,7 +1726,7 @@ double read_res(ecpic2d_ctx *c, int slot, int *rc) {
     }
 
 int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
-    const int A = c->cur, Nc = c->Nc, gN = grid_for(c->N), gC = grid_for(Nc);
+    const int A = c->cur, Nc = c->Nc, gC = grid_for(Nc);
     hipStream_t s = c->stream;
     k2_fill_u64<<<1, 2 * MAXK, 0, s>>>(c->res, 2 * MAXK);
     k2_fill_i32<<<1, 1, 0, s>>>(c->flags, 1);
@@ -1728,8 +1740,6 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     k2_fill<<<gC, BLOCK, 0, s>>>(c->J1, Nc, 0.0);
     k2_fill<<<gC, BLOCK, 0, s>>>(c->J2, Nc, 0.0);
     int di = 0;
-    LAUNCH_P(c->P, k2_init_I<PP><<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->az, c->d1[0],
-                                                       c->d2[0], c->N, c->M1, c->M2, dt));
     const Sym sy = sym_of(c);
     double r = 0.0;
     int k;
@@ -1737,7 +1747,13 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
         SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
                     c->pk1, c->pk2, c->tstart[c->ts], c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
                     c->res + k, c->flags, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
-        timed(c, "sweep_I", [&] { LAUNCH_P(c->P, k2_sweep_I<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
+        timed(c, "sweep_I", [&] {
+            if (k == 0) {
+                LAUNCH_P(c->P, k2_sweep_I<PP, true><<<n_tiles(c), BLOCK, 0, s>>>(a));
+            } else {
+                LAUNCH_P(c->P, k2_sweep_I<PP, false><<<n_tiles(c), BLOCK, 0, s>>>(a));
+            }
+        });
         spectral<2>(c, "solve_I", Ptrs<2>{{c->J1, c->J2}}, 3, OpM1inv{sy},
                     EpiI{c->en1, c->en2, c->ek1, c->ek2, c->eb1, c->eb2, c->res + MAXK + k});
         unsigned long long b[2];
