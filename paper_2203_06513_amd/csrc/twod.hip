@@ -389,6 +389,7 @@ struct SweepArgs {
     double *J1, *J2;                     // current of d^(k) (accumulated, zero on entry)
     unsigned long long *res;             // max |d^(k+1) - d^(k)|, as bits
     int *flags;
+    const int *gate;                     // nonzero: an earlier sweep converged, nothing to do
     int M1, M2, TW;
     double inv_dx1, inv_dx2, dt, w;
 };
@@ -587,6 +588,7 @@ constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 template <int P, bool FIRST>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && P == 3 ? 3 : 1))) void k2_sweep_I(
     SweepArgs a) {
+    if (*a.gate) return;   // uniform over the grid
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
     __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
     __shared__ int qI[BLOCK / WAVE][QCAP];
@@ -943,12 +945,14 @@ struct DepArgs {
     double dt, w;
     int mode;            // 0: charge w Lambda0; 1: Subsystem III source
     int first;           // III: first iteration of the substep
+    const int *gate;     // III: nonzero once an earlier iteration converged (nothing to do)
 };
 
 // mode 1: S += w (A^n + A^(k)) / (gamma(p, A^n) + gamma(p, A^(k))) Lambda0(x_a),
 // with A^(k) the field of a^(k) = a^n - dt (e^n + e^(k)) / 2.
 template <int P>
 __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
+    if (a.gate && *a.gate) return;   // uniform over the grid
     constexpr int PR = P + 1, PCM = TWMAX + P, PS = PR * PCM;
     __shared__ double sAn[PS], sAk[PS], sS[PS];
     const int nseg = a.M2 / a.TW;
@@ -1153,6 +1157,25 @@ __global__ __launch_bounds__(BLOCK) void k2_gauss(const double *__restrict__ u1,
     block_max_to(m, res);
 }
 
+// End of one fixed-point iteration (unless an earlier one converged): its
+// residuals ra, rb (rb may be null) and the status flags (may be null) go to
+// the host mirror h[0..2], and the gate closes when a flag is set, a residual
+// is not finite, or the larger one is at most tol: the conditions on which the
+// host stops at this iteration.
+__global__ void k2_check(const unsigned long long *ra, const unsigned long long *rb, const int *flags, double tol,
+                         int *gate, double *h) {
+    if (*gate) return;
+    double a, b = 0.0;
+    const unsigned long long ba = *ra, bb = rb ? *rb : 0ull;
+    memcpy(&a, &ba, sizeof(a));
+    memcpy(&b, &bb, sizeof(b));
+    const int f = flags ? *flags : 0;
+    h[0] = a;
+    h[1] = b;
+    h[2] = (double)f;
+    if (f || !isfinite(a) || !isfinite(b) || fmax(a, b) <= tol) *gate = 1;
+}
+
 // ---------------------------------------------------------------------------
 // Spectral solves: 2D FFT (rows, then columns with the spectral step fused)
 // ---------------------------------------------------------------------------
@@ -1271,7 +1294,9 @@ struct Ptrs {
 // accumulators of the next deposit).
 template <int NB>
 __global__ __launch_bounds__(BLOCK) void k2_fft_rows_fwd(Ptrs<NB> src, int zero_mask, double2 *__restrict__ Z,
-                                                         int M1, int M2, const double2 *__restrict__ tw2) {
+                                                         int M1, int M2, const double2 *__restrict__ tw2,
+                                                         const int *gate) {
+    if (gate && *gate) return;   // uniform over the grid
     __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
     const int n = M2, T = n >> 3, per = BLOCK / T;
     const int fl = threadIdx.x / T, t = threadIdx.x - fl * T, f = blockIdx.x * per + fl;
@@ -1315,7 +1340,8 @@ struct Sym {
 // groups go to blocks on the same XCD.
 template <int NB, class Op>
 __global__ __launch_bounds__(BLOCK) void k2_fft_cols(double2 *__restrict__ Z, int M1, int M2,
-                                                     const double2 *__restrict__ tw1, Op op) {
+                                                     const double2 *__restrict__ tw1, Op op, const int *gate) {
+    if (gate && *gate) return;   // uniform over the grid
     __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
     const int n = M1, T = n >> 3, per = BLOCK / T;
     const int c = threadIdx.x % per, t = threadIdx.x / per;
@@ -1360,7 +1386,9 @@ __global__ __launch_bounds__(BLOCK) void k2_fft_cols(double2 *__restrict__ Z, in
 // into epi.res (if set).
 template <int NB, class Epi>
 __global__ __launch_bounds__(BLOCK) void k2_fft_rows_inv(const double2 *__restrict__ Z, int M1, int M2,
-                                                         const double2 *__restrict__ tw2, double invN, Epi epi) {
+                                                         const double2 *__restrict__ tw2, double invN, Epi epi,
+                                                         const int *gate) {
+    if (gate && *gate) return;   // uniform over the grid
     __shared__ double2 lds[8 * BLOCK], stw[MAXM / 2];
     const int n = M2, T = n >> 3, per = BLOCK / T;
     const int fl = threadIdx.x / T, t = threadIdx.x - fl * T, f = blockIdx.x * per + fl;
@@ -1407,7 +1435,7 @@ struct EpiI {
         const double d = fabs(e - ek[g]);
         ek[g] = e;
         eb[g] = 0.5 * (en + e);
-        return d;
+        return isfinite(d) ? d : HUGE_VAL;   // a non-finite field shows in the residual
     }
 };
 
@@ -1451,7 +1479,7 @@ struct EpiIII {
     __device__ double operator()(int, int g, double v) const {
         const double d = fabs(v - ezk[g]);
         ezk[g] = v;
-        return d;
+        return isfinite(d) ? d : HUGE_VAL;   // a non-finite field shows in the residual
     }
 };
 
@@ -1577,6 +1605,9 @@ struct ecpic2d_ctx {
     double *partial = nullptr;    // RED_BLOCKS + 8
     unsigned long long *res = nullptr;   // 3 * MAXK + 4 slots
     int *flags = nullptr;
+    int *gate = nullptr;                 // set once an iteration has converged (or failed)
+    double *hres = nullptr, *hres_dev = nullptr;   // pinned mirror: 3 values per iteration (I, then III)
+    hipEvent_t ev[2] = {};
     bool have_particles = false;
     std::vector<double> m0row, m1row;
     Prof2 prof;
@@ -1682,17 +1713,27 @@ void sort_tiles(ecpic2d_ctx *c, int di) {
 
 // Forward rows -> columns with op -> inverse rows with epi, over NB grids.
 template <int NB, class Op, class Epi>
-void spectral(ecpic2d_ctx *c, const char *name, Ptrs<NB> src, int zero_mask, Op op, Epi epi) {
+void spectral(ecpic2d_ctx *c, const char *name, Ptrs<NB> src, int zero_mask, Op op, Epi epi,
+              const int *gate = nullptr) {
     timed(c, name, [&] {
         // transforms per block: BLOCK / (n / 8) for n points
         const int rows = NB * c->M1, per_row = BLOCK / (c->M2 / 8), per_col = BLOCK / (c->M1 / 8);
         const int grow = (rows + per_row - 1) / per_row, gcol = (c->M2 + per_col - 1) / per_col;
-        k2_fft_rows_fwd<NB><<<grow, BLOCK, 0, c->stream>>>(src, zero_mask, c->Z, c->M1, c->M2, c->tw2);
-        k2_fft_cols<NB, Op><<<gcol, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw1, op);
+        k2_fft_rows_fwd<NB><<<grow, BLOCK, 0, c->stream>>>(src, zero_mask, c->Z, c->M1, c->M2, c->tw2, gate);
+        k2_fft_cols<NB, Op><<<gcol, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw1, op, gate);
         if (Op::INVERSE)
             k2_fft_rows_inv<NB, Epi><<<grow, BLOCK, 0, c->stream>>>(c->Z, c->M1, c->M2, c->tw2, 1.0 / (double)c->Nc,
-                                                                  epi);
+                                                                  epi, gate);
     });
+}
+
+// Host view of one iteration's mirror (residuals h[0], h[1], flags h[2]).
+int status_of(const double *h) {
+    const int f = (int)h[2];
+    if (f & FLAG_NONFINITE) return ECPIC_ENONFINITE;
+    if (f & FLAG_CFL) return ECPIC_ECFL;
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return ECPIC_ENONFINITE;
+    return ECPIC_OK;
 }
 
 int flags_status(ecpic2d_ctx *c) {
@@ -1739,14 +1780,15 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     k2_copy<<<gC, BLOCK, 0, s>>>(c->eb2, c->e2, Nc);
     k2_fill<<<gC, BLOCK, 0, s>>>(c->J1, Nc, 0.0);
     k2_fill<<<gC, BLOCK, 0, s>>>(c->J2, Nc, 0.0);
-    int di = 0;
+    k2_fill_i32<<<1, 1, 0, s>>>(c->gate, 1);
     const Sym sy = sym_of(c);
-    double r = 0.0;
-    int k;
-    for (k = 0; k < c->kmax; ++k) {
+    // Sweep k reads d^(k) from buffer k & 1 and writes d^(k+1) to the other;
+    // then the field update, the check, and event ev[k & 1].
+    auto iterate = [&](int k) {
+        const int di = k & 1;
         SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
                     c->pk1, c->pk2, c->tstart[c->ts], c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
-                    c->res + k, c->flags, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
+                    c->res + k, c->flags, c->gate, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
         timed(c, "sweep_I", [&] {
             if (k == 0) {
                 LAUNCH_P(c->P, k2_sweep_I<PP, true><<<n_tiles(c), BLOCK, 0, s>>>(a));
@@ -1755,19 +1797,33 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
             }
         });
         spectral<2>(c, "solve_I", Ptrs<2>{{c->J1, c->J2}}, 3, OpM1inv{sy},
-                    EpiI{c->en1, c->en2, c->ek1, c->ek2, c->eb1, c->eb2, c->res + MAXK + k});
-        unsigned long long b[2];
-        hipMemcpyAsync(&b[0], c->res + k, sizeof(b[0]), hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(&b[1], c->res + MAXK + k, sizeof(b[1]), hipMemcpyDeviceToHost, s);
-        int rc = flags_status(c);
-        if (rc) return rc;
-        double rx, re;
-        std::memcpy(&rx, &b[0], sizeof(rx));
-        std::memcpy(&re, &b[1], sizeof(re));
-        r = std::max(rx, re);
+                    EpiI{c->en1, c->en2, c->ek1, c->ek2, c->eb1, c->eb2, c->res + MAXK + k}, c->gate);
+        k2_check<<<1, 1, 0, s>>>(c->res + k, c->res + MAXK + k, c->flags, c->tol, c->gate, c->hres_dev + 3 * k);
+        hipEventRecord(c->ev[k & 1], s);
+    };
+    // Iteration k + 1 is queued before iteration k is read back, so the GPU
+    // does not wait for the host; it does nothing if iteration k closed the gate.
+    // With kernel timing on, iterations are queued one at a time (every timed
+    // launch does its work).
+    const bool ahead = !c->prof.on;
+    double r = 0.0;
+    int k, rc = ECPIC_OK;
+    iterate(0);
+    for (k = 0; k < c->kmax; ++k) {
+        if (ahead && k + 1 < c->kmax) iterate(k + 1);
+        if (hipEventSynchronize(c->ev[k & 1]) != hipSuccess) return ECPIC_EDEVICE;
+        const double *h = c->hres + 3 * k;
+        rc = status_of(h);
+        if (rc) break;
+        r = std::max(h[0], h[1]);
         if (r <= c->tol) break;
-        di = 1 - di;
+        if (!ahead && k + 1 < c->kmax) iterate(k + 1);
     }
+    if (rc) {
+        sync2(c);
+        return rc;
+    }
+    const int di = k & 1;
     if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
     if (k == c->kmax) return ECPIC_ENOTCONV;
     // commit x^n + d^(k) (buffer di), p^(k+1), e^(k+1): new tiles and counts, the
@@ -1804,19 +1860,34 @@ int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     // constant part in Fourier space
     spectral<2>(c, "solve_III", Ptrs<2>{{c->ezn, c->az}}, 0, OpIIIrhs{sy, c->R, c->M2, dt},
                 EpiStore<2>{Ptrs<2>{{nullptr, nullptr}}, nullptr});
-    double r = 0.0;
-    int k;
-    for (k = 0; k < c->kmax; ++k) {
+    k2_fill_i32<<<1, 1, 0, s>>>(c->gate, 1);
+    auto iterate = [&](int k) {   // as in Subsystem I: deposit, solve, check, event ev[k & 1]
         DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->az, c->ezn, c->ezk, c->S,
-                  c->pk1, c->M1, c->M2, c->TW, dt, c->w, 1, k == 0};
+                  c->pk1, c->M1, c->M2, c->TW, dt, c->w, 1, k == 0, c->gate};
         timed(c, "deposit_III", [&] { LAUNCH_P(c->P, k2_deposit0<PP><<<n_tiles(c), BLOCK, 0, s>>>(a)); });
         spectral<1>(c, "solve_III", Ptrs<1>{{c->S}}, 1, OpIII{sy, c->R, c->M2, dt},
-                    EpiIII{c->ezk, c->res + 2 * MAXK + k});
-        int rc = 0;
-        r = read_res(c, 2 * MAXK + k, &rc);
-        if (rc) return rc;
-        if (!std::isfinite(r)) return ECPIC_ENONFINITE;
+                    EpiIII{c->ezk, c->res + 2 * MAXK + k}, c->gate);
+        k2_check<<<1, 1, 0, s>>>(c->res + 2 * MAXK + k, nullptr, nullptr, c->tol, c->gate,
+                                 c->hres_dev + 3 * (MAXK + k));
+        hipEventRecord(c->ev[k & 1], s);
+    };
+    const bool ahead = !c->prof.on;
+    double r = 0.0;
+    int k, rc = ECPIC_OK;
+    iterate(0);
+    for (k = 0; k < c->kmax; ++k) {
+        if (ahead && k + 1 < c->kmax) iterate(k + 1);
+        if (hipEventSynchronize(c->ev[k & 1]) != hipSuccess) return ECPIC_EDEVICE;
+        const double *h = c->hres + 3 * (MAXK + k);
+        rc = status_of(h);
+        if (rc) break;
+        r = h[0];
         if (r <= c->tol) break;
+        if (!ahead && k + 1 < c->kmax) iterate(k + 1);
+    }
+    if (rc) {
+        sync2(c);
+        return rc;
     }
     if (st) { st->sweeps = std::min(k + 1, c->kmax); st->residual = r; st->reserved = 0; }
     if (k == c->kmax) return ECPIC_ENOTCONV;
@@ -1913,8 +1984,18 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     for (double **gp : grids) rc |= dalloc(c, gp, Nc);
     rc |= dalloc(c, &c->Z, 3 * Nc) | dalloc(c, &c->R, Nc) | dalloc(c, &c->tw1, (size_t)c->M1 / 2) |
           dalloc(c, &c->tw2, (size_t)c->M2 / 2) | dalloc(c, &c->sym, 4 * (size_t)(c->M1 + c->M2)) |
-          dalloc(c, &c->partial, RED_BLOCKS + 16) | dalloc(c, &c->res, 3 * MAXK + 4) | dalloc(c, &c->flags, 1);
-    if (rc) { ecpic2d_destroy(c); return ECPIC_ENOMEM; }
+          dalloc(c, &c->partial, RED_BLOCKS + 16) | dalloc(c, &c->res, 3 * MAXK + 4) | dalloc(c, &c->flags, 1) |
+          dalloc(c, &c->gate, 1);
+    if (rc || hipHostMalloc((void **)&c->hres, sizeof(double) * 6 * MAXK, hipHostMallocMapped) != hipSuccess) {
+        ecpic2d_destroy(c);
+        return ECPIC_ENOMEM;
+    }
+    if (hipHostGetDevicePointer((void **)&c->hres_dev, c->hres, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+        ecpic2d_destroy(c);
+        return ECPIC_EDEVICE;
+    }
     // twiddles and 1D symbols (host, long double)
     const long double PI = 3.14159265358979323846264338327950288L;
     std::vector<double2> t1(c->M1 / 2), t2(c->M2 / 2);
@@ -1960,6 +2041,9 @@ int ecpic2d_destroy(ecpic2d_ctx *c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     for (auto &pe : c->prof.pending) { hipEventDestroy(pe.second.first); hipEventDestroy(pe.second.second); }
     for (void *p : c->allocs) hipFree(p);
+    if (c->hres) hipHostFree(c->hres);
+    for (hipEvent_t e : c->ev)
+        if (e) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
     return ECPIC_OK;

@@ -182,6 +182,33 @@ def test_dense_tiles_take_the_direct_resort():
         assert ctx.gauss_residual() < 1e-13
 
 
+def test_nonfinite_field_is_reported_and_state_restorable():
+    """A NaN coefficient of e (Subsystem I) or of a_z (Subsystem III) stops the
+    fixed point with ECPIC_ENONFINITE and commits nothing; with the fields set
+    again the run matches the oracle."""
+    w, o, s, ctx = setup("twod16", n=1500)
+    with ctx:
+        good = ctx.get_fields()
+        parts = ctx.get_particles()
+        for name, call in (("e", ctx.substep_I), ("az", ctx.substep_III)):
+            bad = {k: v.copy() for k, v in good.items()}
+            bad[name][17] = np.nan
+            ctx.set_fields(**bad)
+            with pytest.raises(ec.EcpicError) as e:
+                call()
+            assert e.value.status == ec.ENONFINITE, name
+            after, fields = ctx.get_particles(), ctx.get_fields()
+            for k in parts:
+                np.testing.assert_array_equal(after[k], parts[k])
+            for k in good:
+                np.testing.assert_array_equal(fields[k], bad[k])
+        ctx.set_fields(**good)
+        kg, kIIIg = ctx.step(2)
+        st, ko, kIIIo = o.step(s, 2)
+        assert st == 0 and np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
+        compare(w, ctx.state(), s, 3e-11)
+
+
 def test_edge_positions_and_order():
     """Particles on and just inside the domain boundary, negative and beyond-L
     positions (wrapped), returned in input order."""
