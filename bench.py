@@ -250,10 +250,11 @@ def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
 
 
 # 2D model, per particle: a Subsystem I sweep reads x1, x2, p1, p2 and d^(k) (48 B) and
-# writes d^(k+1) and p^(k+1) (32 B); the commit reads x, p, d, p^(k+1) (64 B) and writes
-# x, p and the cell (36 B); the sort reads x, p, id, cell and writes x, p, id (60 B);
-# Subsystem II reads x, p and writes p (48 B); the III source reads x, p (32 B).
-TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 100.0, "sort": 60.0, "rotate_II": 48.0, "deposit_III": 32.0}
+# writes d^(k+1) and p^(k+1) (32 B); the commit reads x and d (32 B) and writes the packed
+# new tile and column (4 B); the sort (arrival lists and re-sort) reads that word twice,
+# x, d, p^(k+1) and the id (60 B) and writes x, p, id (36 B); Subsystem II reads x, p and
+# writes p (48 B); the III source reads x, p (32 B).
+TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 36.0, "sort": 96.0, "rotate_II": 48.0, "deposit_III": 32.0}
 TWOD_KERNELS = ("sweep_I", "solve_I", "commit_I", "sort", "rotate_II", "deposit_III", "solve_III", "maxwell_IV")
 FP64_PEAK_TFLOPS = 78.6
 
@@ -327,7 +328,8 @@ def twod_run(ec, w, steps: int, warmup: int, profile_steps: int):
         traffic = twod_traffic_from_profile(w.name, N)
         roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
-                "kernel": f"k2_sweep_I<{w.degree}> (2D Subsystem I Picard sweep)",
+                "kernel": f"k2_sweep_I<{w.degree}, *> (2D Subsystem I Picard sweep, average over the "
+                          f"sweeps of a step; sweep 0 also forms the explicit start)",
                 "algorithmic_flops_per_particle": fl, "avg_launch_us": us["sweep_I"],
                 "algorithmic_bytes_per_particle": TWOD_BYTES["sweep_I"], "hbm_frac": frac.get("sweep_I")}
     return {"config": f"{w.name}: {w.L1:.4g} x {w.L2:.4g}, {w.M1} x {w.M2} cells, degree {w.degree}, "
