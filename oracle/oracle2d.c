@@ -1,7 +1,8 @@
 /*
  * Plain FP64 CPU oracle of the reduced 2D model (Sections 2.2, 3.2 and 4.3 of Li,
  * "Energy conserving particle-in-cell methods for relativistic Vlasov-Maxwell
- * equations of laser-plasma interaction"), spin term off (hbar = 0).
+ * equations of laser-plasma interaction"), without spin (the plain functions) and with
+ * the spin terms (the _s functions, hbar != 0).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
  * baseline leg of the benchmark may load this file's library.  It shares no
@@ -41,6 +42,19 @@
  *     iteration preconditioned by M0 converges to the same solution;
  *   - Subsystem IV: the linear system for e_xy solved exactly, then b_z;
  *   - Lie-Trotter step: I, II, III, IV in the order the splitting numbers them.
+ * With spin (Section 2.2's Zeeman term hbar sum_a w s_a . B_h(x_a), Section 4.3):
+ *   - B_h = (dA_z/dx2, -dA_z/dx1, B_z); dA_z/dx2 has the coefficients (G a)_2 on the
+ *     degrees (p, p-1) and dA_z/dx1 the coefficients (G a)_1 on (p-1, p), so
+ *     G* a = ((G a)_2, -(G a)_1) and Lambda1* pairs (p, p-1) with s_x and (p-1, p)
+ *     with s_y;
+ *   - Subsystem I: the divided differences of dA_z/dx2, dA_z/dx1 and B_z along the
+ *     same two legs as A_z's are the means of their derivatives along the legs (the
+ *     derivative coefficients are again backward differences); the momentum
+ *     update subtracts dt hbar (s_x DD(dA_z/dx2) - s_y DD(dA_z/dx1) + s_z DD(B_z));
+ *   - Subsystem II: ds/dt = s x B_h(x) with B_h fixed, so s turns about B_h by the
+ *     angle -|B_h| dt (Rodrigues' formula), and p turns by B_z as without spin;
+ *   - Subsystem III: the right-hand side gains hbar dt G*^T Lambda1*(X^n)^T W S_xy;
+ *   - Subsystem IV: it gains hbar dt C^T Lambda2(X^n)^T W S_z.
  */
 #include <math.h>
 #include <stdint.h>
@@ -647,6 +661,344 @@ void orc2_substep_IV(const orc2_cfg *c, double h, double *e, double *bz)
     for (long i = 0; i < N; ++i) bz[i] -= h * cb[i];
     memcpy(e, en, sizeof(double) * N2);
     free(rhs); free(t); free(en); free(mb); free(cb);
+}
+
+/* ------------------------------------------------------------------ */
+/* Spin terms (hbar != 0): Zeeman energy and the four substeps.         */
+/* ------------------------------------------------------------------ */
+
+/* B_h(x) = (dA_z/dx2, -dA_z/dx1, B_z) from ga = G a_z and b_z. */
+void orc2_bfield(const orc2_cfg *c, const double *ga, const double *bz, double x1, double x2, double *B)
+{
+    long N = nodes(c);
+    int p = c->p;
+    B[0] = orc2_eval(c, ga + N, p, p - 1, x1, x2);
+    B[1] = -orc2_eval(c, ga, p - 1, p, x1, x2);
+    B[2] = orc2_eval(c, bz, p - 1, p - 1, x1, x2);
+}
+
+/* The Hamiltonian with the Zeeman term: out = {kinetic, 1/2 e^T M1 e, 1/2 b^T M2 b,
+ * 1/2 e_z^T M0 e_z, 1/2 a^T K a, hbar sum_a w s_a . B_h(x_a), total}. */
+void orc2_energy_s(const orc2_cfg *c, double hbar, const double *x1, const double *x2, const double *p1,
+                   const double *p2, const double *sx, const double *sy, const double *sz, const double *e,
+                   const double *bz, const double *ez, const double *az, double *out)
+{
+    long N = nodes(c);
+    orc2_energy(c, x1, x2, p1, p2, e, bz, ez, az, out);
+    double *ga = malloc(sizeof(double) * 2 * N);
+    orc2_apply_G(c, az, ga);
+    double zee = 0.0;
+    for (int64_t a = 0; a < c->n; ++a) {
+        double B[3];
+        orc2_bfield(c, ga, bz, x1[a], x2[a], B);
+        zee += c->w * (sx[a] * B[0] + sy[a] * B[1] + sz[a] * B[2]);
+    }
+    free(ga);
+    out[6] = out[5] + hbar * zee;
+    out[5] = hbar * zee;
+}
+
+/* Derivative coefficients of the fields in B_h (backward differences, any degree):
+ * gg2 = G (G a)_2 (d/dx1, d/dx2 of dA_z/dx2), gg1 = G (G a)_1, gb = G b_z. */
+typedef struct {
+    double hbar;
+    const double *sx, *sy, *sz;
+    double *gg1, *gg2, *gb;
+} orc2_spin;
+
+static void spin_derivs(const orc2_cfg *c, const double *ga, const double *bz, orc2_spin *sp)
+{
+    long N = nodes(c);
+    sp->gg1 = malloc(sizeof(double) * 2 * N);
+    sp->gg2 = malloc(sizeof(double) * 2 * N);
+    sp->gb = malloc(sizeof(double) * 2 * N);
+    orc2_apply_G(c, ga, sp->gg1);
+    orc2_apply_G(c, ga + N, sp->gg2);
+    orc2_apply_G(c, bz, sp->gb);
+}
+
+static void spin_free(orc2_spin *sp) { free(sp->gg1); free(sp->gg2); free(sp->gb); }
+
+/* The spin part of (1/w) times the discrete gradient of H in x for particle a with
+ * increment d, divided by hbar:
+ *   s_x DD(dA_z/dx2) - s_y DD(dA_z/dx1) + s_z DD(B_z),
+ * DD(F) = (mean of dF/dx1 along (x1, x2 + d2) -> (x1 + d1, x2 + d2),
+ *          mean of dF/dx2 along (x1, x2) -> (x1, x2 + d2)). */
+static void spin_force(const orc2_cfg *c, const orc2_spin *sp, int64_t a, double x1, double x2, double d1,
+                       double d2, double *F)
+{
+    long N = nodes(c);
+    int p = c->p;
+    double b1 = x1 + d1, b2 = x2 + d2;
+    /* dA_z/dx2 on (p, p-1): d/dx1 on (p-1, p-1), d/dx2 on (p, p-2) */
+    double Dy1 = orc2_line_mean(c, sp->gg2, p - 1, p - 1, x1, b2, b1, b2);
+    double Dy2 = orc2_line_mean(c, sp->gg2 + N, p, p - 2, x1, x2, x1, b2);
+    /* dA_z/dx1 on (p-1, p): d/dx1 on (p-2, p), d/dx2 on (p-1, p-1) */
+    double Dx1 = orc2_line_mean(c, sp->gg1, p - 2, p, x1, b2, b1, b2);
+    double Dx2 = orc2_line_mean(c, sp->gg1 + N, p - 1, p - 1, x1, x2, x1, b2);
+    /* B_z on (p-1, p-1): d/dx1 on (p-2, p-1), d/dx2 on (p-1, p-2) */
+    double Db1 = orc2_line_mean(c, sp->gb, p - 2, p - 1, x1, b2, b1, b2);
+    double Db2 = orc2_line_mean(c, sp->gb + N, p - 1, p - 2, x1, x2, x1, b2);
+    F[0] = sp->sx[a] * Dy1 - sp->sy[a] * Dx1 + sp->sz[a] * Db1;
+    F[1] = sp->sx[a] * Dy2 - sp->sy[a] * Dx2 + sp->sz[a] * Db2;
+}
+
+/* Subsystem I with spin: the map of orc2_particle_map with the momentum update
+ * p^{n+1} = p^n + dt (Ebar + F - hbar spin_force). */
+static void particle_map_s(const orc2_cfg *c, const orc2_spin *sp, int64_t a, double x1, double x2, double p1,
+                           double p2, double d1, double d2, const double *ebar, const double *az, const double *ga,
+                           double *pn, double *dn)
+{
+    long N = nodes(c);
+    int p = c->p;
+    double b1 = x1 + d1, b2 = x2 + d2;
+    double E1 = orc2_line_mean(c, ebar, p - 1, p, x1, x2, b1, b2);
+    double E2 = orc2_line_mean(c, ebar + N, p, p - 1, x1, x2, b1, b2);
+    double Aa = orc2_eval(c, az, p, p, x1, x2), Ab = orc2_eval(c, az, p, p, b1, b2);
+    double D2 = orc2_line_mean(c, ga + N, p, p - 1, x1, x2, x1, b2);
+    double D1 = orc2_line_mean(c, ga, p - 1, p, x1, b2, b1, b2);
+    double Fs[2];
+    spin_force(c, sp, a, x1, x2, d1, d2, Fs);
+    double ga_ = gam(p1, p2, Aa), gb = gam(p1, p2, Ab);
+    double f = -(Aa + Ab) / (ga_ + gb);
+    double q1 = p1 + c->dt * (E1 + f * D1 - sp->hbar * Fs[0]);
+    double q2 = p2 + c->dt * (E2 + f * D2 - sp->hbar * Fs[1]);
+    double gc = gam(q1, q2, Ab);
+    pn[0] = q1;
+    pn[1] = q2;
+    dn[0] = c->dt * (p1 + q1) / (gb + gc);
+    dn[1] = c->dt * (p2 + q2) / (gb + gc);
+}
+
+/* One evaluation of the Subsystem I map with spin for particle a (tests). */
+void orc2_particle_map_s(const orc2_cfg *c, double hbar, const double *sx, const double *sy, const double *sz,
+                         int64_t a, double x1, double x2, double p1, double p2, double d1, double d2,
+                         const double *ebar, const double *az, const double *bz, double *pn, double *dn)
+{
+    long N = nodes(c);
+    double *ga = malloc(sizeof(double) * 2 * N);
+    orc2_apply_G(c, az, ga);
+    orc2_spin sp = {hbar, sx, sy, sz, NULL, NULL, NULL};
+    spin_derivs(c, ga, bz, &sp);
+    particle_map_s(c, &sp, a, x1, x2, p1, p2, d1, d2, ebar, az, ga, pn, dn);
+    spin_free(&sp);
+    free(ga);
+}
+
+int orc2_substep_I_s(const orc2_cfg *cfg, double h, double hbar, double *x1, double *x2, double *p1, double *p2,
+                     const double *sx, const double *sy, const double *sz, double *e, const double *az,
+                     const double *bz, int32_t *sweeps, double *res)
+{
+    orc2_cfg ch = *cfg;
+    ch.dt = h;
+    const orc2_cfg *c = &ch;
+    long N = nodes(c), N2 = 2 * N;
+    int64_t n = c->n;
+    int p = c->p;
+    double *d = malloc(sizeof(double) * 2 * n), *dn = malloc(sizeof(double) * 2 * n),
+           *pk = malloc(sizeof(double) * 2 * n);
+    double *ek = malloc(sizeof(double) * N2), *enew = malloc(sizeof(double) * N2),
+           *ebar = malloc(sizeof(double) * N2), *J = malloc(sizeof(double) * N2),
+           *MJ = malloc(sizeof(double) * N2), *ga = malloc(sizeof(double) * N2);
+    if (!d || !dn || !pk || !ek || !enew || !ebar || !J || !MJ || !ga) return ORC2_ENOMEM;
+    orc2_apply_G(c, az, ga);
+    orc2_spin sp = {hbar, sx, sy, sz, NULL, NULL, NULL};
+    spin_derivs(c, ga, bz, &sp);
+    for (int64_t a = 0; a < n; ++a) {
+        double g = gam(p1[a], p2[a], orc2_eval(c, az, p, p, x1[a], x2[a]));
+        d[2 * a] = c->dt * p1[a] / g;
+        d[2 * a + 1] = c->dt * p2[a] / g;
+    }
+    memcpy(ek, e, sizeof(double) * N2);
+    int status = ORC2_ENOTCONV, k;
+    double r = 0.0;
+    for (k = 0; k < c->kmax; ++k) {
+        for (long i = 0; i < N2; ++i) ebar[i] = 0.5 * (e[i] + ek[i]);
+        memset(J, 0, sizeof(double) * N2);
+        double rx = 0.0;
+        for (int64_t a = 0; a < n; ++a) {
+            particle_map_s(c, &sp, a, x1[a], x2[a], p1[a], p2[a], d[2 * a], d[2 * a + 1], ebar, az, ga, &pk[2 * a],
+                           &dn[2 * a]);
+            double b1 = x1[a] + d[2 * a], b2 = x2[a] + d[2 * a + 1];
+            orc2_line_deposit(c, J, p - 1, p, x1[a], x2[a], b1, b2, c->w * d[2 * a]);
+            orc2_line_deposit(c, J + N, p, p - 1, x1[a], x2[a], b1, b2, c->w * d[2 * a + 1]);
+            for (int q = 0; q < 2; ++q) {
+                double dd = fabs(dn[2 * a + q] - d[2 * a + q]);
+                if (dd > rx) rx = dd;
+            }
+        }
+        orc2_solve_M1(c, J, MJ);
+        double re = 0.0;
+        for (long i = 0; i < N2; ++i) {
+            enew[i] = e[i] - MJ[i];
+            double de = fabs(enew[i] - ek[i]);
+            if (de > re) re = de;
+        }
+        r = rx > re ? rx : re;
+        if (r <= c->tol) {
+            for (int64_t a = 0; a < n; ++a) {
+                x1[a] = wrapL(x1[a] + d[2 * a], c->L1);
+                x2[a] = wrapL(x2[a] + d[2 * a + 1], c->L2);
+                p1[a] = pk[2 * a];
+                p2[a] = pk[2 * a + 1];
+            }
+            memcpy(e, enew, sizeof(double) * N2);
+            status = ORC2_OK;
+            ++k;
+            break;
+        }
+        double *t = d; d = dn; dn = t;
+        memcpy(ek, enew, sizeof(double) * N2);
+    }
+    if (sweeps) *sweeps = k;
+    if (res) *res = r;
+    spin_free(&sp);
+    free(d); free(dn); free(pk); free(ek); free(enew); free(ebar); free(J); free(MJ); free(ga);
+    return status;
+}
+
+/* Subsystem II with spin: p as without spin; ds/dt = s x B_h(x) with B_h fixed
+ * turns s about k = B_h/|B_h| by the angle -|B_h| h:
+ * s' = s cos(th) - (k x s) sin(th) + k (k . s)(1 - cos(th)), th = |B_h| h. */
+void orc2_substep_II_s(const orc2_cfg *c, double h, const double *x1, const double *x2, double *p1, double *p2,
+                       double *sx, double *sy, double *sz, const double *bz, const double *az)
+{
+    long N = nodes(c);
+    double *ga = malloc(sizeof(double) * 2 * N);
+    orc2_apply_G(c, az, ga);
+    for (int64_t a = 0; a < c->n; ++a) {
+        double B[3];
+        orc2_bfield(c, ga, bz, x1[a], x2[a], B);
+        double nb = sqrt(B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+        if (nb == 0.0) continue;
+        double k0 = B[0] / nb, k1 = B[1] / nb, k2 = B[2] / nb, th = nb * h;
+        double s0 = sx[a], s1 = sy[a], s2 = sz[a];
+        double kx0 = k1 * s2 - k2 * s1, kx1 = k2 * s0 - k0 * s2, kx2 = k0 * s1 - k1 * s0;
+        double ks = k0 * s0 + k1 * s1 + k2 * s2, cs = cos(th), sn = sin(th);
+        sx[a] = s0 * cs - kx0 * sn + k0 * ks * (1.0 - cs);
+        sy[a] = s1 * cs - kx1 * sn + k1 * ks * (1.0 - cs);
+        sz[a] = s2 * cs - kx2 * sn + k2 * ks * (1.0 - cs);
+    }
+    free(ga);
+    orc2_substep_II(c, h, x1, x2, p1, p2, bz, az);
+}
+
+/* The spin sources at the particles: sxy = G*^T (Lambda1*(X)^T W S_xy), i.e.
+ * G2^T D_x - G1^T D_y with D_x = sum w s_x N^p N^{p-1}, D_y = sum w s_y N^{p-1} N^p;
+ * dz = Lambda2(X)^T W S_z = sum w s_z N^{p-1} N^{p-1}. */
+void orc2_spin_sources(const orc2_cfg *c, const double *x1, const double *x2, const double *sx, const double *sy,
+                       const double *sz, double *sxy, double *dz)
+{
+    long N = nodes(c);
+    int p = c->p;
+    double *u = calloc((size_t)(2 * N), sizeof(double));
+    if (dz) memset(dz, 0, sizeof(double) * N);
+    for (int64_t a = 0; a < c->n; ++a) {
+        if (sxy) {
+            deposit_point(c, u, p - 1, p, x1[a], x2[a], -c->w * sy[a]);   /* slot of (G a)_1 */
+            deposit_point(c, u + N, p, p - 1, x1[a], x2[a], c->w * sx[a]); /* slot of (G a)_2 */
+        }
+        if (dz) deposit_point(c, dz, p - 1, p - 1, x1[a], x2[a], c->w * sz[a]);
+    }
+    if (sxy) orc2_apply_GT(c, u, sxy);
+    free(u);
+}
+
+/* Subsystem III with spin: the right-hand side of orc2_substep_III plus
+ * hbar h G*^T Lambda1*(X^n)^T W S_xy^n. */
+int orc2_substep_III_s(const orc2_cfg *cfg, double h, double hbar, const double *x1, const double *x2,
+                       const double *p1, const double *p2, const double *sx, const double *sy, double *ez,
+                       double *az, int32_t *iters, double *res)
+{
+    orc2_cfg ch = *cfg;
+    ch.dt = h;
+    const orc2_cfg *c = &ch;
+    long N = nodes(c);
+    int64_t n = c->n;
+    int p = c->p;
+    double *An = malloc(sizeof(double) * n), *gn = malloc(sizeof(double) * n);
+    double *rhs = malloc(sizeof(double) * N), *t = malloc(sizeof(double) * N), *ek = malloc(sizeof(double) * N),
+           *ak = malloc(sizeof(double) * N), *S = malloc(sizeof(double) * N), *en = malloc(sizeof(double) * N),
+           *src = malloc(sizeof(double) * N);
+    for (int64_t a = 0; a < n; ++a) {
+        An[a] = orc2_eval(c, az, p, p, x1[a], x2[a]);
+        gn[a] = gam(p1[a], p2[a], An[a]);
+    }
+    orc2_spin_sources(c, x1, x2, sx, sy, NULL, src, NULL);
+    op_M0K(c, -0.25 * h * h, ez, rhs);
+    orc2_apply_K(c, az, t);
+    for (long i = 0; i < N; ++i) rhs[i] += h * t[i] + hbar * h * src[i];
+    memcpy(ek, ez, sizeof(double) * N);
+    int status = ORC2_ENOTCONV, k;
+    double r = 0.0;
+    for (k = 0; k < c->kmax; ++k) {
+        for (long i = 0; i < N; ++i) ak[i] = az[i] - 0.5 * h * (ez[i] + ek[i]);
+        memset(S, 0, sizeof(double) * N);
+        for (int64_t a = 0; a < n; ++a) {
+            double Ak = orc2_eval(c, ak, p, p, x1[a], x2[a]);
+            double q = c->w * (An[a] + Ak) / (gn[a] + gam(p1[a], p2[a], Ak));
+            deposit_point(c, S, p, p, x1[a], x2[a], q);
+        }
+        for (long i = 0; i < N; ++i) S[i] = rhs[i] + h * S[i];
+        solve2(c, op_M0K, 0.25 * h * h, N, 0, S, en);
+        r = 0.0;
+        for (long i = 0; i < N; ++i) {
+            double de = fabs(en[i] - ek[i]);
+            if (de > r) r = de;
+        }
+        memcpy(ek, en, sizeof(double) * N);
+        if (r <= c->tol) {
+            for (long i = 0; i < N; ++i) az[i] = az[i] - 0.5 * h * (ez[i] + en[i]);
+            memcpy(ez, en, sizeof(double) * N);
+            status = ORC2_OK;
+            ++k;
+            break;
+        }
+    }
+    if (iters) *iters = k;
+    if (res) *res = r;
+    free(An); free(gn); free(rhs); free(t); free(ek); free(ak); free(S); free(en); free(src);
+    return status;
+}
+
+/* Subsystem IV with spin: (M1 + h^2 C^T M2 C/4) e^{n+1} = (M1 - h^2 C^T M2 C/4) e^n
+ * + h C^T M2 b^n + hbar h C^T Lambda2(X^n)^T W S_z^n, b^{n+1} = b^n - h C (e^n + e^{n+1})/2. */
+void orc2_substep_IV_s(const orc2_cfg *c, double h, double hbar, const double *x1, const double *x2,
+                       const double *sz, double *e, double *bz)
+{
+    long N = nodes(c), N2 = 2 * N;
+    double *rhs = malloc(sizeof(double) * N2), *t = malloc(sizeof(double) * N2), *en = malloc(sizeof(double) * N2),
+           *mb = malloc(sizeof(double) * N), *cb = malloc(sizeof(double) * N), *dz = malloc(sizeof(double) * N);
+    orc2_spin_sources(c, x1, x2, NULL, NULL, sz, NULL, dz);
+    op_M1C(c, -0.25 * h * h, e, rhs);
+    orc2_apply_M2(c, bz, mb);
+    for (long i = 0; i < N; ++i) mb[i] += hbar * dz[i];
+    orc2_apply_CT(c, mb, t);
+    for (long i = 0; i < N2; ++i) rhs[i] += h * t[i];
+    solve2(c, op_M1C, 0.25 * h * h, N2, 0, rhs, en);
+    for (long i = 0; i < N2; ++i) t[i] = 0.5 * (e[i] + en[i]);
+    orc2_apply_C(c, t, cb);
+    for (long i = 0; i < N; ++i) bz[i] -= h * cb[i];
+    memcpy(e, en, sizeof(double) * N2);
+    free(rhs); free(t); free(en); free(mb); free(cb); free(dz);
+}
+
+/* Lie-Trotter step with spin: I, II, III, IV over dt each. */
+int orc2_step_s(const orc2_cfg *c, double hbar, int32_t nsteps, double *x1, double *x2, double *p1, double *p2,
+                double *sx, double *sy, double *sz, double *e, double *bz, double *ez, double *az,
+                int32_t *sweeps_I, int32_t *iters_III)
+{
+    for (int32_t s = 0; s < nsteps; ++s) {
+        int st = orc2_substep_I_s(c, c->dt, hbar, x1, x2, p1, p2, sx, sy, sz, e, az, bz,
+                                  sweeps_I ? &sweeps_I[s] : NULL, NULL);
+        if (st) return st;
+        orc2_substep_II_s(c, c->dt, x1, x2, p1, p2, sx, sy, sz, bz, az);
+        st = orc2_substep_III_s(c, c->dt, hbar, x1, x2, p1, p2, sx, sy, ez, az, iters_III ? &iters_III[s] : NULL,
+                                NULL);
+        if (st) return st;
+        orc2_substep_IV_s(c, c->dt, hbar, x1, x2, sz, e, bz);
+    }
+    return ORC2_OK;
 }
 
 /* ------------------------------------------------------------------ */

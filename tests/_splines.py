@@ -44,3 +44,13 @@ def basis_values(M: int, dx: float, deg: int, x: float) -> np.ndarray:
         e[j] = 1.0
         out[j] = periodic_spline(e, dx, deg)(x)
     return out
+
+
+def basis_derivs(M: int, dx: float, deg: int, x: float) -> np.ndarray:
+    """Vector over j (mod M) of dN^deg_j/dx at x (scipy's own derivative)."""
+    out = np.zeros(M)
+    for j in range(M):
+        e = np.zeros(M)
+        e[j] = 1.0
+        out[j] = periodic_spline(e, dx, deg).derivative()(x)
+    return out

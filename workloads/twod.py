@@ -1,4 +1,4 @@
-"""Seeded synthetic workloads of the reduced 2D model (Section 2.2), spin off.
+"""Seeded synthetic workloads of the reduced 2D model (Section 2.2).
 
 Like the 1D module, this draws random numbers and samples closed-form initial
 profiles only: no spline evaluation, no mass matrix, no solve.  Both the oracle
@@ -16,7 +16,13 @@ its 2D model (normalised units: plasma frequency 1, light speed 1):
 * ``twod512`` -- 16 pi x 16 pi, 512 x 512 cells (dx = 0.098, about one Debye
   length at sigma = 0.1), cubic, 2^24 particles (64 per cell), ripple 1 % at
   mode (8, 8), A_z wave 0.05 at modes (8, 4), TE wave 0.05 at mode 8, dt = 0.05,
-  tolerance 1e-12.
+  tolerance 1e-12;
+* ``twod16s``, ``twod8x16s`` -- the two small plasmas with spin: hbar = 0.1 and
+  spins uniform on the unit sphere (as the 1D spin workload at scale);
+* ``twod512s`` -- ``twod512`` with the same spins.
+
+Spins are drawn after every other array, so a workload without spin draws
+exactly what it drew before spins existed.
 
 Coefficients are sampled at the Greville abscissae of each tensor-product
 basis, as in 1D.
@@ -53,6 +59,8 @@ class Workload2D:
     te_mode: int = 1
     seed: int = 0
     kmax: int = 50
+    hbar: float = 0.0                    # spin coupling (Section 2.2)
+    spin: str = "none"                   # "none" | "sphere" (uniform on the unit sphere)
 
     @property
     def dx1(self) -> float:
@@ -81,6 +89,9 @@ WORKLOADS_2D: Dict[str, Workload2D] = {
                           n_particles=1 << 24, dt=0.05, steps=100, tol=1e-12, sigma=0.1, ripple=0.01,
                           ripple_mode=(8, 8), az_amp=0.05, az_mode=(8, 4), te_amp=0.05, te_mode=8, seed=5120),
 }
+WORKLOADS_2D["twod16s"] = WORKLOADS_2D["twod16"].scaled(name="twod16s", hbar=0.1, spin="sphere")
+WORKLOADS_2D["twod8x16s"] = WORKLOADS_2D["twod8x16"].scaled(name="twod8x16s", hbar=0.1, spin="sphere")
+WORKLOADS_2D["twod512s"] = WORKLOADS_2D["twod512"].scaled(name="twod512s", hbar=0.1, spin="sphere")
 
 
 def get2d(name: str) -> Workload2D:
@@ -125,7 +136,8 @@ def _grid(w: Workload2D, s1: float, s2: float):
 
 def generate2d(w: Workload2D, n: Optional[int] = None, seed: Optional[int] = None) -> dict:
     """Initial state arrays (float64, host): x1, x2, p1, p2 (length n); e (e1 then e2,
-    2 M1 M2), bz, ez, az (M1 M2), row-major with index i1 M2 + i2."""
+    2 M1 M2), bz, ez, az (M1 M2), row-major with index i1 M2 + i2; with spin also sx,
+    sy, sz (length n)."""
     n = w.n_particles if n is None else int(n)
     rng = np.random.Generator(np.random.PCG64(w.seed if seed is None else seed))
     x1 = _coordinate(rng.random(n), w.L1, w.ripple, w.ripple_mode[0])
@@ -147,6 +159,12 @@ def generate2d(w: Workload2D, n: Optional[int] = None, seed: Optional[int] = Non
     _, E2 = _grid(w, 0.5 * p, 0.5 * (p + 1))
     e1 = -(w.te_amp * omt / kt) * np.cos(kt * E2)
     e2 = np.zeros((w.M1, w.M2))
-    return {"x1": x1.astype(np.float64), "x2": x2.astype(np.float64), "p1": p1, "p2": p2,
-            "e": np.concatenate([e1.ravel(), e2.ravel()]), "bz": bz.ravel().copy(),
-            "ez": ez.ravel().copy(), "az": az.ravel().copy()}
+    out = {"x1": x1.astype(np.float64), "x2": x2.astype(np.float64), "p1": p1, "p2": p2,
+           "e": np.concatenate([e1.ravel(), e2.ravel()]), "bz": bz.ravel().copy(),
+           "ez": ez.ravel().copy(), "az": az.ravel().copy()}
+    if w.spin == "sphere":   # drawn after every other array: a workload without spin draws what it did
+        u = rng.uniform(-1.0, 1.0, n)
+        phi = rng.uniform(0.0, 2.0 * math.pi, n)
+        r = np.sqrt(1.0 - u * u)
+        out.update(sx=r * np.cos(phi), sy=r * np.sin(phi), sz=u)
+    return out
