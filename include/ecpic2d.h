@@ -3,7 +3,7 @@
  * particle-in-cell step of the reduced 2D relativistic Vlasov-Maxwell model
  * (Li, "Energy conserving particle-in-cell methods for relativistic
  * Vlasov-Maxwell equations of laser-plasma interaction", Sections 2.2, 3.2 and
- * 4.3), spin term off (hbar = 0).
+ * 4.3), with or without the spin terms (hbar, the particles' spins s_a).
  *
  * State (Section 3.2): particle positions x_a = (x1, x2) and momenta
  * p_a = (p1, p2) with a common weight w; the fields on a periodic uniform grid of
@@ -19,8 +19,15 @@
  *
  * A Lie-Trotter step applies the four subsystems of the Section 4.3 splitting in
  * order: I (positions, momenta and e_xy by the discrete gradient, Picard
- * iteration), II (rotation of the momenta by B_z), III (a_z and e_z, fixed
- * point), IV (e_xy and b_z, Maxwell).
+ * iteration), II (rotation of the momenta by B_z, and of the spins about B_h),
+ * III (a_z and e_z, fixed point), IV (e_xy and b_z, Maxwell).
+ *
+ * With spin (cfg.spin = 1) the Hamiltonian carries the Zeeman term
+ * hbar sum_a w s_a . B_h(x_a), B_h = (dA_z/dx2, -dA_z/dx1, B_z) (Section 2.2):
+ * Subsystem I adds its force (the divided differences of s . B_h along the two
+ * legs of the discrete gradient), II turns every spin about B_h(x_a) exactly,
+ * and III and IV add the constant sources hbar G*^T Lambda1*(X)^T W S_xy and
+ * hbar C^T Lambda2(X)^T W S_z.
  *
  * Every call returns an ecpic_status (ecpic.h).  Unless stated otherwise:
  *   - host arrays are read or written during the call only and never kept;
@@ -54,7 +61,11 @@ typedef struct {
     double dt;                /* time step of ecpic2d_step; 0 < dt < min(L1/M1, L2/M2) */
     double picard_tol;        /* absolute max-norm tolerance of the fixed points (> 0) */
     int32_t device;           /* HIP device ordinal */
-    int32_t reserved;         /* must be 0 */
+    int32_t spin;             /* 1: the particles carry spins (ecpic2d_set_spins) and the hbar terms are
+                                 on; 0: no spin */
+    double hbar;              /* normalised Planck constant of the Zeeman term; must be 0 without spin.
+                                 With hbar = 0 the spins still precess in Subsystem II but act on
+                                 nothing. */
 } ecpic2d_config;
 
 typedef struct {
@@ -69,7 +80,8 @@ typedef struct {
     double b_z;       /* 1/2 b_z^T M2 b_z */
     double e_z;       /* 1/2 e_z^T M0 e_z */
     double a_z;       /* 1/2 a_z^T K a_z, K = G^T M1 G (|grad A_z|^2 / 2) */
-    double total;     /* the discrete Hamiltonian of Section 3.2 with hbar = 0 */
+    double total;     /* the discrete Hamiltonian of Section 3.2 (the Zeeman term included) */
+    double zeeman;    /* hbar sum_a w s_a . B_h(x_a) (0 without spin) */
 } ecpic2d_energy_parts;
 
 /* Create a context on cfg->device and allocate every device buffer for N
@@ -87,6 +99,13 @@ int ecpic2d_destroy(ecpic2d_ctx *ctx);
 int ecpic2d_set_particles(ecpic2d_ctx *ctx, const double *x1, const double *x2, const double *p1,
                           const double *p2, int64_t n);
 int ecpic2d_get_particles(ecpic2d_ctx *ctx, double *x1, double *x2, double *p1, double *p2, int64_t n);
+
+/* Spins s_a = (s_x, s_y, s_z) (Section 2.2; needs cfg.spin), host arrays of n =
+ * n_particles entries in the order given to set_particles.  set_particles sets
+ * every spin to zero; get_spins returns them in that order.  EINVAL without spin,
+ * if n differs or a value is not finite; ESTATE before set_particles. */
+int ecpic2d_set_spins(ecpic2d_ctx *ctx, const double *sx, const double *sy, const double *sz, int64_t n);
+int ecpic2d_get_spins(ecpic2d_ctx *ctx, double *sx, double *sy, double *sz, int64_t n);
 
 /* Field coefficients, host arrays of M1 M2 entries each (layout above).  A NULL
  * input sets that field to zero; a NULL output skips it. */
@@ -106,16 +125,19 @@ int ecpic2d_solve_gauss(ecpic2d_ctx *ctx);
  * may be NULL.  ENOTCONV and ENONFINITE leave the state as before the call. */
 int ecpic2d_substep_I(ecpic2d_ctx *ctx, double dt, ecpic2d_iter_stats *stats);
 
-/* Subsystem II: every momentum turned by the angle B_z(x_a) dt / gamma_a
- * (exact solution of the subsystem). */
+/* Subsystem II: every momentum turned by the angle B_z(x_a) dt / gamma_a, and
+ * with spin every spin turned about B_h(x_a) by the angle -|B_h(x_a)| dt
+ * (ds/dt = s x B_h, Rodrigues' formula): the exact solution of the subsystem. */
 int ecpic2d_substep_II(ecpic2d_ctx *ctx, double dt);
 
 /* Subsystem III: (a_z, e_z) by the implicit midpoint scheme, fixed point on e_z
- * with the linear part (M0 + dt^2 K / 4) solved exactly.  ENOTCONV leaves the
- * state as before the call. */
+ * with the linear part (M0 + dt^2 K / 4) solved exactly; with spin the right-hand
+ * side carries hbar dt G*^T Lambda1*(X)^T W S_xy.  ENOTCONV and ENONFINITE leave
+ * the state as before the call. */
 int ecpic2d_substep_III(ecpic2d_ctx *ctx, double dt, ecpic2d_iter_stats *stats);
 
-/* Subsystem IV: (e_xy, b_z) by the implicit midpoint scheme, solved exactly. */
+/* Subsystem IV: (e_xy, b_z) by the implicit midpoint scheme, solved exactly; with
+ * spin the b_z term of the e_xy equation carries hbar Lambda2(X)^T W S_z. */
 int ecpic2d_substep_IV(ecpic2d_ctx *ctx, double dt);
 
 /* nsteps Lie-Trotter steps I, II, III, IV with the configured dt.

@@ -16,7 +16,7 @@ from ._lib import EcpicError, load as _load1
 # Every symbol include/ecpic2d.h declares.
 EXPORTS_2D = (
     "ecpic2d_create", "ecpic2d_destroy", "ecpic2d_set_particles", "ecpic2d_get_particles",
-    "ecpic2d_set_fields", "ecpic2d_get_fields", "ecpic2d_solve_gauss", "ecpic2d_substep_I",
+    "ecpic2d_set_spins", "ecpic2d_get_spins", "ecpic2d_set_fields", "ecpic2d_get_fields", "ecpic2d_solve_gauss", "ecpic2d_substep_I",
     "ecpic2d_substep_II", "ecpic2d_substep_III", "ecpic2d_substep_IV", "ecpic2d_step", "ecpic2d_energy",
     "ecpic2d_gauss_residual", "ecpic2d_deposit_charge", "ecpic2d_profile_enable", "ecpic2d_kernel_time",
 )
@@ -26,7 +26,7 @@ class Config2D(C.Structure):
     _fields_ = [("L1", C.c_double), ("L2", C.c_double), ("M1", C.c_int32), ("M2", C.c_int32),
                 ("degree", C.c_int32), ("picard_max_iter", C.c_int32), ("n_particles", C.c_int64),
                 ("weight", C.c_double), ("dt", C.c_double), ("picard_tol", C.c_double), ("device", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("spin", C.c_int32), ("hbar", C.c_double)]
 
 
 class IterStats2D(C.Structure):
@@ -35,7 +35,7 @@ class IterStats2D(C.Structure):
 
 class EnergyParts2D(C.Structure):
     _fields_ = [("kinetic", C.c_double), ("e_xy", C.c_double), ("b_z", C.c_double), ("e_z", C.c_double),
-                ("a_z", C.c_double), ("total", C.c_double)]
+                ("a_z", C.c_double), ("total", C.c_double), ("zeeman", C.c_double)]
 
 
 _bound = False
@@ -53,6 +53,8 @@ def load() -> C.CDLL:
             "ecpic2d_destroy": [V],
             "ecpic2d_set_particles": [V, V, V, V, V, C.c_int64],
             "ecpic2d_get_particles": [V, V, V, V, V, C.c_int64],
+            "ecpic2d_set_spins": [V, V, V, V, C.c_int64],
+            "ecpic2d_get_spins": [V, V, V, V, C.c_int64],
             "ecpic2d_set_fields": [V, V, V, V, V, V],
             "ecpic2d_get_fields": [V, V, V, V, V, V],
             "ecpic2d_solve_gauss": [V],
@@ -94,9 +96,11 @@ def _p(a: Optional[np.ndarray]):
 class Context2D:
     """One 2D simulation context on one GPU (ecpic2d_create ... ecpic2d_destroy)."""
 
-    def __init__(self, L1, L2, M1, M2, degree, n_particles, dt, tol, weight=0.0, kmax=0, device=0):
+    def __init__(self, L1, L2, M1, M2, degree, n_particles, dt, tol, weight=0.0, kmax=0, device=0, spin=0,
+                 hbar=0.0):
         self.cfg = Config2D(float(L1), float(L2), int(M1), int(M2), int(degree), int(kmax), int(n_particles),
-                            float(weight), float(dt), float(tol), int(device), 0)
+                            float(weight), float(dt), float(tol), int(device), int(spin), float(hbar))
+        self.spin = bool(spin)
         self.M1, self.M2, self.N = int(M1), int(M2), int(n_particles)
         self.Nc = self.M1 * self.M2
         self._h = C.c_void_p()
@@ -105,8 +109,10 @@ class Context2D:
     @classmethod
     def from_workload(cls, w, n=None, **kw):
         n = w.n_particles if n is None else int(n)
+        spin = getattr(w, "spin", "none") != "none"
         args = dict(L1=w.L1, L2=w.L2, M1=w.M1, M2=w.M2, degree=w.degree, n_particles=n, dt=w.dt, tol=w.tol,
-                    weight=w.L1 * w.L2 / n if n else 0.0, kmax=w.kmax)
+                    weight=w.L1 * w.L2 / n if n else 0.0, kmax=w.kmax, spin=int(spin),
+                    hbar=getattr(w, "hbar", 0.0) if spin else 0.0)
         args.update(kw)
         return cls(**args)
 
@@ -137,6 +143,15 @@ class Context2D:
         _check(load().ecpic2d_get_particles(self._h, *[_p(v) for v in out], self.N), "ecpic2d_get_particles")
         return dict(zip(("x1", "x2", "p1", "p2"), out))
 
+    def set_spins(self, sx, sy, sz):
+        a = [_vec(v, self.N) for v in (sx, sy, sz)]
+        _check(load().ecpic2d_set_spins(self._h, *[_p(v) for v in a], self.N), "ecpic2d_set_spins")
+
+    def get_spins(self):
+        out = [np.empty(self.N) for _ in range(3)]
+        _check(load().ecpic2d_get_spins(self._h, *[_p(v) for v in out], self.N), "ecpic2d_get_spins")
+        return dict(zip(("sx", "sy", "sz"), out))
+
     def set_fields(self, e=None, bz=None, ez=None, az=None):
         """e: V1 coefficients e1 then e2 (2 M1 M2); bz, ez, az: M1 M2 each; None sets zero."""
         N = self.Nc
@@ -153,14 +168,19 @@ class Context2D:
         return {"e": np.concatenate(out[:2]), "bz": out[2], "ez": out[3], "az": out[4]}
 
     def load(self, arrays: dict, solve_gauss: bool = True):
-        """Particles and fields from a generator dict (x1, x2, p1, p2, e, bz, ez, az)."""
+        """Particles and fields from a generator dict (x1, x2, p1, p2, e, bz, ez, az; sx,
+        sy, sz with spin)."""
         self.set_particles(arrays["x1"], arrays["x2"], arrays["p1"], arrays["p2"])
+        if self.spin:
+            self.set_spins(arrays["sx"], arrays["sy"], arrays["sz"])
         self.set_fields(arrays["e"], arrays["bz"], arrays["ez"], arrays["az"])
         if solve_gauss:
             self.solve_gauss()
 
     def state(self) -> dict:
         s = self.get_particles()
+        if self.spin:
+            s.update(self.get_spins())
         s.update(self.get_fields())
         return s
 
@@ -199,10 +219,11 @@ class Context2D:
 
     # -- diagnostics -----------------------------------------------------------
     def energy(self):
-        """[kinetic, 1/2 e^T M1 e, 1/2 b^T M2 b, 1/2 e_z^T M0 e_z, 1/2 a^T K a, H]."""
+        """[kinetic, 1/2 e^T M1 e, 1/2 b^T M2 b, 1/2 e_z^T M0 e_z, 1/2 a^T K a, H, Zeeman]
+        (H includes the Zeeman term; 0 without spin)."""
         e = EnergyParts2D()
         _check(load().ecpic2d_energy(self._h, C.byref(e)), "ecpic2d_energy")
-        return np.array([e.kinetic, e.e_xy, e.b_z, e.e_z, e.a_z, e.total])
+        return np.array([e.kinetic, e.e_xy, e.b_z, e.e_z, e.a_z, e.total, e.zeeman])
 
     def gauss_residual(self, vec=False):
         m = C.c_double()

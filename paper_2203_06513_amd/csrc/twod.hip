@@ -375,6 +375,131 @@ __device__ __forceinline__ double gather00(const double *__restrict__ f, int M1,
     return s;
 }
 
+// sum f_{i1,i2} N^{D1}_{i1}(x1) N^{D2}_{i2}(x2) at a point of cell (c1, c2), from
+// global memory (diagnostics).
+template <int D1, int D2>
+__device__ __forceinline__ double gatherg(const double *__restrict__ f, int M1, int M2, int c1, int c2, double t1,
+                                          double t2) {
+    double b1[D1 + 1], b2[D2 + 1];
+    basis_values<D1>(t1, b1);
+    basis_values<D2>(t2, b2);
+    double s = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 <= D1; ++m1) {
+        const double *row = f + wrapi(c1 - m1, M1) * M2;
+        double t = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 <= D2; ++m2) t += b2[m2] * row[wrapi(c2 - m2, M2)];
+        s += b1[m1] * t;
+    }
+    return s;
+}
+
+// Zeeman sum w s . B_h(x) over the particles (times hbar on the host), B_h =
+// (dA_z/dx2, -dA_z/dx1, B_z) from G a_z (g1, g2) and b_z.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_zeeman(const double *__restrict__ xi1, const double *__restrict__ xi2,
+                                                   const double *__restrict__ sx, const double *__restrict__ sy,
+                                                   const double *__restrict__ sz, const double *__restrict__ g1,
+                                                   const double *__restrict__ g2, const double *__restrict__ bz,
+                                                   int64_t n, int M1, int M2, double w, double *__restrict__ partial) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c1 = (int)u1, c2 = (int)u2;
+        const double t1 = u1 - c1, t2 = u2 - c2;
+        const double Bx = gatherg<P, P - 1>(g2, M1, M2, c1, c2, t1, t2);
+        const double By = -gatherg<P - 1, P>(g1, M1, M2, c1, c2, t1, t2);
+        const double Bz = gatherg<P - 1, P - 1>(bz, M1, M2, c1, c2, t1, t2);
+        s += w * (sx[i] * Bx + sy[i] * By + sz[i] * Bz);
+    }
+    block_sum_to(s, &partial[blockIdx.x]);
+}
+
+// out[i] = in[id[i]]: values given in the caller's order, put into the sorted order.
+__global__ void k2_gather_id(const double *__restrict__ in, const int32_t *__restrict__ id, double *__restrict__ out,
+                             int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = in[id[i]];
+}
+
+// Spin deposits over tiles (no motion): mode 0: Dx += w s_x N^P(x1) N^{P-1}(x2) and
+// Dy += w s_y N^{P-1}(x1) N^P(x2) (Lambda1*^T W S_xy); mode 1: Dz += w s_z
+// N^{P-1}(x1) N^{P-1}(x2) (Lambda2^T W S_z).  Targets zero on entry.
+template <int P>
+__global__ __launch_bounds__(BLOCK) void k2_deposit_spin(const double *__restrict__ xi1,
+                                                         const double *__restrict__ xi2,
+                                                         const double *__restrict__ sx,
+                                                         const double *__restrict__ sy,
+                                                         const double *__restrict__ sz,
+                                                         const int32_t *__restrict__ start, double *__restrict__ Dx,
+                                                         double *__restrict__ Dy, double *__restrict__ Dz, int M1,
+                                                         int M2, int TW, double w, int mode) {
+    constexpr int PR = P + 1, PCM = TWMAX + P, PS = PR * PCM;
+    __shared__ double sX[PS], sY[PS];
+    const int nseg = M2 / TW;
+    const int tile = tile_of_block();
+    const int r = tile / nseg, c0 = (tile - r * nseg) * TW;
+    const int PC = TW + P;
+    const int R0 = r - P, C0 = c0 - P;
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        sX[t] = 0.0;
+        sY[t] = 0.0;
+    }
+    __syncthreads();
+    const int begin = start[tile], end = start[tile + 1];
+    for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
+        const double u1 = xi1[i], u2 = xi2[i];
+        const int c2 = (int)u2;
+        double a1[P + 1], a2[P + 1], b1[P], b2[P];
+        basis_values<P>(u1 - r, a1);
+        basis_values<P>(u2 - c2, a2);
+        basis_values<P - 1>(u1 - r, b1);
+        basis_values<P - 1>(u2 - c2, b2);
+        if (mode == 0) {
+            const double qx = w * sx[i], qy = w * sy[i];
+#pragma unroll
+            for (int m1 = 0; m1 <= P; ++m1)
+#pragma unroll
+                for (int m2 = 0; m2 <= P; ++m2) {
+                    const int k = (r - m1 - R0) * PC + c2 - m2 - C0;
+                    if (m2 < P) atomicAdd(&sX[k], qx * a1[m1] * b2[m2]);
+                    if (m1 < P) atomicAdd(&sY[k], qy * b1[m1] * a2[m2]);
+                }
+        } else {
+            const double qz = w * sz[i];
+#pragma unroll
+            for (int m1 = 0; m1 < P; ++m1)
+#pragma unroll
+                for (int m2 = 0; m2 < P; ++m2) atomicAdd(&sX[(r - m1 - R0) * PC + c2 - m2 - C0], qz * b1[m1] * b2[m2]);
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
+        const int i = t / PC, j = t - i * PC;
+        const int g = wrapi(R0 + i, M1) * M2 + wrapi(C0 + j, M2);
+        if (mode == 0) {
+            if (sX[t] != 0.0) atomicAdd(&Dx[g], sX[t]);
+            if (sY[t] != 0.0) atomicAdd(&Dy[g], sY[t]);
+        } else if (sX[t] != 0.0) {
+            atomicAdd(&Dz[g], sX[t]);
+        }
+    }
+}
+
+// src = G*^T (Dx, Dy) = G2^T Dx - G1^T Dy, the transposes of the backward
+// differences: (G1^T u)_i = (u_{i1,i2} - u_{i1+1,i2}) / dx1, likewise in x2.
+__global__ __launch_bounds__(BLOCK) void k2_spin_src(const double *__restrict__ Dx, const double *__restrict__ Dy,
+                                                     double *__restrict__ src, int M1, int M2, double inv_dx1,
+                                                     double inv_dx2) {
+    const int N = M1 * M2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
+        const int i1 = i / M2, i2 = i - i1 * M2;
+        src[i] = (Dx[i] - Dx[i1 * M2 + wrapi(i2 + 1, M2)]) * inv_dx2 -
+                 (Dy[i] - Dy[wrapi(i1 + 1, M1) * M2 + i2]) * inv_dx1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Subsystem I sweep (Section 4.3): gather, push, deposit, one tile per block
 // ---------------------------------------------------------------------------
@@ -392,6 +517,8 @@ struct SweepArgs {
     const int *gate;                     // nonzero: an earlier sweep converged, nothing to do
     int M1, M2, TW;
     double inv_dx1, inv_dx2, dt, w;
+    const double *sx, *sy, *sz, *bz;     // spins and b_z (the sweep with spin)
+    double hbar;
 };
 
 // Path integrals of the V1 basis on one piece of the straight step (between two
@@ -431,7 +558,7 @@ __device__ __forceinline__ void piece_integrals(double x1, double x2, double s1,
 
 // The field patch of a tile in LDS (rows r-P-1 .. r+1, columns c0-P-1 .. c0+TW).
 struct Patch {
-    double *E1, *E2, *A, *G1, *G2, *J1, *J2;
+    double *E1, *E2, *A, *G1, *G2, *J1, *J2, *Bz;
     int PC, R0, C0, r;
 };
 
@@ -517,7 +644,7 @@ __device__ __forceinline__ void pieces(const Geo &g, bool live, int first, int l
 // A_z at both ends, the means of dA_z/dx2 along the vertical leg (at x1^n) and of
 // dA_z/dx1 along the horizontal leg (at x2^{n+1}), the push of the Subsystem I
 // scheme, and the stores of particle i.
-template <int P>
+template <int P, bool SPIN>
 __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1, double E2, const Patch &t,
                                        const SweepArgs &a, double &rmax, int &flags) {
     const int PC = t.PC, R0 = t.R0, C0 = t.C0, ca1 = t.r, ca2 = g.ca2, cb1 = g.cb1, cb2 = g.cb2;
@@ -556,10 +683,72 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
         for (int m2 = 0; m2 <= P; ++m2) s += bb2[m2] * t.G1[(ca1 - P + k - R0) * PC + cb2 - m2 - C0];
         Dh += lm1[k] * s;
     }
+    double F1 = 0.0, F2 = 0.0;   // spin force / hbar
+    if constexpr (SPIN) {
+        // Means along the same two legs of the derivatives of dA_z/dx2 (coefficients
+        // G2 = (G a)_2, degrees (P, P-1)), dA_z/dx1 (G1, (P-1, P)) and B_z ((P-1, P-1)):
+        // each derivative's coefficients are backward differences of the field's.
+        double lq2[P + 1], lq1[P + 1], bm1[P], bmb2[P];
+        line_mean_v1<P - 1>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, lq2);   // degree P-2, indices ca2 - P + 1 + k
+        line_mean_v1<P - 1>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, lq1);   // degree P-2, indices ca1 - P + 1 + k
+        basis_values<P - 1>(g.x1 - ca1, bm1);
+        basis_values<P - 1>(g.y2 - cb2, bmb2);
+        const double i1 = a.inv_dx1, i2 = a.inv_dx2;
+        double Sy2 = 0.0, Sx2 = 0.0, Sb2 = 0.0;   // x2 leg at x1^n
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1) {
+            const int row = (ca1 - m1 - R0) * PC - C0;
+            double ty = 0.0, tx = 0.0, tb = 0.0;
+#pragma unroll
+            for (int k = 0; k <= P + 1; ++k) {
+                const int c = row + ca2 - P + k;   // column ca2 - P + k
+                tx += lm2[k] * (t.G1[c] - t.G1[c - 1]);
+                if (k >= 1) {
+                    ty += lq2[k - 1] * (t.G2[c] - t.G2[c - 1]);
+                    tb += lq2[k - 1] * (t.Bz[c] - t.Bz[c - 1]);
+                }
+            }
+            Sy2 += ba1[m1] * ty;
+            if (m1 < P) {
+                Sx2 += bm1[m1] * tx;
+                Sb2 += bm1[m1] * tb;
+            }
+        }
+        double Sy1 = 0.0, Sx1 = 0.0, Sb1 = 0.0;   // x1 leg at x2^{n+1}
+#pragma unroll
+        for (int k = 0; k <= P + 1; ++k) {
+            const int r1 = (ca1 - P + k - R0) * PC - C0, r0 = r1 - PC;   // rows ca1 - P + k and the one below
+            double ty = 0.0, tx = 0.0, tb = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 <= P; ++m2) {
+                const int c = cb2 - m2;
+                tx += bb2[m2] * (t.G1[r1 + c] - t.G1[r0 + c]);
+                if (m2 < P) {
+                    ty += bmb2[m2] * (t.G2[r1 + c] - t.G2[r0 + c]);
+                    tb += bmb2[m2] * (t.Bz[r1 + c] - t.Bz[r0 + c]);
+                }
+            }
+            Sy1 += lm1[k] * ty;
+            if (k >= 1) {
+                Sx1 += lq1[k - 1] * tx;
+                Sb1 += lq1[k - 1] * tb;
+            }
+        }
+        const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
+        F1 = (sx * Sy1 - sy * Sx1 + sz * Sb1) * i1;
+        F2 = (sx * Sy2 - sy * Sx2 + sz * Sb2) * i2;
+    }
     const double q1 = g.q1, q2 = g.q2, pp = q1 * q1 + q2 * q2;
     const double gA = sqrt(1.0 + pp + Aa * Aa), gB = sqrt(1.0 + pp + Ab * Ab);
     const double f = -(Aa + Ab) / (gA + gB);
-    const double n1 = q1 + a.dt * (E1 + f * Dh), n2 = q2 + a.dt * (E2 + f * Dv);
+    double n1, n2;
+    if constexpr (SPIN) {
+        n1 = q1 + a.dt * (E1 + f * Dh - a.hbar * F1);
+        n2 = q2 + a.dt * (E2 + f * Dv - a.hbar * F2);
+    } else {
+        n1 = q1 + a.dt * (E1 + f * Dh);
+        n2 = q2 + a.dt * (E2 + f * Dv);
+    }
     const double gC = sqrt(1.0 + n1 * n1 + n2 * n2 + Ab * Ab);
     const double sc = a.dt / (gB + gC);
     const double e1 = (q1 + n1) * sc, e2 = (q2 + n2) * sc;
@@ -585,19 +774,19 @@ constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 // FIRST (sweep 0): the increment is the explicit start d^(0) = dt p^n /
 // gamma(x^n, p^n), formed from A_z on the patch and stored; that variant is held
 // to three waves per SIMD (168 VGPRs) at p = 3, like the others.
-template <int P, bool FIRST>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && P == 3 ? 3 : 1))) void k2_sweep_I(
+template <int P, bool FIRST, bool SPIN>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && !SPIN && P == 3 ? 3 : 1))) void k2_sweep_I(
     SweepArgs a) {
     if (*a.gate) return;   // uniform over the grid
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
-    __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS];
+    __shared__ double sE1[PS], sE2[PS], sA[PS], sG1[PS], sG2[PS], sJ1[PS], sJ2[PS], sBz[SPIN ? PS : 1];
     __shared__ int qI[BLOCK / WAVE][QCAP];
     __shared__ double qV[BLOCK / WAVE][QV][QCAP];
     const int nseg = a.M2 / a.TW;
     const int tile = tile_of_block();
     const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
     const int PC = a.TW + P + 2;
-    const Patch t{sE1, sE2, sA, sG1, sG2, sJ1, sJ2, PC, r - P - 1, c0 - P - 1, r};
+    const Patch t{sE1, sE2, sA, sG1, sG2, sJ1, sJ2, sBz, PC, r - P - 1, c0 - P - 1, r};
     for (int k = threadIdx.x; k < PR * PC; k += blockDim.x) {
         const int i = k / PC, j = k - i * PC;
         const int g = wrapi(t.R0 + i, a.M1) * a.M2 + wrapi(t.C0 + j, a.M2);
@@ -608,6 +797,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && 
         sG2[k] = a.g2a[g];
         sJ1[k] = 0.0;
         sJ2[k] = 0.0;
+        if constexpr (SPIN) sBz[k] = a.bz[g];
     }
     __syncthreads();
     const int begin = a.start[tile], end = a.start[tile + 1];
@@ -629,7 +819,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && 
         double E1 = v[4], E2 = v[5];
         const Geo g = geometry(a, v[0], v[1], a.p1[i], a.p2[i], v[2], v[3], valid, r, flags);
         pieces<P>(g, valid, 1, 2, t, a.w, E1, E2);
-        finish<P>(g, valid, i, E1, E2, t, a, rmax, flags);
+        finish<P, SPIN>(g, valid, i, E1, E2, t, a, rmax, flags);
         head += n;
     };
     const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
@@ -679,7 +869,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && 
             qv[5][slot] = E2;
         }
         tail += __builtin_popcountll(cm);
-        if (live && !cross) finish<P>(g, live, i, E1, E2, t, a, rmax, flags);
+        if (live && !cross) finish<P, SPIN>(g, live, i, E1, E2, t, a, rmax, flags);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -797,12 +987,16 @@ struct Resort {
     int32_t *did;
     int M1, M2;
     double inv_dx1, inv_dx2;
+    const double *ss[3];   // spins (null without spin)
+    double *os[3];
     __device__ __forceinline__ void put(int j, int i) const {
         o1[j] = new_coord(xi1[i], d1[i], inv_dx1, M1);
         o2[j] = new_coord(xi2[i], d2[i], inv_dx2, M2);
         r1[j] = pk1[i];
         r2[j] = pk2[i];
         did[j] = sid[i];
+        if (ss[0])
+            for (int q = 0; q < 3; ++q) os[q][j] = ss[q][i];
     }
 };
 
@@ -895,7 +1089,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k2_tile_resort(Resort a) {
     // One output array at a time: the old tile read in order (and the
     // arrivals), each value placed in LDS at its new position, the tile written
     // in order.
-    for (int f = 0; f < 5; ++f) {
+    const int nf = a.ss[0] ? 8 : 5;   // with spin: s_x, s_y, s_z as well
+    for (int f = 0; f < nf; ++f) {
         __syncthreads();
         for (int q0 = threadIdx.x; q0 < nsrc; q0 += RB * nt) {
             int i[RB], p[RB];
@@ -914,7 +1109,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k2_tile_resort(Resort a) {
                     case 1: v[k] = new_coord(a.xi2[i[k]], a.d2[i[k]], a.inv_dx2, a.M2); break;
                     case 2: v[k] = a.pk1[i[k]]; break;
                     case 3: v[k] = a.pk2[i[k]]; break;
-                    default: v[k] = (double)a.sid[i[k]]; break;
+                    case 4: v[k] = (double)a.sid[i[k]]; break;
+                    default: v[k] = a.ss[f - 5][i[k]]; break;
                 }
             }
 #pragma unroll
@@ -922,9 +1118,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k2_tile_resort(Resort a) {
                 if (i[k] >= 0) val[p[k]] = v[k];
         }
         __syncthreads();
-        double *out = f == 0 ? a.o1 : f == 1 ? a.o2 : f == 2 ? a.r1 : a.r2;
+        double *out = f == 0 ? a.o1 : f == 1 ? a.o2 : f == 2 ? a.r1 : f == 3 ? a.r2 : f == 4 ? nullptr : a.os[f - 5];
         for (int p = threadIdx.x; p < cnt; p += nt) {
-            if (f < 4) out[base + p] = val[p];
+            if (f != 4) out[base + p] = val[p];
             else a.did[base + p] = (int32_t)val[p];
         }
     }
@@ -1023,30 +1219,41 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
 }
 
 // Subsystem II over tiles: B_z (V2) and A_z (V0) gathered from the tile's LDS
-// patch, every momentum turned by the angle B_z dt / gamma.
-template <int P>
-__global__ __launch_bounds__(BLOCK) void k2_rotate_tiles(const double *__restrict__ xi1,
-                                                         const double *__restrict__ xi2, double *__restrict__ p1,
-                                                         double *__restrict__ p2, const int32_t *__restrict__ start,
-                                                         const double *__restrict__ bz, const double *__restrict__ az,
-                                                         int M1, int M2, int TW, double dt) {
+// patch, every momentum turned by the angle B_z dt / gamma.  SPIN: every spin
+// also turns about B_h = (dA_z/dx2, -dA_z/dx1, B_z) by the angle -|B_h| dt
+// (ds/dt = s x B_h, Rodrigues' formula), with G a_z staged as well.
+struct RotArgs {
+    const double *xi1, *xi2;
+    double *p1, *p2, *sx, *sy, *sz;
+    const int32_t *start;
+    const double *bz, *az, *g1, *g2;
+    int M1, M2, TW;
+    double dt;
+};
+
+template <int P, bool SPIN>
+__global__ __launch_bounds__(BLOCK) void k2_rotate_tiles(RotArgs a) {
     constexpr int PR = P + 1, PCM = TWMAX + P, PS = PR * PCM;
-    __shared__ double sA[PS], sB[PS];
-    const int nseg = M2 / TW;
+    __shared__ double sA[PS], sB[PS], sG1[SPIN ? PS : 1], sG2[SPIN ? PS : 1];
+    const int nseg = a.M2 / a.TW;
     const int tile = tile_of_block();
-    const int r = tile / nseg, c0 = (tile - r * nseg) * TW;
-    const int PC = TW + P;
+    const int r = tile / nseg, c0 = (tile - r * nseg) * a.TW;
+    const int PC = a.TW + P;
     const int R0 = r - P, C0 = c0 - P;
     for (int t = threadIdx.x; t < PR * PC; t += blockDim.x) {
         const int i = t / PC, j = t - i * PC;
-        const int g = wrapi(R0 + i, M1) * M2 + wrapi(C0 + j, M2);
-        sA[t] = az[g];
-        sB[t] = bz[g];
+        const int g = wrapi(R0 + i, a.M1) * a.M2 + wrapi(C0 + j, a.M2);
+        sA[t] = a.az[g];
+        sB[t] = a.bz[g];
+        if constexpr (SPIN) {
+            sG1[t] = a.g1[g];
+            sG2[t] = a.g2[g];
+        }
     }
     __syncthreads();
-    const int begin = start[tile], end = start[tile + 1];
+    const int begin = a.start[tile], end = a.start[tile + 1];
     for (int i = begin + threadIdx.x; i < end; i += blockDim.x) {
-        const double u1 = xi1[i], u2 = xi2[i];
+        const double u1 = a.xi1[i], u2 = a.xi2[i];
         const int c2 = (int)u2;
         const double t1 = u1 - r, t2 = u2 - c2;
         double a1[P + 1], a2[P + 1], b1[P], b2[P];
@@ -1054,25 +1261,47 @@ __global__ __launch_bounds__(BLOCK) void k2_rotate_tiles(const double *__restric
         basis_values<P>(t2, a2);
         basis_values<P - 1>(t1, b1);
         basis_values<P - 1>(t2, b2);
-        double A = 0.0, B = 0.0;
+        double A = 0.0, B = 0.0, Bx = 0.0, By = 0.0;
 #pragma unroll
         for (int m1 = 0; m1 <= P; ++m1) {
-            double ta = 0.0, tb = 0.0;
+            double ta = 0.0, tb = 0.0, tx = 0.0, ty = 0.0;
 #pragma unroll
             for (int m2 = 0; m2 <= P; ++m2) {
                 const int s = (r - m1 - R0) * PC + c2 - m2 - C0;
                 ta += a2[m2] * sA[s];
                 if (m1 < P && m2 < P) tb += b2[m2] * sB[s];
+                if constexpr (SPIN) {
+                    if (m2 < P) tx += b2[m2] * sG2[s];   // dA_z/dx2: degrees (P, P-1)
+                    if (m1 < P) ty += a2[m2] * sG1[s];   // dA_z/dx1: degrees (P-1, P)
+                }
             }
             A += a1[m1] * ta;
             if (m1 < P) B += b1[m1] * tb;
+            if constexpr (SPIN) {
+                Bx += a1[m1] * tx;
+                if (m1 < P) By -= b1[m1] * ty;
+            }
         }
-        const double q1 = p1[i], q2 = p2[i];
-        const double th = B * dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+        const double q1 = a.p1[i], q2 = a.p2[i];
+        const double th = B * a.dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
         double sn, cs;
         sincos(th, &sn, &cs);
-        p1[i] = q1 * cs + q2 * sn;
-        p2[i] = -q1 * sn + q2 * cs;
+        a.p1[i] = q1 * cs + q2 * sn;
+        a.p2[i] = -q1 * sn + q2 * cs;
+        if constexpr (SPIN) {
+            const double nb = sqrt(Bx * Bx + By * By + B * B);
+            if (nb > 0.0) {
+                const double k0 = Bx / nb, k1 = By / nb, k2 = B / nb;
+                const double s0 = a.sx[i], s1 = a.sy[i], s2 = a.sz[i];
+                const double x0 = k1 * s2 - k2 * s1, x1 = k2 * s0 - k0 * s2, x2 = k0 * s1 - k1 * s0;
+                const double ks = k0 * s0 + k1 * s1 + k2 * s2;
+                double sb, cb;
+                sincos(nb * a.dt, &sb, &cb);
+                a.sx[i] = s0 * cb - x0 * sb + k0 * ks * (1.0 - cb);
+                a.sy[i] = s1 * cb - x1 * sb + k1 * ks * (1.0 - cb);
+                a.sz[i] = s2 * cb - x2 * sb + k2 * ks * (1.0 - cb);
+            }
+        }
     }
 }
 
@@ -1459,6 +1688,21 @@ struct OpIIIrhs {
     }
 };
 
+// With spin (v[2] = G*^T Lambda1*^T W S_xy): R gains dt hbar v[2].
+struct OpIIIrhsS {
+    static constexpr bool INVERSE = false;
+    Sym s;
+    double2 *R;
+    int M2;
+    double dt, hbar;
+    __device__ void operator()(int k1, int k2, double2 (&v)[3]) const {
+        const double kp = kappa(s, k1, k2), m0 = s.m0a[k1] * s.m0b[k2];
+        const double ce = m0 - 0.25 * dt * dt * kp, ca = dt * kp, cs = dt * hbar;
+        R[(size_t)k1 * M2 + k2] = make_double2(ce * v[0].x + ca * v[1].x + cs * v[2].x,
+                                               ce * v[0].y + ca * v[1].y + cs * v[2].y);
+    }
+};
+
 // Subsystem III solve: e = (R + dt S) / (M0 + q K).
 struct OpIII {
     static constexpr bool INVERSE = true;
@@ -1488,24 +1732,43 @@ struct EpiIII {
 //   b' = ((1 - q sigma) b - dt (c1 e2 - c2 e1)) / (1 + q sigma),
 //   e1' = e1 - dt conj(c2) (m1b/m0b) (b + b')/2,  e2' = e2 + dt conj(c1) (m1a/m0a) (b + b')/2,
 // the implicit midpoint step of the Maxwell subsystem eliminated for b.
+// One Fourier mode of the Maxwell step (e1, e2, b in place).
+__device__ __forceinline__ void maxwell_mode(const Sym &s, double dt, int k1, int k2, double2 &e1, double2 &e2,
+                                             double2 &b) {
+    const double2 c1 = make_double2(s.cra[k1], s.cia[k1]), c2 = make_double2(s.crb[k2], s.cib[k2]);
+    const double ra = s.m1a[k1] / s.m0a[k1], rb = s.m1b[k2] / s.m0b[k2];
+    const double sig = (c1.x * c1.x + c1.y * c1.y) * ra + (c2.x * c2.x + c2.y * c2.y) * rb;
+    const double q = 0.25 * dt * dt;
+    const double2 t1 = cmul(c1, e2), t2 = cmul(c2, e1);
+    const double2 ce = make_double2(t1.x - t2.x, t1.y - t2.y);
+    const double den = 1.0 / (1.0 + q * sig), num = 1.0 - q * sig;
+    const double2 bn = make_double2((num * b.x - dt * ce.x) * den, (num * b.y - dt * ce.y) * den);
+    const double2 bm = make_double2(0.5 * (b.x + bn.x), 0.5 * (b.y + bn.y));
+    const double2 u1 = cmul(make_double2(c2.x, -c2.y), bm), u2 = cmul(make_double2(c1.x, -c1.y), bm);
+    e1 = make_double2(e1.x - dt * rb * u1.x, e1.y - dt * rb * u1.y);
+    e2 = make_double2(e2.x + dt * ra * u2.x, e2.y + dt * ra * u2.y);
+    b = bn;
+}
+
 struct OpIV {
     static constexpr bool INVERSE = true;
     Sym s;
     double dt;
-    __device__ void operator()(int k1, int k2, double2 (&v)[3]) const {
-        const double2 c1 = make_double2(s.cra[k1], s.cia[k1]), c2 = make_double2(s.crb[k2], s.cib[k2]);
-        const double ra = s.m1a[k1] / s.m0a[k1], rb = s.m1b[k2] / s.m0b[k2];
-        const double sig = (c1.x * c1.x + c1.y * c1.y) * ra + (c2.x * c2.x + c2.y * c2.y) * rb;
-        const double q = 0.25 * dt * dt;
-        const double2 t1 = cmul(c1, v[1]), t2 = cmul(c2, v[0]);
-        const double2 ce = make_double2(t1.x - t2.x, t1.y - t2.y);
-        const double den = 1.0 / (1.0 + q * sig), num = 1.0 - q * sig;
-        const double2 bn = make_double2((num * v[2].x - dt * ce.x) * den, (num * v[2].y - dt * ce.y) * den);
-        const double2 bm = make_double2(0.5 * (v[2].x + bn.x), 0.5 * (v[2].y + bn.y));
-        const double2 u1 = cmul(make_double2(c2.x, -c2.y), bm), u2 = cmul(make_double2(c1.x, -c1.y), bm);
-        v[0] = make_double2(v[0].x - dt * rb * u1.x, v[0].y - dt * rb * u1.y);
-        v[1] = make_double2(v[1].x + dt * ra * u2.x, v[1].y + dt * ra * u2.y);
-        v[2] = bn;
+    __device__ void operator()(int k1, int k2, double2 (&v)[3]) const { maxwell_mode(s, dt, k1, k2, v[0], v[1], v[2]); }
+};
+
+// With spin the b_z equation carries hbar Lambda2^T W S_z (v[3], constant): with
+// b~ = b + hbar M2^{-1} D_z the scheme is the one without spin, so b~ is stepped
+// and the shift taken off again.
+struct OpIVs {
+    static constexpr bool INVERSE = true;
+    Sym s;
+    double dt, hbar;
+    __device__ void operator()(int k1, int k2, double2 (&v)[4]) const {
+        const double sh = hbar / (s.m1a[k1] * s.m1b[k2]);
+        double2 b = make_double2(v[2].x + sh * v[3].x, v[2].y + sh * v[3].y);
+        maxwell_mode(s, dt, k1, k2, v[0], v[1], b);
+        v[2] = make_double2(b.x - sh * v[3].x, b.y - sh * v[3].y);
     }
 };
 
@@ -1534,7 +1797,7 @@ struct EpiStore {
     __device__ double operator()(int b, int g, double v) const {
 #pragma unroll
         for (int q = 0; q < NB; ++q)
-            if (b == q) out.p[q][g] = v;
+            if (b == q && out.p[q]) out.p[q][g] = v;
         return 0.0;
     }
 };
@@ -1606,6 +1869,10 @@ struct ecpic2d_ctx {
     unsigned long long *res = nullptr;   // 3 * MAXK + 4 slots
     int *flags = nullptr;
     int *gate = nullptr;                 // set once an iteration has converged (or failed)
+    int spin = 0;                        // particles carry spins (hbar terms on)
+    double hbar = 0.0;
+    double *sx[2] = {}, *sy[2] = {}, *sz[2] = {};   // spins, in the particle buffers' order
+    double *Dx = nullptr, *Dy = nullptr, *Dz = nullptr, *ssrc = nullptr;   // spin deposits and G*^T source
     double *hres = nullptr, *hres_dev = nullptr;   // pinned mirror: 3 values per iteration (I, then III)
     hipEvent_t ev[2] = {};
     bool have_particles = false;
@@ -1704,7 +1971,8 @@ void sort_tiles(ecpic2d_ctx *c, int di) {
                                                      c->mig);
         const Resort r{c->xi1[A], c->xi2[A], c->d1[di], c->d2[di], c->pk1, c->pk2, c->id[A], c->cell, c->mig,
                        c->tstart[T0], c->tstart[T1], c->tstay, c->xi1[B], c->xi2[B], c->p1[B], c->p2[B], c->id[B],
-                       c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2};
+                       c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2, {c->sx[A], c->sy[A], c->sz[A]},
+                       {c->sx[B], c->sy[B], c->sz[B]}};
         k2_tile_resort<<<nt, SORT_THREADS, 0, c->stream>>>(r);
     });
     c->cur = B;
@@ -1788,12 +2056,19 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
         const int di = k & 1;
         SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
                     c->pk1, c->pk2, c->tstart[c->ts], c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
-                    c->res + k, c->flags, c->gate, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w};
+                    c->res + k, c->flags, c->gate, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w,
+                    c->sx[A], c->sy[A], c->sz[A], c->bz, c->hbar};
         timed(c, "sweep_I", [&] {
-            if (k == 0) {
-                LAUNCH_P(c->P, k2_sweep_I<PP, true><<<n_tiles(c), BLOCK, 0, s>>>(a));
+            if (c->spin) {
+                if (k == 0) {
+                    LAUNCH_P(c->P, k2_sweep_I<PP, true, true><<<n_tiles(c), BLOCK, 0, s>>>(a));
+                } else {
+                    LAUNCH_P(c->P, k2_sweep_I<PP, false, true><<<n_tiles(c), BLOCK, 0, s>>>(a));
+                }
+            } else if (k == 0) {
+                LAUNCH_P(c->P, k2_sweep_I<PP, true, false><<<n_tiles(c), BLOCK, 0, s>>>(a));
             } else {
-                LAUNCH_P(c->P, k2_sweep_I<PP, false><<<n_tiles(c), BLOCK, 0, s>>>(a));
+                LAUNCH_P(c->P, k2_sweep_I<PP, false, false><<<n_tiles(c), BLOCK, 0, s>>>(a));
             }
         });
         spectral<2>(c, "solve_I", Ptrs<2>{{c->J1, c->J2}}, 3, OpM1inv{sy},
@@ -1841,10 +2116,17 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
 
 int substep_II(ecpic2d_ctx *c, double dt) {
     const int A = c->cur;
+    if (c->spin)
+        k2_grad<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->az, c->g1a, c->g2a, c->M1, c->M2, 1.0 / c->dx1,
+                                                          1.0 / c->dx2);
+    const RotArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->sx[A], c->sy[A], c->sz[A], c->tstart[c->ts],
+                    c->bz, c->az, c->g1a, c->g2a, c->M1, c->M2, c->TW, dt};
     timed(c, "rotate_II", [&] {
-        LAUNCH_P(c->P, k2_rotate_tiles<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(
-                           c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->bz, c->az, c->M1, c->M2,
-                           c->TW, dt));
+        if (c->spin) {
+            LAUNCH_P(c->P, k2_rotate_tiles<PP, true><<<n_tiles(c), BLOCK, 0, c->stream>>>(a));
+        } else {
+            LAUNCH_P(c->P, k2_rotate_tiles<PP, false><<<n_tiles(c), BLOCK, 0, c->stream>>>(a));
+        }
     });
     return ECPIC_OK;
 }
@@ -1857,9 +2139,20 @@ int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
     k2_copy<<<gC, BLOCK, 0, s>>>(c->ezk, c->ez, Nc);
     k2_fill<<<gC, BLOCK, 0, s>>>(c->S, Nc, 0.0);
     const Sym sy = sym_of(c);
-    // constant part in Fourier space
-    spectral<2>(c, "solve_III", Ptrs<2>{{c->ezn, c->az}}, 0, OpIIIrhs{sy, c->R, c->M2, dt},
-                EpiStore<2>{Ptrs<2>{{nullptr, nullptr}}, nullptr});
+    // constant part in Fourier space (with spin: plus dt hbar G*^T Lambda1*^T W S_xy)
+    if (c->spin) {
+        k2_fill<<<gC, BLOCK, 0, s>>>(c->Dx, Nc, 0.0);
+        k2_fill<<<gC, BLOCK, 0, s>>>(c->Dy, Nc, 0.0);
+        LAUNCH_P(c->P, k2_deposit_spin<PP><<<n_tiles(c), BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->sx[A], c->sy[A],
+                                                                         c->sz[A], c->tstart[c->ts], c->Dx, c->Dy,
+                                                                         nullptr, c->M1, c->M2, c->TW, c->w, 0));
+        k2_spin_src<<<gC, BLOCK, 0, s>>>(c->Dx, c->Dy, c->ssrc, c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2);
+        spectral<3>(c, "solve_III", Ptrs<3>{{c->ezn, c->az, c->ssrc}}, 0, OpIIIrhsS{sy, c->R, c->M2, dt, c->hbar},
+                    EpiStore<3>{Ptrs<3>{{nullptr, nullptr, nullptr}}, nullptr});
+    } else {
+        spectral<2>(c, "solve_III", Ptrs<2>{{c->ezn, c->az}}, 0, OpIIIrhs{sy, c->R, c->M2, dt},
+                    EpiStore<2>{Ptrs<2>{{nullptr, nullptr}}, nullptr});
+    }
     k2_fill_i32<<<1, 1, 0, s>>>(c->gate, 1);
     auto iterate = [&](int k) {   // as in Subsystem I: deposit, solve, check, event ev[k & 1]
         DepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->tstart[c->ts], c->az, c->ezn, c->ezk, c->S,
@@ -1896,6 +2189,16 @@ int substep_III(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
 }
 
 int substep_IV(ecpic2d_ctx *c, double dt) {
+    if (c->spin) {   // with the constant source hbar C^T Lambda2^T W S_z
+        const int A = c->cur;
+        k2_fill<<<grid_for(c->Nc), BLOCK, 0, c->stream>>>(c->Dz, c->Nc, 0.0);
+        LAUNCH_P(c->P, k2_deposit_spin<PP><<<n_tiles(c), BLOCK, 0, c->stream>>>(
+                           c->xi1[A], c->xi2[A], c->sx[A], c->sy[A], c->sz[A], c->tstart[c->ts], nullptr, nullptr,
+                           c->Dz, c->M1, c->M2, c->TW, c->w, 1));
+        spectral<4>(c, "maxwell_IV", Ptrs<4>{{c->e1, c->e2, c->bz, c->Dz}}, 0, OpIVs{sym_of(c), dt, c->hbar},
+                    EpiStore<4>{Ptrs<4>{{c->e1, c->e2, c->bz, nullptr}}, nullptr});
+        return ECPIC_OK;
+    }
     spectral<3>(c, "maxwell_IV", Ptrs<3>{{c->e1, c->e2, c->bz}}, 0, OpIV{sym_of(c), dt},
                 EpiStore<3>{Ptrs<3>{{c->e1, c->e2, c->bz}}, nullptr});
     return ECPIC_OK;
@@ -1941,7 +2244,8 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     if (!(g.L1 > 0) || !(g.L2 > 0) || !pow2(g.M1) || !pow2(g.M2) || g.degree < 2 || g.degree > 5 ||
         g.n_particles < 0 || g.n_particles > INT32_MAX || !(g.picard_tol > 0) || g.picard_max_iter < 0 ||
         g.picard_max_iter > MAXK || !(g.dt > 0) || !(g.dt < std::min(dx1, dx2)) || g.weight < 0 ||
-        !std::isfinite(g.weight) || g.reserved != 0)
+        !std::isfinite(g.weight) || (g.spin != 0 && g.spin != 1) || !std::isfinite(g.hbar) ||
+        (!g.spin && g.hbar != 0.0))
         return ECPIC_EINVAL;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || g.device < 0 || g.device >= ndev) return ECPIC_EDEVICE;
@@ -1963,6 +2267,8 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     c->dx2 = dx2;
     c->w = g.weight > 0 ? g.weight : (c->N > 0 ? g.L1 * g.L2 / (double)c->N : 0.0);
     c->tol = g.picard_tol;
+    c->spin = g.spin;
+    c->hbar = g.hbar;
     c->m0row = mass_row2(c->P);
     c->m1row = mass_row2(c->P - 1);
     if (hipStreamCreate(&c->stream) != hipSuccess) { delete c; return ECPIC_EDEVICE; }
@@ -1982,7 +2288,11 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
     double **grids[] = {&c->e1, &c->e2, &c->bz, &c->ez, &c->az, &c->en1, &c->en2, &c->ek1, &c->ek2, &c->eb1,
                         &c->eb2, &c->J1, &c->J2, &c->g1a, &c->g2a, &c->ezn, &c->ezk, &c->S, &c->tmp};
     for (double **gp : grids) rc |= dalloc(c, gp, Nc);
-    rc |= dalloc(c, &c->Z, 3 * Nc) | dalloc(c, &c->R, Nc) | dalloc(c, &c->tw1, (size_t)c->M1 / 2) |
+    if (c->spin) {
+        for (int b = 0; b < 2; ++b) rc |= dalloc(c, &c->sx[b], N) | dalloc(c, &c->sy[b], N) | dalloc(c, &c->sz[b], N);
+        rc |= dalloc(c, &c->Dx, Nc) | dalloc(c, &c->Dy, Nc) | dalloc(c, &c->Dz, Nc) | dalloc(c, &c->ssrc, Nc);
+    }
+    rc |= dalloc(c, &c->Z, 4 * Nc) | dalloc(c, &c->R, Nc) | dalloc(c, &c->tw1, (size_t)c->M1 / 2) |
           dalloc(c, &c->tw2, (size_t)c->M2 / 2) | dalloc(c, &c->sym, 4 * (size_t)(c->M1 + c->M2)) |
           dalloc(c, &c->partial, RED_BLOCKS + 16) | dalloc(c, &c->res, 3 * MAXK + 4) | dalloc(c, &c->flags, 1) |
           dalloc(c, &c->gate, 1);
@@ -2076,10 +2386,50 @@ int ecpic2d_set_particles(ecpic2d_ctx *c, const double *x1, const double *x2, co
     k2_bin_new<<<grid_for(n), BLOCK, 0, s>>>(c->d1[0], c->d2[0], c->xi1[A], c->xi2[A], c->cell, c->count, n,
                                              c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2, c->flags);
     sort_particles(c);
+    if (c->spin)   // the spins start at zero; ecpic2d_set_spins gives them
+        for (double *sp : {c->sx[c->cur], c->sy[c->cur], c->sz[c->cur]})
+            k2_fill<<<grid_for(n), BLOCK, 0, s>>>(sp, n, 0.0);
     int rc = flags_status(c);
     if (rc) return rc == ECPIC_ENONFINITE ? ECPIC_EINVAL : rc;
     c->have_particles = true;
     return ECPIC_OK;
+}
+
+int ecpic2d_set_spins(ecpic2d_ctx *c, const double *sx, const double *sy, const double *sz, int64_t n) {
+    if (!c || !c->spin || n != c->N || (n > 0 && (!sx || !sy || !sz))) return ECPIC_EINVAL;
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(sx[i]) || !std::isfinite(sy[i]) || !std::isfinite(sz[i])) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int A = c->cur;
+    const size_t bytes = sizeof(double) * (size_t)n;
+    const double *in[3] = {sx, sy, sz};
+    double *dst[3] = {c->sx[A], c->sy[A], c->sz[A]};
+    for (int q = 0; q < 3 && n > 0; ++q) {
+        // staging buffer: pk1 (free between substeps), in the caller's order
+        if (hipMemcpyAsync(c->pk1, in[q], bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return ECPIC_EDEVICE;
+        k2_gather_id<<<grid_for(n), BLOCK, 0, c->stream>>>(c->pk1, c->id[A], dst[q], n);
+    }
+    return sync2(c);
+}
+
+int ecpic2d_get_spins(ecpic2d_ctx *c, double *sx, double *sy, double *sz, int64_t n) {
+    if (!c || !c->spin || n != c->N || (n > 0 && (!sx || !sy || !sz))) return ECPIC_EINVAL;
+    if (!c->have_particles) return ECPIC_ESTATE;
+    hipSetDevice(c->device);
+    const int A = c->cur;
+    const size_t bytes = sizeof(double) * (size_t)n;
+    double *outs[3] = {sx, sy, sz};
+    const double *srcs[3] = {c->sx[A], c->sy[A], c->sz[A]};
+    for (int q = 0; q < 3 && n > 0; ++q) {
+        k2_unsort<<<grid_for(n), BLOCK, 0, c->stream>>>(srcs[q], c->id[A], c->pk1, n, 1.0);
+        if (hipMemcpyAsync(outs[q], c->pk1, bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+            return ECPIC_EDEVICE;
+        int rc = sync2(c);
+        if (rc) return rc;
+    }
+    return sync2(c);
 }
 
 int ecpic2d_get_particles(ecpic2d_ctx *c, double *x1, double *x2, double *p1, double *p2, int64_t n) {
@@ -2211,7 +2561,13 @@ int ecpic2d_energy(ecpic2d_ctx *c, ecpic2d_energy_parts *out) {
     k2_grad<<<grid_for(c->Nc), BLOCK, 0, s>>>(c->az, c->g1a, c->g2a, c->M1, c->M2, 1.0 / c->dx1, 1.0 / c->dx2);
     quad(c, c->g1a, P - 1, P, 5);
     quad(c, c->g2a, P, P - 1, 6);
-    double v[7];
+    if (c->spin) {
+        k2_fill<<<1, BLOCK, 0, s>>>(c->partial, RED_BLOCKS, 0.0);
+        LAUNCH_P(P, k2_zeeman<PP><<<gN, BLOCK, 0, s>>>(c->xi1[A], c->xi2[A], c->sx[A], c->sy[A], c->sz[A], c->g1a,
+                                                        c->g2a, c->bz, c->N, c->M1, c->M2, c->w, c->partial));
+        k2_sum<<<1, BLOCK, 0, s>>>(c->partial, gN, c->partial + RED_BLOCKS + 7);
+    }
+    double v[8];
     if (hipMemcpyAsync(v, c->partial + RED_BLOCKS, sizeof(v), hipMemcpyDeviceToHost, s) != hipSuccess)
         return ECPIC_EDEVICE;
     int rc = sync2(c);
@@ -2221,7 +2577,8 @@ int ecpic2d_energy(ecpic2d_ctx *c, ecpic2d_energy_parts *out) {
     out->b_z = 0.5 * v[3];
     out->e_z = 0.5 * v[4];
     out->a_z = 0.5 * (v[5] + v[6]);
-    out->total = out->kinetic + out->e_xy + out->b_z + out->e_z + out->a_z;
+    out->zeeman = c->spin ? c->hbar * v[7] : 0.0;
+    out->total = out->kinetic + out->e_xy + out->b_z + out->e_z + out->a_z + out->zeeman;
     return ECPIC_OK;
 }
 

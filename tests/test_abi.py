@@ -35,7 +35,8 @@ def test_2d_invalid_config_without_device():
     """2D configurations outside the documented ranges are rejected before any
     device is touched."""
     bad = [dict(M1=12), dict(M2=4), dict(M1=1024), dict(degree=1), dict(degree=6), dict(dt=0.8),
-           dict(tol=0.0), dict(n_particles=-1), dict(kmax=65), dict(L1=-1.0), dict(weight=float("nan"))]
+           dict(tol=0.0), dict(n_particles=-1), dict(kmax=65), dict(L1=-1.0), dict(weight=float("nan")),
+           dict(hbar=0.1), dict(spin=2), dict(spin=1, hbar=float("inf"))]
     for b in bad:
         args = dict(L1=8.0, L2=8.0, M1=16, M2=16, degree=3, n_particles=10, dt=0.05, tol=1e-12)
         args.update(b)

@@ -157,14 +157,14 @@ def test_lie_steps_match_oracle_and_conserve():
     w, o, s, ctx = setup("twod16", n=1500)
     with ctx:
         H0 = ctx.energy()
-        np.testing.assert_allclose(H0, o.energy(s), rtol=1e-13, atol=1e-15)
+        np.testing.assert_allclose(H0[:6], o.energy(s), rtol=1e-13, atol=1e-15)
         kg, kIIIg = ctx.step(3)
         st, ko, kIIIo = o.step(s, 3)
         assert st == 0
         assert np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
         compare(w, ctx.state(), s, 3e-11)
         H1 = ctx.energy()
-        np.testing.assert_allclose(H1, o.energy(s), rtol=1e-11, atol=1e-14)
+        np.testing.assert_allclose(H1[:6], o.energy(s), rtol=1e-11, atol=1e-14)
         assert abs(H1[5] - H0[5]) <= 1e-12 * H0[5]
         assert ctx.gauss_residual() < 1e-13
 
