@@ -23,7 +23,8 @@ ms/step, drift), the spin model ("spin": Lie-Trotter steps I, II, III on
 spin4096, 1.6e7 particles with spins, per-kernel averages and HBM fractions of
 the particle passes), and the 2D model ("twod": Lie-Trotter steps I-IV on
 twod512, 512 x 512 cells and 2^24 particles, per-kernel times per step and HBM
-fractions of the particle passes).
+fractions of the particle passes; "twod_spin": the same on twod512s, whose
+particles carry spins, hbar = 0.1).
 
 Prints ONE JSON line.  `value` is the throughput of the learned form on the
 headline workload (the whole hot path: network tables, predictor, FP32 and
@@ -255,6 +256,8 @@ def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
 # x, d, p^(k+1) and the id (60 B) and writes x, p, id (36 B); Subsystem II reads x, p and
 # writes p (48 B); the III source reads x, p (32 B).
 TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 36.0, "sort": 96.0, "rotate_II": 48.0, "deposit_III": 32.0}
+# With spin the sweep reads s (24 B), the sort moves it (48 B) and Subsystem II turns it (48 B).
+TWOD_SPIN_BYTES = {"sweep_I": 24.0, "sort": 48.0, "rotate_II": 48.0}
 TWOD_KERNELS = ("sweep_I", "solve_I", "commit_I", "sort", "rotate_II", "deposit_III", "solve_III", "maxwell_IV")
 FP64_PEAK_TFLOPS = 78.6
 
@@ -318,11 +321,13 @@ def twod_run(ec, w, steps: int, warmup: int, profile_steps: int):
         times = {n: ctx.kernel_time(n) for n in TWOD_KERNELS}
         ctx.profile(False)
     N = w.n_particles
+    spin = getattr(w, "spin", "none") != "none"
+    nbytes = {n: b + (TWOD_SPIN_BYTES.get(n, 0.0) if spin else 0.0) for n, b in TWOD_BYTES.items()}
     us = {n: round(1e3 * ms / cnt, 2) for n, (ms, cnt) in times.items() if cnt}
-    frac = {n: round(N * b / (us[n] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for n, b in TWOD_BYTES.items() if n in us}
+    frac = {n: round(N * b / (us[n] * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) for n, b in nbytes.items() if n in us}
     per_step = {n: round(1e3 * ms / profile_steps, 1) for n, (ms, cnt) in times.items() if cnt}
     roof = None
-    if "sweep_I" in us:
+    if "sweep_I" in us and not spin:   # the FP64 operation count is the one without spin
         fl = twod_sweep_flops(w.degree)
         achieved = N * fl / (us["sweep_I"] * 1e-6) / 1e12
         traffic = twod_traffic_from_profile(w.name, N)
@@ -406,6 +411,7 @@ def main():
     ap.add_argument("--spin-steps", type=int, default=20)
     ap.add_argument("--twod", default="twod512", help="2D workload (empty for none)")
     ap.add_argument("--twod-steps", type=int, default=10)
+    ap.add_argument("--twod-spin", default="twod512s", help="2D workload with spin (empty for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=800_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
@@ -480,6 +486,14 @@ def main():
         print(f"bench: {args.twod} {twod['ms_per_step']:.3f} ms/step, {twod['mean_sweeps_I']:.2f} sweeps, "
               f"kernels us/step {twod['kernels_us_per_step']}, HBM fractions {twod['hbm_frac']}",
               file=sys.stderr, flush=True)
+    twod_spin = None
+    if args.twod_spin:
+        from workloads.twod import get2d
+        twod_spin = twod_run(ec, get2d(args.twod_spin), args.twod_steps, args.graded_warmup,
+                             args.graded_profile_steps)
+        print(f"bench: {args.twod_spin} {twod_spin['ms_per_step']:.3f} ms/step, "
+              f"{twod_spin['mean_sweeps_I']:.2f} sweeps, kernels us/step {twod_spin['kernels_us_per_step']}",
+              file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel, the FP64 Subsystem I sweep of the plain form, on
     # the largest graded workload (else the headline one)
@@ -530,6 +544,7 @@ def main():
         "warm_start_ab": {"steps": args.ab_steps, "workloads": ab},
         "spin": spin,
         "twod": twod,
+        "twod_spin": twod_spin,
         "kernels_plain": sp["kernels_us"],
         "kernels_learned": sl["kernels_us"],
     }

@@ -773,9 +773,11 @@ constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 
 // FIRST (sweep 0): the increment is the explicit start d^(0) = dt p^n /
 // gamma(x^n, p^n), formed from A_z on the patch and stored; that variant is held
-// to three waves per SIMD (168 VGPRs) at p = 3, like the others.
+// to three waves per SIMD (168 VGPRs) at p = 3, like the others.  SPIN: the
+// spin force as well; held to two waves per SIMD for p <= 3.
 template <int P, bool FIRST, bool SPIN>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(FIRST && !SPIN && P == 3 ? 3 : 1))) void k2_sweep_I(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!SPIN ? (FIRST && P == 3 ? 3 : 1)
+                                                                            : (P <= 3 ? 2 : 1)))) void k2_sweep_I(
     SweepArgs a) {
     if (*a.gate) return;   // uniform over the grid
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
