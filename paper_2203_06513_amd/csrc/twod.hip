@@ -694,19 +694,27 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
         basis_values<P - 1>(g.x1 - ca1, bm1);
         basis_values<P - 1>(g.y2 - cb2, bmb2);
         const double i1 = a.inv_dx1, i2 = a.inv_dx2;
-        double Sy2 = 0.0, Sx2 = 0.0, Sb2 = 0.0;   // x2 leg at x1^n
+        // Summation by parts: sum_k m_k (F_k - F_{k-1}) = sum_j F_j (m_j - m_{j+1}), so
+        // every patch value is read once, with difference weights formed once.
+        // x2 leg at x1^n: columns ca2 - P - 1 + j, j = 0..P+2.
+        double wa[P + 3], wb[P + 3];   // weights of lm2 (degree P-1) and lq2 (degree P-2)
+#pragma unroll
+        for (int j = 0; j <= P + 2; ++j) {
+            const double m0 = j >= 1 ? lm2[j - 1] : 0.0, m1 = j <= P + 1 ? lm2[j] : 0.0;
+            const double q0 = j >= 2 ? lq2[j - 2] : 0.0, q1 = (j >= 1 && j <= P + 1) ? lq2[j - 1] : 0.0;
+            wa[j] = m0 - m1;
+            wb[j] = q0 - q1;
+        }
+        double Sy2 = 0.0, Sx2 = 0.0, Sb2 = 0.0;
 #pragma unroll
         for (int m1 = 0; m1 <= P; ++m1) {
-            const int row = (ca1 - m1 - R0) * PC - C0;
+            const int row = (ca1 - m1 - R0) * PC - C0 + ca2 - P - 1;
             double ty = 0.0, tx = 0.0, tb = 0.0;
 #pragma unroll
-            for (int k = 0; k <= P + 1; ++k) {
-                const int c = row + ca2 - P + k;   // column ca2 - P + k
-                tx += lm2[k] * (t.G1[c] - t.G1[c - 1]);
-                if (k >= 1) {
-                    ty += lq2[k - 1] * (t.G2[c] - t.G2[c - 1]);
-                    tb += lq2[k - 1] * (t.Bz[c] - t.Bz[c - 1]);
-                }
+            for (int j = 0; j <= P + 2; ++j) {
+                if (j >= 1) ty += wb[j] * t.G2[row + j];
+                tx += wa[j] * t.G1[row + j];
+                if (j >= 1) tb += wb[j] * t.Bz[row + j];
             }
             Sy2 += ba1[m1] * ty;
             if (m1 < P) {
@@ -714,25 +722,26 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
                 Sb2 += bm1[m1] * tb;
             }
         }
-        double Sy1 = 0.0, Sx1 = 0.0, Sb1 = 0.0;   // x1 leg at x2^{n+1}
+        // x1 leg at x2^{n+1}: rows ca1 - P - 1 + j, j = 0..P+2; per row the x2 sums first.
+        double Sy1 = 0.0, Sx1 = 0.0, Sb1 = 0.0;
 #pragma unroll
-        for (int k = 0; k <= P + 1; ++k) {
-            const int r1 = (ca1 - P + k - R0) * PC - C0, r0 = r1 - PC;   // rows ca1 - P + k and the one below
+        for (int j = 0; j <= P + 2; ++j) {
+            const double m0 = j >= 1 ? lm1[j - 1] : 0.0, m1 = j <= P + 1 ? lm1[j] : 0.0;
+            const double q0 = j >= 2 ? lq1[j - 2] : 0.0, q1 = (j >= 1 && j <= P + 1) ? lq1[j - 1] : 0.0;
+            const int row = (ca1 - P - 1 + j - R0) * PC - C0;
             double ty = 0.0, tx = 0.0, tb = 0.0;
 #pragma unroll
             for (int m2 = 0; m2 <= P; ++m2) {
-                const int c = cb2 - m2;
-                tx += bb2[m2] * (t.G1[r1 + c] - t.G1[r0 + c]);
+                const int c = row + cb2 - m2;
+                tx += bb2[m2] * t.G1[c];
                 if (m2 < P) {
-                    ty += bmb2[m2] * (t.G2[r1 + c] - t.G2[r0 + c]);
-                    tb += bmb2[m2] * (t.Bz[r1 + c] - t.Bz[r0 + c]);
+                    ty += bmb2[m2] * t.G2[c];
+                    tb += bmb2[m2] * t.Bz[c];
                 }
             }
-            Sy1 += lm1[k] * ty;
-            if (k >= 1) {
-                Sx1 += lq1[k - 1] * tx;
-                Sb1 += lq1[k - 1] * tb;
-            }
+            Sy1 += (m0 - m1) * ty;
+            Sx1 += (q0 - q1) * tx;
+            Sb1 += (q0 - q1) * tb;
         }
         const double sx = a.sx[i], sy = a.sy[i], sz = a.sz[i];
         F1 = (sx * Sy1 - sy * Sx1 + sz * Sb1) * i1;
