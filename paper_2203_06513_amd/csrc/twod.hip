@@ -1,5 +1,5 @@
-// Reduced 2D model (Sections 2.2, 3.2 and 4.3), hbar = 0: kernels, spectral
-// solves and the C ABI of include/ecpic2d.h.
+// Reduced 2D model (Sections 2.2, 3.2 and 4.3), without and with the spin terms
+// (hbar): kernels, spectral solves and the C ABI of include/ecpic2d.h.
 //
 // Data layout in HBM (one context):
 //   particles  SoA, grouped by tile (TW cells of one row) in tile order, double
@@ -10,7 +10,8 @@
 //              cells.  start[c] is where cell c's share of its tile begins in the
 //              sorted count (start[first cell of a tile] is the tile's offset).
 //              The Picard iterate d = x^{n+1} - x^n (physical units) and p^{k+1}
-//              live in more buffers.
+//              live in more buffers; with spin, sx, sy, sz (f64) are double
+//              buffered with the particles.
 //   fields     row-major M1 x M2 coefficient grids, index i1 M2 + i2 (no halo;
 //              the tile kernels wrap indices while staging).
 //   spectra    M1 x M2 complex grids for the linear solves.
@@ -26,8 +27,10 @@
 // products of circulants (periodic B-spline mass matrices and differences), so
 // the 2D discrete Fourier transform diagonalises it: M1, M0 + dt^2 K/4 and the
 // Maxwell system are solved exactly by a forward transform, a division by the
-// symbol and an inverse transform.  The transforms are radix-2 Stockham FFTs in
-// LDS (rows in one kernel, columns with the spectral step fused in the next).
+// symbol and an inverse transform.  The transforms are Stockham FFTs with the
+// values in registers (radix 8) and LDS between stages (rows in one kernel,
+// columns with the spectral step fused in the next, inverse rows with an
+// epilogue).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
