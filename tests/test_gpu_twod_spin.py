@@ -158,3 +158,24 @@ def test_full_size_spin_step_properties():
         assert ctx.gauss_residual() < 1e-13
         sp = ctx.get_spins()
         assert np.abs(np.sqrt(sp["sx"] ** 2 + sp["sy"] ** 2 + sp["sz"] ** 2) - 1.0).max() < 1e-13
+
+
+@pytest.mark.parametrize("degree", [2, 4, 5])
+def test_other_degrees_with_spin(degree):
+    """Degrees 2 (the derivative fields of the spin force on degree 0), 4 and 5 (the
+    spin sweep at its register limits): Subsystem I and a whole Lie step with spin
+    against the oracle element by element."""
+    w = get2d("twod16s").scaled(degree=degree, n_particles=900 if degree < 5 else 250)
+    arr = generate2d(w)
+    o = Oracle2D.from_workload(w)
+    s = initial_state2d(o, arr)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        kg, _ = ctx.substep_I()
+        st, ko, _ = o.substep_I_s(s)
+        assert st == 0 and abs(kg - ko) <= 1
+        compare(w, ctx.state(), s, 1e-11)
+        ctx.step(1)
+        assert o.step_s(s, 1)[0] == 0
+        compare(w, ctx.state(), s, 3e-11)
+        assert ctx.gauss_residual() < 1e-13
