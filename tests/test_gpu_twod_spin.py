@@ -179,3 +179,15 @@ def test_other_degrees_with_spin(degree):
         assert o.step_s(s, 1)[0] == 0
         compare(w, ctx.state(), s, 3e-11)
         assert ctx.gauss_residual() < 1e-13
+
+
+def test_dense_tiles_move_the_spins():
+    """About 10^4 particles per tile (more than the re-sort keeps in LDS): the direct
+    re-sort path carries the spins with their particles; one Lie step with spin
+    against the oracle."""
+    w, o, s, ctx = setup("twod8x16s", n=80000)
+    with ctx:
+        kg, kIIIg = ctx.step(1)
+        st, ko, kIIIo = o.step_s(s, 1)
+        assert st == 0 and np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
+        compare(w, ctx.state(), s, 1e-11)
