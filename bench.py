@@ -250,12 +250,13 @@ def spin_run(ec, w, steps: int, warmup: int, profile_steps: int):
             "hbm_frac": {n: round(v, 4) for n, v in frac.items()}}
 
 
-# 2D model, per particle: a Subsystem I sweep reads x1, x2, p1, p2 and d^(k) (48 B) and
-# writes d^(k+1) and p^(k+1) (32 B); the commit reads x and d (32 B) and writes the packed
+# 2D model, per particle: a Subsystem I sweep reads x1, x2, p1, p2, d^(k), A_z(x^n) and
+# gamma^n (64 B) and writes d^(k+1) and p^(k+1) (32 B) (the first sweep reads 32 B and writes
+# d^(0), A_z(x^n), gamma^n and the iterate: 64 B); the commit reads x and d (32 B) and writes the packed
 # new tile and column (4 B); the sort (arrival lists and re-sort) reads that word twice,
 # x, d, p^(k+1) and the id (60 B) and writes x, p, id (36 B); Subsystem II reads x, p and
 # writes p (48 B); the III source reads x, p (32 B).
-TWOD_BYTES = {"sweep_I": 80.0, "commit_I": 36.0, "sort": 96.0, "rotate_II": 48.0, "deposit_III": 32.0}
+TWOD_BYTES = {"sweep_I": 96.0, "commit_I": 36.0, "sort": 96.0, "rotate_II": 48.0, "deposit_III": 32.0}
 # With spin the sweep reads s (24 B), the sort moves it (48 B) and Subsystem II turns it (48 B).
 TWOD_SPIN_BYTES = {"sweep_I": 24.0, "sort": 48.0, "rotate_II": 48.0}
 TWOD_KERNELS = ("sweep_I", "solve_I", "commit_I", "sort", "rotate_II", "deposit_III", "solve_III", "maxwell_IV")
@@ -269,17 +270,19 @@ def twod_sweep_flops(P: int) -> float:
         P-1 splines in both coordinates by Horner (2 P(P+1) + 2 P(P-1) FMA), two
         outer products (2 P(P+1) FMA), the weights (2 P): 12 P^2 + 6 P per point;
       mean field gather and current deposit: 2 P(P+1) FMA and 2 P(P+1) mul+add;
-      A_z at both ends: basis 4 P(P+1) FMA, contraction 2 (P+1)(P+2) FMA;
+      A_z at the end point: basis in both coordinates 2 P(P+1) FMA, contraction
+        (P+1)(P+2) FMA (A_z and gamma at the start are fixed over the iteration and
+        formed once, by the first sweep); the basis in x1 at the start, P(P+1) FMA;
       the two leg means of grad A_z: P^2 FMA for the piece means and (P+1)(P+2) +
         (P+1) FMA for the contraction, each;
-      the push (three gammas, the update): 30."""
-    return (P * (12 * P * P + 6 * P) + 4 * P * (P + 1) + 4 * P * (P + 1) + 8 * P * (P + 1) + 4 * (P + 1) * (P + 2)
-            + 2 * (2 * P * P + 2 * (P + 1) * (P + 2) + 2 * (P + 1)) + 30)
+      the push (two gammas, the update): 26."""
+    return (P * (12 * P * P + 6 * P) + 4 * P * (P + 1) + 4 * P * (P + 1) + 6 * P * (P + 1) + 2 * (P + 1) * (P + 2)
+            + 2 * (2 * P * P + 2 * (P + 1) * (P + 2) + 2 * (P + 1)) + 26)
 
 
 def twod_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("twod.hip", "spline.hpp", "common.hpp", "internal.hpp"):
+    for f in ("twod.hip", "coef.hpp", "spline.hpp", "common.hpp", "internal.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2203_06513_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 

@@ -42,13 +42,16 @@
 #include <vector>
 
 #include "../../include/ecpic2d.h"
+#include "coef.hpp"
 #include "common.hpp"
 #include "spline.hpp"
 
 namespace ecpic2d {
 
 using ecpic::basis_values;
-using ecpic::line_mean_v1;
+using ecpic::frcp;
+using ecpic::fsqrt;
+using ecpic::piece_means;
 using ecpic::wave_sum_dpp;
 
 constexpr int WAVE = 64;
@@ -522,7 +525,39 @@ struct SweepArgs {
     double inv_dx1, inv_dx2, dt, w;
     const double *sx, *sy, *sz, *bz;     // spins and b_z (the sweep with spin)
     double hbar;
+    double *azn, *gamn;                  // A_z(x^n) and gamma(x^n, p^n): formed by sweep 0, read by the rest
 };
+
+// Line mean of the V1 basis (degree P-1) along one leg of the step, from t0 in
+// [0, 1) of cell c0 to t1 in (-1, 2) (cell units, c0 frame); s = +1 / -1 / 0
+// tells whether t1 lies in cell c0+1 / c0-1 / c0, and rlen is 1 / |t1 - t0|
+// (used only when s != 0).  lb[k], k = 0..P+1, is the mean of Lambda1_{c0-P+k}:
+// the mean over each piece of the leg (the part in c0 and the part in c0+s),
+// weighted by the piece's share of the length.
+template <int P>
+__device__ __forceinline__ void leg_mean_v1(double t0, double t1, int s, double rlen, double (&lb)[P + 2]) {
+    constexpr int D = P - 1;
+    const double t1c = fmin(fmax(t1, 0.0), 1.0);
+    double avgA[D + 1], avgB[D + 1];
+    piece_means<D>(fmin(t0, t1c), fmax(t0, t1c), avgA);
+    // the piece in the neighbour cell: [0, t1 - 1] (s = +1) or [t1 + 1, 1] (s = -1)
+    const double as = s < 0 ? t1 + 1.0 : 0.0, bs = s > 0 ? t1 - 1.0 : (s < 0 ? 1.0 : 0.0);
+    piece_means<D>(as, bs, avgB);
+    const double wB = s != 0 ? (bs - as) * rlen : 0.0, wA = 1.0 - wB;
+#pragma unroll
+    for (int k = 0; k <= P + 1; ++k) {
+        const double v = (k >= 1 && k <= P) ? wA * avgA[P - k] : 0.0;   // index c0 - m, k = P - m
+        double vb = 0.0;                                                 // index c0 + s - m
+        if (s > 0 && P + 1 - k >= 0 && P + 1 - k <= D) vb = avgB[P + 1 - k < 0 ? 0 : (P + 1 - k > D ? D : P + 1 - k)];
+        if (s < 0 && P - 1 - k >= 0 && P - 1 - k <= D) vb = avgB[P - 1 - k < 0 ? 0 : (P - 1 - k > D ? D : P - 1 - k)];
+        lb[k] = v + wB * vb;
+    }
+}
+
+// 1 / |s| for a leg of s cells, with |s| raised to a tiny normal floor: a leg
+// that crosses a grid line is longer than that unless it starts within the
+// floor of the line, where the split of its (vanishing) length does not matter.
+__device__ __forceinline__ double leg_rcp(double s) { return frcp(fmax(fabs(s), 1.0e-290)); }
 
 // Path integrals of the V1 basis on one piece of the straight step (between two
 // grid-line crossings, inside cell (k1, k2)), both components, by the P-point
@@ -597,8 +632,8 @@ __device__ __forceinline__ Geo geometry(const SweepArgs &a, double x1, double x2
     }
     g.mn1 = min(ca1, g.cb1);
     g.mn2 = min(g.ca2, g.cb2);
-    const double bA = g.cb1 != ca1 ? ((double)max(ca1, g.cb1) - g.x1) / g.s1 : 1.0;
-    const double bB = g.cb2 != g.ca2 ? ((double)max(g.ca2, g.cb2) - g.x2) / g.s2 : 1.0;
+    const double bA = g.cb1 != ca1 ? ((double)max(ca1, g.cb1) - g.x1) * copysign(leg_rcp(g.s1), g.s1) : 1.0;
+    const double bB = g.cb2 != g.ca2 ? ((double)max(g.ca2, g.cb2) - g.x2) * copysign(leg_rcp(g.s2), g.s2) : 1.0;
     g.lo = fmin(bA, bB);
     g.hi = fmax(bA, bB);
     return g;
@@ -644,33 +679,53 @@ __device__ __forceinline__ void pieces(const Geo &g, bool live, int first, int l
     }
 }
 
-// A_z at both ends, the means of dA_z/dx2 along the vertical leg (at x1^n) and of
-// dA_z/dx1 along the horizontal leg (at x2^{n+1}), the push of the Subsystem I
-// scheme, and the stores of particle i.
-template <int P, bool SPIN>
-__device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1, double E2, const Patch &t,
-                                       const SweepArgs &a, double &rmax, int &flags) {
-    const int PC = t.PC, R0 = t.R0, C0 = t.C0, ca1 = t.r, ca2 = g.ca2, cb1 = g.cb1, cb2 = g.cb2;
-    double ba1[P + 1], ba2[P + 1], bb1[P + 1], bb2[P + 1];
-    basis_values<P>(g.x1 - ca1, ba1);
-    basis_values<P>(g.x2 - ca2, ba2);
-    basis_values<P>(g.y1 - cb1, bb1);
-    basis_values<P>(g.y2 - cb2, bb2);
-    double Aa = 0.0, Ab = 0.0;
+// A_z at a start point x (x1 in the tile's row) from the patch.
+template <int P>
+__device__ __forceinline__ double start_A(const Patch &t, double x1, double x2) {
+    const int c2 = (int)x2;
+    double b1[P + 1], b2[P + 1];
+    basis_values<P>(x1 - t.r, b1);
+    basis_values<P>(x2 - c2, b2);
+    double A = 0.0;
 #pragma unroll
     for (int m1 = 0; m1 <= P; ++m1) {
-        double ta = 0.0, tb = 0.0;
+        double ta = 0.0;
 #pragma unroll
-        for (int m2 = 0; m2 <= P; ++m2) {
-            ta += ba2[m2] * t.A[(ca1 - m1 - R0) * PC + ca2 - m2 - C0];
-            tb += bb2[m2] * t.A[(cb1 - m1 - R0) * PC + cb2 - m2 - C0];
-        }
-        Aa += ba1[m1] * ta;
+        for (int m2 = 0; m2 <= P; ++m2) ta += b2[m2] * t.A[(t.r - m1 - t.R0) * t.PC + c2 - m2 - t.C0];
+        A += b1[m1] * ta;
+    }
+    return A;
+}
+
+// gamma(x, p) from A_z(x) = A and p = (q1, q2).
+__device__ __forceinline__ double gamma_of(double q1, double q2, double A) {
+    return fsqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+}
+
+// A_z at the end point, the means of dA_z/dx2 along the vertical leg (at x1^n) and
+// of dA_z/dx1 along the horizontal leg (at x2^{n+1}), the push of the Subsystem I
+// scheme, and the stores of particle i.  Aa = A_z(x^n) and gA = gamma(x^n, p^n)
+// are fixed over the iteration.
+template <int P, bool SPIN>
+__device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1, double E2, double Aa, double gA,
+                                       const Patch &t, const SweepArgs &a, double &rmax, int &flags) {
+    const int PC = t.PC, R0 = t.R0, C0 = t.C0, ca1 = t.r, ca2 = g.ca2, cb1 = g.cb1, cb2 = g.cb2;
+    double ba1[P + 1], bb1[P + 1], bb2[P + 1];
+    basis_values<P>(g.x1 - ca1, ba1);
+    basis_values<P>(g.y1 - cb1, bb1);
+    basis_values<P>(g.y2 - cb2, bb2);
+    double Ab = 0.0;
+#pragma unroll
+    for (int m1 = 0; m1 <= P; ++m1) {
+        double tb = 0.0;
+#pragma unroll
+        for (int m2 = 0; m2 <= P; ++m2) tb += bb2[m2] * t.A[(cb1 - m1 - R0) * PC + cb2 - m2 - C0];
         Ab += bb1[m1] * tb;
     }
+    const double rl2 = leg_rcp(g.s2), rl1 = leg_rcp(g.s1);
     double lm2[P + 2], lm1[P + 2];
-    line_mean_v1<P>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, lm2);   // indices ca2 - P + k
-    line_mean_v1<P>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, lm1);   // indices ca1 - P + k
+    leg_mean_v1<P>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, rl2, lm2);   // indices ca2 - P + k
+    leg_mean_v1<P>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, rl1, lm1);   // indices ca1 - P + k
     double Dv = 0.0, Dh = 0.0;
 #pragma unroll
     for (int m1 = 0; m1 <= P; ++m1) {
@@ -692,8 +747,8 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
         // G2 = (G a)_2, degrees (P, P-1)), dA_z/dx1 (G1, (P-1, P)) and B_z ((P-1, P-1)):
         // each derivative's coefficients are backward differences of the field's.
         double lq2[P + 1], lq1[P + 1], bm1[P], bmb2[P];
-        line_mean_v1<P - 1>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, lq2);   // degree P-2, indices ca2 - P + 1 + k
-        line_mean_v1<P - 1>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, lq1);   // degree P-2, indices ca1 - P + 1 + k
+        leg_mean_v1<P - 1>(g.x2 - ca2, g.y2 - ca2, cb2 - ca2, rl2, lq2);   // degree P-2, indices ca2 - P + 1 + k
+        leg_mean_v1<P - 1>(g.x1 - ca1, g.y1 - ca1, cb1 - ca1, rl1, lq1);   // degree P-2, indices ca1 - P + 1 + k
         basis_values<P - 1>(g.x1 - ca1, bm1);
         basis_values<P - 1>(g.y2 - cb2, bmb2);
         const double i1 = a.inv_dx1, i2 = a.inv_dx2;
@@ -750,9 +805,9 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
         F1 = (sx * Sy1 - sy * Sx1 + sz * Sb1) * i1;
         F2 = (sx * Sy2 - sy * Sx2 + sz * Sb2) * i2;
     }
-    const double q1 = g.q1, q2 = g.q2, pp = q1 * q1 + q2 * q2;
-    const double gA = sqrt(1.0 + pp + Aa * Aa), gB = sqrt(1.0 + pp + Ab * Ab);
-    const double f = -(Aa + Ab) / (gA + gB);
+    const double q1 = g.q1, q2 = g.q2;
+    const double gB = gamma_of(q1, q2, Ab);
+    const double f = -(Aa + Ab) * frcp(gA + gB);
     double n1, n2;
     if constexpr (SPIN) {
         n1 = q1 + a.dt * (E1 + f * Dh - a.hbar * F1);
@@ -761,8 +816,8 @@ __device__ __forceinline__ void finish(const Geo &g, bool live, int i, double E1
         n1 = q1 + a.dt * (E1 + f * Dh);
         n2 = q2 + a.dt * (E2 + f * Dv);
     }
-    const double gC = sqrt(1.0 + n1 * n1 + n2 * n2 + Ab * Ab);
-    const double sc = a.dt / (gB + gC);
+    const double gC = gamma_of(n1, n2, Ab);
+    const double sc = a.dt * frcp(gB + gC);
     const double e1 = (q1 + n1) * sc, e2 = (q2 + n2) * sc;
     if (live) {
         if (!isfinite(e1 + e2 + n1 + n2)) flags |= FLAG_NONFINITE;
@@ -784,12 +839,14 @@ constexpr int QCAP = 2 * WAVE;
 constexpr int QV = 6;   // x1, x2, d1, d2, E1, E2
 
 // FIRST (sweep 0): the increment is the explicit start d^(0) = dt p^n /
-// gamma(x^n, p^n), formed from A_z on the patch and stored; that variant is held
+// gamma(x^n, p^n), formed from A_z on the patch and stored with A_z(x^n) and
+// gamma(x^n, p^n), which the later sweeps read instead; that variant is held
 // to three waves per SIMD (168 VGPRs) at p = 3, like the others.  SPIN: the
-// spin force as well; held to two waves per SIMD for p <= 3.
+// spin force as well; held to three waves per SIMD for p <= 3 (a few registers
+// spilled) after the first sweep, two in it.
 template <int P, bool FIRST, bool SPIN>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!SPIN ? (FIRST && P == 3 ? 3 : 1)
-                                                                            : (P <= 3 ? 2 : 1)))) void k2_sweep_I(
+                                                                            : (P <= 3 ? (FIRST ? 2 : 3) : 1)))) void k2_sweep_I(
     SweepArgs a) {
     if (*a.gate) return;   // uniform over the grid
     constexpr int PR = P + 3, PCM = TWMAX + P + 2, PS = PR * PCM;
@@ -831,9 +888,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!SPIN ? (
         const int i = valid ? qi[slot] : begin;
         if (!valid) v[0] = (double)r, v[1] = (double)c0;   // any point of the tile
         double E1 = v[4], E2 = v[5];
-        const Geo g = geometry(a, v[0], v[1], a.p1[i], a.p2[i], v[2], v[3], valid, r, flags);
+        const double q1 = a.p1[i], q2 = a.p2[i];
+        const Geo g = geometry(a, v[0], v[1], q1, q2, v[2], v[3], valid, r, flags);
         pieces<P>(g, valid, 1, 2, t, a.w, E1, E2);
-        finish<P, SPIN>(g, valid, i, E1, E2, t, a, rmax, flags);
+        const double An = start_A<P>(t, v[0], v[1]);   // formed again rather than queued
+        finish<P, SPIN>(g, valid, i, E1, E2, An, gamma_of(q1, q2, An), t, a, rmax, flags);
         head += n;
     };
     const int nw = blockDim.x / WAVE, passes = (end - begin + WAVE - 1) / WAVE;   // none for an empty tile
@@ -842,30 +901,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!SPIN ? (
         const bool live = i < end;
         const int ii = live ? i : begin;
         const double x1 = a.xi1[ii], x2 = a.xi2[ii], q1 = a.p1[ii], q2 = a.p2[ii];
-        double D1, D2;
+        double D1, D2, An, gn;
         if constexpr (FIRST) {
-            const int c2 = (int)x2;
-            double b1[P + 1], b2[P + 1];
-            basis_values<P>(x1 - r, b1);
-            basis_values<P>(x2 - c2, b2);
-            double A = 0.0;
-#pragma unroll
-            for (int m1 = 0; m1 <= P; ++m1) {
-                double ta = 0.0;
-#pragma unroll
-                for (int m2 = 0; m2 <= P; ++m2) ta += b2[m2] * t.A[(r - m1 - t.R0) * PC + c2 - m2 - t.C0];
-                A += b1[m1] * ta;
-            }
-            const double sc = a.dt / sqrt(1.0 + q1 * q1 + q2 * q2 + A * A);
+            An = start_A<P>(t, x1, x2);
+            gn = gamma_of(q1, q2, An);
+            const double sc = a.dt * frcp(gn);
             D1 = q1 * sc;
             D2 = q2 * sc;
             if (live) {
                 a.d1[i] = D1;
                 a.d2[i] = D2;
+                a.azn[i] = An;
+                a.gamn[i] = gn;
             }
         } else {
             D1 = a.d1[ii];
             D2 = a.d2[ii];
+            An = a.azn[ii];
+            gn = a.gamn[ii];
         }
         const Geo g = geometry(a, x1, x2, q1, q2, D1, D2, live, r, flags);
         double E1 = 0.0, E2 = 0.0;
@@ -883,7 +936,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(!SPIN ? (
             qv[5][slot] = E2;
         }
         tail += __builtin_popcountll(cm);
-        if (live && !cross) finish<P, SPIN>(g, live, i, E1, E2, t, a, rmax, flags);
+        if (live && !cross) finish<P, SPIN>(g, live, i, E1, E2, An, gn, t, a, rmax, flags);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1213,7 +1266,7 @@ __global__ __launch_bounds__(BLOCK) void k2_deposit0(DepArgs a) {
                 An = a.anp[ii];
             }
             const double q1 = a.p1[ii], q2 = a.p2[ii], pp = 1.0 + q1 * q1 + q2 * q2;
-            q = a.w * (An + Ak) / (sqrt(pp + An * An) + sqrt(pp + Ak * Ak));
+            q = a.w * (An + Ak) * frcp(fsqrt(pp + An * An) + fsqrt(pp + Ak * Ak));
         }
         if (live) {
 #pragma unroll
@@ -1868,6 +1921,7 @@ struct ecpic2d_ctx {
     double *xi1[2] = {}, *xi2[2] = {}, *p1[2] = {}, *p2[2] = {};
     int32_t *id[2] = {};
     double *d1[2] = {}, *d2[2] = {}, *pk1 = nullptr, *pk2 = nullptr;
+    double *azn = nullptr, *gamn = nullptr;   // A_z(x^n), gamma^n during Subsystem I (sweep order)
     int32_t *cell = nullptr /* new cell (set_particles) or packed new tile and column (commit) */, *count = nullptr,
             *start = nullptr, *bsum = nullptr;
     int32_t *mig = nullptr;   // arrivals per new tile, after the stayers' slots
@@ -2071,7 +2125,7 @@ int substep_I(ecpic2d_ctx *c, double dt, ecpic2d_iter_stats *st) {
         SweepArgs a{c->xi1[A], c->xi2[A], c->p1[A], c->p2[A], c->d1[di], c->d2[di], c->d1[1 - di], c->d2[1 - di],
                     c->pk1, c->pk2, c->tstart[c->ts], c->eb1, c->eb2, c->az, c->g1a, c->g2a, c->J1, c->J2,
                     c->res + k, c->flags, c->gate, c->M1, c->M2, c->TW, 1.0 / c->dx1, 1.0 / c->dx2, dt, c->w,
-                    c->sx[A], c->sy[A], c->sz[A], c->bz, c->hbar};
+                    c->sx[A], c->sy[A], c->sz[A], c->bz, c->hbar, c->azn, c->gamn};
         timed(c, "sweep_I", [&] {
             if (c->spin) {
                 if (k == 0) {
@@ -2293,7 +2347,8 @@ int ecpic2d_create(const ecpic2d_config *cfg, ecpic2d_ctx **out) {
               dalloc(c, &c->p2[b], N) | dalloc(c, &c->id[b], N) | dalloc(c, &c->d1[b], N) |
               dalloc(c, &c->d2[b], N);
     }
-    rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->cell, N) | dalloc(c, &c->mig, N) |
+    rc |= dalloc(c, &c->pk1, N) | dalloc(c, &c->pk2, N) | dalloc(c, &c->azn, N) | dalloc(c, &c->gamn, N) |
+          dalloc(c, &c->cell, N) | dalloc(c, &c->mig, N) |
           dalloc(c, &c->count, Nc) | dalloc(c, &c->start, Nc + 1) | dalloc(c, &c->bsum, Nc / SCAN_TILE + 2);
     c->ntiles = c->M1 * (c->M2 / c->TW);
     rc |= dalloc(c, &c->tstart[0], (size_t)c->ntiles + 1) | dalloc(c, &c->tstart[1], (size_t)c->ntiles + 1) |
