@@ -104,38 +104,6 @@ __device__ __forceinline__ void piece_means(T a, T b, T (&avg)[D + 1]) {
     }
 }
 
-// Line mean of the V1 basis (degree P-1) along a step that starts at t0 in
-// [0, 1) of cell c0 and ends at t1 = t0 + dr in (-1, 2) (cell units, c0 frame);
-// s = +1 / -1 / 0 tells whether the end lies in cell c0+1 / c0-1 / c0.
-// Output lb[k], k = 0..P+1, is the mean of Lambda1_{c0-P+k}.
-template <int P, typename T>
-__device__ __forceinline__ void line_mean_v1(T t0, T t1, int s, T (&lb)[P + 2]) {
-    constexpr int D = P - 1;
-    const T one = (T)1, zero = (T)0;
-    T t1c = t1 < zero ? zero : (t1 > one ? one : t1);
-    T a = t0 < t1c ? t0 : t1c;
-    T b = t0 < t1c ? t1c : t0;
-    T avgA[D + 1];
-    piece_means<D>(a, b, avgA);
-    // second piece in the neighbour cell: [0, t1 - 1] (s = +1) or [t1 + 1, 1] (s = -1)
-    T as = s > 0 ? zero : (s < 0 ? t1 + one : zero);
-    T bs = s > 0 ? t1 - one : (s < 0 ? one : zero);
-    T avgB[D + 1];
-    piece_means<D>(as, bs, avgB);
-    T lenA = b - a, lenB = bs - as;
-    T wB = s != 0 ? lenB / (lenA + lenB) : zero;
-    T wA = one - wB;
-#pragma unroll
-    for (int k = 0; k <= P + 1; ++k) {
-        // main piece: index c0 - m  <->  k = P - m
-        T v = (k >= 1 && k <= P) ? wA * avgA[P - k] : zero;
-        // neighbour piece: index c0 + s - m  <->  k = P + s - m
-        T vr = (P + 1 - k >= 0 && P + 1 - k <= D) ? avgB[(P + 1 - k) < 0 ? 0 : ((P + 1 - k) > D ? D : (P + 1 - k))] : zero;
-        T vl = (P - 1 - k >= 0 && P - 1 - k <= D) ? avgB[(P - 1 - k) < 0 ? 0 : ((P - 1 - k) > D ? D : (P - 1 - k))] : zero;
-        lb[k] = v + wB * (s > 0 ? vr : vl);
-    }
-}
-
 // Geometry of a step from t0 in [0, 1) of cell c to t1 in (-1, 2) (c frame):
 // the main piece stays in cell c, the side piece (if any) lies in cell c + s.
 // sA, sB are the signed lengths of the pieces, [aA, bA] and [aB, bB] their
