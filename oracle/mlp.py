@@ -123,3 +123,51 @@ def features(o, s, idx, degree: int):
         out[r, 3 + 2 * (degree + 1):3 + 4 * (degree + 1)] = s["az"][win]
         out[r, 3 + 4 * (degree + 1):] = s["ex"][win]
     return out
+
+
+# -- training: initialisation, sampling and the Adam update ------------------
+_M64 = (1 << 64) - 1
+
+
+def splitmix64(z: int) -> int:
+    """The output function of splitmix64 (Steele, Lea and Flood, 2014) for state z:
+    add the golden-ratio increment, then xor-shift-multiply twice and xor-shift."""
+    z = (z + 0x9E3779B97F4A7C15) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def unit_uniform(seed: int, k: int) -> float:
+    """The k-th draw of a counter-based stream: the top 53 bits of
+    splitmix64(seed xor splitmix64(k)) as a double in [0, 1)."""
+    return (splitmix64((seed ^ splitmix64(k)) & _M64) >> 11) * 2.0 ** -53
+
+
+def glorot_init(seed: int, d_in: int, h: int = HIDDEN) -> np.ndarray:
+    """Glorot-uniform weights (Glorot and Bengio, 2010), zero biases: parameter k of
+    a weight matrix with fan-in a and fan-out b is (2 u_k - 1) sqrt(6 / (a + b))."""
+    W1, b1, W2, b2, W3, b3 = unpack(np.arange(n_params(d_in, h), dtype=np.float64), d_in, h)
+    theta = np.zeros(n_params(d_in, h))
+    for block, (a, b) in ((W1, (d_in, h)), (W2, (h, h)), (W3, (h, N_OUT))):
+        for k in block.ravel().astype(np.int64):
+            theta[k] = (2.0 * unit_uniform(seed, int(k)) - 1.0) * math.sqrt(6.0 / (a + b))
+    return theta
+
+
+def batch_indices(seed: int, step: int, batch: int, n: int) -> np.ndarray:
+    """Sample j of training step `step`: record splitmix64(seed xor splitmix64(step B + j)) mod n."""
+    return np.array([splitmix64((seed ^ splitmix64(step * batch + j)) & _M64) % n for j in range(batch)],
+                    dtype=np.int64)
+
+
+def adam_step(theta, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1) at step t >= 1: the biased
+    first and second moment estimates, their bias corrections by 1 - beta^t, and the
+    step lr m_hat / (sqrt(v_hat) + eps).  Returns (theta, m, v)."""
+    g = np.asarray(g, np.float64)
+    m = beta1 * np.asarray(m, np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return np.asarray(theta, np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

@@ -108,6 +108,66 @@ def test_ws_tables_vs_fp64_forward():
     assert err <= 1.2e-2 * spread
 
 
+def test_ws_first_training_step_vs_fp64_reference():
+    """One step of the GPU training (Glorot start, normalisation statistics, the
+    sampled batch, forward and backward pass, Adam) against the FP64 reference doing
+    the same from the definitions: the normalisation to FP32 rounding, the new
+    weights to 2e-7 where the gradient is well above its FP32 error, and elsewhere
+    a move of at most lr (the first Adam step has length lr).  Then a second step
+    (ws_train starts again from the same initialisation), whose moments now mix
+    two gradients, from the GPU's first-step weights."""
+    w = workloads.get("langmuir64")
+    D = mlp.n_features(w.degree)
+    P = mlp.n_params(D)
+    seed, B, lr = 11, 256, 1e-3
+    with ec.Context.from_workload(w, map=ec.MAP_SEIDEL) as c:
+        c.load(workloads.generate(w))
+        c.ws_record(1, 4 * w.n_particles)
+        c.step(2)
+        feat, targ = c.ws_get_records()
+        c.ws_record(0)
+        c.ws_train(steps=1, batch=B, lr=lr, seed=seed)
+        wts = c.ws_get_weights()
+        c.ws_train(steps=2, batch=B, lr=lr, seed=seed)
+        theta2 = c.ws_get_weights()[:P].astype(np.float64)
+    n = len(feat)
+    assert n == 2 * w.n_particles
+    theta1 = wts[:P].astype(np.float64)
+    mu, sd = wts[P:P + D + 2], wts[P + D + 2:P + 2 * (D + 2)]
+    allv = np.concatenate([feat, targ], axis=1).astype(np.float64)
+    m64, s64 = allv.mean(axis=0), allv.std(axis=0)
+    s64[~(s64 > 1e-12 * np.maximum(1.0, np.abs(m64)))] = 1.0
+    assert np.all(np.abs(mu - m64) <= 1e-6 * np.maximum(np.abs(m64), s64))
+    assert np.all(np.abs(sd - s64) <= 1e-6 * s64)
+    theta0 = mlp.glorot_init(seed, D)
+    idx = mlp.batch_indices(seed, 0, B, n)
+    X = (feat[idx].astype(np.float64) - mu[:D]) / sd[:D]
+    T = (targ[idx].astype(np.float64) - mu[D:]) / sd[D:]
+    _, g = mlp.loss_and_grad(theta0, X, T)
+    ref, _, _ = mlp.adam_step(theta0, 0.0, 0.0, g, 1, lr)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    err = np.abs(theta1 - ref)
+    print(f"\n{n} records, batch {B}: {big.sum()} of {P} gradients well resolved, max error there "
+          f"{err[big].max():.2e}, elsewhere max move {np.abs(theta1 - theta0)[~big].max():.2e}")
+    assert big.sum() > 0.8 * P   # the weights of features that are constant here have no gradient
+    assert err[big].max() <= 2e-7
+    assert np.all(np.abs(theta1 - theta0.astype(np.float32))[~big] <= lr * (1.0 + 1e-5) + 1e-7)
+    # step 2 from the GPU's weights after step 1, the moments of step 1 from the FP64 gradient
+    m1, v1 = 0.1 * g, 0.001 * g * g
+    idx2 = mlp.batch_indices(seed, 1, B, n)
+    X2 = (feat[idx2].astype(np.float64) - mu[:D]) / sd[:D]
+    T2 = (targ[idx2].astype(np.float64) - mu[D:]) / sd[D:]
+    _, g2 = mlp.loss_and_grad(theta1, X2, T2)
+    ref2, _, _ = mlp.adam_step(theta1, m1, v1, g2, 2, lr)
+    both = (np.abs(g) > 0.1 * np.abs(g).max()) & (np.abs(g2) > 0.1 * np.abs(g2).max())
+    err2 = np.abs(theta2 - ref2)[both]
+    print(f"step 2: {both.sum()} coordinates with both gradients resolved to 1e-3, max error {err2.max():.2e}")
+    assert both.sum() >= 10
+    assert err2.max() <= 2e-6
+    # every coordinate: |m_hat| / sqrt(v_hat) <= 1.0014 at t = 2 (Cauchy-Schwarz on the two terms)
+    assert np.all(np.abs(theta2 - theta1) <= 1.0015 * lr + 1e-7)
+
+
 @pytest.fixture(scope="module")
 def trained():
     """Pairs recorded over 12 steps of a 200k-particle pump workload, then trained."""

@@ -78,3 +78,68 @@ def test_features_translation_invariant():
     assert np.abs(f1 - f0).max() < 1e-12
     assert f0.shape == (50, mlp.n_features(w.degree))
     assert np.all(np.abs(f0[:, 0]) <= 0.5)
+
+
+# -- training: the counter-based generator, the initialisation, Adam ---------
+def test_splitmix64_published_sequence():
+    """splitmix64 seeded with 0 gives e220a8397b1dcdaf, 6e789e6aa1b965f4,
+    06c45d188009454f (its published first outputs); the state advances by the
+    golden-ratio increment between calls."""
+    gamma = 0x9E3779B97F4A7C15
+    outs = [mlp.splitmix64((k * gamma) & ((1 << 64) - 1)) for k in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_glorot_init_bounds_and_variance():
+    """Weights lie in +-sqrt(6 / (fan_in + fan_out)) with the variance of that
+    uniform law (bound^2 / 3); biases start at zero."""
+    D = mlp.n_features(3)
+    th = mlp.glorot_init(7, D)
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(th, D)
+    for W, (a, b) in ((W1, (D, 64)), (W2, (64, 64)), (W3, (64, 2))):
+        L = math.sqrt(6.0 / (a + b))
+        assert np.abs(W).max() <= L
+        if W.size >= 1000:
+            assert abs(W.var() / (L * L / 3.0) - 1.0) < 0.1
+    assert not np.any(b1) and not np.any(b2) and not np.any(b3)
+    assert np.array_equal(th, mlp.glorot_init(7, D)) and not np.array_equal(th, mlp.glorot_init(8, D))
+
+
+def test_batch_indices_range_and_spread():
+    idx = mlp.batch_indices(3, 5, 4096, 1000)
+    assert idx.min() >= 0 and idx.max() < 1000
+    counts = np.bincount(idx, minlength=1000)
+    assert counts.max() < 20 and np.count_nonzero(counts) > 950
+
+
+def test_adam_first_step_has_length_lr():
+    """At t = 1 the bias-corrected moments are g and g^2, so every coordinate with
+    |g| >> eps moves by lr against the sign of its gradient, whatever |g| is."""
+    rng = np.random.default_rng(1)
+    g = rng.choice([-1.0, 1.0], 200) * 10.0 ** rng.uniform(-4, 4, 200)
+    th, m, v = mlp.adam_step(np.zeros(200), np.zeros(200), np.zeros(200), g, 1, 1e-3)
+    assert np.allclose(th, -1e-3 * np.sign(g), rtol=1e-3, atol=0)
+
+
+def test_adam_invariant_to_gradient_scale():
+    """Rescaling every gradient by c > 0 leaves the iterates unchanged (up to eps)."""
+    rng = np.random.default_rng(2)
+    gs = rng.normal(0.0, 1.0, (6, 50))
+    out = []
+    for c in (1.0, 1000.0):
+        th, m, v = np.zeros(50), np.zeros(50), np.zeros(50)
+        for t, g in enumerate(gs, start=1):
+            th, m, v = mlp.adam_step(th, m, v, c * g, t, 0.01)
+        out.append(th)
+    assert np.allclose(out[0], out[1], rtol=1e-6, atol=1e-9)
+
+
+def test_adam_minimises_a_quadratic():
+    """On f = sum a_i (x_i - c_i)^2 / 2 with curvatures over four decades Adam reaches the minimum."""
+    a = np.logspace(-2, 2, 8)
+    cst = np.linspace(-1.0, 1.0, 8)
+    th, m, v = np.zeros(8), np.zeros(8), np.zeros(8)
+    for t in range(1, 4001):
+        lr = 0.05 if t <= 2000 else 0.005
+        th, m, v = mlp.adam_step(th, m, v, a * (th - cst), t, lr)
+    assert np.abs(th - cst).max() < 1e-2
