@@ -235,6 +235,45 @@ def test_edge_positions_and_order():
         compare(w, ctx.state(), s, 1e-11)
 
 
+def test_grid_lines_corners_and_tiny_steps():
+    """Degenerate steps: particles exactly on interior grid lines and on cell
+    corners, with momenta zero, +-1e-300 and +-1e-16, and steps that start just
+    off a cell corner and cross both grid lines next to it; one substep I and one
+    Lie step against the oracle."""
+    w = get2d("twod16").scaled(n_particles=64)
+    arr = generate2d(w)
+    dx1, dx2 = w.L1 / w.M1, w.L2 / w.M2
+    rng = np.random.default_rng(5)
+    c1 = rng.integers(0, w.M1, 64)
+    c2 = rng.integers(0, w.M2, 64)
+    mom = np.array([0.0, 1e-300, -1e-300, 1e-16, -1e-16, 0.05, -0.05, 0.02])
+    arr["x1"] = c1 * dx1
+    arr["x2"] = c2 * dx2
+    arr["x2"][::3] += 0.5 * dx2          # on an x1 grid line only
+    arr["p1"] = mom[np.arange(64) % 8]
+    arr["p2"] = mom[(np.arange(64) // 8) % 8]
+    # steps from just below and left of a corner across both of its grid lines
+    arr["x1"][56:] = c1[56:] * dx1 - 1e-4 * dx1
+    arr["x2"][56:] = c2[56:] * dx2 - 1e-4 * dx2
+    arr["p1"][56:] = 0.05
+    arr["p2"][56:] = 0.05 * dx2 / dx1
+    arr["x1"] = np.mod(arr["x1"], w.L1)
+    arr["x2"] = np.mod(arr["x2"], w.L2)
+    o = Oracle2D.from_workload(w)
+    s = initial_state2d(o, arr)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        ctx.substep_I()
+        assert o.substep_I(s)[0] == 0
+        compare(w, ctx.state(), s, 1e-11)
+        ctx.step(1)
+        assert o.step(s, 1)[0] == 0
+        g = ctx.state()
+    for k in g:
+        assert np.all(np.isfinite(g[k])), k
+    compare(w, g, s, 1e-11)
+
+
 def test_no_particles_and_rollback():
     w = get2d("twod16")
     arr = generate2d(w, n=0)
