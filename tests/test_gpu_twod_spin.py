@@ -191,3 +191,41 @@ def test_dense_tiles_move_the_spins():
         st, ko, kIIIo = o.step_s(s, 1)
         assert st == 0 and np.abs(kg - ko).max() <= 1 and np.abs(kIIIg - kIIIo).max() <= 1
         compare(w, ctx.state(), s, 1e-11)
+
+
+def test_degenerate_steps_and_spins():
+    """Particles on grid lines and cell corners with momenta 0, +-1e-300, +-1e-16,
+    steps across both grid lines next to a corner, and spins along each axis and
+    zero: one Lie step with spin against the oracle."""
+    w = get2d("twod16s").scaled(n_particles=64)
+    arr = generate2d(w)
+    dx1, dx2 = w.L1 / w.M1, w.L2 / w.M2
+    rng = np.random.default_rng(6)
+    c1 = rng.integers(0, w.M1, 64)
+    c2 = rng.integers(0, w.M2, 64)
+    mom = np.array([0.0, 1e-300, -1e-300, 1e-16, -1e-16, 0.05, -0.05, 0.02])
+    arr["x1"] = c1 * dx1
+    arr["x2"] = c2 * dx2
+    arr["x2"][::3] += 0.5 * dx2
+    arr["p1"] = mom[np.arange(64) % 8]
+    arr["p2"] = mom[(np.arange(64) // 8) % 8]
+    arr["x1"][56:] = c1[56:] * dx1 - 1e-4 * dx1
+    arr["x2"][56:] = c2[56:] * dx2 - 1e-4 * dx2
+    arr["p1"][56:] = 0.05
+    arr["p2"][56:] = 0.05 * dx2 / dx1
+    arr["x1"] = np.mod(arr["x1"], w.L1)
+    arr["x2"] = np.mod(arr["x2"], w.L2)
+    axes = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [0.0, 0.0, -1.0], [0.0, 0.0, 0.0]])
+    sp = axes[np.arange(64) % 5]
+    arr["sx"], arr["sy"], arr["sz"] = sp[:, 0].copy(), sp[:, 1].copy(), sp[:, 2].copy()
+    o = Oracle2D.from_workload(w)
+    s = initial_state2d(o, arr)
+    with ec.Context2D.from_workload(w) as ctx:
+        ctx.load(arr)
+        ctx.step(1)
+        assert o.step_s(s, 1)[0] == 0
+        g = ctx.state()
+    for k in g:
+        assert np.all(np.isfinite(g[k])), k
+    assert np.all(g["sx"][4::5] == 0.0) and np.all(g["sz"][4::5] == 0.0)   # a zero spin stays zero
+    compare(w, g, s, 3e-11)
